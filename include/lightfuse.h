@@ -1,0 +1,217 @@
+/*
+ * lightfuse.h -- C ABI of the MI355X (gfx950) one-bounce 2D-Gaussian-surfel
+ * ray tracer: the data-parallel hot path of LightFuse's relightable
+ * reconstruction (arXiv 2608.29269, Sec. 3).
+ *
+ * Conventions
+ *  - Every pointer documented "device" is caller-owned HIP device memory
+ *    (e.g. PyTorch tensors); the library never frees it.  Scene arrays passed
+ *    to lf_scene_set are retained (not copied) and must stay alive and
+ *    unmoved until the next lf_scene_set or lf_destroy.
+ *  - The library owns only what lives inside an lf_ctx: BVHs, per-surfel
+ *    trace records, environment sampling tables, queues and scratch.
+ *  - All calls are asynchronous on the context's stream.  Argument errors are
+ *    returned synchronously (LF_EINVAL, nothing is launched).  Conditions
+ *    found on the device (invalid transforms, traversal-stack overflow) are
+ *    latched in a device status word and returned by the next lf_sync.
+ *  - Arrays are row-major and contiguous; float is IEEE binary32.
+ *  - A context is not thread-safe; use one context per host thread/stream.
+ */
+#ifndef LIGHTFUSE_H
+#define LIGHTFUSE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LF_OK = 0,
+  LF_EINVAL = 1,       /* invalid argument (synchronous) or invalid device data (latched) */
+  LF_ENOMEM = 2,       /* device allocation failed */
+  LF_EDEVICE = 3,      /* HIP runtime error */
+  LF_EBUSY = 4,        /* server queue full */
+  LF_EOVERFLOW = 5,    /* traversal stack or queue overflow seen on the device */
+  LF_EUNSUPPORTED = 6  /* valid but unsupported configuration (e.g. k > 64, BVH deeper than the stack) */
+} lf_status;
+
+typedef struct lf_ctx lf_ctx;
+
+/* Creates a context on HIP device `device` that issues all work on
+ * `hip_stream` (a hipStream_t; NULL = the null stream). */
+lf_status lf_create(lf_ctx **out, int device, void *hip_stream);
+void lf_destroy(lf_ctx *ctx);
+/* Message of the last non-OK status of this context (never NULL). */
+const char *lf_last_error(const lf_ctx *ctx);
+/* Waits for the context's stream and returns (then clears) any latched device status. */
+lf_status lf_sync(lf_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Scene: shared background B plus M movable objects O_o, each a set of 2D
+ * Gaussian surfels G_i = (mu_i, q_i, s_i, alpha_i, a_i, m_i, r_i)
+ * (Sec. 3.1, Eq. gaussian-primitive; the splatting feature f_i is not traced).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const float *mu;        /* device [n,3] centre; object space for object surfels */
+  const float *q;         /* device [n,4] orientation quaternion (w,x,y,z), any nonzero norm */
+  const float *scale;     /* device [n,2] in-plane scales s_u, s_v > 0 */
+  const float *opacity;   /* device [n]   alpha in (0,1] */
+  const float *albedo;    /* device [n,3] base colour a in [0,1]^3 */
+  const float *roughness; /* device [n]   r in [0,1] */
+  const float *metallic;  /* device [n]   m in [0,1] */
+  int64_t n;              /* 1 <= n < 2^31 */
+  int32_t n_objects;      /* M, 0 <= M <= 63 */
+  const int64_t *object_offset; /* host [M+2], non-decreasing: background surfels are
+                                   [0, off[1]), object o (0-based) is [off[o+1], off[o+2]),
+                                   off[0] = 0 and off[M+1] = n */
+} lf_surfels;
+
+/* Retains the scene pointers and builds one bounding-volume hierarchy per
+ * instance (background and each object, in object space): per-surfel trace
+ * records, Morton codes, radix sort and a linear BVH (Karras 2012), then the
+ * bounds.  LF_EUNSUPPORTED if a hierarchy is deeper than the traversal stack. */
+lf_status lf_scene_set(lf_ctx *ctx, const lf_surfels *surfels);
+/* Recomputes trace records and bounds bottom-up after in-place updates of the
+ * retained arrays (same n, same object ranges); the hierarchy is kept. */
+lf_status lf_scene_refit(lf_ctx *ctx);
+
+/* Rigid transform T_{k,o} = (R, t) per object for one state k; it moves only
+ * centres and orientations (Sec. 3.1, Eq. state-assembly):
+ * mu' = R mu + t, frame' = R frame.  R must be a rotation; the library uses
+ * the Gram-Schmidt orthonormalisation of its first two columns (third column
+ * = their cross product) in double precision. */
+typedef struct {
+  const float *R; /* device [M,3,3] row-major, or NULL if M == 0 */
+  const float *t; /* device [M,3], or NULL if M == 0 */
+} lf_transforms;
+
+/* State environment map E_k: lat-long, +Y up, row r covers polar angle
+ * [r, r+1) pi/h from +Y, column c covers azimuth [c, c+1) 2pi/w measured
+ * from +X towards +Z; scene-linear RGB. */
+typedef struct {
+  const float *texels; /* device [h,w,3] */
+  int32_t h, w;        /* 1 <= h, w <= 8192 */
+} lf_envmap;
+
+/* Explicit rays (origins, unit directions); ray id i = array index. */
+typedef struct {
+  const float *o; /* device [n,3] */
+  const float *d; /* device [n,3] unit */
+  int64_t n;
+} lf_rays;
+
+/* Pinhole camera; pose is the 3x4 camera-to-world matrix (row-major) whose
+ * columns are (right, up, back, centre); the camera looks along -back.  The
+ * ray of pixel (x, y), y = 0 at the top, passes through the pixel centre;
+ * it is computed in binary32 with a fixed operation order so it is
+ * reproducible bit for bit.  Ray ids enumerate cameras in order, then pixels
+ * row-major: id = offset_c + y*w + x with offset_c = sum of earlier w*h. */
+typedef struct {
+  float pose[12];
+  float fov_y_deg; /* 0 < fov < 180 */
+  int32_t w, h;    /* >= 1 */
+} lf_camera;
+#define LF_MAX_CAMERAS 16
+
+#define LF_FLAG_NO_SECONDARY  (1u << 0) /* shade with the unshadowed E(w); trace no secondary ray */
+#define LF_FLAG_NO_BACKGROUND (1u << 1) /* drop the T*E(d) term behind partial coverage */
+#define LF_FLAG_BSDF_ONLY     (1u << 2) /* sample only the cosine/GGX mixture (no env importance sampling) */
+#define LF_FLAG_DIFFUSE_ONLY  (1u << 3) /* Lambert lobe only */
+#define LF_FLAG_BRUTE_FORCE   (1u << 4) /* test every surfel of every instance (no BVH); for testing */
+
+/* Tracing and estimator parameters.  Readings of points the paper leaves
+ * open (Sec. 3.2 "finite support", "opacity threshold", epsilon of
+ * Eq. surface-record; Sec. 3.3 estimator constants) are the defaults set by
+ * lf_params_default. */
+typedef struct {
+  int32_t k;        /* hits kept per ray, 1..64 (default 32) */
+  int32_t spp;      /* S shading samples per primary hit, 1..64 (default 1) */
+  uint64_t seed;    /* sampler seed; the same seed replays the same paths */
+  double alpha_min; /* opacity threshold, hits with alpha*exp(-rho^2/2) < alpha_min are culled (1/255) */
+  double alpha_cap; /* effective-opacity cap (0.99) */
+  double support_sigma; /* finite support radius in units of sigma (3) */
+  double eps;       /* epsilon of the composite normalisation (1e-6) */
+  double t_min;     /* smallest accepted ray parameter (1e-4) */
+  double secondary_offset; /* secondary origin = x_bar + offset * n_bar (1e-3) */
+  uint32_t flags;   /* LF_FLAG_* */
+} lf_params;
+void lf_params_default(lf_params *p);
+
+typedef struct {
+  float *radiance;      /* device [R,3] pixel radiance L (Eq. path-estimator, plus T*E(d)) */
+  float *depth;         /* device [R]   composited plane-intersection depth (ray parameter) */
+  float *normal;        /* device [R,3] composited unit normal facing the ray (0 on a miss) */
+  float *alpha;         /* device [R]   accumulated opacity A */
+  int32_t *hit_idx;     /* device [R,k] primary hit surfel indices in order, -1 padded; or NULL */
+  int32_t *sec_hit_idx; /* device [R,S,k] secondary hit lists (-1 padded, all -1 if not traced); or NULL */
+} lf_outputs;
+
+/* Forward render of one state (Sec. 3.2 tracing and compositing; Sec. 3.3
+ * one-bounce estimator): for each ray, the k closest valid hits sorted by
+ * (t, surfel index) are composited front to back into a surface record; S
+ * directions are drawn by one-sample power-heuristic MIS between environment
+ * importance sampling and a cosine/GGX mixture; each live direction traces
+ * one secondary ray whose record returns T2*E(w) + A2*L2, L2 being two
+ * unshadowed environment samples at the secondary record.  Pixel value
+ * L = A * mean_s F_s + T * E(d).
+ * Exactly one of `rays` (non-NULL) or `cams`/`n_cams` (1..LF_MAX_CAMERAS,
+ * host array) selects the rays.  radiance/depth/normal/alpha must be
+ * non-NULL device arrays with R rows. */
+lf_status lf_render(lf_ctx *ctx, const lf_transforms *xf, const lf_envmap *env, const lf_rays *rays,
+                    const lf_camera *cams, int32_t n_cams, const lf_params *p, lf_outputs *out);
+
+/* Upstream gradients of the outputs (device, same shapes; NULL = zero). */
+typedef struct {
+  const float *d_radiance, *d_depth, *d_normal, *d_alpha;
+} lf_grad_out;
+/* Parameter gradients (device, shapes of the scene arrays and env map).
+ * All eight must be non-NULL; they are OVERWRITTEN.  d_q is with respect to
+ * the raw (unnormalised) quaternion; the rest with respect to the values
+ * passed in. */
+typedef struct {
+  float *d_mu, *d_q, *d_scale, *d_opacity, *d_albedo, *d_roughness, *d_metallic, *d_env;
+} lf_grad_in;
+
+/* Reverse mode of lf_render under path replay (Sec. 3.3, PRB paragraph):
+ * the same seed replays the same paths; hit sets and their order, sampled
+ * directions, technique/lobe choices, MIS and pdf factors, secondary origins
+ * and records are held fixed, while gradients flow through the primary
+ * compositing (geometry, opacity, materials; Sec. 3.2), the primary BRDF and
+ * every environment texel read.  Hit lists are recomputed, never stored.
+ * Arguments as for lf_render with identical values. */
+lf_status lf_render_backward(lf_ctx *ctx, const lf_transforms *xf, const lf_envmap *env, const lf_rays *rays,
+                             const lf_camera *cams, int32_t n_cams, const lf_params *p, const lf_grad_out *g,
+                             lf_grad_in *grads);
+
+/* Scene-linear L1 objective of inverse rendering (Sec. 3.4,
+ * Eq. training-objectives, data term): loss = mean |pred - target| over n
+ * values; grad = sign(pred - target)/n (sign(0) = 0).  loss: device scalar;
+ * grad: device [n] or NULL. */
+lf_status lf_l1_loss(lf_ctx *ctx, const float *pred, const float *target, int64_t n, float *loss, float *grad);
+
+/* Pinhole rays of one camera (device o, d: [w*h,3]) exactly as lf_render
+ * generates them. */
+lf_status lf_raygen(lf_ctx *ctx, const lf_camera *cam, float *o, float *d);
+
+/* Introspection of the current scene's hierarchies (synchronous). */
+typedef struct {
+  int32_t n_instances;  /* M + 1 */
+  int64_t n_surfels;
+  int64_t n_nodes;      /* internal nodes over all instances */
+  int32_t max_depth;    /* deepest leaf (root = depth 0) */
+  int32_t stack_size;   /* traversal stack entries per ray */
+} lf_scene_info;
+lf_status lf_scene_get_info(lf_ctx *ctx, lf_scene_info *info);
+
+/* Copies instance `inst`'s hierarchy to host memory: n-1 internal nodes as
+ * child boxes [n-1, 2, 6] (lo xyz, hi xyz), children [n-1, 2] (>= 0 internal
+ * node within the instance, < 0 leaf ~position), leaf order perm [n] (surfel
+ * index of each leaf position, global), leaf boxes [n, 6] by leaf position.
+ * Any pointer may be NULL. */
+lf_status lf_scene_copy_bvh(lf_ctx *ctx, int32_t inst, float *node_boxes, int32_t *children, int32_t *perm,
+                            float *leaf_boxes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,258 @@
+"""MI355X (gfx950) one-bounce ray tracer of 2D Gaussian surfels: the
+data-parallel hot path of LightFuse (arXiv 2608.29269, Sec. 3).
+
+Thin Python layer over liblightfuse.so (include/lightfuse.h): PyTorch only
+provides device memory and the stream; every step runs in the HIP library.
+
+    tr = Tracer()
+    tr.set_scene(mu, q, scale, opacity, albedo, roughness, metallic, object_offset)
+    out = tr.render(env, R, t, cameras=[cam], k=32, spp=1, seed=7)
+    grads = tr.render_backward(env, R, t, cameras=[cam], ..., d_radiance=...)
+
+`RenderFn` wraps the pair as a torch.autograd.Function.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import (FLAG_BRUTE_FORCE, FLAG_BSDF_ONLY, FLAG_DIFFUSE_ONLY, FLAG_NO_BACKGROUND, FLAG_NO_SECONDARY,
+                   LFError)
+
+__all__ = ["Tracer", "RenderFn", "LFError", "FLAG_NO_SECONDARY", "FLAG_NO_BACKGROUND", "FLAG_BSDF_ONLY",
+           "FLAG_DIFFUSE_ONLY", "FLAG_BRUTE_FORCE", "camera_struct"]
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_tensor(t, name, shape_tail, n=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32:
+        raise ValueError(f"{name} must be a float32 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape[1:]) != tuple(shape_tail) or (n is not None and t.shape[0] != n):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [{n}, {', '.join(map(str, shape_tail))}]")
+
+
+def camera_struct(cam) -> _lib.Camera:
+    """lf_camera from an object with pose[12], fov_y_deg, w, h."""
+    c = _lib.Camera()
+    for i, v in enumerate(list(cam.pose)):
+        c.pose[i] = float(v)
+    c.fov_y_deg = float(cam.fov_y_deg)
+    c.w = int(cam.w)
+    c.h = int(cam.h)
+    return c
+
+
+class Tracer:
+    """One lf_ctx bound to a device and the current torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.L = _lib.load()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        st = self.L.lf_create(C.byref(ctx), device, C.c_void_p(self.stream.cuda_stream))
+        if st != 0:
+            raise LFError(st, "lf_create failed")
+        self.ctx = ctx
+        self.scene = None
+        self.n = 0
+        self.n_objects = 0
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.lf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        _lib.check(st, self.ctx)
+
+    # ------------------------------------------------------------------ scene
+    def set_scene(self, mu, q, scale, opacity, albedo, roughness, metallic, object_offset: Sequence[int]):
+        n = int(mu.shape[0])
+        for t, nm, tail in ((mu, "mu", (3,)), (q, "q", (4,)), (scale, "scale", (2,)), (opacity, "opacity", ()),
+                            (albedo, "albedo", (3,)), (roughness, "roughness", ()), (metallic, "metallic", ())):
+            _check_tensor(t, nm, tail, n)
+        off = (C.c_int64 * len(object_offset))(*[int(x) for x in object_offset])
+        s = _lib.Surfels(_ptr(mu), _ptr(q), _ptr(scale), _ptr(opacity), _ptr(albedo), _ptr(roughness),
+                         _ptr(metallic), n, len(object_offset) - 2, C.cast(off, C.POINTER(C.c_int64)))
+        # the library retains the pointers: keep the tensors alive
+        self.scene = dict(mu=mu, q=q, scale=scale, opacity=opacity, albedo=albedo, roughness=roughness,
+                          metallic=metallic)
+        self.object_offset = [int(x) for x in object_offset]
+        self._chk(self.L.lf_scene_set(self.ctx, C.byref(s)))
+        self.n = n
+        self.n_objects = len(object_offset) - 2
+
+    def refit(self):
+        self._chk(self.L.lf_scene_refit(self.ctx))
+
+    def info(self) -> dict:
+        i = _lib.SceneInfo()
+        self._chk(self.L.lf_scene_get_info(self.ctx, C.byref(i)))
+        return dict(n_instances=i.n_instances, n_surfels=i.n_surfels, n_nodes=i.n_nodes, max_depth=i.max_depth,
+                    stack_size=i.stack_size)
+
+    def copy_bvh(self, inst: int):
+        import numpy as np
+        n = self.object_offset[inst + 1] - self.object_offset[inst]
+        nn = max(n - 1, 0)
+        boxes = np.zeros((nn, 2, 6), np.float32)
+        ch = np.zeros((nn, 2), np.int32)
+        perm = np.zeros(n, np.int32)
+        leaf = np.zeros((n, 6), np.float32)
+        self._chk(self.L.lf_scene_copy_bvh(self.ctx, inst, boxes.ctypes.data, ch.ctypes.data, perm.ctypes.data,
+                                           leaf.ctypes.data))
+        return boxes, ch, perm, leaf
+
+    # ------------------------------------------------------------------ calls
+    @staticmethod
+    def params(k=32, spp=1, seed=0, flags=0, **kw) -> _lib.Params:
+        p = _lib.Params()
+        _lib.load().lf_params_default(C.byref(p))
+        p.k, p.spp, p.seed, p.flags = int(k), int(spp), int(seed), int(flags)
+        for key, v in kw.items():
+            setattr(p, key, v)
+        return p
+
+    def _args(self, env, R, t, rays, cameras):
+        import torch
+        _check_tensor(env, "env", (env.shape[1], 3))
+        em = _lib.EnvMap(_ptr(env), env.shape[0], env.shape[1])
+        if self.n_objects > 0:
+            _check_tensor(R, "R", (3, 3), self.n_objects)
+            _check_tensor(t, "t", (3,), self.n_objects)
+        xf = _lib.Transforms(_ptr(R) if self.n_objects else None, _ptr(t) if self.n_objects else None)
+        if rays is not None:
+            o, d = rays
+            _check_tensor(o, "rays.o", (3,))
+            _check_tensor(d, "rays.d", (3,), o.shape[0])
+            rs = _lib.Rays(_ptr(o), _ptr(d), o.shape[0])
+            return em, xf, C.byref(rs), None, 0, int(o.shape[0]), rs
+        cams = (_lib.Camera * len(cameras))(*[camera_struct(c) for c in cameras])
+        R_ = sum(int(c.w) * int(c.h) for c in cameras)
+        return em, xf, None, cams, len(cameras), R_, None
+
+    def render(self, env, R=None, t=None, rays=None, cameras=None, k=32, spp=1, seed=0, flags=0,
+               hit_idx=False, sec_hit_idx=False, out=None, **kw) -> dict:
+        import torch
+        em, xf, rp, cams, nc, nr, keep = self._args(env, R, t, rays, cameras)
+        p = self.params(k, spp, seed, flags, **kw)
+        dev = self.device
+        if out is None:
+            out = dict(radiance=torch.empty((nr, 3), device=dev), depth=torch.empty(nr, device=dev),
+                       normal=torch.empty((nr, 3), device=dev), alpha=torch.empty(nr, device=dev))
+            if hit_idx:
+                out["hit_idx"] = torch.empty((nr, k), dtype=torch.int32, device=dev)
+            if sec_hit_idx:
+                out["sec_hit_idx"] = torch.empty((nr, spp, k), dtype=torch.int32, device=dev)
+        o = _lib.Outputs(_ptr(out["radiance"]), _ptr(out["depth"]), _ptr(out["normal"]), _ptr(out["alpha"]),
+                         _ptr(out.get("hit_idx")), _ptr(out.get("sec_hit_idx")))
+        self._chk(self.L.lf_render(self.ctx, C.byref(xf), C.byref(em), rp, cams, nc, C.byref(p), C.byref(o)))
+        return out
+
+    def render_backward(self, env, R=None, t=None, rays=None, cameras=None, k=32, spp=1, seed=0, flags=0,
+                        d_radiance=None, d_depth=None, d_normal=None, d_alpha=None, grads=None, **kw) -> dict:
+        import torch
+        em, xf, rp, cams, nc, nr, keep = self._args(env, R, t, rays, cameras)
+        p = self.params(k, spp, seed, flags, **kw)
+        for g, nm, tail in ((d_radiance, "d_radiance", (3,)), (d_depth, "d_depth", ()),
+                            (d_normal, "d_normal", (3,)), (d_alpha, "d_alpha", ())):
+            if g is not None:
+                _check_tensor(g, nm, tail, nr)
+        if grads is None:
+            grads = {k_: torch.empty_like(v) for k_, v in self.scene.items()}
+            grads["env"] = torch.empty_like(env)
+        go = _lib.GradOut(_ptr(d_radiance), _ptr(d_depth), _ptr(d_normal), _ptr(d_alpha))
+        gi = _lib.GradIn(_ptr(grads["mu"]), _ptr(grads["q"]), _ptr(grads["scale"]), _ptr(grads["opacity"]),
+                         _ptr(grads["albedo"]), _ptr(grads["roughness"]), _ptr(grads["metallic"]),
+                         _ptr(grads["env"]))
+        self._chk(self.L.lf_render_backward(self.ctx, C.byref(xf), C.byref(em), rp, cams, nc, C.byref(p),
+                                            C.byref(go), C.byref(gi)))
+        return grads
+
+    def l1_loss(self, pred, target, want_grad=True):
+        import torch
+        if pred.shape != target.shape:
+            raise ValueError("pred and target shapes differ")
+        loss = torch.empty((), device=self.device)
+        grad = torch.empty_like(pred) if want_grad else None
+        self._chk(self.L.lf_l1_loss(self.ctx, _ptr(pred), _ptr(target), pred.numel(), _ptr(loss), _ptr(grad)))
+        return loss, grad
+
+    def raygen(self, camera):
+        import torch
+        n = int(camera.w) * int(camera.h)
+        o = torch.empty((n, 3), device=self.device)
+        d = torch.empty((n, 3), device=self.device)
+        c = camera_struct(camera)
+        self._chk(self.L.lf_raygen(self.ctx, C.byref(c), _ptr(o), _ptr(d)))
+        return o, d
+
+    def sync(self):
+        self._chk(self.L.lf_sync(self.ctx))
+
+
+def _render_fn():
+    import torch
+
+    class RenderFn(torch.autograd.Function):
+        """Differentiable render: forward -> lf_render, backward -> lf_render_backward
+        (path replay; hit lists are recomputed, not saved).  The scene tensors must
+        be the ones registered with tracer.set_scene; they are refit on entry."""
+
+        @staticmethod
+        def forward(ctx, tracer, cfg, mu, q, scale, opacity, albedo, roughness, metallic, env):
+            for k_, v in zip(("mu", "q", "scale", "opacity", "albedo", "roughness", "metallic"),
+                             (mu, q, scale, opacity, albedo, roughness, metallic)):
+                if tracer.scene is None or tracer.scene[k_].data_ptr() != v.data_ptr():
+                    raise ValueError(f"{k_} is not the tensor registered with Tracer.set_scene")
+            tracer.refit()
+            out = tracer.render(env, **cfg)
+            ctx.tracer, ctx.cfg = tracer, cfg
+            ctx.save_for_backward(env)
+            return out["radiance"], out["depth"], out["normal"], out["alpha"]
+
+        @staticmethod
+        def backward(ctx, g_rad, g_depth, g_normal, g_alpha):
+            (env,) = ctx.saved_tensors
+            cfg = {k_: v for k_, v in ctx.cfg.items() if k_ not in ("hit_idx", "sec_hit_idx")}
+            cont = (lambda g: None if g is None else g.contiguous())
+            g = ctx.tracer.render_backward(env, d_radiance=cont(g_rad), d_depth=cont(g_depth),
+                                           d_normal=cont(g_normal), d_alpha=cont(g_alpha), **cfg)
+            return (None, None, g["mu"], g["q"], g["scale"], g["opacity"], g["albedo"], g["roughness"],
+                    g["metallic"], g["env"])
+
+    return RenderFn
+
+
+class _Lazy:
+    _cls = None
+
+    def __get__(self, obj, owner):
+        if _Lazy._cls is None:
+            _Lazy._cls = _render_fn()
+        return _Lazy._cls
+
+
+class _NS:
+    RenderFn = _Lazy()
+
+
+def __getattr__(name):
+    if name == "RenderFn":
+        return _NS.RenderFn
+    raise AttributeError(name)

@@ -1,0 +1,519 @@
+// lf_api.hip -- host runtime behind include/lightfuse.h: context, argument
+// validation, library-owned device memory, scene build/refit and the launch
+// sequences of the forward and backward passes.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lf_internal.h"
+#include "lf_kernels.h"
+
+namespace {
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  bool ensure(size_t bytes) {
+    if (bytes <= cap && p) return true;
+    release();
+    size_t b = bytes ? bytes : 16;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return false;
+    }
+    cap = b;
+    return true;
+  }
+  template <class T>
+  T *as() const { return (T *)p; }
+};
+
+constexpr double kPiHost = 3.14159265358979323846;
+
+}  // namespace
+
+struct lf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // scene
+  bool has_scene = false;
+  lf::SurfelArrays s{};
+  int n_inst = 0;
+  std::vector<int32_t> h_first, h_n, h_node_off, h_root;
+  int64_t n_nodes = 0;
+  int32_t max_depth = 0;
+  double built_alpha_min = 0, built_sig2 = 0;
+  DevBuf d_first, d_n, d_root;
+  DevBuf rec, nodes, perm, leaf_parent, node_parent, flags, leafbox, rootbox, inst, status;
+  DevBuf keys, keys2, vals2, hist, boxidx, ibounds, depth;
+  // per call
+  DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;
+  DevBuf queue, qcount, contrib, frozen, l1acc, cams;
+  lf::CamArgs h_cams{};
+};
+
+namespace {
+
+lf_status fail(lf_ctx *c, lf_status st, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return st;
+}
+
+lf_status check_hip(lf_ctx *c, const char *where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, LF_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+  return LF_OK;
+}
+
+bool set_device(lf_ctx *c) { return hipSetDevice(c->device) == hipSuccess; }
+
+lf_status refit_impl(lf_ctx *c, double alpha_min, double sig2) {
+  lf::launch_refit(c->s, alpha_min, sig2, c->perm.as<int32_t>(), c->leaf_parent.as<int32_t>(),
+                   c->node_parent.as<int32_t>(), c->flags.as<int32_t>(), c->n_nodes, c->n_inst,
+                   c->nodes.as<lf::BNode>(), c->rec.as<lf::TraceRec>(), c->leafbox.as<float>(),
+                   c->rootbox.as<float>(), c->status.as<uint32_t>(), c->stream);
+  c->built_alpha_min = alpha_min;
+  c->built_sig2 = sig2;
+  return check_hip(c, "refit");
+}
+
+lf_status validate_params(lf_ctx *c, const lf_params *p) {
+  if (!p) return fail(c, LF_EINVAL, "params is NULL");
+  if (p->k < 1 || p->k > 64) return fail(c, p->k > 64 ? LF_EUNSUPPORTED : LF_EINVAL, "k=%d not in 1..64", p->k);
+  if (p->spp < 1 || p->spp > 64) return fail(c, LF_EINVAL, "spp=%d not in 1..64", p->spp);
+  if (!(p->alpha_min > 0.0) || !(p->alpha_cap > 0.0 && p->alpha_cap < 1.0) || !(p->support_sigma > 0.0) ||
+      !(p->eps >= 0.0) || !(p->t_min >= 0.0) || !std::isfinite(p->secondary_offset))
+    return fail(c, LF_EINVAL, "invalid tracing constants");
+  if (p->flags & ~0x1Fu) return fail(c, LF_EINVAL, "unknown flags 0x%x", p->flags);
+  return LF_OK;
+}
+
+// Common validation and setup of lf_render / lf_render_backward.
+lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, const lf_rays *rays,
+                  const lf_camera *cams, int32_t n_cams, const lf_params *p, lf::RenderArgs &a) {
+  if (!c) return LF_EINVAL;
+  if (!c->has_scene) return fail(c, LF_EINVAL, "no scene set");
+  lf_status st = validate_params(c, p);
+  if (st) return st;
+  if (!env || !env->texels || env->h < 1 || env->w < 1 || env->h > 8192 || env->w > 8192)
+    return fail(c, LF_EINVAL, "invalid environment map");
+  int M = c->n_inst - 1;
+  if (M > 0 && (!xf || !xf->R || !xf->t)) return fail(c, LF_EINVAL, "scene has %d objects but no transforms", M);
+  if ((rays != nullptr) == (cams != nullptr && n_cams > 0))
+    return fail(c, LF_EINVAL, "pass exactly one of rays or cameras");
+  memset(&a, 0, sizeof a);
+  int64_t R = 0;
+  if (rays) {
+    if (rays->n < 0 || (rays->n > 0 && (!rays->o || !rays->d))) return fail(c, LF_EINVAL, "invalid rays");
+    R = rays->n;
+    a.rays.o = rays->o;
+    a.rays.d = rays->d;
+    a.rays.n = R;
+  } else {
+    if (n_cams > LF_MAX_CAMERAS) return fail(c, LF_EINVAL, "at most %d cameras per call", LF_MAX_CAMERAS);
+    lf::CamArgs &ca = c->h_cams;
+    memset(&ca, 0, sizeof ca);
+    ca.n_cams = n_cams;
+    for (int i = 0; i < n_cams; ++i) {
+      const lf_camera &cm = cams[i];
+      if (cm.w < 1 || cm.h < 1 || !(cm.fov_y_deg > 0.f && cm.fov_y_deg < 180.f))
+        return fail(c, LF_EINVAL, "invalid camera %d", i);
+      for (int k = 0; k < 12; ++k) {
+        if (!std::isfinite(cm.pose[k])) return fail(c, LF_EINVAL, "non-finite camera pose %d", i);
+        ca.pose[i][k] = cm.pose[k];
+      }
+      ca.tan_half[i] = (float)std::tan((double)cm.fov_y_deg * kPiHost / 360.0);
+      ca.w[i] = cm.w;
+      ca.h[i] = cm.h;
+      ca.first[i + 1] = ca.first[i] + (int64_t)cm.w * cm.h;
+    }
+    R = ca.first[n_cams];
+    if (!c->cams.ensure(sizeof(lf::CamArgs))) return fail(c, LF_ENOMEM, "cameras");
+    if (hipMemcpyAsync(c->cams.p, &ca, sizeof ca, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return check_hip(c, "camera upload");
+    a.rays.cams = c->cams.as<lf::CamArgs>();
+  }
+  if (R * (int64_t)p->spp >= (int64_t)INT32_MAX) return fail(c, LF_EUNSUPPORTED, "too many rays x samples");
+  a.R = R;
+  double sig2 = p->support_sigma * p->support_sigma;
+  if (p->alpha_min != c->built_alpha_min || sig2 != c->built_sig2) {
+    if ((st = refit_impl(c, p->alpha_min, sig2))) return st;
+  }
+  // state assembly: instance records for this state's transforms
+  lf::launch_instances(M > 0 ? xf->R : nullptr, M > 0 ? xf->t : nullptr, c->rootbox.as<float>(),
+                       c->d_first.as<int32_t>(), c->d_n.as<int32_t>(), c->d_root.as<int32_t>(), c->n_inst,
+                       c->inst.as<lf::InstRec>(), c->status.as<uint32_t>(), c->stream);
+  // environment importance-sampling tables
+  int H = env->h, W = env->w;
+  if (!c->env_cdf_row.ensure(sizeof(double) * (H + 1)) || !c->env_cdf_col.ensure(sizeof(double) * H * (W + 1)) ||
+      !c->env_lum.ensure(sizeof(double) * H * W) || !c->env_rowsum.ensure(sizeof(double) * H) ||
+      !c->env_roww.ensure(sizeof(double) * H) || !c->env_scal.ensure(sizeof(double) * 2))
+    return fail(c, LF_ENOMEM, "environment tables");
+  lf::launch_env_tables(env->texels, H, W, p->flags, c->env_cdf_row.as<double>(), c->env_cdf_col.as<double>(),
+                        c->env_lum.as<double>(), c->env_rowsum.as<double>(), c->env_roww.as<double>(),
+                        c->env_scal.as<double>(), c->stream);
+  a.S.rec = c->rec.as<lf::TraceRec>();
+  a.S.nodes = c->nodes.as<lf::BNode>();
+  a.S.inst = c->inst.as<lf::InstRec>();
+  a.S.n_inst = c->n_inst;
+  a.S.n_rec = (int32_t)c->s.n;
+  a.S.n_nodes = (int32_t)c->n_nodes;
+  a.S.mu = c->s.mu; a.S.q = c->s.q; a.S.scale = c->s.scale; a.S.opacity = c->s.opacity;
+  a.S.albedo = c->s.albedo; a.S.roughness = c->s.roughness; a.S.metallic = c->s.metallic;
+  a.P.k = p->k;
+  a.P.spp = p->spp;
+  a.P.seed = p->seed;
+  a.P.alpha_min = p->alpha_min;
+  a.P.alpha_cap = p->alpha_cap;
+  a.P.sig2 = sig2;
+  a.P.eps = p->eps;
+  a.P.t_min = p->t_min;
+  a.P.sec_off = p->secondary_offset;
+  a.P.flags = p->flags;
+  a.E.tex = env->texels;
+  a.E.H = H;
+  a.E.W = W;
+  a.E.cdf_row = c->env_cdf_row.as<double>();
+  a.E.cdf_col = c->env_cdf_col.as<double>();
+  a.E.lum = c->env_lum.as<double>();
+  a.E.rowsum = c->env_rowsum.as<double>();
+  a.E.roww = c->env_roww.as<double>();
+  a.E.scal = c->env_scal.as<double>();
+  a.status = c->status.as<uint32_t>();
+  const bool trace2 = !(p->flags & LF_FLAG_NO_SECONDARY);
+  int64_t RS = R * p->spp;
+  if (trace2) {
+    if (!c->queue.ensure(sizeof(lf::SecEntry) * (RS > 0 ? RS : 1)) || !c->qcount.ensure(sizeof(uint32_t)))
+      return fail(c, LF_ENOMEM, "secondary queue");
+    a.queue = c->queue.as<lf::SecEntry>();
+    a.queue_count = c->qcount.as<uint32_t>();
+    lf::launch_fill_u32(a.queue_count, 0u, 1, c->stream);
+  }
+  return check_hip(c, "prepare");
+}
+
+}  // namespace
+
+extern "C" {
+
+void lf_params_default(lf_params *p) {
+  if (!p) return;
+  p->k = 32;
+  p->spp = 1;
+  p->seed = 0;
+  p->alpha_min = 1.0 / 255.0;
+  p->alpha_cap = 0.99;
+  p->support_sigma = 3.0;
+  p->eps = 1e-6;
+  p->t_min = 1e-4;
+  p->secondary_offset = 1e-3;
+  p->flags = 0;
+}
+
+lf_status lf_create(lf_ctx **out, int device, void *hip_stream) {
+  if (!out) return LF_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return LF_EDEVICE;
+  }
+  lf_ctx *c = new lf_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (!set_device(c) || !c->status.ensure(sizeof(uint32_t))) {
+    delete c;
+    return LF_EDEVICE;
+  }
+  lf::launch_fill_u32(c->status.as<uint32_t>(), 0u, 1, c->stream);
+  if (check_hip(c, "create")) {
+    delete c;
+    return LF_EDEVICE;
+  }
+  *out = c;
+  return LF_OK;
+}
+
+void lf_destroy(lf_ctx *c) {
+  if (!c) return;
+  set_device(c);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  delete c;
+}
+
+const char *lf_last_error(const lf_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+lf_status lf_sync(lf_ctx *c) {
+  if (!c) return LF_EINVAL;
+  set_device(c);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "sync");
+  uint32_t st = 0;
+  if (hipMemcpy(&st, c->status.p, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return check_hip(c, "sync");
+  if (st) {
+    lf::launch_fill_u32(c->status.as<uint32_t>(), 0u, 1, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    if (st & lf::kStatusOverflow) return fail(c, LF_EOVERFLOW, "traversal stack overflow on the device");
+    if (st & lf::kStatusBadTransform) return fail(c, LF_EINVAL, "degenerate or non-finite object transform");
+    if (st & lf::kStatusBvhCorrupt) return fail(c, LF_EDEVICE, "out-of-range hierarchy index on the device");
+  }
+  return LF_OK;
+}
+
+lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
+  if (!c) return LF_EINVAL;
+  if (!sf) return fail(c, LF_EINVAL, "surfels is NULL");
+  if (!sf->mu || !sf->q || !sf->scale || !sf->opacity || !sf->albedo || !sf->roughness || !sf->metallic)
+    return fail(c, LF_EINVAL, "surfel array is NULL");
+  if (sf->n < 1 || sf->n >= (int64_t)INT32_MAX) return fail(c, LF_EINVAL, "n=%lld out of range", (long long)sf->n);
+  if (sf->n_objects < 0 || sf->n_objects > lf::kMaxInst - 1)
+    return fail(c, sf->n_objects < 0 ? LF_EINVAL : LF_EUNSUPPORTED, "n_objects=%d not in 0..%d", sf->n_objects,
+                lf::kMaxInst - 1);
+  if (!sf->object_offset) return fail(c, LF_EINVAL, "object_offset is NULL");
+  int n_inst = sf->n_objects + 1;
+  const int64_t *off = sf->object_offset;
+  if (off[0] != 0 || off[n_inst] != sf->n) return fail(c, LF_EINVAL, "object_offset must start at 0 and end at n");
+  for (int i = 0; i < n_inst; ++i)
+    if (off[i + 1] < off[i]) return fail(c, LF_EINVAL, "object_offset must be non-decreasing");
+  set_device(c);
+  c->has_scene = false;
+  c->s = lf::SurfelArrays{sf->mu, sf->q, sf->scale, sf->opacity, sf->albedo, sf->roughness, sf->metallic, sf->n};
+  c->n_inst = n_inst;
+  c->h_first.assign(n_inst, 0);
+  c->h_n.assign(n_inst, 0);
+  c->h_node_off.assign(n_inst, 0);
+  c->h_root.assign(n_inst, 0);
+  int64_t nodes = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    c->h_first[i] = (int32_t)off[i];
+    c->h_n[i] = (int32_t)(off[i + 1] - off[i]);
+    c->h_node_off[i] = (int32_t)nodes;
+    if (c->h_n[i] >= 2) c->h_root[i] = (int32_t)nodes;
+    else if (c->h_n[i] == 1) c->h_root[i] = ~c->h_first[i];
+    nodes += c->h_n[i] > 1 ? c->h_n[i] - 1 : 0;
+  }
+  c->n_nodes = nodes;
+  const int64_t n = sf->n;
+  bool ok = c->d_first.ensure(4 * n_inst) && c->d_n.ensure(4 * n_inst) && c->d_root.ensure(4 * n_inst) &&
+            c->rec.ensure(sizeof(lf::TraceRec) * n) && c->nodes.ensure(sizeof(lf::BNode) * (nodes ? nodes : 1)) &&
+            c->perm.ensure(4 * n) && c->leaf_parent.ensure(4 * n) && c->node_parent.ensure(4 * (nodes ? nodes : 1)) &&
+            c->flags.ensure(4 * (nodes ? nodes : 1)) && c->leafbox.ensure(24 * n) &&
+            c->rootbox.ensure(24 * n_inst) && c->inst.ensure(sizeof(lf::InstRec) * n_inst) &&
+            c->keys.ensure(8 * n) && c->keys2.ensure(8 * n) && c->vals2.ensure(4 * n) &&
+            c->hist.ensure(4 * lf::radix_sort_hist_words(n)) && c->boxidx.ensure(24 * n) &&
+            c->ibounds.ensure(24 * n_inst) && c->depth.ensure(4);
+  if (!ok) return fail(c, LF_ENOMEM, "scene buffers for n=%lld", (long long)n);
+  if (hipMemcpy(c->d_first.p, c->h_first.data(), 4 * n_inst, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_n.p, c->h_n.data(), 4 * n_inst, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_root.p, c->h_root.data(), 4 * n_inst, hipMemcpyHostToDevice) != hipSuccess)
+    return check_hip(c, "scene upload");
+  lf_params dp;
+  lf_params_default(&dp);
+  const double sig2 = dp.support_sigma * dp.support_sigma;
+  hipStream_t st = c->stream;
+  lf::launch_boxes_by_index(c->s, dp.alpha_min, sig2, c->boxidx.as<float>(), st);
+  lf::launch_instance_bounds(c->boxidx.as<float>(), c->d_first.as<int32_t>(), c->d_n.as<int32_t>(), n_inst,
+                             c->ibounds.as<float>(), st);
+  lf::launch_morton(c->boxidx.as<float>(), c->ibounds.as<float>(), c->d_first.as<int32_t>(), c->d_n.as<int32_t>(),
+                    n_inst, n, c->keys.as<uint64_t>(), c->perm.as<int32_t>(), st);
+  lf::radix_sort(c->keys.as<uint64_t>(), c->perm.as<int32_t>(), c->keys2.as<uint64_t>(), c->vals2.as<int32_t>(),
+                 c->hist.as<uint32_t>(), n, st);
+  for (int i = 0; i < n_inst; ++i)
+    lf::launch_karras(c->keys.as<uint64_t>(), c->h_first[i], c->h_n[i], c->h_node_off[i], i, c->nodes.as<lf::BNode>(),
+                      c->node_parent.as<int32_t>(), c->leaf_parent.as<int32_t>(), c->status.as<uint32_t>(), st);
+  lf::launch_fill_u32(c->depth.as<uint32_t>(), 0u, 1, st);
+  lf::launch_depth(c->leaf_parent.as<int32_t>(), c->node_parent.as<int32_t>(), n, c->n_nodes,
+                   c->depth.as<int32_t>(), c->status.as<uint32_t>(), st);
+  lf_status s2 = refit_impl(c, dp.alpha_min, sig2);
+  if (s2) return s2;
+  if (hipStreamSynchronize(st) != hipSuccess) return check_hip(c, "scene build");
+  if (hipMemcpy(&c->max_depth, c->depth.p, 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return check_hip(c, "scene build");
+  uint32_t bst = 0;
+  if (hipMemcpy(&bst, c->status.p, 4, hipMemcpyDeviceToHost) != hipSuccess) return check_hip(c, "scene build");
+  if (bst & lf::kStatusBvhCorrupt) {
+    lf::launch_fill_u32(c->status.as<uint32_t>(), 0u, 1, st);
+    return fail(c, LF_EDEVICE, "hierarchy build produced an out-of-range index");
+  }
+  if (c->max_depth > lf::kStack)
+    return fail(c, LF_EUNSUPPORTED, "hierarchy depth %d exceeds the traversal stack (%d)", c->max_depth, lf::kStack);
+  c->has_scene = true;
+  return check_hip(c, "scene build");
+}
+
+lf_status lf_scene_refit(lf_ctx *c) {
+  if (!c) return LF_EINVAL;
+  if (!c->has_scene) return fail(c, LF_EINVAL, "no scene set");
+  set_device(c);
+  return refit_impl(c, c->built_alpha_min, c->built_sig2);
+}
+
+lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, const lf_rays *rays,
+                    const lf_camera *cams, int32_t n_cams, const lf_params *p, lf_outputs *out) {
+  if (!c) return LF_EINVAL;
+  if (!out) return fail(c, LF_EINVAL, "outputs struct is NULL");
+  set_device(c);
+  lf::RenderArgs a;
+  lf_status st = prepare(c, xf, env, rays, cams, n_cams, p, a);
+  if (st) return st;
+  if (a.R == 0) return LF_OK;
+  if (!out->radiance || !out->depth || !out->normal || !out->alpha)
+    return fail(c, LF_EINVAL, "radiance, depth, normal and alpha outputs are required");
+  a.radiance = out->radiance;
+  a.depth = out->depth;
+  a.normal = out->normal;
+  a.alpha = out->alpha;
+  a.hit_idx = out->hit_idx;
+  a.sec_hit_idx = out->sec_hit_idx;
+  const bool trace2 = !(p->flags & LF_FLAG_NO_SECONDARY);
+  if (trace2) {
+    if (!c->contrib.ensure(sizeof(float) * 3 * a.R * p->spp)) return fail(c, LF_ENOMEM, "contributions");
+    a.contrib = c->contrib.as<float>();
+  } else if (out->sec_hit_idx) {
+    lf::launch_fill_u32((uint32_t *)out->sec_hit_idx, 0xffffffffu, a.R * p->spp * p->k, c->stream);
+  }
+  lf::launch_primary(a, false, c->stream);
+  if (trace2) {
+    lf::launch_secondary(a, false, c->stream);
+    lf::launch_resolve(a, c->stream);
+  }
+  return check_hip(c, "render");
+}
+
+lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, const lf_rays *rays,
+                             const lf_camera *cams, int32_t n_cams, const lf_params *p, const lf_grad_out *g,
+                             lf_grad_in *gi) {
+  if (!c) return LF_EINVAL;
+  if (!g) return fail(c, LF_EINVAL, "upstream gradients struct is NULL");
+  if (!gi || !gi->d_mu || !gi->d_q || !gi->d_scale || !gi->d_opacity || !gi->d_albedo || !gi->d_roughness ||
+      !gi->d_metallic || !gi->d_env)
+    return fail(c, LF_EINVAL, "all eight gradient outputs are required");
+  set_device(c);
+  lf::RenderArgs a;
+  lf_status st = prepare(c, xf, env, rays, cams, n_cams, p, a);
+  if (st) return st;
+  const int64_t n = c->s.n;
+  hipStream_t s = c->stream;
+  lf::launch_fill_f32(gi->d_mu, 0.f, 3 * n, s);
+  lf::launch_fill_f32(gi->d_q, 0.f, 4 * n, s);
+  lf::launch_fill_f32(gi->d_scale, 0.f, 2 * n, s);
+  lf::launch_fill_f32(gi->d_opacity, 0.f, n, s);
+  lf::launch_fill_f32(gi->d_albedo, 0.f, 3 * n, s);
+  lf::launch_fill_f32(gi->d_roughness, 0.f, n, s);
+  lf::launch_fill_f32(gi->d_metallic, 0.f, n, s);
+  lf::launch_fill_f32(gi->d_env, 0.f, (int64_t)3 * env->h * env->w, s);
+  if (a.R == 0) return check_hip(c, "backward");
+  const bool trace2 = !(p->flags & LF_FLAG_NO_SECONDARY);
+  if (trace2) {
+    if (!c->frozen.ensure(sizeof(lf::SecFrozen) * a.R * p->spp)) return fail(c, LF_ENOMEM, "frozen records");
+    a.frozen = c->frozen.as<lf::SecFrozen>();
+    lf::launch_primary(a, true, s);
+    lf::launch_secondary(a, true, s);
+  }
+  lf::GradArgs ga{g->d_radiance, g->d_depth, g->d_normal, g->d_alpha, gi->d_mu, gi->d_q, gi->d_scale,
+                  gi->d_opacity, gi->d_albedo, gi->d_roughness, gi->d_metallic, gi->d_env};
+  lf::launch_adjoint(a, ga, s);
+  return check_hip(c, "backward");
+}
+
+lf_status lf_l1_loss(lf_ctx *c, const float *pred, const float *target, int64_t n, float *loss, float *grad) {
+  if (!c) return LF_EINVAL;
+  if (!pred || !target || !loss || n < 0) return fail(c, LF_EINVAL, "invalid loss arguments");
+  set_device(c);
+  if (!c->l1acc.ensure(sizeof(double))) return fail(c, LF_ENOMEM, "loss accumulator");
+  lf::launch_l1(pred, target, n, loss, grad, c->l1acc.as<double>(), c->stream);
+  return check_hip(c, "l1 loss");
+}
+
+lf_status lf_raygen(lf_ctx *c, const lf_camera *cam, float *o, float *d) {
+  if (!c) return LF_EINVAL;
+  if (!cam || !o || !d || cam->w < 1 || cam->h < 1 || !(cam->fov_y_deg > 0.f && cam->fov_y_deg < 180.f))
+    return fail(c, LF_EINVAL, "invalid raygen arguments");
+  set_device(c);
+  lf::CamArgs &ca = c->h_cams;
+  memset(&ca, 0, sizeof ca);
+  ca.n_cams = 1;
+  for (int k = 0; k < 12; ++k) ca.pose[0][k] = cam->pose[k];
+  ca.tan_half[0] = (float)std::tan((double)cam->fov_y_deg * kPiHost / 360.0);
+  ca.w[0] = cam->w;
+  ca.h[0] = cam->h;
+  ca.first[1] = (int64_t)cam->w * cam->h;
+  if (!c->cams.ensure(sizeof(lf::CamArgs))) return fail(c, LF_ENOMEM, "cameras");
+  if (hipMemcpyAsync(c->cams.p, &ca, sizeof ca, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return check_hip(c, "camera upload");
+  lf::launch_raygen(c->cams.as<lf::CamArgs>(), (int64_t)cam->w * cam->h, o, d, c->stream);
+  return check_hip(c, "raygen");
+}
+
+lf_status lf_scene_get_info(lf_ctx *c, lf_scene_info *info) {
+  if (!c) return LF_EINVAL;
+  if (!info) return fail(c, LF_EINVAL, "info is NULL");
+  if (!c->has_scene) return fail(c, LF_EINVAL, "no scene set");
+  info->n_instances = c->n_inst;
+  info->n_surfels = c->s.n;
+  info->n_nodes = c->n_nodes;
+  info->max_depth = c->max_depth;
+  info->stack_size = lf::kStack;
+  return LF_OK;
+}
+
+lf_status lf_scene_copy_bvh(lf_ctx *c, int32_t inst, float *node_boxes, int32_t *children, int32_t *perm,
+                            float *leaf_boxes) {
+  if (!c) return LF_EINVAL;
+  if (!c->has_scene) return fail(c, LF_EINVAL, "no scene set");
+  if (inst < 0 || inst >= c->n_inst) return fail(c, LF_EINVAL, "instance %d out of range", inst);
+  set_device(c);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "copy bvh");
+  int32_t n = c->h_n[inst], first = c->h_first[inst];
+  int32_t nn = n > 1 ? n - 1 : 0;
+  if (nn > 0 && (node_boxes || children)) {
+    std::vector<lf::BNode> h(nn);
+    if (hipMemcpy(h.data(), c->nodes.as<lf::BNode>() + c->h_node_off[inst], sizeof(lf::BNode) * nn,
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return check_hip(c, "copy bvh");
+    for (int32_t i = 0; i < nn; ++i) {
+      if (node_boxes) {
+        float *b = node_boxes + 12 * (int64_t)i;
+        for (int k = 0; k < 3; ++k) {
+          b[k] = h[i].lo0[k]; b[3 + k] = h[i].hi0[k]; b[6 + k] = h[i].lo1[k]; b[9 + k] = h[i].hi1[k];
+        }
+      }
+      if (children) {
+        int32_t c0 = h[i].c0, c1 = h[i].c1;
+        children[2 * i + 0] = c0 >= 0 ? c0 - c->h_node_off[inst] : ~((~c0) - first);
+        children[2 * i + 1] = c1 >= 0 ? c1 - c->h_node_off[inst] : ~((~c1) - first);
+      }
+    }
+  }
+  if (perm && n > 0 &&
+      hipMemcpy(perm, c->perm.as<int32_t>() + first, 4 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess)
+    return check_hip(c, "copy bvh");
+  if (leaf_boxes && n > 0 &&
+      hipMemcpy(leaf_boxes, c->leafbox.as<float>() + 6 * (int64_t)first, 24 * (size_t)n, hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return check_hip(c, "copy bvh");
+  return LF_OK;
+}
+
+}  // extern "C"

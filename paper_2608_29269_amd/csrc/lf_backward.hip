@@ -1,0 +1,226 @@
+// lf_backward.hip -- reverse mode of the forward path under path replay
+// (Sec. 3.3, PRB paragraph).  Per primary ray the hit list is recomputed by a
+// fresh traversal (never stored), the surface record is recomposited, the S
+// sampling decisions are regenerated from the seed and the frozen secondary
+// quantities are read from the replay pass.  The adjoint then runs through
+// the primary BRDF and every environment texel read, through the normal
+// normalisation and the front-to-back compositing (suffix sums over the hit
+// list), and through plane intersection and effective opacity into
+// (mu, q, s, alpha, a, m, r), accumulated with float atomics.
+#include "lf_device.h"
+#include "lf_kernels.h"
+
+namespace lf {
+
+namespace {
+
+inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+__device__ __forceinline__ void env_scatter(const EnvView &E, float *genv, d3 w, d3 g) {
+  Taps tp;
+  env_taps(E, w, tp);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (tp.w[k] == 0.0) continue;
+    float *p = genv + 3 * tp.i[k];
+    atomicAdd(p + 0, (float)(tp.w[k] * g.x));
+    atomicAdd(p + 1, (float)(tp.w[k] * g.y));
+    atomicAdd(p + 2, (float)(tp.w[k] * g.z));
+  }
+}
+
+// reverse of fcos(): accumulates into gn (unit normal), ga, gm, gr
+__device__ __forceinline__ void fcos_bwd(d3 n, d3 wi, d3 wo, d3 a, double m, double r, uint32_t flags, d3 gfc,
+                                         d3 &gn, d3 &ga, double &gm, double &gr) {
+  double ci = dot(n, wi);
+  ga = ga + ((1.0 - m) * kInvPi * ci) * gfc;
+  gm += -(gfc.x * a.x + gfc.y * a.y + gfc.z * a.z) * kInvPi * ci;
+  double gci = (gfc.x * a.x + gfc.y * a.y + gfc.z * a.z) * (1.0 - m) * kInvPi;
+  if (!(flags & LF_FLAG_DIFFUSE_ONLY)) {
+    Spec s;
+    spec_setup(n, wi, wo, r, s);
+    double a2 = s.a2;
+    double sc = s.D * s.G1i * s.G1o / (4.0 * s.co);
+    const double ac[3] = {a.x, a.y, a.z}, gc[3] = {gfc.x, gfc.y, gfc.z};
+    double gsc = 0.0, gac[3];
+    for (int c = 0; c < 3; ++c) {
+      double F0 = 0.04 * (1.0 - m) + ac[c] * m;
+      gsc += gc[c] * (F0 + (1.0 - F0) * s.P);
+      double gF0 = gc[c] * sc * (1.0 - s.P);
+      gac[c] = gF0 * m;
+      gm += gF0 * (ac[c] - 0.04);
+    }
+    ga = ga + mk(gac[0], gac[1], gac[2]);
+    double u = s.ch * s.ch * (a2 - 1.0) + 1.0;
+    double dD_dch = -4.0 * a2 * s.ch * (a2 - 1.0) / (kPi * u * u * u);
+    double dD_da2 = (u - 2.0 * a2 * s.ch * s.ch) / (kPi * u * u * u);
+    double si = sqrt(a2 + (1.0 - a2) * s.ci * s.ci), so = sqrt(a2 + (1.0 - a2) * s.co * s.co);
+    double dG1i_dc = 2.0 * a2 / (si * (s.ci + si) * (s.ci + si));
+    double dG1o_dc = 2.0 * a2 / (so * (s.co + so) * (s.co + so));
+    double dG1i_da2 = -s.ci * (1.0 - s.ci * s.ci) / (si * (s.ci + si) * (s.ci + si));
+    double dG1o_da2 = -s.co * (1.0 - s.co * s.co) / (so * (s.co + so) * (s.co + so));
+    double gch = gsc * dD_dch * s.G1i * s.G1o / (4.0 * s.co);
+    gci += gsc * s.D * dG1i_dc * s.G1o / (4.0 * s.co);
+    double gco = gsc * s.D * s.G1i * (dG1o_dc * s.co - s.G1o) / (4.0 * s.co * s.co);
+    double ga2 = gsc * (dD_da2 * s.G1i * s.G1o + s.D * (dG1i_da2 * s.G1o + s.G1i * dG1o_da2)) / (4.0 * s.co);
+    if (!s.rclamp) gr += ga2 * 4.0 * s.reff * s.reff * s.reff;
+    gn = gn + gco * wo + gch * s.h;
+  }
+  gn = gn + gci * wi;
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_adjoint(RenderArgs a, GradArgs G) {
+  __shared__ int stk[kStack * kBlock];
+  const int64_t ray = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (ray >= a.R) return;
+  const TraceParams &P = a.P;
+  const int S = P.spp;
+  float of[3], df[3];
+  load_ray(a.rays, ray, of, df);
+  d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
+  KBuf<K> kb;
+  Record rc;
+  trace<K>(a.S, P, o, d, kb, stk + threadIdx.x, a.status);
+  composite<K>(a.S, P, kb, o, d, rc);
+  d3 gL = G.d_radiance ? ld3(G.d_radiance + 3 * ray) : mk(0, 0, 0);
+  double gdepth = G.d_depth ? (double)G.d_depth[ray] : 0.0;
+  d3 gn = G.d_normal ? ld3(G.d_normal + 3 * ray) : mk(0, 0, 0);
+  double gA = G.d_alpha ? (double)G.d_alpha[ray] : 0.0, gT = 0.0;
+  if (!(P.flags & LF_FLAG_NO_BACKGROUND)) {
+    d3 Ed = env_eval(a.E, d);
+    gT += dot(gL, Ed);
+    env_scatter(a.E, G.g_env, d, rc.T * gL);
+  }
+  if (rc.nh == 0) return;
+  const double c_env = a.E.scal[1];
+  const bool trace2 = !(P.flags & LF_FLAG_NO_SECONDARY);
+  d3 wo = -d;
+  d3 ga = mk(0, 0, 0);
+  double gm = 0.0, gr = 0.0;
+  for (int s = 0; s < S; ++s) {
+    d3 w;
+    double K_;
+    if (!primary_sample(a.E, P, rc, wo, ray, s, c_env, w, K_)) continue;
+    double T2 = 1.0;
+    d3 ce = mk(0, 0, 0), cb = mk(0, 0, 0), we = mk(0, 0, 1), wb = mk(0, 0, 1);
+    uint32_t has = 0;
+    if (trace2) {
+      const SecFrozen f = a.frozen[ray * S + s];
+      T2 = f.T2;
+      ce = ld3(f.ce); cb = ld3(f.cb); we = ld3(f.we); wb = ld3(f.wb);
+      has = f.has;
+    }
+    d3 E = env_eval(a.E, w);
+    d3 Lin = T2 * E;
+    if (has & 1u) { d3 Ee = env_eval(a.E, we); Lin = Lin + mk(ce.x * Ee.x, ce.y * Ee.y, ce.z * Ee.z); }
+    if (has & 2u) { d3 Eb = env_eval(a.E, wb); Lin = Lin + mk(cb.x * Eb.x, cb.y * Eb.y, cb.z * Eb.z); }
+    d3 fc = fcos(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags);
+    d3 Ls = K_ * mk(fc.x * Lin.x, fc.y * Lin.y, fc.z * Lin.z);
+    gA += dot(gL, Ls) / S;
+    d3 gF = (rc.A / S) * gL;
+    d3 gfc = K_ * mk(gF.x * Lin.x, gF.y * Lin.y, gF.z * Lin.z);
+    d3 gLin = K_ * mk(gF.x * fc.x, gF.y * fc.y, gF.z * fc.z);
+    env_scatter(a.E, G.g_env, w, T2 * gLin);
+    if (has & 1u) env_scatter(a.E, G.g_env, we, mk(ce.x * gLin.x, ce.y * gLin.y, ce.z * gLin.z));
+    if (has & 2u) env_scatter(a.E, G.g_env, wb, mk(cb.x * gLin.x, cb.y * gLin.y, cb.z * gLin.z));
+    fcos_bwd(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags, gfc, gn, ga, gm, gr);
+  }
+  // normalisation n_bar = N / |N|
+  const double inv = 1.0 / (rc.A + P.eps);
+  d3 gN = mk(0, 0, 0);
+  if (rc.nl > 0.0) gN = (1.0 / rc.nl) * (gn - dot(rc.n, gn) * rc.n);
+  d3 N = rc.nl * rc.n;
+  // z_bar = Z * inv with inv = 1/(A + eps)
+  const double gZt = gdepth * inv, gZm = gm * inv, gZr = gr * inv;
+  const d3 gZn = inv * gN, gZa = inv * ga;
+  gA += -inv * (gdepth * rc.depth + dot(gN, N) + dot(ga, rc.a) + gm * rc.m + gr * rc.r);
+  // compositing adjoint, back to front: with v_j = gA + sum_z gZ . z_j and the
+  // suffix V_j = sum_{i>j} w_i v_i, d/d(alpha_j) = T_j v_j - (V_j + gT T)/(1 - alpha_j)
+  double V = 0.0, Tafter = rc.T;
+  for (int it = 0; it < K; ++it) {
+    const double t = kb.t[K - 1];
+    const uint32_t id = kb.id[K - 1];
+    krotr<K>(kb);
+    if (!(t > -INFINITY && t < INFINITY)) continue;
+    const int orig = (int)(id & kIdMask);
+    const bool flip = (id & kFlipBit) != 0;
+    HitQ h;
+    hit_quantities(a.S, P, orig, flip, t, o, d, h);
+    const double Tj = Tafter / (1.0 - h.at);
+    const double wj = Tj * h.at;
+    const d3 aj = ld3(a.S.albedo + 3 * (int64_t)orig);
+    const double mj = a.S.metallic[orig], rj = a.S.roughness[orig];
+    const double vj = gA + gZt * t + gZm * mj + gZr * rj + dot(gZn, h.nw) + dot(gZa, aj);
+    const double gat = Tj * vj - (V + gT * rc.T) / (1.0 - h.at);
+    V += wj * vj;
+    Tafter = Tj;
+    // attributes
+    const InstRec &I = a.S.inst[h.inst];
+    d3 oo, dd;
+    to_object(I, o, d, oo, dd);
+    double gt = gZt * wj;
+    d3 gnw = wj * gZn;
+    d3 gno = I.identity ? gnw : mulT(I.R, gnw);
+    if (flip) gno = -gno;
+    const int64_t i = orig;
+    atomicAdd(G.g_albedo + 3 * i + 0, (float)(gZa.x * wj));
+    atomicAdd(G.g_albedo + 3 * i + 1, (float)(gZa.y * wj));
+    atomicAdd(G.g_albedo + 3 * i + 2, (float)(gZa.z * wj));
+    atomicAdd(G.g_metallic + i, (float)(gZm * wj));
+    atomicAdd(G.g_roughness + i, (float)(gZr * wj));
+    // effective opacity alpha_t = min(cap, alpha exp(-rho^2/2))
+    const double graw = h.raw > P.alpha_cap ? 0.0 : gat;
+    atomicAdd(G.g_opacity + i, (float)(graw * h.g));
+    const double grho2 = graw * h.alpha * h.g * (-0.5);
+    const double gxu = grho2 * 2.0 * h.xu, gxv = grho2 * 2.0 * h.xv;
+    atomicAdd(G.g_scale + 2 * i + 0, (float)(-gxu * h.xu / h.su));
+    atomicAdd(G.g_scale + 2 * i + 1, (float)(-gxv * h.xv / h.sv));
+    const d3 gdl = (gxu / h.su) * h.tu + (gxv / h.sv) * h.tv;
+    const d3 gtu = (gxu / h.su) * h.dl, gtv = (gxv / h.sv) * h.dl;
+    // dl = o + t d - mu ; t = n.(mu - o) / (n.d)
+    gt += dot(gdl, dd);
+    const double den = dot(h.n, dd);
+    d3 gmu = (gt / den) * h.n - gdl;
+    d3 gnn = gno - (gt / den) * h.dl;
+    atomicAdd(G.g_mu + 3 * i + 0, (float)gmu.x);
+    atomicAdd(G.g_mu + 3 * i + 1, (float)gmu.y);
+    atomicAdd(G.g_mu + 3 * i + 2, (float)gmu.z);
+    // frame columns (t_u, t_v, n) of rot(q_hat) -> q_hat -> raw q
+    const double w = h.qw, x = h.qx, y = h.qy, z = h.qz;
+    // G row-major: G[r][0] = gtu_r, G[r][1] = gtv_r, G[r][2] = gnn_r
+    const double G0 = gtu.x, G1 = gtv.x, G2 = gnn.x, G3 = gtu.y, G4 = gtv.y, G5 = gnn.y, G6 = gtu.z, G7 = gtv.z,
+                 G8 = gnn.z;
+    double gq0 = G1 * (-2 * z) + G2 * (2 * y) + G3 * (2 * z) + G5 * (-2 * x) + G6 * (-2 * y) + G7 * (2 * x);
+    double gq1 = G1 * (2 * y) + G2 * (2 * z) + G3 * (2 * y) + G4 * (-4 * x) + G5 * (-2 * w) + G6 * (2 * z) +
+                 G7 * (2 * w) + G8 * (-4 * x);
+    double gq2 = G0 * (-4 * y) + G1 * (2 * x) + G2 * (2 * w) + G3 * (2 * x) + G5 * (2 * z) + G6 * (-2 * w) +
+                 G7 * (2 * z) + G8 * (-4 * y);
+    double gq3 = G0 * (-4 * z) + G1 * (-2 * w) + G2 * (2 * x) + G3 * (2 * w) + G4 * (-4 * z) + G5 * (2 * y) +
+                 G6 * (2 * x) + G7 * (2 * y);
+    const double pq = gq0 * w + gq1 * x + gq2 * y + gq3 * z;
+    atomicAdd(G.g_q + 4 * i + 0, (float)((gq0 - w * pq) / h.qlen));
+    atomicAdd(G.g_q + 4 * i + 1, (float)((gq1 - x * pq) / h.qlen));
+    atomicAdd(G.g_q + 4 * i + 2, (float)((gq2 - y * pq) / h.qlen));
+    atomicAdd(G.g_q + 4 * i + 3, (float)((gq3 - z * pq) / h.qlen));
+  }
+}
+
+template <int K>
+void adjoint_k(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
+  hipLaunchKernelGGL(k_adjoint<K>, dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, g);
+}
+
+}  // namespace
+
+void launch_adjoint(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
+  if (a.R <= 0) return;
+  switch (kbucket(a.P.k)) {
+    case 8: adjoint_k<8>(a, g, st); break;
+    case 16: adjoint_k<16>(a, g, st); break;
+    case 32: adjoint_k<32>(a, g, st); break;
+    default: adjoint_k<64>(a, g, st); break;
+  }
+}
+
+}  // namespace lf

@@ -1,0 +1,407 @@
+// lf_bvh.hip -- per-surfel prep, Morton codes, LSD radix sort, linear BVH
+// (Karras 2012, "Maximizing Parallelism in the Construction of BVHs, Octrees,
+// and k-d Trees") and bottom-up refit for gfx950.
+//
+// One hierarchy per instance (background and each object, in object space).
+// Leaves hold one surfel; internal nodes store both children's boxes so a
+// traversal step is one 64-byte fetch.  Surfel boxes bound the support
+// ellipse rho^2 <= rho^2_max (3-sigma support and opacity threshold) and are
+// rounded outward to binary32.
+#include "lf_device.h"
+#include "lf_kernels.h"
+
+namespace lf {
+
+namespace {
+
+// Trace record and conservative box of surfel i.
+__device__ __forceinline__ void surfel_prep(const SurfelArrays &s, int64_t i, double alpha_min, double sig2,
+                                            TraceRec &r, float *lo, float *hi) {
+  const float *q = s.q + 4 * i;
+  double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+  double ql = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw /= ql; qx /= ql; qy /= ql; qz /= ql;
+  d3 tu, tv, n;
+  quat_frame(qw, qx, qy, qz, tu, tv, n);
+  double su = s.scale[2 * i], sv = s.scale[2 * i + 1], al = s.opacity[i];
+  double rho2max = fmin(sig2, 2.0 * log(al / alpha_min));
+  r.n[0] = n.x; r.n[1] = n.y; r.n[2] = n.z;
+  r.a[0] = tu.x / su; r.a[1] = tu.y / su; r.a[2] = tu.z / su;
+  r.b[0] = tv.x / sv; r.b[1] = tv.y / sv; r.b[2] = tv.z / sv;
+  r.mu[0] = s.mu[3 * i]; r.mu[1] = s.mu[3 * i + 1]; r.mu[2] = s.mu[3 * i + 2];
+  r.orig = (int32_t)i;
+  r.rho2max = rho2max;
+  if (!(rho2max >= 0.0)) {  // never valid (also NaN): empty box
+    lo[0] = lo[1] = lo[2] = INFINITY;
+    hi[0] = hi[1] = hi[2] = -INFINITY;
+    return;
+  }
+  double rr = sqrt(rho2max) * (1.0 + 1e-12);
+  const double tuv[3][2] = {{su * tu.x, sv * tv.x}, {su * tu.y, sv * tv.y}, {su * tu.z, sv * tv.z}};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double e = rr * sqrt(tuv[k][0] * tuv[k][0] + tuv[k][1] * tuv[k][1]);
+    double c = (double)r.mu[k];
+    lo[k] = round_down_f(c - e);
+    hi[k] = round_up_f(c + e);
+  }
+}
+
+__global__ void k_boxes_by_index(SurfelArrays s, double alpha_min, double sig2, float *box6) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.n) return;
+  TraceRec r;
+  float lo[3], hi[3];
+  surfel_prep(s, i, alpha_min, sig2, r, lo, hi);
+  for (int k = 0; k < 3; ++k) { box6[6 * i + k] = lo[k]; box6[6 * i + 3 + k] = hi[k]; }
+}
+
+// one block per instance: bounds of the (finite) box centres
+__global__ void k_instance_bounds(const float *box6, const int32_t *first, const int32_t *cnt, float *out) {
+  int inst = blockIdx.x;
+  __shared__ float red[6][256];
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = first[inst] + threadIdx.x; i < (int64_t)first[inst] + cnt[inst]; i += blockDim.x) {
+    const float *b = box6 + 6 * i;
+    if (!(b[0] <= b[3])) continue;  // empty box
+    for (int k = 0; k < 3; ++k) {
+      float c = 0.5f * (b[k] + b[3 + k]);
+      lo[k] = fminf(lo[k], c);
+      hi[k] = fmaxf(hi[k], c);
+    }
+  }
+  for (int k = 0; k < 3; ++k) { red[k][threadIdx.x] = lo[k]; red[3 + k][threadIdx.x] = hi[k]; }
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 3; ++k) {
+        red[k][threadIdx.x] = fminf(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+        red[3 + k][threadIdx.x] = fmaxf(red[3 + k][threadIdx.x], red[3 + k][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 6; ++k) out[6 * inst + k] = red[k][0];
+}
+
+__device__ __forceinline__ uint64_t spread3(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | x << 32) & 0x1f00000000ffffull;
+  x = (x | x << 16) & 0x1f0000ff0000ffull;
+  x = (x | x << 8) & 0x100f00f00f00f00full;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
+}
+
+__global__ void k_morton(const float *box6, const float *ib, const int32_t *first, const int32_t *cnt, int n_inst,
+                         int64_t n, uint64_t *keys, int32_t *vals) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int inst = 0;
+  for (int j = 1; j < n_inst; ++j)
+    if (i >= first[j] && cnt[j] > 0) inst = j;
+  const float *b = box6 + 6 * i;
+  const float *B = ib + 6 * inst;
+  uint64_t code = 0;
+  if (b[0] <= b[3]) {
+    uint64_t c[3];
+    for (int k = 0; k < 3; ++k) {
+      float ext = B[3 + k] - B[k];
+      float x = ext > 0.f ? (0.5f * (b[k] + b[3 + k]) - B[k]) / ext : 0.5f;
+      x = fminf(fmaxf(x, 0.f), 1.f);
+      c[k] = (uint64_t)fminf(x * 524288.0f, 524287.0f);  // 19 bits per axis
+    }
+    code = (spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]);
+  }
+  keys[i] = ((uint64_t)inst << 57) | code;
+  vals[i] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------- radix sort
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *keys, int64_t n, int shift, uint32_t *hist,
+                                                        int nb) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    int64_t i = base + r * RS_THREADS + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of len words in place, one block of 1024 threads
+__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t *a, int64_t len) {
+  __shared__ uint32_t part[1024];
+  int64_t per = (len + 1023) / 1024;
+  int64_t b = threadIdx.x * per, e = b + per < len ? b + per : len;
+  uint32_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += a[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int64_t i = b; i < e; ++i) {
+    uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout,
+                                                           int32_t *vout, int64_t n, int shift,
+                                                           const uint32_t *offs, int nb) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wc[RS_THREADS / 64][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  base[threadIdx.x] = offs[(int64_t)threadIdx.x * nb + blockIdx.x];
+  const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
+  int64_t tile = (int64_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    for (int w = 0; w < RS_THREADS / 64; ++w) wc[w][threadIdx.x] = 0;
+    __syncthreads();
+    int64_t i = tile + r * RS_THREADS + threadIdx.x;
+    bool valid = i < n;
+    uint64_t key = valid ? kin[i] : 0ull;
+    uint32_t dg = (uint32_t)((key >> shift) & 255u);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (dg >> b) & 1u;
+      uint64_t m = __ballot(valid && bit);
+      peers &= bit ? m : ~m;
+    }
+    uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0) wc[wave][dg] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t off = base[dg] + rank;
+      for (int w = 0; w < wave; ++w) off += wc[w][dg];
+      if (off < (uint64_t)n) {  // always true for consistent offsets
+        kout[off] = key;
+        vout[off] = vin[i];
+      }
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+    for (int w = 0; w < RS_THREADS / 64; ++w) tot += wc[w][threadIdx.x];
+    base[threadIdx.x] += tot;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- Karras hierarchy
+__device__ __forceinline__ int delta(const uint64_t *k, int n, int i, int j) {
+  if (j < 0 || j >= n) return -1;
+  uint64_t a = k[i], b = k[j];
+  if (a == b) return 64 + __clz((unsigned)(i ^ j));
+  return __clzll(a ^ b);
+}
+
+__global__ void k_karras(const uint64_t *keys, int32_t first, int32_t n, int32_t node_off, int32_t inst,
+                         BNode *nodes, int32_t *node_parent, int32_t *leaf_parent, uint32_t *status) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n == 1) {
+    if (i == 0) leaf_parent[first] = -(inst + 2);
+    return;
+  }
+  if (i >= n - 1) return;
+  const uint64_t *k = keys + first;
+  int d = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) >= 0 ? 1 : -1;
+  int dmin = delta(k, n, i, i - d);
+  int lmax = 2;
+  while (delta(k, n, i, i + lmax * d) > dmin) lmax <<= 1;
+  int l = 0;
+  for (int t = lmax >> 1; t >= 1; t >>= 1)
+    if (delta(k, n, i, i + (l + t) * d) > dmin) l += t;
+  int j = i + l * d;
+  int dnode = delta(k, n, i, j);
+  int s = 0, t = l;
+  do {
+    t = (t + 1) >> 1;
+    if (delta(k, n, i, i + (s + t) * d) > dnode) s += t;
+  } while (t > 1);
+  int g = i + s * d + (d < 0 ? -1 : 0);
+  int lo = i < j ? i : j, hi = i < j ? j : i;
+  if (g < 0 || g + 1 > n - 1 || lo < 0 || hi > n - 1) {  // never taken for a consistent split
+    atomicOr(status, kStatusBvhCorrupt);
+    return;
+  }
+  int me = node_off + i;
+  int c0, c1;
+  if (lo == g) {
+    c0 = ~(first + g);
+    leaf_parent[first + g] = (me << 1) | 0;
+  } else {
+    c0 = node_off + g;
+    node_parent[node_off + g] = (me << 1) | 0;
+  }
+  if (hi == g + 1) {
+    c1 = ~(first + g + 1);
+    leaf_parent[first + g + 1] = (me << 1) | 1;
+  } else {
+    c1 = node_off + g + 1;
+    node_parent[node_off + g + 1] = (me << 1) | 1;
+  }
+  nodes[me].c0 = c0;
+  nodes[me].c1 = c1;
+  nodes[me].pad0 = nodes[me].pad1 = 0;
+  if (i == 0) node_parent[me] = -(inst + 2);
+}
+
+__global__ void k_depth(const int32_t *leaf_parent, const int32_t *node_parent, int64_t n, int64_t n_nodes,
+                        int32_t *max_depth, uint32_t *status) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int dep = 0;
+  int p = leaf_parent[i];
+  while (p >= 0) {
+    if ((p >> 1) >= n_nodes || dep > 4096) {
+      atomicOr(status, kStatusBvhCorrupt);
+      break;
+    }
+    ++dep;
+    p = node_parent[p >> 1];
+  }
+  atomicMax(max_depth, dep);
+}
+
+// trace records by leaf position and bounds from the leaves up; a node's
+// second arriving child computes its box (release/acquire on the arrival count)
+__global__ void k_refit(SurfelArrays s, double alpha_min, double sig2, const int32_t *perm,
+                        const int32_t *leaf_parent, const int32_t *node_parent, int32_t *flags, BNode *nodes,
+                        int64_t n_nodes, int n_inst, TraceRec *rec, float *leaf_box6, float *root_box6,
+                        uint32_t *status) {
+  int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= s.n) return;
+  int orig = perm[pos];
+  if (orig < 0 || orig >= s.n) {
+    atomicOr(status, kStatusBvhCorrupt);
+    return;
+  }
+  TraceRec r;
+  float lo[3], hi[3];
+  surfel_prep(s, orig, alpha_min, sig2, r, lo, hi);
+  rec[pos] = r;
+  for (int k = 0; k < 3; ++k) { leaf_box6[6 * pos + k] = lo[k]; leaf_box6[6 * pos + 3 + k] = hi[k]; }
+  int pp = leaf_parent[pos];
+  int steps = 0;
+  while (pp >= 0) {
+    int p = pp >> 1, side = pp & 1;
+    if (p >= n_nodes || ++steps > 4096) {  // never taken for a consistent hierarchy
+      atomicOr(status, kStatusBvhCorrupt);
+      return;
+    }
+    BNode *nd = nodes + p;
+    float *dlo = side ? nd->lo1 : nd->lo0, *dhi = side ? nd->hi1 : nd->hi0;
+    for (int k = 0; k < 3; ++k) { dlo[k] = lo[k]; dhi[k] = hi[k]; }
+    int old = __hip_atomic_fetch_add(flags + p, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 0) return;
+    const float *slo = side ? nd->lo0 : nd->lo1, *shi = side ? nd->hi0 : nd->hi1;
+    for (int k = 0; k < 3; ++k) { lo[k] = fminf(lo[k], slo[k]); hi[k] = fmaxf(hi[k], shi[k]); }
+    pp = node_parent[p];
+  }
+  int inst = -pp - 2;
+  if (inst < 0 || inst >= n_inst) {
+    atomicOr(status, kStatusBvhCorrupt);
+    return;
+  }
+  for (int k = 0; k < 3; ++k) { root_box6[6 * inst + k] = lo[k]; root_box6[6 * inst + 3 + k] = hi[k]; }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f32(float *p, float v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void launch_boxes_by_index(const SurfelArrays &s, double alpha_min, double sig2, float *box6, hipStream_t st) {
+  if (s.n <= 0) return;
+  hipLaunchKernelGGL(k_boxes_by_index, dim3(blocks(s.n, 256)), dim3(256), 0, st, s, alpha_min, sig2, box6);
+}
+
+void launch_instance_bounds(const float *box6, const int32_t *inst_first, const int32_t *inst_n, int n_inst,
+                            float *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_instance_bounds, dim3(n_inst), dim3(256), 0, st, box6, inst_first, inst_n, out);
+}
+
+void launch_morton(const float *box6, const float *inst_bounds, const int32_t *inst_first, const int32_t *inst_n,
+                   int n_inst, int64_t n, uint64_t *keys, int32_t *vals, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_morton, dim3(blocks(n, 256)), dim3(256), 0, st, box6, inst_bounds, inst_first, inst_n, n_inst,
+                     n, keys, vals);
+}
+
+size_t radix_sort_hist_words(int64_t n) { return (size_t)256 * blocks(n > 0 ? n : 1, RS_TILE); }
+
+void radix_sort(uint64_t *keys, int32_t *vals, uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist, int64_t n,
+                hipStream_t st) {
+  if (n <= 1) return;
+  int nb = (int)blocks(n, RS_TILE);
+  uint64_t *ka = keys, *kb = keys_tmp;
+  int32_t *va = vals, *vb = vals_tmp;
+  for (int pass = 0; pass < 8; ++pass) {
+    int shift = 8 * pass;
+    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, st, ka, n, shift, hist, nb);
+    hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, hist, (int64_t)256 * nb);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, st, ka, va, kb, vb, n, shift, hist, nb);
+    uint64_t *tk = ka; ka = kb; kb = tk;
+    int32_t *tv = va; va = vb; vb = tv;
+  }
+  // 8 passes: the result is back in (keys, vals)
+}
+
+void launch_karras(const uint64_t *keys, int32_t first, int32_t n, int32_t node_off, int32_t inst, BNode *nodes,
+                   int32_t *node_parent, int32_t *leaf_parent, uint32_t *status, hipStream_t st) {
+  if (n <= 0) return;
+  int64_t work = n > 1 ? n - 1 : 1;
+  hipLaunchKernelGGL(k_karras, dim3(blocks(work, 256)), dim3(256), 0, st, keys, first, n, node_off, inst, nodes,
+                     node_parent, leaf_parent, status);
+}
+
+void launch_depth(const int32_t *leaf_parent, const int32_t *node_parent, int64_t n, int64_t n_nodes,
+                  int32_t *max_depth, uint32_t *status, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_depth, dim3(blocks(n, 256)), dim3(256), 0, st, leaf_parent, node_parent, n, n_nodes,
+                     max_depth, status);
+}
+
+void launch_refit(const SurfelArrays &s, double alpha_min, double sig2, const int32_t *perm,
+                  const int32_t *leaf_parent, const int32_t *node_parent, int32_t *flags, int64_t n_nodes,
+                  int n_inst, BNode *nodes, TraceRec *rec, float *leaf_box6, float *root_box6, uint32_t *status,
+                  hipStream_t st) {
+  if (s.n <= 0) return;
+  if (n_nodes > 0) launch_fill_u32((uint32_t *)flags, 0u, n_nodes, st);
+  hipLaunchKernelGGL(k_refit, dim3(blocks(s.n, 256)), dim3(256), 0, st, s, alpha_min, sig2, perm, leaf_parent,
+                     node_parent, flags, nodes, n_nodes, n_inst, rec, leaf_box6, root_box6, status);
+}
+
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks(n, 256)), dim3(256), 0, st, p, v, n);
+}
+void launch_fill_f32(float *p, float v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_f32, dim3(blocks(n, 256)), dim3(256), 0, st, p, v, n);
+}
+
+}  // namespace lf

@@ -1,0 +1,705 @@
+// lf_device.h -- device functions of the gfx950 tracer: ray generation,
+// BVH traversal with a k-closest hit buffer, front-to-back compositing,
+// environment sampling and the metallic-roughness BRDF.
+//
+// Precision split.  Every discrete decision of the method (which surfels are
+// hit, their (t, index) order, the k-truncation, the sampled directions,
+// technique/lobe choices, hemisphere tests, texel choices) is taken in double
+// precision from the binary32 inputs, so the results agree with exact
+// arithmetic except for inputs within a few ulps of a switching point.  The
+// BVH is traversed with binary32 boxes and slab tests made conservative by
+// construction, so traversal never culls a valid hit.
+#pragma once
+#include "lf_internal.h"
+
+namespace lf {
+
+// ------------------------------------------------------------------ vectors
+struct d3 { double x, y, z; };
+__device__ __forceinline__ d3 mk(double x, double y, double z) { return d3{x, y, z}; }
+__device__ __forceinline__ d3 operator+(d3 a, d3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ d3 operator-(d3 a, d3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ d3 operator*(double s, d3 a) { return mk(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ d3 operator-(d3 a) { return mk(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ d3 cross(d3 a, d3 b) {
+  return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double lum(d3 c) { return 0.2126 * c.x + 0.7152 * c.y + 0.0722 * c.z; }
+__device__ __forceinline__ double clampd(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
+__device__ __forceinline__ d3 ld3(const float *p) { return mk(p[0], p[1], p[2]); }
+// M (row-major 3x3) times v, and its transpose
+__device__ __forceinline__ d3 mul(const double *M, d3 v) {
+  return mk(M[0] * v.x + M[1] * v.y + M[2] * v.z, M[3] * v.x + M[4] * v.y + M[5] * v.z,
+            M[6] * v.x + M[7] * v.y + M[8] * v.z);
+}
+__device__ __forceinline__ d3 mulT(const double *M, d3 v) {
+  return mk(M[0] * v.x + M[3] * v.y + M[6] * v.z, M[1] * v.x + M[4] * v.y + M[7] * v.z,
+            M[2] * v.x + M[5] * v.y + M[8] * v.z);
+}
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kInvPi = 1.0 / kPi;
+
+// ------------------------------------------------------------------ sampler
+// SplitMix64 (Steele, Lea & Flood 2014) chained over (seed, ray, sample, dim);
+// the top 24 bits give a uniform in [0,1) that is exact in float and double.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ double urand(uint64_t seed, uint64_t ray, uint64_t s, uint32_t dim) {
+  uint64_t h = splitmix64(seed ^ splitmix64(ray ^ splitmix64((s << 8) | (uint64_t)dim)));
+  return (double)(h >> 40) * (1.0 / 16777216.0);
+}
+
+// ------------------------------------------------------------------ frames
+// columns of the rotation of a unit quaternion (w,x,y,z)
+__device__ __forceinline__ void quat_frame(double w, double x, double y, double z, d3 &tu, d3 &tv, d3 &n) {
+  tu = mk(1 - 2 * (y * y + z * z), 2 * (x * y + w * z), 2 * (x * z - w * y));
+  tv = mk(2 * (x * y - w * z), 1 - 2 * (x * x + z * z), 2 * (y * z + w * x));
+  n = mk(2 * (x * z + w * y), 2 * (y * z - w * x), 1 - 2 * (x * x + y * y));
+}
+
+// branchless orthonormal basis about n (Duff et al. 2017)
+__device__ __forceinline__ void onb(d3 n, d3 &b1, d3 &b2) {
+  double sign = n.z >= 0.0 ? 1.0 : -1.0;
+  double a = -1.0 / (sign + n.z);
+  double b = n.x * n.y * a;
+  b1 = mk(1.0 + sign * n.x * n.x * a, sign * b, -sign * n.x);
+  b2 = mk(b, sign + n.y * n.y * a, -n.y);
+}
+
+// ------------------------------------------------------------------ raygen
+// Pinhole ray through the centre of pixel `pix` of camera c, in binary32
+// with a fixed operation order, no contraction, correctly rounded division
+// and square root (so every implementation produces the same bits).
+__device__ __noinline__ void raygen_f32(const CamArgs &ca, int c, int64_t pix, float *o, float *d) {
+#pragma clang fp contract(off)
+  const float *P = ca.pose[c];
+  int32_t w = ca.w[c], h = ca.h[c];
+  float fw = (float)w, fh = (float)h;
+  float aspect = fw / fh;
+  int64_t px = pix % w, py = pix / w;
+  float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  float th = ca.tan_half[c];
+  float sx = (2.0f * fx / fw - 1.0f) * th;
+  sx = sx * aspect;
+  float sy = (1.0f - 2.0f * fy / fh) * th;
+  float dx = P[0] * sx, dy = P[4] * sx, dz = P[8] * sx;
+  dx = dx + P[1] * sy;
+  dy = dy + P[5] * sy;
+  dz = dz + P[9] * sy;
+  dx = dx - P[2];
+  dy = dy - P[6];
+  dz = dz - P[10];
+  float ss = dx * dx;
+  ss = ss + dy * dy;
+  ss = ss + dz * dz;
+  float len = sqrtf(ss);
+  d[0] = dx / len;
+  d[1] = dy / len;
+  d[2] = dz / len;
+  o[0] = P[3];
+  o[1] = P[7];
+  o[2] = P[11];
+}
+
+__device__ __forceinline__ void load_ray(const RaySource &rs, int64_t id, float *o, float *d) {
+  if (rs.o) {
+    o[0] = rs.o[3 * id + 0]; o[1] = rs.o[3 * id + 1]; o[2] = rs.o[3 * id + 2];
+    d[0] = rs.d[3 * id + 0]; d[1] = rs.d[3 * id + 1]; d[2] = rs.d[3 * id + 2];
+  } else {
+    const CamArgs &ca = *rs.cams;
+    int c = 0;
+    while (c + 1 < ca.n_cams && id >= ca.first[c + 1]) ++c;
+    raygen_f32(ca, c, id - ca.first[c], o, d);
+  }
+}
+
+// ------------------------------------------------------------------ k-closest buffer
+// Sorted by (t, surfel index).  The first K-k slots hold -inf sentinels so
+// that the k-th hit always sits in the last (static) slot.
+template <int K>
+struct KBuf {
+  double t[K];
+  uint32_t id[K];  // surfel index | kFlipBit if the stored normal faces away from the ray
+};
+
+__device__ __forceinline__ bool kless(double t1, uint32_t i1, double t2, uint32_t i2) {
+  return t1 < t2 || (t1 == t2 && (i1 & kIdMask) < (i2 & kIdMask));
+}
+
+template <int K>
+__device__ __forceinline__ void kinit(KBuf<K> &b, int k) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    bool sentinel = j < K - k;
+    b.t[j] = sentinel ? -INFINITY : INFINITY;
+    b.id[j] = sentinel ? 0u : kIdMask;
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void kinsert(KBuf<K> &b, double t, uint32_t id) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    bool sw = kless(t, id, b.t[j], b.id[j]);
+    double tt = b.t[j];
+    uint32_t ti = b.id[j];
+    b.t[j] = sw ? t : tt;
+    b.id[j] = sw ? id : ti;
+    t = sw ? tt : t;
+    id = sw ? ti : id;
+  }
+}
+
+// Rotations used to walk the buffer with one loop body (static register
+// indexing): after K rotations the buffer is back in its original order.
+template <int K>
+__device__ __forceinline__ void krotl(KBuf<K> &b) {
+  double t0 = b.t[0];
+  uint32_t i0 = b.id[0];
+#pragma unroll
+  for (int j = 0; j < K - 1; ++j) { b.t[j] = b.t[j + 1]; b.id[j] = b.id[j + 1]; }
+  b.t[K - 1] = t0;
+  b.id[K - 1] = i0;
+}
+template <int K>
+__device__ __forceinline__ void krotr(KBuf<K> &b) {
+  double t0 = b.t[K - 1];
+  uint32_t i0 = b.id[K - 1];
+#pragma unroll
+  for (int j = K - 1; j > 0; --j) { b.t[j] = b.t[j - 1]; b.id[j] = b.id[j - 1]; }
+  b.t[0] = t0;
+  b.id[0] = i0;
+}
+
+// ------------------------------------------------------------------ traversal
+// adjacent binary32 values (finite arguments)
+__device__ __forceinline__ float next_up_f(float f) {
+  if (f == 0.0f) return 1.4e-45f;
+  int b = __float_as_int(f);
+  return __int_as_float(f > 0.0f ? b + 1 : b - 1);
+}
+__device__ __forceinline__ float next_down_f(float f) { return -next_up_f(-f); }
+__device__ __forceinline__ float round_up_f(double v) {
+  float f = (float)v;
+  return ((double)f < v && isfinite(f)) ? next_up_f(f) : f;
+}
+__device__ __forceinline__ float round_down_f(double v) {
+  float f = (float)v;
+  return ((double)f > v && isfinite(f)) ? next_down_f(f) : f;
+}
+
+// exact slab test of a double ray against a double box: entry/exit t
+__device__ __forceinline__ bool slab64(d3 o, d3 d, const double *lo, const double *hi, double &tn, double &tf) {
+  tn = -INFINITY;
+  tf = INFINITY;
+  const double oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (dd[a] == 0.0) {
+      if (oo[a] < lo[a] || oo[a] > hi[a]) return false;
+    } else {
+      double i = 1.0 / dd[a];
+      double t0 = (lo[a] - oo[a]) * i, t1 = (hi[a] - oo[a]) * i;
+      tn = fmax(tn, fmin(t0, t1));
+      tf = fmin(tf, fmax(t0, t1));
+    }
+  }
+  return tn <= tf;
+}
+
+struct RayF {
+  float ax, ay, az;   // origin + pad (used against the low planes)
+  float bx, by, bz;   // origin - pad (used against the high planes)
+  float ix, iy, iz;   // 1/d
+};
+
+__device__ __forceinline__ void child_test(const RayF &r, const float *lo, const float *hi, float tlo, float thi,
+                                           bool &hit, float &tn) {
+  float t0x = (lo[0] - r.ax) * r.ix, t1x = (hi[0] - r.bx) * r.ix;
+  float t0y = (lo[1] - r.ay) * r.iy, t1y = (hi[1] - r.by) * r.iy;
+  float t0z = (lo[2] - r.az) * r.iz, t1z = (hi[2] - r.bz) * r.iz;
+  float n = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tlo));
+  float f = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), thi));
+  // widen by the rounding of the subtraction, product and reciprocal (Ize 2013)
+  n = n - 1e-6f * fabsf(n);
+  f = f + 1e-6f * fabsf(f);
+  hit = n <= f;
+  tn = n;
+}
+
+__device__ __forceinline__ float inv_dir(float d) {
+  float dd = fabsf(d) < 1e-20f ? copysignf(1e-20f, d) : d;
+  return 1.0f / dd;
+}
+
+// Test one surfel (leaf position pos) against the object-space ray; insert
+// it if valid and among the k closest.
+template <int K>
+__device__ __forceinline__ void test_surfel(const TraceRec *__restrict__ recs, int pos, d3 o, d3 d, double t_min,
+                                            KBuf<K> &kb) {
+  const TraceRec &r = recs[pos];
+  d3 n = mk(r.n[0], r.n[1], r.n[2]);
+  double den = dot(n, d);
+  if (!(fabs(den) >= 1e-12)) return;
+  d3 mu = mk((double)r.mu[0], (double)r.mu[1], (double)r.mu[2]);
+  double t = dot(n, mu - o) / den;
+  if (!(t > t_min)) return;
+  uint32_t id = (uint32_t)r.orig | (den > 0.0 ? kFlipBit : 0u);
+  if (!kless(t, id, kb.t[K - 1], kb.id[K - 1])) return;
+  d3 dl = (o + t * d) - mu;
+  double xu = dl.x * r.a[0] + dl.y * r.a[1] + dl.z * r.a[2];
+  double xv = dl.x * r.b[0] + dl.y * r.b[1] + dl.z * r.b[2];
+  double rho2 = xu * xu + xv * xv;
+  if (!(rho2 <= r.rho2max)) return;
+  kinsert<K>(kb, t, id);
+}
+
+// object-space ray of instance I
+__device__ __forceinline__ void to_object(const InstRec &I, d3 o, d3 d, d3 &oo, d3 &dd) {
+  if (I.identity) {
+    oo = o;
+    dd = d;
+  } else {
+    oo = mulT(I.R, o - mk(I.t[0], I.t[1], I.t[2]));
+    dd = mulT(I.R, d);
+  }
+}
+
+// Collects the k closest valid hits of the world ray (o, d) over all
+// instances.  stk points at this lane's first LDS stack slot (stride kBlock).
+template <int K>
+__device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, KBuf<K> &kb, int *stk,
+                      uint32_t *status) {
+  kinit<K>(kb, P.k);
+  const bool brute = (P.flags & LF_FLAG_BRUTE_FORCE) != 0;
+  for (int ii = 0; ii < S.n_inst; ++ii) {
+    const InstRec &I = S.inst[ii];
+    if (I.n <= 0) continue;
+    double itn, itf;
+    if (!slab64(o, d, I.lo, I.hi, itn, itf)) continue;
+    if (itf < P.t_min) continue;
+    if (kb.t[K - 1] < INFINITY && itn > kb.t[K - 1]) continue;
+    d3 oo, dd;
+    to_object(I, o, d, oo, dd);
+    if (brute) {
+      const int end = I.first + I.n <= S.n_rec ? I.first + I.n : S.n_rec;
+      for (int pos = I.first < 0 ? 0 : I.first; pos < end; ++pos) test_surfel<K>(S.rec, pos, oo, dd, P.t_min, kb);
+      continue;
+    }
+    // binary32 ray for the slab tests, padded by its own rounding error over the
+    // instance's parameter range so the tests stay conservative
+    float ofx = (float)oo.x, ofy = (float)oo.y, ofz = (float)oo.z;
+    float dfx = (float)dd.x, dfy = (float)dd.y, dfz = (float)dd.z;
+    double eo = fmax(fmax(fabs(oo.x - ofx), fabs(oo.y - ofy)), fabs(oo.z - ofz));
+    double ed = fmax(fmax(fabs(dd.x - dfx), fabs(dd.y - dfy)), fabs(dd.z - dfz));
+    float pad = (float)((eo + ed * fmax(fabs(itf), fabs(itn)) + 1e-30) * 1.001) + 1e-30f;
+    RayF rf;
+    rf.ax = ofx + pad; rf.ay = ofy + pad; rf.az = ofz + pad;
+    rf.bx = ofx - pad; rf.by = ofy - pad; rf.bz = ofz - pad;
+    rf.ix = inv_dir(dfx); rf.iy = inv_dir(dfy); rf.iz = inv_dir(dfz);
+    // (lo - (o + pad), hi - (o - pad)) is the box grown by pad on every side,
+    // whatever the sign of the direction
+    const float tlo = (float)(0.5 * P.t_min);
+    int cur = I.root;
+    int sp = 0;
+    while (true) {
+      if (cur >= S.n_nodes || ~cur >= S.n_rec) {  // never taken for a consistent hierarchy
+        atomicOr(status, kStatusBvhCorrupt);
+        break;
+      }
+      if (cur >= 0) {
+        const BNode nd = S.nodes[cur];
+        float thi = kb.t[K - 1] < INFINITY ? round_up_f(kb.t[K - 1]) * (1.0f + 1e-6f) : INFINITY;
+        bool h0, h1;
+        float tn0, tn1;
+        child_test(rf, nd.lo0, nd.hi0, tlo, thi, h0, tn0);
+        child_test(rf, nd.lo1, nd.hi1, tlo, thi, h1, tn1);
+        if (h0 && h1) {
+          int nr = tn0 <= tn1 ? nd.c0 : nd.c1;
+          int fr = tn0 <= tn1 ? nd.c1 : nd.c0;
+          if (sp >= kStack) {
+            atomicOr(status, kStatusOverflow);
+            break;
+          }
+          stk[sp * kBlock] = fr;
+          ++sp;
+          cur = nr;
+          continue;
+        } else if (h0) {
+          cur = nd.c0;
+          continue;
+        } else if (h1) {
+          cur = nd.c1;
+          continue;
+        }
+      } else {
+        test_surfel<K>(S.rec, ~cur, oo, dd, P.t_min, kb);
+      }
+      if (sp == 0) break;
+      --sp;
+      cur = stk[sp * kBlock];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ compositing
+// Surface record of Eq. surface-record, in double precision.
+struct Record {
+  double A, T;
+  d3 x, n, a;   // composited position, unit normal (0 on a miss), base colour
+  double m, r, depth;
+  double nl;    // length of the composited normal before renormalisation
+  int nh;
+};
+
+__device__ __forceinline__ int inst_of(const SceneView &S, int orig) {
+  int ii = 0;
+  for (int j = 1; j < S.n_inst; ++j)
+    if (orig >= S.inst[j].first && S.inst[j].n > 0) ii = j;
+  return ii;
+}
+
+// Per-hit live quantities recomputed from the caller's arrays.
+struct HitQ {
+  double at, raw, g, rho2, xu, xv;
+  d3 nw;   // world normal facing the ray
+  d3 dl;   // object-space x - mu
+  d3 tu, tv, n;  // object-space frame
+  double qlen, qw, qx, qy, qz;  // normalised quaternion and raw norm
+  double su, sv, alpha;
+  int inst;
+};
+
+__device__ __forceinline__ void hit_quantities(const SceneView &S, const TraceParams &P, int orig, bool flip,
+                                               double t, d3 o, d3 d, HitQ &h) {
+  h.inst = inst_of(S, orig);
+  const InstRec &I = S.inst[h.inst];
+  d3 oo, dd;
+  to_object(I, o, d, oo, dd);
+  const float *q = S.q + 4 * (int64_t)orig;
+  double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+  h.qlen = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  h.qw = qw / h.qlen; h.qx = qx / h.qlen; h.qy = qy / h.qlen; h.qz = qz / h.qlen;
+  quat_frame(h.qw, h.qx, h.qy, h.qz, h.tu, h.tv, h.n);
+  d3 mu = ld3(S.mu + 3 * (int64_t)orig);
+  h.su = S.scale[2 * (int64_t)orig];
+  h.sv = S.scale[2 * (int64_t)orig + 1];
+  h.alpha = S.opacity[orig];
+  h.dl = (oo + t * dd) - mu;
+  h.xu = dot(h.dl, h.tu) / h.su;
+  h.xv = dot(h.dl, h.tv) / h.sv;
+  h.rho2 = h.xu * h.xu + h.xv * h.xv;
+  h.g = exp(-0.5 * h.rho2);
+  h.raw = h.alpha * h.g;
+  h.at = h.raw > P.alpha_cap ? P.alpha_cap : h.raw;
+  d3 nw = I.identity ? h.n : mul(I.R, h.n);
+  h.nw = flip ? -nw : nw;
+}
+
+// Effective opacity and ray-facing world normal of one hit (forward only).
+__device__ __forceinline__ void hit_alpha_normal(const SceneView &S, const TraceParams &P, int orig, bool flip,
+                                                 double t, d3 o, d3 d, double &at, d3 &nw) {
+  const InstRec &I = S.inst[inst_of(S, orig)];
+  d3 oo, dd;
+  to_object(I, o, d, oo, dd);
+  const float *q = S.q + 4 * (int64_t)orig;
+  double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+  double ql = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw /= ql; qx /= ql; qy /= ql; qz /= ql;
+  d3 tu, tv, n;
+  quat_frame(qw, qx, qy, qz, tu, tv, n);
+  d3 dl = (oo + t * dd) - ld3(S.mu + 3 * (int64_t)orig);
+  double xu = dot(dl, tu) / (double)S.scale[2 * (int64_t)orig];
+  double xv = dot(dl, tv) / (double)S.scale[2 * (int64_t)orig + 1];
+  double raw = (double)S.opacity[orig] * exp(-0.5 * (xu * xu + xv * xv));
+  at = raw > P.alpha_cap ? P.alpha_cap : raw;
+  d3 w = I.identity ? n : mul(I.R, n);
+  nw = flip ? -w : w;
+}
+
+template <int K>
+__device__ void composite(const SceneView &S, const TraceParams &P, KBuf<K> &kb, d3 o, d3 d, Record &rc) {
+  double T = 1.0, A = 0.0, Zt = 0.0, Zm = 0.0, Zr = 0.0;
+  d3 Zx = mk(0, 0, 0), Zn = mk(0, 0, 0), Za = mk(0, 0, 0);
+  int nh = 0;
+  for (int it = 0; it < K; ++it) {
+    const double t = kb.t[0];
+    const uint32_t id = kb.id[0];
+    krotl<K>(kb);
+    if (t > -INFINITY && t < INFINITY) {
+      int orig = (int)(id & kIdMask);
+      double at;
+      d3 nw;
+      hit_alpha_normal(S, P, orig, (id & kFlipBit) != 0, t, o, d, at, nw);
+      double w = T * at;
+      A += w;
+      Zt += w * t;
+      Zx = Zx + w * (o + t * d);
+      Zn = Zn + w * nw;
+      Za = Za + w * ld3(S.albedo + 3 * (int64_t)orig);
+      Zm += w * (double)S.metallic[orig];
+      Zr += w * (double)S.roughness[orig];
+      T *= (1.0 - at);
+      ++nh;
+    }
+  }
+  double inv = 1.0 / (A + P.eps);
+  rc.A = A;
+  rc.T = T;
+  rc.nh = nh;
+  rc.depth = Zt * inv;
+  rc.x = inv * Zx;
+  rc.a = inv * Za;
+  rc.m = Zm * inv;
+  rc.r = Zr * inv;
+  d3 N = inv * Zn;
+  double nl = sqrt(dot(N, N));
+  rc.nl = nl;
+  rc.n = (nh > 0 && nl > 0.0) ? (1.0 / nl) * N : mk(0, 0, 0);
+}
+
+// ------------------------------------------------------------------ environment
+__device__ __forceinline__ void dir_to_uv(d3 w, double &u, double &v) {
+  double th = acos(clampd(w.y, -1.0, 1.0));
+  double ph = atan2(w.z, w.x);
+  if (ph < 0.0) ph += 2.0 * kPi;
+  u = ph / (2.0 * kPi);
+  v = th / kPi;
+}
+
+struct Taps {
+  int64_t i[4];
+  double w[4];
+};
+
+// bilinear taps at (v*H - 1/2, u*W - 1/2); wraps in u, clamps in v
+__device__ __forceinline__ void env_taps(const EnvView &E, d3 w, Taps &tp) {
+  double u, v;
+  dir_to_uv(w, u, v);
+  double x = u * E.W - 0.5, y = v * E.H - 0.5;
+  double x0 = floor(x), y0 = floor(y);
+  double fx = x - x0, fy = y - y0;
+  int64_t c0 = (((int64_t)x0) % E.W + E.W) % E.W, c1 = (c0 + 1) % E.W;
+  int64_t r0 = (int64_t)y0, r1 = r0 + 1;
+  r0 = r0 < 0 ? 0 : (r0 > E.H - 1 ? E.H - 1 : r0);
+  r1 = r1 < 0 ? 0 : (r1 > E.H - 1 ? E.H - 1 : r1);
+  tp.i[0] = r0 * E.W + c0; tp.w[0] = (1 - fy) * (1 - fx);
+  tp.i[1] = r0 * E.W + c1; tp.w[1] = (1 - fy) * fx;
+  tp.i[2] = r1 * E.W + c0; tp.w[2] = fy * (1 - fx);
+  tp.i[3] = r1 * E.W + c1; tp.w[3] = fy * fx;
+}
+
+__device__ __forceinline__ d3 env_eval(const EnvView &E, d3 w) {
+  Taps tp;
+  env_taps(E, w, tp);
+  d3 c = mk(0, 0, 0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c = c + tp.w[k] * ld3(E.tex + 3 * tp.i[k]);
+  return c;
+}
+
+__device__ __forceinline__ int cdf_search(const double *cdf, int n, double u) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (cdf[mid + 1] > u) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ double env_texel_pdf(const EnvView &E, int r, int c, double sin_th) {
+  double total = E.scal[0];
+  if (!(sin_th > 0.0) || !(total > 0.0) || !(E.rowsum[r] > 0.0)) return 0.0;
+  double prow = E.roww[r] / total, pcol = E.lum[(int64_t)r * E.W + c] / E.rowsum[r];
+  return prow * pcol * (double)E.H * (double)E.W / (2.0 * kPi * kPi * sin_th);
+}
+
+__device__ __forceinline__ double env_pdf(const EnvView &E, d3 w) {
+  double u, v;
+  dir_to_uv(w, u, v);
+  int r = (int)floor(v * E.H), c = (int)floor(u * E.W);
+  r = r > E.H - 1 ? E.H - 1 : r;
+  c = c > E.W - 1 ? E.W - 1 : c;
+  return env_texel_pdf(E, r, c, sin(v * kPi));
+}
+
+__device__ __forceinline__ double env_sample(const EnvView &E, double ua, double ub, d3 &w) {
+  int r = cdf_search(E.cdf_row, E.H, ua);
+  const double *cc = E.cdf_col + (int64_t)r * (E.W + 1);
+  int c = cdf_search(cc, E.W, ub);
+  double orow = (ua - E.cdf_row[r]) / (E.cdf_row[r + 1] - E.cdf_row[r]);
+  double ocol = (ub - cc[c]) / (cc[c + 1] - cc[c]);
+  double v = (r + orow) / E.H, u = (c + ocol) / E.W;
+  double th = v * kPi, ph = u * 2.0 * kPi;
+  double st = sin(th);
+  w = mk(st * cos(ph), cos(th), st * sin(ph));
+  return env_texel_pdf(E, r, c, st);
+}
+
+// ------------------------------------------------------------------ BRDF
+// Lambert + GGX (Walter et al. 2007), separable Smith G1, Schlick Fresnel,
+// F0 = 0.04 (1 - m) + a m, alpha_g = clamp(r, 0.08, 1)^2.
+struct Spec {
+  double ci, co, ch, vh, a2, D, G1i, G1o, P, reff;
+  bool rclamp;
+  d3 h;
+};
+
+__device__ __forceinline__ void spec_setup(d3 n, d3 wi, d3 wo, double r, Spec &s) {
+  d3 h = wi + wo;
+  s.h = (1.0 / sqrt(dot(h, h))) * h;
+  s.ci = dot(n, wi);
+  s.co = dot(n, wo);
+  s.ch = dot(n, s.h);
+  s.vh = dot(wo, s.h);
+  s.rclamp = (r < 0.08 || r > 1.0);
+  s.reff = clampd(r, 0.08, 1.0);
+  double ag = s.reff * s.reff;
+  s.a2 = ag * ag;
+  double den = s.ch * s.ch * (s.a2 - 1.0) + 1.0;
+  s.D = s.a2 / (kPi * den * den);
+  s.G1i = 2.0 * s.ci / (s.ci + sqrt(s.a2 + (1.0 - s.a2) * s.ci * s.ci));
+  s.G1o = 2.0 * s.co / (s.co + sqrt(s.a2 + (1.0 - s.a2) * s.co * s.co));
+  double om = 1.0 - s.vh;
+  s.P = om * om * om * om * om;
+}
+
+// f(wi, wo) (no cosine), zero below either hemisphere
+__device__ __forceinline__ d3 brdf(d3 n, d3 wi, d3 wo, d3 a, double m, double r, uint32_t flags) {
+  double ci = dot(n, wi), co = dot(n, wo);
+  if (!(ci > 0.0) || !(co > 0.0)) return mk(0, 0, 0);
+  d3 f = ((1.0 - m) * kInvPi) * a;
+  if (flags & LF_FLAG_DIFFUSE_ONLY) return f;
+  Spec s;
+  spec_setup(n, wi, wo, r, s);
+  double sc = s.D * s.G1i * s.G1o / (4.0 * ci * co);
+  d3 F0 = mk(0.04 * (1.0 - m) + a.x * m, 0.04 * (1.0 - m) + a.y * m, 0.04 * (1.0 - m) + a.z * m);
+  return f + sc * mk(F0.x + (1.0 - F0.x) * s.P, F0.y + (1.0 - F0.y) * s.P, F0.z + (1.0 - F0.z) * s.P);
+}
+
+// f(wi, wo) * (n . wi) for a frozen live sample (no hemisphere test)
+__device__ __forceinline__ d3 fcos(d3 n, d3 wi, d3 wo, d3 a, double m, double r, uint32_t flags) {
+  double ci = dot(n, wi);
+  d3 f = ((1.0 - m) * kInvPi * ci) * a;
+  if (flags & LF_FLAG_DIFFUSE_ONLY) return f;
+  Spec s;
+  spec_setup(n, wi, wo, r, s);
+  double sc = s.D * s.G1i * s.G1o / (4.0 * s.co);
+  d3 F0 = mk(0.04 * (1.0 - m) + a.x * m, 0.04 * (1.0 - m) + a.y * m, 0.04 * (1.0 - m) + a.z * m);
+  return f + sc * mk(F0.x + (1.0 - F0.x) * s.P, F0.y + (1.0 - F0.y) * s.P, F0.z + (1.0 - F0.z) * s.P);
+}
+
+__device__ __forceinline__ double q_spec(d3 a, double m, uint32_t flags) {
+  if (flags & LF_FLAG_DIFFUSE_ONLY) return 0.0;
+  d3 F0 = mk(0.04 * (1.0 - m) + a.x * m, 0.04 * (1.0 - m) + a.y * m, 0.04 * (1.0 - m) + a.z * m);
+  double lf = lum(F0), ld = lum((1.0 - m) * a);
+  if (!(lf + ld > 0.0)) return 0.5;
+  return clampd(lf / (lf + ld), 0.1, 0.9);
+}
+
+__device__ __forceinline__ double pdf_bsdf(d3 n, d3 wi, d3 wo, d3 a, double m, double r, uint32_t flags) {
+  double ci = dot(n, wi);
+  if (!(ci > 0.0)) return 0.0;
+  double qs = q_spec(a, m, flags);
+  double pc = ci * kInvPi;
+  if (qs == 0.0) return pc;
+  Spec s;
+  spec_setup(n, wi, wo, r, s);
+  double pg = (s.ci > 0.0 && s.vh > 0.0) ? s.D * s.ch / (4.0 * fabs(s.vh)) : 0.0;
+  return qs * pg + (1.0 - qs) * pc;
+}
+
+// cosine (Malley) or GGX half-vector (Walter et al. 2007) direction
+__device__ __forceinline__ d3 sample_lobe(d3 n, d3 wo, double r, bool spec, double u1, double u2) {
+  d3 b1, b2;
+  onb(n, b1, b2);
+  double ph = 2.0 * kPi * u2;
+  if (!spec) {
+    double rr = sqrt(u1);
+    return (rr * cos(ph)) * b1 + (rr * sin(ph)) * b2 + sqrt(1.0 - u1) * n;
+  }
+  double reff = clampd(r, 0.08, 1.0), ag = reff * reff, a2 = ag * ag;
+  double c2 = (1.0 - u1) / (1.0 + (a2 - 1.0) * u1);
+  double ct = sqrt(c2), st = sqrt(1.0 - c2 < 0.0 ? 0.0 : 1.0 - c2);
+  d3 h = (st * cos(ph)) * b1 + (st * sin(ph)) * b2 + ct * n;
+  double oh = dot(wo, h);
+  return (2.0 * oh) * h - wo;
+}
+
+// One primary sample s: technique and direction by one-sample power-heuristic
+// MIS; returns false for a dead sample.  K = c_t p_t / ((c_e p_e)^2 + (c_b p_b)^2).
+__device__ __forceinline__ bool primary_sample(const EnvView &E, const TraceParams &P, const Record &rc, d3 wo,
+                                               int64_t ray, int s, double c_env, d3 &w, double &K) {
+  if (rc.nh == 0) return false;
+  double u0 = urand(P.seed, ray, s, 0), u1 = urand(P.seed, ray, s, 1);
+  double u2 = urand(P.seed, ray, s, 2), u3 = urand(P.seed, ray, s, 3);
+  bool use_env = u0 < c_env;
+  double pe = 0.0, pb;
+  if (use_env) {
+    pe = env_sample(E, u2, u3, w);
+  } else {
+    double qs = q_spec(rc.a, rc.m, P.flags);
+    w = sample_lobe(rc.n, wo, rc.r, u1 < qs, u2, u3);
+  }
+  if (!(dot(rc.n, w) > 0.0)) return false;
+  pb = pdf_bsdf(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags);
+  if (!use_env) pe = c_env > 0.0 ? env_pdf(E, w) : 0.0;
+  double c_bsdf = 1.0 - c_env;
+  double ct = use_env ? c_env : c_bsdf, pt = use_env ? pe : pb;
+  if (!(pt > 0.0)) return false;
+  double den = (c_env * pe) * (c_env * pe) + (c_bsdf * pb) * (c_bsdf * pb);
+  K = ct * pt / den;
+  return true;
+}
+
+// Frozen coefficients of the two unshadowed environment samples at a
+// secondary record (two-sample power heuristic).
+struct SecCoef {
+  d3 ce, cb, we, wb;
+  bool has_e, has_b;
+};
+
+__device__ __forceinline__ void secondary_coefs(const EnvView &E, const TraceParams &P, const Record &r2, d3 w,
+                                                int64_t ray, int s, double c_env, SecCoef &sc) {
+  sc.ce = mk(0, 0, 0);
+  sc.cb = mk(0, 0, 0);
+  sc.we = mk(0, 0, 0);
+  sc.wb = mk(0, 0, 0);
+  sc.has_e = sc.has_b = false;
+  if (r2.nh == 0) return;
+  d3 wo2 = -w;
+  if (c_env > 0.0) {
+    double u4 = urand(P.seed, ray, s, 4), u5 = urand(P.seed, ray, s, 5);
+    double pe2 = env_sample(E, u4, u5, sc.we);
+    double c2 = dot(r2.n, sc.we);
+    if (c2 > 0.0 && pe2 > 0.0) {
+      d3 f2 = brdf(r2.n, sc.we, wo2, r2.a, r2.m, r2.r, P.flags);
+      double pb2 = pdf_bsdf(r2.n, sc.we, wo2, r2.a, r2.m, r2.r, P.flags);
+      double wgt = pe2 * pe2 / (pe2 * pe2 + pb2 * pb2);
+      sc.ce = (r2.A * wgt * c2 / pe2) * f2;
+      sc.has_e = true;
+    }
+  }
+  double u6 = urand(P.seed, ray, s, 6), u7 = urand(P.seed, ray, s, 7), u8 = urand(P.seed, ray, s, 8);
+  double qs2 = q_spec(r2.a, r2.m, P.flags);
+  sc.wb = sample_lobe(r2.n, wo2, r2.r, u6 < qs2, u7, u8);
+  double c2 = dot(r2.n, sc.wb);
+  if (c2 > 0.0) {
+    double pb2 = pdf_bsdf(r2.n, sc.wb, wo2, r2.a, r2.m, r2.r, P.flags);
+    double pe2 = c_env > 0.0 ? env_pdf(E, sc.wb) : 0.0;
+    if (pb2 > 0.0) {
+      d3 f2 = brdf(r2.n, sc.wb, wo2, r2.a, r2.m, r2.r, P.flags);
+      double wgt = pb2 * pb2 / (pe2 * pe2 + pb2 * pb2);
+      sc.cb = (r2.A * wgt * c2 / pb2) * f2;
+      sc.has_b = true;
+    }
+  }
+}
+
+}  // namespace lf

@@ -1,0 +1,122 @@
+// lf_internal.h -- data layouts shared by the host runtime and the gfx950
+// kernels of liblightfuse.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lightfuse.h"
+
+namespace lf {
+
+constexpr int kBlock = 128;       // threads per block of the tracing kernels (2 wave64)
+constexpr int kStack = 64;        // traversal stack entries per lane (LDS)
+constexpr int kMaxInst = 64;      // background + up to 63 objects
+constexpr uint32_t kFlipBit = 0x80000000u;
+constexpr uint32_t kIdMask = 0x7fffffffu;
+
+// Status bits latched on the device.
+constexpr uint32_t kStatusOverflow = 1u;
+constexpr uint32_t kStatusBadTransform = 2u;
+constexpr uint32_t kStatusBvhCorrupt = 4u;   // an index read from the hierarchy was out of range
+
+// Per-surfel trace record, stored in leaf (Morton) order: everything the
+// ray-surfel decision needs, in double precision so that hit sets and their
+// (t, index) order are decided exactly as in FP64 arithmetic.  96 bytes.
+struct alignas(16) TraceRec {
+  double n[3];      // object-space unit normal (third frame column)
+  double a[3];      // t_u / s_u
+  double b[3];      // t_v / s_v
+  float mu[3];      // object-space centre (exact in double)
+  int32_t orig;     // surfel index in the caller's arrays
+  double rho2max;   // min(sigma^2, 2 ln(alpha / alpha_min)): support and threshold as one predicate
+};
+static_assert(sizeof(TraceRec) == 96, "TraceRec layout");
+
+// Binary BVH node holding both children's boxes (one 64-byte fetch per
+// visited node).  Child >= 0: internal node index (global); < 0: ~leaf
+// position (global).
+struct alignas(16) BNode {
+  float lo0[3], hi0[3];
+  float lo1[3], hi1[3];
+  int32_t c0, c1;
+  int32_t pad0, pad1;
+};
+static_assert(sizeof(BNode) == 64, "BNode layout");
+
+// One instance of the two-level scene for the current state: background
+// (identity) or an object with its rigid transform.
+struct alignas(16) InstRec {
+  double R[9];      // object -> world rotation (orthonormalised), row-major
+  double t[3];      // object -> world translation
+  double lo[3], hi[3];  // world-space bounds of the instance (conservative)
+  int32_t root;     // root node (>= 0), ~leaf (< 0) for one surfel; unused if n == 0
+  int32_t identity; // 1: background (no transform)
+  int32_t first;    // first surfel index / leaf position of the instance
+  int32_t n;        // surfel count
+};
+
+struct SceneView {
+  const TraceRec *rec;   // [N] leaf order
+  const BNode *nodes;    // internal nodes of all instances
+  const InstRec *inst;   // [n_inst]
+  int32_t n_inst;
+  int32_t n_rec;         // N
+  int32_t n_nodes;       // internal nodes over all instances
+  const float *mu, *q, *scale, *opacity, *albedo, *roughness, *metallic;  // caller arrays (orig index)
+};
+
+struct TraceParams {
+  int32_t k, spp;
+  uint64_t seed;
+  double alpha_min, alpha_cap, sig2, eps, t_min, sec_off;
+  uint32_t flags;
+};
+
+struct EnvView {
+  const float *tex;        // [H,W,3]
+  int32_t H, W;
+  const double *cdf_row;   // [H+1]
+  const double *cdf_col;   // [H,(W+1)]
+  const double *lum;       // [H,W]  max(lum, 0)
+  const double *rowsum;    // [H]
+  const double *roww;      // [H]
+  const double *scal;      // [0] total weight, [1] c_env
+};
+
+struct CamArgs {
+  float pose[LF_MAX_CAMERAS][12];
+  float tan_half[LF_MAX_CAMERAS];
+  int32_t w[LF_MAX_CAMERAS], h[LF_MAX_CAMERAS];
+  int64_t first[LF_MAX_CAMERAS + 1];  // ray-id offsets
+  int32_t n_cams;
+};
+
+struct RaySource {
+  const float *o, *d;     // explicit rays, or NULL to use cams
+  int64_t n;
+  const CamArgs *cams;    // device copy of the cameras
+};
+
+// Secondary ray queued by the primary pass (one per live sample).
+struct alignas(16) SecEntry {
+  double o[3];
+  double w[3];
+  float thr[3];        // K * f * cos * A / S of the primary sample
+  int32_t ray;         // primary ray id
+  int32_t s;           // sample index
+  int32_t pad;
+};
+static_assert(sizeof(SecEntry) == 80, "SecEntry layout");
+
+// Frozen secondary quantities of one (ray, sample) for the replayed backward.
+struct alignas(16) SecFrozen {
+  float T2;
+  float ce[3];   // A2 x frozen factors of the environment sample at the secondary record
+  float cb[3];   // A2 x frozen factors of the BSDF sample at the secondary record
+  float we[3];
+  float wb[3];
+  uint32_t has;  // bit0: env sample, bit1: BSDF sample
+};
+static_assert(sizeof(SecFrozen) == 64, "SecFrozen layout");
+
+}  // namespace lf

@@ -1,0 +1,417 @@
+// lf_render.hip -- forward path of the gfx950 tracer (wavefront form):
+//   instances  : per-state rigid transforms -> instance records (Eq. state-assembly)
+//   env tables : piecewise-constant importance-sampling tables of E_k
+//   primary    : ray generation, traversal + k-closest buffer, compositing into
+//                the surface record (Eq. surface-record), outputs, sampling of
+//                S directions and ballot-compacted enqueue of live secondaries
+//   secondary  : trace of the compacted queue, secondary record, two
+//                unshadowed env samples, per-sample contribution
+//   resolve    : pixel radiance = T E(d) + sum_s contributions (fixed order)
+#include "lf_device.h"
+#include "lf_kernels.h"
+
+namespace lf {
+
+namespace {
+
+inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+__global__ void k_instances(const float *R, const float *t, const float *root_box6, const int32_t *first,
+                            const int32_t *cnt, const int32_t *root, int n_inst, InstRec *out, uint32_t *status) {
+  int ii = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ii >= n_inst) return;
+  InstRec I;
+  I.first = first[ii];
+  I.n = cnt[ii];
+  I.root = root[ii];
+  I.identity = ii == 0;
+  const float *rb = root_box6 + 6 * ii;
+  double blo[3] = {rb[0], rb[1], rb[2]}, bhi[3] = {rb[3], rb[4], rb[5]};
+  if (ii == 0) {
+    for (int k = 0; k < 9; ++k) I.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    for (int k = 0; k < 3; ++k) I.t[k] = 0.0;
+  } else {
+    const float *A = R + 9 * (ii - 1);
+    // Gram-Schmidt of the first two columns, third = cross product
+    d3 c0 = mk(A[0], A[3], A[6]), c1 = mk(A[1], A[4], A[7]);
+    double l0 = sqrt(dot(c0, c0));
+    bool bad = !(l0 > 1e-6);
+    c0 = (1.0 / l0) * c0;
+    c1 = c1 - dot(c0, c1) * c0;
+    double l1 = sqrt(dot(c1, c1));
+    bad = bad || !(l1 > 1e-6);
+    c1 = (1.0 / l1) * c1;
+    d3 c2 = cross(c0, c1);
+    const float *tt = t + 3 * (ii - 1);
+    bad = bad || !isfinite(tt[0]) || !isfinite(tt[1]) || !isfinite(tt[2]);
+    if (bad) {
+      atomicOr(status, kStatusBadTransform);
+      I.n = 0;
+    }
+    I.R[0] = c0.x; I.R[1] = c1.x; I.R[2] = c2.x;
+    I.R[3] = c0.y; I.R[4] = c1.y; I.R[5] = c2.y;
+    I.R[6] = c0.z; I.R[7] = c1.z; I.R[8] = c2.z;
+    for (int k = 0; k < 3; ++k) I.t[k] = tt[k];
+  }
+  // world bounds: transformed corners of the object-space root box, padded
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (I.n > 0 && blo[0] <= bhi[0]) {
+    for (int c = 0; c < 8; ++c) {
+      d3 p = mk((c & 1) ? bhi[0] : blo[0], (c & 2) ? bhi[1] : blo[1], (c & 4) ? bhi[2] : blo[2]);
+      d3 w = mul(I.R, p) + mk(I.t[0], I.t[1], I.t[2]);
+      const double ww[3] = {w.x, w.y, w.z};
+      for (int k = 0; k < 3; ++k) { lo[k] = fmin(lo[k], ww[k]); hi[k] = fmax(hi[k], ww[k]); }
+    }
+    for (int k = 0; k < 3; ++k) {
+      double pad = 1e-9 * (fabs(lo[k]) + fabs(hi[k])) + 1e-30;
+      lo[k] -= pad;
+      hi[k] += pad;
+    }
+  } else {
+    I.n = 0;
+  }
+  for (int k = 0; k < 3; ++k) { I.lo[k] = lo[k]; I.hi[k] = hi[k]; }
+  out[ii] = I;
+}
+
+// one block per env row: clamped luminance, row sum, conditional CDF (double)
+__global__ __launch_bounds__(256) void k_env_rows(const float *tex, int H, int W, double *cdf_col, double *lum,
+                                                  double *rowsum, double *roww) {
+  int r = blockIdx.x;
+  __shared__ double part[256];
+  __shared__ double carry;
+  if (threadIdx.x == 0) carry = 0.0;
+  __syncthreads();
+  // pass 1: row sum
+  double s = 0.0;
+  for (int c = threadIdx.x; c < W; c += 256) {
+    const float *p = tex + 3 * ((int64_t)r * W + c);
+    double l = 0.2126 * p[0] + 0.7152 * p[1] + 0.0722 * p[2];
+    if (!(l > 0.0)) l = 0.0;
+    lum[(int64_t)r * W + c] = l;
+    s += l;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  double rs = part[0];
+  __syncthreads();
+  double *cc = cdf_col + (int64_t)r * (W + 1);
+  // pass 2: inclusive scan in chunks of 256
+  for (int c0 = 0; c0 < W; c0 += 256) {
+    int c = c0 + threadIdx.x;
+    double v = (c < W) ? lum[(int64_t)r * W + c] : 0.0;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      double x = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0.0;
+      __syncthreads();
+      part[threadIdx.x] += x;
+      __syncthreads();
+    }
+    if (c < W) cc[c + 1] = rs > 0.0 ? (carry + part[threadIdx.x]) / rs : (double)(c + 1) / W;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += part[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    cc[0] = 0.0;
+    cc[W] = 1.0;
+    rowsum[r] = rs;
+    roww[r] = rs * sin((r + 0.5) * kPi / H);
+  }
+}
+
+// one block: marginal CDF over rows, total weight, c_env
+__global__ __launch_bounds__(256) void k_env_marginal(int H, uint32_t flags, const double *roww, double *cdf_row,
+                                                      double *scal) {
+  __shared__ double part[256];
+  __shared__ double carry;
+  __shared__ double total;
+  double s = 0.0;
+  for (int r = threadIdx.x; r < H; r += 256) s += roww[r];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { total = part[0]; carry = 0.0; }
+  __syncthreads();
+  double tot = total;
+  for (int r0 = 0; r0 < H; r0 += 256) {
+    int r = r0 + threadIdx.x;
+    part[threadIdx.x] = r < H ? roww[r] : 0.0;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      double x = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0.0;
+      __syncthreads();
+      part[threadIdx.x] += x;
+      __syncthreads();
+    }
+    if (r < H) cdf_row[r + 1] = tot > 0.0 ? (carry + part[threadIdx.x]) / tot : (double)(r + 1) / H;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += part[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    cdf_row[0] = 0.0;
+    cdf_row[H] = 1.0;
+    scal[0] = tot;
+    scal[1] = (tot > 0.0 && !(flags & LF_FLAG_BSDF_ONLY)) ? 0.5 : 0.0;
+  }
+}
+
+__device__ __forceinline__ void wave_enqueue(bool live, const SecEntry &e, SecEntry *queue, uint32_t *count) {
+  uint64_t mask = __ballot(live);
+  if (mask == 0) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader);
+  if (live) {
+    uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
+    queue[base + (uint32_t)__popcll(mask & lt)] = e;
+  }
+}
+
+// Primary pass.  replay = true regenerates the queue only (backward).
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_primary(RenderArgs a, bool replay) {
+  __shared__ int stk[kStack * kBlock];
+  const int64_t ray = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool active = ray < a.R;
+  const TraceParams &P = a.P;
+  const int S = P.spp;
+  float of[3] = {0, 0, 0}, df[3] = {0, 0, 1};
+  if (active) load_ray(a.rays, ray, of, df);
+  d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
+  KBuf<K> kb;
+  Record rc;
+  rc.nh = 0;
+  if (active) {
+    trace<K>(a.S, P, o, d, kb, stk + threadIdx.x, a.status);
+    composite<K>(a.S, P, kb, o, d, rc);
+  }
+  const double c_env = a.E.scal[1];
+  d3 wo = -d;
+  d3 L = mk(0, 0, 0);
+  if (active && !replay) {
+    a.depth[ray] = (float)rc.depth;
+    a.alpha[ray] = (float)rc.A;
+    for (int c = 0; c < 3; ++c) a.normal[3 * ray + c] = (float)(c == 0 ? rc.n.x : (c == 1 ? rc.n.y : rc.n.z));
+    if (a.hit_idx) {
+      int j = 0;
+#pragma unroll
+      for (int e = 0; e < K; ++e)
+        if (kb.t[e] > -INFINITY) {
+          if (j < P.k) a.hit_idx[ray * P.k + j] = kb.t[e] < INFINITY ? (int32_t)(kb.id[e] & kIdMask) : -1;
+          ++j;
+        }
+    }
+    if (!(P.flags & LF_FLAG_NO_BACKGROUND)) L = rc.T * env_eval(a.E, d);
+  }
+  const bool trace2 = !(P.flags & LF_FLAG_NO_SECONDARY);
+  for (int s = 0; s < S; ++s) {
+    d3 w = mk(0, 0, 1);
+    double K_ = 0.0;
+    bool live = active && primary_sample(a.E, P, rc, wo, ray, s, c_env, w, K_);
+    d3 thr = mk(0, 0, 0);
+    if (live) thr = (K_ * rc.A / S) * fcos(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags);
+    if (!trace2) {
+      if (live && !replay) {
+        d3 E = env_eval(a.E, w);
+        L = L + mk(thr.x * E.x, thr.y * E.y, thr.z * E.z);
+      }
+      continue;
+    }
+    SecEntry e;
+    if (live) {
+      d3 o2 = rc.x + P.sec_off * rc.n;
+      e.o[0] = o2.x; e.o[1] = o2.y; e.o[2] = o2.z;
+      e.w[0] = w.x; e.w[1] = w.y; e.w[2] = w.z;
+      e.thr[0] = (float)thr.x; e.thr[1] = (float)thr.y; e.thr[2] = (float)thr.z;
+      e.ray = (int32_t)ray;
+      e.s = s;
+      e.pad = 0;
+    }
+    wave_enqueue(live, e, a.queue, a.queue_count);
+    if (active && !live) {
+      int64_t cs = ray * S + s;
+      if (!replay) {
+        a.contrib[3 * cs + 0] = 0.f; a.contrib[3 * cs + 1] = 0.f; a.contrib[3 * cs + 2] = 0.f;
+        if (a.sec_hit_idx)
+          for (int j = 0; j < P.k; ++j) a.sec_hit_idx[cs * P.k + j] = -1;
+      } else {
+        SecFrozen f = {};
+        f.T2 = 1.0f;
+        a.frozen[cs] = f;
+      }
+    }
+  }
+  if (active && !replay) {
+    a.radiance[3 * ray + 0] = (float)L.x;
+    a.radiance[3 * ray + 1] = (float)L.y;
+    a.radiance[3 * ray + 2] = (float)L.z;
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_secondary(RenderArgs a, bool replay) {
+  __shared__ int stk[kStack * kBlock];
+  const uint32_t count = *a.queue_count;
+  const uint32_t qi = blockIdx.x * kBlock + threadIdx.x;
+  if (qi >= count) return;
+  const SecEntry e = a.queue[qi];
+  const TraceParams &P = a.P;
+  d3 o = mk(e.o[0], e.o[1], e.o[2]), w = mk(e.w[0], e.w[1], e.w[2]);
+  KBuf<K> kb;
+  Record r2;
+  trace<K>(a.S, P, o, w, kb, stk + threadIdx.x, a.status);
+  composite<K>(a.S, P, kb, o, w, r2);
+  const double c_env = a.E.scal[1];
+  SecCoef sc;
+  secondary_coefs(a.E, P, r2, w, e.ray, e.s, c_env, sc);
+  const int64_t cs = (int64_t)e.ray * P.spp + e.s;
+  if (replay) {
+    SecFrozen f;
+    f.T2 = (float)r2.T;
+    f.ce[0] = (float)sc.ce.x; f.ce[1] = (float)sc.ce.y; f.ce[2] = (float)sc.ce.z;
+    f.cb[0] = (float)sc.cb.x; f.cb[1] = (float)sc.cb.y; f.cb[2] = (float)sc.cb.z;
+    f.we[0] = (float)sc.we.x; f.we[1] = (float)sc.we.y; f.we[2] = (float)sc.we.z;
+    f.wb[0] = (float)sc.wb.x; f.wb[1] = (float)sc.wb.y; f.wb[2] = (float)sc.wb.z;
+    f.has = (sc.has_e ? 1u : 0u) | (sc.has_b ? 2u : 0u);
+    a.frozen[cs] = f;
+    return;
+  }
+  d3 Lin = r2.T * env_eval(a.E, w);
+  if (sc.has_e) {
+    d3 Ee = env_eval(a.E, sc.we);
+    Lin = Lin + mk(sc.ce.x * Ee.x, sc.ce.y * Ee.y, sc.ce.z * Ee.z);
+  }
+  if (sc.has_b) {
+    d3 Eb = env_eval(a.E, sc.wb);
+    Lin = Lin + mk(sc.cb.x * Eb.x, sc.cb.y * Eb.y, sc.cb.z * Eb.z);
+  }
+  a.contrib[3 * cs + 0] = (float)(e.thr[0] * Lin.x);
+  a.contrib[3 * cs + 1] = (float)(e.thr[1] * Lin.y);
+  a.contrib[3 * cs + 2] = (float)(e.thr[2] * Lin.z);
+  if (a.sec_hit_idx) {
+    int j = 0;
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+      if (kb.t[q] > -INFINITY) {
+        if (j < P.k) a.sec_hit_idx[cs * P.k + j] = kb.t[q] < INFINITY ? (int32_t)(kb.id[q] & kIdMask) : -1;
+        ++j;
+      }
+  }
+}
+
+__global__ void k_resolve(float *radiance, const float *contrib, int64_t R, int S) {
+  int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ray >= R) return;
+  double L[3] = {radiance[3 * ray], radiance[3 * ray + 1], radiance[3 * ray + 2]};
+  for (int s = 0; s < S; ++s)
+    for (int c = 0; c < 3; ++c) L[c] += (double)contrib[3 * (ray * S + s) + c];
+  for (int c = 0; c < 3; ++c) radiance[3 * ray + c] = (float)L[c];
+}
+
+__global__ void k_raygen(const CamArgs *cams, int64_t n, float *o, float *d) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  raygen_f32(*cams, 0, i, o + 3 * i, d + 3 * i);
+}
+
+__global__ __launch_bounds__(256) void k_l1(const float *pred, const float *target, int64_t n, float *grad,
+                                            double *acc) {
+  __shared__ double part[256];
+  double s = 0.0;
+  double inv = 1.0 / (double)n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float d = pred[i] - target[i];
+    s += fabs((double)d);
+    if (grad) grad[i] = (float)((d > 0.f ? 1.0 : (d < 0.f ? -1.0 : 0.0)) * inv);
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(acc, part[0]);
+}
+
+__global__ void k_l1_final(const double *acc, int64_t n, float *loss) { *loss = (float)(*acc / (double)n); }
+__global__ void k_zero_f64(double *p) { *p = 0.0; }
+
+template <int K>
+void primary_k(const RenderArgs &a, bool replay, hipStream_t st) {
+  hipLaunchKernelGGL(k_primary<K>, dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, replay);
+}
+template <int K>
+void secondary_k(const RenderArgs &a, bool replay, hipStream_t st) {
+  int64_t cap = a.R * a.P.spp;
+  hipLaunchKernelGGL(k_secondary<K>, dim3(blocks(cap, kBlock)), dim3(kBlock), 0, st, a, replay);
+}
+
+}  // namespace
+
+void launch_instances(const float *R, const float *t, const float *root_box6, const int32_t *inst_first,
+                      const int32_t *inst_n, const int32_t *inst_root, int n_inst, InstRec *out, uint32_t *status,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_instances, dim3(1), dim3(64), 0, st, R, t, root_box6, inst_first, inst_n, inst_root, n_inst,
+                     out, status);
+}
+
+void launch_env_tables(const float *tex, int H, int W, uint32_t flags, double *cdf_row, double *cdf_col, double *lum,
+                       double *rowsum, double *roww, double *scal, hipStream_t st) {
+  hipLaunchKernelGGL(k_env_rows, dim3(H), dim3(256), 0, st, tex, H, W, cdf_col, lum, rowsum, roww);
+  hipLaunchKernelGGL(k_env_marginal, dim3(1), dim3(256), 0, st, H, flags, roww, cdf_row, scal);
+}
+
+void launch_primary(const RenderArgs &a, bool replay, hipStream_t st) {
+  if (a.R <= 0) return;
+  switch (kbucket(a.P.k)) {
+    case 8: primary_k<8>(a, replay, st); break;
+    case 16: primary_k<16>(a, replay, st); break;
+    case 32: primary_k<32>(a, replay, st); break;
+    default: primary_k<64>(a, replay, st); break;
+  }
+}
+
+void launch_secondary(const RenderArgs &a, bool replay, hipStream_t st) {
+  if (a.R <= 0) return;
+  switch (kbucket(a.P.k)) {
+    case 8: secondary_k<8>(a, replay, st); break;
+    case 16: secondary_k<16>(a, replay, st); break;
+    case 32: secondary_k<32>(a, replay, st); break;
+    default: secondary_k<64>(a, replay, st); break;
+  }
+}
+
+void launch_resolve(const RenderArgs &a, hipStream_t st) {
+  if (a.R <= 0) return;
+  hipLaunchKernelGGL(k_resolve, dim3(blocks(a.R, 256)), dim3(256), 0, st, a.radiance, a.contrib, a.R, a.P.spp);
+}
+
+void launch_raygen(const CamArgs *cams, int64_t n, float *o, float *d, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_raygen, dim3(blocks(n, 256)), dim3(256), 0, st, cams, n, o, d);
+}
+
+void launch_l1(const float *pred, const float *target, int64_t n, float *loss, float *grad, double *acc,
+               hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(1), 0, st, acc);
+  if (n > 0) {
+    unsigned nb = blocks(n, 256);
+    if (nb > 2048) nb = 2048;
+    hipLaunchKernelGGL(k_l1, dim3(nb), dim3(256), 0, st, pred, target, n, grad, acc);
+  }
+  hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(1), 0, st, acc, n > 0 ? n : 1, loss);
+}
+
+}  // namespace lf

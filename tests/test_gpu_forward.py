@@ -1,0 +1,218 @@
+"""GPU parity of the forward path (raygen, traversal, k-closest hit lists,
+compositing, one-bounce shading) against the FP64 oracle, element by element,
+through the C ABI.  Requires an MI355X."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from tests.gpu_common import ambiguous, dev, rel_close, run_oracle, state_args, upload_scene
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-4  # radiance/depth/normal/alpha, relative with floor 1e-3 * mean|ref|
+
+
+@pytest.fixture(scope="module")
+def tracer():
+    import paper_2608_29269_amd as lf
+    return lf.Tracer()
+
+
+def _compare(out, ref, amb, check_sec=False, spp=1):
+    T = out["radiance"].device
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    ok = ~amb
+    assert ok.mean() > 0.99, f"ambiguous fraction {amb.mean():.4f}"
+    np.testing.assert_array_equal(g["hit_idx"][ok], ref["hit_idx"][ok])
+    if check_sec:
+        np.testing.assert_array_equal(g["sec_hit_idx"][ok], ref["sec_hit_idx"][ok])
+    for key in ("radiance", "depth", "normal", "alpha"):
+        e = rel_close(g[key][ok], ref[key][ok], RTOL)
+        assert e < RTOL, (key, e)
+
+
+def test_raygen_is_bitwise_identical(tracer):
+    rng = np.random.default_rng(0)
+    for w, h, fov in ((64, 64, 60.0), (37, 23, 50.0), (800, 800, 60.0), (1024, 1024, 60.0), (5, 300, 110.0)):
+        cam = scenegen.sphere_camera(rng, w, h, fov_y_deg=fov)
+        o, d = tracer.raygen(cam)
+        ro, rd, _ = oracle.raygen(cam)
+        assert np.array_equal(o.cpu().numpy().view(np.uint32), ro.view(np.uint32))
+        assert np.array_equal(d.cpu().numpy().view(np.uint32), rd.view(np.uint32)), (w, h)
+
+
+def test_c1_primary_only_full(tracer):
+    wl = scenegen.make_workload(1)
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    cam = st.cameras[0]
+    out = tracer.render(**state_args(tracer, wl.scene, st), cameras=[cam], k=wl.k, spp=wl.spp, seed=wl.seed,
+                        flags=1, hit_idx=True)
+    o, d, ids = oracle.raygen(cam)
+    ref = run_oracle(wl.scene, st, o, d, ids, wl.k, wl.spp, wl.seed, 1)
+    amb = ambiguous(ref["margins"], include_secondary=False)
+    assert amb.sum() == 0
+    _compare(out, ref, amb)
+
+
+@pytest.mark.parametrize("k", [1, 5, 16, 40, 64])
+def test_k_buckets_and_explicit_rays(tracer, k):
+    wl = scenegen.make_workload(1)
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    o, d, ids = oracle.raygen(st.cameras[0], np.arange(0, 4096, 3))  # 1366 rays: ragged last block
+    out = tracer.render(**state_args(tracer, wl.scene, st), rays=(dev(o), dev(d)), k=k, spp=2, seed=3,
+                        flags=1, hit_idx=True)
+    ref = run_oracle(wl.scene, st, o, d, np.arange(len(o)), k, 2, 3, 1)
+    _compare(out, ref, ambiguous(ref["margins"], False))
+
+
+@pytest.fixture(scope="module")
+def c2_small():
+    return scenegen.make_workload(2, scale=0.1, resolution=96)  # 20k surfels, 96x96
+
+
+def test_bvh_traversal_equals_brute_force(tracer, c2_small):
+    wl = c2_small
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    a = tracer.render(**state_args(tracer, wl.scene, st), cameras=st.cameras, k=32, spp=2, seed=9, hit_idx=True,
+                      sec_hit_idx=True)
+    b = tracer.render(**state_args(tracer, wl.scene, st), cameras=st.cameras, k=32, spp=2, seed=9, hit_idx=True,
+                      sec_hit_idx=True, flags=16)
+    for key in a:
+        assert np.array_equal(a[key].cpu().numpy(), b[key].cpu().numpy()), key
+
+
+def test_c2_one_bounce_parity(tracer, c2_small):
+    wl = c2_small
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    cam = st.cameras[0]
+    spp = 2
+    out = tracer.render(**state_args(tracer, wl.scene, st), cameras=[cam], k=32, spp=spp, seed=wl.seed,
+                        hit_idx=True, sec_hit_idx=True)
+    pix = np.arange(0, cam.w * cam.h, 4)
+    o, d, ids = oracle.raygen(cam, pix)
+    ref = run_oracle(wl.scene, st, o, d, ids, 32, spp, wl.seed, 0)
+    amb = ambiguous(ref["margins"])
+    sub = {k: v[pix] for k, v in out.items()}
+    _compare(sub, ref, amb, check_sec=True, spp=spp)
+    assert (ref["sec_alpha"] > 0).mean() > 0.05  # secondaries really hit geometry
+
+
+def test_instanced_multi_state_parity(tracer):
+    wl = scenegen.make_workload(4, scale=0.02, resolution=64)  # 10k background + 8 x 400
+    upload_scene(tracer, wl.scene)
+    for si, st in enumerate(wl.states[:2]):
+        cam = st.cameras[0]
+        out = tracer.render(**state_args(tracer, wl.scene, st), cameras=[cam], k=32, spp=4, seed=wl.seed + si,
+                            hit_idx=True, sec_hit_idx=True)
+        pix = np.arange(0, cam.w * cam.h, 3)
+        o, d, ids = oracle.raygen(cam, pix)
+        ref = run_oracle(wl.scene, st, o, d, ids, 32, 4, wl.seed + si, 0)
+        sub = {k: v[pix] for k, v in out.items()}
+        _compare(sub, ref, ambiguous(ref["margins"]), check_sec=True, spp=4)
+
+
+def test_forward_is_deterministic(tracer, c2_small):
+    wl = c2_small
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    a = tracer.render(**state_args(tracer, wl.scene, st), cameras=st.cameras, k=32, spp=4, seed=1)
+    b = tracer.render(**state_args(tracer, wl.scene, st), cameras=st.cameras, k=32, spp=4, seed=1)
+    for key in a:
+        assert np.array_equal(a[key].cpu().numpy(), b[key].cpu().numpy()), key
+
+
+def test_flags_furnace_on_gpu(tracer):
+    # floor + roof, white Lambert, constant env: every sample returns a_bar * L_in (zero variance)
+    from tests.helpers import make_scene
+    sc = make_scene([[0, 0, 0], [0, 0, 0.5]], scale=[[10, 10]] * 2, opacity=[1, 1], albedo=[[1, 1, 1]] * 2,
+                    metallic=[0, 0])
+    upload_scene(tracer, sc)
+    n = 300
+    o = np.tile([[0.0, 0.0, 0.25]], (n, 1)).astype(np.float32)
+    d = np.tile([[0.0, 0.0, -1.0]], (n, 1)).astype(np.float32)
+    env = scenegen.constant_env(1.0, 8, 16)
+    out = tracer.render(env=dev(env), rays=(dev(o), dev(d)), k=8, spp=2, seed=4, flags=4 | 8)
+    L = out["radiance"].cpu().numpy()
+    assert np.all(np.abs(L - 1.0) < 1e-5)
+    st = scenegen.State(R=np.zeros((0, 3, 3), np.float32), t=np.zeros((0, 3), np.float32), env=env, cameras=[])
+    ref = run_oracle(sc, st, o, d, np.arange(n), 8, 2, 4, 4 | 8)
+    assert rel_close(L, ref["radiance"], 1e-6) < 1e-6
+
+
+def test_edge_cases(tracer):
+    from tests.helpers import make_scene
+    import paper_2608_29269_amd as lf
+    sc = make_scene([[0, 0, 0]], scale=[[0.3, 0.2]], opacity=[0.8])
+    upload_scene(tracer, sc)
+    env = dev(scenegen.lognormal_env(np.random.default_rng(1), 16, 32))
+    # empty ray batch
+    z = dev(np.zeros((0, 3), np.float32))
+    out = tracer.render(env=env, rays=(z, z), k=4, spp=1)
+    assert out["radiance"].shape[0] == 0
+    # all rays miss: radiance = E(d), alpha = depth = 0, normal = 0
+    o = np.tile([[5.0, 5.0, 5.0]], (10, 1)).astype(np.float32)
+    d = np.tile([[0.0, 1.0, 0.0]], (10, 1)).astype(np.float32)
+    out = tracer.render(env=env, rays=(dev(o), dev(d)), k=4, spp=3, seed=2)
+    assert np.all(out["alpha"].cpu().numpy() == 0) and np.all(out["normal"].cpu().numpy() == 0)
+    Ed = oracle.env_lookup(env.cpu().numpy(), [0, 1.0, 0])
+    np.testing.assert_allclose(out["radiance"].cpu().numpy(), np.tile(Ed, (10, 1)), rtol=1e-6)
+    # invalid arguments are rejected synchronously
+    with pytest.raises(lf.LFError):
+        tracer.render(env=env, rays=(dev(o), dev(d)), k=0, spp=1)
+    with pytest.raises(lf.LFError):
+        tracer.render(env=env, rays=(dev(o), dev(d)), k=4, spp=0)
+    with pytest.raises(lf.LFError):
+        tracer.render(env=env, rays=(dev(o), dev(d)), k=65, spp=1)
+    tracer.sync()
+
+
+def test_bvh_structure_and_refit(tracer, c2_small):
+    wl = c2_small
+    ts = upload_scene(tracer, wl.scene)
+    info = tracer.info()
+    assert info["max_depth"] <= info["stack_size"]
+
+    def check():
+        boxes, ch, perm, leaf = tracer.copy_bvh(0)
+        n = wl.scene.n
+        assert sorted(perm.tolist()) == list(range(n))
+        # re-union from the leaves equals the stored child boxes exactly
+        def union(c):
+            if c < 0:
+                return leaf[~c]
+            b = boxes[c]
+            return np.concatenate([np.minimum(b[0, :3], b[1, :3]), np.maximum(b[0, 3:], b[1, 3:])])
+        seen = np.zeros(n, int)
+        stack = [0]
+        while stack:
+            i = stack.pop()
+            for s in range(2):
+                c = ch[i, s]
+                if c < 0:
+                    seen[~c] += 1
+                    assert np.array_equal(boxes[i, s], leaf[~c])
+                else:
+                    assert np.array_equal(boxes[i, s], union(c))
+                    stack.append(c)
+        assert np.all(seen == 1)
+    check()
+    # in-place update + refit keeps the hierarchy valid and matches the oracle
+    rng = np.random.default_rng(3)
+    ts["mu"] += 0.01 * dev(rng.standard_normal((wl.scene.n, 3)).astype(np.float32))
+    tracer.refit()
+    check()
+    moved = wl.scene.copy()
+    moved.mu = ts["mu"].cpu().numpy()
+    st = wl.states[0]
+    cam = st.cameras[0]
+    out = tracer.render(**state_args(tracer, moved, st), cameras=[cam], k=32, spp=1, seed=5, hit_idx=True,
+                        flags=1)
+    pix = np.arange(0, cam.w * cam.h, 5)
+    o, d, ids = oracle.raygen(cam, pix)
+    ref = run_oracle(moved, st, o, d, ids, 32, 1, 5, 1)
+    _compare({k: v[pix] for k, v in out.items()}, ref, ambiguous(ref["margins"], False))
