@@ -211,6 +211,26 @@ lf_status lf_scene_get_info(lf_ctx *ctx, lf_scene_info *info);
 lf_status lf_scene_copy_bvh(lf_ctx *ctx, int32_t inst, float *node_boxes, int32_t *children, int32_t *perm,
                             float *leaf_boxes);
 
+/* Rays traced by lf_render calls since the previous lf_stats_get: primary
+ * rays and secondary rays actually traced (live samples).  Accumulated on the
+ * device without synchronisation; lf_stats_get synchronises, returns and
+ * resets them.  Replay passes of lf_render_backward are not counted. */
+typedef struct {
+  int64_t rays_primary;
+  int64_t rays_secondary;
+} lf_render_stats;
+lf_status lf_stats_get(lf_ctx *ctx, lf_render_stats *stats);
+
+/* Per-phase device timers.  When enabled, every phase below is bracketed by
+ * HIP events on the context's stream; lf_profile_read synchronises, returns
+ * the accumulated milliseconds and launch counts per phase and resets them.
+ * Phases: 0 refit, 1 state and environment tables, 2 primary, 3 secondary,
+ * 4 resolve, 5 replay primary, 6 replay secondary, 7 adjoint, 8 gradient
+ * zeroing, 9 loss. */
+#define LF_NUM_PHASES 10
+lf_status lf_profile_enable(lf_ctx *ctx, int enable);
+lf_status lf_profile_read(lf_ctx *ctx, double *ms /*[LF_NUM_PHASES]*/, int64_t *count /*[LF_NUM_PHASES]*/);
+
 #ifdef __cplusplus
 }
 #endif

@@ -211,6 +211,9 @@ def backward(sa: SceneArrays, o, d, ids, p: Params, g_radiance=None, g_depth=Non
     keep, r = _rays(o, d, ids)
     n = sa.mu.shape[0]
     ups = [None if a is None else _d(a) for a in (g_radiance, g_depth, g_normal, g_alpha)]
+    for a, shape in zip(ups, ((r.n, 3), (r.n,), (r.n, 3), (r.n,))):
+        if a is not None and a.shape != shape:
+            raise ValueError(f"upstream gradient of shape {a.shape}, expected {shape}")
     up = _Upstream(*[_ptr(a) for a in ups])
     g = dict(mu=np.zeros((n, 3)), q=np.zeros((n, 4)), scale=np.zeros((n, 2)), opacity=np.zeros(n),
              albedo=np.zeros((n, 3)), roughness=np.zeros(n), metallic=np.zeros(n), env=np.zeros(sa.env.shape))

@@ -205,6 +205,20 @@ class Tracer:
     def sync(self):
         self._chk(self.L.lf_sync(self.ctx))
 
+    def stats(self) -> dict:
+        st = _lib.RenderStats()
+        self._chk(self.L.lf_stats_get(self.ctx, C.byref(st)))
+        return dict(rays_primary=st.rays_primary, rays_secondary=st.rays_secondary)
+
+    def profile(self, enable: bool = True):
+        self._chk(self.L.lf_profile_enable(self.ctx, int(enable)))
+
+    def profile_read(self) -> dict:
+        ms = (C.c_double * _lib.NUM_PHASES)()
+        n = (C.c_int64 * _lib.NUM_PHASES)()
+        self._chk(self.L.lf_profile_read(self.ctx, ms, n))
+        return {name: (ms[i], n[i]) for i, name in enumerate(_lib.PHASES)}
+
 
 def _render_fn():
     import torch

@@ -76,6 +76,14 @@ class SceneInfo(C.Structure):
                 ("max_depth", C.c_int32), ("stack_size", C.c_int32)]
 
 
+class RenderStats(C.Structure):
+    _fields_ = [("rays_primary", C.c_int64), ("rays_secondary", C.c_int64)]
+
+
+NUM_PHASES = 10
+PHASES = ("refit", "state_env", "primary", "secondary", "resolve", "replay_primary", "replay_secondary",
+          "adjoint", "zero_grads", "loss")
+
 # every symbol include/lightfuse.h declares, with its ctypes signature
 SIGNATURES = {
     "lf_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
@@ -94,6 +102,9 @@ SIGNATURES = {
     "lf_raygen": (C.c_int, [C.c_void_p, C.POINTER(Camera), C.c_void_p, C.c_void_p]),
     "lf_scene_get_info": (C.c_int, [C.c_void_p, C.POINTER(SceneInfo)]),
     "lf_scene_copy_bvh": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lf_stats_get": (C.c_int, [C.c_void_p, C.POINTER(RenderStats)]),
+    "lf_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "lf_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
 
 _lib = None

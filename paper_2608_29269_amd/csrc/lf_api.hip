@@ -64,6 +64,15 @@ struct lf_ctx {
   DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;
   DevBuf queue, qcount, contrib, frozen, l1acc, cams;
   lf::CamArgs h_cams{};
+  // ray counters since the last lf_stats_get
+  int64_t acc_primary = 0;
+  DevBuf acc_secondary;
+  // phase timers
+  bool profiling = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<hipEvent_t> pool;
+  double prof_ms[LF_NUM_PHASES] = {};
+  int64_t prof_n[LF_NUM_PHASES] = {};
 };
 
 namespace {
@@ -88,7 +97,40 @@ lf_status check_hip(lf_ctx *c, const char *where) {
 
 bool set_device(lf_ctx *c) { return hipSetDevice(c->device) == hipSuccess; }
 
+hipEvent_t take_event(lf_ctx *c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// Brackets one phase with events when profiling is enabled.
+struct Phase {
+  lf_ctx *c;
+  int id;
+  hipEvent_t a = nullptr, b = nullptr;
+  Phase(lf_ctx *c_, int id_) : c(c_), id(id_) {
+    if (!c->profiling) return;
+    a = take_event(c);
+    b = take_event(c);
+    if (a) (void)hipEventRecord(a, c->stream);
+  }
+  ~Phase() {
+    if (!c->profiling || !a || !b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({id, {a, b}});
+  }
+};
+
 lf_status refit_impl(lf_ctx *c, double alpha_min, double sig2) {
+  Phase ph(c, 0);
   lf::launch_refit(c->s, alpha_min, sig2, c->perm.as<int32_t>(), c->leaf_parent.as<int32_t>(),
                    c->node_parent.as<int32_t>(), c->flags.as<int32_t>(), c->n_nodes, c->n_inst,
                    c->nodes.as<lf::BNode>(), c->rec.as<lf::TraceRec>(), c->leafbox.as<float>(),
@@ -161,6 +203,7 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
     if ((st = refit_impl(c, p->alpha_min, sig2))) return st;
   }
   // state assembly: instance records for this state's transforms
+  Phase ph(c, 1);
   lf::launch_instances(M > 0 ? xf->R : nullptr, M > 0 ? xf->t : nullptr, c->rootbox.as<float>(),
                        c->d_first.as<int32_t>(), c->d_n.as<int32_t>(), c->d_root.as<int32_t>(), c->n_inst,
                        c->inst.as<lf::InstRec>(), c->status.as<uint32_t>(), c->stream);
@@ -242,11 +285,12 @@ lf_status lf_create(lf_ctx **out, int device, void *hip_stream) {
   lf_ctx *c = new lf_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
-  if (!set_device(c) || !c->status.ensure(sizeof(uint32_t))) {
+  if (!set_device(c) || !c->status.ensure(sizeof(uint32_t)) || !c->acc_secondary.ensure(8)) {
     delete c;
     return LF_EDEVICE;
   }
   lf::launch_fill_u32(c->status.as<uint32_t>(), 0u, 1, c->stream);
+  lf::launch_fill_u32(c->acc_secondary.as<uint32_t>(), 0u, 2, c->stream);
   if (check_hip(c, "create")) {
     delete c;
     return LF_EDEVICE;
@@ -260,6 +304,11 @@ void lf_destroy(lf_ctx *c) {
   set_device(c);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
+  for (auto &pe : c->pending) {
+    (void)hipEventDestroy(pe.second.first);
+    (void)hipEventDestroy(pe.second.second);
+  }
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -393,11 +442,20 @@ lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, co
   } else if (out->sec_hit_idx) {
     lf::launch_fill_u32((uint32_t *)out->sec_hit_idx, 0xffffffffu, a.R * p->spp * p->k, c->stream);
   }
-  lf::launch_primary(a, false, c->stream);
-  if (trace2) {
-    lf::launch_secondary(a, false, c->stream);
-    lf::launch_resolve(a, c->stream);
+  {
+    Phase ph(c, 2);
+    lf::launch_primary(a, false, c->stream);
   }
+  if (trace2) {
+    {
+      Phase ph(c, 3);
+      lf::launch_secondary(a, false, c->stream);
+    }
+    Phase ph(c, 4);
+    lf::launch_resolve(a, c->stream);
+    lf::launch_accum(c->acc_secondary.as<unsigned long long>(), a.queue_count, c->stream);
+  }
+  c->acc_primary += a.R;
   return check_hip(c, "render");
 }
 
@@ -415,25 +473,36 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
   if (st) return st;
   const int64_t n = c->s.n;
   hipStream_t s = c->stream;
-  lf::launch_fill_f32(gi->d_mu, 0.f, 3 * n, s);
-  lf::launch_fill_f32(gi->d_q, 0.f, 4 * n, s);
-  lf::launch_fill_f32(gi->d_scale, 0.f, 2 * n, s);
-  lf::launch_fill_f32(gi->d_opacity, 0.f, n, s);
-  lf::launch_fill_f32(gi->d_albedo, 0.f, 3 * n, s);
-  lf::launch_fill_f32(gi->d_roughness, 0.f, n, s);
-  lf::launch_fill_f32(gi->d_metallic, 0.f, n, s);
-  lf::launch_fill_f32(gi->d_env, 0.f, (int64_t)3 * env->h * env->w, s);
+  {
+    Phase ph0(c, 8);
+    lf::launch_fill_f32(gi->d_mu, 0.f, 3 * n, s);
+    lf::launch_fill_f32(gi->d_q, 0.f, 4 * n, s);
+    lf::launch_fill_f32(gi->d_scale, 0.f, 2 * n, s);
+    lf::launch_fill_f32(gi->d_opacity, 0.f, n, s);
+    lf::launch_fill_f32(gi->d_albedo, 0.f, 3 * n, s);
+    lf::launch_fill_f32(gi->d_roughness, 0.f, n, s);
+    lf::launch_fill_f32(gi->d_metallic, 0.f, n, s);
+    lf::launch_fill_f32(gi->d_env, 0.f, (int64_t)3 * env->h * env->w, s);
+  }
+
   if (a.R == 0) return check_hip(c, "backward");
   const bool trace2 = !(p->flags & LF_FLAG_NO_SECONDARY);
   if (trace2) {
     if (!c->frozen.ensure(sizeof(lf::SecFrozen) * a.R * p->spp)) return fail(c, LF_ENOMEM, "frozen records");
     a.frozen = c->frozen.as<lf::SecFrozen>();
-    lf::launch_primary(a, true, s);
+    {
+      Phase ph(c, 5);
+      lf::launch_primary(a, true, s);
+    }
+    Phase ph(c, 6);
     lf::launch_secondary(a, true, s);
   }
   lf::GradArgs ga{g->d_radiance, g->d_depth, g->d_normal, g->d_alpha, gi->d_mu, gi->d_q, gi->d_scale,
                   gi->d_opacity, gi->d_albedo, gi->d_roughness, gi->d_metallic, gi->d_env};
-  lf::launch_adjoint(a, ga, s);
+  {
+    Phase ph(c, 7);
+    lf::launch_adjoint(a, ga, s);
+  }
   return check_hip(c, "backward");
 }
 
@@ -442,6 +511,7 @@ lf_status lf_l1_loss(lf_ctx *c, const float *pred, const float *target, int64_t 
   if (!pred || !target || !loss || n < 0) return fail(c, LF_EINVAL, "invalid loss arguments");
   set_device(c);
   if (!c->l1acc.ensure(sizeof(double))) return fail(c, LF_ENOMEM, "loss accumulator");
+  Phase ph(c, 9);
   lf::launch_l1(pred, target, n, loss, grad, c->l1acc.as<double>(), c->stream);
   return check_hip(c, "l1 loss");
 }
@@ -464,6 +534,52 @@ lf_status lf_raygen(lf_ctx *c, const lf_camera *cam, float *o, float *d) {
     return check_hip(c, "camera upload");
   lf::launch_raygen(c->cams.as<lf::CamArgs>(), (int64_t)cam->w * cam->h, o, d, c->stream);
   return check_hip(c, "raygen");
+}
+
+lf_status lf_stats_get(lf_ctx *c, lf_render_stats *st) {
+  if (!c) return LF_EINVAL;
+  if (!st) return fail(c, LF_EINVAL, "stats is NULL");
+  set_device(c);
+  unsigned long long q = 0;
+  if (hipStreamSynchronize(c->stream) != hipSuccess ||
+      hipMemcpy(&q, c->acc_secondary.p, sizeof q, hipMemcpyDeviceToHost) != hipSuccess)
+    return check_hip(c, "stats");
+  st->rays_primary = c->acc_primary;
+  st->rays_secondary = (int64_t)q;
+  c->acc_primary = 0;
+  lf::launch_fill_u32(c->acc_secondary.as<uint32_t>(), 0u, 2, c->stream);
+  return check_hip(c, "stats");
+}
+
+lf_status lf_profile_enable(lf_ctx *c, int enable) {
+  if (!c) return LF_EINVAL;
+  c->profiling = enable != 0;
+  return LF_OK;
+}
+
+lf_status lf_profile_read(lf_ctx *c, double *ms, int64_t *count) {
+  if (!c) return LF_EINVAL;
+  if (!ms || !count) return fail(c, LF_EINVAL, "profile outputs are NULL");
+  set_device(c);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "profile");
+  for (auto &pe : c->pending) {
+    float t = 0.f;
+    if (pe.first >= 0 && hipEventElapsedTime(&t, pe.second.first, pe.second.second) == hipSuccess) {
+      c->prof_ms[pe.first] += t;
+      c->prof_n[pe.first] += 1;
+    }
+    (void)hipGetLastError();
+    c->pool.push_back(pe.second.first);
+    c->pool.push_back(pe.second.second);
+  }
+  c->pending.clear();
+  for (int i = 0; i < LF_NUM_PHASES; ++i) {
+    ms[i] = c->prof_ms[i];
+    count[i] = c->prof_n[i];
+    c->prof_ms[i] = 0.0;
+    c->prof_n[i] = 0;
+  }
+  return LF_OK;
 }
 
 lf_status lf_scene_get_info(lf_ctx *c, lf_scene_info *info) {

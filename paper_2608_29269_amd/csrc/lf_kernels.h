@@ -62,6 +62,7 @@ struct RenderArgs {
 void launch_primary(const RenderArgs &a, bool replay, hipStream_t st);
 void launch_secondary(const RenderArgs &a, bool replay, hipStream_t st);
 void launch_resolve(const RenderArgs &a, hipStream_t st);
+void launch_accum(unsigned long long *acc, const uint32_t *count, hipStream_t st);
 void launch_raygen(const CamArgs *cams, int64_t n, float *o, float *d, hipStream_t st);
 void launch_l1(const float *pred, const float *target, int64_t n, float *loss, float *grad, double *acc,
                hipStream_t st);

@@ -345,6 +345,8 @@ __global__ __launch_bounds__(256) void k_l1(const float *pred, const float *targ
   if (threadIdx.x == 0) atomicAdd(acc, part[0]);
 }
 
+__global__ void k_accum(unsigned long long *acc, const uint32_t *count) { *acc += *count; }
+
 __global__ void k_l1_final(const double *acc, int64_t n, float *loss) { *loss = (float)(*acc / (double)n); }
 __global__ void k_zero_f64(double *p) { *p = 0.0; }
 
@@ -401,6 +403,10 @@ void launch_resolve(const RenderArgs &a, hipStream_t st) {
 void launch_raygen(const CamArgs *cams, int64_t n, float *o, float *d, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_raygen, dim3(blocks(n, 256)), dim3(256), 0, st, cams, n, o, d);
+}
+
+void launch_accum(unsigned long long *acc, const uint32_t *count, hipStream_t st) {
+  hipLaunchKernelGGL(k_accum, dim3(1), dim3(1), 0, st, acc, count);
 }
 
 void launch_l1(const float *pred, const float *target, int64_t n, float *loss, float *grad, double *acc,
