@@ -118,6 +118,7 @@ typedef struct {
 #define LF_FLAG_BSDF_ONLY     (1u << 2) /* sample only the cosine/GGX mixture (no env importance sampling) */
 #define LF_FLAG_DIFFUSE_ONLY  (1u << 3) /* Lambert lobe only */
 #define LF_FLAG_BRUTE_FORCE   (1u << 4) /* test every surfel of every instance (no BVH); for testing */
+#define LF_FLAG_COUNT         (1u << 5) /* accumulate traversal counters (lf_trace_counters) */
 
 /* Tracing and estimator parameters.  Readings of points the paper leaves
  * open (Sec. 3.2 "finite support", "opacity threshold", epsilon of
@@ -220,6 +221,12 @@ typedef struct {
   int64_t rays_secondary;
 } lf_render_stats;
 lf_status lf_stats_get(lf_ctx *ctx, lf_render_stats *stats);
+
+/* Traversal counters accumulated by calls made with LF_FLAG_COUNT since the
+ * previous read (synchronous; resets them): [0] primary rays, [1] internal
+ * nodes visited, [2] surfels tested, [3] hits inserted into k-buffers, then
+ * [4..7] the same for secondary rays. */
+lf_status lf_trace_counters(lf_ctx *ctx, uint64_t *counters /*[8]*/);
 
 /* Per-phase device timers.  When enabled, every phase below is bracketed by
  * HIP events on the context's stream; lf_profile_read synchronises, returns

@@ -17,7 +17,7 @@ import ctypes as C
 from typing import Optional, Sequence
 
 from . import _lib
-from ._lib import (FLAG_BRUTE_FORCE, FLAG_BSDF_ONLY, FLAG_DIFFUSE_ONLY, FLAG_NO_BACKGROUND, FLAG_NO_SECONDARY,
+from ._lib import (FLAG_BRUTE_FORCE, FLAG_COUNT, FLAG_BSDF_ONLY, FLAG_DIFFUSE_ONLY, FLAG_NO_BACKGROUND, FLAG_NO_SECONDARY,
                    LFError)
 
 __all__ = ["Tracer", "RenderFn", "LFError", "FLAG_NO_SECONDARY", "FLAG_NO_BACKGROUND", "FLAG_BSDF_ONLY",
@@ -209,6 +209,12 @@ class Tracer:
         st = _lib.RenderStats()
         self._chk(self.L.lf_stats_get(self.ctx, C.byref(st)))
         return dict(rays_primary=st.rays_primary, rays_secondary=st.rays_secondary)
+
+    def trace_counters(self) -> dict:
+        c = (C.c_uint64 * 8)()
+        self._chk(self.L.lf_trace_counters(self.ctx, c))
+        keys = ("rays", "nodes", "tests", "inserts")
+        return {"primary": dict(zip(keys, c[:4])), "secondary": dict(zip(keys, c[4:]))}
 
     def profile(self, enable: bool = True):
         self._chk(self.L.lf_profile_enable(self.ctx, int(enable)))

@@ -20,6 +20,7 @@ FLAG_NO_BACKGROUND = 1 << 1
 FLAG_BSDF_ONLY = 1 << 2
 FLAG_DIFFUSE_ONLY = 1 << 3
 FLAG_BRUTE_FORCE = 1 << 4
+FLAG_COUNT = 1 << 5
 MAX_CAMERAS = 16
 
 _fp = C.POINTER(C.c_float)
@@ -104,6 +105,7 @@ SIGNATURES = {
     "lf_scene_copy_bvh": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lf_stats_get": (C.c_int, [C.c_void_p, C.POINTER(RenderStats)]),
     "lf_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "lf_trace_counters": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
     "lf_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
 

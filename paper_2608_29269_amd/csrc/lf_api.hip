@@ -58,15 +58,15 @@ struct lf_ctx {
   int32_t max_depth = 0;
   double built_alpha_min = 0, built_sig2 = 0;
   DevBuf d_first, d_n, d_root;
-  DevBuf rec, nodes, perm, leaf_parent, node_parent, flags, leafbox, rootbox, inst, status;
+  DevBuf rec, filt, nodes, perm, leaf_parent, node_parent, flags, leafbox, rootbox, inst, status;
   DevBuf keys, keys2, vals2, hist, boxidx, ibounds, depth;
   // per call
   DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;
-  DevBuf queue, qcount, contrib, frozen, l1acc, cams;
+  DevBuf queue, qcount, contrib, frozen, l1acc, cams, rec1, rec2, retry, rcount, seeds;
   lf::CamArgs h_cams{};
   // ray counters since the last lf_stats_get
   int64_t acc_primary = 0;
-  DevBuf acc_secondary;
+  DevBuf acc_secondary, counters;
   // phase timers
   bool profiling = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
@@ -133,8 +133,8 @@ lf_status refit_impl(lf_ctx *c, double alpha_min, double sig2) {
   Phase ph(c, 0);
   lf::launch_refit(c->s, alpha_min, sig2, c->perm.as<int32_t>(), c->leaf_parent.as<int32_t>(),
                    c->node_parent.as<int32_t>(), c->flags.as<int32_t>(), c->n_nodes, c->n_inst,
-                   c->nodes.as<lf::BNode>(), c->rec.as<lf::TraceRec>(), c->leafbox.as<float>(),
-                   c->rootbox.as<float>(), c->status.as<uint32_t>(), c->stream);
+                   c->nodes.as<lf::BNode>(), c->rec.as<lf::TraceRec>(), c->filt.as<lf::FiltRec>(),
+                   c->leafbox.as<float>(), c->rootbox.as<float>(), c->status.as<uint32_t>(), c->stream);
   c->built_alpha_min = alpha_min;
   c->built_sig2 = sig2;
   return check_hip(c, "refit");
@@ -147,7 +147,7 @@ lf_status validate_params(lf_ctx *c, const lf_params *p) {
   if (!(p->alpha_min > 0.0) || !(p->alpha_cap > 0.0 && p->alpha_cap < 1.0) || !(p->support_sigma > 0.0) ||
       !(p->eps >= 0.0) || !(p->t_min >= 0.0) || !std::isfinite(p->secondary_offset))
     return fail(c, LF_EINVAL, "invalid tracing constants");
-  if (p->flags & ~0x1Fu) return fail(c, LF_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~0x3Fu) return fail(c, LF_EINVAL, "unknown flags 0x%x", p->flags);
   return LF_OK;
 }
 
@@ -217,6 +217,7 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
                         c->env_lum.as<double>(), c->env_rowsum.as<double>(), c->env_roww.as<double>(),
                         c->env_scal.as<double>(), c->stream);
   a.S.rec = c->rec.as<lf::TraceRec>();
+  a.S.filt = c->filt.as<lf::FiltRec>();
   a.S.nodes = c->nodes.as<lf::BNode>();
   a.S.inst = c->inst.as<lf::InstRec>();
   a.S.n_inst = c->n_inst;
@@ -234,6 +235,7 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
   a.P.t_min = p->t_min;
   a.P.sec_off = p->secondary_offset;
   a.P.flags = p->flags;
+  a.P.counters = (p->flags & LF_FLAG_COUNT) ? c->counters.as<unsigned long long>() : nullptr;
   a.E.tex = env->texels;
   a.E.H = H;
   a.E.W = W;
@@ -245,12 +247,21 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
   a.E.scal = c->env_scal.as<double>();
   a.status = c->status.as<uint32_t>();
   const bool trace2 = !(p->flags & LF_FLAG_NO_SECONDARY);
-  int64_t RS = R * p->spp;
+  const int64_t RS = R * p->spp;
+  const int64_t R1 = R > 0 ? R : 1;
+  if (!c->rec1.ensure(sizeof(lf::SurfRec) * R1) || !c->rcount.ensure(sizeof(uint32_t)) ||
+      !c->retry.ensure(sizeof(int32_t) * (trace2 && RS > R1 ? RS : R1)))
+    return fail(c, LF_ENOMEM, "surface records");
+  a.rec1 = c->rec1.as<lf::SurfRec>();
+  a.retry = c->retry.as<int32_t>();
+  a.retry_count = c->rcount.as<uint32_t>();
   if (trace2) {
-    if (!c->queue.ensure(sizeof(lf::SecEntry) * (RS > 0 ? RS : 1)) || !c->qcount.ensure(sizeof(uint32_t)))
+    if (!c->queue.ensure(sizeof(lf::SecEntry) * (RS > 0 ? RS : 1)) || !c->qcount.ensure(sizeof(uint32_t)) ||
+        !c->rec2.ensure(sizeof(lf::SurfRec) * (RS > 0 ? RS : 1)))
       return fail(c, LF_ENOMEM, "secondary queue");
     a.queue = c->queue.as<lf::SecEntry>();
     a.queue_count = c->qcount.as<uint32_t>();
+    a.rec2 = c->rec2.as<lf::SurfRec>();
     lf::launch_fill_u32(a.queue_count, 0u, 1, c->stream);
   }
   return check_hip(c, "prepare");
@@ -285,12 +296,14 @@ lf_status lf_create(lf_ctx **out, int device, void *hip_stream) {
   lf_ctx *c = new lf_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
-  if (!set_device(c) || !c->status.ensure(sizeof(uint32_t)) || !c->acc_secondary.ensure(8)) {
+  if (!set_device(c) || !c->status.ensure(sizeof(uint32_t)) || !c->acc_secondary.ensure(8) ||
+      !c->counters.ensure(64)) {
     delete c;
     return LF_EDEVICE;
   }
   lf::launch_fill_u32(c->status.as<uint32_t>(), 0u, 1, c->stream);
   lf::launch_fill_u32(c->acc_secondary.as<uint32_t>(), 0u, 2, c->stream);
+  lf::launch_fill_u32(c->counters.as<uint32_t>(), 0u, 16, c->stream);
   if (check_hip(c, "create")) {
     delete c;
     return LF_EDEVICE;
@@ -365,7 +378,7 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
   c->n_nodes = nodes;
   const int64_t n = sf->n;
   bool ok = c->d_first.ensure(4 * n_inst) && c->d_n.ensure(4 * n_inst) && c->d_root.ensure(4 * n_inst) &&
-            c->rec.ensure(sizeof(lf::TraceRec) * n) && c->nodes.ensure(sizeof(lf::BNode) * (nodes ? nodes : 1)) &&
+            c->rec.ensure(sizeof(lf::TraceRec) * n) && c->filt.ensure(sizeof(lf::FiltRec) * n) && c->nodes.ensure(sizeof(lf::BNode) * (nodes ? nodes : 1)) &&
             c->perm.ensure(4 * n) && c->leaf_parent.ensure(4 * n) && c->node_parent.ensure(4 * (nodes ? nodes : 1)) &&
             c->flags.ensure(4 * (nodes ? nodes : 1)) && c->leafbox.ensure(24 * n) &&
             c->rootbox.ensure(24 * n_inst) && c->inst.ensure(sizeof(lf::InstRec) * n_inst) &&
@@ -444,12 +457,14 @@ lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, co
   }
   {
     Phase ph(c, 2);
-    lf::launch_primary(a, false, c->stream);
+    lf::launch_trace1(a, false, c->stream);
+    lf::launch_shade1(a, false, c->stream);
   }
   if (trace2) {
     {
       Phase ph(c, 3);
-      lf::launch_secondary(a, false, c->stream);
+      lf::launch_trace2(a, c->stream);
+      lf::launch_shade2(a, false, c->stream);
     }
     Phase ph(c, 4);
     lf::launch_resolve(a, c->stream);
@@ -487,21 +502,27 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
 
   if (a.R == 0) return check_hip(c, "backward");
   const bool trace2 = !(p->flags & LF_FLAG_NO_SECONDARY);
+  if (!c->seeds.ensure(sizeof(lf::AdjSeed) * a.R)) return fail(c, LF_ENOMEM, "adjoint seeds");
+  a.seeds = c->seeds.as<lf::AdjSeed>();
+  if (trace2 && !c->frozen.ensure(sizeof(lf::SecFrozen) * a.R * p->spp))
+    return fail(c, LF_ENOMEM, "frozen records");
+  a.frozen = trace2 ? c->frozen.as<lf::SecFrozen>() : nullptr;
+  {
+    Phase ph(c, 5);
+    lf::launch_trace1(a, true, s);
+    if (trace2) lf::launch_shade1(a, true, s);
+  }
   if (trace2) {
-    if (!c->frozen.ensure(sizeof(lf::SecFrozen) * a.R * p->spp)) return fail(c, LF_ENOMEM, "frozen records");
-    a.frozen = c->frozen.as<lf::SecFrozen>();
-    {
-      Phase ph(c, 5);
-      lf::launch_primary(a, true, s);
-    }
     Phase ph(c, 6);
-    lf::launch_secondary(a, true, s);
+    lf::launch_trace2(a, s);
+    lf::launch_shade2(a, true, s);
   }
   lf::GradArgs ga{g->d_radiance, g->d_depth, g->d_normal, g->d_alpha, gi->d_mu, gi->d_q, gi->d_scale,
                   gi->d_opacity, gi->d_albedo, gi->d_roughness, gi->d_metallic, gi->d_env};
   {
     Phase ph(c, 7);
-    lf::launch_adjoint(a, ga, s);
+    lf::launch_adjoint_shade(a, ga, s);
+    lf::launch_adjoint_trace(a, ga, s);
   }
   return check_hip(c, "backward");
 }
@@ -549,6 +570,17 @@ lf_status lf_stats_get(lf_ctx *c, lf_render_stats *st) {
   c->acc_primary = 0;
   lf::launch_fill_u32(c->acc_secondary.as<uint32_t>(), 0u, 2, c->stream);
   return check_hip(c, "stats");
+}
+
+lf_status lf_trace_counters(lf_ctx *c, uint64_t *out) {
+  if (!c) return LF_EINVAL;
+  if (!out) return fail(c, LF_EINVAL, "counters output is NULL");
+  set_device(c);
+  if (hipStreamSynchronize(c->stream) != hipSuccess ||
+      hipMemcpy(out, c->counters.p, 64, hipMemcpyDeviceToHost) != hipSuccess)
+    return check_hip(c, "counters");
+  lf::launch_fill_u32(c->counters.as<uint32_t>(), 0u, 16, c->stream);
+  return check_hip(c, "counters");
 }
 
 lf_status lf_profile_enable(lf_ctx *c, int enable) {

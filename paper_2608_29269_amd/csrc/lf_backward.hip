@@ -16,6 +16,20 @@ namespace {
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+__device__ __forceinline__ void wave_append_i32(bool live, int32_t v, int32_t *list, uint32_t *count) {
+  uint64_t mask = __ballot(live);
+  if (mask == 0) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader);
+  if (live) {
+    uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
+    list[base + (uint32_t)__popcll(mask & lt)] = v;
+  }
+}
+
 __device__ __forceinline__ void env_scatter(const EnvView &E, float *genv, d3 w, d3 g) {
   Taps tp;
   env_taps(E, w, tp);
@@ -69,33 +83,38 @@ __device__ __forceinline__ void fcos_bwd(d3 n, d3 wi, d3 wo, d3 a, double m, dou
   gn = gn + gci * wi;
 }
 
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_adjoint(RenderArgs a, GradArgs G) {
-  __shared__ int stk[kStack * kBlock];
-  const int64_t ray = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+// ---------------------------------------------------------------- shading adjoint
+// Per primary ray: reverse of L = A * mean_s F_s + T * E(d) with
+// F_s = K_s f(w_s) (n.w_s) (T2 E(w_s) + ce E(w_e) + cb E(w_b)); environment
+// gradients are scattered here, and the adjoints of the surface record are
+// reduced to the seeds of the compositing adjoint.
+__global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G) {
+  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ray >= a.R) return;
   const TraceParams &P = a.P;
   const int S = P.spp;
   float of[3], df[3];
   load_ray(a.rays, ray, of, df);
-  d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
-  KBuf<K> kb;
-  Record rc;
-  trace<K>(a.S, P, o, d, kb, stk + threadIdx.x, a.status);
-  composite<K>(a.S, P, kb, o, d, rc);
-  d3 gL = G.d_radiance ? ld3(G.d_radiance + 3 * ray) : mk(0, 0, 0);
-  double gdepth = G.d_depth ? (double)G.d_depth[ray] : 0.0;
+  const d3 d = mk(df[0], df[1], df[2]);
+  const Record rc = load_record(a.rec1 + ray);
+  const d3 gL = G.d_radiance ? ld3(G.d_radiance + 3 * ray) : mk(0, 0, 0);
+  const double gdepth = G.d_depth ? (double)G.d_depth[ray] : 0.0;
   d3 gn = G.d_normal ? ld3(G.d_normal + 3 * ray) : mk(0, 0, 0);
   double gA = G.d_alpha ? (double)G.d_alpha[ray] : 0.0, gT = 0.0;
   if (!(P.flags & LF_FLAG_NO_BACKGROUND)) {
-    d3 Ed = env_eval(a.E, d);
+    const d3 Ed = env_eval(a.E, d);
     gT += dot(gL, Ed);
     env_scatter(a.E, G.g_env, d, rc.T * gL);
   }
-  if (rc.nh == 0) return;
+  AdjSeed sd = {};
+  sd.T = (float)rc.T;
+  if (rc.nh == 0) {
+    a.seeds[ray] = sd;
+    return;
+  }
   const double c_env = a.E.scal[1];
   const bool trace2 = !(P.flags & LF_FLAG_NO_SECONDARY);
-  d3 wo = -d;
+  const d3 wo = -d;
   d3 ga = mk(0, 0, 0);
   double gm = 0.0, gr = 0.0;
   for (int s = 0; s < S; ++s) {
@@ -111,109 +130,177 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(RenderArgs a, GradArgs G) {
       ce = ld3(f.ce); cb = ld3(f.cb); we = ld3(f.we); wb = ld3(f.wb);
       has = f.has;
     }
-    d3 E = env_eval(a.E, w);
+    const d3 E = env_eval(a.E, w);
     d3 Lin = T2 * E;
-    if (has & 1u) { d3 Ee = env_eval(a.E, we); Lin = Lin + mk(ce.x * Ee.x, ce.y * Ee.y, ce.z * Ee.z); }
-    if (has & 2u) { d3 Eb = env_eval(a.E, wb); Lin = Lin + mk(cb.x * Eb.x, cb.y * Eb.y, cb.z * Eb.z); }
-    d3 fc = fcos(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags);
-    d3 Ls = K_ * mk(fc.x * Lin.x, fc.y * Lin.y, fc.z * Lin.z);
+    if (has & 1u) { const d3 Ee = env_eval(a.E, we); Lin = Lin + mk(ce.x * Ee.x, ce.y * Ee.y, ce.z * Ee.z); }
+    if (has & 2u) { const d3 Eb = env_eval(a.E, wb); Lin = Lin + mk(cb.x * Eb.x, cb.y * Eb.y, cb.z * Eb.z); }
+    const d3 fc = fcos(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags);
+    const d3 Ls = K_ * mk(fc.x * Lin.x, fc.y * Lin.y, fc.z * Lin.z);
     gA += dot(gL, Ls) / S;
-    d3 gF = (rc.A / S) * gL;
-    d3 gfc = K_ * mk(gF.x * Lin.x, gF.y * Lin.y, gF.z * Lin.z);
-    d3 gLin = K_ * mk(gF.x * fc.x, gF.y * fc.y, gF.z * fc.z);
+    const d3 gF = (rc.A / S) * gL;
+    const d3 gfc = K_ * mk(gF.x * Lin.x, gF.y * Lin.y, gF.z * Lin.z);
+    const d3 gLin = K_ * mk(gF.x * fc.x, gF.y * fc.y, gF.z * fc.z);
     env_scatter(a.E, G.g_env, w, T2 * gLin);
     if (has & 1u) env_scatter(a.E, G.g_env, we, mk(ce.x * gLin.x, ce.y * gLin.y, ce.z * gLin.z));
     if (has & 2u) env_scatter(a.E, G.g_env, wb, mk(cb.x * gLin.x, cb.y * gLin.y, cb.z * gLin.z));
     fcos_bwd(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags, gfc, gn, ga, gm, gr);
   }
-  // normalisation n_bar = N / |N|
+  // normalisation n_bar = N / |N|; z_bar = Z * inv with inv = 1/(A + eps)
   const double inv = 1.0 / (rc.A + P.eps);
   d3 gN = mk(0, 0, 0);
   if (rc.nl > 0.0) gN = (1.0 / rc.nl) * (gn - dot(rc.n, gn) * rc.n);
-  d3 N = rc.nl * rc.n;
-  // z_bar = Z * inv with inv = 1/(A + eps)
-  const double gZt = gdepth * inv, gZm = gm * inv, gZr = gr * inv;
-  const d3 gZn = inv * gN, gZa = inv * ga;
+  const d3 N = rc.nl * rc.n;
   gA += -inv * (gdepth * rc.depth + dot(gN, N) + dot(ga, rc.a) + gm * rc.m + gr * rc.r);
-  // compositing adjoint, back to front: with v_j = gA + sum_z gZ . z_j and the
-  // suffix V_j = sum_{i>j} w_i v_i, d/d(alpha_j) = T_j v_j - (V_j + gT T)/(1 - alpha_j)
-  double V = 0.0, Tafter = rc.T;
+  sd.gA = (float)gA;
+  sd.gT = (float)gT;
+  sd.gZt = (float)(gdepth * inv);
+  sd.gZm = (float)(gm * inv);
+  sd.gZr = (float)(gr * inv);
+  sd.gZn[0] = (float)(gN.x * inv); sd.gZn[1] = (float)(gN.y * inv); sd.gZn[2] = (float)(gN.z * inv);
+  sd.gZa[0] = (float)(ga.x * inv); sd.gZa[1] = (float)(ga.y * inv); sd.gZa[2] = (float)(ga.z * inv);
+  sd.pad[0] = 1.0f;  // ray has hits
+  a.seeds[ray] = sd;
+}
+
+// ---------------------------------------------------------------- compositing adjoint
+// Back to front over the recomputed hit list: with v_j = gA + sum_z gZ . z_j
+// and the suffix V_j = sum_{i>j} w_i v_i,
+//   d/d(alpha_j) = T_j v_j - (V_j + gT T) / (1 - alpha_j),
+// then through the effective opacity and the plane intersection into
+// (mu, q, s, alpha) and through the composited attributes into (a, m, r).
+template <int K, class B>
+__device__ void adjoint_hits(const RenderArgs &a, const GradArgs &G, const AdjSeed &sd, B &kb, d3 o, d3 d) {
+  const TraceParams &P = a.P;
+  const double gA = sd.gA, gT = sd.gT, gZt = sd.gZt, gZm = sd.gZm, gZr = sd.gZr, Tfin = sd.T;
+  const d3 gZn = mk(sd.gZn[0], sd.gZn[1], sd.gZn[2]), gZa = mk(sd.gZa[0], sd.gZa[1], sd.gZa[2]);
+  double V = 0.0, Tafter = Tfin;
   for (int it = 0; it < K; ++it) {
-    const double t = kb.t[K - 1];
+    const double tkey = (double)kb.t[K - 1];
     const uint32_t id = kb.id[K - 1];
-    krotr<K>(kb);
-    if (!(t > -INFINITY && t < INFINITY)) continue;
-    const int orig = (int)(id & kIdMask);
-    const bool flip = (id & kFlipBit) != 0;
-    HitQ h;
-    hit_quantities(a.S, P, orig, flip, t, o, d, h);
-    const double Tj = Tafter / (1.0 - h.at);
-    const double wj = Tj * h.at;
-    const d3 aj = ld3(a.S.albedo + 3 * (int64_t)orig);
-    const double mj = a.S.metallic[orig], rj = a.S.roughness[orig];
-    const double vj = gA + gZt * t + gZm * mj + gZr * rj + dot(gZn, h.nw) + dot(gZa, aj);
-    const double gat = Tj * vj - (V + gT * rc.T) / (1.0 - h.at);
+    krotr<B, K>(kb);
+    if (!(tkey > -INFINITY && tkey < INFINITY)) continue;
+    HitE he;
+    hit_exact(a.S, P, id, o, d, he);
+    const int64_t i = he.orig;
+    const double Tj = Tafter / (1.0 - he.at);
+    const double wj = Tj * he.at;
+    const d3 aj = ld3(a.S.albedo + 3 * i);
+    const double mj = a.S.metallic[i], rj = a.S.roughness[i];
+    const double vj = gA + gZt * he.t + gZm * mj + gZr * rj + dot(gZn, he.nw) + dot(gZa, aj);
+    const double gat = Tj * vj - (V + gT * Tfin) / (1.0 - he.at);
     V += wj * vj;
     Tafter = Tj;
     // attributes
-    const InstRec &I = a.S.inst[h.inst];
-    d3 oo, dd;
-    to_object(I, o, d, oo, dd);
-    double gt = gZt * wj;
-    d3 gnw = wj * gZn;
-    d3 gno = I.identity ? gnw : mulT(I.R, gnw);
-    if (flip) gno = -gno;
-    const int64_t i = orig;
     atomicAdd(G.g_albedo + 3 * i + 0, (float)(gZa.x * wj));
     atomicAdd(G.g_albedo + 3 * i + 1, (float)(gZa.y * wj));
     atomicAdd(G.g_albedo + 3 * i + 2, (float)(gZa.z * wj));
     atomicAdd(G.g_metallic + i, (float)(gZm * wj));
     atomicAdd(G.g_roughness + i, (float)(gZr * wj));
+    // frame of the raw quaternion, object-space ray of the hit's instance
+    const InstRec &I = a.S.inst[he.inst];
+    d3 oo, dd;
+    to_object(I, o, d, oo, dd);
+    const float *q = a.S.q + 4 * i;
+    const double qlen = sqrt((double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3]);
+    const double w = q[0] / qlen, x = q[1] / qlen, y = q[2] / qlen, z = q[3] / qlen;
+    d3 tu, tv, n;
+    quat_frame(w, x, y, z, tu, tv, n);
+    const d3 mu = ld3(a.S.mu + 3 * i);
+    const double su = a.S.scale[2 * i], sv = a.S.scale[2 * i + 1], alpha = a.S.opacity[i];
+    const d3 dl = (oo + he.t * dd) - mu;
+    const double xu = dot(dl, tu) / su, xv = dot(dl, tv) / sv;
+    const double g = exp(-0.5 * (xu * xu + xv * xv));
+    const double raw = alpha * g;
     // effective opacity alpha_t = min(cap, alpha exp(-rho^2/2))
-    const double graw = h.raw > P.alpha_cap ? 0.0 : gat;
-    atomicAdd(G.g_opacity + i, (float)(graw * h.g));
-    const double grho2 = graw * h.alpha * h.g * (-0.5);
-    const double gxu = grho2 * 2.0 * h.xu, gxv = grho2 * 2.0 * h.xv;
-    atomicAdd(G.g_scale + 2 * i + 0, (float)(-gxu * h.xu / h.su));
-    atomicAdd(G.g_scale + 2 * i + 1, (float)(-gxv * h.xv / h.sv));
-    const d3 gdl = (gxu / h.su) * h.tu + (gxv / h.sv) * h.tv;
-    const d3 gtu = (gxu / h.su) * h.dl, gtv = (gxv / h.sv) * h.dl;
-    // dl = o + t d - mu ; t = n.(mu - o) / (n.d)
-    gt += dot(gdl, dd);
-    const double den = dot(h.n, dd);
-    d3 gmu = (gt / den) * h.n - gdl;
-    d3 gnn = gno - (gt / den) * h.dl;
+    const double graw = raw > P.alpha_cap ? 0.0 : gat;
+    atomicAdd(G.g_opacity + i, (float)(graw * g));
+    const double grho2 = graw * alpha * g * (-0.5);
+    const double gxu = grho2 * 2.0 * xu, gxv = grho2 * 2.0 * xv;
+    atomicAdd(G.g_scale + 2 * i + 0, (float)(-gxu * xu / su));
+    atomicAdd(G.g_scale + 2 * i + 1, (float)(-gxv * xv / sv));
+    const d3 gdl = (gxu / su) * tu + (gxv / sv) * tv;
+    const d3 gtu = (gxu / su) * dl, gtv = (gxv / sv) * dl;
+    // dl = o + t d - mu ; t = n.(mu - o) / (n.d) ; composited normal = +-R n
+    const double gt = gZt * wj + dot(gdl, dd);
+    const double den = dot(n, dd);
+    const d3 gnw = wj * gZn;
+    d3 gno = I.identity ? gnw : mulT(I.R, gnw);
+    if (id & kFlipBit) gno = -gno;
+    const d3 gmu = (gt / den) * n - gdl;
+    const d3 gnn = gno - (gt / den) * dl;
     atomicAdd(G.g_mu + 3 * i + 0, (float)gmu.x);
     atomicAdd(G.g_mu + 3 * i + 1, (float)gmu.y);
     atomicAdd(G.g_mu + 3 * i + 2, (float)gmu.z);
-    // frame columns (t_u, t_v, n) of rot(q_hat) -> q_hat -> raw q
-    const double w = h.qw, x = h.qx, y = h.qy, z = h.qz;
-    // G row-major: G[r][0] = gtu_r, G[r][1] = gtv_r, G[r][2] = gnn_r
+    // columns (t_u, t_v, n) of rot(q_hat) -> q_hat -> raw q;  G[r][c] row-major
     const double G0 = gtu.x, G1 = gtv.x, G2 = gnn.x, G3 = gtu.y, G4 = gtv.y, G5 = gnn.y, G6 = gtu.z, G7 = gtv.z,
                  G8 = gnn.z;
-    double gq0 = G1 * (-2 * z) + G2 * (2 * y) + G3 * (2 * z) + G5 * (-2 * x) + G6 * (-2 * y) + G7 * (2 * x);
-    double gq1 = G1 * (2 * y) + G2 * (2 * z) + G3 * (2 * y) + G4 * (-4 * x) + G5 * (-2 * w) + G6 * (2 * z) +
-                 G7 * (2 * w) + G8 * (-4 * x);
-    double gq2 = G0 * (-4 * y) + G1 * (2 * x) + G2 * (2 * w) + G3 * (2 * x) + G5 * (2 * z) + G6 * (-2 * w) +
-                 G7 * (2 * z) + G8 * (-4 * y);
-    double gq3 = G0 * (-4 * z) + G1 * (-2 * w) + G2 * (2 * x) + G3 * (2 * w) + G4 * (-4 * z) + G5 * (2 * y) +
-                 G6 * (2 * x) + G7 * (2 * y);
+    const double gq0 = G1 * (-2 * z) + G2 * (2 * y) + G3 * (2 * z) + G5 * (-2 * x) + G6 * (-2 * y) + G7 * (2 * x);
+    const double gq1 = G1 * (2 * y) + G2 * (2 * z) + G3 * (2 * y) + G4 * (-4 * x) + G5 * (-2 * w) + G6 * (2 * z) +
+                       G7 * (2 * w) + G8 * (-4 * x);
+    const double gq2 = G0 * (-4 * y) + G1 * (2 * x) + G2 * (2 * w) + G3 * (2 * x) + G5 * (2 * z) + G6 * (-2 * w) +
+                       G7 * (2 * z) + G8 * (-4 * y);
+    const double gq3 = G0 * (-4 * z) + G1 * (-2 * w) + G2 * (2 * x) + G3 * (2 * w) + G4 * (-4 * z) + G5 * (2 * y) +
+                       G6 * (2 * x) + G7 * (2 * y);
     const double pq = gq0 * w + gq1 * x + gq2 * y + gq3 * z;
-    atomicAdd(G.g_q + 4 * i + 0, (float)((gq0 - w * pq) / h.qlen));
-    atomicAdd(G.g_q + 4 * i + 1, (float)((gq1 - x * pq) / h.qlen));
-    atomicAdd(G.g_q + 4 * i + 2, (float)((gq2 - y * pq) / h.qlen));
-    atomicAdd(G.g_q + 4 * i + 3, (float)((gq3 - z * pq) / h.qlen));
+    atomicAdd(G.g_q + 4 * i + 0, (float)((gq0 - w * pq) / qlen));
+    atomicAdd(G.g_q + 4 * i + 1, (float)((gq1 - x * pq) / qlen));
+    atomicAdd(G.g_q + 4 * i + 2, (float)((gq2 - y * pq) / qlen));
+    atomicAdd(G.g_q + 4 * i + 3, (float)((gq3 - z * pq) / qlen));
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_adj_trace(RenderArgs a, GradArgs G) {
+  __shared__ int stk[kStack * kBlock];
+  const int64_t ray = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool active = ray < a.R;
+  AdjSeed sd = {};
+  if (active) {
+    sd = a.seeds[ray];
+    active = sd.pad[0] != 0.0f;
+  }
+  float of[3] = {0, 0, 0}, df[3] = {0, 0, 1};
+  if (active) load_ray(a.rays, ray, of, df);
+  const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
+  KBufF<K> kb;
+  kb.collide = false;
+  if (active) trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
+  const bool again = active && kb.collide;
+  wave_append_i32(again, (int32_t)ray, a.retry, a.retry_count);
+  if (active && !again) adjoint_hits<K>(a, G, sd, kb, o, d);
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_adj_trace_exact(RenderArgs a, GradArgs G) {
+  __shared__ int stk[kStack * kBlock];
+  const uint32_t cnt = *a.retry_count;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
+    const int64_t ray = a.retry[i];
+    const AdjSeed sd = a.seeds[ray];
+    float of[3], df[3];
+    load_ray(a.rays, ray, of, df);
+    const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
+    KBufD<K> kb;
+    trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
+    adjoint_hits<K>(a, G, sd, kb, o, d);
   }
 }
 
 template <int K>
 void adjoint_k(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
-  hipLaunchKernelGGL(k_adjoint<K>, dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, g);
+  launch_fill_u32(a.retry_count, 0u, 1, st);
+  hipLaunchKernelGGL(k_adj_trace<K>, dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, g);
+  hipLaunchKernelGGL(k_adj_trace_exact<K>, dim3(512), dim3(kBlock), 0, st, a, g);
 }
 
 }  // namespace
 
-void launch_adjoint(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
+void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
+  if (a.R <= 0) return;
+  hipLaunchKernelGGL(k_adj_shade, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, g);
+}
+
+void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
   if (a.R <= 0) return;
   switch (kbucket(a.P.k)) {
     case 8: adjoint_k<8>(a, g, st); break;

@@ -16,7 +16,7 @@ namespace {
 
 // Trace record and conservative box of surfel i.
 __device__ __forceinline__ void surfel_prep(const SurfelArrays &s, int64_t i, double alpha_min, double sig2,
-                                            TraceRec &r, float *lo, float *hi) {
+                                            TraceRec &r, float *lo, float *hi, FiltRec *filt = nullptr) {
   const float *q = s.q + 4 * i;
   double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
   double ql = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
@@ -31,6 +31,16 @@ __device__ __forceinline__ void surfel_prep(const SurfelArrays &s, int64_t i, do
   r.mu[0] = s.mu[3 * i]; r.mu[1] = s.mu[3 * i + 1]; r.mu[2] = s.mu[3 * i + 2];
   r.orig = (int32_t)i;
   r.rho2max = rho2max;
+  if (filt) {
+    FiltRec f;
+    f.v0 = make_float4((float)n.x, (float)n.y, (float)n.z, (float)r.a[0]);
+    f.v1 = make_float4((float)r.a[1], (float)r.a[2], (float)r.b[0], (float)r.b[1]);
+    f.v2 = make_float4((float)r.b[2], r.mu[0], r.mu[1], r.mu[2]);
+    const bool ok = rho2max >= 0.0;
+    f.v3 = make_float4(ok ? round_up_f(rho2max) : -1.0f, ok ? round_up_f(sqrt(rho2max)) : 0.0f,
+                       round_up_f(1.0 / fmin(su, sv)), 0.0f);
+    *filt = f;
+  }
   if (!(rho2max >= 0.0)) {  // never valid (also NaN): empty box
     lo[0] = lo[1] = lo[2] = INFINITY;
     hi[0] = hi[1] = hi[2] = -INFINITY;
@@ -282,8 +292,8 @@ __global__ void k_depth(const int32_t *leaf_parent, const int32_t *node_parent, 
 // second arriving child computes its box (release/acquire on the arrival count)
 __global__ void k_refit(SurfelArrays s, double alpha_min, double sig2, const int32_t *perm,
                         const int32_t *leaf_parent, const int32_t *node_parent, int32_t *flags, BNode *nodes,
-                        int64_t n_nodes, int n_inst, TraceRec *rec, float *leaf_box6, float *root_box6,
-                        uint32_t *status) {
+                        int64_t n_nodes, int n_inst, TraceRec *rec, FiltRec *filt, float *leaf_box6,
+                        float *root_box6, uint32_t *status) {
   int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (pos >= s.n) return;
   int orig = perm[pos];
@@ -293,7 +303,7 @@ __global__ void k_refit(SurfelArrays s, double alpha_min, double sig2, const int
   }
   TraceRec r;
   float lo[3], hi[3];
-  surfel_prep(s, orig, alpha_min, sig2, r, lo, hi);
+  surfel_prep(s, orig, alpha_min, sig2, r, lo, hi, filt + pos);
   rec[pos] = r;
   for (int k = 0; k < 3; ++k) { leaf_box6[6 * pos + k] = lo[k]; leaf_box6[6 * pos + 3 + k] = hi[k]; }
   int pp = leaf_parent[pos];
@@ -387,12 +397,12 @@ void launch_depth(const int32_t *leaf_parent, const int32_t *node_parent, int64_
 
 void launch_refit(const SurfelArrays &s, double alpha_min, double sig2, const int32_t *perm,
                   const int32_t *leaf_parent, const int32_t *node_parent, int32_t *flags, int64_t n_nodes,
-                  int n_inst, BNode *nodes, TraceRec *rec, float *leaf_box6, float *root_box6, uint32_t *status,
-                  hipStream_t st) {
+                  int n_inst, BNode *nodes, TraceRec *rec, FiltRec *filt, float *leaf_box6, float *root_box6,
+                  uint32_t *status, hipStream_t st) {
   if (s.n <= 0) return;
   if (n_nodes > 0) launch_fill_u32((uint32_t *)flags, 0u, n_nodes, st);
   hipLaunchKernelGGL(k_refit, dim3(blocks(s.n, 256)), dim3(256), 0, st, s, alpha_min, sig2, perm, leaf_parent,
-                     node_parent, flags, nodes, n_nodes, n_inst, rec, leaf_box6, root_box6, status);
+                     node_parent, flags, nodes, n_nodes, n_inst, rec, filt, leaf_box6, root_box6, status);
 }
 
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {

@@ -119,57 +119,96 @@ __device__ __forceinline__ void load_ray(const RaySource &rs, int64_t id, float 
   }
 }
 
-// ------------------------------------------------------------------ k-closest buffer
-// Sorted by (t, surfel index).  The first K-k slots hold -inf sentinels so
-// that the k-th hit always sits in the last (static) slot.
+// ------------------------------------------------------------------ k-closest buffers
+// Hits are ordered by (t, surfel index).  Entries hold the leaf position of
+// the surfel and a flip bit (stored normal faces away from the ray).  The
+// first K-k slots hold -inf sentinels so the k-th hit always sits in the last
+// (static) slot.
+//
+// KBufF (fast path) keys on t rounded to binary32, which preserves the order
+// of distinct keys; two keys that round to the same float are flagged as a
+// collision and the ray is re-traced with KBufD, which keys on the exact
+// double t and breaks exact ties by surfel index.
 template <int K>
-struct KBuf {
+struct KBufF {
+  float t[K];
+  uint32_t id[K];
+  bool collide;
+};
+template <int K>
+struct KBufD {
   double t[K];
-  uint32_t id[K];  // surfel index | kFlipBit if the stored normal faces away from the ray
+  uint32_t id[K];
 };
 
-__device__ __forceinline__ bool kless(double t1, uint32_t i1, double t2, uint32_t i2) {
-  return t1 < t2 || (t1 == t2 && (i1 & kIdMask) < (i2 & kIdMask));
-}
-
 template <int K>
-__device__ __forceinline__ void kinit(KBuf<K> &b, int k) {
+__device__ __forceinline__ void kinit(KBufF<K> &b, int k) {
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    bool sentinel = j < K - k;
-    b.t[j] = sentinel ? -INFINITY : INFINITY;
-    b.id[j] = sentinel ? 0u : kIdMask;
+    b.t[j] = j < K - k ? -INFINITY : INFINITY;
+    b.id[j] = kIdMask;
+  }
+  b.collide = false;
+}
+template <int K>
+__device__ __forceinline__ void kinit(KBufD<K> &b, int k) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    b.t[j] = j < K - k ? -INFINITY : INFINITY;
+    b.id[j] = kIdMask;
   }
 }
 
 template <int K>
-__device__ __forceinline__ void kinsert(KBuf<K> &b, double t, uint32_t id) {
+__device__ __forceinline__ void kinsert(KBufF<K> &b, float t, uint32_t id) {
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    bool sw = kless(t, id, b.t[j], b.id[j]);
-    double tt = b.t[j];
-    uint32_t ti = b.id[j];
-    b.t[j] = sw ? t : tt;
-    b.id[j] = sw ? id : ti;
-    t = sw ? tt : t;
-    id = sw ? ti : id;
+    const float bt = b.t[j];
+    b.collide |= (t == bt) & (bt < INFINITY);  // two real keys rounded to the same float
+    const bool sw = t < bt;
+    const uint32_t bi = b.id[j];
+    b.t[j] = sw ? t : bt;
+    b.id[j] = sw ? id : bi;
+    t = sw ? bt : t;
+    id = sw ? bi : id;
   }
 }
 
-// Rotations used to walk the buffer with one loop body (static register
-// indexing): after K rotations the buffer is back in its original order.
+// exact order: t, then surfel index (read from the trace record on a tie)
+__device__ __forceinline__ bool kless_exact(const TraceRec *recs, double t1, uint32_t i1, double t2, uint32_t i2) {
+  if (t1 != t2) return t1 < t2;
+  if ((i2 & kIdMask) == kIdMask) return true;  // empty slot
+  return recs[i1 & kIdMask].orig < recs[i2 & kIdMask].orig;
+}
+
 template <int K>
-__device__ __forceinline__ void krotl(KBuf<K> &b) {
-  double t0 = b.t[0];
+__device__ __forceinline__ void kinsert(KBufD<K> &b, const TraceRec *recs, double t, uint32_t id) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const double bt = b.t[j];
+    const uint32_t bi = b.id[j];
+    const bool sw = (t < bt) || (t == bt && kless_exact(recs, t, id, bt, bi));
+    b.t[j] = sw ? t : bt;
+    b.id[j] = sw ? id : bi;
+    t = sw ? bt : t;
+    id = sw ? bi : id;
+  }
+}
+
+// Rotations walk a buffer with one loop body (static register indexing):
+// after K rotations the buffer is back in its original order.
+template <class B, int K>
+__device__ __forceinline__ void krotl(B &b) {
+  auto t0 = b.t[0];
   uint32_t i0 = b.id[0];
 #pragma unroll
   for (int j = 0; j < K - 1; ++j) { b.t[j] = b.t[j + 1]; b.id[j] = b.id[j + 1]; }
   b.t[K - 1] = t0;
   b.id[K - 1] = i0;
 }
-template <int K>
-__device__ __forceinline__ void krotr(KBuf<K> &b) {
-  double t0 = b.t[K - 1];
+template <class B, int K>
+__device__ __forceinline__ void krotr(B &b) {
+  auto t0 = b.t[K - 1];
   uint32_t i0 = b.id[K - 1];
 #pragma unroll
   for (int j = K - 1; j > 0; --j) { b.t[j] = b.t[j - 1]; b.id[j] = b.id[j - 1]; }
@@ -213,10 +252,17 @@ __device__ __forceinline__ bool slab64(d3 o, d3 d, const double *lo, const doubl
   return tn <= tf;
 }
 
+// Binary32 view of the object-space ray.  (lo - (o + pad), hi - (o - pad))
+// tests the box grown by pad on every side whatever the direction's sign, so
+// with pad >= the rounding error of the ray over the instance's parameter
+// range the slab tests never cull a box the exact ray enters.
 struct RayF {
-  float ax, ay, az;   // origin + pad (used against the low planes)
-  float bx, by, bz;   // origin - pad (used against the high planes)
+  float ax, ay, az;   // origin + pad (low planes)
+  float bx, by, bz;   // origin - pad (high planes)
   float ix, iy, iz;   // 1/d
+  float ox, oy, oz;   // origin
+  float dx, dy, dz;   // direction
+  float oabs;         // max |origin component|
 };
 
 __device__ __forceinline__ void child_test(const RayF &r, const float *lo, const float *hi, float tlo, float thi,
@@ -238,26 +284,81 @@ __device__ __forceinline__ float inv_dir(float d) {
   return 1.0f / dd;
 }
 
-// Test one surfel (leaf position pos) against the object-space ray; insert
-// it if valid and among the k closest.
-template <int K>
-__device__ __forceinline__ void test_surfel(const TraceRec *__restrict__ recs, int pos, d3 o, d3 d, double t_min,
-                                            KBuf<K> &kb) {
-  const TraceRec &r = recs[pos];
+// Exact (double) plane intersection and support test of the surfel at leaf
+// position pos against the object-space ray (o, d).  Returns false if the
+// surfel is not hit; otherwise t and the flip bit.
+__device__ __forceinline__ bool exact_hit(const TraceRec &r, d3 o, d3 d, double t_min, double &t, bool &flip) {
   d3 n = mk(r.n[0], r.n[1], r.n[2]);
   double den = dot(n, d);
-  if (!(fabs(den) >= 1e-12)) return;
+  if (!(fabs(den) >= 1e-12)) return false;
   d3 mu = mk((double)r.mu[0], (double)r.mu[1], (double)r.mu[2]);
-  double t = dot(n, mu - o) / den;
-  if (!(t > t_min)) return;
-  uint32_t id = (uint32_t)r.orig | (den > 0.0 ? kFlipBit : 0u);
-  if (!kless(t, id, kb.t[K - 1], kb.id[K - 1])) return;
+  t = dot(n, mu - o) / den;
+  if (!(t > t_min)) return false;
   d3 dl = (o + t * d) - mu;
   double xu = dl.x * r.a[0] + dl.y * r.a[1] + dl.z * r.a[2];
   double xv = dl.x * r.b[0] + dl.y * r.b[1] + dl.z * r.b[2];
   double rho2 = xu * xu + xv * xv;
-  if (!(rho2 <= r.rho2max)) return;
-  kinsert<K>(kb, t, id);
+  flip = den > 0.0;
+  return rho2 <= r.rho2max;
+}
+
+// Binary32 pre-filter: rejects a surfel only if, with a bound on every
+// rounding error of the binary32 evaluation (a factor of about 8 above the
+// first-order error of each product and sum), its plane intersection is
+// certainly behind t_min or beyond tk_up, or its local radius certainly lies
+// outside the support.  Everything else goes to exact_hit.
+__device__ __forceinline__ bool prefilter(const FiltRec &F, const RayF &r, float t_min_f, float tk_up) {
+  const float4 v0 = F.v0, v1 = F.v1, v2 = F.v2, v3 = F.v3;
+  const float nx = v0.x, ny = v0.y, nz = v0.z;
+  const float mx = v2.y, my = v2.z, mz = v2.w;
+  const float den = nx * r.dx + ny * r.dy + nz * r.dz;
+  const float adb = fabsf(den);
+  if (!(adb >= 1e-7f)) return true;  // grazing: decide exactly
+  const float rx = mx - r.ox, ry = my - r.oy, rz = mz - r.oz;
+  const float num = nx * rx + ny * ry + nz * rz;
+  const float t = num * __builtin_amdgcn_rcpf(den);
+  const float S = r.oabs + fmaxf(fmaxf(fabsf(mx), fabsf(my)), fabsf(mz));
+  const float et = 2e-6f * (S * (1.0f + 1.0f / adb) + fabsf(t));
+  if (t + et <= t_min_f) return false;
+  if (t - et > tk_up) return false;
+  const float dx = r.ox + t * r.dx - mx, dy = r.oy + t * r.dy - my, dz = r.oz + t * r.dz - mz;
+  const float xu = dx * v0.w + dy * v1.x + dz * v1.y;
+  const float xv = dx * v1.z + dy * v1.w + dz * v2.x;
+  const float rho2 = xu * xu + xv * xv;
+  const float exi = 1.8f * v3.z * (et + 2e-6f * (S + fabsf(t)));
+  const float margin = exi * (2.0f * v3.y + exi) + 1e-6f * fabsf(v3.x);
+  return rho2 <= v3.x + margin;
+}
+
+// Test one surfel and insert it if valid and among the k closest.
+template <int K>
+__device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3 d, const RayF &rf, double t_min,
+                                           float t_min_f, KBufF<K> &kb) {
+  const float tk = kb.t[K - 1];
+  const float tk_up = tk < INFINITY ? next_up_f(tk) : INFINITY;
+  if (!prefilter(S.filt[pos], rf, t_min_f, tk_up)) return 0;
+  double t;
+  bool flip;
+  if (!exact_hit(S.rec[pos], o, d, t_min, t, flip)) return 0;
+  const float tf = (float)t;
+  if (tf > tk) return 0;  // round-to-nearest is monotone: t > t_k exactly
+  if (tf == tk) kb.collide = true;
+  kinsert<K>(kb, tf, (uint32_t)pos | (flip ? kFlipBit : 0u));
+  return 1;
+}
+template <int K>
+__device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3 d, const RayF &rf, double t_min,
+                                           float t_min_f, KBufD<K> &kb) {
+  const double tk = kb.t[K - 1];
+  const float tk_up = tk < INFINITY ? round_up_f(tk) : INFINITY;
+  if (!prefilter(S.filt[pos], rf, t_min_f, tk_up)) return 0;
+  double t;
+  bool flip;
+  if (!exact_hit(S.rec[pos], o, d, t_min, t, flip)) return 0;
+  const uint32_t id = (uint32_t)pos | (flip ? kFlipBit : 0u);
+  if (!(t < tk || (t == tk && kless_exact(S.rec, t, id, tk, kb.id[K - 1])))) return 0;
+  kinsert<K>(kb, S.rec, t, id);
+  return 1;
 }
 
 // object-space ray of instance I
@@ -271,40 +372,57 @@ __device__ __forceinline__ void to_object(const InstRec &I, d3 o, d3 d, d3 &oo, 
   }
 }
 
-// Collects the k closest valid hits of the world ray (o, d) over all
-// instances.  stk points at this lane's first LDS stack slot (stride kBlock).
+__device__ __forceinline__ int inst_of(const SceneView &S, int pos) {
+  int ii = 0;
+  for (int j = 1; j < S.n_inst; ++j)
+    if (pos >= S.inst[j].first && S.inst[j].n > 0) ii = j;
+  return ii;
+}
+
 template <int K>
-__device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, KBuf<K> &kb, int *stk,
-                      uint32_t *status) {
+__device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K - 1]; }
+template <int K>
+__device__ __forceinline__ double kth(const KBufD<K> &b) { return b.t[K - 1]; }
+
+// Collects the k closest valid hits of the world ray (o, d) over all
+// instances into kb.  stk points at this lane's first LDS stack slot (stride
+// kBlock).
+template <int K, class B>
+__device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &kb, int *stk, uint32_t *status,
+                      int counter_base = 0) {
   kinit<K>(kb, P.k);
   const bool brute = (P.flags & LF_FLAG_BRUTE_FORCE) != 0;
+  const float t_min_f = round_down_f(P.t_min);
+  uint32_t c_nodes = 0, c_tests = 0, c_ins = 0;
   for (int ii = 0; ii < S.n_inst; ++ii) {
     const InstRec &I = S.inst[ii];
     if (I.n <= 0) continue;
     double itn, itf;
     if (!slab64(o, d, I.lo, I.hi, itn, itf)) continue;
     if (itf < P.t_min) continue;
-    if (kb.t[K - 1] < INFINITY && itn > kb.t[K - 1]) continue;
+    if (itn > kth<K>(kb) * (1.0 + 1e-6)) continue;
     d3 oo, dd;
     to_object(I, o, d, oo, dd);
+    RayF rf;
+    rf.ox = (float)oo.x; rf.oy = (float)oo.y; rf.oz = (float)oo.z;
+    rf.dx = (float)dd.x; rf.dy = (float)dd.y; rf.dz = (float)dd.z;
+    rf.oabs = fmaxf(fmaxf(fabsf(rf.ox), fabsf(rf.oy)), fabsf(rf.oz));
+    {
+      double eo = fmax(fmax(fabs(oo.x - rf.ox), fabs(oo.y - rf.oy)), fabs(oo.z - rf.oz));
+      double ed = fmax(fmax(fabs(dd.x - rf.dx), fabs(dd.y - rf.dy)), fabs(dd.z - rf.dz));
+      float pad = (float)((eo + ed * fmax(fabs(itf), fabs(itn)) + 1e-30) * 1.001) + 1e-30f;
+      rf.ax = rf.ox + pad; rf.ay = rf.oy + pad; rf.az = rf.oz + pad;
+      rf.bx = rf.ox - pad; rf.by = rf.oy - pad; rf.bz = rf.oz - pad;
+      rf.ix = inv_dir(rf.dx); rf.iy = inv_dir(rf.dy); rf.iz = inv_dir(rf.dz);
+    }
     if (brute) {
       const int end = I.first + I.n <= S.n_rec ? I.first + I.n : S.n_rec;
-      for (int pos = I.first < 0 ? 0 : I.first; pos < end; ++pos) test_surfel<K>(S.rec, pos, oo, dd, P.t_min, kb);
+      for (int pos = I.first < 0 ? 0 : I.first; pos < end; ++pos) {
+        c_ins += test_surfel<K>(S, pos, oo, dd, rf, P.t_min, t_min_f, kb);
+        ++c_tests;
+      }
       continue;
     }
-    // binary32 ray for the slab tests, padded by its own rounding error over the
-    // instance's parameter range so the tests stay conservative
-    float ofx = (float)oo.x, ofy = (float)oo.y, ofz = (float)oo.z;
-    float dfx = (float)dd.x, dfy = (float)dd.y, dfz = (float)dd.z;
-    double eo = fmax(fmax(fabs(oo.x - ofx), fabs(oo.y - ofy)), fabs(oo.z - ofz));
-    double ed = fmax(fmax(fabs(dd.x - dfx), fabs(dd.y - dfy)), fabs(dd.z - dfz));
-    float pad = (float)((eo + ed * fmax(fabs(itf), fabs(itn)) + 1e-30) * 1.001) + 1e-30f;
-    RayF rf;
-    rf.ax = ofx + pad; rf.ay = ofy + pad; rf.az = ofz + pad;
-    rf.bx = ofx - pad; rf.by = ofy - pad; rf.bz = ofz - pad;
-    rf.ix = inv_dir(dfx); rf.iy = inv_dir(dfy); rf.iz = inv_dir(dfz);
-    // (lo - (o + pad), hi - (o - pad)) is the box grown by pad on every side,
-    // whatever the sign of the direction
     const float tlo = (float)(0.5 * P.t_min);
     int cur = I.root;
     int sp = 0;
@@ -314,15 +432,17 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, KBuf
         break;
       }
       if (cur >= 0) {
+        ++c_nodes;
         const BNode nd = S.nodes[cur];
-        float thi = kb.t[K - 1] < INFINITY ? round_up_f(kb.t[K - 1]) * (1.0f + 1e-6f) : INFINITY;
+        const double tk = kth<K>(kb);
+        const float thi = tk < INFINITY ? round_up_f(tk) * (1.0f + 1e-6f) : INFINITY;
         bool h0, h1;
         float tn0, tn1;
         child_test(rf, nd.lo0, nd.hi0, tlo, thi, h0, tn0);
         child_test(rf, nd.lo1, nd.hi1, tlo, thi, h1, tn1);
         if (h0 && h1) {
-          int nr = tn0 <= tn1 ? nd.c0 : nd.c1;
-          int fr = tn0 <= tn1 ? nd.c1 : nd.c0;
+          const int nr = tn0 <= tn1 ? nd.c0 : nd.c1;
+          const int fr = tn0 <= tn1 ? nd.c1 : nd.c0;
           if (sp >= kStack) {
             atomicOr(status, kStatusOverflow);
             break;
@@ -339,12 +459,19 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, KBuf
           continue;
         }
       } else {
-        test_surfel<K>(S.rec, ~cur, oo, dd, P.t_min, kb);
+        c_ins += test_surfel<K>(S, ~cur, oo, dd, rf, P.t_min, t_min_f, kb);
+        ++c_tests;
       }
       if (sp == 0) break;
       --sp;
       cur = stk[sp * kBlock];
     }
+  }
+  if (P.counters) {
+    atomicAdd(P.counters + counter_base + 0, 1ull);
+    atomicAdd(P.counters + counter_base + 1, (unsigned long long)c_nodes);
+    atomicAdd(P.counters + counter_base + 2, (unsigned long long)c_tests);
+    atomicAdd(P.counters + counter_base + 3, (unsigned long long)c_ins);
   }
 }
 
@@ -358,98 +485,81 @@ struct Record {
   int nh;
 };
 
-__device__ __forceinline__ int inst_of(const SceneView &S, int orig) {
-  int ii = 0;
-  for (int j = 1; j < S.n_inst; ++j)
-    if (orig >= S.inst[j].first && S.inst[j].n > 0) ii = j;
-  return ii;
+__device__ __forceinline__ void store_record(const Record &rc, SurfRec *out) {
+  SurfRec s;
+  s.x[0] = rc.x.x; s.x[1] = rc.x.y; s.x[2] = rc.x.z;
+  s.n[0] = rc.n.x; s.n[1] = rc.n.y; s.n[2] = rc.n.z;
+  s.a[0] = rc.a.x; s.a[1] = rc.a.y; s.a[2] = rc.a.z;
+  s.A = rc.A; s.T = rc.T; s.m = rc.m; s.r = rc.r; s.depth = rc.depth; s.nl = rc.nl;
+  s.nh = rc.nh;
+  s.pad = 0;
+  *out = s;
+}
+__device__ __forceinline__ Record load_record(const SurfRec *in) {
+  const SurfRec s = *in;
+  Record rc;
+  rc.x = mk(s.x[0], s.x[1], s.x[2]);
+  rc.n = mk(s.n[0], s.n[1], s.n[2]);
+  rc.a = mk(s.a[0], s.a[1], s.a[2]);
+  rc.A = s.A; rc.T = s.T; rc.m = s.m; rc.r = s.r; rc.depth = s.depth; rc.nl = s.nl;
+  rc.nh = s.nh;
+  return rc;
 }
 
-// Per-hit live quantities recomputed from the caller's arrays.
-struct HitQ {
-  double at, raw, g, rho2, xu, xv;
-  d3 nw;   // world normal facing the ray
-  d3 dl;   // object-space x - mu
-  d3 tu, tv, n;  // object-space frame
-  double qlen, qw, qx, qy, qz;  // normalised quaternion and raw norm
-  double su, sv, alpha;
-  int inst;
+// Exact quantities of one hit (leaf position pos) of the world ray (o, d):
+// depth t, effective opacity (Eq. gaussian-response, capped) and the world
+// normal turned towards the ray.  Uses the same arithmetic as exact_hit.
+struct HitE {
+  double t, at;
+  d3 nw;
+  int orig, inst;
 };
-
-__device__ __forceinline__ void hit_quantities(const SceneView &S, const TraceParams &P, int orig, bool flip,
-                                               double t, d3 o, d3 d, HitQ &h) {
-  h.inst = inst_of(S, orig);
+__device__ __forceinline__ void hit_exact(const SceneView &S, const TraceParams &P, uint32_t id, d3 o, d3 d,
+                                          HitE &h) {
+  const int pos = (int)(id & kIdMask);
+  const TraceRec r = S.rec[pos];
+  h.inst = inst_of(S, pos);
   const InstRec &I = S.inst[h.inst];
   d3 oo, dd;
   to_object(I, o, d, oo, dd);
-  const float *q = S.q + 4 * (int64_t)orig;
-  double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
-  h.qlen = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-  h.qw = qw / h.qlen; h.qx = qx / h.qlen; h.qy = qy / h.qlen; h.qz = qz / h.qlen;
-  quat_frame(h.qw, h.qx, h.qy, h.qz, h.tu, h.tv, h.n);
-  d3 mu = ld3(S.mu + 3 * (int64_t)orig);
-  h.su = S.scale[2 * (int64_t)orig];
-  h.sv = S.scale[2 * (int64_t)orig + 1];
-  h.alpha = S.opacity[orig];
-  h.dl = (oo + t * dd) - mu;
-  h.xu = dot(h.dl, h.tu) / h.su;
-  h.xv = dot(h.dl, h.tv) / h.sv;
-  h.rho2 = h.xu * h.xu + h.xv * h.xv;
-  h.g = exp(-0.5 * h.rho2);
-  h.raw = h.alpha * h.g;
-  h.at = h.raw > P.alpha_cap ? P.alpha_cap : h.raw;
-  d3 nw = I.identity ? h.n : mul(I.R, h.n);
-  h.nw = flip ? -nw : nw;
+  d3 n = mk(r.n[0], r.n[1], r.n[2]);
+  d3 mu = mk((double)r.mu[0], (double)r.mu[1], (double)r.mu[2]);
+  h.t = dot(n, mu - oo) / dot(n, dd);
+  d3 dl = (oo + h.t * dd) - mu;
+  double xu = dl.x * r.a[0] + dl.y * r.a[1] + dl.z * r.a[2];
+  double xv = dl.x * r.b[0] + dl.y * r.b[1] + dl.z * r.b[2];
+  double raw = (double)S.opacity[r.orig] * exp(-0.5 * (xu * xu + xv * xv));
+  h.at = raw > P.alpha_cap ? P.alpha_cap : raw;
+  d3 nw = I.identity ? n : mul(I.R, n);
+  h.nw = (id & kFlipBit) ? -nw : nw;
+  h.orig = r.orig;
 }
 
-// Effective opacity and ray-facing world normal of one hit (forward only).
-__device__ __forceinline__ void hit_alpha_normal(const SceneView &S, const TraceParams &P, int orig, bool flip,
-                                                 double t, d3 o, d3 d, double &at, d3 &nw) {
-  const InstRec &I = S.inst[inst_of(S, orig)];
-  d3 oo, dd;
-  to_object(I, o, d, oo, dd);
-  const float *q = S.q + 4 * (int64_t)orig;
-  double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
-  double ql = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-  qw /= ql; qx /= ql; qy /= ql; qz /= ql;
-  d3 tu, tv, n;
-  quat_frame(qw, qx, qy, qz, tu, tv, n);
-  d3 dl = (oo + t * dd) - ld3(S.mu + 3 * (int64_t)orig);
-  double xu = dot(dl, tu) / (double)S.scale[2 * (int64_t)orig];
-  double xv = dot(dl, tv) / (double)S.scale[2 * (int64_t)orig + 1];
-  double raw = (double)S.opacity[orig] * exp(-0.5 * (xu * xu + xv * xv));
-  at = raw > P.alpha_cap ? P.alpha_cap : raw;
-  d3 w = I.identity ? n : mul(I.R, n);
-  nw = flip ? -w : w;
-}
-
-template <int K>
-__device__ void composite(const SceneView &S, const TraceParams &P, KBuf<K> &kb, d3 o, d3 d, Record &rc) {
+template <int K, class B>
+__device__ void composite(const SceneView &S, const TraceParams &P, B &kb, d3 o, d3 d, Record &rc) {
   double T = 1.0, A = 0.0, Zt = 0.0, Zm = 0.0, Zr = 0.0;
   d3 Zx = mk(0, 0, 0), Zn = mk(0, 0, 0), Za = mk(0, 0, 0);
   int nh = 0;
   for (int it = 0; it < K; ++it) {
-    const double t = kb.t[0];
+    const double t = (double)kb.t[0];
     const uint32_t id = kb.id[0];
-    krotl<K>(kb);
+    krotl<B, K>(kb);
     if (t > -INFINITY && t < INFINITY) {
-      int orig = (int)(id & kIdMask);
-      double at;
-      d3 nw;
-      hit_alpha_normal(S, P, orig, (id & kFlipBit) != 0, t, o, d, at, nw);
-      double w = T * at;
+      HitE h;
+      hit_exact(S, P, id, o, d, h);
+      const double w = T * h.at;
       A += w;
-      Zt += w * t;
-      Zx = Zx + w * (o + t * d);
-      Zn = Zn + w * nw;
-      Za = Za + w * ld3(S.albedo + 3 * (int64_t)orig);
-      Zm += w * (double)S.metallic[orig];
-      Zr += w * (double)S.roughness[orig];
-      T *= (1.0 - at);
+      Zt += w * h.t;
+      Zx = Zx + w * (o + h.t * d);
+      Zn = Zn + w * h.nw;
+      Za = Za + w * ld3(S.albedo + 3 * (int64_t)h.orig);
+      Zm += w * (double)S.metallic[h.orig];
+      Zr += w * (double)S.roughness[h.orig];
+      T *= (1.0 - h.at);
       ++nh;
     }
   }
-  double inv = 1.0 / (A + P.eps);
+  const double inv = 1.0 / (A + P.eps);
   rc.A = A;
   rc.T = T;
   rc.nh = nh;
@@ -458,10 +568,22 @@ __device__ void composite(const SceneView &S, const TraceParams &P, KBuf<K> &kb,
   rc.a = inv * Za;
   rc.m = Zm * inv;
   rc.r = Zr * inv;
-  d3 N = inv * Zn;
-  double nl = sqrt(dot(N, N));
+  const d3 N = inv * Zn;
+  const double nl = sqrt(dot(N, N));
   rc.nl = nl;
   rc.n = (nh > 0 && nl > 0.0) ? (1.0 / nl) * N : mk(0, 0, 0);
+}
+
+// hit list (surfel indices in order, -1 padded) for debugging/parity outputs
+template <int K, class B>
+__device__ void write_hits(const SceneView &S, const B &kb, int k, int32_t *out) {
+  int j = 0;
+#pragma unroll
+  for (int e = 0; e < K; ++e)
+    if (kb.t[e] > -INFINITY) {
+      if (j < k) out[j] = kb.t[e] < INFINITY ? S.rec[kb.id[e] & kIdMask].orig : -1;
+      ++j;
+    }
 }
 
 // ------------------------------------------------------------------ environment

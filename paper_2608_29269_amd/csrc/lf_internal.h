@@ -32,6 +32,14 @@ struct alignas(16) TraceRec {
 };
 static_assert(sizeof(TraceRec) == 96, "TraceRec layout");
 
+// Binary32 copy of the trace record used by the pre-filter, 64 bytes:
+// v0 = (n.x, n.y, n.z, a.x), v1 = (a.y, a.z, b.x, b.y), v2 = (b.z, mu.x, mu.y, mu.z),
+// v3 = (rho2max rounded up, sqrt(rho2max) rounded up, max(|a|,|b|) rounded up, 0).
+struct alignas(16) FiltRec {
+  float4 v0, v1, v2, v3;
+};
+static_assert(sizeof(FiltRec) == 64, "FiltRec layout");
+
 // Binary BVH node holding both children's boxes (one 64-byte fetch per
 // visited node).  Child >= 0: internal node index (global); < 0: ~leaf
 // position (global).
@@ -57,6 +65,7 @@ struct alignas(16) InstRec {
 
 struct SceneView {
   const TraceRec *rec;   // [N] leaf order
+  const FiltRec *filt;   // [N] leaf order
   const BNode *nodes;    // internal nodes of all instances
   const InstRec *inst;   // [n_inst]
   int32_t n_inst;
@@ -70,6 +79,7 @@ struct TraceParams {
   uint64_t seed;
   double alpha_min, alpha_cap, sig2, eps, t_min, sec_off;
   uint32_t flags;
+  unsigned long long *counters;  // [8] traversal counters when LF_FLAG_COUNT is set
 };
 
 struct EnvView {
@@ -107,6 +117,24 @@ struct alignas(16) SecEntry {
   int32_t pad;
 };
 static_assert(sizeof(SecEntry) == 80, "SecEntry layout");
+
+// Composited surface record of one ray (Eq. surface-record), double
+// precision, written by the tracing passes and read by the shading passes.
+struct alignas(16) SurfRec {
+  double x[3], n[3], a[3];
+  double A, T, m, r, depth, nl;
+  int32_t nh, pad;
+};
+static_assert(sizeof(SurfRec) == 128, "SurfRec layout");
+
+// Seeds of the compositing adjoint of one ray (from the shading adjoint).
+struct alignas(16) AdjSeed {
+  float gA, gT, gZt, gZm, gZr;
+  float gZn[3], gZa[3];
+  float T;
+  float pad[4];
+};
+static_assert(sizeof(AdjSeed) == 64, "AdjSeed layout");
 
 // Frozen secondary quantities of one (ray, sample) for the replayed backward.
 struct alignas(16) SecFrozen {

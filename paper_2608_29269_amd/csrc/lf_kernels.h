@@ -31,8 +31,8 @@ void launch_depth(const int32_t *leaf_parent, const int32_t *node_parent, int64_
 // trace records + bottom-up bounds
 void launch_refit(const SurfelArrays &s, double alpha_min, double sig2, const int32_t *perm,
                   const int32_t *leaf_parent, const int32_t *node_parent, int32_t *flags, int64_t n_nodes,
-                  int n_inst, BNode *nodes, TraceRec *rec, float *leaf_box6, float *root_box6, uint32_t *status,
-                  hipStream_t st);
+                  int n_inst, BNode *nodes, TraceRec *rec, FiltRec *filt, float *leaf_box6, float *root_box6,
+                  uint32_t *status, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t st);
 
@@ -53,14 +53,23 @@ struct RenderArgs {
   float *radiance, *depth, *normal, *alpha;
   int32_t *hit_idx, *sec_hit_idx;
   // scratch
-  SecEntry *queue;
+  SurfRec *rec1;        // [R] primary surface records
+  SurfRec *rec2;        // [R*S] secondary surface records (queue order)
+  SecEntry *queue;      // [R*S]
   uint32_t *queue_count;
+  int32_t *retry;       // [max(R, R*S)] rays / queue entries re-traced with exact keys
+  uint32_t *retry_count;
   float *contrib;       // [R*S*3]
   SecFrozen *frozen;    // [R*S] (backward replay)
+  AdjSeed *seeds;       // [R] (backward)
   uint32_t *status;
 };
-void launch_primary(const RenderArgs &a, bool replay, hipStream_t st);
-void launch_secondary(const RenderArgs &a, bool replay, hipStream_t st);
+// primary: traversal + compositing (fast keys, then exact re-trace of collisions), then shading
+void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st);
+void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st);
+// secondary: traversal + compositing of the queue, then the two environment samples
+void launch_trace2(const RenderArgs &a, hipStream_t st);
+void launch_shade2(const RenderArgs &a, bool replay, hipStream_t st);
 void launch_resolve(const RenderArgs &a, hipStream_t st);
 void launch_accum(unsigned long long *acc, const uint32_t *count, hipStream_t st);
 void launch_raygen(const CamArgs *cams, int64_t n, float *o, float *d, hipStream_t st);
@@ -72,7 +81,9 @@ struct GradArgs {
   const float *d_radiance, *d_depth, *d_normal, *d_alpha;
   float *g_mu, *g_q, *g_scale, *g_opacity, *g_albedo, *g_roughness, *g_metallic, *g_env;
 };
-void launch_adjoint(const RenderArgs &a, const GradArgs &g, hipStream_t st);
+// shading adjoint (env gradients, compositing seeds) then traversal + compositing adjoint
+void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st);
+void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st);
 
 inline int kbucket(int k) { return k <= 8 ? 8 : (k <= 16 ? 16 : (k <= 32 ? 32 : 64)); }
 

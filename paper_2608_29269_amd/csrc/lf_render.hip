@@ -165,7 +165,9 @@ __global__ __launch_bounds__(256) void k_env_marginal(int H, uint32_t flags, con
   }
 }
 
-__device__ __forceinline__ void wave_enqueue(bool live, const SecEntry &e, SecEntry *queue, uint32_t *count) {
+// Wave-aggregated append: one atomic per wave, slots in lane order.
+template <class T>
+__device__ __forceinline__ void wave_append(bool live, const T &e, T *queue, uint32_t *count) {
   uint64_t mask = __ballot(live);
   if (mask == 0) return;
   const int lane = __lane_id();
@@ -179,59 +181,89 @@ __device__ __forceinline__ void wave_enqueue(bool live, const SecEntry &e, SecEn
   }
 }
 
-// Primary pass.  replay = true regenerates the queue only (backward).
+// ---------------------------------------------------------------- primary tracing
+template <int K, class B>
+__device__ __forceinline__ void finish_primary(const RenderArgs &a, bool replay, int64_t ray, B &kb, d3 o, d3 d) {
+  Record rc;
+  composite<K>(a.S, a.P, kb, o, d, rc);
+  store_record(rc, a.rec1 + ray);
+  if (replay) return;
+  a.depth[ray] = (float)rc.depth;
+  a.alpha[ray] = (float)rc.A;
+  a.normal[3 * ray + 0] = (float)rc.n.x;
+  a.normal[3 * ray + 1] = (float)rc.n.y;
+  a.normal[3 * ray + 2] = (float)rc.n.z;
+  if (a.hit_idx) write_hits<K>(a.S, kb, a.P.k, a.hit_idx + ray * a.P.k);
+}
+
+// fast keys; rays whose binary32 keys collide are appended to the retry list
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_primary(RenderArgs a, bool replay) {
+__global__ __launch_bounds__(kBlock) void k_trace1(RenderArgs a, bool replay) {
   __shared__ int stk[kStack * kBlock];
   const int64_t ray = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool active = ray < a.R;
+  float of[3] = {0, 0, 0}, df[3] = {0, 0, 1};
+  if (active) load_ray(a.rays, ray, of, df);
+  const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
+  KBufF<K> kb;
+  kb.collide = false;
+  if (active) trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
+  const bool again = active && kb.collide;
+  wave_append<int32_t>(again, (int32_t)ray, a.retry, a.retry_count);
+  if (active && !again) finish_primary<K>(a, replay, ray, kb, o, d);
+}
+
+// exact keys for the retried rays
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_trace1_exact(RenderArgs a, bool replay) {
+  __shared__ int stk[kStack * kBlock];
+  const uint32_t cnt = *a.retry_count;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
+    const int64_t ray = a.retry[i];
+    float of[3], df[3];
+    load_ray(a.rays, ray, of, df);
+    const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
+    KBufD<K> kb;
+    trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
+    finish_primary<K>(a, replay, ray, kb, o, d);
+  }
+}
+
+// ---------------------------------------------------------------- primary shading
+// Background term, S sampled directions (one-sample MIS), ballot-compacted
+// enqueue of live secondary rays.  replay = true regenerates the queue only.
+__global__ __launch_bounds__(256) void k_shade1(RenderArgs a, bool replay) {
+  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = ray < a.R;
   const TraceParams &P = a.P;
   const int S = P.spp;
   float of[3] = {0, 0, 0}, df[3] = {0, 0, 1};
   if (active) load_ray(a.rays, ray, of, df);
-  d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
-  KBuf<K> kb;
+  const d3 d = mk(df[0], df[1], df[2]);
   Record rc;
   rc.nh = 0;
-  if (active) {
-    trace<K>(a.S, P, o, d, kb, stk + threadIdx.x, a.status);
-    composite<K>(a.S, P, kb, o, d, rc);
-  }
+  if (active) rc = load_record(a.rec1 + ray);
   const double c_env = a.E.scal[1];
-  d3 wo = -d;
+  const d3 wo = -d;
   d3 L = mk(0, 0, 0);
-  if (active && !replay) {
-    a.depth[ray] = (float)rc.depth;
-    a.alpha[ray] = (float)rc.A;
-    for (int c = 0; c < 3; ++c) a.normal[3 * ray + c] = (float)(c == 0 ? rc.n.x : (c == 1 ? rc.n.y : rc.n.z));
-    if (a.hit_idx) {
-      int j = 0;
-#pragma unroll
-      for (int e = 0; e < K; ++e)
-        if (kb.t[e] > -INFINITY) {
-          if (j < P.k) a.hit_idx[ray * P.k + j] = kb.t[e] < INFINITY ? (int32_t)(kb.id[e] & kIdMask) : -1;
-          ++j;
-        }
-    }
-    if (!(P.flags & LF_FLAG_NO_BACKGROUND)) L = rc.T * env_eval(a.E, d);
-  }
+  if (active && !replay && !(P.flags & LF_FLAG_NO_BACKGROUND)) L = rc.T * env_eval(a.E, d);
   const bool trace2 = !(P.flags & LF_FLAG_NO_SECONDARY);
   for (int s = 0; s < S; ++s) {
     d3 w = mk(0, 0, 1);
     double K_ = 0.0;
-    bool live = active && primary_sample(a.E, P, rc, wo, ray, s, c_env, w, K_);
+    const bool live = active && primary_sample(a.E, P, rc, wo, ray, s, c_env, w, K_);
     d3 thr = mk(0, 0, 0);
     if (live) thr = (K_ * rc.A / S) * fcos(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags);
     if (!trace2) {
       if (live && !replay) {
-        d3 E = env_eval(a.E, w);
+        const d3 E = env_eval(a.E, w);
         L = L + mk(thr.x * E.x, thr.y * E.y, thr.z * E.z);
       }
       continue;
     }
     SecEntry e;
     if (live) {
-      d3 o2 = rc.x + P.sec_off * rc.n;
+      const d3 o2 = rc.x + P.sec_off * rc.n;
       e.o[0] = o2.x; e.o[1] = o2.y; e.o[2] = o2.z;
       e.w[0] = w.x; e.w[1] = w.y; e.w[2] = w.z;
       e.thr[0] = (float)thr.x; e.thr[1] = (float)thr.y; e.thr[2] = (float)thr.z;
@@ -239,11 +271,13 @@ __global__ __launch_bounds__(kBlock) void k_primary(RenderArgs a, bool replay) {
       e.s = s;
       e.pad = 0;
     }
-    wave_enqueue(live, e, a.queue, a.queue_count);
+    wave_append<SecEntry>(live, e, a.queue, a.queue_count);
     if (active && !live) {
-      int64_t cs = ray * S + s;
+      const int64_t cs = ray * S + s;
       if (!replay) {
-        a.contrib[3 * cs + 0] = 0.f; a.contrib[3 * cs + 1] = 0.f; a.contrib[3 * cs + 2] = 0.f;
+        a.contrib[3 * cs + 0] = 0.f;
+        a.contrib[3 * cs + 1] = 0.f;
+        a.contrib[3 * cs + 2] = 0.f;
         if (a.sec_hit_idx)
           for (int j = 0; j < P.k; ++j) a.sec_hit_idx[cs * P.k + j] = -1;
       } else {
@@ -260,19 +294,64 @@ __global__ __launch_bounds__(kBlock) void k_primary(RenderArgs a, bool replay) {
   }
 }
 
+// ---------------------------------------------------------------- secondary tracing
+template <int K, class B>
+__device__ __forceinline__ void finish_secondary(const RenderArgs &a, uint32_t qi, const SecEntry &e, B &kb, d3 o,
+                                                 d3 w) {
+  Record r2;
+  composite<K>(a.S, a.P, kb, o, w, r2);
+  store_record(r2, a.rec2 + qi);
+  if (a.sec_hit_idx) {
+    const int64_t cs = (int64_t)e.ray * a.P.spp + e.s;
+    write_hits<K>(a.S, kb, a.P.k, a.sec_hit_idx + cs * a.P.k);
+  }
+}
+
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_secondary(RenderArgs a, bool replay) {
+__global__ __launch_bounds__(kBlock) void k_trace2(RenderArgs a) {
   __shared__ int stk[kStack * kBlock];
   const uint32_t count = *a.queue_count;
+  if (blockIdx.x * kBlock >= count) return;  // whole block past the queue
   const uint32_t qi = blockIdx.x * kBlock + threadIdx.x;
+  const bool active = qi < count;
+  SecEntry e;
+  d3 o = mk(0, 0, 0), w = mk(0, 0, 1);
+  if (active) {
+    e = a.queue[qi];
+    o = mk(e.o[0], e.o[1], e.o[2]);
+    w = mk(e.w[0], e.w[1], e.w[2]);
+  }
+  KBufF<K> kb;
+  kb.collide = false;
+  if (active) trace<K>(a.S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4);
+  const bool again = active && kb.collide;
+  wave_append<int32_t>(again, (int32_t)qi, a.retry, a.retry_count);
+  if (active && !again) finish_secondary<K>(a, qi, e, kb, o, w);
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_trace2_exact(RenderArgs a) {
+  __shared__ int stk[kStack * kBlock];
+  const uint32_t cnt = *a.retry_count;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
+    const uint32_t qi = (uint32_t)a.retry[i];
+    const SecEntry e = a.queue[qi];
+    const d3 o = mk(e.o[0], e.o[1], e.o[2]), w = mk(e.w[0], e.w[1], e.w[2]);
+    KBufD<K> kb;
+    trace<K>(a.S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4);
+    finish_secondary<K>(a, qi, e, kb, o, w);
+  }
+}
+
+// ---------------------------------------------------------------- secondary shading
+__global__ __launch_bounds__(256) void k_shade2(RenderArgs a, bool replay) {
+  const uint32_t count = *a.queue_count;
+  const uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x;
   if (qi >= count) return;
   const SecEntry e = a.queue[qi];
   const TraceParams &P = a.P;
-  d3 o = mk(e.o[0], e.o[1], e.o[2]), w = mk(e.w[0], e.w[1], e.w[2]);
-  KBuf<K> kb;
-  Record r2;
-  trace<K>(a.S, P, o, w, kb, stk + threadIdx.x, a.status);
-  composite<K>(a.S, P, kb, o, w, r2);
+  const d3 w = mk(e.w[0], e.w[1], e.w[2]);
+  const Record r2 = load_record(a.rec2 + qi);
   const double c_env = a.E.scal[1];
   SecCoef sc;
   secondary_coefs(a.E, P, r2, w, e.ray, e.s, c_env, sc);
@@ -290,25 +369,16 @@ __global__ __launch_bounds__(kBlock) void k_secondary(RenderArgs a, bool replay)
   }
   d3 Lin = r2.T * env_eval(a.E, w);
   if (sc.has_e) {
-    d3 Ee = env_eval(a.E, sc.we);
+    const d3 Ee = env_eval(a.E, sc.we);
     Lin = Lin + mk(sc.ce.x * Ee.x, sc.ce.y * Ee.y, sc.ce.z * Ee.z);
   }
   if (sc.has_b) {
-    d3 Eb = env_eval(a.E, sc.wb);
+    const d3 Eb = env_eval(a.E, sc.wb);
     Lin = Lin + mk(sc.cb.x * Eb.x, sc.cb.y * Eb.y, sc.cb.z * Eb.z);
   }
   a.contrib[3 * cs + 0] = (float)(e.thr[0] * Lin.x);
   a.contrib[3 * cs + 1] = (float)(e.thr[1] * Lin.y);
   a.contrib[3 * cs + 2] = (float)(e.thr[2] * Lin.z);
-  if (a.sec_hit_idx) {
-    int j = 0;
-#pragma unroll
-    for (int q = 0; q < K; ++q)
-      if (kb.t[q] > -INFINITY) {
-        if (j < P.k) a.sec_hit_idx[cs * P.k + j] = kb.t[q] < INFINITY ? (int32_t)(kb.id[q] & kIdMask) : -1;
-        ++j;
-      }
-  }
 }
 
 __global__ void k_resolve(float *radiance, const float *contrib, int64_t R, int S) {
@@ -350,14 +420,20 @@ __global__ void k_accum(unsigned long long *acc, const uint32_t *count) { *acc +
 __global__ void k_l1_final(const double *acc, int64_t n, float *loss) { *loss = (float)(*acc / (double)n); }
 __global__ void k_zero_f64(double *p) { *p = 0.0; }
 
+constexpr unsigned kExactBlocks = 512;
+
 template <int K>
-void primary_k(const RenderArgs &a, bool replay, hipStream_t st) {
-  hipLaunchKernelGGL(k_primary<K>, dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, replay);
+void trace1_k(const RenderArgs &a, bool replay, hipStream_t st) {
+  launch_fill_u32(a.retry_count, 0u, 1, st);
+  hipLaunchKernelGGL(k_trace1<K>, dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, replay);
+  hipLaunchKernelGGL(k_trace1_exact<K>, dim3(kExactBlocks), dim3(kBlock), 0, st, a, replay);
 }
 template <int K>
-void secondary_k(const RenderArgs &a, bool replay, hipStream_t st) {
-  int64_t cap = a.R * a.P.spp;
-  hipLaunchKernelGGL(k_secondary<K>, dim3(blocks(cap, kBlock)), dim3(kBlock), 0, st, a, replay);
+void trace2_k(const RenderArgs &a, hipStream_t st) {
+  launch_fill_u32(a.retry_count, 0u, 1, st);
+  const int64_t cap = a.R * a.P.spp;
+  hipLaunchKernelGGL(k_trace2<K>, dim3(blocks(cap, kBlock)), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL(k_trace2_exact<K>, dim3(kExactBlocks), dim3(kBlock), 0, st, a);
 }
 
 }  // namespace
@@ -375,24 +451,34 @@ void launch_env_tables(const float *tex, int H, int W, uint32_t flags, double *c
   hipLaunchKernelGGL(k_env_marginal, dim3(1), dim3(256), 0, st, H, flags, roww, cdf_row, scal);
 }
 
-void launch_primary(const RenderArgs &a, bool replay, hipStream_t st) {
+void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st) {
   if (a.R <= 0) return;
   switch (kbucket(a.P.k)) {
-    case 8: primary_k<8>(a, replay, st); break;
-    case 16: primary_k<16>(a, replay, st); break;
-    case 32: primary_k<32>(a, replay, st); break;
-    default: primary_k<64>(a, replay, st); break;
+    case 8: trace1_k<8>(a, replay, st); break;
+    case 16: trace1_k<16>(a, replay, st); break;
+    case 32: trace1_k<32>(a, replay, st); break;
+    default: trace1_k<64>(a, replay, st); break;
   }
 }
 
-void launch_secondary(const RenderArgs &a, bool replay, hipStream_t st) {
+void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st) {
+  if (a.R <= 0) return;
+  hipLaunchKernelGGL(k_shade1, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, replay);
+}
+
+void launch_trace2(const RenderArgs &a, hipStream_t st) {
   if (a.R <= 0) return;
   switch (kbucket(a.P.k)) {
-    case 8: secondary_k<8>(a, replay, st); break;
-    case 16: secondary_k<16>(a, replay, st); break;
-    case 32: secondary_k<32>(a, replay, st); break;
-    default: secondary_k<64>(a, replay, st); break;
+    case 8: trace2_k<8>(a, st); break;
+    case 16: trace2_k<16>(a, st); break;
+    case 32: trace2_k<32>(a, st); break;
+    default: trace2_k<64>(a, st); break;
   }
+}
+
+void launch_shade2(const RenderArgs &a, bool replay, hipStream_t st) {
+  if (a.R <= 0) return;
+  hipLaunchKernelGGL(k_shade2, dim3(blocks(a.R * a.P.spp, 256)), dim3(256), 0, st, a, replay);
 }
 
 void launch_resolve(const RenderArgs &a, hipStream_t st) {
