@@ -119,6 +119,8 @@ typedef struct {
 #define LF_FLAG_DIFFUSE_ONLY  (1u << 3) /* Lambert lobe only */
 #define LF_FLAG_BRUTE_FORCE   (1u << 4) /* test every surfel of every instance (no BVH); for testing */
 #define LF_FLAG_COUNT         (1u << 5) /* accumulate traversal counters (lf_trace_counters) */
+#define LF_FLAG_UNSORTED      (1u << 6) /* trace secondary rays in queue order instead of regrouping them
+                                           by direction octant and origin (same results, less coherent) */
 
 /* Tracing and estimator parameters.  Readings of points the paper leaves
  * open (Sec. 3.2 "finite support", "opacity threshold", epsilon of

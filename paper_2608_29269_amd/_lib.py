@@ -21,6 +21,7 @@ FLAG_BSDF_ONLY = 1 << 2
 FLAG_DIFFUSE_ONLY = 1 << 3
 FLAG_BRUTE_FORCE = 1 << 4
 FLAG_COUNT = 1 << 5
+FLAG_UNSORTED = 1 << 6
 MAX_CAMERAS = 16
 
 _fp = C.POINTER(C.c_float)

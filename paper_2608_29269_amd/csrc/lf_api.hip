@@ -63,6 +63,7 @@ struct lf_ctx {
   // per call
   DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;
   DevBuf queue, qcount, contrib, frozen, l1acc, cams, rec1, rec2, retry, rcount, seeds;
+  DevBuf bounds, skeys, skeys2, svals, svals2, shist;
   lf::CamArgs h_cams{};
   // ray counters since the last lf_stats_get
   int64_t acc_primary = 0;
@@ -147,7 +148,7 @@ lf_status validate_params(lf_ctx *c, const lf_params *p) {
   if (!(p->alpha_min > 0.0) || !(p->alpha_cap > 0.0 && p->alpha_cap < 1.0) || !(p->support_sigma > 0.0) ||
       !(p->eps >= 0.0) || !(p->t_min >= 0.0) || !std::isfinite(p->secondary_offset))
     return fail(c, LF_EINVAL, "invalid tracing constants");
-  if (p->flags & ~0x3Fu) return fail(c, LF_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~0x7Fu) return fail(c, LF_EINVAL, "unknown flags 0x%x", p->flags);
   return LF_OK;
 }
 
@@ -204,9 +205,10 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
   }
   // state assembly: instance records for this state's transforms
   Phase ph(c, 1);
+  if (!c->bounds.ensure(6 * sizeof(double))) return fail(c, LF_ENOMEM, "bounds");
   lf::launch_instances(M > 0 ? xf->R : nullptr, M > 0 ? xf->t : nullptr, c->rootbox.as<float>(),
                        c->d_first.as<int32_t>(), c->d_n.as<int32_t>(), c->d_root.as<int32_t>(), c->n_inst,
-                       c->inst.as<lf::InstRec>(), c->status.as<uint32_t>(), c->stream);
+                       c->inst.as<lf::InstRec>(), c->bounds.as<double>(), c->status.as<uint32_t>(), c->stream);
   // environment importance-sampling tables
   int H = env->h, W = env->w;
   if (!c->env_cdf_row.ensure(sizeof(double) * (H + 1)) || !c->env_cdf_col.ensure(sizeof(double) * H * (W + 1)) ||
@@ -263,8 +265,25 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
     a.queue_count = c->qcount.as<uint32_t>();
     a.rec2 = c->rec2.as<lf::SurfRec>();
     lf::launch_fill_u32(a.queue_count, 0u, 1, c->stream);
+    if (!(p->flags & LF_FLAG_UNSORTED)) {
+      const int64_t n2 = RS > 0 ? RS : 1;
+      if (!c->skeys.ensure(8 * n2) || !c->skeys2.ensure(8 * n2) || !c->svals.ensure(4 * n2) ||
+          !c->svals2.ensure(4 * n2) || !c->shist.ensure(4 * lf::radix_sort_hist_words(n2)))
+        return fail(c, LF_ENOMEM, "secondary sort buffers");
+      a.order = c->svals.as<int32_t>();
+    }
   }
   return check_hip(c, "prepare");
+}
+
+// regroups the secondary queue by direction octant and origin for coherent traversal
+void sort_secondaries(lf_ctx *c, const lf::RenderArgs &a) {
+  if (!a.order) return;
+  const int64_t cap = a.R * a.P.spp;
+  lf::launch_secondary_keys(a.queue, a.queue_count, cap, c->bounds.as<double>(), c->skeys.as<uint64_t>(),
+                            c->svals.as<int32_t>(), c->stream);
+  lf::radix_sort(c->skeys.as<uint64_t>(), c->svals.as<int32_t>(), c->skeys2.as<uint64_t>(), c->svals2.as<int32_t>(),
+                 c->shist.as<uint32_t>(), cap, c->stream, 32);
 }
 
 }  // namespace
@@ -463,6 +482,7 @@ lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, co
   if (trace2) {
     {
       Phase ph(c, 3);
+      sort_secondaries(c, a);
       lf::launch_trace2(a, c->stream);
       lf::launch_shade2(a, false, c->stream);
     }
@@ -514,6 +534,7 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
   }
   if (trace2) {
     Phase ph(c, 6);
+    sort_secondaries(c, a);
     lf::launch_trace2(a, s);
     lf::launch_shade2(a, true, s);
   }

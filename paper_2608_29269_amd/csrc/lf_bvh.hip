@@ -364,12 +364,13 @@ void launch_morton(const float *box6, const float *inst_bounds, const int32_t *i
 size_t radix_sort_hist_words(int64_t n) { return (size_t)256 * blocks(n > 0 ? n : 1, RS_TILE); }
 
 void radix_sort(uint64_t *keys, int32_t *vals, uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist, int64_t n,
-                hipStream_t st) {
+                hipStream_t st, int key_bits) {
   if (n <= 1) return;
   int nb = (int)blocks(n, RS_TILE);
   uint64_t *ka = keys, *kb = keys_tmp;
   int32_t *va = vals, *vb = vals_tmp;
-  for (int pass = 0; pass < 8; ++pass) {
+  const int passes = (key_bits + 15) / 16 * 2;  // even, so the result lands back in (keys, vals)
+  for (int pass = 0; pass < passes; ++pass) {
     int shift = 8 * pass;
     hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, st, ka, n, shift, hist, nb);
     hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, hist, (int64_t)256 * nb);
@@ -377,7 +378,7 @@ void radix_sort(uint64_t *keys, int32_t *vals, uint64_t *keys_tmp, int32_t *vals
     uint64_t *tk = ka; ka = kb; kb = tk;
     int32_t *tv = va; va = vb; vb = tv;
   }
-  // 8 passes: the result is back in (keys, vals)
+  // an even number of passes: the result is back in (keys, vals)
 }
 
 void launch_karras(const uint64_t *keys, int32_t first, int32_t n, int32_t node_off, int32_t inst, BNode *nodes,

@@ -21,7 +21,7 @@ void launch_morton(const float *box6, const float *inst_bounds, const int32_t *i
 // stable LSD radix sort of (keys, vals); tmp buffers of the same sizes; hist scratch
 size_t radix_sort_hist_words(int64_t n);
 void radix_sort(uint64_t *keys, int32_t *vals, uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist, int64_t n,
-                hipStream_t st);
+                hipStream_t st, int key_bits = 64);
 // Karras (2012) hierarchy of one instance
 void launch_karras(const uint64_t *keys, int32_t first, int32_t n, int32_t node_off, int32_t inst, BNode *nodes,
                    int32_t *node_parent, int32_t *leaf_parent, uint32_t *status, hipStream_t st);
@@ -38,8 +38,11 @@ void launch_fill_f32(float *p, float v, int64_t n, hipStream_t st);
 
 // ---- per-render (lf_render.hip)
 void launch_instances(const float *R, const float *t, const float *root_box6, const int32_t *inst_first,
-                      const int32_t *inst_n, const int32_t *inst_root, int n_inst, InstRec *out, uint32_t *status,
-                      hipStream_t st);
+                      const int32_t *inst_n, const int32_t *inst_root, int n_inst, InstRec *out, double *bounds6,
+                      uint32_t *status, hipStream_t st);
+// sort keys of the secondary queue: (direction octant, origin Morton code); entries past the count sort last
+void launch_secondary_keys(const SecEntry *queue, const uint32_t *count, int64_t cap, const double *bounds6,
+                           uint64_t *keys, int32_t *vals, hipStream_t st);
 void launch_env_tables(const float *tex, int H, int W, uint32_t flags, double *cdf_row, double *cdf_col, double *lum,
                        double *rowsum, double *roww, double *scal, hipStream_t st);
 
@@ -57,6 +60,7 @@ struct RenderArgs {
   SurfRec *rec2;        // [R*S] secondary surface records (queue order)
   SecEntry *queue;      // [R*S]
   uint32_t *queue_count;
+  const int32_t *order; // [R*S] trace order of the queue (sorted for coherence), or NULL
   int32_t *retry;       // [max(R, R*S)] rays / queue entries re-traced with exact keys
   uint32_t *retry_count;
   float *contrib;       // [R*S*3]

@@ -17,61 +17,103 @@ namespace {
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 __global__ void k_instances(const float *R, const float *t, const float *root_box6, const int32_t *first,
-                            const int32_t *cnt, const int32_t *root, int n_inst, InstRec *out, uint32_t *status) {
-  int ii = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ii >= n_inst) return;
-  InstRec I;
-  I.first = first[ii];
-  I.n = cnt[ii];
-  I.root = root[ii];
-  I.identity = ii == 0;
-  const float *rb = root_box6 + 6 * ii;
-  double blo[3] = {rb[0], rb[1], rb[2]}, bhi[3] = {rb[3], rb[4], rb[5]};
-  if (ii == 0) {
-    for (int k = 0; k < 9; ++k) I.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
-    for (int k = 0; k < 3; ++k) I.t[k] = 0.0;
-  } else {
-    const float *A = R + 9 * (ii - 1);
-    // Gram-Schmidt of the first two columns, third = cross product
-    d3 c0 = mk(A[0], A[3], A[6]), c1 = mk(A[1], A[4], A[7]);
-    double l0 = sqrt(dot(c0, c0));
-    bool bad = !(l0 > 1e-6);
-    c0 = (1.0 / l0) * c0;
-    c1 = c1 - dot(c0, c1) * c0;
-    double l1 = sqrt(dot(c1, c1));
-    bad = bad || !(l1 > 1e-6);
-    c1 = (1.0 / l1) * c1;
-    d3 c2 = cross(c0, c1);
-    const float *tt = t + 3 * (ii - 1);
-    bad = bad || !isfinite(tt[0]) || !isfinite(tt[1]) || !isfinite(tt[2]);
-    if (bad) {
-      atomicOr(status, kStatusBadTransform);
+                            const int32_t *cnt, const int32_t *root, int n_inst, InstRec *out, double *bounds6,
+                            uint32_t *status) {
+  const int ii = threadIdx.x;  // one block of kMaxInst threads
+  __shared__ double sb[kMaxInst][6];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (ii < n_inst) {
+    InstRec I;
+    I.first = first[ii];
+    I.n = cnt[ii];
+    I.root = root[ii];
+    I.identity = ii == 0;
+    const float *rb = root_box6 + 6 * ii;
+    const double blo[3] = {rb[0], rb[1], rb[2]}, bhi[3] = {rb[3], rb[4], rb[5]};
+    if (ii == 0) {
+      for (int k = 0; k < 9; ++k) I.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+      for (int k = 0; k < 3; ++k) I.t[k] = 0.0;
+    } else {
+      const float *A = R + 9 * (ii - 1);
+      // Gram-Schmidt of the first two columns, third = cross product
+      d3 c0 = mk(A[0], A[3], A[6]), c1 = mk(A[1], A[4], A[7]);
+      const double l0 = sqrt(dot(c0, c0));
+      bool bad = !(l0 > 1e-6);
+      c0 = (1.0 / l0) * c0;
+      c1 = c1 - dot(c0, c1) * c0;
+      const double l1 = sqrt(dot(c1, c1));
+      bad = bad || !(l1 > 1e-6);
+      c1 = (1.0 / l1) * c1;
+      const d3 c2 = cross(c0, c1);
+      const float *tt = t + 3 * (ii - 1);
+      bad = bad || !isfinite(tt[0]) || !isfinite(tt[1]) || !isfinite(tt[2]);
+      if (bad) {
+        atomicOr(status, kStatusBadTransform);
+        I.n = 0;
+      }
+      I.R[0] = c0.x; I.R[1] = c1.x; I.R[2] = c2.x;
+      I.R[3] = c0.y; I.R[4] = c1.y; I.R[5] = c2.y;
+      I.R[6] = c0.z; I.R[7] = c1.z; I.R[8] = c2.z;
+      for (int k = 0; k < 3; ++k) I.t[k] = tt[k];
+    }
+    // world bounds: transformed corners of the object-space root box, padded
+    if (I.n > 0 && blo[0] <= bhi[0]) {
+      for (int c = 0; c < 8; ++c) {
+        const d3 p = mk((c & 1) ? bhi[0] : blo[0], (c & 2) ? bhi[1] : blo[1], (c & 4) ? bhi[2] : blo[2]);
+        const d3 w = mul(I.R, p) + mk(I.t[0], I.t[1], I.t[2]);
+        const double ww[3] = {w.x, w.y, w.z};
+        for (int k = 0; k < 3; ++k) { lo[k] = fmin(lo[k], ww[k]); hi[k] = fmax(hi[k], ww[k]); }
+      }
+      for (int k = 0; k < 3; ++k) {
+        const double pad = 1e-9 * (fabs(lo[k]) + fabs(hi[k])) + 1e-30;
+        lo[k] -= pad;
+        hi[k] += pad;
+      }
+    } else {
       I.n = 0;
     }
-    I.R[0] = c0.x; I.R[1] = c1.x; I.R[2] = c2.x;
-    I.R[3] = c0.y; I.R[4] = c1.y; I.R[5] = c2.y;
-    I.R[6] = c0.z; I.R[7] = c1.z; I.R[8] = c2.z;
-    for (int k = 0; k < 3; ++k) I.t[k] = tt[k];
+    for (int k = 0; k < 3; ++k) { I.lo[k] = lo[k]; I.hi[k] = hi[k]; }
+    out[ii] = I;
+    for (int k = 0; k < 3; ++k) { sb[ii][k] = lo[k]; sb[ii][3 + k] = hi[k]; }
   }
-  // world bounds: transformed corners of the object-space root box, padded
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  if (I.n > 0 && blo[0] <= bhi[0]) {
-    for (int c = 0; c < 8; ++c) {
-      d3 p = mk((c & 1) ? bhi[0] : blo[0], (c & 2) ? bhi[1] : blo[1], (c & 4) ? bhi[2] : blo[2]);
-      d3 w = mul(I.R, p) + mk(I.t[0], I.t[1], I.t[2]);
-      const double ww[3] = {w.x, w.y, w.z};
-      for (int k = 0; k < 3; ++k) { lo[k] = fmin(lo[k], ww[k]); hi[k] = fmax(hi[k], ww[k]); }
-    }
-    for (int k = 0; k < 3; ++k) {
-      double pad = 1e-9 * (fabs(lo[k]) + fabs(hi[k])) + 1e-30;
-      lo[k] -= pad;
-      hi[k] += pad;
-    }
-  } else {
-    I.n = 0;
+  __syncthreads();
+  // union of the instance bounds
+  if (ii == 0) {
+    double u[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int j = 0; j < n_inst; ++j)
+      for (int k = 0; k < 3; ++k) { u[k] = fmin(u[k], sb[j][k]); u[3 + k] = fmax(u[3 + k], sb[j][3 + k]); }
+    for (int k = 0; k < 6; ++k) bounds6[k] = u[k];
   }
-  for (int k = 0; k < 3; ++k) { I.lo[k] = lo[k]; I.hi[k] = hi[k]; }
-  out[ii] = I;
+}
+
+__device__ __forceinline__ uint32_t spread3_10(uint32_t x) {
+  x &= 0x3ffu;
+  x = (x | (x << 16)) & 0x030000ffu;
+  x = (x | (x << 8)) & 0x0300f00fu;
+  x = (x | (x << 4)) & 0x030c30c3u;
+  x = (x | (x << 2)) & 0x09249249u;
+  return x;
+}
+
+__global__ void k_secondary_keys(const SecEntry *queue, const uint32_t *count, int64_t cap, const double *b,
+                                 uint64_t *keys, int32_t *vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cap) return;
+  vals[i] = (int32_t)i;
+  if (i >= (int64_t)*count) {
+    keys[i] = 0xffffffffull;
+    return;
+  }
+  const SecEntry e = queue[i];
+  uint32_t c[3];
+  for (int k = 0; k < 3; ++k) {
+    const double ext = b[3 + k] - b[k];
+    double x = ext > 0.0 ? (e.o[k] - b[k]) / ext : 0.5;
+    x = fmin(fmax(x, 0.0), 1.0);
+    c[k] = (uint32_t)fmin(x * 512.0, 511.0);  // 9 bits per axis
+  }
+  const uint32_t oct = (e.w[0] < 0.0 ? 1u : 0u) | (e.w[1] < 0.0 ? 2u : 0u) | (e.w[2] < 0.0 ? 4u : 0u);
+  keys[i] = ((uint64_t)oct << 27) | (spread3_10(c[0]) << 2) | (spread3_10(c[1]) << 1) | spread3_10(c[2]);
 }
 
 // one block per env row: clamped luminance, row sum, conditional CDF (double)
@@ -312,8 +354,9 @@ __global__ __launch_bounds__(kBlock) void k_trace2(RenderArgs a) {
   __shared__ int stk[kStack * kBlock];
   const uint32_t count = *a.queue_count;
   if (blockIdx.x * kBlock >= count) return;  // whole block past the queue
-  const uint32_t qi = blockIdx.x * kBlock + threadIdx.x;
-  const bool active = qi < count;
+  const uint32_t slot = blockIdx.x * kBlock + threadIdx.x;
+  const bool active = slot < count;
+  const uint32_t qi = active ? (a.order ? (uint32_t)a.order[slot] : slot) : 0u;
   SecEntry e;
   d3 o = mk(0, 0, 0), w = mk(0, 0, 1);
   if (active) {
@@ -439,10 +482,17 @@ void trace2_k(const RenderArgs &a, hipStream_t st) {
 }  // namespace
 
 void launch_instances(const float *R, const float *t, const float *root_box6, const int32_t *inst_first,
-                      const int32_t *inst_n, const int32_t *inst_root, int n_inst, InstRec *out, uint32_t *status,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(k_instances, dim3(1), dim3(64), 0, st, R, t, root_box6, inst_first, inst_n, inst_root, n_inst,
-                     out, status);
+                      const int32_t *inst_n, const int32_t *inst_root, int n_inst, InstRec *out, double *bounds6,
+                      uint32_t *status, hipStream_t st) {
+  hipLaunchKernelGGL(k_instances, dim3(1), dim3(kMaxInst), 0, st, R, t, root_box6, inst_first, inst_n, inst_root,
+                     n_inst, out, bounds6, status);
+}
+
+void launch_secondary_keys(const SecEntry *queue, const uint32_t *count, int64_t cap, const double *bounds6,
+                           uint64_t *keys, int32_t *vals, hipStream_t st) {
+  if (cap <= 0) return;
+  hipLaunchKernelGGL(k_secondary_keys, dim3(blocks(cap, 256)), dim3(256), 0, st, queue, count, cap, bounds6, keys,
+                     vals);
 }
 
 void launch_env_tables(const float *tex, int H, int W, uint32_t flags, double *cdf_row, double *cdf_col, double *lum,

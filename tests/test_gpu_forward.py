@@ -216,3 +216,18 @@ def test_bvh_structure_and_refit(tracer, c2_small):
     o, d, ids = oracle.raygen(cam, pix)
     ref = run_oracle(moved, st, o, d, ids, 32, 1, 5, 1)
     _compare({k: v[pix] for k, v in out.items()}, ref, ambiguous(ref["margins"], False))
+
+
+def test_secondary_regrouping_is_transparent(tracer, c2_small):
+    """Tracing the secondary queue in regrouped order gives bitwise the same
+    outputs as tracing it in queue order."""
+    import paper_2608_29269_amd as lf
+    wl = c2_small
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    a = tracer.render(**state_args(tracer, wl.scene, st), cameras=st.cameras, k=32, spp=4, seed=2,
+                      sec_hit_idx=True)
+    b = tracer.render(**state_args(tracer, wl.scene, st), cameras=st.cameras, k=32, spp=4, seed=2,
+                      sec_hit_idx=True, flags=lf._lib.FLAG_UNSORTED)
+    for key in a:
+        assert np.array_equal(a[key].cpu().numpy(), b[key].cpu().numpy()), key
