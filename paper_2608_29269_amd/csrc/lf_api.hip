@@ -59,7 +59,8 @@ struct lf_ctx {
   double built_alpha_min = 0, built_sig2 = 0;
   DevBuf d_first, d_n, d_root;
   DevBuf rec, filt, nodes, perm, leaf_parent, node_parent, flags, leafbox, rootbox, inst, status;
-  DevBuf keys, keys2, vals2, hist, boxidx, ibounds, depth;
+  DevBuf keys, keys2, vals2, hist, boxidx, ibounds, depth, nodes4, flag4, idx4;
+  int64_t n_nodes4 = 0;
   // per call
   DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;
   DevBuf queue, qcount, contrib, frozen, l1acc, cams, rec1, rec2, retry, rcount, seeds;
@@ -136,6 +137,8 @@ lf_status refit_impl(lf_ctx *c, double alpha_min, double sig2) {
                    c->node_parent.as<int32_t>(), c->flags.as<int32_t>(), c->n_nodes, c->n_inst,
                    c->nodes.as<lf::BNode>(), c->rec.as<lf::TraceRec>(), c->filt.as<lf::FiltRec>(),
                    c->leafbox.as<float>(), c->rootbox.as<float>(), c->status.as<uint32_t>(), c->stream);
+  lf::launch_collapse(c->nodes.as<lf::BNode>(), c->flag4.as<uint32_t>(), c->idx4.as<uint32_t>(), c->n_nodes,
+                      c->nodes4.as<lf::BNode4>(), c->status.as<uint32_t>(), c->stream);
   c->built_alpha_min = alpha_min;
   c->built_sig2 = sig2;
   return check_hip(c, "refit");
@@ -220,11 +223,11 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
                         c->env_scal.as<double>(), c->stream);
   a.S.rec = c->rec.as<lf::TraceRec>();
   a.S.filt = c->filt.as<lf::FiltRec>();
-  a.S.nodes = c->nodes.as<lf::BNode>();
+  a.S.nodes = c->nodes4.as<lf::BNode4>();
   a.S.inst = c->inst.as<lf::InstRec>();
   a.S.n_inst = c->n_inst;
   a.S.n_rec = (int32_t)c->s.n;
-  a.S.n_nodes = (int32_t)c->n_nodes;
+  a.S.n_nodes = (int32_t)c->n_nodes4;
   a.S.mu = c->s.mu; a.S.q = c->s.q; a.S.scale = c->s.scale; a.S.opacity = c->s.opacity;
   a.S.albedo = c->s.albedo; a.S.roughness = c->s.roughness; a.S.metallic = c->s.metallic;
   a.P.k = p->k;
@@ -426,6 +429,34 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
   lf::launch_fill_u32(c->depth.as<uint32_t>(), 0u, 1, st);
   lf::launch_depth(c->leaf_parent.as<int32_t>(), c->node_parent.as<int32_t>(), n, c->n_nodes,
                    c->depth.as<int32_t>(), c->status.as<uint32_t>(), st);
+  // 4-wide hierarchy: index of every even-depth internal node, roots remapped
+  const int64_t nn = nodes ? nodes : 1;
+  if (!c->flag4.ensure(4 * nn) || !c->idx4.ensure(4 * nn)) return fail(c, LF_ENOMEM, "4-wide index");
+  lf::launch_wide_index(c->node_parent.as<int32_t>(), c->n_nodes, c->flag4.as<uint32_t>(), c->idx4.as<uint32_t>(),
+                        c->status.as<uint32_t>(), st);
+  c->n_nodes4 = 0;
+  if (nodes > 0) {
+    uint32_t last_idx = 0, last_flag = 0;
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(&last_idx, c->idx4.as<uint32_t>() + nodes - 1, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(&last_flag, c->flag4.as<uint32_t>() + nodes - 1, 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return check_hip(c, "4-wide index");
+    c->n_nodes4 = (int64_t)last_idx + last_flag;
+    std::vector<int32_t> root4(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+      root4[i] = c->h_root[i];
+      if (c->h_n[i] >= 2) {
+        uint32_t r = 0;
+        if (hipMemcpy(&r, c->idx4.as<uint32_t>() + c->h_root[i], 4, hipMemcpyDeviceToHost) != hipSuccess)
+          return check_hip(c, "4-wide roots");
+        root4[i] = (int32_t)r;
+      }
+    }
+    if (hipMemcpy(c->d_root.p, root4.data(), 4 * n_inst, hipMemcpyHostToDevice) != hipSuccess)
+      return check_hip(c, "4-wide roots");
+  }
+  if (!c->nodes4.ensure(sizeof(lf::BNode4) * (c->n_nodes4 ? c->n_nodes4 : 1)))
+    return fail(c, LF_ENOMEM, "4-wide nodes");
   lf_status s2 = refit_impl(c, dp.alpha_min, sig2);
   if (s2) return s2;
   if (hipStreamSynchronize(st) != hipSuccess) return check_hip(c, "scene build");
@@ -437,8 +468,10 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
     lf::launch_fill_u32(c->status.as<uint32_t>(), 0u, 1, st);
     return fail(c, LF_EDEVICE, "hierarchy build produced an out-of-range index");
   }
-  if (c->max_depth > lf::kStack)
-    return fail(c, LF_EUNSUPPORTED, "hierarchy depth %d exceeds the traversal stack (%d)", c->max_depth, lf::kStack);
+  // a 4-wide step pushes at most three entries and halves the depth
+  if (3 * ((c->max_depth + 1) / 2) > lf::kStack)
+    return fail(c, LF_EUNSUPPORTED, "hierarchy depth %d needs more than the traversal stack (%d)", c->max_depth,
+                lf::kStack);
   c->has_scene = true;
   return check_hip(c, "scene build");
 }

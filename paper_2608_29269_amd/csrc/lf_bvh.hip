@@ -331,6 +331,71 @@ __global__ void k_refit(SurfelArrays s, double alpha_min, double sig2, const int
   for (int k = 0; k < 3; ++k) { root_box6[6 * inst + k] = lo[k]; root_box6[6 * inst + 3 + k] = hi[k]; }
 }
 
+// depth of every internal node (root = 0) and the flag "starts a 4-wide node"
+__global__ void k_node_depth(const int32_t *node_parent, int64_t n_nodes, uint32_t *flag, uint32_t *status) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_nodes) return;
+  int dep = 0;
+  int p = node_parent[i];
+  while (p >= 0) {
+    if ((p >> 1) >= n_nodes || dep > 4096) {
+      atomicOr(status, kStatusBvhCorrupt);
+      break;
+    }
+    ++dep;
+    p = node_parent[p >> 1];
+  }
+  flag[i] = (dep & 1) == 0 ? 1u : 0u;
+}
+
+__device__ __forceinline__ void put_child(BNode4 &q, int slot, int32_t child, const float *lo, const float *hi) {
+  q.lox[slot] = lo[0]; q.loy[slot] = lo[1]; q.loz[slot] = lo[2];
+  q.hix[slot] = hi[0]; q.hiy[slot] = hi[1]; q.hiz[slot] = hi[2];
+  q.child[slot] = child;
+}
+
+// 4-wide node of every even-depth binary node: its leaf children and the
+// children of its internal children, with the boxes the refit stored
+__global__ void k_collapse(const BNode *nodes, const uint32_t *flag, const uint32_t *idx4, int64_t n_nodes,
+                           BNode4 *out, uint32_t *status) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_nodes || !flag[b]) return;
+  const BNode nb = nodes[b];
+  BNode4 q;
+  for (int s = 0; s < 4; ++s) {
+    q.lox[s] = q.loy[s] = q.loz[s] = INFINITY;
+    q.hix[s] = q.hiy[s] = q.hiz[s] = -INFINITY;
+    q.child[s] = 0;
+    q.pad[s] = 0;
+  }
+  int slot = 0;
+  for (int side = 0; side < 2; ++side) {
+    const int32_t c = side ? nb.c1 : nb.c0;
+    if (c < 0) {
+      put_child(q, slot++, c, side ? nb.lo1 : nb.lo0, side ? nb.hi1 : nb.hi0);
+      continue;
+    }
+    if (c >= n_nodes) {
+      atomicOr(status, kStatusBvhCorrupt);
+      return;
+    }
+    const BNode nc = nodes[c];
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int32_t g = s2 ? nc.c1 : nc.c0;
+      int32_t e = g;
+      if (g >= 0) {
+        if (g >= n_nodes || !flag[g]) {
+          atomicOr(status, kStatusBvhCorrupt);
+          return;
+        }
+        e = (int32_t)idx4[g];
+      }
+      put_child(q, slot++, e, s2 ? nc.lo1 : nc.lo0, s2 ? nc.hi1 : nc.hi0);
+    }
+  }
+  out[idx4[b]] = q;
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -404,6 +469,21 @@ void launch_refit(const SurfelArrays &s, double alpha_min, double sig2, const in
   if (n_nodes > 0) launch_fill_u32((uint32_t *)flags, 0u, n_nodes, st);
   hipLaunchKernelGGL(k_refit, dim3(blocks(s.n, 256)), dim3(256), 0, st, s, alpha_min, sig2, perm, leaf_parent,
                      node_parent, flags, nodes, n_nodes, n_inst, rec, filt, leaf_box6, root_box6, status);
+}
+
+void launch_wide_index(const int32_t *node_parent, int64_t n_nodes, uint32_t *flag, uint32_t *idx4,
+                       uint32_t *status, hipStream_t st) {
+  if (n_nodes <= 0) return;
+  hipLaunchKernelGGL(k_node_depth, dim3(blocks(n_nodes, 256)), dim3(256), 0, st, node_parent, n_nodes, flag, status);
+  hipMemcpyAsync(idx4, flag, sizeof(uint32_t) * n_nodes, hipMemcpyDeviceToDevice, st);
+  hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, idx4, n_nodes);
+}
+
+void launch_collapse(const BNode *nodes, const uint32_t *flag, const uint32_t *idx4, int64_t n_nodes, BNode4 *out,
+                     uint32_t *status, hipStream_t st) {
+  if (n_nodes <= 0) return;
+  hipLaunchKernelGGL(k_collapse, dim3(blocks(n_nodes, 256)), dim3(256), 0, st, nodes, flag, idx4, n_nodes, out,
+                     status);
 }
 
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {

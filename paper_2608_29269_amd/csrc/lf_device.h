@@ -252,36 +252,67 @@ __device__ __forceinline__ bool slab64(d3 o, d3 d, const double *lo, const doubl
   return tn <= tf;
 }
 
-// Binary32 view of the object-space ray.  (lo - (o + pad), hi - (o - pad))
-// tests the box grown by pad on every side whatever the direction's sign, so
-// with pad >= the rounding error of the ray over the instance's parameter
-// range the slab tests never cull a box the exact ray enters.
+// Binary32 view of the object-space ray for the slab tests.  The near plane
+// of each axis is the low one for a non-negative direction component and the
+// high one otherwise; near planes are met from origin + pad and far planes
+// from origin - pad (signs follow the direction), i.e. every box is grown by
+// pad, with pad >= the rounding error of the binary32 ray over the instance's
+// parameter range, so a box the exact ray enters is never culled.  A box with
+// lo > hi (empty) always misses.
 struct RayF {
-  float ax, ay, az;   // origin + pad (low planes)
-  float bx, by, bz;   // origin - pad (high planes)
-  float ix, iy, iz;   // 1/d
-  float ox, oy, oz;   // origin
-  float dx, dy, dz;   // direction
-  float oabs;         // max |origin component|
+  float nox, noy, noz;   // origin used against near planes
+  float fox, foy, foz;   // origin used against far planes
+  float ix, iy, iz;      // 1/d
+  bool sx, sy, sz;       // d >= 0 per axis
+  float ox, oy, oz;      // origin
+  float dx, dy, dz;      // direction
+  float oabs;            // max |origin component|
 };
-
-__device__ __forceinline__ void child_test(const RayF &r, const float *lo, const float *hi, float tlo, float thi,
-                                           bool &hit, float &tn) {
-  float t0x = (lo[0] - r.ax) * r.ix, t1x = (hi[0] - r.bx) * r.ix;
-  float t0y = (lo[1] - r.ay) * r.iy, t1y = (hi[1] - r.by) * r.iy;
-  float t0z = (lo[2] - r.az) * r.iz, t1z = (hi[2] - r.bz) * r.iz;
-  float n = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tlo));
-  float f = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), thi));
-  // widen by the rounding of the subtraction, product and reciprocal (Ize 2013)
-  n = n - 1e-6f * fabsf(n);
-  f = f + 1e-6f * fabsf(f);
-  hit = n <= f;
-  tn = n;
-}
 
 __device__ __forceinline__ float inv_dir(float d) {
   float dd = fabsf(d) < 1e-20f ? copysignf(1e-20f, d) : d;
   return 1.0f / dd;
+}
+
+__device__ __forceinline__ void make_rayf(d3 oo, d3 dd, double tabs, RayF &rf) {
+  rf.ox = (float)oo.x; rf.oy = (float)oo.y; rf.oz = (float)oo.z;
+  rf.dx = (float)dd.x; rf.dy = (float)dd.y; rf.dz = (float)dd.z;
+  rf.oabs = fmaxf(fmaxf(fabsf(rf.ox), fabsf(rf.oy)), fabsf(rf.oz));
+  const double eo = fmax(fmax(fabs(oo.x - rf.ox), fabs(oo.y - rf.oy)), fabs(oo.z - rf.oz));
+  const double ed = fmax(fmax(fabs(dd.x - rf.dx), fabs(dd.y - rf.dy)), fabs(dd.z - rf.dz));
+  const float pad = (float)((eo + ed * tabs + 1e-30) * 1.001) + 1e-30f;
+  rf.ix = inv_dir(rf.dx); rf.iy = inv_dir(rf.dy); rf.iz = inv_dir(rf.dz);
+  rf.sx = rf.ix >= 0.f; rf.sy = rf.iy >= 0.f; rf.sz = rf.iz >= 0.f;
+  rf.nox = rf.sx ? rf.ox + pad : rf.ox - pad;
+  rf.noy = rf.sy ? rf.oy + pad : rf.oy - pad;
+  rf.noz = rf.sz ? rf.oz + pad : rf.oz - pad;
+  rf.fox = rf.sx ? rf.ox - pad : rf.ox + pad;
+  rf.foy = rf.sy ? rf.oy - pad : rf.oy + pad;
+  rf.foz = rf.sz ? rf.oz - pad : rf.oz + pad;
+}
+
+// one box: entry t, or +inf if the (conservative) test misses
+__device__ __forceinline__ void child_test4(const RayF &r, float lx, float ly, float lz, float hx, float hy, float hz,
+                                            float tlo, float thi, float &tn) {
+  const float nx = r.sx ? lx : hx, fx = r.sx ? hx : lx;
+  const float ny = r.sy ? ly : hy, fy = r.sy ? hy : ly;
+  const float nz = r.sz ? lz : hz, fz = r.sz ? hz : lz;
+  float n = fmaxf(fmaxf((nx - r.nox) * r.ix, (ny - r.noy) * r.iy), fmaxf((nz - r.noz) * r.iz, tlo));
+  float f = fminf(fminf((fx - r.fox) * r.ix, (fy - r.foy) * r.iy), fminf((fz - r.foz) * r.iz, thi));
+  // widen by the rounding of the subtraction, product and reciprocal (Ize 2013)
+  n = n - 1e-6f * fabsf(n);
+  f = f + 1e-6f * fabsf(f);
+  tn = (n <= f) ? n : INFINITY;
+}
+
+__device__ __forceinline__ void cswap(float &ta, int &ca, float &tb, int &cb) {
+  const bool sw = tb < ta;
+  const float t = sw ? tb : ta;
+  const int c = sw ? cb : ca;
+  tb = sw ? ta : tb;
+  cb = sw ? ca : cb;
+  ta = t;
+  ca = c;
 }
 
 // Exact (double) plane intersection and support test of the surfel at leaf
@@ -404,17 +435,7 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
     d3 oo, dd;
     to_object(I, o, d, oo, dd);
     RayF rf;
-    rf.ox = (float)oo.x; rf.oy = (float)oo.y; rf.oz = (float)oo.z;
-    rf.dx = (float)dd.x; rf.dy = (float)dd.y; rf.dz = (float)dd.z;
-    rf.oabs = fmaxf(fmaxf(fabsf(rf.ox), fabsf(rf.oy)), fabsf(rf.oz));
-    {
-      double eo = fmax(fmax(fabs(oo.x - rf.ox), fabs(oo.y - rf.oy)), fabs(oo.z - rf.oz));
-      double ed = fmax(fmax(fabs(dd.x - rf.dx), fabs(dd.y - rf.dy)), fabs(dd.z - rf.dz));
-      float pad = (float)((eo + ed * fmax(fabs(itf), fabs(itn)) + 1e-30) * 1.001) + 1e-30f;
-      rf.ax = rf.ox + pad; rf.ay = rf.oy + pad; rf.az = rf.oz + pad;
-      rf.bx = rf.ox - pad; rf.by = rf.oy - pad; rf.bz = rf.oz - pad;
-      rf.ix = inv_dir(rf.dx); rf.iy = inv_dir(rf.dy); rf.iz = inv_dir(rf.dz);
-    }
+    make_rayf(oo, dd, fmax(fabs(itf), fabs(itn)), rf);
     if (brute) {
       const int end = I.first + I.n <= S.n_rec ? I.first + I.n : S.n_rec;
       for (int pos = I.first < 0 ? 0 : I.first; pos < end; ++pos) {
@@ -433,29 +454,36 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
       }
       if (cur >= 0) {
         ++c_nodes;
-        const BNode nd = S.nodes[cur];
+        const BNode4 &nd = S.nodes[cur];
+        const float4 lx = *(const float4 *)nd.lox, ly = *(const float4 *)nd.loy, lz = *(const float4 *)nd.loz;
+        const float4 hx = *(const float4 *)nd.hix, hy = *(const float4 *)nd.hiy, hz = *(const float4 *)nd.hiz;
+        const int4 ch = *(const int4 *)nd.child;
         const double tk = kth<K>(kb);
         const float thi = tk < INFINITY ? round_up_f(tk) * (1.0f + 1e-6f) : INFINITY;
-        bool h0, h1;
-        float tn0, tn1;
-        child_test(rf, nd.lo0, nd.hi0, tlo, thi, h0, tn0);
-        child_test(rf, nd.lo1, nd.hi1, tlo, thi, h1, tn1);
-        if (h0 && h1) {
-          const int nr = tn0 <= tn1 ? nd.c0 : nd.c1;
-          const int fr = tn0 <= tn1 ? nd.c1 : nd.c0;
-          if (sp >= kStack) {
+        float t0, t1, t2, t3;
+        child_test4(rf, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tlo, thi, t0);
+        child_test4(rf, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tlo, thi, t1);
+        child_test4(rf, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, tlo, thi, t2);
+        child_test4(rf, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, tlo, thi, t3);
+        int c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
+        // sort the four (entry t, child) pairs, misses carry +inf
+        cswap(t0, c0, t1, c1);
+        cswap(t2, c2, t3, c3);
+        cswap(t0, c0, t2, c2);
+        cswap(t1, c1, t3, c3);
+        cswap(t1, c1, t2, c2);
+        if (t0 == INFINITY) {
+          // no child hit: pop below
+        } else {
+          const int nhit = 1 + (t1 < INFINITY) + (t2 < INFINITY) + (t3 < INFINITY);
+          if (sp + nhit - 1 > kStack) {
             atomicOr(status, kStatusOverflow);
             break;
           }
-          stk[sp * kBlock] = fr;
-          ++sp;
-          cur = nr;
-          continue;
-        } else if (h0) {
-          cur = nd.c0;
-          continue;
-        } else if (h1) {
-          cur = nd.c1;
+          if (t3 < INFINITY) stk[(sp++) * kBlock] = c3;
+          if (t2 < INFINITY) stk[(sp++) * kBlock] = c2;
+          if (t1 < INFINITY) stk[(sp++) * kBlock] = c1;
+          cur = c0;
           continue;
         }
       } else {

@@ -51,13 +51,25 @@ struct alignas(16) BNode {
 };
 static_assert(sizeof(BNode) == 64, "BNode layout");
 
+// 4-wide node used by traversal, 128 bytes (one cache line): the binary
+// hierarchy collapsed so that every internal node at even depth holds its
+// (up to four) grandchildren.  Child >= 0: 4-wide node index (global); < 0:
+// ~leaf position; unused slots have an empty box (lo > hi).
+struct alignas(16) BNode4 {
+  float lox[4], loy[4], loz[4];
+  float hix[4], hiy[4], hiz[4];
+  int32_t child[4];
+  int32_t pad[4];
+};
+static_assert(sizeof(BNode4) == 128, "BNode4 layout");
+
 // One instance of the two-level scene for the current state: background
 // (identity) or an object with its rigid transform.
 struct alignas(16) InstRec {
   double R[9];      // object -> world rotation (orthonormalised), row-major
   double t[3];      // object -> world translation
   double lo[3], hi[3];  // world-space bounds of the instance (conservative)
-  int32_t root;     // root node (>= 0), ~leaf (< 0) for one surfel; unused if n == 0
+  int32_t root;     // root 4-wide node (>= 0), ~leaf (< 0) for one surfel; unused if n == 0
   int32_t identity; // 1: background (no transform)
   int32_t first;    // first surfel index / leaf position of the instance
   int32_t n;        // surfel count
@@ -66,11 +78,11 @@ struct alignas(16) InstRec {
 struct SceneView {
   const TraceRec *rec;   // [N] leaf order
   const FiltRec *filt;   // [N] leaf order
-  const BNode *nodes;    // internal nodes of all instances
+  const BNode4 *nodes;   // 4-wide nodes of all instances
   const InstRec *inst;   // [n_inst]
   int32_t n_inst;
   int32_t n_rec;         // N
-  int32_t n_nodes;       // internal nodes over all instances
+  int32_t n_nodes;       // 4-wide nodes over all instances
   const float *mu, *q, *scale, *opacity, *albedo, *roughness, *metallic;  // caller arrays (orig index)
 };
 

@@ -33,6 +33,12 @@ void launch_refit(const SurfelArrays &s, double alpha_min, double sig2, const in
                   const int32_t *leaf_parent, const int32_t *node_parent, int32_t *flags, int64_t n_nodes,
                   int n_inst, BNode *nodes, TraceRec *rec, FiltRec *filt, float *leaf_box6, float *root_box6,
                   uint32_t *status, hipStream_t st);
+// 4-wide hierarchy: flags of even-depth internal nodes and their exclusive prefix sum (index of the 4-wide node)
+void launch_wide_index(const int32_t *node_parent, int64_t n_nodes, uint32_t *flag, uint32_t *idx4,
+                       uint32_t *status, hipStream_t st);
+// 4-wide nodes from the refitted binary nodes
+void launch_collapse(const BNode *nodes, const uint32_t *flag, const uint32_t *idx4, int64_t n_nodes, BNode4 *out,
+                     uint32_t *status, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t st);
 

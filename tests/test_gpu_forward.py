@@ -175,7 +175,8 @@ def test_bvh_structure_and_refit(tracer, c2_small):
     wl = c2_small
     ts = upload_scene(tracer, wl.scene)
     info = tracer.info()
-    assert info["max_depth"] <= info["stack_size"]
+    # a 4-wide traversal step pushes at most 3 entries and covers two levels
+    assert 3 * ((info["max_depth"] + 1) // 2) <= info["stack_size"]
 
     def check():
         boxes, ch, perm, leaf = tracer.copy_bvh(0)
