@@ -240,6 +240,87 @@ lf_status lf_trace_counters(lf_ctx *ctx, uint64_t *counters /*[8]*/);
 lf_status lf_profile_enable(lf_ctx *ctx, int enable);
 lf_status lf_profile_read(lf_ctx *ctx, double *ms /*[LF_NUM_PHASES]*/, int64_t *count /*[LF_NUM_PHASES]*/);
 
+/* ---------------------------------------------------------------------------
+ * Relight server.  Rearranging objects or relighting re-renders the resident
+ * scene with new object transforms and a new environment map (Sec. 4,
+ * rearrangement and relighting; Sec. 1, appearance recomputed after every
+ * interaction).  The server renders many such requests at once by
+ * continuous batching: every iteration is one batched forward pass (primary
+ * trace, shading, secondary trace, shading, resolve) over 128-ray chunks
+ * drawn round robin from all admitted requests, each with its own
+ * transforms, environment, camera, S and seed.  A request's outputs equal
+ * those of lf_render with the same inputs bit for bit (ray ids and sampler
+ * counters are local to the request).
+ *
+ * Admission is FIFO: a waiting request is admitted when one of max_slots is
+ * free and the sum of the working sets of admitted requests stays within
+ * hbm_budget_bytes.  The working set of a request of R = w*h rays and S
+ * samples is charged as R*(32 + 44*S) bytes (outputs and its share of the
+ * secondary-ray state) plus its environment copy and sampling tables.
+ * Buffers the server allocates up front (batch scratch sized by batch_rays
+ * and max_spp, one environment slot per request slot) are not charged.
+ *
+ * The server has its own HIP stream and host thread.  It reads the context's
+ * scene: lf_scene_set and lf_scene_refit return LF_EBUSY while a server of
+ * the context exists, and every server must be destroyed before its context.
+ * The server functions are thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct lf_server lf_server;
+
+typedef struct {
+  int32_t max_slots;        /* requests admitted at once, 1..64 (default 16) */
+  int64_t hbm_budget_bytes; /* admission budget of the admitted working sets (default 16 GiB) */
+  int32_t tile_rays;        /* smallest share of primary rays a request gets per iteration;
+                               multiple of 128 (default 65536) */
+  int32_t batch_rays;       /* primary rays per iteration, multiple of 128, >= tile_rays (default 262144) */
+  int32_t max_spp;          /* largest S a request may ask for, 1..64 (default 4) */
+  int32_t max_pending;      /* waiting requests before lf_server_submit returns LF_EBUSY (default 4096) */
+  lf_params params;         /* k, constants and flags shared by every request (spp and seed are
+                               per request; LF_FLAG_COUNT and LF_FLAG_NO_SECONDARY are not served) */
+} lf_server_config;
+void lf_server_config_default(lf_server_config *cfg);
+
+/* One render request.  Every buffer must stay valid until the request has
+ * completed (lf_server_poll reports done or lf_server_wait returned). */
+typedef struct {
+  lf_transforms xf;   /* host or device [M,3,3] and [M,3] (NULL if M == 0) */
+  lf_envmap env;      /* host or device texels; copied into the request's slot on admission */
+  lf_camera cam;      /* one pinhole camera; R = cam.w * cam.h rays, ids from 0 */
+  int32_t spp;        /* S, 1..max_spp */
+  uint64_t seed;      /* sampler seed */
+  lf_outputs out;     /* device radiance/depth/normal/alpha with R rows; hit_idx and
+                         sec_hit_idx must be NULL */
+} lf_request;
+
+/* Creates a server over ctx's current scene (synchronises ctx's stream). */
+lf_status lf_server_create(lf_ctx *ctx, const lf_server_config *cfg, lf_server **out);
+/* Validates and enqueues a request; non-blocking.  LF_EBUSY if max_pending
+ * requests are waiting, LF_EUNSUPPORTED if its working set alone exceeds the
+ * budget (both count as rejected).  *ticket >= 1 identifies it. */
+lf_status lf_server_submit(lf_server *srv, const lf_request *req, uint64_t *ticket);
+/* *done = 1 once the request has completed; returns the request's status
+ * (LF_OK, or the error that ended it; LF_EINVAL for an unknown ticket). */
+lf_status lf_server_poll(lf_server *srv, uint64_t ticket, int *done);
+/* Blocks until the request has completed; returns its status. */
+lf_status lf_server_wait(lf_server *srv, uint64_t ticket);
+/* Milliseconds from submission to completion of a completed request. */
+lf_status lf_server_latency(lf_server *srv, uint64_t ticket, double *ms);
+
+typedef struct {
+  double p50_ms, p99_ms;   /* latency percentiles over completed requests (nearest rank) */
+  double rays_per_s;       /* traced rays (primary + live secondary) per second of serving
+                              (first submission to last completion) */
+  int64_t completed, rejected;
+  int64_t rays_primary, rays_secondary;
+  int64_t iterations;      /* batched passes launched */
+} lf_server_stats;
+lf_status lf_server_stats_get(lf_server *srv, lf_server_stats *stats);
+/* Message of the server's last error (never NULL). */
+const char *lf_server_last_error(lf_server *srv);
+/* Finishes the iterations in flight, cancels requests not yet completed
+ * (their status becomes LF_EBUSY) and frees the server. */
+void lf_server_destroy(lf_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,9 @@ provides device memory and the stream; every step runs in the HIP library.
     out = tr.render(env, R, t, cameras=[cam], k=32, spp=1, seed=7)
     grads = tr.render_backward(env, R, t, cameras=[cam], ..., d_radiance=...)
 
-`RenderFn` wraps the pair as a torch.autograd.Function.
+`RenderFn` wraps the pair as a torch.autograd.Function.  `Server` serves
+rearrange-and-relight requests against the tracer's scene by continuous
+batching (lf_server_*).
 """
 from __future__ import annotations
 
@@ -20,7 +22,7 @@ from . import _lib
 from ._lib import (FLAG_BRUTE_FORCE, FLAG_COUNT, FLAG_BSDF_ONLY, FLAG_DIFFUSE_ONLY, FLAG_NO_BACKGROUND, FLAG_NO_SECONDARY,
                    LFError)
 
-__all__ = ["Tracer", "RenderFn", "LFError", "FLAG_NO_SECONDARY", "FLAG_NO_BACKGROUND", "FLAG_BSDF_ONLY",
+__all__ = ["Tracer", "RenderFn", "Server", "LFError", "FLAG_NO_SECONDARY", "FLAG_NO_BACKGROUND", "FLAG_BSDF_ONLY",
            "FLAG_DIFFUSE_ONLY", "FLAG_BRUTE_FORCE", "camera_struct"]
 
 
@@ -224,6 +226,99 @@ class Tracer:
         n = (C.c_int64 * _lib.NUM_PHASES)()
         self._chk(self.L.lf_profile_read(self.ctx, ms, n))
         return {name: (ms[i], n[i]) for i, name in enumerate(_lib.PHASES)}
+
+
+class Server:
+    """Relight server over a Tracer's scene (lf_server_*): requests carry
+    per-object transforms, an environment map, one camera, S and a seed; the
+    library batches all admitted requests into shared wavefront passes.
+    Request tensors are kept alive here until the request has completed."""
+
+    def __init__(self, tracer: Tracer, max_slots=16, hbm_budget_bytes=16 << 30, tile_rays=65536,
+                 batch_rays=262144, max_spp=4, max_pending=4096, k=32, flags=0, **kw):
+        self.L = tracer.L
+        self.tracer = tracer
+        cfg = _lib.ServerConfig()
+        self.L.lf_server_config_default(C.byref(cfg))
+        cfg.max_slots, cfg.hbm_budget_bytes, cfg.tile_rays = int(max_slots), int(hbm_budget_bytes), int(tile_rays)
+        cfg.batch_rays, cfg.max_spp, cfg.max_pending = int(batch_rays), int(max_spp), int(max_pending)
+        cfg.params = Tracer.params(k, max_spp, 0, flags, **kw)
+        srv = C.c_void_p()
+        tracer._chk(self.L.lf_server_create(tracer.ctx, C.byref(cfg), C.byref(srv)))
+        self.srv = srv
+        self.cfg = cfg
+        self._keep = {}
+
+    def _chk(self, st):
+        if st != 0:
+            raise LFError(st, self.L.lf_server_last_error(self.srv).decode())
+
+    def submit(self, env, camera, R=None, t=None, spp=1, seed=0, out=None) -> int:
+        """Enqueues a request and returns its ticket; env, R, t are float32
+        tensors (CUDA or CPU), outputs are allocated unless given."""
+        import torch
+        n = int(camera.w) * int(camera.h)
+        dev = self.tracer.device
+        if out is None:
+            out = dict(radiance=torch.empty((n, 3), device=dev), depth=torch.empty(n, device=dev),
+                       normal=torch.empty((n, 3), device=dev), alpha=torch.empty(n, device=dev))
+        for key, tail in (("radiance", (3,)), ("depth", ()), ("normal", (3,)), ("alpha", ())):
+            _check_tensor(out[key], key, tail, n)
+        for x, nm in ((env, "env"), (R, "R"), (t, "t")):
+            if x is not None and (x.dtype != torch.float32 or not x.is_contiguous()):
+                raise ValueError(f"{nm} must be a contiguous float32 tensor")
+        if env.dim() != 3 or env.shape[2] != 3:
+            raise ValueError("env must be [H, W, 3]")
+        m = self.tracer.n_objects
+        if m > 0 and (R is None or t is None or tuple(R.shape) != (m, 3, 3) or tuple(t.shape) != (m, 3)):
+            raise ValueError(f"R and t must be [{m},3,3] and [{m},3]")
+        req = _lib.Request()
+        req.xf = _lib.Transforms(_ptr(R) if m else None, _ptr(t) if m else None)
+        req.env = _lib.EnvMap(_ptr(env), env.shape[0], env.shape[1])
+        req.cam = camera_struct(camera)
+        req.spp, req.seed = int(spp), int(seed)
+        req.out = _lib.Outputs(_ptr(out["radiance"]), _ptr(out["depth"]), _ptr(out["normal"]), _ptr(out["alpha"]),
+                               None, None)
+        tk = C.c_uint64()
+        self._chk(self.L.lf_server_submit(self.srv, C.byref(req), C.byref(tk)))
+        self._keep[tk.value] = (env, R, t, out)
+        return tk.value
+
+    def poll(self, ticket: int) -> bool:
+        done = C.c_int()
+        self._chk(self.L.lf_server_poll(self.srv, int(ticket), C.byref(done)))
+        return bool(done.value)
+
+    def wait(self, ticket: int) -> dict:
+        """Blocks until the request completes; returns its outputs."""
+        self._chk(self.L.lf_server_wait(self.srv, int(ticket)))
+        return self._keep.pop(int(ticket))[3]
+
+    def result(self, ticket: int) -> dict:
+        """Outputs of a completed request (after poll returned True)."""
+        return self._keep.pop(int(ticket))[3]
+
+    def latency_ms(self, ticket: int) -> float:
+        ms = C.c_double()
+        self._chk(self.L.lf_server_latency(self.srv, int(ticket), C.byref(ms)))
+        return ms.value
+
+    def stats(self) -> dict:
+        st = _lib.ServerStats()
+        self._chk(self.L.lf_server_stats_get(self.srv, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in _lib.ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "srv", None):
+            self.L.lf_server_destroy(self.srv)
+            self.srv = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _render_fn():

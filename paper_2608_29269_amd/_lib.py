@@ -82,6 +82,22 @@ class RenderStats(C.Structure):
     _fields_ = [("rays_primary", C.c_int64), ("rays_secondary", C.c_int64)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("tile_rays", C.c_int32),
+                ("batch_rays", C.c_int32), ("max_spp", C.c_int32), ("max_pending", C.c_int32), ("params", Params)]
+
+
+class Request(C.Structure):
+    _fields_ = [("xf", Transforms), ("env", EnvMap), ("cam", Camera), ("spp", C.c_int32), ("seed", C.c_uint64),
+                ("out", Outputs)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("p50_ms", C.c_double), ("p99_ms", C.c_double), ("rays_per_s", C.c_double),
+                ("completed", C.c_int64), ("rejected", C.c_int64), ("rays_primary", C.c_int64),
+                ("rays_secondary", C.c_int64), ("iterations", C.c_int64)]
+
+
 NUM_PHASES = 10
 PHASES = ("refit", "state_env", "primary", "secondary", "resolve", "replay_primary", "replay_secondary",
           "adjoint", "zero_grads", "loss")
@@ -108,6 +124,15 @@ SIGNATURES = {
     "lf_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "lf_trace_counters": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
     "lf_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "lf_server_config_default": (None, [C.POINTER(ServerConfig)]),
+    "lf_server_create": (C.c_int, [C.c_void_p, C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),
+    "lf_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "lf_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]),
+    "lf_server_wait": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "lf_server_latency": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_double)]),
+    "lf_server_stats_get": (C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    "lf_server_last_error": (C.c_char_p, [C.c_void_p]),
+    "lf_server_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None

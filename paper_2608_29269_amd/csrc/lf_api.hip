@@ -8,76 +8,10 @@
 #include <string>
 #include <vector>
 
-#include "lf_internal.h"
+#include "lf_host.h"
 #include "lf_kernels.h"
 
-namespace {
-
-struct DevBuf {
-  void *p = nullptr;
-  size_t cap = 0;
-  DevBuf() = default;
-  DevBuf(const DevBuf &) = delete;
-  DevBuf &operator=(const DevBuf &) = delete;
-  ~DevBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    cap = 0;
-  }
-  bool ensure(size_t bytes) {
-    if (bytes <= cap && p) return true;
-    release();
-    size_t b = bytes ? bytes : 16;
-    if (hipMalloc(&p, b) != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      return false;
-    }
-    cap = b;
-    return true;
-  }
-  template <class T>
-  T *as() const { return (T *)p; }
-};
-
-constexpr double kPiHost = 3.14159265358979323846;
-
-}  // namespace
-
-struct lf_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  // scene
-  bool has_scene = false;
-  lf::SurfelArrays s{};
-  int n_inst = 0;
-  std::vector<int32_t> h_first, h_n, h_node_off, h_root;
-  int64_t n_nodes = 0;
-  int32_t max_depth = 0;
-  double built_alpha_min = 0, built_sig2 = 0;
-  DevBuf d_first, d_n, d_root;
-  DevBuf rec, filt, nodes, perm, leaf_parent, node_parent, flags, leafbox, rootbox, inst, status;
-  DevBuf keys, keys2, vals2, hist, boxidx, ibounds, depth, nodes4, flag4, idx4;
-  int64_t n_nodes4 = 0;
-  // per call
-  DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;
-  DevBuf queue, qcount, contrib, frozen, l1acc, cams, rec1, rec2, retry, rcount, seeds;
-  DevBuf bounds, skeys, skeys2, svals, svals2, shist;
-  lf::CamArgs h_cams{};
-  // ray counters since the last lf_stats_get
-  int64_t acc_primary = 0;
-  DevBuf acc_secondary, counters;
-  // phase timers
-  bool profiling = false;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-  std::vector<hipEvent_t> pool;
-  double prof_ms[LF_NUM_PHASES] = {};
-  int64_t prof_n[LF_NUM_PHASES] = {};
-};
-
-namespace {
+namespace lfh {
 
 lf_status fail(lf_ctx *c, lf_status st, const char *fmt, ...) {
   if (c) {
@@ -98,6 +32,15 @@ lf_status check_hip(lf_ctx *c, const char *where) {
 }
 
 bool set_device(lf_ctx *c) { return hipSetDevice(c->device) == hipSuccess; }
+
+}  // namespace lfh
+
+using lfh::check_hip;
+using lfh::fail;
+using lfh::set_device;
+using lfh::kPiHost;
+
+namespace {
 
 hipEvent_t take_event(lf_ctx *c) {
   if (!c->pool.empty()) {
@@ -131,6 +74,10 @@ struct Phase {
   }
 };
 
+}  // namespace
+
+namespace lfh {
+
 lf_status refit_impl(lf_ctx *c, double alpha_min, double sig2) {
   Phase ph(c, 0);
   lf::launch_refit(c->s, alpha_min, sig2, c->perm.as<int32_t>(), c->leaf_parent.as<int32_t>(),
@@ -154,6 +101,67 @@ lf_status validate_params(lf_ctx *c, const lf_params *p) {
   if (p->flags & ~0x7Fu) return fail(c, LF_EINVAL, "unknown flags 0x%x", p->flags);
   return LF_OK;
 }
+
+lf_status camera_args(lf_ctx *c, const lf_camera &cm, lf::CamArgs &ca) {
+  if (cm.w < 1 || cm.h < 1 || !(cm.fov_y_deg > 0.f && cm.fov_y_deg < 180.f))
+    return fail(c, LF_EINVAL, "invalid camera");
+  const int i = ca.n_cams;
+  if (i >= LF_MAX_CAMERAS) return fail(c, LF_EINVAL, "at most %d cameras per call", LF_MAX_CAMERAS);
+  for (int k = 0; k < 12; ++k) {
+    if (!std::isfinite(cm.pose[k])) return fail(c, LF_EINVAL, "non-finite camera pose");
+    ca.pose[i][k] = cm.pose[k];
+  }
+  ca.tan_half[i] = (float)std::tan((double)cm.fov_y_deg * kPiHost / 360.0);
+  ca.w[i] = cm.w;
+  ca.h[i] = cm.h;
+  ca.first[i + 1] = ca.first[i] + (int64_t)cm.w * cm.h;
+  ca.n_cams = i + 1;
+  return LF_OK;
+}
+
+void scene_view(const lf_ctx *c, lf::SceneView &S) {
+  S.rec = c->rec.as<lf::TraceRec>();
+  S.filt = c->filt.as<lf::FiltRec>();
+  S.nodes = c->nodes4.as<lf::BNode4>();
+  S.inst = nullptr;
+  S.n_inst = c->n_inst;
+  S.n_rec = (int32_t)c->s.n;
+  S.n_nodes = (int32_t)c->n_nodes4;
+  S.mu = c->s.mu; S.q = c->s.q; S.scale = c->s.scale; S.opacity = c->s.opacity;
+  S.albedo = c->s.albedo; S.roughness = c->s.roughness; S.metallic = c->s.metallic;
+}
+
+void trace_params(const lf_ctx *c, const lf_params *p, lf::TraceParams &P) {
+  P.k = p->k;
+  P.spp = p->spp;
+  P.seed = p->seed;
+  P.alpha_min = p->alpha_min;
+  P.alpha_cap = p->alpha_cap;
+  P.sig2 = p->support_sigma * p->support_sigma;
+  P.eps = p->eps;
+  P.t_min = p->t_min;
+  P.sec_off = p->secondary_offset;
+  P.flags = p->flags;
+  P.counters = (p->flags & LF_FLAG_COUNT) ? c->counters.as<unsigned long long>() : nullptr;
+}
+
+bool ensure_env_tables(DevBuf &cdf_row, DevBuf &cdf_col, DevBuf &lum, DevBuf &rowsum, DevBuf &roww, DevBuf &scal,
+                       int H, int W) {
+  return cdf_row.ensure(sizeof(double) * (H + 1)) && cdf_col.ensure(sizeof(double) * H * (W + 1)) &&
+         lum.ensure(sizeof(double) * H * W) && rowsum.ensure(sizeof(double) * H) && roww.ensure(sizeof(double) * H) &&
+         scal.ensure(sizeof(double) * 2);
+}
+
+int64_t env_table_bytes(int H, int W) {
+  return (int64_t)sizeof(double) * ((H + 1) + (int64_t)H * (W + 1) + (int64_t)H * W + 2 * H + 2);
+}
+
+}  // namespace lfh
+
+using lfh::refit_impl;
+using lfh::validate_params;
+
+namespace {
 
 // Common validation and setup of lf_render / lf_render_backward.
 lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, const lf_rays *rays,
@@ -180,20 +188,8 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
     if (n_cams > LF_MAX_CAMERAS) return fail(c, LF_EINVAL, "at most %d cameras per call", LF_MAX_CAMERAS);
     lf::CamArgs &ca = c->h_cams;
     memset(&ca, 0, sizeof ca);
-    ca.n_cams = n_cams;
-    for (int i = 0; i < n_cams; ++i) {
-      const lf_camera &cm = cams[i];
-      if (cm.w < 1 || cm.h < 1 || !(cm.fov_y_deg > 0.f && cm.fov_y_deg < 180.f))
-        return fail(c, LF_EINVAL, "invalid camera %d", i);
-      for (int k = 0; k < 12; ++k) {
-        if (!std::isfinite(cm.pose[k])) return fail(c, LF_EINVAL, "non-finite camera pose %d", i);
-        ca.pose[i][k] = cm.pose[k];
-      }
-      ca.tan_half[i] = (float)std::tan((double)cm.fov_y_deg * kPiHost / 360.0);
-      ca.w[i] = cm.w;
-      ca.h[i] = cm.h;
-      ca.first[i + 1] = ca.first[i] + (int64_t)cm.w * cm.h;
-    }
+    for (int i = 0; i < n_cams; ++i)
+      if ((st = lfh::camera_args(c, cams[i], ca))) return fail(c, st, "camera %d: %s", i, c->err.c_str());
     R = ca.first[n_cams];
     if (!c->cams.ensure(sizeof(lf::CamArgs))) return fail(c, LF_ENOMEM, "cameras");
     if (hipMemcpyAsync(c->cams.p, &ca, sizeof ca, hipMemcpyHostToDevice, c->stream) != hipSuccess)
@@ -204,6 +200,7 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
   a.R = R;
   double sig2 = p->support_sigma * p->support_sigma;
   if (p->alpha_min != c->built_alpha_min || sig2 != c->built_sig2) {
+    if (c->servers > 0) return fail(c, LF_EBUSY, "tracing constants differ from the scene a server is serving");
     if ((st = refit_impl(c, p->alpha_min, sig2))) return st;
   }
   // state assembly: instance records for this state's transforms
@@ -214,33 +211,16 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
                        c->inst.as<lf::InstRec>(), c->bounds.as<double>(), c->status.as<uint32_t>(), c->stream);
   // environment importance-sampling tables
   int H = env->h, W = env->w;
-  if (!c->env_cdf_row.ensure(sizeof(double) * (H + 1)) || !c->env_cdf_col.ensure(sizeof(double) * H * (W + 1)) ||
-      !c->env_lum.ensure(sizeof(double) * H * W) || !c->env_rowsum.ensure(sizeof(double) * H) ||
-      !c->env_roww.ensure(sizeof(double) * H) || !c->env_scal.ensure(sizeof(double) * 2))
+  if (!lfh::ensure_env_tables(c->env_cdf_row, c->env_cdf_col, c->env_lum, c->env_rowsum, c->env_roww, c->env_scal,
+                              H, W))
     return fail(c, LF_ENOMEM, "environment tables");
   lf::launch_env_tables(env->texels, H, W, p->flags, c->env_cdf_row.as<double>(), c->env_cdf_col.as<double>(),
                         c->env_lum.as<double>(), c->env_rowsum.as<double>(), c->env_roww.as<double>(),
                         c->env_scal.as<double>(), c->stream);
-  a.S.rec = c->rec.as<lf::TraceRec>();
-  a.S.filt = c->filt.as<lf::FiltRec>();
-  a.S.nodes = c->nodes4.as<lf::BNode4>();
+  lfh::scene_view(c, a.S);
   a.S.inst = c->inst.as<lf::InstRec>();
-  a.S.n_inst = c->n_inst;
-  a.S.n_rec = (int32_t)c->s.n;
-  a.S.n_nodes = (int32_t)c->n_nodes4;
-  a.S.mu = c->s.mu; a.S.q = c->s.q; a.S.scale = c->s.scale; a.S.opacity = c->s.opacity;
-  a.S.albedo = c->s.albedo; a.S.roughness = c->s.roughness; a.S.metallic = c->s.metallic;
-  a.P.k = p->k;
-  a.P.spp = p->spp;
-  a.P.seed = p->seed;
-  a.P.alpha_min = p->alpha_min;
-  a.P.alpha_cap = p->alpha_cap;
-  a.P.sig2 = sig2;
-  a.P.eps = p->eps;
-  a.P.t_min = p->t_min;
-  a.P.sec_off = p->secondary_offset;
-  a.P.flags = p->flags;
-  a.P.counters = (p->flags & LF_FLAG_COUNT) ? c->counters.as<unsigned long long>() : nullptr;
+  lfh::trace_params(c, p, a.P);
+  a.spp_stride = p->spp;
   a.E.tex = env->texels;
   a.E.H = H;
   a.E.W = W;
@@ -282,9 +262,9 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
 // regroups the secondary queue by direction octant and origin for coherent traversal
 void sort_secondaries(lf_ctx *c, const lf::RenderArgs &a) {
   if (!a.order) return;
-  const int64_t cap = a.R * a.P.spp;
-  lf::launch_secondary_keys(a.queue, a.queue_count, cap, c->bounds.as<double>(), c->skeys.as<uint64_t>(),
-                            c->svals.as<int32_t>(), c->stream);
+  const int64_t cap = a.R * a.spp_stride;
+  lf::launch_secondary_keys(a.queue, a.queue_count, cap, c->bounds.as<double>(), nullptr, nullptr,
+                            c->skeys.as<uint64_t>(), c->svals.as<int32_t>(), c->stream);
   lf::radix_sort(c->skeys.as<uint64_t>(), c->svals.as<int32_t>(), c->skeys2.as<uint64_t>(), c->svals2.as<int32_t>(),
                  c->shist.as<uint32_t>(), cap, c->stream, 32);
 }
@@ -380,6 +360,7 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
   if (off[0] != 0 || off[n_inst] != sf->n) return fail(c, LF_EINVAL, "object_offset must start at 0 and end at n");
   for (int i = 0; i < n_inst; ++i)
     if (off[i + 1] < off[i]) return fail(c, LF_EINVAL, "object_offset must be non-decreasing");
+  if (c->servers > 0) return fail(c, LF_EBUSY, "a relight server is reading the scene");
   set_device(c);
   c->has_scene = false;
   c->s = lf::SurfelArrays{sf->mu, sf->q, sf->scale, sf->opacity, sf->albedo, sf->roughness, sf->metallic, sf->n};
@@ -479,6 +460,7 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
 lf_status lf_scene_refit(lf_ctx *c) {
   if (!c) return LF_EINVAL;
   if (!c->has_scene) return fail(c, LF_EINVAL, "no scene set");
+  if (c->servers > 0) return fail(c, LF_EBUSY, "a relight server is reading the scene");
   set_device(c);
   return refit_impl(c, c->built_alpha_min, c->built_sig2);
 }
@@ -598,12 +580,8 @@ lf_status lf_raygen(lf_ctx *c, const lf_camera *cam, float *o, float *d) {
   set_device(c);
   lf::CamArgs &ca = c->h_cams;
   memset(&ca, 0, sizeof ca);
-  ca.n_cams = 1;
-  for (int k = 0; k < 12; ++k) ca.pose[0][k] = cam->pose[k];
-  ca.tan_half[0] = (float)std::tan((double)cam->fov_y_deg * kPiHost / 360.0);
-  ca.w[0] = cam->w;
-  ca.h[0] = cam->h;
-  ca.first[1] = (int64_t)cam->w * cam->h;
+  lf_status st = lfh::camera_args(c, *cam, ca);
+  if (st) return st;
   if (!c->cams.ensure(sizeof(lf::CamArgs))) return fail(c, LF_ENOMEM, "cameras");
   if (hipMemcpyAsync(c->cams.p, &ca, sizeof ca, hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return check_hip(c, "camera upload");

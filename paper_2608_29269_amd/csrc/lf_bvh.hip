@@ -475,7 +475,8 @@ void launch_wide_index(const int32_t *node_parent, int64_t n_nodes, uint32_t *fl
                        uint32_t *status, hipStream_t st) {
   if (n_nodes <= 0) return;
   hipLaunchKernelGGL(k_node_depth, dim3(blocks(n_nodes, 256)), dim3(256), 0, st, node_parent, n_nodes, flag, status);
-  hipMemcpyAsync(idx4, flag, sizeof(uint32_t) * n_nodes, hipMemcpyDeviceToDevice, st);
+  // a failure stays in the runtime's last error, which the caller checks
+  (void)hipMemcpyAsync(idx4, flag, sizeof(uint32_t) * n_nodes, hipMemcpyDeviceToDevice, st);
   hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, idx4, n_nodes);
 }
 

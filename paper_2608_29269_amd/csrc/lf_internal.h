@@ -159,4 +159,28 @@ struct alignas(16) SecFrozen {
 };
 static_assert(sizeof(SecFrozen) == 64, "SecFrozen layout");
 
+// ---- continuous batching: several requests share one wavefront pass.
+// The batch is a list of 128-ray chunks; every chunk belongs to one request
+// (its slot) and covers consecutive ray ids of that request.
+constexpr int kChunk = kBlock;
+
+struct alignas(16) ChunkDesc {
+  int32_t slot;    // server slot of the request
+  int32_t n;       // valid rays in the chunk (1..kChunk)
+  int64_t first;   // ray id (within the request) of the chunk's first ray
+};
+static_assert(sizeof(ChunkDesc) == 16, "ChunkDesc layout");
+
+// What differs between the requests of a batch.
+struct alignas(16) BatchSlot {
+  const InstRec *inst;      // [n_inst] this request's instance records
+  const double *bounds;     // [6] world bounds of its instances
+  const CamArgs *cam;       // camera 0 generates the request's rays
+  EnvView E;                // its environment map and sampling tables
+  float *radiance, *depth, *normal, *alpha;  // its outputs, indexed by ray id
+  uint64_t seed;
+  int32_t spp;
+  int32_t pad;
+};
+
 }  // namespace lf

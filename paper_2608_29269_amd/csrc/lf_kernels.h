@@ -48,7 +48,8 @@ void launch_instances(const float *R, const float *t, const float *root_box6, co
                       uint32_t *status, hipStream_t st);
 // sort keys of the secondary queue: (direction octant, origin Morton code); entries past the count sort last
 void launch_secondary_keys(const SecEntry *queue, const uint32_t *count, int64_t cap, const double *bounds6,
-                           uint64_t *keys, int32_t *vals, hipStream_t st);
+                           const ChunkDesc *chunks, const BatchSlot *slots, uint64_t *keys, int32_t *vals,
+                           hipStream_t st);
 void launch_env_tables(const float *tex, int H, int W, uint32_t flags, double *cdf_row, double *cdf_col, double *lum,
                        double *rowsum, double *roww, double *scal, hipStream_t st);
 
@@ -73,6 +74,11 @@ struct RenderArgs {
   SecFrozen *frozen;    // [R*S] (backward replay)
   AdjSeed *seeds;       // [R] (backward)
   uint32_t *status;
+  // per-ray sample stride of contrib / frozen and of the queue capacity (spp, or the batch maximum)
+  int32_t spp_stride;
+  // continuous batching (NULL for one request): R = kChunk * number of chunks
+  const ChunkDesc *chunks;
+  const BatchSlot *slots;
 };
 // primary: traversal + compositing (fast keys, then exact re-trace of collisions), then shading
 void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st);

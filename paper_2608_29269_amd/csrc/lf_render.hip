@@ -95,8 +95,8 @@ __device__ __forceinline__ uint32_t spread3_10(uint32_t x) {
   return x;
 }
 
-__global__ void k_secondary_keys(const SecEntry *queue, const uint32_t *count, int64_t cap, const double *b,
-                                 uint64_t *keys, int32_t *vals) {
+__global__ void k_secondary_keys(const SecEntry *queue, const uint32_t *count, int64_t cap, const double *bounds6,
+                                 const ChunkDesc *chunks, const BatchSlot *slots, uint64_t *keys, int32_t *vals) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cap) return;
   vals[i] = (int32_t)i;
@@ -105,6 +105,8 @@ __global__ void k_secondary_keys(const SecEntry *queue, const uint32_t *count, i
     return;
   }
   const SecEntry e = queue[i];
+  // in a batch every request quantises in its own world bounds (only the grouping depends on it)
+  const double *b = chunks ? slots[chunks[e.ray / kChunk].slot].bounds : bounds6;
   uint32_t c[3];
   for (int k = 0; k < 3; ++k) {
     const double ext = b[3 + k] - b[k];
@@ -223,83 +225,145 @@ __device__ __forceinline__ void wave_append(bool live, const T &e, T *queue, uin
   }
 }
 
+// ---------------------------------------------------------------- request views
+// Where the per-request quantities of a ray live: the launch arguments for a
+// single request, the slot of the ray's chunk in a batch.
+struct ReqView {
+  const InstRec *inst;
+  float *radiance, *depth, *normal, *alpha;
+  int64_t local;   // ray id within the request (sampler counter, output index)
+  bool valid;
+};
+
+template <bool B>
+__device__ __forceinline__ ReqView req_view(const RenderArgs &a, int64_t ray) {
+  ReqView v;
+  if constexpr (B) {
+    const bool in = ray < a.R;  // a block may extend past the last chunk
+    const ChunkDesc cd = a.chunks[in ? ray / kChunk : 0];
+    const BatchSlot &sl = a.slots[cd.slot];
+    v.inst = sl.inst;
+    v.radiance = sl.radiance; v.depth = sl.depth; v.normal = sl.normal; v.alpha = sl.alpha;
+    v.local = cd.first + ray % kChunk;
+    v.valid = in && ray % kChunk < cd.n;
+  } else {
+    v.inst = a.S.inst;
+    v.radiance = a.radiance; v.depth = a.depth; v.normal = a.normal; v.alpha = a.alpha;
+    v.local = ray;
+    v.valid = ray < a.R;
+  }
+  return v;
+}
+
+// environment, sampler seed and S of the ray's request
+template <bool B>
+__device__ __forceinline__ void req_shading(const RenderArgs &a, int64_t ray, EnvView &E, TraceParams &P) {
+  P = a.P;
+  if constexpr (B) {
+    const BatchSlot &sl = a.slots[a.chunks[ray < a.R ? ray / kChunk : 0].slot];
+    E = sl.E;
+    P.seed = sl.seed;
+    P.spp = sl.spp;
+  } else {
+    E = a.E;
+  }
+}
+
+template <bool B>
+__device__ __forceinline__ void req_ray(const RenderArgs &a, int64_t ray, const ReqView &v, float *of, float *df) {
+  if constexpr (B) raygen_f32(*a.slots[a.chunks[ray / kChunk].slot].cam, 0, v.local, of, df);
+  else load_ray(a.rays, ray, of, df);
+}
+
 // ---------------------------------------------------------------- primary tracing
-template <int K, class B>
-__device__ __forceinline__ void finish_primary(const RenderArgs &a, bool replay, int64_t ray, B &kb, d3 o, d3 d) {
+template <int K, class B_>
+__device__ __forceinline__ void finish_primary(const RenderArgs &a, const SceneView &S, const ReqView &v, bool replay,
+                                               int64_t ray, B_ &kb, d3 o, d3 d) {
   Record rc;
-  composite<K>(a.S, a.P, kb, o, d, rc);
+  composite<K>(S, a.P, kb, o, d, rc);
   store_record(rc, a.rec1 + ray);
   if (replay) return;
-  a.depth[ray] = (float)rc.depth;
-  a.alpha[ray] = (float)rc.A;
-  a.normal[3 * ray + 0] = (float)rc.n.x;
-  a.normal[3 * ray + 1] = (float)rc.n.y;
-  a.normal[3 * ray + 2] = (float)rc.n.z;
-  if (a.hit_idx) write_hits<K>(a.S, kb, a.P.k, a.hit_idx + ray * a.P.k);
+  const int64_t i = v.local;
+  v.depth[i] = (float)rc.depth;
+  v.alpha[i] = (float)rc.A;
+  v.normal[3 * i + 0] = (float)rc.n.x;
+  v.normal[3 * i + 1] = (float)rc.n.y;
+  v.normal[3 * i + 2] = (float)rc.n.z;
+  if (a.hit_idx) write_hits<K>(S, kb, a.P.k, a.hit_idx + ray * a.P.k);
 }
 
 // fast keys; rays whose binary32 keys collide are appended to the retry list
-template <int K>
+template <int K, bool B>
 __global__ __launch_bounds__(kBlock) void k_trace1(RenderArgs a, bool replay) {
   __shared__ int stk[kStack * kBlock];
   const int64_t ray = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool active = ray < a.R;
+  const ReqView v = req_view<B>(a, ray);
+  SceneView S = a.S;
+  S.inst = v.inst;
+  const bool active = v.valid;
   float of[3] = {0, 0, 0}, df[3] = {0, 0, 1};
-  if (active) load_ray(a.rays, ray, of, df);
+  if (active) req_ray<B>(a, ray, v, of, df);
   const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
   KBufF<K> kb;
   kb.collide = false;
-  if (active) trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
+  if (active) trace<K>(S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
   const bool again = active && kb.collide;
   wave_append<int32_t>(again, (int32_t)ray, a.retry, a.retry_count);
-  if (active && !again) finish_primary<K>(a, replay, ray, kb, o, d);
+  if (active && !again) finish_primary<K>(a, S, v, replay, ray, kb, o, d);
 }
 
 // exact keys for the retried rays
-template <int K>
+template <int K, bool B>
 __global__ __launch_bounds__(kBlock) void k_trace1_exact(RenderArgs a, bool replay) {
   __shared__ int stk[kStack * kBlock];
   const uint32_t cnt = *a.retry_count;
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
     const int64_t ray = a.retry[i];
+    const ReqView v = req_view<B>(a, ray);
+    SceneView S = a.S;
+    S.inst = v.inst;
     float of[3], df[3];
-    load_ray(a.rays, ray, of, df);
+    req_ray<B>(a, ray, v, of, df);
     const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
     KBufD<K> kb;
-    trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
-    finish_primary<K>(a, replay, ray, kb, o, d);
+    trace<K>(S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
+    finish_primary<K>(a, S, v, replay, ray, kb, o, d);
   }
 }
 
 // ---------------------------------------------------------------- primary shading
 // Background term, S sampled directions (one-sample MIS), ballot-compacted
 // enqueue of live secondary rays.  replay = true regenerates the queue only.
+template <bool B>
 __global__ __launch_bounds__(256) void k_shade1(RenderArgs a, bool replay) {
   const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = ray < a.R;
-  const TraceParams &P = a.P;
+  const ReqView v = req_view<B>(a, ray);
+  const bool active = v.valid;
+  EnvView E;
+  TraceParams P;
+  req_shading<B>(a, ray, E, P);
   const int S = P.spp;
   float of[3] = {0, 0, 0}, df[3] = {0, 0, 1};
-  if (active) load_ray(a.rays, ray, of, df);
+  if (active) req_ray<B>(a, ray, v, of, df);
   const d3 d = mk(df[0], df[1], df[2]);
   Record rc;
   rc.nh = 0;
   if (active) rc = load_record(a.rec1 + ray);
-  const double c_env = a.E.scal[1];
+  const double c_env = E.scal[1];
   const d3 wo = -d;
   d3 L = mk(0, 0, 0);
-  if (active && !replay && !(P.flags & LF_FLAG_NO_BACKGROUND)) L = rc.T * env_eval(a.E, d);
+  if (active && !replay && !(P.flags & LF_FLAG_NO_BACKGROUND)) L = rc.T * env_eval(E, d);
   const bool trace2 = !(P.flags & LF_FLAG_NO_SECONDARY);
   for (int s = 0; s < S; ++s) {
     d3 w = mk(0, 0, 1);
     double K_ = 0.0;
-    const bool live = active && primary_sample(a.E, P, rc, wo, ray, s, c_env, w, K_);
+    const bool live = active && primary_sample(E, P, rc, wo, v.local, s, c_env, w, K_);
     d3 thr = mk(0, 0, 0);
     if (live) thr = (K_ * rc.A / S) * fcos(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags);
     if (!trace2) {
       if (live && !replay) {
-        const d3 E = env_eval(a.E, w);
-        L = L + mk(thr.x * E.x, thr.y * E.y, thr.z * E.z);
+        const d3 Ev = env_eval(E, w);
+        L = L + mk(thr.x * Ev.x, thr.y * Ev.y, thr.z * Ev.z);
       }
       continue;
     }
@@ -315,7 +379,7 @@ __global__ __launch_bounds__(256) void k_shade1(RenderArgs a, bool replay) {
     }
     wave_append<SecEntry>(live, e, a.queue, a.queue_count);
     if (active && !live) {
-      const int64_t cs = ray * S + s;
+      const int64_t cs = ray * a.spp_stride + s;
       if (!replay) {
         a.contrib[3 * cs + 0] = 0.f;
         a.contrib[3 * cs + 1] = 0.f;
@@ -330,26 +394,26 @@ __global__ __launch_bounds__(256) void k_shade1(RenderArgs a, bool replay) {
     }
   }
   if (active && !replay) {
-    a.radiance[3 * ray + 0] = (float)L.x;
-    a.radiance[3 * ray + 1] = (float)L.y;
-    a.radiance[3 * ray + 2] = (float)L.z;
+    v.radiance[3 * v.local + 0] = (float)L.x;
+    v.radiance[3 * v.local + 1] = (float)L.y;
+    v.radiance[3 * v.local + 2] = (float)L.z;
   }
 }
 
 // ---------------------------------------------------------------- secondary tracing
-template <int K, class B>
-__device__ __forceinline__ void finish_secondary(const RenderArgs &a, uint32_t qi, const SecEntry &e, B &kb, d3 o,
-                                                 d3 w) {
+template <int K, class B_>
+__device__ __forceinline__ void finish_secondary(const RenderArgs &a, const SceneView &S, uint32_t qi,
+                                                 const SecEntry &e, B_ &kb, d3 o, d3 w) {
   Record r2;
-  composite<K>(a.S, a.P, kb, o, w, r2);
+  composite<K>(S, a.P, kb, o, w, r2);
   store_record(r2, a.rec2 + qi);
   if (a.sec_hit_idx) {
-    const int64_t cs = (int64_t)e.ray * a.P.spp + e.s;
-    write_hits<K>(a.S, kb, a.P.k, a.sec_hit_idx + cs * a.P.k);
+    const int64_t cs = (int64_t)e.ray * a.spp_stride + e.s;
+    write_hits<K>(S, kb, a.P.k, a.sec_hit_idx + cs * a.P.k);
   }
 }
 
-template <int K>
+template <int K, bool B>
 __global__ __launch_bounds__(kBlock) void k_trace2(RenderArgs a) {
   __shared__ int stk[kStack * kBlock];
   const uint32_t count = *a.queue_count;
@@ -358,21 +422,24 @@ __global__ __launch_bounds__(kBlock) void k_trace2(RenderArgs a) {
   const bool active = slot < count;
   const uint32_t qi = active ? (a.order ? (uint32_t)a.order[slot] : slot) : 0u;
   SecEntry e;
+  e.ray = 0;
   d3 o = mk(0, 0, 0), w = mk(0, 0, 1);
   if (active) {
     e = a.queue[qi];
     o = mk(e.o[0], e.o[1], e.o[2]);
     w = mk(e.w[0], e.w[1], e.w[2]);
   }
+  SceneView S = a.S;
+  if constexpr (B) S.inst = a.slots[a.chunks[e.ray / kChunk].slot].inst;
   KBufF<K> kb;
   kb.collide = false;
-  if (active) trace<K>(a.S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4);
+  if (active) trace<K>(S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4);
   const bool again = active && kb.collide;
   wave_append<int32_t>(again, (int32_t)qi, a.retry, a.retry_count);
-  if (active && !again) finish_secondary<K>(a, qi, e, kb, o, w);
+  if (active && !again) finish_secondary<K>(a, S, qi, e, kb, o, w);
 }
 
-template <int K>
+template <int K, bool B>
 __global__ __launch_bounds__(kBlock) void k_trace2_exact(RenderArgs a) {
   __shared__ int stk[kStack * kBlock];
   const uint32_t cnt = *a.retry_count;
@@ -380,25 +447,31 @@ __global__ __launch_bounds__(kBlock) void k_trace2_exact(RenderArgs a) {
     const uint32_t qi = (uint32_t)a.retry[i];
     const SecEntry e = a.queue[qi];
     const d3 o = mk(e.o[0], e.o[1], e.o[2]), w = mk(e.w[0], e.w[1], e.w[2]);
+    SceneView S = a.S;
+    if constexpr (B) S.inst = a.slots[a.chunks[e.ray / kChunk].slot].inst;
     KBufD<K> kb;
-    trace<K>(a.S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4);
-    finish_secondary<K>(a, qi, e, kb, o, w);
+    trace<K>(S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4);
+    finish_secondary<K>(a, S, qi, e, kb, o, w);
   }
 }
 
 // ---------------------------------------------------------------- secondary shading
+template <bool B>
 __global__ __launch_bounds__(256) void k_shade2(RenderArgs a, bool replay) {
   const uint32_t count = *a.queue_count;
   const uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x;
   if (qi >= count) return;
   const SecEntry e = a.queue[qi];
-  const TraceParams &P = a.P;
+  EnvView E;
+  TraceParams P;
+  req_shading<B>(a, e.ray, E, P);
+  const int64_t local = req_view<B>(a, e.ray).local;
   const d3 w = mk(e.w[0], e.w[1], e.w[2]);
   const Record r2 = load_record(a.rec2 + qi);
-  const double c_env = a.E.scal[1];
+  const double c_env = E.scal[1];
   SecCoef sc;
-  secondary_coefs(a.E, P, r2, w, e.ray, e.s, c_env, sc);
-  const int64_t cs = (int64_t)e.ray * P.spp + e.s;
+  secondary_coefs(E, P, r2, w, local, e.s, c_env, sc);
+  const int64_t cs = (int64_t)e.ray * a.spp_stride + e.s;
   if (replay) {
     SecFrozen f;
     f.T2 = (float)r2.T;
@@ -410,13 +483,13 @@ __global__ __launch_bounds__(256) void k_shade2(RenderArgs a, bool replay) {
     a.frozen[cs] = f;
     return;
   }
-  d3 Lin = r2.T * env_eval(a.E, w);
+  d3 Lin = r2.T * env_eval(E, w);
   if (sc.has_e) {
-    const d3 Ee = env_eval(a.E, sc.we);
+    const d3 Ee = env_eval(E, sc.we);
     Lin = Lin + mk(sc.ce.x * Ee.x, sc.ce.y * Ee.y, sc.ce.z * Ee.z);
   }
   if (sc.has_b) {
-    const d3 Eb = env_eval(a.E, sc.wb);
+    const d3 Eb = env_eval(E, sc.wb);
     Lin = Lin + mk(sc.cb.x * Eb.x, sc.cb.y * Eb.y, sc.cb.z * Eb.z);
   }
   a.contrib[3 * cs + 0] = (float)(e.thr[0] * Lin.x);
@@ -424,13 +497,19 @@ __global__ __launch_bounds__(256) void k_shade2(RenderArgs a, bool replay) {
   a.contrib[3 * cs + 2] = (float)(e.thr[2] * Lin.z);
 }
 
-__global__ void k_resolve(float *radiance, const float *contrib, int64_t R, int S) {
-  int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ray >= R) return;
-  double L[3] = {radiance[3 * ray], radiance[3 * ray + 1], radiance[3 * ray + 2]};
+template <bool B>
+__global__ void k_resolve(RenderArgs a) {
+  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ray >= a.R) return;
+  const ReqView v = req_view<B>(a, ray);
+  if (!v.valid) return;
+  int S = a.P.spp;
+  if constexpr (B) S = a.slots[a.chunks[ray / kChunk].slot].spp;
+  float *rad = v.radiance + 3 * v.local;
+  double L[3] = {rad[0], rad[1], rad[2]};
   for (int s = 0; s < S; ++s)
-    for (int c = 0; c < 3; ++c) L[c] += (double)contrib[3 * (ray * S + s) + c];
-  for (int c = 0; c < 3; ++c) radiance[3 * ray + c] = (float)L[c];
+    for (int c = 0; c < 3; ++c) L[c] += (double)a.contrib[3 * (ray * a.spp_stride + s) + c];
+  for (int c = 0; c < 3; ++c) rad[c] = (float)L[c];
 }
 
 __global__ void k_raygen(const CamArgs *cams, int64_t n, float *o, float *d) {
@@ -465,18 +544,36 @@ __global__ void k_zero_f64(double *p) { *p = 0.0; }
 
 constexpr unsigned kExactBlocks = 512;
 
-template <int K>
+template <int K, bool B>
 void trace1_k(const RenderArgs &a, bool replay, hipStream_t st) {
   launch_fill_u32(a.retry_count, 0u, 1, st);
-  hipLaunchKernelGGL(k_trace1<K>, dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, replay);
-  hipLaunchKernelGGL(k_trace1_exact<K>, dim3(kExactBlocks), dim3(kBlock), 0, st, a, replay);
+  hipLaunchKernelGGL((k_trace1<K, B>), dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, replay);
+  hipLaunchKernelGGL((k_trace1_exact<K, B>), dim3(kExactBlocks), dim3(kBlock), 0, st, a, replay);
 }
-template <int K>
+template <int K, bool B>
 void trace2_k(const RenderArgs &a, hipStream_t st) {
   launch_fill_u32(a.retry_count, 0u, 1, st);
-  const int64_t cap = a.R * a.P.spp;
-  hipLaunchKernelGGL(k_trace2<K>, dim3(blocks(cap, kBlock)), dim3(kBlock), 0, st, a);
-  hipLaunchKernelGGL(k_trace2_exact<K>, dim3(kExactBlocks), dim3(kBlock), 0, st, a);
+  const int64_t cap = a.R * a.spp_stride;
+  hipLaunchKernelGGL((k_trace2<K, B>), dim3(blocks(cap, kBlock)), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL((k_trace2_exact<K, B>), dim3(kExactBlocks), dim3(kBlock), 0, st, a);
+}
+template <bool B>
+void trace1_b(const RenderArgs &a, bool replay, hipStream_t st) {
+  switch (kbucket(a.P.k)) {
+    case 8: trace1_k<8, B>(a, replay, st); break;
+    case 16: trace1_k<16, B>(a, replay, st); break;
+    case 32: trace1_k<32, B>(a, replay, st); break;
+    default: trace1_k<64, B>(a, replay, st); break;
+  }
+}
+template <bool B>
+void trace2_b(const RenderArgs &a, hipStream_t st) {
+  switch (kbucket(a.P.k)) {
+    case 8: trace2_k<8, B>(a, st); break;
+    case 16: trace2_k<16, B>(a, st); break;
+    case 32: trace2_k<32, B>(a, st); break;
+    default: trace2_k<64, B>(a, st); break;
+  }
 }
 
 }  // namespace
@@ -489,10 +586,11 @@ void launch_instances(const float *R, const float *t, const float *root_box6, co
 }
 
 void launch_secondary_keys(const SecEntry *queue, const uint32_t *count, int64_t cap, const double *bounds6,
-                           uint64_t *keys, int32_t *vals, hipStream_t st) {
+                           const ChunkDesc *chunks, const BatchSlot *slots, uint64_t *keys, int32_t *vals,
+                           hipStream_t st) {
   if (cap <= 0) return;
-  hipLaunchKernelGGL(k_secondary_keys, dim3(blocks(cap, 256)), dim3(256), 0, st, queue, count, cap, bounds6, keys,
-                     vals);
+  hipLaunchKernelGGL(k_secondary_keys, dim3(blocks(cap, 256)), dim3(256), 0, st, queue, count, cap, bounds6, chunks,
+                     slots, keys, vals);
 }
 
 void launch_env_tables(const float *tex, int H, int W, uint32_t flags, double *cdf_row, double *cdf_col, double *lum,
@@ -503,37 +601,33 @@ void launch_env_tables(const float *tex, int H, int W, uint32_t flags, double *c
 
 void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st) {
   if (a.R <= 0) return;
-  switch (kbucket(a.P.k)) {
-    case 8: trace1_k<8>(a, replay, st); break;
-    case 16: trace1_k<16>(a, replay, st); break;
-    case 32: trace1_k<32>(a, replay, st); break;
-    default: trace1_k<64>(a, replay, st); break;
-  }
+  if (a.chunks) trace1_b<true>(a, replay, st);
+  else trace1_b<false>(a, replay, st);
 }
 
 void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st) {
   if (a.R <= 0) return;
-  hipLaunchKernelGGL(k_shade1, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, replay);
+  if (a.chunks) hipLaunchKernelGGL(k_shade1<true>, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, replay);
+  else hipLaunchKernelGGL(k_shade1<false>, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, replay);
 }
 
 void launch_trace2(const RenderArgs &a, hipStream_t st) {
   if (a.R <= 0) return;
-  switch (kbucket(a.P.k)) {
-    case 8: trace2_k<8>(a, st); break;
-    case 16: trace2_k<16>(a, st); break;
-    case 32: trace2_k<32>(a, st); break;
-    default: trace2_k<64>(a, st); break;
-  }
+  if (a.chunks) trace2_b<true>(a, st);
+  else trace2_b<false>(a, st);
 }
 
 void launch_shade2(const RenderArgs &a, bool replay, hipStream_t st) {
   if (a.R <= 0) return;
-  hipLaunchKernelGGL(k_shade2, dim3(blocks(a.R * a.P.spp, 256)), dim3(256), 0, st, a, replay);
+  const unsigned nb = blocks(a.R * a.spp_stride, 256);
+  if (a.chunks) hipLaunchKernelGGL(k_shade2<true>, dim3(nb), dim3(256), 0, st, a, replay);
+  else hipLaunchKernelGGL(k_shade2<false>, dim3(nb), dim3(256), 0, st, a, replay);
 }
 
 void launch_resolve(const RenderArgs &a, hipStream_t st) {
   if (a.R <= 0) return;
-  hipLaunchKernelGGL(k_resolve, dim3(blocks(a.R, 256)), dim3(256), 0, st, a.radiance, a.contrib, a.R, a.P.spp);
+  if (a.chunks) hipLaunchKernelGGL(k_resolve<true>, dim3(blocks(a.R, 256)), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_resolve<false>, dim3(blocks(a.R, 256)), dim3(256), 0, st, a);
 }
 
 void launch_raygen(const CamArgs *cams, int64_t n, float *o, float *d, hipStream_t st) {

@@ -1,0 +1,614 @@
+// lf_server.hip -- relight server: continuous batching of forward renders of
+// the resident scene (Sec. 4 rearrangement and relighting).  A host thread
+// admits requests (lf_sched.h), stages each admitted request's transforms,
+// camera and environment into its slot (instance records and importance
+// sampling tables are built on the device), and launches batched wavefront
+// passes over 128-ray chunks of all admitted requests on the server's own
+// stream, keeping up to two passes in flight.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "lf_host.h"
+#include "lf_sched.h"
+
+namespace {
+
+using lfh::DevBuf;
+using Clock = std::chrono::steady_clock;
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(Clock::now().time_since_epoch()).count();
+}
+
+enum TicketState { kWaiting = 0, kAdmitted = 1, kDone = 2 };
+
+struct TicketRec {
+  TicketState state = kWaiting;
+  lf_status status = LF_OK;
+  lf_request req{};
+  int64_t rays = 0;
+  double t_submit = 0.0, t_done = 0.0;
+};
+
+// Device state of one request slot.
+struct SlotDev {
+  DevBuf xf;      // [M*9] R then [M*3] t
+  DevBuf inst;    // InstRec[n_inst]
+  DevBuf bounds;  // 6 doubles
+  DevBuf cam;     // CamArgs
+  DevBuf tex, cdf_row, cdf_col, lum, rowsum, roww, scal;
+  DevBuf status;  // status word of the request's instance records (invalid transforms)
+};
+
+// What the host reads back after each pass.
+struct IterReadback {
+  uint32_t status;
+  uint32_t secondaries;
+};
+
+struct InFlight {
+  hipEvent_t done = nullptr;
+  std::vector<lf::SchedTile> tiles;
+  int buf = 0;
+  int64_t primaries = 0;
+};
+
+}  // namespace
+
+struct lf_server {
+  lf_ctx *ctx = nullptr;
+  lf_server_config cfg{};
+  hipStream_t stream = nullptr;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  bool failed = false;
+  lf_status fail_status = LF_OK;
+  std::string err;
+  lf::Scheduler sched;
+  std::unordered_map<uint64_t, TicketRec> tickets;
+  uint64_t next_ticket = 1;
+  std::vector<uint64_t> slot_ticket;
+  std::vector<SlotDev> slots;
+  // pinned staging
+  lf::BatchSlot *h_slots = nullptr;   // [max_slots]
+  lf::CamArgs *h_cams = nullptr;      // [max_slots]
+  lf::ChunkDesc *h_chunks[2] = {nullptr, nullptr};
+  IterReadback *h_rb = nullptr;       // [2]
+  DevBuf d_slots, d_chunks[2];
+  // batch scratch
+  DevBuf rec1, rec2, queue, qcount, retry, rcount, contrib, skeys, skeys2, svals, svals2, shist, status;
+  int64_t max_chunks = 0;
+  // statistics
+  std::vector<double> lat;
+  int64_t completed = 0, rejected = 0, rays_primary = 0, rays_secondary = 0, iterations = 0;
+  double t_first = -1.0, t_last = -1.0;
+};
+
+namespace {
+
+lf_status sfail(lf_server *s, lf_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->err = buf;
+  return st;
+}
+
+int64_t request_cost(const lf_request &r) {
+  const int64_t R = (int64_t)r.cam.w * r.cam.h;
+  const int64_t H = r.env.h, W = r.env.w;
+  return R * (32 + 44 * (int64_t)r.spp) + 12 * H * W + lfh::env_table_bytes((int)H, (int)W);
+}
+
+// Marks a ticket finished (mu held).
+void finish_ticket(lf_server *s, uint64_t t, lf_status st, double when) {
+  auto it = s->tickets.find(t);
+  if (it == s->tickets.end() || it->second.state == kDone) return;
+  it->second.state = kDone;
+  it->second.status = st;
+  it->second.t_done = when;
+  if (st == LF_OK) {
+    s->lat.push_back(when - it->second.t_submit);
+    s->completed += 1;
+    s->t_last = when;
+  }
+}
+
+// Stages an admitted request into its slot: transforms, camera, environment
+// copy, instance records and sampling tables (all on the server stream).
+bool stage_slot(lf_server *s, int slot, const lf_request &r) {
+  lf_ctx *c = s->ctx;
+  SlotDev &sd = s->slots[slot];
+  const int M = c->n_inst - 1;
+  const int H = r.env.h, W = r.env.w;
+  hipStream_t st = s->stream;
+  if (!sd.xf.ensure(sizeof(float) * 12 * (M > 0 ? M : 1)) || !sd.tex.ensure(sizeof(float) * 3 * (size_t)H * W) ||
+      !lfh::ensure_env_tables(sd.cdf_row, sd.cdf_col, sd.lum, sd.rowsum, sd.roww, sd.scal, H, W))
+    return false;
+  float *xf = sd.xf.as<float>();
+  if (M > 0) {
+    if (hipMemcpyAsync(xf, r.xf.R, sizeof(float) * 9 * M, hipMemcpyDefault, st) != hipSuccess ||
+        hipMemcpyAsync(xf + 9 * M, r.xf.t, sizeof(float) * 3 * M, hipMemcpyDefault, st) != hipSuccess)
+      return false;
+  }
+  if (hipMemcpyAsync(sd.tex.p, r.env.texels, sizeof(float) * 3 * (size_t)H * W, hipMemcpyDefault, st) != hipSuccess)
+    return false;
+  lf::CamArgs &ca = s->h_cams[slot];
+  memset(&ca, 0, sizeof ca);
+  if (lfh::camera_args(nullptr, r.cam, ca) != LF_OK) return false;  // validated at submission
+  if (hipMemcpyAsync(sd.cam.p, &ca, sizeof ca, hipMemcpyHostToDevice, st) != hipSuccess) return false;
+  lf::launch_fill_u32(sd.status.as<uint32_t>(), 0u, 1, st);
+  lf::launch_instances(M > 0 ? xf : nullptr, M > 0 ? xf + 9 * M : nullptr, c->rootbox.as<float>(),
+                       c->d_first.as<int32_t>(), c->d_n.as<int32_t>(), c->d_root.as<int32_t>(), c->n_inst,
+                       sd.inst.as<lf::InstRec>(), sd.bounds.as<double>(), sd.status.as<uint32_t>(), st);
+  lf::launch_env_tables(sd.tex.as<float>(), H, W, s->cfg.params.flags, sd.cdf_row.as<double>(),
+                        sd.cdf_col.as<double>(), sd.lum.as<double>(), sd.rowsum.as<double>(), sd.roww.as<double>(),
+                        sd.scal.as<double>(), st);
+  lf::BatchSlot &b = s->h_slots[slot];
+  memset(&b, 0, sizeof b);
+  b.inst = sd.inst.as<lf::InstRec>();
+  b.bounds = sd.bounds.as<double>();
+  b.cam = sd.cam.as<lf::CamArgs>();
+  b.E.tex = sd.tex.as<float>();
+  b.E.H = H;
+  b.E.W = W;
+  b.E.cdf_row = sd.cdf_row.as<double>();
+  b.E.cdf_col = sd.cdf_col.as<double>();
+  b.E.lum = sd.lum.as<double>();
+  b.E.rowsum = sd.rowsum.as<double>();
+  b.E.roww = sd.roww.as<double>();
+  b.E.scal = sd.scal.as<double>();
+  b.radiance = r.out.radiance;
+  b.depth = r.out.depth;
+  b.normal = r.out.normal;
+  b.alpha = r.out.alpha;
+  b.seed = r.seed;
+  b.spp = r.spp;
+  if (hipMemcpyAsync(s->d_slots.as<lf::BatchSlot>() + slot, &b, sizeof b, hipMemcpyHostToDevice, st) != hipSuccess)
+    return false;
+  return hipGetLastError() == hipSuccess;
+}
+
+// Launches one batched pass over the tiles (chunk table in buffer buf).
+bool launch_pass(lf_server *s, const std::vector<lf::SchedTile> &tiles, int buf, InFlight &fl) {
+  lf_ctx *c = s->ctx;
+  hipStream_t st = s->stream;
+  lf::ChunkDesc *hc = s->h_chunks[buf];
+  int64_t nch = 0, prim = 0;
+  for (const lf::SchedTile &t : tiles) {
+    for (int64_t r = 0; r < t.n; r += lf::kChunk) {
+      if (nch >= s->max_chunks) return false;  // the planner never exceeds the batch size
+      hc[nch].slot = t.slot;
+      hc[nch].n = (int32_t)std::min<int64_t>(lf::kChunk, t.n - r);
+      hc[nch].first = t.first + r;
+      ++nch;
+    }
+    prim += t.n;
+  }
+  if (hipMemcpyAsync(s->d_chunks[buf].p, hc, sizeof(lf::ChunkDesc) * nch, hipMemcpyHostToDevice, st) != hipSuccess)
+    return false;
+  lf::RenderArgs a;
+  memset(&a, 0, sizeof a);
+  lfh::scene_view(c, a.S);
+  lfh::trace_params(c, &s->cfg.params, a.P);
+  a.P.spp = s->cfg.max_spp;  // replaced per request in the shading passes
+  a.P.counters = nullptr;
+  a.spp_stride = s->cfg.max_spp;
+  a.R = nch * lf::kChunk;
+  a.chunks = s->d_chunks[buf].as<lf::ChunkDesc>();
+  a.slots = s->d_slots.as<lf::BatchSlot>();
+  a.rec1 = s->rec1.as<lf::SurfRec>();
+  a.rec2 = s->rec2.as<lf::SurfRec>();
+  a.queue = s->queue.as<lf::SecEntry>();
+  a.queue_count = s->qcount.as<uint32_t>();
+  a.retry = s->retry.as<int32_t>();
+  a.retry_count = s->rcount.as<uint32_t>();
+  a.contrib = s->contrib.as<float>();
+  a.status = s->status.as<uint32_t>();
+  const bool sorted = !(s->cfg.params.flags & LF_FLAG_UNSORTED);
+  a.order = sorted ? s->svals.as<int32_t>() : nullptr;
+  lf::launch_fill_u32(a.queue_count, 0u, 1, st);
+  lf::launch_trace1(a, false, st);
+  lf::launch_shade1(a, false, st);
+  if (sorted) {
+    const int64_t cap = a.R * a.spp_stride;
+    lf::launch_secondary_keys(a.queue, a.queue_count, cap, nullptr, a.chunks, a.slots, s->skeys.as<uint64_t>(),
+                              s->svals.as<int32_t>(), st);
+    lf::radix_sort(s->skeys.as<uint64_t>(), s->svals.as<int32_t>(), s->skeys2.as<uint64_t>(),
+                   s->svals2.as<int32_t>(), s->shist.as<uint32_t>(), cap, st, 32);
+  }
+  lf::launch_trace2(a, st);
+  lf::launch_shade2(a, false, st);
+  lf::launch_resolve(a, st);
+  IterReadback *rb = s->h_rb + buf;
+  if (hipMemcpyAsync(&rb->status, a.status, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&rb->secondaries, a.queue_count, 4, hipMemcpyDeviceToHost, st) != hipSuccess)
+    return false;
+  lf::launch_fill_u32(a.status, 0u, 1, st);
+  if (hipEventRecord(fl.done, st) != hipSuccess) return false;
+  fl.tiles = tiles;
+  fl.buf = buf;
+  fl.primaries = prim;
+  return hipGetLastError() == hipSuccess;
+}
+
+lf_status status_of(uint32_t st) {
+  if (st & lf::kStatusOverflow) return LF_EOVERFLOW;
+  if (st & lf::kStatusBadTransform) return LF_EINVAL;
+  if (st & lf::kStatusBvhCorrupt) return LF_EDEVICE;
+  return LF_OK;
+}
+
+// Waits for the oldest pass and completes its requests.
+bool retire_one(lf_server *s, std::deque<InFlight> &fl, std::vector<hipEvent_t> &events) {
+  InFlight f = fl.front();
+  fl.pop_front();
+  if (hipEventSynchronize(f.done) != hipSuccess) return false;
+  const double t = now_ms();
+  const IterReadback rb = s->h_rb[f.buf];
+  const lf_status st = status_of(rb.status);
+  events.push_back(f.done);
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->rays_primary += f.primaries;
+  s->rays_secondary += rb.secondaries;
+  if (st != LF_OK) {
+    // a device condition ends every request of the pass
+    for (const lf::SchedTile &tl : f.tiles) finish_ticket(s, s->slot_ticket[tl.slot], st, t);
+    s->err = "device status set during a batched pass";
+  }
+  for (auto &done : s->sched.retire(f.tiles)) {
+    // the request's own instance status (its pass has completed, so the word is final)
+    uint32_t ist = 0;
+    if (hipMemcpy(&ist, s->slots[done.first].status.p, 4, hipMemcpyDeviceToHost) != hipSuccess) return false;
+    const lf_status rs = status_of(ist);
+    if (rs != LF_OK) s->err = "degenerate or non-finite object transform";
+    finish_ticket(s, done.second, rs, t);
+  }
+  s->cv_done.notify_all();
+  return true;
+}
+
+void fail_all(lf_server *s, lf_status st, const char *why) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->failed = true;
+  s->fail_status = st;
+  s->err = why;
+  const double t = now_ms();
+  for (auto &kv : s->tickets)
+    if (kv.second.state != kDone) finish_ticket(s, kv.first, st, t);
+  s->cv_done.notify_all();
+}
+
+void serve(lf_server *s) {
+  if (hipSetDevice(s->ctx->device) != hipSuccess) {
+    fail_all(s, LF_EDEVICE, "hipSetDevice failed on the server thread");
+    return;
+  }
+  std::deque<InFlight> fl;
+  std::vector<hipEvent_t> events;
+  for (int i = 0; i < 3; ++i) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      fail_all(s, LF_EDEVICE, "event creation failed");
+      return;
+    }
+    events.push_back(e);
+  }
+  int next_buf = 0;
+  bool ok = true;
+  while (ok) {
+    std::vector<std::pair<int, uint64_t>> admitted;
+    std::vector<lf::SchedTile> tiles;
+    std::vector<lf_request> reqs;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (fl.empty()) {
+        s->cv_work.wait(lk, [&] { return s->stop || s->sched.pending() > 0 || s->sched.has_unscheduled(); });
+        if (s->stop) break;
+      }
+      if (!s->stop && fl.size() < 2) {
+        admitted = s->sched.admit();
+        for (auto &ad : admitted) {
+          s->slot_ticket[ad.first] = ad.second;
+          TicketRec &tr = s->tickets[ad.second];
+          tr.state = kAdmitted;
+          reqs.push_back(tr.req);
+        }
+        tiles = s->sched.plan();
+      }
+    }
+    for (size_t i = 0; i < admitted.size() && ok; ++i) ok = stage_slot(s, admitted[i].first, reqs[i]);
+    if (!ok) break;
+    if (!tiles.empty()) {
+      InFlight f;
+      f.done = events.back();
+      events.pop_back();
+      ok = launch_pass(s, tiles, next_buf, f);
+      if (!ok) break;
+      next_buf ^= 1;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->iterations += 1;
+      }
+      fl.push_back(f);
+    }
+    // keep at most two passes in flight; with nothing new to launch, retire
+    while (ok && !fl.empty() && (fl.size() >= 2 || tiles.empty())) {
+      ok = retire_one(s, fl, events);
+      if (tiles.empty()) break;
+    }
+  }
+  while (ok && !fl.empty()) ok = retire_one(s, fl, events);
+  if (!ok) {
+    const hipError_t e = hipGetLastError();
+    char buf[256];
+    snprintf(buf, sizeof buf, "server pass failed: %s", hipGetErrorString(e));
+    fail_all(s, LF_EDEVICE, buf);
+  }
+  (void)hipStreamSynchronize(s->stream);
+  for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  for (InFlight &f : fl) (void)hipEventDestroy(f.done);
+}
+
+}  // namespace
+
+extern "C" {
+
+void lf_server_config_default(lf_server_config *cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof *cfg);
+  cfg->max_slots = 16;
+  cfg->hbm_budget_bytes = (int64_t)16 << 30;
+  cfg->tile_rays = 65536;
+  cfg->batch_rays = 262144;
+  cfg->max_spp = 4;
+  cfg->max_pending = 4096;
+  lf_params_default(&cfg->params);
+}
+
+lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **out) {
+  if (!c || !out) return LF_EINVAL;
+  *out = nullptr;
+  if (!cfg) return lfh::fail(c, LF_EINVAL, "config is NULL");
+  if (!c->has_scene) return lfh::fail(c, LF_EINVAL, "no scene set");
+  if (cfg->max_slots < 1 || cfg->max_slots > 64) return lfh::fail(c, LF_EINVAL, "max_slots not in 1..64");
+  if (cfg->tile_rays < lf::kChunk || cfg->tile_rays % lf::kChunk || cfg->batch_rays < cfg->tile_rays ||
+      cfg->batch_rays % lf::kChunk)
+    return lfh::fail(c, LF_EINVAL, "tile_rays and batch_rays must be multiples of %d with batch >= tile", lf::kChunk);
+  if (cfg->max_spp < 1 || cfg->max_spp > 64) return lfh::fail(c, LF_EINVAL, "max_spp not in 1..64");
+  if (cfg->max_pending < 1 || cfg->hbm_budget_bytes < 1) return lfh::fail(c, LF_EINVAL, "invalid queue or budget");
+  lf_params p = cfg->params;
+  p.spp = cfg->max_spp;
+  lf_status st = lfh::validate_params(c, &p);
+  if (st) return st;
+  if (p.flags & (LF_FLAG_COUNT | LF_FLAG_NO_SECONDARY))
+    return lfh::fail(c, LF_EUNSUPPORTED, "LF_FLAG_COUNT and LF_FLAG_NO_SECONDARY are not served");
+  if ((int64_t)cfg->batch_rays * cfg->max_spp >= (int64_t)INT32_MAX)
+    return lfh::fail(c, LF_EUNSUPPORTED, "batch_rays x max_spp too large");
+  if (!lfh::set_device(c)) return lfh::fail(c, LF_EDEVICE, "hipSetDevice");
+  const double sig2 = p.support_sigma * p.support_sigma;
+  if (p.alpha_min != c->built_alpha_min || sig2 != c->built_sig2) {
+    if (c->servers > 0) return lfh::fail(c, LF_EBUSY, "another server serves other tracing constants");
+    if ((st = lfh::refit_impl(c, p.alpha_min, sig2))) return st;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return lfh::check_hip(c, "server create");
+
+  lf_server *s = new lf_server();
+  s->ctx = c;
+  s->cfg = *cfg;
+  lf::SchedConfig sc;
+  sc.max_slots = cfg->max_slots;
+  sc.budget = cfg->hbm_budget_bytes;
+  sc.tile_rays = cfg->tile_rays;
+  sc.batch_rays = cfg->batch_rays;
+  sc.max_pending = cfg->max_pending;
+  sc.chunk = lf::kChunk;
+  s->sched = lf::Scheduler(sc);
+  s->slot_ticket.assign(cfg->max_slots, 0);
+  s->slots = std::vector<SlotDev>(cfg->max_slots);
+  const int64_t B = cfg->batch_rays;
+  const int64_t BS = B * cfg->max_spp;
+  s->max_chunks = B / lf::kChunk;
+  bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipHostMalloc((void **)&s->h_slots, sizeof(lf::BatchSlot) * cfg->max_slots, hipHostMallocDefault) ==
+                 hipSuccess;
+  ok = ok && hipHostMalloc((void **)&s->h_cams, sizeof(lf::CamArgs) * cfg->max_slots, hipHostMallocDefault) ==
+                 hipSuccess;
+  for (int i = 0; i < 2 && ok; ++i)
+    ok = hipHostMalloc((void **)&s->h_chunks[i], sizeof(lf::ChunkDesc) * s->max_chunks, hipHostMallocDefault) ==
+             hipSuccess &&
+         s->d_chunks[i].ensure(sizeof(lf::ChunkDesc) * s->max_chunks);
+  ok = ok && hipHostMalloc((void **)&s->h_rb, sizeof(IterReadback) * 2, hipHostMallocDefault) == hipSuccess;
+  ok = ok && s->d_slots.ensure(sizeof(lf::BatchSlot) * cfg->max_slots);
+  const int M = c->n_inst - 1;
+  for (int i = 0; i < cfg->max_slots && ok; ++i) {
+    SlotDev &sd = s->slots[i];
+    ok = sd.xf.ensure(sizeof(float) * 12 * (M > 0 ? M : 1)) && sd.inst.ensure(sizeof(lf::InstRec) * c->n_inst) &&
+         sd.bounds.ensure(6 * sizeof(double)) && sd.cam.ensure(sizeof(lf::CamArgs)) && sd.status.ensure(4) &&
+         sd.tex.ensure(sizeof(float) * 3 * 256 * 512) &&
+         lfh::ensure_env_tables(sd.cdf_row, sd.cdf_col, sd.lum, sd.rowsum, sd.roww, sd.scal, 256, 512);
+  }
+  ok = ok && s->rec1.ensure(sizeof(lf::SurfRec) * B) && s->rec2.ensure(sizeof(lf::SurfRec) * BS) &&
+       s->queue.ensure(sizeof(lf::SecEntry) * BS) && s->qcount.ensure(4) && s->retry.ensure(4 * BS) &&
+       s->rcount.ensure(4) && s->contrib.ensure(sizeof(float) * 3 * BS) && s->skeys.ensure(8 * BS) &&
+       s->skeys2.ensure(8 * BS) && s->svals.ensure(4 * BS) && s->svals2.ensure(4 * BS) &&
+       s->shist.ensure(4 * lf::radix_sort_hist_words(BS)) && s->status.ensure(4);
+  if (ok) {
+    lf::launch_fill_u32(s->status.as<uint32_t>(), 0u, 1, s->stream);
+    ok = hipStreamSynchronize(s->stream) == hipSuccess;
+  }
+  if (!ok) {
+    (void)hipGetLastError();
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->h_slots) (void)hipHostFree(s->h_slots);
+    if (s->h_cams) (void)hipHostFree(s->h_cams);
+    for (int i = 0; i < 2; ++i)
+      if (s->h_chunks[i]) (void)hipHostFree(s->h_chunks[i]);
+    if (s->h_rb) (void)hipHostFree(s->h_rb);
+    delete s;
+    return lfh::fail(c, LF_ENOMEM, "server buffers (batch of %lld rays x %d samples)", (long long)B, cfg->max_spp);
+  }
+  c->servers += 1;
+  s->worker = std::thread(serve, s);
+  *out = s;
+  return LF_OK;
+}
+
+lf_status lf_server_submit(lf_server *s, const lf_request *r, uint64_t *ticket) {
+  if (!s) return LF_EINVAL;
+  if (!r || !ticket) return sfail(s, LF_EINVAL, "request or ticket is NULL");
+  const int M = s->ctx->n_inst - 1;
+  const lf_camera &cm = r->cam;
+  if (cm.w < 1 || cm.h < 1 || !(cm.fov_y_deg > 0.f && cm.fov_y_deg < 180.f))
+    return sfail(s, LF_EINVAL, "invalid camera");
+  for (int k = 0; k < 12; ++k)
+    if (!std::isfinite(cm.pose[k])) return sfail(s, LF_EINVAL, "non-finite camera pose");
+  if ((int64_t)cm.w * cm.h >= (int64_t)INT32_MAX) return sfail(s, LF_EUNSUPPORTED, "camera too large");
+  if (r->spp < 1 || r->spp > s->cfg.max_spp) return sfail(s, LF_EINVAL, "spp=%d not in 1..%d", r->spp, s->cfg.max_spp);
+  if (!r->env.texels || r->env.h < 1 || r->env.w < 1 || r->env.h > 8192 || r->env.w > 8192)
+    return sfail(s, LF_EINVAL, "invalid environment map");
+  if (M > 0 && (!r->xf.R || !r->xf.t)) return sfail(s, LF_EINVAL, "scene has %d objects but no transforms", M);
+  if (!r->out.radiance || !r->out.depth || !r->out.normal || !r->out.alpha)
+    return sfail(s, LF_EINVAL, "radiance, depth, normal and alpha outputs are required");
+  if (r->out.hit_idx || r->out.sec_hit_idx) return sfail(s, LF_EUNSUPPORTED, "the server does not return hit lists");
+  const int64_t cost = request_cost(*r);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->failed) return s->fail_status;
+  if (s->stop) return LF_EBUSY;
+  const uint64_t t = s->next_ticket;
+  const lf::Scheduler::Submit res = s->sched.submit(t, (int64_t)cm.w * cm.h, cost);
+  if (res != lf::Scheduler::kOk) {
+    s->rejected += 1;
+    if (res == lf::Scheduler::kBusy) {
+      s->err = "server queue full";
+      return LF_EBUSY;
+    }
+    s->err = "request working set exceeds the HBM budget";
+    return LF_EUNSUPPORTED;
+  }
+  s->next_ticket += 1;
+  TicketRec &tr = s->tickets[t];
+  tr.req = *r;
+  tr.rays = (int64_t)cm.w * cm.h;
+  tr.t_submit = now_ms();
+  if (s->t_first < 0.0) s->t_first = tr.t_submit;
+  *ticket = t;
+  s->cv_work.notify_one();
+  return LF_OK;
+}
+
+lf_status lf_server_poll(lf_server *s, uint64_t ticket, int *done) {
+  if (!s) return LF_EINVAL;
+  if (!done) return sfail(s, LF_EINVAL, "done is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) {
+    s->err = "unknown ticket";
+    return LF_EINVAL;
+  }
+  *done = it->second.state == kDone;
+  return it->second.state == kDone ? it->second.status : LF_OK;
+}
+
+lf_status lf_server_wait(lf_server *s, uint64_t ticket) {
+  if (!s) return LF_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) {
+    s->err = "unknown ticket";
+    return LF_EINVAL;
+  }
+  s->cv_done.wait(lk, [&] { return it->second.state == kDone; });
+  return it->second.status;
+}
+
+lf_status lf_server_latency(lf_server *s, uint64_t ticket, double *ms) {
+  if (!s) return LF_EINVAL;
+  if (!ms) return sfail(s, LF_EINVAL, "ms is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end() || it->second.state != kDone) {
+    s->err = "unknown or unfinished ticket";
+    return LF_EINVAL;
+  }
+  *ms = it->second.t_done - it->second.t_submit;
+  return it->second.status;
+}
+
+lf_status lf_server_stats_get(lf_server *s, lf_server_stats *out) {
+  if (!s) return LF_EINVAL;
+  if (!out) return sfail(s, LF_EINVAL, "stats is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  memset(out, 0, sizeof *out);
+  std::vector<double> v = s->lat;
+  std::sort(v.begin(), v.end());
+  auto rank = [&](double q) {
+    if (v.empty()) return 0.0;
+    size_t i = (size_t)std::ceil(q * (double)v.size());
+    i = i < 1 ? 1 : (i > v.size() ? v.size() : i);
+    return v[i - 1];
+  };
+  out->p50_ms = rank(0.50);
+  out->p99_ms = rank(0.99);
+  out->completed = s->completed;
+  out->rejected = s->rejected;
+  out->rays_primary = s->rays_primary;
+  out->rays_secondary = s->rays_secondary;
+  out->iterations = s->iterations;
+  const double span = s->t_last - s->t_first;
+  out->rays_per_s = span > 0.0 ? (double)(s->rays_primary + s->rays_secondary) / (span * 1e-3) : 0.0;
+  return LF_OK;
+}
+
+const char *lf_server_last_error(lf_server *s) {
+  if (!s) return "null server";
+  std::lock_guard<std::mutex> lk(s->mu);
+  thread_local std::string copy;
+  copy = s->err;
+  return copy.c_str();
+}
+
+void lf_server_destroy(lf_server *s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv_work.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    const double t = now_ms();
+    for (auto &kv : s->tickets)
+      if (kv.second.state != kDone) finish_ticket(s, kv.first, LF_EBUSY, t);
+    s->cv_done.notify_all();
+  }
+  (void)hipSetDevice(s->ctx->device);
+  if (s->stream) {
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamDestroy(s->stream);
+  }
+  if (s->h_slots) (void)hipHostFree(s->h_slots);
+  if (s->h_cams) (void)hipHostFree(s->h_cams);
+  for (int i = 0; i < 2; ++i)
+    if (s->h_chunks[i]) (void)hipHostFree(s->h_chunks[i]);
+  if (s->h_rb) (void)hipHostFree(s->h_rb);
+  s->ctx->servers -= 1;
+  delete s;
+}
+
+}  // extern "C"

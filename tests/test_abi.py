@@ -57,3 +57,53 @@ def test_struct_sizes_match_header(lib):
     assert C.sizeof(_lib.Camera) == 12 * 4 + 4 + 4 + 4
     assert C.sizeof(_lib.Params) == 4 + 4 + 8 + 6 * 8 + 8  # trailing uint32 padded to 8
     assert C.sizeof(_lib.Surfels) == 7 * 8 + 8 + 8 + 8
+
+
+def _c_layout(tmp_path):
+    """sizeof and field offsets of every ABI struct, as a C compiler sees the header."""
+    import subprocess
+    from paper_2608_29269_amd import _lib
+    structs = {"lf_surfels": _lib.Surfels, "lf_transforms": _lib.Transforms, "lf_envmap": _lib.EnvMap,
+               "lf_rays": _lib.Rays, "lf_camera": _lib.Camera, "lf_params": _lib.Params, "lf_outputs": _lib.Outputs,
+               "lf_grad_out": _lib.GradOut, "lf_grad_in": _lib.GradIn, "lf_scene_info": _lib.SceneInfo,
+               "lf_render_stats": _lib.RenderStats, "lf_server_config": _lib.ServerConfig,
+               "lf_request": _lib.Request, "lf_server_stats": _lib.ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            cname, key, val = ln.split()
+            got[(cname, key)] = int(val)
+    return structs, got
+
+
+def test_ctypes_layout_matches_the_c_compiler(tmp_path):
+    structs, got = _c_layout(tmp_path)
+    for cname, py in structs.items():
+        assert C.sizeof(py) == got[(cname, "size")], cname
+        for f, _ in py._fields_:
+            assert getattr(py, f).offset == got[(cname, f)], (cname, f)
+
+
+def test_server_null_paths_and_defaults(lib):
+    from paper_2608_29269_amd import _lib
+    assert lib.lf_server_last_error(None) == b"null server"
+    assert lib.lf_server_create(None, None, None) == 1
+    assert lib.lf_server_submit(None, None, None) == 1
+    assert lib.lf_server_poll(None, 1, None) == 1
+    lib.lf_server_destroy(None)
+    cfg = _lib.ServerConfig()
+    lib.lf_server_config_default(C.byref(cfg))
+    assert (cfg.max_slots, cfg.tile_rays, cfg.batch_rays, cfg.max_spp) == (16, 65536, 262144, 4)
+    assert cfg.hbm_budget_bytes == 16 << 30 and cfg.tile_rays % 128 == 0 and cfg.batch_rays % 128 == 0
+    assert cfg.params.k == 32 and cfg.params.alpha_min == 1.0 / 255.0
