@@ -12,7 +12,9 @@ scene-linear L1 loss against a target rendered from perturbed parameters,
 the replayed backward pass (hit lists recomputed), and an SGD update of all
 parameters.  The metric counts traced rays (primary + live secondary rays)
 per second of fwd+bwd steps; forward-only rays/s and per-phase timings are
-reported alongside.
+reported alongside, and a serving run (Poisson stream of rearrange-and-relight
+requests) gives p50/p99 latency of the continuous-batching server against the
+plain tracer serving the same stream one request at a time.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -48,6 +50,14 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=512, help="primary rays of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fwd-steps", type=int, default=5)
+    ap.add_argument("--serve-requests", type=int, default=40, help="requests per serving run (0 = skip)")
+    ap.add_argument("--serve-loads", type=str, default="0.8",
+                    help="comma-separated arrival rates as fractions of the plain tracer's capacity")
+    ap.add_argument("--serve-policies", type=str, default="0",
+                    help="comma-separated pass-filling policies (0 shortest first, 1 oldest first, 2 round robin)")
+    ap.add_argument("--serve-batch", type=int, default=262144, help="primary rays per batched pass")
+    ap.add_argument("--serve-in-flight", type=int, default=1, help="passes queued on the device at once")
+    ap.add_argument("--serve-only", action="store_true", help="skip the fwd+bwd and CPU legs")
     return ap.parse_args()
 
 
@@ -97,6 +107,12 @@ def main():
     grads = {k: torch.empty_like(v) for k, v in params.items()}
     grads["env"] = torch.empty_like(env)
     lr = 1e-5
+
+    if args.serve_only:
+        serving = serve_bench(tr, sc, args, [float(x) for x in args.serve_loads.split(",") if x],
+                              [int(x) for x in args.serve_policies.split(",") if x])
+        print(json.dumps({"serving": serving}))
+        return
 
     def step():
         tr.refit()
@@ -174,6 +190,11 @@ def main():
                "sample": f"{len(pix)} random pixels of the 1024x1024 camera (plus their live secondary rays), "
                          f"fwd+bwd, 1M surfels brute force in FP64, {cdt:.1f} s"}
 
+    serving = None
+    if args.serve_requests > 0:
+        serving = serve_bench(tr, sc, args, [float(x) for x in args.serve_loads.split(",") if x],
+                              [int(x) for x in args.serve_policies.split(",") if x])
+
     roof = roofline(phases, counts, stats, args, nr)
     res = {
         "metric": "rays/s fwd+bwd at 1M surfels",
@@ -201,8 +222,125 @@ def main():
         "phases_ms_per_step": {k_: v[0] / args.steps for k_, v in phases.items() if v[1]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(res))
+
+
+def serve_bench(tr, sc, args, loads, policies=(0,)):
+    """Relight latency (arrival to result) of a Poisson request stream on the
+    resident scene: the continuous-batching server against the plain tracer
+    serving the same stream FIFO, one request at a time.  Each request draws a
+    rigid transform per object, a 256x512 lognormal env map, a resolution in
+    {256, 512, 1024}^2 and S in {1, 4}; the rate is a fraction of the plain
+    tracer's capacity measured on that mix."""
+    import torch
+
+    import paper_2608_29269_amd as lf
+    import scenegen
+    dev = torch.device("cuda", 0)
+    M = sc.n_objects
+    res_set, spp_set = (256, 512, 1024), (1, 4)
+    # plain capacity on the request mix (each combination equally likely)
+    cal = scenegen.request_stream(M, 6, 1.0, seed=99)
+    svc = []
+    for j, (res, spp) in enumerate([(r, s_) for r in res_set for s_ in spp_set]):
+        q = cal[j]
+        cam = scenegen.sphere_camera(np.random.default_rng(j), res, res)
+        env, R, t = (torch.as_tensor(x, device=dev) for x in (q.env, q.R, q.t))
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tr.render(env, R, t, cameras=[cam], k=32, spp=spp, seed=q.seed)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        svc.append(float(np.median(times[1:])))
+    mean_svc = float(np.mean(svc))
+    capacity = 1.0 / mean_svc
+    log(f"serving: plain capacity {capacity:.2f} requests/s (mean service {mean_svc * 1e3:.1f} ms)")
+    runs = []
+    for load in loads:
+        rate = load * capacity
+        reqs = scenegen.request_stream(M, args.serve_requests, rate, seed=5, resolutions=res_set, spps=spp_set)
+        dv = []
+        for q in reqs:
+            n = q.camera.w * q.camera.h
+            dv.append(dict(env=torch.as_tensor(q.env, device=dev), R=torch.as_tensor(q.R, device=dev),
+                           t=torch.as_tensor(q.t, device=dev),
+                           out=dict(radiance=torch.empty((n, 3), device=dev), depth=torch.empty(n, device=dev),
+                                    normal=torch.empty((n, 3), device=dev), alpha=torch.empty(n, device=dev))))
+        torch.cuda.synchronize()
+        # plain tracer, FIFO, one request at a time
+        tr.stats()
+        lat = []
+        t_start = time.perf_counter()
+        for q, d in zip(reqs, dv):
+            now = time.perf_counter() - t_start
+            if now < q.arrival_s:
+                time.sleep(q.arrival_s - now)
+            tr.render(d["env"], d["R"], d["t"], cameras=[q.camera], k=32, spp=q.spp, seed=q.seed, out=d["out"])
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t_start - q.arrival_s)
+        span = time.perf_counter() - t_start - reqs[0].arrival_s
+        ps = tr.stats()
+        plain = {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(np.mean(lat)) * 1e3,
+                 "rays_per_s": (ps["rays_primary"] + ps["rays_secondary"]) / span}
+        log(f"serving load {load}: plain p50 {plain['p50_ms']:.0f} ms p99 {plain['p99_ms']:.0f} ms")
+        plain["by_class_p50_ms"] = by_class(reqs, lat)
+        # continuous-batching server, per pass-filling policy
+        for policy in policies:
+            srv = lf.Server(tr, max_slots=16, hbm_budget_bytes=16 << 30, tile_rays=65536,
+                            batch_rays=args.serve_batch, max_spp=4, policy=policy,
+                            max_in_flight=args.serve_in_flight)
+            tickets = []
+            t_start = time.perf_counter()
+            for q, d in zip(reqs, dv):
+                now = time.perf_counter() - t_start
+                if now < q.arrival_s:
+                    time.sleep(q.arrival_s - now)
+                tickets.append(srv.submit(d["env"], q.camera, R=d["R"], t=d["t"], spp=q.spp, seed=q.seed,
+                                          out=d["out"]))
+            for tk in tickets:
+                srv.wait(tk)
+            slat = [srv.latency_ms(tk) / 1e3 for tk in tickets]
+            st = srv.stats()
+            srv.close()
+            served = {"policy": POLICY_NAMES[policy], "p50_ms": pct(slat, 50), "p99_ms": pct(slat, 99),
+                      "mean_ms": float(np.mean(slat)) * 1e3, "rays_per_s": st["rays_per_s"],
+                      "passes": st["iterations"], "by_class_p50_ms": by_class(reqs, slat)}
+            log(f"serving load {load}: server ({POLICY_NAMES[policy]}) p50 {served['p50_ms']:.0f} ms "
+                f"p99 {served['p99_ms']:.0f} ms")
+            runs.append({"load": load, "rate_req_per_s": rate, "requests": len(reqs), "server": served,
+                         "plain": plain,
+                         "p99_ratio_plain_over_server": plain["p99_ms"] / served["p99_ms"],
+                         "p50_ratio_plain_over_server": plain["p50_ms"] / served["p50_ms"]})
+    return {"capacity_req_per_s": capacity, "mean_service_ms": mean_svc * 1e3,
+            "service_ms_alone": {f"{r}x{r} S={s_}": v * 1e3
+                                 for (r, s_), v in zip([(r, s_) for r in res_set for s_ in spp_set], svc)},
+            "mix": "resolution {256,512,1024}^2 x S {1,4}, 256x512 env, 8 rigid transforms per request",
+            "server_config": {"max_slots": 16, "hbm_budget_gib": 16, "tile_rays": 65536,
+                              "batch_rays": args.serve_batch, "max_in_flight": args.serve_in_flight},
+            "runs": runs}
+
+
+POLICY_NAMES = {0: "shortest_first", 1: "oldest_first", 2: "round_robin"}
+
+
+def by_class(reqs, lat):
+    """p50 latency (ms) per (resolution, S) class."""
+    out = {}
+    for key in sorted({(q.camera.w, q.spp) for q in reqs}):
+        v = [l for q, l in zip(reqs, lat) if (q.camera.w, q.spp) == key]
+        out[f"{key[0]} S={key[1]}"] = pct(v, 50)
+    return out
+
+
+def pct(v, q):
+    """Nearest-rank percentile in milliseconds of a list of seconds."""
+    a = np.sort(np.asarray(v, np.float64))
+    i = min(max(int(np.ceil(q / 100.0 * len(a))), 1), len(a))
+    return float(a[i - 1] * 1e3)
 
 
 def source_digest():

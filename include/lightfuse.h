@@ -225,10 +225,12 @@ typedef struct {
 lf_status lf_stats_get(lf_ctx *ctx, lf_render_stats *stats);
 
 /* Traversal counters accumulated by calls made with LF_FLAG_COUNT since the
- * previous read (synchronous; resets them): [0] primary rays, [1] internal
+ * previous read (synchronous; resets them): [0] primary rays, [1] 4-wide
  * nodes visited, [2] surfels tested, [3] hits inserted into k-buffers, then
- * [4..7] the same for secondary rays. */
-lf_status lf_trace_counters(lf_ctx *ctx, uint64_t *counters /*[8]*/);
+ * [4..7] the same for secondary rays, [8] primary and [9] secondary rays
+ * re-traced with exact keys because two binary32 keys collided. */
+#define LF_NUM_COUNTERS 10
+lf_status lf_trace_counters(lf_ctx *ctx, uint64_t *counters /*[LF_NUM_COUNTERS]*/);
 
 /* Per-phase device timers.  When enabled, every phase below is bracketed by
  * HIP events on the context's stream; lf_profile_read synchronises, returns
@@ -247,7 +249,7 @@ lf_status lf_profile_read(lf_ctx *ctx, double *ms /*[LF_NUM_PHASES]*/, int64_t *
  * interaction).  The server renders many such requests at once by
  * continuous batching: every iteration is one batched forward pass (primary
  * trace, shading, secondary trace, shading, resolve) over 128-ray chunks
- * drawn round robin from all admitted requests, each with its own
+ * drawn from all admitted requests (policy below), each with its own
  * transforms, environment, camera, S and seed.  A request's outputs equal
  * those of lf_render with the same inputs bit for bit (ray ids and sampler
  * counters are local to the request).
@@ -267,6 +269,11 @@ lf_status lf_profile_read(lf_ctx *ctx, double *ms /*[LF_NUM_PHASES]*/, int64_t *
  * ------------------------------------------------------------------------- */
 typedef struct lf_server lf_server;
 
+/* Which admitted requests fill a pass first (admission itself is always FIFO). */
+#define LF_SCHED_SHORTEST_FIRST 0 /* smallest remaining work, rays x (1 + S), first; each takes all it can */
+#define LF_SCHED_OLDEST_FIRST   1 /* admission order; each takes all it can (FIFO with backfill) */
+#define LF_SCHED_ROUND_ROBIN    2 /* max(tile_rays, batch_rays / active) rays each, in turn */
+
 typedef struct {
   int32_t max_slots;        /* requests admitted at once, 1..64 (default 16) */
   int64_t hbm_budget_bytes; /* admission budget of the admitted working sets (default 16 GiB) */
@@ -275,6 +282,9 @@ typedef struct {
   int32_t batch_rays;       /* primary rays per iteration, multiple of 128, >= tile_rays (default 262144) */
   int32_t max_spp;          /* largest S a request may ask for, 1..64 (default 4) */
   int32_t max_pending;      /* waiting requests before lf_server_submit returns LF_EBUSY (default 4096) */
+  int32_t policy;           /* LF_SCHED_* (default LF_SCHED_SHORTEST_FIRST) */
+  int32_t max_in_flight;    /* passes queued on the device at once, 1..2 (default 1: a new arrival
+                               joins the next pass) */
   lf_params params;         /* k, constants and flags shared by every request (spp and seed are
                                per request; LF_FLAG_COUNT and LF_FLAG_NO_SECONDARY are not served) */
 } lf_server_config;

@@ -213,10 +213,12 @@ class Tracer:
         return dict(rays_primary=st.rays_primary, rays_secondary=st.rays_secondary)
 
     def trace_counters(self) -> dict:
-        c = (C.c_uint64 * 8)()
+        c = (C.c_uint64 * 10)()
         self._chk(self.L.lf_trace_counters(self.ctx, c))
         keys = ("rays", "nodes", "tests", "inserts")
-        return {"primary": dict(zip(keys, c[:4])), "secondary": dict(zip(keys, c[4:]))}
+        p, s_ = dict(zip(keys, c[:4])), dict(zip(keys, c[4:8]))
+        p["retries"], s_["retries"] = c[8], c[9]
+        return {"primary": p, "secondary": s_}
 
     def profile(self, enable: bool = True):
         self._chk(self.L.lf_profile_enable(self.ctx, int(enable)))
@@ -235,13 +237,15 @@ class Server:
     Request tensors are kept alive here until the request has completed."""
 
     def __init__(self, tracer: Tracer, max_slots=16, hbm_budget_bytes=16 << 30, tile_rays=65536,
-                 batch_rays=262144, max_spp=4, max_pending=4096, k=32, flags=0, **kw):
+                 batch_rays=262144, max_spp=4, max_pending=4096, policy=_lib.SCHED_SHORTEST_FIRST,
+                 max_in_flight=1, k=32, flags=0, **kw):
         self.L = tracer.L
         self.tracer = tracer
         cfg = _lib.ServerConfig()
         self.L.lf_server_config_default(C.byref(cfg))
         cfg.max_slots, cfg.hbm_budget_bytes, cfg.tile_rays = int(max_slots), int(hbm_budget_bytes), int(tile_rays)
         cfg.batch_rays, cfg.max_spp, cfg.max_pending = int(batch_rays), int(max_spp), int(max_pending)
+        cfg.policy, cfg.max_in_flight = int(policy), int(max_in_flight)
         cfg.params = Tracer.params(k, max_spp, 0, flags, **kw)
         srv = C.c_void_p()
         tracer._chk(self.L.lf_server_create(tracer.ctx, C.byref(cfg), C.byref(srv)))

@@ -23,6 +23,7 @@ FLAG_BRUTE_FORCE = 1 << 4
 FLAG_COUNT = 1 << 5
 FLAG_UNSORTED = 1 << 6
 MAX_CAMERAS = 16
+SCHED_SHORTEST_FIRST, SCHED_OLDEST_FIRST, SCHED_ROUND_ROBIN = 0, 1, 2
 
 _fp = C.POINTER(C.c_float)
 _i32p = C.POINTER(C.c_int32)
@@ -84,7 +85,8 @@ class RenderStats(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("max_slots", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("tile_rays", C.c_int32),
-                ("batch_rays", C.c_int32), ("max_spp", C.c_int32), ("max_pending", C.c_int32), ("params", Params)]
+                ("batch_rays", C.c_int32), ("max_spp", C.c_int32), ("max_pending", C.c_int32),
+                ("policy", C.c_int32), ("max_in_flight", C.c_int32), ("params", Params)]
 
 
 class Request(C.Structure):

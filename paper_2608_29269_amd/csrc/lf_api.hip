@@ -235,10 +235,10 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
   const int64_t RS = R * p->spp;
   const int64_t R1 = R > 0 ? R : 1;
   if (!c->rec1.ensure(sizeof(lf::SurfRec) * R1) || !c->rcount.ensure(sizeof(uint32_t)) ||
-      !c->retry.ensure(sizeof(int32_t) * (trace2 && RS > R1 ? RS : R1)))
+      !c->retry.ensure(sizeof(lf::RetryEnt) * (trace2 && RS > R1 ? RS : R1)))
     return fail(c, LF_ENOMEM, "surface records");
   a.rec1 = c->rec1.as<lf::SurfRec>();
-  a.retry = c->retry.as<int32_t>();
+  a.retry = c->retry.as<lf::RetryEnt>();
   a.retry_count = c->rcount.as<uint32_t>();
   if (trace2) {
     if (!c->queue.ensure(sizeof(lf::SecEntry) * (RS > 0 ? RS : 1)) || !c->qcount.ensure(sizeof(uint32_t)) ||
@@ -299,13 +299,13 @@ lf_status lf_create(lf_ctx **out, int device, void *hip_stream) {
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   if (!set_device(c) || !c->status.ensure(sizeof(uint32_t)) || !c->acc_secondary.ensure(8) ||
-      !c->counters.ensure(64)) {
+      !c->counters.ensure(8 * LF_NUM_COUNTERS)) {
     delete c;
     return LF_EDEVICE;
   }
   lf::launch_fill_u32(c->status.as<uint32_t>(), 0u, 1, c->stream);
   lf::launch_fill_u32(c->acc_secondary.as<uint32_t>(), 0u, 2, c->stream);
-  lf::launch_fill_u32(c->counters.as<uint32_t>(), 0u, 16, c->stream);
+  lf::launch_fill_u32(c->counters.as<uint32_t>(), 0u, 2 * LF_NUM_COUNTERS, c->stream);
   if (check_hip(c, "create")) {
     delete c;
     return LF_EDEVICE;
@@ -609,9 +609,9 @@ lf_status lf_trace_counters(lf_ctx *c, uint64_t *out) {
   if (!out) return fail(c, LF_EINVAL, "counters output is NULL");
   set_device(c);
   if (hipStreamSynchronize(c->stream) != hipSuccess ||
-      hipMemcpy(out, c->counters.p, 64, hipMemcpyDeviceToHost) != hipSuccess)
+      hipMemcpy(out, c->counters.p, 8 * LF_NUM_COUNTERS, hipMemcpyDeviceToHost) != hipSuccess)
     return check_hip(c, "counters");
-  lf::launch_fill_u32(c->counters.as<uint32_t>(), 0u, 16, c->stream);
+  lf::launch_fill_u32(c->counters.as<uint32_t>(), 0u, 2 * LF_NUM_COUNTERS, c->stream);
   return check_hip(c, "counters");
 }
 

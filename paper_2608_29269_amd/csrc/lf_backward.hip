@@ -16,20 +16,6 @@ namespace {
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-__device__ __forceinline__ void wave_append_i32(bool live, int32_t v, int32_t *list, uint32_t *count) {
-  uint64_t mask = __ballot(live);
-  if (mask == 0) return;
-  const int lane = __lane_id();
-  const int leader = __ffsll((unsigned long long)mask) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
-  base = __shfl(base, leader);
-  if (live) {
-    uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
-    list[base + (uint32_t)__popcll(mask & lt)] = v;
-  }
-}
-
 __device__ __forceinline__ void env_scatter(const EnvView &E, float *genv, d3 w, d3 g) {
   Taps tp;
   env_taps(E, w, tp);
@@ -266,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_trace(RenderArgs a, GradArgs G) 
   kb.collide = false;
   if (active) trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
   const bool again = active && kb.collide;
-  wave_append_i32(again, (int32_t)ray, a.retry, a.retry_count);
+  queue_retry<K>(again, (int32_t)ray, kb, a.retry, a.retry_count, nullptr);
   if (active && !again) adjoint_hits<K>(a, G, sd, kb, o, d);
 }
 
@@ -275,13 +261,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_trace_exact(RenderArgs a, GradAr
   __shared__ int stk[kStack * kBlock];
   const uint32_t cnt = *a.retry_count;
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
-    const int64_t ray = a.retry[i];
+    const RetryEnt re = a.retry[i];
+    const int64_t ray = re.id;
     const AdjSeed sd = a.seeds[ray];
     float of[3], df[3];
     load_ray(a.rays, ray, of, df);
     const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
     KBufD<K> kb;
-    trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
+    trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0, retry_bound(re));
     adjoint_hits<K>(a, G, sd, kb, o, d);
   }
 }

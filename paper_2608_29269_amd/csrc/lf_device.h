@@ -364,7 +364,7 @@ __device__ __forceinline__ bool prefilter(const FiltRec &F, const RayF &r, float
 // Test one surfel and insert it if valid and among the k closest.
 template <int K>
 __device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3 d, const RayF &rf, double t_min,
-                                           float t_min_f, KBufF<K> &kb) {
+                                           float t_min_f, KBufF<K> &kb, double) {
   const float tk = kb.t[K - 1];
   const float tk_up = tk < INFINITY ? next_up_f(tk) : INFINITY;
   if (!prefilter(S.filt[pos], rf, t_min_f, tk_up)) return 0;
@@ -377,15 +377,18 @@ __device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3
   kinsert<K>(kb, tf, (uint32_t)pos | (flip ? kFlipBit : 0u));
   return 1;
 }
+// t_bound >= the exact k-th distance of the ray (known from a first trace)
 template <int K>
 __device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3 d, const RayF &rf, double t_min,
-                                           float t_min_f, KBufD<K> &kb) {
+                                           float t_min_f, KBufD<K> &kb, double t_bound) {
   const double tk = kb.t[K - 1];
-  const float tk_up = tk < INFINITY ? round_up_f(tk) : INFINITY;
+  const double tb = fmin(tk, t_bound);
+  const float tk_up = tb < INFINITY ? round_up_f(tb) : INFINITY;
   if (!prefilter(S.filt[pos], rf, t_min_f, tk_up)) return 0;
   double t;
   bool flip;
   if (!exact_hit(S.rec[pos], o, d, t_min, t, flip)) return 0;
+  if (t > t_bound) return 0;  // beyond the k-th distance: not among the k closest
   const uint32_t id = (uint32_t)pos | (flip ? kFlipBit : 0u);
   if (!(t < tk || (t == tk && kless_exact(S.rec, t, id, tk, kb.id[K - 1])))) return 0;
   kinsert<K>(kb, S.rec, t, id);
@@ -417,10 +420,11 @@ __device__ __forceinline__ double kth(const KBufD<K> &b) { return b.t[K - 1]; }
 
 // Collects the k closest valid hits of the world ray (o, d) over all
 // instances into kb.  stk points at this lane's first LDS stack slot (stride
-// kBlock).
+// kBlock).  t_bound, if finite, is an upper bound of the exact k-th distance
+// (from an earlier trace of the same ray): everything beyond it is pruned.
 template <int K, class B>
 __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &kb, int *stk, uint32_t *status,
-                      int counter_base = 0) {
+                      int counter_base = 0, double t_bound = INFINITY) {
   kinit<K>(kb, P.k);
   const bool brute = (P.flags & LF_FLAG_BRUTE_FORCE) != 0;
   const float t_min_f = round_down_f(P.t_min);
@@ -431,7 +435,7 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
     double itn, itf;
     if (!slab64(o, d, I.lo, I.hi, itn, itf)) continue;
     if (itf < P.t_min) continue;
-    if (itn > kth<K>(kb) * (1.0 + 1e-6)) continue;
+    if (itn > fmin(kth<K>(kb), t_bound) * (1.0 + 1e-6)) continue;
     d3 oo, dd;
     to_object(I, o, d, oo, dd);
     RayF rf;
@@ -439,7 +443,7 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
     if (brute) {
       const int end = I.first + I.n <= S.n_rec ? I.first + I.n : S.n_rec;
       for (int pos = I.first < 0 ? 0 : I.first; pos < end; ++pos) {
-        c_ins += test_surfel<K>(S, pos, oo, dd, rf, P.t_min, t_min_f, kb);
+        c_ins += test_surfel<K>(S, pos, oo, dd, rf, P.t_min, t_min_f, kb, t_bound);
         ++c_tests;
       }
       continue;
@@ -458,7 +462,7 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
         const float4 lx = *(const float4 *)nd.lox, ly = *(const float4 *)nd.loy, lz = *(const float4 *)nd.loz;
         const float4 hx = *(const float4 *)nd.hix, hy = *(const float4 *)nd.hiy, hz = *(const float4 *)nd.hiz;
         const int4 ch = *(const int4 *)nd.child;
-        const double tk = kth<K>(kb);
+        const double tk = fmin(kth<K>(kb), t_bound);
         const float thi = tk < INFINITY ? round_up_f(tk) * (1.0f + 1e-6f) : INFINITY;
         float t0, t1, t2, t3;
         child_test4(rf, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tlo, thi, t0);
@@ -487,7 +491,7 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
           continue;
         }
       } else {
-        c_ins += test_surfel<K>(S, ~cur, oo, dd, rf, P.t_min, t_min_f, kb);
+        c_ins += test_surfel<K>(S, ~cur, oo, dd, rf, P.t_min, t_min_f, kb, t_bound);
         ++c_tests;
       }
       if (sp == 0) break;
@@ -850,6 +854,38 @@ __device__ __forceinline__ void secondary_coefs(const EnvView &E, const TracePar
       sc.has_b = true;
     }
   }
+}
+
+// Wave-aggregated append: one atomic per wave, slots in lane order.
+template <class T>
+__device__ __forceinline__ void wave_append(bool live, const T &e, T *queue, uint32_t *count) {
+  uint64_t mask = __ballot(live);
+  if (mask == 0) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader);
+  if (live) {
+    uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
+    queue[base + (uint32_t)__popcll(mask & lt)] = e;
+  }
+}
+
+// Queues a ray whose binary32 keys collided for the exact re-trace.
+template <int K>
+__device__ __forceinline__ void queue_retry(bool again, int32_t id, const KBufF<K> &kb, RetryEnt *retry,
+                                            uint32_t *count, unsigned long long *counter) {
+  RetryEnt e;
+  e.id = id;
+  e.tk = kb.t[K - 1];
+  wave_append<RetryEnt>(again, e, retry, count);
+  if (counter && again) atomicAdd(counter, 1ull);
+}
+
+// Upper bound of the exact k-th distance of a queued retry.
+__device__ __forceinline__ double retry_bound(const RetryEnt &e) {
+  return e.tk < INFINITY ? (double)next_up_f(e.tk) : INFINITY;
 }
 
 }  // namespace lf

@@ -68,7 +68,7 @@ struct RenderArgs {
   SecEntry *queue;      // [R*S]
   uint32_t *queue_count;
   const int32_t *order; // [R*S] trace order of the queue (sorted for coherence), or NULL
-  int32_t *retry;       // [max(R, R*S)] rays / queue entries re-traced with exact keys
+  RetryEnt *retry;      // [max(R, R*S)] rays / queue entries re-traced with exact keys
   uint32_t *retry_count;
   float *contrib;       // [R*S*3]
   SecFrozen *frozen;    // [R*S] (backward replay)

@@ -209,22 +209,6 @@ __global__ __launch_bounds__(256) void k_env_marginal(int H, uint32_t flags, con
   }
 }
 
-// Wave-aggregated append: one atomic per wave, slots in lane order.
-template <class T>
-__device__ __forceinline__ void wave_append(bool live, const T &e, T *queue, uint32_t *count) {
-  uint64_t mask = __ballot(live);
-  if (mask == 0) return;
-  const int lane = __lane_id();
-  const int leader = __ffsll((unsigned long long)mask) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
-  base = __shfl(base, leader);
-  if (live) {
-    uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
-    queue[base + (uint32_t)__popcll(mask & lt)] = e;
-  }
-}
-
 // ---------------------------------------------------------------- request views
 // Where the per-request quantities of a ray live: the launch arguments for a
 // single request, the slot of the ray's chunk in a batch.
@@ -308,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_trace1(RenderArgs a, bool replay) {
   kb.collide = false;
   if (active) trace<K>(S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
   const bool again = active && kb.collide;
-  wave_append<int32_t>(again, (int32_t)ray, a.retry, a.retry_count);
+  queue_retry<K>(again, (int32_t)ray, kb, a.retry, a.retry_count, a.P.counters ? a.P.counters + 8 : nullptr);
   if (active && !again) finish_primary<K>(a, S, v, replay, ray, kb, o, d);
 }
 
@@ -318,7 +302,8 @@ __global__ __launch_bounds__(kBlock) void k_trace1_exact(RenderArgs a, bool repl
   __shared__ int stk[kStack * kBlock];
   const uint32_t cnt = *a.retry_count;
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
-    const int64_t ray = a.retry[i];
+    const RetryEnt re = a.retry[i];
+    const int64_t ray = re.id;
     const ReqView v = req_view<B>(a, ray);
     SceneView S = a.S;
     S.inst = v.inst;
@@ -326,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_trace1_exact(RenderArgs a, bool repl
     req_ray<B>(a, ray, v, of, df);
     const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
     KBufD<K> kb;
-    trace<K>(S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
+    trace<K>(S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0, retry_bound(re));
     finish_primary<K>(a, S, v, replay, ray, kb, o, d);
   }
 }
@@ -435,7 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_trace2(RenderArgs a) {
   kb.collide = false;
   if (active) trace<K>(S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4);
   const bool again = active && kb.collide;
-  wave_append<int32_t>(again, (int32_t)qi, a.retry, a.retry_count);
+  queue_retry<K>(again, (int32_t)qi, kb, a.retry, a.retry_count, a.P.counters ? a.P.counters + 9 : nullptr);
   if (active && !again) finish_secondary<K>(a, S, qi, e, kb, o, w);
 }
 
@@ -444,13 +429,14 @@ __global__ __launch_bounds__(kBlock) void k_trace2_exact(RenderArgs a) {
   __shared__ int stk[kStack * kBlock];
   const uint32_t cnt = *a.retry_count;
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
-    const uint32_t qi = (uint32_t)a.retry[i];
+    const RetryEnt re = a.retry[i];
+    const uint32_t qi = (uint32_t)re.id;
     const SecEntry e = a.queue[qi];
     const d3 o = mk(e.o[0], e.o[1], e.o[2]), w = mk(e.w[0], e.w[1], e.w[2]);
     SceneView S = a.S;
     if constexpr (B) S.inst = a.slots[a.chunks[e.ray / kChunk].slot].inst;
     KBufD<K> kb;
-    trace<K>(S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4);
+    trace<K>(S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4, retry_bound(re));
     finish_secondary<K>(a, S, qi, e, kb, o, w);
   }
 }

@@ -10,9 +10,15 @@
 //  - Admission is FIFO: the oldest waiting request is admitted when a slot is
 //    free and the budget still holds its cost; nothing overtakes it.
 //  - Every iteration (one batched wavefront pass) draws tiles of consecutive
-//    rays from the admitted requests, round robin, until the batch is full.
-//    A request gets max(tile_rays, batch_rays / active) rays per iteration,
-//    rounded to whole 128-ray chunks; only its last tile may be ragged.
+//    rays from the admitted requests until the batch is full; only a
+//    request's last tile may be ragged, every other tile is whole 128-ray
+//    chunks.  Which requests go first is the policy:
+//      kShortestFirst  smallest remaining work (rays x (1 + S)) first, each
+//                      taking all it can (short requests finish in one pass);
+//      kOldestFirst    admission order, each taking all it can (FIFO with
+//                      backfill of the room the oldest leaves);
+//      kRoundRobin     max(tile_rays, batch_rays / active) rays each,
+//                      starting after the request served last.
 //  - An iteration's tiles complete together; a request completes when all of
 //    its rays have completed, which frees its slot and its budget.
 #pragma once
@@ -25,7 +31,10 @@
 
 namespace lf {
 
+enum SchedPolicy { kShortestFirst = 0, kOldestFirst = 1, kRoundRobin = 2 };
+
 struct SchedConfig {
+  int policy = kShortestFirst;
   int max_slots = 16;
   int64_t budget = int64_t(16) << 30;
   int64_t tile_rays = 65536;   // multiple of chunk
@@ -48,10 +57,11 @@ class Scheduler {
 
   const SchedConfig &config() const { return cfg_; }
 
-  Submit submit(uint64_t ticket, int64_t rays, int64_t cost) {
+  // work_per_ray weighs a ray's cost for kShortestFirst (e.g. 1 + S)
+  Submit submit(uint64_t ticket, int64_t rays, int64_t cost, int64_t work_per_ray = 1) {
     if (cost > cfg_.budget) return kTooBig;
     if ((int)pending_.size() >= cfg_.max_pending) return kBusy;
-    pending_.push_back({ticket, rays, cost});
+    pending_.push_back({ticket, rays, cost, work_per_ray});
     return kOk;
   }
 
@@ -70,6 +80,7 @@ class Scheduler {
       sl.cost = w.cost;
       sl.next = 0;
       sl.done = 0;
+      sl.wpr = w.wpr;
       sl.seq = seq_++;
       used_ += w.cost;
       out.push_back({s, w.ticket});
@@ -86,14 +97,25 @@ class Scheduler {
       if (slots_[s].busy && slots_[s].next < slots_[s].rays) act.push_back(s);
     std::vector<SchedTile> tiles;
     if (act.empty()) return tiles;
-    std::sort(act.begin(), act.end(), [&](int a, int b) { return slots_[a].seq < slots_[b].seq; });
     const int64_t ch = cfg_.chunk;
-    int64_t quota = std::max(cfg_.tile_rays, round_up(cfg_.batch_rays / (int64_t)act.size(), ch));
-    int64_t room = cfg_.batch_rays;
-    // round robin: start after the request served last in the previous iteration
+    int64_t quota = cfg_.batch_rays;
     size_t start = 0;
-    while (start < act.size() && slots_[act[start]].seq <= last_seq_) ++start;
-    if (start == act.size()) start = 0;
+    if (cfg_.policy == kShortestFirst) {
+      std::sort(act.begin(), act.end(), [&](int a, int b) {
+        const Slot &x = slots_[a], &y = slots_[b];
+        const int64_t wx = (x.rays - x.next) * x.wpr, wy = (y.rays - y.next) * y.wpr;
+        return wx != wy ? wx < wy : x.seq < y.seq;
+      });
+    } else {
+      std::sort(act.begin(), act.end(), [&](int a, int b) { return slots_[a].seq < slots_[b].seq; });
+    }
+    if (cfg_.policy == kRoundRobin) {
+      quota = std::max(cfg_.tile_rays, round_up(cfg_.batch_rays / (int64_t)act.size(), ch));
+      // start after the request served last in the previous iteration
+      while (start < act.size() && slots_[act[start]].seq <= last_seq_) ++start;
+      if (start == act.size()) start = 0;
+    }
+    int64_t room = cfg_.batch_rays;
     for (size_t i = 0; i < act.size(); ++i) {
       Slot &sl = slots_[act[(start + i) % act.size()]];
       const int64_t cap = std::min(quota, room);
@@ -149,12 +171,12 @@ class Scheduler {
  private:
   struct Waiting {
     uint64_t ticket;
-    int64_t rays, cost;
+    int64_t rays, cost, wpr;
   };
   struct Slot {
     bool busy = false;
     uint64_t ticket = 0;
-    int64_t rays = 0, cost = 0, next = 0, done = 0;
+    int64_t rays = 0, cost = 0, next = 0, done = 0, wpr = 1;
     uint64_t seq = 0;
   };
   static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }

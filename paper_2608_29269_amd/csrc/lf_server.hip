@@ -4,7 +4,7 @@
 // camera and environment into its slot (instance records and importance
 // sampling tables are built on the device), and launches batched wavefront
 // passes over 128-ray chunks of all admitted requests on the server's own
-// stream, keeping up to two passes in flight.
+// stream (one or two passes queued on the device).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -215,7 +215,7 @@ bool launch_pass(lf_server *s, const std::vector<lf::SchedTile> &tiles, int buf,
   a.rec2 = s->rec2.as<lf::SurfRec>();
   a.queue = s->queue.as<lf::SecEntry>();
   a.queue_count = s->qcount.as<uint32_t>();
-  a.retry = s->retry.as<int32_t>();
+  a.retry = s->retry.as<lf::RetryEnt>();
   a.retry_count = s->rcount.as<uint32_t>();
   a.contrib = s->contrib.as<float>();
   a.status = s->status.as<uint32_t>();
@@ -320,7 +320,7 @@ void serve(lf_server *s) {
         s->cv_work.wait(lk, [&] { return s->stop || s->sched.pending() > 0 || s->sched.has_unscheduled(); });
         if (s->stop) break;
       }
-      if (!s->stop && fl.size() < 2) {
+      if (!s->stop && (int)fl.size() < s->cfg.max_in_flight) {
         admitted = s->sched.admit();
         for (auto &ad : admitted) {
           s->slot_ticket[ad.first] = ad.second;
@@ -346,8 +346,8 @@ void serve(lf_server *s) {
       }
       fl.push_back(f);
     }
-    // keep at most two passes in flight; with nothing new to launch, retire
-    while (ok && !fl.empty() && (fl.size() >= 2 || tiles.empty())) {
+    // keep at most max_in_flight passes queued; with nothing new to launch, retire
+    while (ok && !fl.empty() && ((int)fl.size() >= s->cfg.max_in_flight || tiles.empty())) {
       ok = retire_one(s, fl, events);
       if (tiles.empty()) break;
     }
@@ -377,6 +377,8 @@ void lf_server_config_default(lf_server_config *cfg) {
   cfg->batch_rays = 262144;
   cfg->max_spp = 4;
   cfg->max_pending = 4096;
+  cfg->policy = LF_SCHED_SHORTEST_FIRST;
+  cfg->max_in_flight = 1;
   lf_params_default(&cfg->params);
 }
 
@@ -391,6 +393,9 @@ lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **o
     return lfh::fail(c, LF_EINVAL, "tile_rays and batch_rays must be multiples of %d with batch >= tile", lf::kChunk);
   if (cfg->max_spp < 1 || cfg->max_spp > 64) return lfh::fail(c, LF_EINVAL, "max_spp not in 1..64");
   if (cfg->max_pending < 1 || cfg->hbm_budget_bytes < 1) return lfh::fail(c, LF_EINVAL, "invalid queue or budget");
+  if (cfg->policy < LF_SCHED_SHORTEST_FIRST || cfg->policy > LF_SCHED_ROUND_ROBIN)
+    return lfh::fail(c, LF_EINVAL, "unknown scheduling policy %d", cfg->policy);
+  if (cfg->max_in_flight < 1 || cfg->max_in_flight > 2) return lfh::fail(c, LF_EINVAL, "max_in_flight not in 1..2");
   lf_params p = cfg->params;
   p.spp = cfg->max_spp;
   lf_status st = lfh::validate_params(c, &p);
@@ -411,6 +416,7 @@ lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **o
   s->ctx = c;
   s->cfg = *cfg;
   lf::SchedConfig sc;
+  sc.policy = cfg->policy;
   sc.max_slots = cfg->max_slots;
   sc.budget = cfg->hbm_budget_bytes;
   sc.tile_rays = cfg->tile_rays;
@@ -443,7 +449,7 @@ lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **o
          lfh::ensure_env_tables(sd.cdf_row, sd.cdf_col, sd.lum, sd.rowsum, sd.roww, sd.scal, 256, 512);
   }
   ok = ok && s->rec1.ensure(sizeof(lf::SurfRec) * B) && s->rec2.ensure(sizeof(lf::SurfRec) * BS) &&
-       s->queue.ensure(sizeof(lf::SecEntry) * BS) && s->qcount.ensure(4) && s->retry.ensure(4 * BS) &&
+       s->queue.ensure(sizeof(lf::SecEntry) * BS) && s->qcount.ensure(4) && s->retry.ensure(sizeof(lf::RetryEnt) * BS) &&
        s->rcount.ensure(4) && s->contrib.ensure(sizeof(float) * 3 * BS) && s->skeys.ensure(8 * BS) &&
        s->skeys2.ensure(8 * BS) && s->svals.ensure(4 * BS) && s->svals2.ensure(4 * BS) &&
        s->shist.ensure(4 * lf::radix_sort_hist_words(BS)) && s->status.ensure(4);
@@ -490,7 +496,7 @@ lf_status lf_server_submit(lf_server *s, const lf_request *r, uint64_t *ticket) 
   if (s->failed) return s->fail_status;
   if (s->stop) return LF_EBUSY;
   const uint64_t t = s->next_ticket;
-  const lf::Scheduler::Submit res = s->sched.submit(t, (int64_t)cm.w * cm.h, cost);
+  const lf::Scheduler::Submit res = s->sched.submit(t, (int64_t)cm.w * cm.h, cost, 1 + (int64_t)r->spp);
   if (res != lf::Scheduler::kOk) {
     s->rejected += 1;
     if (res == lf::Scheduler::kBusy) {

@@ -8,8 +8,10 @@
 
 extern "C" {
 
-void *sched_create(int max_slots, int64_t budget, int64_t tile_rays, int64_t batch_rays, int max_pending) {
+void *sched_create(int policy, int max_slots, int64_t budget, int64_t tile_rays, int64_t batch_rays,
+                   int max_pending) {
   lf::SchedConfig c;
+  c.policy = policy;
   c.max_slots = max_slots;
   c.budget = budget;
   c.tile_rays = tile_rays;
@@ -21,8 +23,8 @@ void *sched_create(int max_slots, int64_t budget, int64_t tile_rays, int64_t bat
 
 void sched_destroy(void *s) { delete (lf::Scheduler *)s; }
 
-int sched_submit(void *s, uint64_t ticket, int64_t rays, int64_t cost) {
-  return (int)((lf::Scheduler *)s)->submit(ticket, rays, cost);
+int sched_submit(void *s, uint64_t ticket, int64_t rays, int64_t cost, int64_t work_per_ray) {
+  return (int)((lf::Scheduler *)s)->submit(ticket, rays, cost, work_per_ray);
 }
 
 // admitted (slot, ticket) pairs into out[2*i], out[2*i+1]; returns the count

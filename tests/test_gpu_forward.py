@@ -232,3 +232,44 @@ def test_secondary_regrouping_is_transparent(tracer, c2_small):
                       sec_hit_idx=True, flags=lf._lib.FLAG_UNSORTED)
     for key in a:
         assert np.array_equal(a[key].cpu().numpy(), b[key].cpu().numpy()), key
+
+
+def test_key_collisions_are_resolved_exactly(tracer):
+    """Exact duplicates (equal t: the lower index first) and near duplicates one
+    binary32 step apart along z (equal binary32 keys, different double t) force
+    the exact re-trace; every hit list equals the oracle's."""
+    import paper_2608_29269_amd as lf
+    from tests.helpers import make_scene
+    rng = np.random.default_rng(7)
+    n = 2000
+    mu = np.column_stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(-0.5, 0.5, n)])
+    mu = mu.astype(np.float32).astype(np.float64)
+    tilt = rng.normal(0, 0.1, (n, 2))
+    q = np.column_stack([np.ones(n), tilt, np.zeros(n)])
+    scale = np.exp(rng.uniform(np.log(0.1), np.log(0.3), (n, 2)))
+    opac = np.full(n, 0.3)
+    dup = rng.choice(n, 400, replace=False)
+    near = rng.choice(n, 400, replace=False)
+    mu_near = mu[near].copy()
+    mu_near[:, 2] = np.nextafter(mu_near[:, 2].astype(np.float32), np.float32(np.inf)).astype(np.float64)
+    sc = make_scene(np.vstack([mu, mu[dup], mu_near]), q=np.vstack([q, q[dup], q[near]]),
+                    scale=np.vstack([scale, scale[dup], scale[near]]),
+                    opacity=np.concatenate([opac, opac[dup], opac[near]]),
+                    albedo=rng.uniform(0, 1, (n + 800, 3)), roughness=rng.uniform(0, 1, n + 800),
+                    metallic=rng.uniform(0, 1, n + 800))
+    upload_scene(tracer, sc)
+    m = 3000
+    o = np.column_stack([rng.uniform(-0.9, 0.9, m), rng.uniform(-0.9, 0.9, m), np.full(m, 3.0)]).astype(np.float32)
+    dirs = np.column_stack([rng.normal(0, 0.05, m), rng.normal(0, 0.05, m), -np.ones(m)])
+    d = (dirs / np.linalg.norm(dirs, axis=1, keepdims=True)).astype(np.float32)
+    env = scenegen.constant_env(1.0, 8, 16)
+    tracer.trace_counters()
+    out = tracer.render(env=dev(env), rays=(dev(o), dev(d)), k=16, spp=1, seed=1, flags=lf._lib.FLAG_COUNT | 1,
+                        hit_idx=True)
+    cnt = tracer.trace_counters()
+    st = scenegen.State(R=np.zeros((0, 3, 3), np.float32), t=np.zeros((0, 3), np.float32), env=env, cameras=[])
+    ref = run_oracle(sc, st, o, d, np.arange(m), 16, 1, 1, 1)
+    assert cnt["primary"]["retries"] > 20, cnt
+    np.testing.assert_array_equal(out["hit_idx"].cpu().numpy(), ref["hit_idx"])
+    for key in ("depth", "normal", "alpha"):
+        assert rel_close(out[key].cpu().numpy(), ref[key], RTOL) < RTOL, key

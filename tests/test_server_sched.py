@@ -10,6 +10,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CHUNK = 128
+SHORTEST, OLDEST, ROUND_ROBIN = 0, 1, 2
 
 
 @pytest.fixture(scope="module")
@@ -21,9 +22,9 @@ def S(tmp_path_factory):
                            os.path.join(ROOT, "tests", "sched_capi.cpp"), "-o", so])
     L = C.CDLL(so)
     L.sched_create.restype = C.c_void_p
-    L.sched_create.argtypes = [C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_int]
+    L.sched_create.argtypes = [C.c_int, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_int]
     L.sched_destroy.argtypes = [C.c_void_p]
-    L.sched_submit.argtypes = [C.c_void_p, C.c_uint64, C.c_int64, C.c_int64]
+    L.sched_submit.argtypes = [C.c_void_p, C.c_uint64, C.c_int64, C.c_int64, C.c_int64]
     for f in ("sched_admit", "sched_plan"):
         getattr(L, f).argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int]
     L.sched_retire.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int64), C.c_int]
@@ -33,15 +34,15 @@ def S(tmp_path_factory):
 
 
 class Sched:
-    def __init__(self, L, max_slots=4, budget=1 << 40, tile=256, batch=1024, max_pending=100):
+    def __init__(self, L, max_slots=4, budget=1 << 40, tile=256, batch=1024, max_pending=100, policy=ROUND_ROBIN):
         self.L = L
-        self.h = L.sched_create(max_slots, budget, tile, batch, max_pending)
+        self.h = L.sched_create(policy, max_slots, budget, tile, batch, max_pending)
 
     def __del__(self):
         self.L.sched_destroy(self.h)
 
-    def submit(self, t, rays, cost=0):
-        return self.L.sched_submit(self.h, t, rays, cost)
+    def submit(self, t, rays, cost=0, wpr=1):
+        return self.L.sched_submit(self.h, t, rays, cost, wpr)
 
     def admit(self):
         buf = (C.c_int64 * 256)()
@@ -117,12 +118,12 @@ def test_ragged_last_tile_and_small_requests(S):
     assert sorted(t for _, t in done) == [1, 2] and s.active == 0
 
 
-def _simulate(S, rng, n_req, max_slots, tile, batch, budget, steps=20000):
-    s = Sched(S, max_slots=max_slots, tile=tile, batch=batch, budget=budget, max_pending=10 ** 6)
+def _simulate(S, rng, n_req, max_slots, tile, batch, budget, policy, steps=20000):
+    s = Sched(S, max_slots=max_slots, tile=tile, batch=batch, budget=budget, max_pending=10 ** 6, policy=policy)
     rays = {t: int(rng.integers(1, 6000)) for t in range(1, n_req + 1)}
     cost = {t: int(rng.integers(1, budget // 3)) for t in rays}
     for t in rays:
-        assert s.submit(t, rays[t], cost[t]) == 0
+        assert s.submit(t, rays[t], cost[t], int(rng.integers(1, 6))) == 0
     covered = {t: np.zeros(rays[t], np.int32) for t in rays}
     slot_of = {}
     admitted, completed = [], []
@@ -163,15 +164,44 @@ def _simulate(S, rng, n_req, max_slots, tile, batch, budget, steps=20000):
     assert s.used == 0 and s.active == 0 and s.pending == 0
 
 
-@pytest.mark.parametrize("seed", range(6))
-def test_random_streams_keep_the_invariants(S, seed):
+@pytest.mark.parametrize("policy", [SHORTEST, OLDEST, ROUND_ROBIN])
+@pytest.mark.parametrize("seed", range(4))
+def test_random_streams_keep_the_invariants(S, seed, policy):
     rng = np.random.default_rng(seed)
     _simulate(S, rng, n_req=60, max_slots=int(rng.integers(1, 9)), tile=128 * int(rng.integers(1, 4)),
-              batch=128 * int(rng.integers(4, 20)), budget=1000)
+              batch=128 * int(rng.integers(4, 20)), budget=1000, policy=policy)
+
+
+def test_shortest_first_takes_the_smallest_remaining_work(S):
+    s = Sched(S, max_slots=8, tile=128, batch=4096, policy=SHORTEST)
+    s.submit(1, 10000, wpr=2)   # work 20000
+    s.submit(2, 3000, wpr=5)    # work 15000
+    s.submit(3, 1000, wpr=2)    # work 2000
+    s.admit()
+    tiles = s.plan()
+    # smallest work first, each taking all it can: 1000 (padded to 1024) and 3000 fill the 4096
+    assert tiles == [(2, 0, 1000), (1, 0, 3000)]
+    done = s.retire(tiles)
+    assert sorted(t for _, t in done) == [2, 3]
+    assert s.plan() == [(0, 0, 4096)]
+    s.submit(4, 200, wpr=1)  # a late small request overtakes the large one's remainder
+    s.admit()
+    tiles = s.plan()
+    assert tiles[0][2] == 200 and tiles[1] == (0, 4096, 3840)
+
+
+def test_oldest_first_backfills_behind_the_oldest(S):
+    s = Sched(S, max_slots=8, tile=128, batch=4096, policy=OLDEST)
+    s.submit(1, 3000)
+    s.submit(2, 100000)
+    s.submit(3, 5)
+    s.admit()
+    assert s.plan() == [(0, 0, 3000), (1, 0, 1024)]  # the oldest first, the next fills the room
+    assert s.plan() == [(1, 1024, 4096)]
 
 
 def test_round_robin_serves_everyone(S):
-    s = Sched(S, max_slots=10, tile=256, batch=1024)
+    s = Sched(S, max_slots=10, tile=256, batch=1024, policy=ROUND_ROBIN)
     for t in range(1, 11):
         s.submit(t, 10 ** 6)
     s.admit()
