@@ -262,7 +262,7 @@ lf_status lf_profile_read(lf_ctx *ctx, double *ms /*[LF_NUM_PHASES]*/, int64_t *
  * Buffers the server allocates up front (batch scratch sized by batch_rays
  * and max_spp, one environment slot per request slot) are not charged.
  *
- * The server has its own HIP stream and host thread.  It reads the context's
+ * The server has its own HIP streams and host thread.  It reads the context's
  * scene: lf_scene_set and lf_scene_refit return LF_EBUSY while a server of
  * the context exists, and every server must be destroyed before its context.
  * The server functions are thread-safe.
@@ -283,8 +283,9 @@ typedef struct {
   int32_t max_spp;          /* largest S a request may ask for, 1..64 (default 4) */
   int32_t max_pending;      /* waiting requests before lf_server_submit returns LF_EBUSY (default 4096) */
   int32_t policy;           /* LF_SCHED_* (default LF_SCHED_SHORTEST_FIRST) */
-  int32_t max_in_flight;    /* passes queued on the device at once, 1..2 (default 1: a new arrival
-                               joins the next pass) */
+  int32_t max_in_flight;    /* passes running at once, 1..4, each on its own stream with its own
+                               scratch (default 2): the latency-bound tail of one pass overlaps
+                               the next, and a new arrival starts on a free lane */
   lf_params params;         /* k, constants and flags shared by every request (spp and seed are
                                per request; LF_FLAG_COUNT and LF_FLAG_NO_SECONDARY are not served) */
 } lf_server_config;

@@ -2,9 +2,10 @@
 // the resident scene (Sec. 4 rearrangement and relighting).  A host thread
 // admits requests (lf_sched.h), stages each admitted request's transforms,
 // camera and environment into its slot (instance records and importance
-// sampling tables are built on the device), and launches batched wavefront
-// passes over 128-ray chunks of all admitted requests on the server's own
-// stream (one or two passes queued on the device).
+// sampling tables are built on the device) and launches batched wavefront
+// passes over 128-ray chunks of the admitted requests.  Up to max_in_flight
+// passes run at once, each on a lane of its own (stream and scratch), so the
+// latency-bound tail of one pass overlaps the bulk of the next.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -12,7 +13,6 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <deque>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -47,6 +47,7 @@ struct SlotDev {
   DevBuf cam;     // CamArgs
   DevBuf tex, cdf_row, cdf_col, lum, rowsum, roww, scal;
   DevBuf status;  // status word of the request's instance records (invalid transforms)
+  hipEvent_t staged = nullptr;  // recorded after the slot's staging on the staging lane's stream
 };
 
 // What the host reads back after each pass.
@@ -55,11 +56,16 @@ struct IterReadback {
   uint32_t secondaries;
 };
 
-struct InFlight {
+// One pass at a time on its own stream with its own scratch.
+struct Lane {
+  hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
+  bool busy = false;
   std::vector<lf::SchedTile> tiles;
-  int buf = 0;
   int64_t primaries = 0;
+  lf::ChunkDesc *h_chunks = nullptr;  // pinned
+  IterReadback *h_rb = nullptr;       // pinned
+  DevBuf d_chunks, rec1, rec2, queue, qcount, retry, rcount, contrib, skeys, skeys2, svals, svals2, shist, status;
 };
 
 }  // namespace
@@ -67,11 +73,11 @@ struct InFlight {
 struct lf_server {
   lf_ctx *ctx = nullptr;
   lf_server_config cfg{};
-  hipStream_t stream = nullptr;
   std::thread worker;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   bool stop = false;
+  bool kicked = false;  // a request was submitted since the last plan
   bool failed = false;
   lf_status fail_status = LF_OK;
   std::string err;
@@ -80,14 +86,10 @@ struct lf_server {
   uint64_t next_ticket = 1;
   std::vector<uint64_t> slot_ticket;
   std::vector<SlotDev> slots;
-  // pinned staging
-  lf::BatchSlot *h_slots = nullptr;   // [max_slots]
-  lf::CamArgs *h_cams = nullptr;      // [max_slots]
-  lf::ChunkDesc *h_chunks[2] = {nullptr, nullptr};
-  IterReadback *h_rb = nullptr;       // [2]
-  DevBuf d_slots, d_chunks[2];
-  // batch scratch
-  DevBuf rec1, rec2, queue, qcount, retry, rcount, contrib, skeys, skeys2, svals, svals2, shist, status;
+  std::vector<Lane> lanes;
+  lf::BatchSlot *h_slots = nullptr;   // [max_slots] pinned staging of the slot table
+  lf::CamArgs *h_cams = nullptr;      // [max_slots] pinned staging of the cameras
+  DevBuf d_slots;                     // BatchSlot[max_slots]
   int64_t max_chunks = 0;
   // statistics
   std::vector<double> lat;
@@ -128,14 +130,14 @@ void finish_ticket(lf_server *s, uint64_t t, lf_status st, double when) {
   }
 }
 
-// Stages an admitted request into its slot: transforms, camera, environment
-// copy, instance records and sampling tables (all on the server stream).
-bool stage_slot(lf_server *s, int slot, const lf_request &r) {
+// Stages an admitted request into its slot on stream st: transforms, camera,
+// environment copy, instance records, sampling tables and the slot table
+// entry; records the slot's staged event.
+bool stage_slot(lf_server *s, int slot, const lf_request &r, hipStream_t st) {
   lf_ctx *c = s->ctx;
   SlotDev &sd = s->slots[slot];
   const int M = c->n_inst - 1;
   const int H = r.env.h, W = r.env.w;
-  hipStream_t st = s->stream;
   if (!sd.xf.ensure(sizeof(float) * 12 * (M > 0 ? M : 1)) || !sd.tex.ensure(sizeof(float) * 3 * (size_t)H * W) ||
       !lfh::ensure_env_tables(sd.cdf_row, sd.cdf_col, sd.lum, sd.rowsum, sd.roww, sd.scal, H, W))
     return false;
@@ -180,16 +182,19 @@ bool stage_slot(lf_server *s, int slot, const lf_request &r) {
   b.spp = r.spp;
   if (hipMemcpyAsync(s->d_slots.as<lf::BatchSlot>() + slot, &b, sizeof b, hipMemcpyHostToDevice, st) != hipSuccess)
     return false;
+  if (hipEventRecord(sd.staged, st) != hipSuccess) return false;
   return hipGetLastError() == hipSuccess;
 }
 
-// Launches one batched pass over the tiles (chunk table in buffer buf).
-bool launch_pass(lf_server *s, const std::vector<lf::SchedTile> &tiles, int buf, InFlight &fl) {
+// Launches one batched pass over the tiles on lane L.
+bool launch_pass(lf_server *s, Lane &L, const std::vector<lf::SchedTile> &tiles) {
   lf_ctx *c = s->ctx;
-  hipStream_t st = s->stream;
-  lf::ChunkDesc *hc = s->h_chunks[buf];
+  hipStream_t st = L.stream;
+  lf::ChunkDesc *hc = L.h_chunks;
   int64_t nch = 0, prim = 0;
   for (const lf::SchedTile &t : tiles) {
+    // the slot may have been staged on another lane's stream
+    if (hipStreamWaitEvent(st, s->slots[t.slot].staged, 0) != hipSuccess) return false;
     for (int64_t r = 0; r < t.n; r += lf::kChunk) {
       if (nch >= s->max_chunks) return false;  // the planner never exceeds the batch size
       hc[nch].slot = t.slot;
@@ -199,7 +204,7 @@ bool launch_pass(lf_server *s, const std::vector<lf::SchedTile> &tiles, int buf,
     }
     prim += t.n;
   }
-  if (hipMemcpyAsync(s->d_chunks[buf].p, hc, sizeof(lf::ChunkDesc) * nch, hipMemcpyHostToDevice, st) != hipSuccess)
+  if (hipMemcpyAsync(L.d_chunks.p, hc, sizeof(lf::ChunkDesc) * nch, hipMemcpyHostToDevice, st) != hipSuccess)
     return false;
   lf::RenderArgs a;
   memset(&a, 0, sizeof a);
@@ -209,40 +214,39 @@ bool launch_pass(lf_server *s, const std::vector<lf::SchedTile> &tiles, int buf,
   a.P.counters = nullptr;
   a.spp_stride = s->cfg.max_spp;
   a.R = nch * lf::kChunk;
-  a.chunks = s->d_chunks[buf].as<lf::ChunkDesc>();
+  a.chunks = L.d_chunks.as<lf::ChunkDesc>();
   a.slots = s->d_slots.as<lf::BatchSlot>();
-  a.rec1 = s->rec1.as<lf::SurfRec>();
-  a.rec2 = s->rec2.as<lf::SurfRec>();
-  a.queue = s->queue.as<lf::SecEntry>();
-  a.queue_count = s->qcount.as<uint32_t>();
-  a.retry = s->retry.as<lf::RetryEnt>();
-  a.retry_count = s->rcount.as<uint32_t>();
-  a.contrib = s->contrib.as<float>();
-  a.status = s->status.as<uint32_t>();
+  a.rec1 = L.rec1.as<lf::SurfRec>();
+  a.rec2 = L.rec2.as<lf::SurfRec>();
+  a.queue = L.queue.as<lf::SecEntry>();
+  a.queue_count = L.qcount.as<uint32_t>();
+  a.retry = L.retry.as<lf::RetryEnt>();
+  a.retry_count = L.rcount.as<uint32_t>();
+  a.contrib = L.contrib.as<float>();
+  a.status = L.status.as<uint32_t>();
   const bool sorted = !(s->cfg.params.flags & LF_FLAG_UNSORTED);
-  a.order = sorted ? s->svals.as<int32_t>() : nullptr;
+  a.order = sorted ? L.svals.as<int32_t>() : nullptr;
   lf::launch_fill_u32(a.queue_count, 0u, 1, st);
   lf::launch_trace1(a, false, st);
   lf::launch_shade1(a, false, st);
   if (sorted) {
     const int64_t cap = a.R * a.spp_stride;
-    lf::launch_secondary_keys(a.queue, a.queue_count, cap, nullptr, a.chunks, a.slots, s->skeys.as<uint64_t>(),
-                              s->svals.as<int32_t>(), st);
-    lf::radix_sort(s->skeys.as<uint64_t>(), s->svals.as<int32_t>(), s->skeys2.as<uint64_t>(),
-                   s->svals2.as<int32_t>(), s->shist.as<uint32_t>(), cap, st, 32);
+    lf::launch_secondary_keys(a.queue, a.queue_count, cap, nullptr, a.chunks, a.slots, L.skeys.as<uint64_t>(),
+                              L.svals.as<int32_t>(), st);
+    lf::radix_sort(L.skeys.as<uint64_t>(), L.svals.as<int32_t>(), L.skeys2.as<uint64_t>(), L.svals2.as<int32_t>(),
+                   L.shist.as<uint32_t>(), cap, st, 32);
   }
   lf::launch_trace2(a, st);
   lf::launch_shade2(a, false, st);
   lf::launch_resolve(a, st);
-  IterReadback *rb = s->h_rb + buf;
-  if (hipMemcpyAsync(&rb->status, a.status, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(&rb->secondaries, a.queue_count, 4, hipMemcpyDeviceToHost, st) != hipSuccess)
+  if (hipMemcpyAsync(&L.h_rb->status, a.status, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&L.h_rb->secondaries, a.queue_count, 4, hipMemcpyDeviceToHost, st) != hipSuccess)
     return false;
   lf::launch_fill_u32(a.status, 0u, 1, st);
-  if (hipEventRecord(fl.done, st) != hipSuccess) return false;
-  fl.tiles = tiles;
-  fl.buf = buf;
-  fl.primaries = prim;
+  if (hipEventRecord(L.done, st) != hipSuccess) return false;
+  L.tiles = tiles;
+  L.primaries = prim;
+  L.busy = true;
   return hipGetLastError() == hipSuccess;
 }
 
@@ -253,33 +257,44 @@ lf_status status_of(uint32_t st) {
   return LF_OK;
 }
 
-// Waits for the oldest pass and completes its requests.
-bool retire_one(lf_server *s, std::deque<InFlight> &fl, std::vector<hipEvent_t> &events) {
-  InFlight f = fl.front();
-  fl.pop_front();
-  if (hipEventSynchronize(f.done) != hipSuccess) return false;
+// Completes the requests of lane L's finished pass.
+bool retire(lf_server *s, Lane &L) {
   const double t = now_ms();
-  const IterReadback rb = s->h_rb[f.buf];
+  const IterReadback rb = *L.h_rb;
   const lf_status st = status_of(rb.status);
-  events.push_back(f.done);
+  L.busy = false;
   std::lock_guard<std::mutex> lk(s->mu);
-  s->rays_primary += f.primaries;
+  s->rays_primary += L.primaries;
   s->rays_secondary += rb.secondaries;
   if (st != LF_OK) {
     // a device condition ends every request of the pass
-    for (const lf::SchedTile &tl : f.tiles) finish_ticket(s, s->slot_ticket[tl.slot], st, t);
+    for (const lf::SchedTile &tl : L.tiles) finish_ticket(s, s->slot_ticket[tl.slot], st, t);
     s->err = "device status set during a batched pass";
   }
-  for (auto &done : s->sched.retire(f.tiles)) {
-    // the request's own instance status (its pass has completed, so the word is final)
+  for (auto &done : s->sched.retire(L.tiles)) {
+    // the request's own instance status (all of its passes have completed, so the word is final)
     uint32_t ist = 0;
     if (hipMemcpy(&ist, s->slots[done.first].status.p, 4, hipMemcpyDeviceToHost) != hipSuccess) return false;
     const lf_status rs = status_of(ist);
     if (rs != LF_OK) s->err = "degenerate or non-finite object transform";
     finish_ticket(s, done.second, rs, t);
   }
+  L.tiles.clear();
   s->cv_done.notify_all();
   return true;
+}
+
+// Retires every lane whose pass has finished; returns how many (-1 on error).
+int poll_lanes(lf_server *s) {
+  int n = 0;
+  for (Lane &L : s->lanes) {
+    if (!L.busy) continue;
+    const hipError_t q = hipEventQuery(L.done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess || !retire(s, L)) return -1;
+    ++n;
+  }
+  return n;
 }
 
 void fail_all(lf_server *s, lf_status st, const char *why) {
@@ -298,29 +313,25 @@ void serve(lf_server *s) {
     fail_all(s, LF_EDEVICE, "hipSetDevice failed on the server thread");
     return;
   }
-  std::deque<InFlight> fl;
-  std::vector<hipEvent_t> events;
-  for (int i = 0; i < 3; ++i) {
-    hipEvent_t e = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      fail_all(s, LF_EDEVICE, "event creation failed");
-      return;
-    }
-    events.push_back(e);
-  }
-  int next_buf = 0;
   bool ok = true;
   while (ok) {
+    Lane *free_lane = nullptr;
+    int busy = 0;
+    for (Lane &L : s->lanes) {
+      if (L.busy) ++busy;
+      else if (!free_lane) free_lane = &L;
+    }
     std::vector<std::pair<int, uint64_t>> admitted;
-    std::vector<lf::SchedTile> tiles;
     std::vector<lf_request> reqs;
+    std::vector<lf::SchedTile> tiles;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      if (fl.empty()) {
+      if (busy == 0) {
         s->cv_work.wait(lk, [&] { return s->stop || s->sched.pending() > 0 || s->sched.has_unscheduled(); });
         if (s->stop) break;
       }
-      if (!s->stop && (int)fl.size() < s->cfg.max_in_flight) {
+      if (!s->stop && free_lane) {
+        s->kicked = false;
         admitted = s->sched.admit();
         for (auto &ad : admitted) {
           s->slot_ticket[ad.first] = ad.second;
@@ -331,37 +342,58 @@ void serve(lf_server *s) {
         tiles = s->sched.plan();
       }
     }
-    for (size_t i = 0; i < admitted.size() && ok; ++i) ok = stage_slot(s, admitted[i].first, reqs[i]);
-    if (!ok) break;
-    if (!tiles.empty()) {
-      InFlight f;
-      f.done = events.back();
-      events.pop_back();
-      ok = launch_pass(s, tiles, next_buf, f);
+    if (free_lane) {
+      for (size_t i = 0; i < admitted.size() && ok; ++i)
+        ok = stage_slot(s, admitted[i].first, reqs[i], free_lane->stream);
       if (!ok) break;
-      next_buf ^= 1;
-      {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->iterations += 1;
-      }
-      fl.push_back(f);
     }
-    // keep at most max_in_flight passes queued; with nothing new to launch, retire
-    while (ok && !fl.empty() && ((int)fl.size() >= s->cfg.max_in_flight || tiles.empty())) {
-      ok = retire_one(s, fl, events);
-      if (tiles.empty()) break;
+    if (!tiles.empty()) {
+      ok = launch_pass(s, *free_lane, tiles);
+      if (!ok) break;
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->iterations += 1;
+      continue;  // fill the other lanes before waiting
     }
+    if (busy == 0) continue;
+    // every lane busy, or nothing new to launch: wait until a pass finishes
+    int n = 0;
+    while (ok && (n = poll_lanes(s)) == 0) {
+      std::unique_lock<std::mutex> lk(s->mu);
+      // wake early for new work when a lane is free
+      if (free_lane && (s->kicked || s->sched.has_unscheduled())) break;
+      s->cv_work.wait_for(lk, std::chrono::microseconds(100));
+    }
+    if (n < 0) ok = false;
   }
-  while (ok && !fl.empty()) ok = retire_one(s, fl, events);
+  // drain
+  for (Lane &L : s->lanes) {
+    if (!L.busy) continue;
+    if (hipEventSynchronize(L.done) != hipSuccess || !retire(s, L)) ok = false;
+  }
   if (!ok) {
     const hipError_t e = hipGetLastError();
     char buf[256];
     snprintf(buf, sizeof buf, "server pass failed: %s", hipGetErrorString(e));
     fail_all(s, LF_EDEVICE, buf);
   }
-  (void)hipStreamSynchronize(s->stream);
-  for (hipEvent_t e : events) (void)hipEventDestroy(e);
-  for (InFlight &f : fl) (void)hipEventDestroy(f.done);
+  for (Lane &L : s->lanes) (void)hipStreamSynchronize(L.stream);
+}
+
+void free_server(lf_server *s) {
+  for (Lane &L : s->lanes) {
+    if (L.stream) {
+      (void)hipStreamSynchronize(L.stream);
+      (void)hipStreamDestroy(L.stream);
+    }
+    if (L.done) (void)hipEventDestroy(L.done);
+    if (L.h_chunks) (void)hipHostFree(L.h_chunks);
+    if (L.h_rb) (void)hipHostFree(L.h_rb);
+  }
+  for (SlotDev &sd : s->slots)
+    if (sd.staged) (void)hipEventDestroy(sd.staged);
+  if (s->h_slots) (void)hipHostFree(s->h_slots);
+  if (s->h_cams) (void)hipHostFree(s->h_cams);
+  delete s;
 }
 
 }  // namespace
@@ -378,7 +410,7 @@ void lf_server_config_default(lf_server_config *cfg) {
   cfg->max_spp = 4;
   cfg->max_pending = 4096;
   cfg->policy = LF_SCHED_SHORTEST_FIRST;
-  cfg->max_in_flight = 1;
+  cfg->max_in_flight = 2;
   lf_params_default(&cfg->params);
 }
 
@@ -395,7 +427,7 @@ lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **o
   if (cfg->max_pending < 1 || cfg->hbm_budget_bytes < 1) return lfh::fail(c, LF_EINVAL, "invalid queue or budget");
   if (cfg->policy < LF_SCHED_SHORTEST_FIRST || cfg->policy > LF_SCHED_ROUND_ROBIN)
     return lfh::fail(c, LF_EINVAL, "unknown scheduling policy %d", cfg->policy);
-  if (cfg->max_in_flight < 1 || cfg->max_in_flight > 2) return lfh::fail(c, LF_EINVAL, "max_in_flight not in 1..2");
+  if (cfg->max_in_flight < 1 || cfg->max_in_flight > 4) return lfh::fail(c, LF_EINVAL, "max_in_flight not in 1..4");
   lf_params p = cfg->params;
   p.spp = cfg->max_spp;
   lf_status st = lfh::validate_params(c, &p);
@@ -426,47 +458,47 @@ lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **o
   s->sched = lf::Scheduler(sc);
   s->slot_ticket.assign(cfg->max_slots, 0);
   s->slots = std::vector<SlotDev>(cfg->max_slots);
+  s->lanes = std::vector<Lane>(cfg->max_in_flight);
   const int64_t B = cfg->batch_rays;
   const int64_t BS = B * cfg->max_spp;
   s->max_chunks = B / lf::kChunk;
-  bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && hipHostMalloc((void **)&s->h_slots, sizeof(lf::BatchSlot) * cfg->max_slots, hipHostMallocDefault) ==
-                 hipSuccess;
+  bool ok = hipHostMalloc((void **)&s->h_slots, sizeof(lf::BatchSlot) * cfg->max_slots, hipHostMallocDefault) ==
+            hipSuccess;
   ok = ok && hipHostMalloc((void **)&s->h_cams, sizeof(lf::CamArgs) * cfg->max_slots, hipHostMallocDefault) ==
                  hipSuccess;
-  for (int i = 0; i < 2 && ok; ++i)
-    ok = hipHostMalloc((void **)&s->h_chunks[i], sizeof(lf::ChunkDesc) * s->max_chunks, hipHostMallocDefault) ==
-             hipSuccess &&
-         s->d_chunks[i].ensure(sizeof(lf::ChunkDesc) * s->max_chunks);
-  ok = ok && hipHostMalloc((void **)&s->h_rb, sizeof(IterReadback) * 2, hipHostMallocDefault) == hipSuccess;
   ok = ok && s->d_slots.ensure(sizeof(lf::BatchSlot) * cfg->max_slots);
   const int M = c->n_inst - 1;
   for (int i = 0; i < cfg->max_slots && ok; ++i) {
     SlotDev &sd = s->slots[i];
-    ok = sd.xf.ensure(sizeof(float) * 12 * (M > 0 ? M : 1)) && sd.inst.ensure(sizeof(lf::InstRec) * c->n_inst) &&
+    ok = hipEventCreateWithFlags(&sd.staged, hipEventDisableTiming) == hipSuccess &&
+         sd.xf.ensure(sizeof(float) * 12 * (M > 0 ? M : 1)) && sd.inst.ensure(sizeof(lf::InstRec) * c->n_inst) &&
          sd.bounds.ensure(6 * sizeof(double)) && sd.cam.ensure(sizeof(lf::CamArgs)) && sd.status.ensure(4) &&
          sd.tex.ensure(sizeof(float) * 3 * 256 * 512) &&
          lfh::ensure_env_tables(sd.cdf_row, sd.cdf_col, sd.lum, sd.rowsum, sd.roww, sd.scal, 256, 512);
   }
-  ok = ok && s->rec1.ensure(sizeof(lf::SurfRec) * B) && s->rec2.ensure(sizeof(lf::SurfRec) * BS) &&
-       s->queue.ensure(sizeof(lf::SecEntry) * BS) && s->qcount.ensure(4) && s->retry.ensure(sizeof(lf::RetryEnt) * BS) &&
-       s->rcount.ensure(4) && s->contrib.ensure(sizeof(float) * 3 * BS) && s->skeys.ensure(8 * BS) &&
-       s->skeys2.ensure(8 * BS) && s->svals.ensure(4 * BS) && s->svals2.ensure(4 * BS) &&
-       s->shist.ensure(4 * lf::radix_sort_hist_words(BS)) && s->status.ensure(4);
-  if (ok) {
-    lf::launch_fill_u32(s->status.as<uint32_t>(), 0u, 1, s->stream);
-    ok = hipStreamSynchronize(s->stream) == hipSuccess;
+  for (Lane &L : s->lanes) {
+    if (!ok) break;
+    ok = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&L.done, hipEventDisableTiming) == hipSuccess &&
+         hipHostMalloc((void **)&L.h_chunks, sizeof(lf::ChunkDesc) * s->max_chunks, hipHostMallocDefault) ==
+             hipSuccess &&
+         hipHostMalloc((void **)&L.h_rb, sizeof(IterReadback), hipHostMallocDefault) == hipSuccess &&
+         L.d_chunks.ensure(sizeof(lf::ChunkDesc) * s->max_chunks) && L.rec1.ensure(sizeof(lf::SurfRec) * B) &&
+         L.rec2.ensure(sizeof(lf::SurfRec) * BS) && L.queue.ensure(sizeof(lf::SecEntry) * BS) &&
+         L.qcount.ensure(4) && L.retry.ensure(sizeof(lf::RetryEnt) * BS) && L.rcount.ensure(4) &&
+         L.contrib.ensure(sizeof(float) * 3 * BS) && L.skeys.ensure(8 * BS) && L.skeys2.ensure(8 * BS) &&
+         L.svals.ensure(4 * BS) && L.svals2.ensure(4 * BS) && L.shist.ensure(4 * lf::radix_sort_hist_words(BS)) &&
+         L.status.ensure(4);
+    if (ok) {
+      lf::launch_fill_u32(L.status.as<uint32_t>(), 0u, 1, L.stream);
+      ok = hipStreamSynchronize(L.stream) == hipSuccess;
+    }
   }
   if (!ok) {
     (void)hipGetLastError();
-    if (s->stream) (void)hipStreamDestroy(s->stream);
-    if (s->h_slots) (void)hipHostFree(s->h_slots);
-    if (s->h_cams) (void)hipHostFree(s->h_cams);
-    for (int i = 0; i < 2; ++i)
-      if (s->h_chunks[i]) (void)hipHostFree(s->h_chunks[i]);
-    if (s->h_rb) (void)hipHostFree(s->h_rb);
-    delete s;
-    return lfh::fail(c, LF_ENOMEM, "server buffers (batch of %lld rays x %d samples)", (long long)B, cfg->max_spp);
+    free_server(s);
+    return lfh::fail(c, LF_ENOMEM, "server buffers (batch of %lld rays x %d samples, %d lanes)", (long long)B,
+                     cfg->max_spp, cfg->max_in_flight);
   }
   c->servers += 1;
   s->worker = std::thread(serve, s);
@@ -513,6 +545,7 @@ lf_status lf_server_submit(lf_server *s, const lf_request *r, uint64_t *ticket) 
   tr.t_submit = now_ms();
   if (s->t_first < 0.0) s->t_first = tr.t_submit;
   *ticket = t;
+  s->kicked = true;
   s->cv_work.notify_one();
   return LF_OK;
 }
@@ -604,17 +637,8 @@ void lf_server_destroy(lf_server *s) {
     s->cv_done.notify_all();
   }
   (void)hipSetDevice(s->ctx->device);
-  if (s->stream) {
-    (void)hipStreamSynchronize(s->stream);
-    (void)hipStreamDestroy(s->stream);
-  }
-  if (s->h_slots) (void)hipHostFree(s->h_slots);
-  if (s->h_cams) (void)hipHostFree(s->h_cams);
-  for (int i = 0; i < 2; ++i)
-    if (s->h_chunks[i]) (void)hipHostFree(s->h_chunks[i]);
-  if (s->h_rb) (void)hipHostFree(s->h_rb);
   s->ctx->servers -= 1;
-  delete s;
+  free_server(s);
 }
 
 }  // extern "C"

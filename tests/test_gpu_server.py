@@ -39,11 +39,15 @@ def _alone(tr, q):
     return tr.render(dev(q.env), R=dev(q.R), t=dev(q.t), cameras=[q.camera], k=32, spp=q.spp, seed=q.seed)
 
 
-def test_served_in_a_mix_equals_rendered_alone(setup):
+@pytest.mark.parametrize("policy,lanes", [(0, 2), (1, 1), (2, 3)])
+def test_served_in_a_mix_equals_rendered_alone(setup, policy, lanes):
+    """Several passes run at once (one per lane); a request's tiles land in
+    passes on different lanes, after its slot was staged on one of them."""
     import paper_2608_29269_amd as lf
     tr, wl = setup
     reqs = _requests(9, seed=1)
-    srv = lf.Server(tr, max_slots=3, tile_rays=256, batch_rays=1024, max_spp=4)
+    srv = lf.Server(tr, max_slots=3, tile_rays=256, batch_rays=1024, max_spp=4, policy=policy,
+                    max_in_flight=lanes)
     try:
         tickets = [srv.submit(dev(q.env), q.camera, R=dev(q.R), t=dev(q.t), spp=q.spp, seed=q.seed) for q in reqs]
         outs = [srv.wait(t) for t in tickets]
