@@ -449,14 +449,23 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
       continue;
     }
     const float tlo = (float)(0.5 * P.t_min);
+    // Two phases per round (Aila and Laine 2009, "while-while" with postponed
+    // leaves): lanes step through internal nodes together, each postponing the
+    // first leaf it meets, until no lane of the wave is still without a leaf;
+    // then the wave tests leaves together.  kDone ends a lane; it is never a
+    // leaf (~kDone = INT_MAX >= n_rec).
+    constexpr int kDone = (int)0x80000000;
     int cur = I.root;
+    int pend = kDone;
     int sp = 0;
-    while (true) {
-      if (cur >= S.n_nodes || ~cur >= S.n_rec) {  // never taken for a consistent hierarchy
-        atomicOr(status, kStatusBvhCorrupt);
-        break;
-      }
-      if (cur >= 0) {
+    while (cur != kDone || pend != kDone) {
+      while (cur >= 0) {
+        if (cur >= S.n_nodes) {  // never taken for a consistent hierarchy
+          atomicOr(status, kStatusBvhCorrupt);
+          cur = kDone;
+          pend = kDone;
+          break;
+        }
         ++c_nodes;
         const BNode4 &nd = S.nodes[cur];
         const float4 lx = *(const float4 *)nd.lox, ly = *(const float4 *)nd.loy, lz = *(const float4 *)nd.loz;
@@ -477,26 +486,46 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
         cswap(t1, c1, t3, c3);
         cswap(t1, c1, t2, c2);
         if (t0 == INFINITY) {
-          // no child hit: pop below
+          cur = sp ? stk[(--sp) * kBlock] : kDone;
         } else {
           const int nhit = 1 + (t1 < INFINITY) + (t2 < INFINITY) + (t3 < INFINITY);
           if (sp + nhit - 1 > kStack) {
             atomicOr(status, kStatusOverflow);
+            cur = kDone;
+            pend = kDone;
             break;
           }
           if (t3 < INFINITY) stk[(sp++) * kBlock] = c3;
           if (t2 < INFINITY) stk[(sp++) * kBlock] = c2;
           if (t1 < INFINITY) stk[(sp++) * kBlock] = c1;
           cur = c0;
-          continue;
         }
-      } else {
-        c_ins += test_surfel<K>(S, ~cur, oo, dd, rf, P.t_min, t_min_f, kb, t_bound);
+        if (cur < 0 && cur != kDone && pend == kDone) {  // postpone the first leaf, keep traversing
+          pend = cur;
+          cur = sp ? stk[(--sp) * kBlock] : kDone;
+        }
+        if (!__any(pend == kDone && cur >= 0)) break;  // every lane holds a leaf or is done
+      }
+      // the postponed leaf, then the leaves on top of the stack
+      while (true) {
+        int leaf;
+        if (pend != kDone) {
+          leaf = pend;
+          pend = kDone;
+        } else if (cur < 0 && cur != kDone) {
+          leaf = cur;
+          cur = sp ? stk[(--sp) * kBlock] : kDone;
+        } else {
+          break;
+        }
+        if (~leaf >= S.n_rec) {  // never taken for a consistent hierarchy
+          atomicOr(status, kStatusBvhCorrupt);
+          cur = kDone;
+          break;
+        }
+        c_ins += test_surfel<K>(S, ~leaf, oo, dd, rf, P.t_min, t_min_f, kb, t_bound);
         ++c_tests;
       }
-      if (sp == 0) break;
-      --sp;
-      cur = stk[sp * kBlock];
     }
   }
   if (P.counters) {
