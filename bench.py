@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--serve-batch", type=int, default=262144, help="primary rays per batched pass")
     ap.add_argument("--serve-in-flight", type=int, default=2, help="concurrent passes (one stream each)")
     ap.add_argument("--serve-only", action="store_true", help="skip the fwd+bwd and CPU legs")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -68,6 +70,13 @@ def main():
               "multi-GPU path in this build; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_probe:
+        src = torch.ones(1 << 28, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4}))
+        return
 
     import paper_2608_29269_amd as lf
     import scenegen
@@ -351,58 +360,67 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def roofline(phases, counts, stats, args, nr):
-    """Roofline of the dominant phase: algorithmic bytes per launch (per-ray
-    figures from the oracle's counts on the CPU sample) over its average
-    launch duration measured with HIP events on the library's stream."""
+# Kernels that each own one phase timer (one launch per call) and what they process.
+KERNEL_OF_PHASE = {"trace1": "k_trace1<32, false>", "trace1_exact": "k_trace1_exact<32, false>",
+                   "trace2": "k_trace2<32, false>", "trace2_exact": "k_trace2_exact<32, false>",
+                   "adj_trace": "k_adj_trace<32>", "adj_trace_exact": "k_adj_trace_exact<32>"}
+
+
+def kernel_bytes(counts, stats, steps):
+    """Algorithmic HBM bytes per launch of each tracing kernel: per-ray
+    figures times the rays one launch processes.  h_touch (supports crossed
+    before the k-th hit) and h_comp (composited hits) are counted by the
+    oracle on the CPU sample of the same workload."""
     import oracle
-    name, (ms, n) = max(((k, v) for k, v in phases.items() if v[1]), key=lambda kv: kv[1][0])
-    avg_s = ms / n / 1e3
-    if counts is None:
-        return {"bound": "hbm", "kernel": name, "avg_ms": ms / n, "achieved": None, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": None, "traffic": None}
     c = counts
-    npri = c.shape[0]
     sec = max(c[:, oracle.C_SEC_RAYS].sum(), 1.0)
     touch_p = c[:, oracle.C_TOUCH_PRI].mean()
     comp_p = c[:, oracle.C_COMP_PRI].mean()
-    live_p = c[:, oracle.C_SEC_RAYS].mean()
     touch_s = c[:, oracle.C_TOUCH_SEC].sum() / sec
     comp_s = c[:, oracle.C_COMP_SEC].sum() / sec
-    env_p = c[:, oracle.C_ENV].mean()                       # all env lookups per primary ray
-    env_s = (env_p - 1.0 - live_p) * npri / sec            # secondary-record lookups per secondary ray
-    rays_pri = stats["rays_primary"] / max(args.steps, 1)
-    rays_sec = stats["rays_secondary"] / max(args.steps, 1)
-    per = {
-        # outputs 32 B; 40 B geometry per crossed support; 20 B material per composited hit;
-        # 48 B per bilinear env lookup; 44 B per queued secondary ray
-        "primary": (32 + 40 * touch_p + 20 * comp_p + 48 * 1 + 44 * live_p) * rays_pri,
-        "replay_primary": (40 * touch_p + 20 * comp_p + 44 * live_p) * rays_pri,
-        "secondary": (44 + 40 * touch_s + 20 * comp_s + 48 * (1 + env_s) + 12) * rays_sec,
-        "replay_secondary": (44 + 40 * touch_s + 20 * comp_s + 44) * rays_sec,
-        # upstream 12 B; re-read of geometry and material; 120 B gradient read-modify-write per
-        # composited hit; env reads (48 B) and env-gradient read-modify-write (96 B) per lookup;
-        # 44 B of frozen secondary data per live sample
-        "adjoint": (12 + 40 * touch_p + 20 * comp_p + 120 * comp_p + 144 * env_p + 44 * live_p) * rays_pri,
+    rays_pri = stats["rays_primary"] / max(steps, 1)
+    rays_sec = stats["rays_secondary"] / max(steps, 1)
+    per_ray = {
+        # 40 B of geometry per crossed support, 20 B of material per composited hit, 60 B surface
+        # record out, 20 B of depth/normal/alpha out (rays come from the camera on the device)
+        "trace1": 40 * touch_p + 20 * comp_p + 60 + 20,
+        # 44 B queued ray in (origin, direction, id, sample, throughput), same per-hit bytes, 60 B record out
+        "trace2": 44 + 40 * touch_s + 20 * comp_s + 60,
+        # 44 B of adjoint seeds in, per-hit bytes, 120 B gradient read-modify-write per composited hit
+        "adj_trace": 44 + 40 * touch_p + 20 * comp_p + 120 * comp_p,
     }
-    if name not in per:
-        return {"bound": "hbm", "kernel": name, "avg_ms": ms / n, "achieved": None, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": None, "traffic": None}
-    bytes_launch = per[name]
-    achieved = bytes_launch / avg_s / 1e9
-    traffic = None
+    rays = {"trace1": rays_pri, "trace2": rays_sec, "adj_trace": rays_pri}
+    return {k: per_ray[k] * rays[k] for k in per_ray}, per_ray, rays
+
+
+def roofline(phases, counts, stats, args, nr):
+    """Roofline of the dominant kernel: algorithmic bytes per launch over its
+    average launch duration, measured with HIP events on the library's stream
+    (each of these phases holds exactly one launch per call)."""
+    cand = {k: v for k, v in phases.items() if k in KERNEL_OF_PHASE and v[1]}
+    name, (ms, n) = max(cand.items(), key=lambda kv: kv[1][0])
+    avg_ms = ms / n
+    out = {"bound": "hbm", "kernel": KERNEL_OF_PHASE[name], "phase": name, "avg_ms": avg_ms, "achieved": None,
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None}
+    if counts is None:
+        return out
+    per_launch, per_ray, rays = kernel_bytes(counts, stats, args.steps)
+    if name not in per_launch:
+        return out
+    achieved = per_launch[name] / (avg_ms * 1e-3) / 1e9
+    out.update(achieved=float(achieved), frac=float(achieved / HBM_PEAK_GBS),
+               alg_bytes_per_launch=float(per_launch[name]), alg_bytes_per_ray=float(per_ray[name]),
+               rays_per_launch=float(rays[name]))
     tf = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tf):
         try:
             tj = json.load(open(tf))
-            e = tj.get(name)
-            if e and e.get("source_digest") == source_digest():
-                traffic = e.get("bytes_per_launch")
-        except Exception:
-            traffic = None
-    return {"bound": "hbm", "kernel": name, "avg_ms": ms / n, "achieved": float(achieved), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": float(achieved / HBM_PEAK_GBS), "traffic": traffic,
-            "alg_bytes_per_launch": float(bytes_launch)}
+            e = tj.get("kernels", {}).get(out["kernel"])
+            if e and tj.get("source_digest") == source_digest():
+                out["traffic"] = e.get("hbm_bytes_per_launch")
+        except (OSError, ValueError):
+            out["traffic"] = None
+    return out
 
 
 if __name__ == "__main__":

@@ -235,17 +235,21 @@ lf_status lf_trace_counters(lf_ctx *ctx, uint64_t *counters /*[LF_NUM_COUNTERS]*
 /* Per-phase device timers.  When enabled, every phase below is bracketed by
  * HIP events on the context's stream; lf_profile_read synchronises, returns
  * the accumulated milliseconds and launch counts per phase and resets them.
- * Phases: 0 refit, 1 state and environment tables, 2 primary, 3 secondary,
- * 4 resolve, 5 replay primary, 6 replay secondary, 7 adjoint, 8 gradient
- * zeroing, 9 loss. */
-#define LF_NUM_PHASES 10
+ * Phases: 0 refit, 1 state and environment tables, 2 primary traversal
+ * (binary32 keys), 3 primary exact re-trace, 4 primary shading, 5 secondary
+ * regrouping, 6 secondary traversal, 7 secondary exact re-trace, 8 secondary
+ * shading, 9 resolve, 10 replay of the primary pass, 11 replay of the
+ * secondary pass, 12 shading adjoint, 13 traversal and compositing adjoint,
+ * 14 its exact re-trace, 15 gradient zeroing, 16 loss.  Phases 2, 3, 6, 7, 13
+ * and 14 each hold exactly one kernel launch per call. */
+#define LF_NUM_PHASES 17
 lf_status lf_profile_enable(lf_ctx *ctx, int enable);
 lf_status lf_profile_read(lf_ctx *ctx, double *ms /*[LF_NUM_PHASES]*/, int64_t *count /*[LF_NUM_PHASES]*/);
 
 /* ---------------------------------------------------------------------------
  * Relight server.  Rearranging objects or relighting re-renders the resident
- * scene with new object transforms and a new environment map (Sec. 4,
- * rearrangement and relighting; Sec. 1, appearance recomputed after every
+ * scene with new object transforms and a new environment map (Sec. 3.4,
+ * scene editing and relighting; Sec. 1, appearance recomputed after every
  * interaction).  The server renders many such requests at once by
  * continuous batching: every iteration is one batched forward pass (primary
  * trace, shading, secondary trace, shading, resolve) over 128-ray chunks

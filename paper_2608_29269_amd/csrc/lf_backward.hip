@@ -274,10 +274,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_trace_exact(RenderArgs a, GradAr
 }
 
 template <int K>
-void adjoint_k(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
-  launch_fill_u32(a.retry_count, 0u, 1, st);
-  hipLaunchKernelGGL(k_adj_trace<K>, dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, g);
-  hipLaunchKernelGGL(k_adj_trace_exact<K>, dim3(512), dim3(kBlock), 0, st, a, g);
+void adjoint_k(const RenderArgs &a, const GradArgs &g, int part, hipStream_t st) {
+  if (part & kPartFast) {
+    launch_fill_u32(a.retry_count, 0u, 1, st);
+    hipLaunchKernelGGL(k_adj_trace<K>, dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, g);
+  }
+  if (part & kPartExact) hipLaunchKernelGGL(k_adj_trace_exact<K>, dim3(512), dim3(kBlock), 0, st, a, g);
 }
 
 }  // namespace
@@ -287,13 +289,13 @@ void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st
   hipLaunchKernelGGL(k_adj_shade, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, g);
 }
 
-void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
+void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st, int part) {
   if (a.R <= 0) return;
   switch (kbucket(a.P.k)) {
-    case 8: adjoint_k<8>(a, g, st); break;
-    case 16: adjoint_k<16>(a, g, st); break;
-    case 32: adjoint_k<32>(a, g, st); break;
-    default: adjoint_k<64>(a, g, st); break;
+    case 8: adjoint_k<8>(a, g, part, st); break;
+    case 16: adjoint_k<16>(a, g, part, st); break;
+    case 32: adjoint_k<32>(a, g, part, st); break;
+    default: adjoint_k<64>(a, g, part, st); break;
   }
 }
 

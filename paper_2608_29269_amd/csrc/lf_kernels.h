@@ -80,11 +80,13 @@ struct RenderArgs {
   const ChunkDesc *chunks;
   const BatchSlot *slots;
 };
+// Parts of a traversal launch: 1 = fast keys (collisions queued for retry), 2 = exact re-trace.
+constexpr int kPartFast = 1, kPartExact = 2, kPartBoth = 3;
 // primary: traversal + compositing (fast keys, then exact re-trace of collisions), then shading
-void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st);
+void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st, int part = kPartBoth);
 void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st);
 // secondary: traversal + compositing of the queue, then the two environment samples
-void launch_trace2(const RenderArgs &a, hipStream_t st);
+void launch_trace2(const RenderArgs &a, hipStream_t st, int part = kPartBoth);
 void launch_shade2(const RenderArgs &a, bool replay, hipStream_t st);
 void launch_resolve(const RenderArgs &a, hipStream_t st);
 void launch_accum(unsigned long long *acc, const uint32_t *count, hipStream_t st);
@@ -99,7 +101,7 @@ struct GradArgs {
 };
 // shading adjoint (env gradients, compositing seeds) then traversal + compositing adjoint
 void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st);
-void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st);
+void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st, int part = kPartBoth);
 
 inline int kbucket(int k) { return k <= 8 ? 8 : (k <= 16 ? 16 : (k <= 32 ? 32 : 64)); }
 

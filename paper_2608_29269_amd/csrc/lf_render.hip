@@ -531,34 +531,39 @@ __global__ void k_zero_f64(double *p) { *p = 0.0; }
 constexpr unsigned kExactBlocks = 512;
 
 template <int K, bool B>
-void trace1_k(const RenderArgs &a, bool replay, hipStream_t st) {
-  launch_fill_u32(a.retry_count, 0u, 1, st);
-  hipLaunchKernelGGL((k_trace1<K, B>), dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, replay);
-  hipLaunchKernelGGL((k_trace1_exact<K, B>), dim3(kExactBlocks), dim3(kBlock), 0, st, a, replay);
+void trace1_k(const RenderArgs &a, bool replay, int part, hipStream_t st) {
+  if (part & kPartFast) {
+    launch_fill_u32(a.retry_count, 0u, 1, st);
+    hipLaunchKernelGGL((k_trace1<K, B>), dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, replay);
+  }
+  if (part & kPartExact)
+    hipLaunchKernelGGL((k_trace1_exact<K, B>), dim3(kExactBlocks), dim3(kBlock), 0, st, a, replay);
 }
 template <int K, bool B>
-void trace2_k(const RenderArgs &a, hipStream_t st) {
-  launch_fill_u32(a.retry_count, 0u, 1, st);
-  const int64_t cap = a.R * a.spp_stride;
-  hipLaunchKernelGGL((k_trace2<K, B>), dim3(blocks(cap, kBlock)), dim3(kBlock), 0, st, a);
-  hipLaunchKernelGGL((k_trace2_exact<K, B>), dim3(kExactBlocks), dim3(kBlock), 0, st, a);
+void trace2_k(const RenderArgs &a, int part, hipStream_t st) {
+  if (part & kPartFast) {
+    launch_fill_u32(a.retry_count, 0u, 1, st);
+    const int64_t cap = a.R * a.spp_stride;
+    hipLaunchKernelGGL((k_trace2<K, B>), dim3(blocks(cap, kBlock)), dim3(kBlock), 0, st, a);
+  }
+  if (part & kPartExact) hipLaunchKernelGGL((k_trace2_exact<K, B>), dim3(kExactBlocks), dim3(kBlock), 0, st, a);
 }
 template <bool B>
-void trace1_b(const RenderArgs &a, bool replay, hipStream_t st) {
+void trace1_b(const RenderArgs &a, bool replay, int part, hipStream_t st) {
   switch (kbucket(a.P.k)) {
-    case 8: trace1_k<8, B>(a, replay, st); break;
-    case 16: trace1_k<16, B>(a, replay, st); break;
-    case 32: trace1_k<32, B>(a, replay, st); break;
-    default: trace1_k<64, B>(a, replay, st); break;
+    case 8: trace1_k<8, B>(a, replay, part, st); break;
+    case 16: trace1_k<16, B>(a, replay, part, st); break;
+    case 32: trace1_k<32, B>(a, replay, part, st); break;
+    default: trace1_k<64, B>(a, replay, part, st); break;
   }
 }
 template <bool B>
-void trace2_b(const RenderArgs &a, hipStream_t st) {
+void trace2_b(const RenderArgs &a, int part, hipStream_t st) {
   switch (kbucket(a.P.k)) {
-    case 8: trace2_k<8, B>(a, st); break;
-    case 16: trace2_k<16, B>(a, st); break;
-    case 32: trace2_k<32, B>(a, st); break;
-    default: trace2_k<64, B>(a, st); break;
+    case 8: trace2_k<8, B>(a, part, st); break;
+    case 16: trace2_k<16, B>(a, part, st); break;
+    case 32: trace2_k<32, B>(a, part, st); break;
+    default: trace2_k<64, B>(a, part, st); break;
   }
 }
 
@@ -585,10 +590,10 @@ void launch_env_tables(const float *tex, int H, int W, uint32_t flags, double *c
   hipLaunchKernelGGL(k_env_marginal, dim3(1), dim3(256), 0, st, H, flags, roww, cdf_row, scal);
 }
 
-void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st) {
+void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st, int part) {
   if (a.R <= 0) return;
-  if (a.chunks) trace1_b<true>(a, replay, st);
-  else trace1_b<false>(a, replay, st);
+  if (a.chunks) trace1_b<true>(a, replay, part, st);
+  else trace1_b<false>(a, replay, part, st);
 }
 
 void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st) {
@@ -597,10 +602,10 @@ void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st) {
   else hipLaunchKernelGGL(k_shade1<false>, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, replay);
 }
 
-void launch_trace2(const RenderArgs &a, hipStream_t st) {
+void launch_trace2(const RenderArgs &a, hipStream_t st, int part) {
   if (a.R <= 0) return;
-  if (a.chunks) trace2_b<true>(a, st);
-  else trace2_b<false>(a, st);
+  if (a.chunks) trace2_b<true>(a, part, st);
+  else trace2_b<false>(a, part, st);
 }
 
 void launch_shade2(const RenderArgs &a, bool replay, hipStream_t st) {

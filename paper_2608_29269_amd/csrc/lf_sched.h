@@ -1,6 +1,6 @@
 // lf_sched.h -- admission and tile planning of the relight server
 // (continuous batching of forward renders of one resident scene; every
-// rearrangement or relighting request re-renders the scene, Sec. 4 and the
+// rearrangement or relighting request re-renders the scene, Sec. 3.4 and the
 // interaction loop of Sec. 1).  Plain C++17, no device code: the server
 // (lf_server.hip) executes what it decides and reports completed work back.
 //

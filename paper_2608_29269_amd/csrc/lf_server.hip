@@ -1,5 +1,5 @@
 // lf_server.hip -- relight server: continuous batching of forward renders of
-// the resident scene (Sec. 4 rearrangement and relighting).  A host thread
+// the resident scene (Sec. 3.4, scene editing and relighting).  A host thread
 // admits requests (lf_sched.h), stages each admitted request's transforms,
 // camera and environment into its slot (instance records and importance
 // sampling tables are built on the device) and launches batched wavefront
