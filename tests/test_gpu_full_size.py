@@ -1,0 +1,106 @@
+"""Parity at the full workload sizes (200k to 1M surfels, 800^2 to 1024^2
+images, S up to 4), in the launch configuration the benchmark times: whole
+images in one call.  The oracle computes sampled pixels one by one; forward
+outputs are compared on those pixels, and gradients are compared with an
+upstream gradient that is non-zero only on them (every other ray then adds
+exactly nothing).  Requires an MI355X."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from tests.gpu_common import ambiguous, dev, rel_close, run_oracle, state_args, upload_scene
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-4
+GTOL = 1e-3
+N_SAMPLE = 48
+
+
+@pytest.fixture(scope="module")
+def tracer():
+    import paper_2608_29269_amd as lf
+    return lf.Tracer()
+
+
+def _sampled_rays(cams, m, seed):
+    """m random ray ids over the cameras of one call, with their rays."""
+    rng = np.random.default_rng(seed)
+    sizes = [c.w * c.h for c in cams]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    ids = np.sort(rng.choice(off[-1], m, replace=False))
+    o, d = [], []
+    for i in ids:
+        c = int(np.searchsorted(off, i, side="right") - 1)
+        oo, dd, _ = oracle.raygen(cams[c], np.array([i - off[c]]))
+        o.append(oo[0])
+        d.append(dd[0])
+    return ids, np.array(o, np.float32), np.array(d, np.float32)
+
+
+@pytest.mark.parametrize("which,state", [(2, 0), (3, 0), (4, 0), (4, 3), (5, 0)])
+def test_full_size_forward_on_sampled_pixels(tracer, which, state):
+    wl = scenegen.make_workload(which)
+    st = wl.states[state]
+    print(f"workload {which} state {state}: {wl.scene.n} surfels, {len(st.cameras)} x "
+          f"{st.cameras[0].w}x{st.cameras[0].h}, S={wl.spp}", flush=True)
+    upload_scene(tracer, wl.scene)
+    out = tracer.render(**state_args(tracer, wl.scene, st), cameras=st.cameras, k=wl.k, spp=wl.spp,
+                        seed=wl.seed + state)
+    tracer.sync()
+    ids, o, d = _sampled_rays(st.cameras, N_SAMPLE, which * 10 + state)
+    ref = run_oracle(wl.scene, st, o, d, ids, wl.k, wl.spp, wl.seed + state, 0)
+    amb = ambiguous(ref["margins"])
+    ok = ~amb
+    assert ok.mean() >= 0.9, amb.mean()
+    for key in ("radiance", "depth", "normal", "alpha"):
+        g = out[key].cpu().numpy()[ids]
+        assert rel_close(g[ok], ref[key][ok], RTOL) < RTOL, key
+
+
+def _grad_check(g_gpu, g_ref, name):
+    a = np.asarray(g_gpu, np.float64).ravel()
+    b = np.asarray(g_ref, np.float64).ravel()
+    nb = np.linalg.norm(b)
+    if nb == 0:
+        assert np.abs(a).max() == 0, name
+        return
+    assert np.linalg.norm(a - b) <= GTOL * nb, (name, np.linalg.norm(a - b) / nb)
+    floor = 1e-3 * np.abs(b).max()
+    err = np.abs(a - b) / np.maximum(np.abs(b), floor)
+    assert err.max() <= 2e-2, (name, err.max())
+
+
+@pytest.mark.parametrize("which", [3, 5])
+def test_full_size_gradients_from_sampled_pixels(tracer, which):
+    """The training-step configuration (300k surfels, 4 x 800^2, S=1) and the
+    benchmark configuration (1M surfels, 1024^2, S=4)."""
+    wl = scenegen.make_workload(which)
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    cams = st.cameras
+    n = sum(c.w * c.h for c in cams)
+    ids, o, d = _sampled_rays(cams, N_SAMPLE, 100 + which)
+    sa = oracle.SceneArrays(wl.scene, st.R, st.t, st.env)
+    p = oracle.Params(k=wl.k, spp=wl.spp, seed=wl.seed)
+    fwd = oracle.render(sa, o, d, ids, p, lists=False)
+    amb = ambiguous(fwd["margins"])
+    rng = np.random.default_rng(which)
+    up = dict(radiance=rng.standard_normal((N_SAMPLE, 3)), depth=rng.standard_normal(N_SAMPLE),
+              normal=rng.standard_normal((N_SAMPLE, 3)), alpha=rng.standard_normal(N_SAMPLE))
+    full = {}
+    for k_, v in up.items():
+        v[amb] = 0.0
+        up[k_] = v.astype(np.float32)
+        f = np.zeros((n,) + v.shape[1:], np.float32)
+        f[ids] = up[k_]
+        full[k_] = dev(f)
+    g_ref = oracle.backward(sa, o, d, ids, p, g_radiance=up["radiance"], g_depth=up["depth"],
+                            g_normal=up["normal"], g_alpha=up["alpha"])
+    g = tracer.render_backward(**state_args(tracer, wl.scene, st), cameras=cams, k=wl.k, spp=wl.spp,
+                               seed=wl.seed, d_radiance=full["radiance"], d_depth=full["depth"],
+                               d_normal=full["normal"], d_alpha=full["alpha"])
+    tracer.sync()
+    for name in ("mu", "q", "scale", "opacity", "albedo", "roughness", "metallic", "env"):
+        _grad_check(g[name].cpu().numpy(), g_ref[name], name)
