@@ -159,19 +159,25 @@ __device__ __forceinline__ void kinit(KBufD<K> &b, int k) {
   }
 }
 
+// Insertion into the sorted buffer without a carried dependency: since the
+// buffer is non-decreasing, "key < t[j]" is monotone in j, and slot j takes
+// t[j-1] if the key also precedes t[j-1], the key if it precedes t[j] only,
+// and keeps t[j] otherwise (equal keys stay ahead of the new one).  Slots are
+// updated from the top down so t[j-1] is still the old value; every slot's
+// comparisons are independent of the others.
 template <int K>
 __device__ __forceinline__ void kinsert(KBufF<K> &b, float t, uint32_t id) {
+  bool col = false;
 #pragma unroll
-  for (int j = 0; j < K; ++j) {
+  for (int j = K - 1; j >= 0; --j) {
     const float bt = b.t[j];
-    b.collide |= (t == bt) & (bt < INFINITY);  // two real keys rounded to the same float
-    const bool sw = t < bt;
-    const uint32_t bi = b.id[j];
-    b.t[j] = sw ? t : bt;
-    b.id[j] = sw ? id : bi;
-    t = sw ? bt : t;
-    id = sw ? bi : id;
+    col |= (t == bt) & (bt < INFINITY);  // two real keys rounded to the same float
+    const bool here = t < bt;
+    const bool below = j > 0 && t < b.t[j > 0 ? j - 1 : 0];
+    b.t[j] = here ? (below ? b.t[j > 0 ? j - 1 : 0] : t) : bt;
+    b.id[j] = here ? (below ? b.id[j > 0 ? j - 1 : 0] : id) : b.id[j];
   }
+  b.collide |= col;
 }
 
 // exact order: t, then surfel index (read from the trace record on a tie)
@@ -181,6 +187,8 @@ __device__ __forceinline__ bool kless_exact(const TraceRec *recs, double t1, uin
   return recs[i1 & kIdMask].orig < recs[i2 & kIdMask].orig;
 }
 
+// (carried form: the FP64 buffer of the rare exact re-trace keeps the
+// smaller register footprint)
 template <int K>
 __device__ __forceinline__ void kinsert(KBufD<K> &b, const TraceRec *recs, double t, uint32_t id) {
 #pragma unroll
