@@ -361,9 +361,7 @@ def source_digest():
 
 
 # Kernels that each own one phase timer (one launch per call) and what they process.
-KERNEL_OF_PHASE = {"trace1": "k_trace1<32, false>", "trace1_exact": "k_trace1_exact<32, false>",
-                   "trace2": "k_trace2<32, false>", "trace2_exact": "k_trace2_exact<32, false>",
-                   "adj_trace": "k_adj_trace<32>", "adj_trace_exact": "k_adj_trace_exact<32>"}
+KERNEL_OF_PHASE = {"trace1": "k_trace1<32, false>", "trace2": "k_trace2<32, false>", "adj_trace": "k_adj_trace<32>"}
 
 
 def kernel_bytes(counts, stats, steps):

@@ -227,22 +227,22 @@ lf_status lf_stats_get(lf_ctx *ctx, lf_render_stats *stats);
 /* Traversal counters accumulated by calls made with LF_FLAG_COUNT since the
  * previous read (synchronous; resets them): [0] primary rays, [1] 4-wide
  * nodes visited, [2] surfels tested, [3] hits inserted into k-buffers, then
- * [4..7] the same for secondary rays, [8] primary and [9] secondary rays
- * re-traced with exact keys because two binary32 keys collided. */
+ * [4..7] the same for secondary rays, [8] primary and [9] secondary hits
+ * whose binary32 distance key equalled one already held, placed by exact
+ * FP64 keys. */
 #define LF_NUM_COUNTERS 10
 lf_status lf_trace_counters(lf_ctx *ctx, uint64_t *counters /*[LF_NUM_COUNTERS]*/);
 
 /* Per-phase device timers.  When enabled, every phase below is bracketed by
  * HIP events on the context's stream; lf_profile_read synchronises, returns
  * the accumulated milliseconds and launch counts per phase and resets them.
- * Phases: 0 refit, 1 state and environment tables, 2 primary traversal
- * (binary32 keys), 3 primary exact re-trace, 4 primary shading, 5 secondary
- * regrouping, 6 secondary traversal, 7 secondary exact re-trace, 8 secondary
- * shading, 9 resolve, 10 replay of the primary pass, 11 replay of the
- * secondary pass, 12 shading adjoint, 13 traversal and compositing adjoint,
- * 14 its exact re-trace, 15 gradient zeroing, 16 loss.  Phases 2, 3, 6, 7, 13
- * and 14 each hold exactly one kernel launch per call. */
-#define LF_NUM_PHASES 17
+ * Phases: 0 refit, 1 state and environment tables, 2 primary traversal and
+ * compositing, 3 primary shading, 4 secondary regrouping, 5 secondary
+ * traversal and compositing, 6 secondary shading, 7 resolve, 8 replay of the
+ * primary pass, 9 replay of the secondary pass, 10 shading adjoint,
+ * 11 traversal and compositing adjoint, 12 gradient zeroing, 13 loss.
+ * Phases 2, 5 and 11 each hold exactly one kernel launch per call. */
+#define LF_NUM_PHASES 14
 lf_status lf_profile_enable(lf_ctx *ctx, int enable);
 lf_status lf_profile_read(lf_ctx *ctx, double *ms /*[LF_NUM_PHASES]*/, int64_t *count /*[LF_NUM_PHASES]*/);
 

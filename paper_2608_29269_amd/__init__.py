@@ -217,7 +217,7 @@ class Tracer:
         self._chk(self.L.lf_trace_counters(self.ctx, c))
         keys = ("rays", "nodes", "tests", "inserts")
         p, s_ = dict(zip(keys, c[:4])), dict(zip(keys, c[4:8]))
-        p["retries"], s_["retries"] = c[8], c[9]
+        p["ties"], s_["ties"] = c[8], c[9]
         return {"primary": p, "secondary": s_}
 
     def profile(self, enable: bool = True):

@@ -100,10 +100,9 @@ class ServerStats(C.Structure):
                 ("rays_secondary", C.c_int64), ("iterations", C.c_int64)]
 
 
-NUM_PHASES = 17
-PHASES = ("refit", "state_env", "trace1", "trace1_exact", "shade1", "sort2", "trace2", "trace2_exact", "shade2",
-          "resolve", "replay_primary", "replay_secondary", "adj_shade", "adj_trace", "adj_trace_exact", "zero_grads",
-          "loss")
+NUM_PHASES = 14
+PHASES = ("refit", "state_env", "trace1", "shade1", "sort2", "trace2", "shade2", "resolve", "replay_primary",
+          "replay_secondary", "adj_shade", "adj_trace", "zero_grads", "loss")
 
 # every symbol include/lightfuse.h declares, with its ctypes signature
 SIGNATURES = {

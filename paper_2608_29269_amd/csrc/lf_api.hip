@@ -234,12 +234,8 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
   const bool trace2 = !(p->flags & LF_FLAG_NO_SECONDARY);
   const int64_t RS = R * p->spp;
   const int64_t R1 = R > 0 ? R : 1;
-  if (!c->rec1.ensure(sizeof(lf::SurfRec) * R1) || !c->rcount.ensure(sizeof(uint32_t)) ||
-      !c->retry.ensure(sizeof(lf::RetryEnt) * (trace2 && RS > R1 ? RS : R1)))
-    return fail(c, LF_ENOMEM, "surface records");
+  if (!c->rec1.ensure(sizeof(lf::SurfRec) * R1)) return fail(c, LF_ENOMEM, "surface records");
   a.rec1 = c->rec1.as<lf::SurfRec>();
-  a.retry = c->retry.as<lf::RetryEnt>();
-  a.retry_count = c->rcount.as<uint32_t>();
   if (trace2) {
     if (!c->queue.ensure(sizeof(lf::SecEntry) * (RS > 0 ? RS : 1)) || !c->qcount.ensure(sizeof(uint32_t)) ||
         !c->rec2.ensure(sizeof(lf::SurfRec) * (RS > 0 ? RS : 1)))
@@ -491,34 +487,26 @@ lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, co
   }
   {
     Phase ph(c, 2);
-    lf::launch_trace1(a, false, c->stream, lf::kPartFast);
+    lf::launch_trace1(a, false, c->stream);
   }
   {
     Phase ph(c, 3);
-    lf::launch_trace1(a, false, c->stream, lf::kPartExact);
-  }
-  {
-    Phase ph(c, 4);
     lf::launch_shade1(a, false, c->stream);
   }
   if (trace2) {
     {
-      Phase ph(c, 5);
+      Phase ph(c, 4);
       sort_secondaries(c, a);
     }
     {
+      Phase ph(c, 5);
+      lf::launch_trace2(a, c->stream);
+    }
+    {
       Phase ph(c, 6);
-      lf::launch_trace2(a, c->stream, lf::kPartFast);
-    }
-    {
-      Phase ph(c, 7);
-      lf::launch_trace2(a, c->stream, lf::kPartExact);
-    }
-    {
-      Phase ph(c, 8);
       lf::launch_shade2(a, false, c->stream);
     }
-    Phase ph(c, 9);
+    Phase ph(c, 7);
     lf::launch_resolve(a, c->stream);
     lf::launch_accum(c->acc_secondary.as<unsigned long long>(), a.queue_count, c->stream);
   }
@@ -541,7 +529,7 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
   const int64_t n = c->s.n;
   hipStream_t s = c->stream;
   {
-    Phase ph0(c, 15);
+    Phase ph0(c, 12);
     lf::launch_fill_f32(gi->d_mu, 0.f, 3 * n, s);
     lf::launch_fill_f32(gi->d_q, 0.f, 4 * n, s);
     lf::launch_fill_f32(gi->d_scale, 0.f, 2 * n, s);
@@ -560,12 +548,12 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
     return fail(c, LF_ENOMEM, "frozen records");
   a.frozen = trace2 ? c->frozen.as<lf::SecFrozen>() : nullptr;
   {
-    Phase ph(c, 10);
+    Phase ph(c, 8);
     lf::launch_trace1(a, true, s);
     if (trace2) lf::launch_shade1(a, true, s);
   }
   if (trace2) {
-    Phase ph(c, 11);
+    Phase ph(c, 9);
     sort_secondaries(c, a);
     lf::launch_trace2(a, s);
     lf::launch_shade2(a, true, s);
@@ -573,16 +561,12 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
   lf::GradArgs ga{g->d_radiance, g->d_depth, g->d_normal, g->d_alpha, gi->d_mu, gi->d_q, gi->d_scale,
                   gi->d_opacity, gi->d_albedo, gi->d_roughness, gi->d_metallic, gi->d_env};
   {
-    Phase ph(c, 12);
+    Phase ph(c, 10);
     lf::launch_adjoint_shade(a, ga, s);
   }
   {
-    Phase ph(c, 13);
-    lf::launch_adjoint_trace(a, ga, s, lf::kPartFast);
-  }
-  {
-    Phase ph(c, 14);
-    lf::launch_adjoint_trace(a, ga, s, lf::kPartExact);
+    Phase ph(c, 11);
+    lf::launch_adjoint_trace(a, ga, s);
   }
   return check_hip(c, "backward");
 }
@@ -592,7 +576,7 @@ lf_status lf_l1_loss(lf_ctx *c, const float *pred, const float *target, int64_t 
   if (!pred || !target || !loss || n < 0) return fail(c, LF_EINVAL, "invalid loss arguments");
   set_device(c);
   if (!c->l1acc.ensure(sizeof(double))) return fail(c, LF_ENOMEM, "loss accumulator");
-  Phase ph(c, 16);
+  Phase ph(c, 13);
   lf::launch_l1(pred, target, n, loss, grad, c->l1acc.as<double>(), c->stream);
   return check_hip(c, "l1 loss");
 }

@@ -249,37 +249,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_trace(RenderArgs a, GradArgs G) 
   if (active) load_ray(a.rays, ray, of, df);
   const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
   KBufF<K> kb;
-  kb.collide = false;
-  if (active) trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
-  const bool again = active && kb.collide;
-  queue_retry<K>(again, (int32_t)ray, kb, a.retry, a.retry_count, nullptr);
-  if (active && !again) adjoint_hits<K>(a, G, sd, kb, o, d);
-}
-
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_adj_trace_exact(RenderArgs a, GradArgs G) {
-  __shared__ int stk[kStack * kBlock];
-  const uint32_t cnt = *a.retry_count;
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
-    const RetryEnt re = a.retry[i];
-    const int64_t ray = re.id;
-    const AdjSeed sd = a.seeds[ray];
-    float of[3], df[3];
-    load_ray(a.rays, ray, of, df);
-    const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
-    KBufD<K> kb;
-    trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0, retry_bound(re));
+  if (active) {
+    trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
     adjoint_hits<K>(a, G, sd, kb, o, d);
   }
 }
 
 template <int K>
-void adjoint_k(const RenderArgs &a, const GradArgs &g, int part, hipStream_t st) {
-  if (part & kPartFast) {
-    launch_fill_u32(a.retry_count, 0u, 1, st);
-    hipLaunchKernelGGL(k_adj_trace<K>, dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, g);
-  }
-  if (part & kPartExact) hipLaunchKernelGGL(k_adj_trace_exact<K>, dim3(512), dim3(kBlock), 0, st, a, g);
+void adjoint_k(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_trace<K>, dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, g);
 }
 
 }  // namespace
@@ -289,13 +267,13 @@ void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st
   hipLaunchKernelGGL(k_adj_shade, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, g);
 }
 
-void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st, int part) {
+void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
   if (a.R <= 0) return;
   switch (kbucket(a.P.k)) {
-    case 8: adjoint_k<8>(a, g, part, st); break;
-    case 16: adjoint_k<16>(a, g, part, st); break;
-    case 32: adjoint_k<32>(a, g, part, st); break;
-    default: adjoint_k<64>(a, g, part, st); break;
+    case 8: adjoint_k<8>(a, g, st); break;
+    case 16: adjoint_k<16>(a, g, st); break;
+    case 32: adjoint_k<32>(a, g, st); break;
+    default: adjoint_k<64>(a, g, st); break;
   }
 }
 

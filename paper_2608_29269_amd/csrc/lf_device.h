@@ -125,19 +125,13 @@ __device__ __forceinline__ void load_ray(const RaySource &rs, int64_t id, float 
 // first K-k slots hold -inf sentinels so the k-th hit always sits in the last
 // (static) slot.
 //
-// KBufF (fast path) keys on t rounded to binary32, which preserves the order
-// of distinct keys; two keys that round to the same float are flagged as a
-// collision and the ray is re-traced with KBufD, which keys on the exact
-// double t and breaks exact ties by surfel index.
+// Keys are t rounded to binary32, which preserves the order of distinct
+// keys; a new key equal to one in the buffer is placed by the exact double t
+// and, on exact ties, the surfel index (kinsert_tied), so the buffer always
+// holds the k closest hits in exact (t, index) order.
 template <int K>
 struct KBufF {
   float t[K];
-  uint32_t id[K];
-  bool collide;
-};
-template <int K>
-struct KBufD {
-  double t[K];
   uint32_t id[K];
 };
 
@@ -148,58 +142,23 @@ __device__ __forceinline__ void kinit(KBufF<K> &b, int k) {
     b.t[j] = j < K - k ? -INFINITY : INFINITY;
     b.id[j] = kIdMask;
   }
-  b.collide = false;
-}
-template <int K>
-__device__ __forceinline__ void kinit(KBufD<K> &b, int k) {
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    b.t[j] = j < K - k ? -INFINITY : INFINITY;
-    b.id[j] = kIdMask;
-  }
 }
 
 // Insertion into the sorted buffer without a carried dependency: since the
 // buffer is non-decreasing, "key < t[j]" is monotone in j, and slot j takes
 // t[j-1] if the key also precedes t[j-1], the key if it precedes t[j] only,
-// and keeps t[j] otherwise (equal keys stay ahead of the new one).  Slots are
-// updated from the top down so t[j-1] is still the old value; every slot's
-// comparisons are independent of the others.
+// and keeps t[j] otherwise.  Slots are updated from the top down so t[j-1] is
+// still the old value; every slot's comparisons are independent.  Only used
+// for a key equal to no key in the buffer.
 template <int K>
 __device__ __forceinline__ void kinsert(KBufF<K> &b, float t, uint32_t id) {
-  bool col = false;
 #pragma unroll
   for (int j = K - 1; j >= 0; --j) {
     const float bt = b.t[j];
-    col |= (t == bt) & (bt < INFINITY);  // two real keys rounded to the same float
     const bool here = t < bt;
     const bool below = j > 0 && t < b.t[j > 0 ? j - 1 : 0];
     b.t[j] = here ? (below ? b.t[j > 0 ? j - 1 : 0] : t) : bt;
     b.id[j] = here ? (below ? b.id[j > 0 ? j - 1 : 0] : id) : b.id[j];
-  }
-  b.collide |= col;
-}
-
-// exact order: t, then surfel index (read from the trace record on a tie)
-__device__ __forceinline__ bool kless_exact(const TraceRec *recs, double t1, uint32_t i1, double t2, uint32_t i2) {
-  if (t1 != t2) return t1 < t2;
-  if ((i2 & kIdMask) == kIdMask) return true;  // empty slot
-  return recs[i1 & kIdMask].orig < recs[i2 & kIdMask].orig;
-}
-
-// (carried form: the FP64 buffer of the rare exact re-trace keeps the
-// smaller register footprint)
-template <int K>
-__device__ __forceinline__ void kinsert(KBufD<K> &b, const TraceRec *recs, double t, uint32_t id) {
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const double bt = b.t[j];
-    const uint32_t bi = b.id[j];
-    const bool sw = (t < bt) || (t == bt && kless_exact(recs, t, id, bt, bi));
-    b.t[j] = sw ? t : bt;
-    b.id[j] = sw ? id : bi;
-    t = sw ? bt : t;
-    id = sw ? bi : id;
   }
 }
 
@@ -326,12 +285,25 @@ __device__ __forceinline__ void cswap(float &ta, int &ca, float &tb, int &cb) {
 // Exact (double) plane intersection and support test of the surfel at leaf
 // position pos against the object-space ray (o, d).  Returns false if the
 // surfel is not hit; otherwise t and the flip bit.
+// Plane intersection n.(mu - o) / n.d of the object-space ray with a
+// surfel's plane, with a fixed operation order (no contraction): every
+// recomputation for the same surfel and ray gives the same double.
+__device__ __forceinline__ double plane_den(const TraceRec &r, d3 d) {
+#pragma clang fp contract(off)
+  return r.n[0] * d.x + r.n[1] * d.y + r.n[2] * d.z;
+}
+__device__ __forceinline__ double plane_t(const TraceRec &r, d3 o, double den) {
+#pragma clang fp contract(off)
+  const double mx = (double)r.mu[0] - o.x, my = (double)r.mu[1] - o.y, mz = (double)r.mu[2] - o.z;
+  return (r.n[0] * mx + r.n[1] * my + r.n[2] * mz) / den;
+}
+
 __device__ __forceinline__ bool exact_hit(const TraceRec &r, d3 o, d3 d, double t_min, double &t, bool &flip) {
-  d3 n = mk(r.n[0], r.n[1], r.n[2]);
-  double den = dot(n, d);
+  const double den = plane_den(r, d);
   if (!(fabs(den) >= 1e-12)) return false;
-  d3 mu = mk((double)r.mu[0], (double)r.mu[1], (double)r.mu[2]);
-  t = dot(n, mu - o) / den;
+  const d3 n = mk(r.n[0], r.n[1], r.n[2]);
+  const d3 mu = mk((double)r.mu[0], (double)r.mu[1], (double)r.mu[2]);
+  t = plane_t(r, o, den);
   if (!(t > t_min)) return false;
   d3 dl = (o + t * d) - mu;
   double xu = dl.x * r.a[0] + dl.y * r.a[1] + dl.z * r.a[2];
@@ -370,47 +342,18 @@ __device__ __forceinline__ bool prefilter(const FiltRec &F, const RayF &r, float
 }
 
 // Test one surfel and insert it if valid and among the k closest.
-template <int K>
-__device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3 d, const RayF &rf, double t_min,
-                                           float t_min_f, KBufF<K> &kb, double) {
-  const float tk = kb.t[K - 1];
-  const float tk_up = tk < INFINITY ? next_up_f(tk) : INFINITY;
-  if (!prefilter(S.filt[pos], rf, t_min_f, tk_up)) return 0;
-  double t;
-  bool flip;
-  if (!exact_hit(S.rec[pos], o, d, t_min, t, flip)) return 0;
-  const float tf = (float)t;
-  if (tf > tk) return 0;  // round-to-nearest is monotone: t > t_k exactly
-  if (tf == tk) kb.collide = true;
-  kinsert<K>(kb, tf, (uint32_t)pos | (flip ? kFlipBit : 0u));
-  return 1;
-}
-// t_bound >= the exact k-th distance of the ray (known from a first trace)
-template <int K>
-__device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3 d, const RayF &rf, double t_min,
-                                           float t_min_f, KBufD<K> &kb, double t_bound) {
-  const double tk = kb.t[K - 1];
-  const double tb = fmin(tk, t_bound);
-  const float tk_up = tb < INFINITY ? round_up_f(tb) : INFINITY;
-  if (!prefilter(S.filt[pos], rf, t_min_f, tk_up)) return 0;
-  double t;
-  bool flip;
-  if (!exact_hit(S.rec[pos], o, d, t_min, t, flip)) return 0;
-  if (t > t_bound) return 0;  // beyond the k-th distance: not among the k closest
-  const uint32_t id = (uint32_t)pos | (flip ? kFlipBit : 0u);
-  if (!(t < tk || (t == tk && kless_exact(S.rec, t, id, tk, kb.id[K - 1])))) return 0;
-  kinsert<K>(kb, S.rec, t, id);
-  return 1;
-}
-
-// object-space ray of instance I
+// object-space ray of instance I (fixed operation order, no contraction)
 __device__ __forceinline__ void to_object(const InstRec &I, d3 o, d3 d, d3 &oo, d3 &dd) {
+#pragma clang fp contract(off)
   if (I.identity) {
     oo = o;
     dd = d;
   } else {
-    oo = mulT(I.R, o - mk(I.t[0], I.t[1], I.t[2]));
-    dd = mulT(I.R, d);
+    const double *M = I.R;
+    const double px = o.x - I.t[0], py = o.y - I.t[1], pz = o.z - I.t[2];
+    oo = mk(M[0] * px + M[3] * py + M[6] * pz, M[1] * px + M[4] * py + M[7] * pz, M[2] * px + M[5] * py + M[8] * pz);
+    dd = mk(M[0] * d.x + M[3] * d.y + M[6] * d.z, M[1] * d.x + M[4] * d.y + M[7] * d.z,
+            M[2] * d.x + M[5] * d.y + M[8] * d.z);
   }
 }
 
@@ -421,29 +364,97 @@ __device__ __forceinline__ int inst_of(const SceneView &S, int pos) {
   return ii;
 }
 
+// Exact key of a buffer entry for the world ray (o, d): the same plane_t of
+// the same object-space ray that produced it when it was inserted.
+__device__ __forceinline__ double entry_t(const SceneView &S, uint32_t id, d3 o, d3 d) {
+  const int pos = (int)(id & kIdMask);
+  d3 oo, dd;
+  to_object(S.inst[inst_of(S, pos)], o, d, oo, dd);
+  const TraceRec &r = S.rec[pos];
+  return plane_t(r, oo, plane_den(r, dd));
+}
+
+// Inserts a hit whose binary32 key equals a key already in the buffer.  The
+// buffer is kept in exact (t, original index) order, so its position is the
+// number of entries whose binary32 key is smaller plus the number of tied
+// entries whose exact key is smaller.  Walks the buffer by rotation (static
+// register indexing); returns false if the hit falls beyond the k-th.
+template <int K>
+__device__ __forceinline__ bool kinsert_tied(const SceneView &S, KBufF<K> &b, float tf, double t, uint32_t id, d3 o,
+                                          d3 d) {
+  const int32_t orig = S.rec[id & kIdMask].orig;
+  int p = 0;
+#pragma unroll 1
+  for (int r = 0; r < K; ++r) {
+    const float bt = b.t[0];
+    if (bt < tf) {
+      ++p;
+    } else if (bt == tf) {
+      const double te = entry_t(S, b.id[0], o, d);
+      if (te < t || (te == t && S.rec[b.id[0] & kIdMask].orig < orig)) ++p;
+    }
+    krotl<KBufF<K>, K>(b);
+  }
+  if (p >= K) return false;
+#pragma unroll
+  for (int j = K - 1; j >= 0; --j) {
+    const int jm = j > 0 ? j - 1 : 0;
+    b.t[j] = j > p ? b.t[jm] : (j == p ? tf : b.t[j]);
+    b.id[j] = j > p ? b.id[jm] : (j == p ? id : b.id[j]);
+  }
+  return true;
+}
+
+// Tests the surfel at leaf position pos against the object-space ray
+// (o, d) of the world ray (wo, wd) and inserts a valid hit that belongs to the
+// k closest.  Binary32 keys are roundings of the exact distances and rounding
+// is monotone, so a key above the k-th key is beyond the exact k-th distance
+// and distinct keys order exactly; a key equal to one in the buffer is placed
+// by exact keys.  Returns bit 0: inserted, bit 1: placed by exact keys.
+template <int K>
+__device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3 d, const RayF &rf, double t_min,
+                                           float t_min_f, KBufF<K> &kb, d3 wo, d3 wd) {
+  const float tk = kb.t[K - 1];
+  const float tk_up = tk < INFINITY ? next_up_f(tk) : INFINITY;
+  if (!prefilter(S.filt[pos], rf, t_min_f, tk_up)) return 0;
+  double t;
+  bool flip;
+  if (!exact_hit(S.rec[pos], o, d, t_min, t, flip)) return 0;
+  const float tf = (float)t;
+  if (tf > tk) return 0;
+  const uint32_t id = (uint32_t)pos | (flip ? kFlipBit : 0u);
+  bool tie = false;
+#pragma unroll
+  for (int j = 0; j < K; ++j) tie |= kb.t[j] == tf;
+  if (!tie) {
+    kinsert<K>(kb, tf, id);
+    return 1;
+  }
+  return kinsert_tied<K>(S, kb, tf, t, id, wo, wd) ? 3 : 2;
+}
+
+
+
 template <int K>
 __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K - 1]; }
-template <int K>
-__device__ __forceinline__ double kth(const KBufD<K> &b) { return b.t[K - 1]; }
 
 // Collects the k closest valid hits of the world ray (o, d) over all
 // instances into kb.  stk points at this lane's first LDS stack slot (stride
-// kBlock).  t_bound, if finite, is an upper bound of the exact k-th distance
-// (from an earlier trace of the same ray): everything beyond it is pruned.
+// kBlock).
 template <int K, class B>
 __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &kb, int *stk, uint32_t *status,
-                      int counter_base = 0, double t_bound = INFINITY) {
+                      int counter_base = 0) {
   kinit<K>(kb, P.k);
   const bool brute = (P.flags & LF_FLAG_BRUTE_FORCE) != 0;
   const float t_min_f = round_down_f(P.t_min);
-  uint32_t c_nodes = 0, c_tests = 0, c_ins = 0;
+  uint32_t c_nodes = 0, c_tests = 0, c_ins = 0, c_ties = 0;
   for (int ii = 0; ii < S.n_inst; ++ii) {
     const InstRec &I = S.inst[ii];
     if (I.n <= 0) continue;
     double itn, itf;
     if (!slab64(o, d, I.lo, I.hi, itn, itf)) continue;
     if (itf < P.t_min) continue;
-    if (itn > fmin(kth<K>(kb), t_bound) * (1.0 + 1e-6)) continue;
+    if (itn > kth<K>(kb) * (1.0 + 1e-6)) continue;
     d3 oo, dd;
     to_object(I, o, d, oo, dd);
     RayF rf;
@@ -451,7 +462,9 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
     if (brute) {
       const int end = I.first + I.n <= S.n_rec ? I.first + I.n : S.n_rec;
       for (int pos = I.first < 0 ? 0 : I.first; pos < end; ++pos) {
-        c_ins += test_surfel<K>(S, pos, oo, dd, rf, P.t_min, t_min_f, kb, t_bound);
+        const int r = test_surfel<K>(S, pos, oo, dd, rf, P.t_min, t_min_f, kb, o, d);
+        c_ins += r & 1;
+        c_ties += r >> 1;
         ++c_tests;
       }
       continue;
@@ -479,7 +492,7 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
         const float4 lx = *(const float4 *)nd.lox, ly = *(const float4 *)nd.loy, lz = *(const float4 *)nd.loz;
         const float4 hx = *(const float4 *)nd.hix, hy = *(const float4 *)nd.hiy, hz = *(const float4 *)nd.hiz;
         const int4 ch = *(const int4 *)nd.child;
-        const double tk = fmin(kth<K>(kb), t_bound);
+        const double tk = kth<K>(kb);
         const float thi = tk < INFINITY ? round_up_f(tk) * (1.0f + 1e-6f) : INFINITY;
         float t0, t1, t2, t3;
         child_test4(rf, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tlo, thi, t0);
@@ -531,7 +544,9 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
           cur = kDone;
           break;
         }
-        c_ins += test_surfel<K>(S, ~leaf, oo, dd, rf, P.t_min, t_min_f, kb, t_bound);
+        const int r = test_surfel<K>(S, ~leaf, oo, dd, rf, P.t_min, t_min_f, kb, o, d);
+        c_ins += r & 1;
+        c_ties += r >> 1;
         ++c_tests;
       }
     }
@@ -541,6 +556,7 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
     atomicAdd(P.counters + counter_base + 1, (unsigned long long)c_nodes);
     atomicAdd(P.counters + counter_base + 2, (unsigned long long)c_tests);
     atomicAdd(P.counters + counter_base + 3, (unsigned long long)c_ins);
+    atomicAdd(P.counters + 8 + counter_base / 4, (unsigned long long)c_ties);
   }
 }
 
@@ -593,7 +609,7 @@ __device__ __forceinline__ void hit_exact(const SceneView &S, const TraceParams 
   to_object(I, o, d, oo, dd);
   d3 n = mk(r.n[0], r.n[1], r.n[2]);
   d3 mu = mk((double)r.mu[0], (double)r.mu[1], (double)r.mu[2]);
-  h.t = dot(n, mu - oo) / dot(n, dd);
+  h.t = plane_t(r, oo, plane_den(r, dd));
   d3 dl = (oo + h.t * dd) - mu;
   double xu = dl.x * r.a[0] + dl.y * r.a[1] + dl.z * r.a[2];
   double xv = dl.x * r.b[0] + dl.y * r.b[1] + dl.z * r.b[2];
@@ -907,22 +923,6 @@ __device__ __forceinline__ void wave_append(bool live, const T &e, T *queue, uin
     uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
     queue[base + (uint32_t)__popcll(mask & lt)] = e;
   }
-}
-
-// Queues a ray whose binary32 keys collided for the exact re-trace.
-template <int K>
-__device__ __forceinline__ void queue_retry(bool again, int32_t id, const KBufF<K> &kb, RetryEnt *retry,
-                                            uint32_t *count, unsigned long long *counter) {
-  RetryEnt e;
-  e.id = id;
-  e.tk = kb.t[K - 1];
-  wave_append<RetryEnt>(again, e, retry, count);
-  if (counter && again) atomicAdd(counter, 1ull);
-}
-
-// Upper bound of the exact k-th distance of a queued retry.
-__device__ __forceinline__ double retry_bound(const RetryEnt &e) {
-  return e.tk < INFINITY ? (double)next_up_f(e.tk) : INFINITY;
 }
 
 }  // namespace lf

@@ -62,7 +62,7 @@ struct lf_ctx {
   int64_t n_nodes4 = 0;
   // per call
   lfh::DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;
-  lfh::DevBuf queue, qcount, contrib, frozen, l1acc, cams, rec1, rec2, retry, rcount, seeds;
+  lfh::DevBuf queue, qcount, contrib, frozen, l1acc, cams, rec1, rec2, seeds;
   lfh::DevBuf bounds, skeys, skeys2, svals, svals2, shist;
   lf::CamArgs h_cams{};
   // ray counters since the last lf_stats_get

@@ -119,15 +119,6 @@ struct RaySource {
   const CamArgs *cams;    // device copy of the cameras
 };
 
-// Ray whose binary32 keys collided, queued for an exact re-trace, with the
-// k-th binary32 key of its first trace.  Round-to-nearest is monotone, so
-// that key is the rounding of the exact k-th distance, and its successor
-// bounds the exact k-th distance from above.
-struct RetryEnt {
-  int32_t id;   // ray (primary) or queue index (secondary)
-  float tk;     // k-th binary32 key, +inf if fewer than k hits
-};
-
 // Secondary ray queued by the primary pass (one per live sample).
 struct alignas(16) SecEntry {
   double o[3];

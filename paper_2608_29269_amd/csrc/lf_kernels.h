@@ -68,8 +68,6 @@ struct RenderArgs {
   SecEntry *queue;      // [R*S]
   uint32_t *queue_count;
   const int32_t *order; // [R*S] trace order of the queue (sorted for coherence), or NULL
-  RetryEnt *retry;      // [max(R, R*S)] rays / queue entries re-traced with exact keys
-  uint32_t *retry_count;
   float *contrib;       // [R*S*3]
   SecFrozen *frozen;    // [R*S] (backward replay)
   AdjSeed *seeds;       // [R] (backward)
@@ -80,13 +78,11 @@ struct RenderArgs {
   const ChunkDesc *chunks;
   const BatchSlot *slots;
 };
-// Parts of a traversal launch: 1 = fast keys (collisions queued for retry), 2 = exact re-trace.
-constexpr int kPartFast = 1, kPartExact = 2, kPartBoth = 3;
-// primary: traversal + compositing (fast keys, then exact re-trace of collisions), then shading
-void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st, int part = kPartBoth);
+// primary: traversal + compositing, then shading
+void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st);
 void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st);
 // secondary: traversal + compositing of the queue, then the two environment samples
-void launch_trace2(const RenderArgs &a, hipStream_t st, int part = kPartBoth);
+void launch_trace2(const RenderArgs &a, hipStream_t st);
 void launch_shade2(const RenderArgs &a, bool replay, hipStream_t st);
 void launch_resolve(const RenderArgs &a, hipStream_t st);
 void launch_accum(unsigned long long *acc, const uint32_t *count, hipStream_t st);
@@ -101,7 +97,7 @@ struct GradArgs {
 };
 // shading adjoint (env gradients, compositing seeds) then traversal + compositing adjoint
 void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st);
-void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st, int part = kPartBoth);
+void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st);
 
 inline int kbucket(int k) { return k <= 8 ? 8 : (k <= 16 ? 16 : (k <= 32 ? 32 : 64)); }
 

@@ -276,7 +276,6 @@ __device__ __forceinline__ void finish_primary(const RenderArgs &a, const SceneV
   if (a.hit_idx) write_hits<K>(S, kb, a.P.k, a.hit_idx + ray * a.P.k);
 }
 
-// fast keys; rays whose binary32 keys collide are appended to the retry list
 template <int K, bool B>
 __global__ __launch_bounds__(kBlock) void k_trace1(RenderArgs a, bool replay) {
   __shared__ int stk[kStack * kBlock];
@@ -289,29 +288,8 @@ __global__ __launch_bounds__(kBlock) void k_trace1(RenderArgs a, bool replay) {
   if (active) req_ray<B>(a, ray, v, of, df);
   const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
   KBufF<K> kb;
-  kb.collide = false;
-  if (active) trace<K>(S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
-  const bool again = active && kb.collide;
-  queue_retry<K>(again, (int32_t)ray, kb, a.retry, a.retry_count, a.P.counters ? a.P.counters + 8 : nullptr);
-  if (active && !again) finish_primary<K>(a, S, v, replay, ray, kb, o, d);
-}
-
-// exact keys for the retried rays
-template <int K, bool B>
-__global__ __launch_bounds__(kBlock) void k_trace1_exact(RenderArgs a, bool replay) {
-  __shared__ int stk[kStack * kBlock];
-  const uint32_t cnt = *a.retry_count;
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
-    const RetryEnt re = a.retry[i];
-    const int64_t ray = re.id;
-    const ReqView v = req_view<B>(a, ray);
-    SceneView S = a.S;
-    S.inst = v.inst;
-    float of[3], df[3];
-    req_ray<B>(a, ray, v, of, df);
-    const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
-    KBufD<K> kb;
-    trace<K>(S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0, retry_bound(re));
+  if (active) {
+    trace<K>(S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
     finish_primary<K>(a, S, v, replay, ray, kb, o, d);
   }
 }
@@ -417,26 +395,8 @@ __global__ __launch_bounds__(kBlock) void k_trace2(RenderArgs a) {
   SceneView S = a.S;
   if constexpr (B) S.inst = a.slots[a.chunks[e.ray / kChunk].slot].inst;
   KBufF<K> kb;
-  kb.collide = false;
-  if (active) trace<K>(S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4);
-  const bool again = active && kb.collide;
-  queue_retry<K>(again, (int32_t)qi, kb, a.retry, a.retry_count, a.P.counters ? a.P.counters + 9 : nullptr);
-  if (active && !again) finish_secondary<K>(a, S, qi, e, kb, o, w);
-}
-
-template <int K, bool B>
-__global__ __launch_bounds__(kBlock) void k_trace2_exact(RenderArgs a) {
-  __shared__ int stk[kStack * kBlock];
-  const uint32_t cnt = *a.retry_count;
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
-    const RetryEnt re = a.retry[i];
-    const uint32_t qi = (uint32_t)re.id;
-    const SecEntry e = a.queue[qi];
-    const d3 o = mk(e.o[0], e.o[1], e.o[2]), w = mk(e.w[0], e.w[1], e.w[2]);
-    SceneView S = a.S;
-    if constexpr (B) S.inst = a.slots[a.chunks[e.ray / kChunk].slot].inst;
-    KBufD<K> kb;
-    trace<K>(S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4, retry_bound(re));
+  if (active) {
+    trace<K>(S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4);
     finish_secondary<K>(a, S, qi, e, kb, o, w);
   }
 }
@@ -528,42 +488,31 @@ __global__ void k_accum(unsigned long long *acc, const uint32_t *count) { *acc +
 __global__ void k_l1_final(const double *acc, int64_t n, float *loss) { *loss = (float)(*acc / (double)n); }
 __global__ void k_zero_f64(double *p) { *p = 0.0; }
 
-constexpr unsigned kExactBlocks = 512;
-
 template <int K, bool B>
-void trace1_k(const RenderArgs &a, bool replay, int part, hipStream_t st) {
-  if (part & kPartFast) {
-    launch_fill_u32(a.retry_count, 0u, 1, st);
-    hipLaunchKernelGGL((k_trace1<K, B>), dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, replay);
-  }
-  if (part & kPartExact)
-    hipLaunchKernelGGL((k_trace1_exact<K, B>), dim3(kExactBlocks), dim3(kBlock), 0, st, a, replay);
+void trace1_k(const RenderArgs &a, bool replay, hipStream_t st) {
+  hipLaunchKernelGGL((k_trace1<K, B>), dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, replay);
 }
 template <int K, bool B>
-void trace2_k(const RenderArgs &a, int part, hipStream_t st) {
-  if (part & kPartFast) {
-    launch_fill_u32(a.retry_count, 0u, 1, st);
-    const int64_t cap = a.R * a.spp_stride;
-    hipLaunchKernelGGL((k_trace2<K, B>), dim3(blocks(cap, kBlock)), dim3(kBlock), 0, st, a);
-  }
-  if (part & kPartExact) hipLaunchKernelGGL((k_trace2_exact<K, B>), dim3(kExactBlocks), dim3(kBlock), 0, st, a);
+void trace2_k(const RenderArgs &a, hipStream_t st) {
+  const int64_t cap = a.R * a.spp_stride;
+  hipLaunchKernelGGL((k_trace2<K, B>), dim3(blocks(cap, kBlock)), dim3(kBlock), 0, st, a);
 }
 template <bool B>
-void trace1_b(const RenderArgs &a, bool replay, int part, hipStream_t st) {
+void trace1_b(const RenderArgs &a, bool replay, hipStream_t st) {
   switch (kbucket(a.P.k)) {
-    case 8: trace1_k<8, B>(a, replay, part, st); break;
-    case 16: trace1_k<16, B>(a, replay, part, st); break;
-    case 32: trace1_k<32, B>(a, replay, part, st); break;
-    default: trace1_k<64, B>(a, replay, part, st); break;
+    case 8: trace1_k<8, B>(a, replay, st); break;
+    case 16: trace1_k<16, B>(a, replay, st); break;
+    case 32: trace1_k<32, B>(a, replay, st); break;
+    default: trace1_k<64, B>(a, replay, st); break;
   }
 }
 template <bool B>
-void trace2_b(const RenderArgs &a, int part, hipStream_t st) {
+void trace2_b(const RenderArgs &a, hipStream_t st) {
   switch (kbucket(a.P.k)) {
-    case 8: trace2_k<8, B>(a, part, st); break;
-    case 16: trace2_k<16, B>(a, part, st); break;
-    case 32: trace2_k<32, B>(a, part, st); break;
-    default: trace2_k<64, B>(a, part, st); break;
+    case 8: trace2_k<8, B>(a, st); break;
+    case 16: trace2_k<16, B>(a, st); break;
+    case 32: trace2_k<32, B>(a, st); break;
+    default: trace2_k<64, B>(a, st); break;
   }
 }
 
@@ -590,10 +539,10 @@ void launch_env_tables(const float *tex, int H, int W, uint32_t flags, double *c
   hipLaunchKernelGGL(k_env_marginal, dim3(1), dim3(256), 0, st, H, flags, roww, cdf_row, scal);
 }
 
-void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st, int part) {
+void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st) {
   if (a.R <= 0) return;
-  if (a.chunks) trace1_b<true>(a, replay, part, st);
-  else trace1_b<false>(a, replay, part, st);
+  if (a.chunks) trace1_b<true>(a, replay, st);
+  else trace1_b<false>(a, replay, st);
 }
 
 void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st) {
@@ -602,10 +551,10 @@ void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st) {
   else hipLaunchKernelGGL(k_shade1<false>, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, replay);
 }
 
-void launch_trace2(const RenderArgs &a, hipStream_t st, int part) {
+void launch_trace2(const RenderArgs &a, hipStream_t st) {
   if (a.R <= 0) return;
-  if (a.chunks) trace2_b<true>(a, part, st);
-  else trace2_b<false>(a, part, st);
+  if (a.chunks) trace2_b<true>(a, st);
+  else trace2_b<false>(a, st);
 }
 
 void launch_shade2(const RenderArgs &a, bool replay, hipStream_t st) {

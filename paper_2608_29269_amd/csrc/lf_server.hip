@@ -65,7 +65,7 @@ struct Lane {
   int64_t primaries = 0;
   lf::ChunkDesc *h_chunks = nullptr;  // pinned
   IterReadback *h_rb = nullptr;       // pinned
-  DevBuf d_chunks, rec1, rec2, queue, qcount, retry, rcount, contrib, skeys, skeys2, svals, svals2, shist, status;
+  DevBuf d_chunks, rec1, rec2, queue, qcount, contrib, skeys, skeys2, svals, svals2, shist, status;
 };
 
 }  // namespace
@@ -220,8 +220,6 @@ bool launch_pass(lf_server *s, Lane &L, const std::vector<lf::SchedTile> &tiles)
   a.rec2 = L.rec2.as<lf::SurfRec>();
   a.queue = L.queue.as<lf::SecEntry>();
   a.queue_count = L.qcount.as<uint32_t>();
-  a.retry = L.retry.as<lf::RetryEnt>();
-  a.retry_count = L.rcount.as<uint32_t>();
   a.contrib = L.contrib.as<float>();
   a.status = L.status.as<uint32_t>();
   const bool sorted = !(s->cfg.params.flags & LF_FLAG_UNSORTED);
@@ -485,7 +483,7 @@ lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **o
          hipHostMalloc((void **)&L.h_rb, sizeof(IterReadback), hipHostMallocDefault) == hipSuccess &&
          L.d_chunks.ensure(sizeof(lf::ChunkDesc) * s->max_chunks) && L.rec1.ensure(sizeof(lf::SurfRec) * B) &&
          L.rec2.ensure(sizeof(lf::SurfRec) * BS) && L.queue.ensure(sizeof(lf::SecEntry) * BS) &&
-         L.qcount.ensure(4) && L.retry.ensure(sizeof(lf::RetryEnt) * BS) && L.rcount.ensure(4) &&
+         L.qcount.ensure(4) &&
          L.contrib.ensure(sizeof(float) * 3 * BS) && L.skeys.ensure(8 * BS) && L.skeys2.ensure(8 * BS) &&
          L.svals.ensure(4 * BS) && L.svals2.ensure(4 * BS) && L.shist.ensure(4 * lf::radix_sort_hist_words(BS)) &&
          L.status.ensure(4);
