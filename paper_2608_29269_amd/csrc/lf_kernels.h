@@ -46,7 +46,8 @@ void launch_fill_f32(float *p, float v, int64_t n, hipStream_t st);
 void launch_instances(const float *R, const float *t, const float *root_box6, const int32_t *inst_first,
                       const int32_t *inst_n, const int32_t *inst_root, int n_inst, InstRec *out, double *bounds6,
                       uint32_t *status, hipStream_t st);
-// sort keys of the secondary queue: (direction octant, origin Morton code); entries past the count sort last
+// sort keys of the secondary queue: (direction octant and octahedral cell, origin Morton code); entries past the
+// count sort last
 void launch_secondary_keys(const SecEntry *queue, const uint32_t *count, int64_t cap, const double *bounds6,
                            const ChunkDesc *chunks, const BatchSlot *slots, uint64_t *keys, int32_t *vals,
                            hipStream_t st);
