@@ -115,6 +115,7 @@ lf_status camera_args(lf_ctx *c, const lf_camera &cm, lf::CamArgs &ca) {
   ca.w[i] = cm.w;
   ca.h[i] = cm.h;
   ca.first[i + 1] = ca.first[i] + (int64_t)cm.w * cm.h;
+  ca.tiles[i + 1] = ca.tiles[i] + (int64_t)((cm.w + 15) / 16) * ((cm.h + 7) / 8);
   ca.n_cams = i + 1;
   return LF_OK;
 }
@@ -191,6 +192,7 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
     for (int i = 0; i < n_cams; ++i)
       if ((st = lfh::camera_args(c, cams[i], ca))) return fail(c, st, "camera %d: %s", i, c->err.c_str());
     R = ca.first[n_cams];
+    a.n_tiles = ca.tiles[n_cams];
     if (!c->cams.ensure(sizeof(lf::CamArgs))) return fail(c, LF_ENOMEM, "cameras");
     if (hipMemcpyAsync(c->cams.p, &ca, sizeof ca, hipMemcpyHostToDevice, c->stream) != hipSuccess)
       return check_hip(c, "camera upload");

@@ -238,8 +238,8 @@ __device__ void adjoint_hits(const RenderArgs &a, const GradArgs &G, const AdjSe
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_adj_trace(RenderArgs a, GradArgs G) {
   __shared__ int stk[kStack * kBlock];
-  const int64_t ray = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  bool active = ray < a.R;
+  const int64_t ray = a.n_tiles ? tile_ray(*a.rays.cams) : (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool active = ray >= 0 && ray < a.R;
   AdjSeed sd = {};
   if (active) {
     sd = a.seeds[ray];
@@ -257,7 +257,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_trace(RenderArgs a, GradArgs G) 
 
 template <int K>
 void adjoint_k(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_trace<K>, dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, g);
+  const unsigned nb = a.n_tiles ? (unsigned)a.n_tiles : blocks(a.R, kBlock);
+  hipLaunchKernelGGL(k_adj_trace<K>, dim3(nb), dim3(kBlock), 0, st, a, g);
 }
 
 }  // namespace

@@ -119,6 +119,21 @@ __device__ __forceinline__ void load_ray(const RaySource &rs, int64_t id, float 
   }
 }
 
+// Camera ray of this thread in a primary traversal launch over 16x8-pixel
+// tiles (one per 128-thread block; each wave64 covers an 8x8 half, so a
+// wave's rays are spatially compact).  -1 for a thread outside the image.
+__device__ __forceinline__ int64_t tile_ray(const CamArgs &ca) {
+  int c = 0;
+  while (c + 1 < ca.n_cams && (int64_t)blockIdx.x >= ca.tiles[c + 1]) ++c;
+  const int64_t lt = (int64_t)blockIdx.x - ca.tiles[c];
+  const int nx = (ca.w[c] + 15) / 16;
+  const int tx = (int)(lt % nx), ty = (int)(lt / nx);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x = tx * 16 + wave * 8 + (lane & 7), y = ty * 8 + (lane >> 3);
+  if (x >= ca.w[c] || y >= ca.h[c]) return -1;
+  return ca.first[c] + (int64_t)y * ca.w[c] + x;
+}
+
 // ------------------------------------------------------------------ k-closest buffers
 // Hits are ordered by (t, surfel index).  Entries hold the leaf position of
 // the surfel and a flip bit (stored normal faces away from the ray).  The

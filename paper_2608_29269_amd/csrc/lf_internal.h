@@ -110,6 +110,7 @@ struct CamArgs {
   float tan_half[LF_MAX_CAMERAS];
   int32_t w[LF_MAX_CAMERAS], h[LF_MAX_CAMERAS];
   int64_t first[LF_MAX_CAMERAS + 1];  // ray-id offsets
+  int64_t tiles[LF_MAX_CAMERAS + 1];  // offsets of each camera's 16x8-pixel tiles
   int32_t n_cams;
 };
 

@@ -60,6 +60,7 @@ struct RenderArgs {
   EnvView E;
   RaySource rays;
   int64_t R;
+  int64_t n_tiles;      // camera rays: 16x8-pixel tiles over all cameras (one per block), else 0
   // outputs
   float *radiance, *depth, *normal, *alpha;
   int32_t *hit_idx, *sec_hit_idx;

@@ -292,11 +292,12 @@ __device__ __forceinline__ void finish_primary(const RenderArgs &a, const SceneV
 template <int K, bool B>
 __global__ __launch_bounds__(kBlock) void k_trace1(RenderArgs a, bool replay) {
   __shared__ int stk[kStack * kBlock];
-  const int64_t ray = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const ReqView v = req_view<B>(a, ray);
+  int64_t ray = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (!B && a.n_tiles) ray = tile_ray(*a.rays.cams);
+  const ReqView v = req_view<B>(a, ray < 0 ? 0 : ray);
   SceneView S = a.S;
   S.inst = v.inst;
-  const bool active = v.valid;
+  const bool active = ray >= 0 && v.valid;
   float of[3] = {0, 0, 0}, df[3] = {0, 0, 1};
   if (active) req_ray<B>(a, ray, v, of, df);
   const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
@@ -503,7 +504,8 @@ __global__ void k_zero_f64(double *p) { *p = 0.0; }
 
 template <int K, bool B>
 void trace1_k(const RenderArgs &a, bool replay, hipStream_t st) {
-  hipLaunchKernelGGL((k_trace1<K, B>), dim3(blocks(a.R, kBlock)), dim3(kBlock), 0, st, a, replay);
+  const unsigned nb = (!B && a.n_tiles) ? (unsigned)a.n_tiles : blocks(a.R, kBlock);
+  hipLaunchKernelGGL((k_trace1<K, B>), dim3(nb), dim3(kBlock), 0, st, a, replay);
 }
 template <int K, bool B>
 void trace2_k(const RenderArgs &a, hipStream_t st) {
