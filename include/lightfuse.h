@@ -252,8 +252,9 @@ lf_status lf_profile_read(lf_ctx *ctx, double *ms /*[LF_NUM_PHASES]*/, int64_t *
  * scene editing and relighting; Sec. 1, appearance recomputed after every
  * interaction).  The server renders many such requests at once by
  * continuous batching: every iteration is one batched forward pass (primary
- * trace, shading, secondary trace, shading, resolve) over 128-ray chunks
- * drawn from all admitted requests (policy below), each with its own
+ * trace, shading, secondary trace, shading, resolve) over 128-ray chunks,
+ * each one 16x8-pixel tile of one request's image, drawn from all admitted
+ * requests (policy below), each request with its own
  * transforms, environment, camera, S and seed.  A request's outputs equal
  * those of lf_render with the same inputs bit for bit (ray ids and sampler
  * counters are local to the request).
@@ -281,9 +282,10 @@ typedef struct lf_server lf_server;
 typedef struct {
   int32_t max_slots;        /* requests admitted at once, 1..64 (default 16) */
   int64_t hbm_budget_bytes; /* admission budget of the admitted working sets (default 16 GiB) */
-  int32_t tile_rays;        /* smallest share of primary rays a request gets per iteration;
-                               multiple of 128 (default 65536) */
-  int32_t batch_rays;       /* primary rays per iteration, multiple of 128, >= tile_rays (default 262144) */
+  int32_t tile_rays;        /* smallest share of primary rays a request gets per iteration (round
+                               robin); multiple of 128 (default 65536).  Rays are counted in whole
+                               16x8-pixel tiles of 128 */
+  int32_t batch_rays;       /* primary rays per iteration, multiple of 128, >= tile_rays (default 1048576) */
   int32_t max_spp;          /* largest S a request may ask for, 1..64 (default 4) */
   int32_t max_pending;      /* waiting requests before lf_server_submit returns LF_EBUSY (default 4096) */
   int32_t policy;           /* LF_SCHED_* (default LF_SCHED_SHORTEST_FIRST) */

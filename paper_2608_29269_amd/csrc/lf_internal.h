@@ -162,13 +162,14 @@ static_assert(sizeof(SecFrozen) == 64, "SecFrozen layout");
 
 // ---- continuous batching: several requests share one wavefront pass.
 // The batch is a list of 128-ray chunks; every chunk belongs to one request
-// (its slot) and covers consecutive ray ids of that request.
+// (its slot) and is one 16x8-pixel tile of that request's image (8x8 per
+// wave64), lanes outside the image idle.
 constexpr int kChunk = kBlock;
 
 struct alignas(16) ChunkDesc {
   int32_t slot;    // server slot of the request
-  int32_t n;       // valid rays in the chunk (1..kChunk)
-  int64_t first;   // ray id (within the request) of the chunk's first ray
+  int32_t pad;
+  int64_t tile;    // tile index within the request's image (row-major over 16x8 tiles)
 };
 static_assert(sizeof(ChunkDesc) == 16, "ChunkDesc layout");
 

@@ -241,8 +241,13 @@ __device__ __forceinline__ ReqView req_view(const RenderArgs &a, int64_t ray) {
     const BatchSlot &sl = a.slots[cd.slot];
     v.inst = sl.inst;
     v.radiance = sl.radiance; v.depth = sl.depth; v.normal = sl.normal; v.alpha = sl.alpha;
-    v.local = cd.first + ray % kChunk;
-    v.valid = in && ray % kChunk < cd.n;
+    const int w = sl.cam->w[0], h = sl.cam->h[0];
+    const int nx = (w + 15) / 16;
+    const int lane = (int)(ray % kChunk);
+    const int x = (int)(cd.tile % nx) * 16 + (lane >> 6) * 8 + (lane & 7);
+    const int y = (int)(cd.tile / nx) * 8 + ((lane & 63) >> 3);
+    v.local = (int64_t)y * w + x;
+    v.valid = in && x < w && y < h;
   } else {
     v.inst = a.S.inst;
     v.radiance = a.radiance; v.depth = a.depth; v.normal = a.normal; v.alpha = a.alpha;

@@ -62,7 +62,6 @@ struct Lane {
   hipEvent_t done = nullptr;
   bool busy = false;
   std::vector<lf::SchedTile> tiles;
-  int64_t primaries = 0;
   lf::ChunkDesc *h_chunks = nullptr;  // pinned
   IterReadback *h_rb = nullptr;       // pinned
   DevBuf d_chunks, rec1, rec2, queue, qcount, contrib, skeys, skeys2, svals, svals2, shist, status;
@@ -191,18 +190,18 @@ bool launch_pass(lf_server *s, Lane &L, const std::vector<lf::SchedTile> &tiles)
   lf_ctx *c = s->ctx;
   hipStream_t st = L.stream;
   lf::ChunkDesc *hc = L.h_chunks;
-  int64_t nch = 0, prim = 0;
+  int64_t nch = 0;
   for (const lf::SchedTile &t : tiles) {
     // the slot may have been staged on another lane's stream
     if (hipStreamWaitEvent(st, s->slots[t.slot].staged, 0) != hipSuccess) return false;
+    // scheduled positions are tiles x 128, so every chunk is one whole tile
     for (int64_t r = 0; r < t.n; r += lf::kChunk) {
       if (nch >= s->max_chunks) return false;  // the planner never exceeds the batch size
       hc[nch].slot = t.slot;
-      hc[nch].n = (int32_t)std::min<int64_t>(lf::kChunk, t.n - r);
-      hc[nch].first = t.first + r;
+      hc[nch].pad = 0;
+      hc[nch].tile = (t.first + r) / lf::kChunk;
       ++nch;
     }
-    prim += t.n;
   }
   if (hipMemcpyAsync(L.d_chunks.p, hc, sizeof(lf::ChunkDesc) * nch, hipMemcpyHostToDevice, st) != hipSuccess)
     return false;
@@ -243,7 +242,6 @@ bool launch_pass(lf_server *s, Lane &L, const std::vector<lf::SchedTile> &tiles)
   lf::launch_fill_u32(a.status, 0u, 1, st);
   if (hipEventRecord(L.done, st) != hipSuccess) return false;
   L.tiles = tiles;
-  L.primaries = prim;
   L.busy = true;
   return hipGetLastError() == hipSuccess;
 }
@@ -262,7 +260,6 @@ bool retire(lf_server *s, Lane &L) {
   const lf_status st = status_of(rb.status);
   L.busy = false;
   std::lock_guard<std::mutex> lk(s->mu);
-  s->rays_primary += L.primaries;
   s->rays_secondary += rb.secondaries;
   if (st != LF_OK) {
     // a device condition ends every request of the pass
@@ -275,6 +272,7 @@ bool retire(lf_server *s, Lane &L) {
     if (hipMemcpy(&ist, s->slots[done.first].status.p, 4, hipMemcpyDeviceToHost) != hipSuccess) return false;
     const lf_status rs = status_of(ist);
     if (rs != LF_OK) s->err = "degenerate or non-finite object transform";
+    s->rays_primary += s->tickets[done.second].rays;
     finish_ticket(s, done.second, rs, t);
   }
   L.tiles.clear();
@@ -404,7 +402,7 @@ void lf_server_config_default(lf_server_config *cfg) {
   cfg->max_slots = 16;
   cfg->hbm_budget_bytes = (int64_t)16 << 30;
   cfg->tile_rays = 65536;
-  cfg->batch_rays = 262144;
+  cfg->batch_rays = 1048576;
   cfg->max_spp = 4;
   cfg->max_pending = 4096;
   cfg->policy = LF_SCHED_SHORTEST_FIRST;
@@ -526,7 +524,9 @@ lf_status lf_server_submit(lf_server *s, const lf_request *r, uint64_t *ticket) 
   if (s->failed) return s->fail_status;
   if (s->stop) return LF_EBUSY;
   const uint64_t t = s->next_ticket;
-  const lf::Scheduler::Submit res = s->sched.submit(t, (int64_t)cm.w * cm.h, cost, 1 + (int64_t)r->spp);
+  // scheduled in whole 16x8-pixel tiles (128 positions each, lanes outside the image idle)
+  const int64_t positions = (int64_t)((cm.w + 15) / 16) * ((cm.h + 7) / 8) * lf::kChunk;
+  const lf::Scheduler::Submit res = s->sched.submit(t, positions, cost, 1 + (int64_t)r->spp);
   if (res != lf::Scheduler::kOk) {
     s->rejected += 1;
     if (res == lf::Scheduler::kBusy) {

@@ -104,6 +104,6 @@ def test_server_null_paths_and_defaults(lib):
     lib.lf_server_destroy(None)
     cfg = _lib.ServerConfig()
     lib.lf_server_config_default(C.byref(cfg))
-    assert (cfg.max_slots, cfg.tile_rays, cfg.batch_rays, cfg.max_spp) == (16, 65536, 262144, 4)
+    assert (cfg.max_slots, cfg.tile_rays, cfg.batch_rays, cfg.max_spp) == (16, 65536, 1048576, 4)
     assert cfg.hbm_budget_bytes == 16 << 30 and cfg.tile_rays % 128 == 0 and cfg.batch_rays % 128 == 0
     assert cfg.params.k == 32 and cfg.params.alpha_min == 1.0 / 255.0
