@@ -229,8 +229,10 @@ lf_status lf_stats_get(lf_ctx *ctx, lf_render_stats *stats);
  * nodes visited, [2] surfels tested, [3] hits inserted into k-buffers, then
  * [4..7] the same for secondary rays, [8] primary and [9] secondary hits
  * whose binary32 distance key equalled one already held, placed by exact
- * FP64 keys. */
-#define LF_NUM_COUNTERS 10
+ * FP64 keys, [10] primary and [11] secondary surfel tests that passed the
+ * binary32 pre-filter, [12] primary and [13] secondary valid hits found
+ * (support and threshold met, before truncation to k). */
+#define LF_NUM_COUNTERS 14
 lf_status lf_trace_counters(lf_ctx *ctx, uint64_t *counters /*[LF_NUM_COUNTERS]*/);
 
 /* Per-phase device timers.  When enabled, every phase below is bracketed by

@@ -425,7 +425,8 @@ __device__ __forceinline__ bool kinsert_tied(const SceneView &S, KBufF<K> &b, fl
 // k closest.  Binary32 keys are roundings of the exact distances and rounding
 // is monotone, so a key above the k-th key is beyond the exact k-th distance
 // and distinct keys order exactly; a key equal to one in the buffer is placed
-// by exact keys.  Returns bit 0: inserted, bit 1: placed by exact keys.
+// by exact keys.  Returns bit 0: inserted, bit 1: placed by exact keys,
+// bit 2: passed the binary32 pre-filter, bit 3: valid hit.
 template <int K>
 __device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3 d, const RayF &rf, double t_min,
                                            float t_min_f, KBufF<K> &kb, d3 wo, d3 wd) {
@@ -434,18 +435,18 @@ __device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3
   if (!prefilter(S.filt[pos], rf, t_min_f, tk_up)) return 0;
   double t;
   bool flip;
-  if (!exact_hit(S.rec[pos], o, d, t_min, t, flip)) return 0;
+  if (!exact_hit(S.rec[pos], o, d, t_min, t, flip)) return 4;
   const float tf = (float)t;
-  if (tf > tk) return 0;
+  if (tf > tk) return 12;
   const uint32_t id = (uint32_t)pos | (flip ? kFlipBit : 0u);
   bool tie = false;
 #pragma unroll
   for (int j = 0; j < K; ++j) tie |= kb.t[j] == tf;
   if (!tie) {
     kinsert<K>(kb, tf, id);
-    return 1;
+    return 13;
   }
-  return kinsert_tied<K>(S, kb, tf, t, id, wo, wd) ? 3 : 2;
+  return kinsert_tied<K>(S, kb, tf, t, id, wo, wd) ? 15 : 14;
 }
 
 
@@ -462,7 +463,7 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
   kinit<K>(kb, P.k);
   const bool brute = (P.flags & LF_FLAG_BRUTE_FORCE) != 0;
   const float t_min_f = round_down_f(P.t_min);
-  uint32_t c_nodes = 0, c_tests = 0, c_ins = 0, c_ties = 0;
+  uint32_t c_nodes = 0, c_tests = 0, c_ins = 0, c_ties = 0, c_pass = 0, c_hits = 0;
   for (int ii = 0; ii < S.n_inst; ++ii) {
     const InstRec &I = S.inst[ii];
     if (I.n <= 0) continue;
@@ -479,7 +480,9 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
       for (int pos = I.first < 0 ? 0 : I.first; pos < end; ++pos) {
         const int r = test_surfel<K>(S, pos, oo, dd, rf, P.t_min, t_min_f, kb, o, d);
         c_ins += r & 1;
-        c_ties += r >> 1;
+        c_ties += (r >> 1) & 1;
+        c_pass += (r >> 2) & 1;
+        c_hits += r >> 3;
         ++c_tests;
       }
       continue;
@@ -561,7 +564,9 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
         }
         const int r = test_surfel<K>(S, ~leaf, oo, dd, rf, P.t_min, t_min_f, kb, o, d);
         c_ins += r & 1;
-        c_ties += r >> 1;
+        c_ties += (r >> 1) & 1;
+        c_pass += (r >> 2) & 1;
+        c_hits += r >> 3;
         ++c_tests;
       }
     }
@@ -572,6 +577,8 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
     atomicAdd(P.counters + counter_base + 2, (unsigned long long)c_tests);
     atomicAdd(P.counters + counter_base + 3, (unsigned long long)c_ins);
     atomicAdd(P.counters + 8 + counter_base / 4, (unsigned long long)c_ties);
+    atomicAdd(P.counters + 10 + counter_base / 4, (unsigned long long)c_pass);
+    atomicAdd(P.counters + 12 + counter_base / 4, (unsigned long long)c_hits);
   }
 }
 
