@@ -68,8 +68,10 @@ typedef struct {
 
 /* Retains the scene pointers and builds one bounding-volume hierarchy per
  * instance (background and each object, in object space): per-surfel trace
- * records, Morton codes, radix sort and a linear BVH (Karras 2012), then the
- * bounds.  LF_EUNSUPPORTED if a hierarchy is deeper than the traversal stack. */
+ * records, size-extended Morton codes, radix sort, a binary hierarchy by
+ * parallel locally-ordered clustering of the sorted boxes (Meister and
+ * Bittner 2018), then the bounds and 4-wide nodes.  LF_EUNSUPPORTED if a
+ * hierarchy is deeper than the traversal stack. */
 lf_status lf_scene_set(lf_ctx *ctx, const lf_surfels *surfels);
 /* Recomputes trace records and bounds bottom-up after in-place updates of the
  * retained arrays (same n, same object ranges); the hierarchy is kept. */

@@ -402,9 +402,18 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
                     n_inst, n, c->keys.as<uint64_t>(), c->perm.as<int32_t>(), st);
   lf::radix_sort(c->keys.as<uint64_t>(), c->perm.as<int32_t>(), c->keys2.as<uint64_t>(), c->vals2.as<int32_t>(),
                  c->hist.as<uint32_t>(), n, st);
-  for (int i = 0; i < n_inst; ++i)
-    lf::launch_karras(c->keys.as<uint64_t>(), c->h_first[i], c->h_n[i], c->h_node_off[i], i, c->nodes.as<lf::BNode>(),
-                      c->node_parent.as<int32_t>(), c->leaf_parent.as<int32_t>(), c->status.as<uint32_t>(), st);
+  // hierarchy of every instance by locally-ordered clustering of the sorted boxes
+  if (!c->ploc_i.ensure(sizeof(int32_t) * 5 * n) || !c->ploc_f.ensure(sizeof(float) * 12 * n))
+    return fail(c, LF_ENOMEM, "clustering scratch for n=%lld", (long long)n);
+  int32_t *pi = c->ploc_i.as<int32_t>();
+  float *pf = c->ploc_f.as<float>();
+  for (int i = 0; i < n_inst; ++i) {
+    if (c->h_n[i] < 1) continue;
+    if (!lf::launch_ploc(c->perm.as<int32_t>(), c->boxidx.as<float>(), c->h_first[i], c->h_n[i], c->h_node_off[i], i,
+                         c->nodes.as<lf::BNode>(), c->node_parent.as<int32_t>(), c->leaf_parent.as<int32_t>(), pi,
+                         pi + n, pf, pf + 6 * n, pi + 2 * n, (uint32_t *)(pi + 3 * n), (uint32_t *)(pi + 4 * n), st))
+      return fail(c, LF_EDEVICE, "hierarchy clustering of instance %d failed", i);
+  }
   lf::launch_fill_u32(c->depth.as<uint32_t>(), 0u, 1, st);
   lf::launch_depth(c->leaf_parent.as<int32_t>(), c->node_parent.as<int32_t>(), n, c->n_nodes,
                    c->depth.as<int32_t>(), c->status.as<uint32_t>(), st);

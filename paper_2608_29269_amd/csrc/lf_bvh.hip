@@ -1,6 +1,7 @@
-// lf_bvh.hip -- per-surfel prep, Morton codes, LSD radix sort, linear BVH
-// (Karras 2012, "Maximizing Parallelism in the Construction of BVHs, Octrees,
-// and k-d Trees") and bottom-up refit for gfx950.
+// lf_bvh.hip -- per-surfel prep, size-extended Morton codes, LSD radix sort,
+// hierarchy by parallel locally-ordered clustering (Meister and Bittner 2018,
+// "Parallel Locally-Ordered Clustering for Bounding Volume Hierarchy
+// Construction"), bottom-up refit and the 4-wide collapse, for gfx950.
 //
 // One hierarchy per instance (background and each object, in object space).
 // Leaves hold one surfel; internal nodes store both children's boxes so a
@@ -228,64 +229,121 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, 
   }
 }
 
-// ---------------------------------------------------------------- Karras hierarchy
-__device__ __forceinline__ int delta(const uint64_t *k, int n, int i, int j) {
-  if (j < 0 || j >= n) return -1;
-  uint64_t a = k[i], b = k[j];
-  if (a == b) return 64 + __clz((unsigned)(i ^ j));
-  return __clzll(a ^ b);
+// ---------------------------------------------------------------- PLOC hierarchy
+// Parallel locally-ordered clustering (Meister and Bittner 2018) of one
+// instance's surfels in sorted-key order: every cluster picks, within a
+// window of kPlocR positions on either side, the neighbour whose merged box
+// has the smallest surface area; mutual pairs merge into a new node; the
+// cluster list is compacted in order; repeat until one cluster is left.
+// Node indices count down from the end of the instance's node range, so the
+// last merge (the root) gets its first index.
+constexpr int kPlocR = 16;
+constexpr int kPlocB = 256;
+
+__device__ __forceinline__ float box_area(const float *lo, const float *hi) {
+  const float x = fmaxf(hi[0] - lo[0], 0.f), y = fmaxf(hi[1] - lo[1], 0.f), z = fmaxf(hi[2] - lo[2], 0.f);
+  return x * y + y * z + z * x;
 }
 
-__global__ void k_karras(const uint64_t *keys, int32_t first, int32_t n, int32_t node_off, int32_t inst,
-                         BNode *nodes, int32_t *node_parent, int32_t *leaf_parent, uint32_t *status) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n == 1) {
-    if (i == 0) leaf_parent[first] = -(inst + 2);
-    return;
-  }
-  if (i >= n - 1) return;
-  const uint64_t *k = keys + first;
-  int d = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) >= 0 ? 1 : -1;
-  int dmin = delta(k, n, i, i - d);
-  int lmax = 2;
-  while (delta(k, n, i, i + lmax * d) > dmin) lmax <<= 1;
-  int l = 0;
-  for (int t = lmax >> 1; t >= 1; t >>= 1)
-    if (delta(k, n, i, i + (l + t) * d) > dmin) l += t;
-  int j = i + l * d;
-  int dnode = delta(k, n, i, j);
-  int s = 0, t = l;
-  do {
-    t = (t + 1) >> 1;
-    if (delta(k, n, i, i + (s + t) * d) > dnode) s += t;
-  } while (t > 1);
-  int g = i + s * d + (d < 0 ? -1 : 0);
-  int lo = i < j ? i : j, hi = i < j ? j : i;
-  if (g < 0 || g + 1 > n - 1 || lo < 0 || hi > n - 1) {  // never taken for a consistent split
-    atomicOr(status, kStatusBvhCorrupt);
-    return;
-  }
-  int me = node_off + i;
-  int c0, c1;
-  if (lo == g) {
-    c0 = ~(first + g);
-    leaf_parent[first + g] = (me << 1) | 0;
-  } else {
-    c0 = node_off + g;
-    node_parent[node_off + g] = (me << 1) | 0;
-  }
-  if (hi == g + 1) {
-    c1 = ~(first + g + 1);
-    leaf_parent[first + g + 1] = (me << 1) | 1;
-  } else {
-    c1 = node_off + g + 1;
-    node_parent[node_off + g + 1] = (me << 1) | 1;
-  }
-  nodes[me].c0 = c0;
-  nodes[me].c1 = c1;
-  nodes[me].pad0 = nodes[me].pad1 = 0;
-  if (i == 0) node_parent[me] = -(inst + 2);
+__global__ void k_ploc_init(const int32_t *perm, const float *boxidx, int32_t first, int32_t n, int32_t *cid,
+                            float *cbox) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cid[i] = ~(first + i);
+  const float *b = boxidx + 6 * (int64_t)perm[first + i];
+  for (int k = 0; k < 6; ++k) cbox[6 * i + k] = b[k];
 }
+
+// nearest neighbour by merged surface area, ties by the (lower, higher) index pair
+__global__ __launch_bounds__(kPlocB) void k_ploc_nn(const float *cbox, int m, int32_t *nn) {
+  __shared__ float sb[kPlocB + 2 * kPlocR][6];
+  const int base = blockIdx.x * kPlocB;
+  for (int j = threadIdx.x; j < kPlocB + 2 * kPlocR; j += kPlocB) {
+    const int g = base - kPlocR + j;
+    for (int k = 0; k < 6; ++k) sb[j][k] = (g >= 0 && g < m) ? cbox[6 * g + k] : 0.f;
+  }
+  __syncthreads();
+  const int i = base + threadIdx.x;
+  if (i >= m) return;
+  const float *bi = sb[threadIdx.x + kPlocR];
+  float best = INFINITY;
+  int bj = -1;
+  for (int dd = -kPlocR; dd <= kPlocR; ++dd) {
+    const int j = i + dd;
+    if (dd == 0 || j < 0 || j >= m) continue;
+    const float *bj_ = sb[threadIdx.x + kPlocR + dd];
+    float lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fminf(bi[k], bj_[k]);
+      hi[k] = fmaxf(bi[3 + k], bj_[3 + k]);
+    }
+    const float a = box_area(lo, hi);
+    // with equal areas the pair with the smaller (min, max) index wins, the same on both sides
+    const bool better = a < best || (a == best && bj >= 0 &&
+                                     (min(i, j) < min(i, bj) || (min(i, j) == min(i, bj) && max(i, j) < max(i, bj))));
+    if (bj < 0 || better) {
+      best = a;
+      bj = j;
+    }
+  }
+  nn[i] = bj;
+}
+
+// rem[j] = 1 if j merges into its (lower) mutual nearest neighbour
+__global__ void k_ploc_flags(const int32_t *nn, int m, uint32_t *rem, uint32_t *pre) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const int i = nn[j];
+  const uint32_t r = (i >= 0 && i < j && nn[i] == j) ? 1u : 0u;
+  rem[j] = r;
+  pre[j] = r;
+}
+
+__device__ __forceinline__ void set_parent(int32_t c, int32_t parent_side, int32_t *node_parent, int32_t *leaf_parent) {
+  if (c < 0) leaf_parent[~c] = parent_side;
+  else node_parent[c] = parent_side;
+}
+
+// merges mutual pairs into nodes next_idx - rank and compacts the cluster list
+__global__ void k_ploc_merge(const int32_t *nn, const uint32_t *pre, int m, int32_t next_idx, const int32_t *cid,
+                             const float *cbox, int32_t *cid2, float *cbox2, BNode *nodes, int32_t *node_parent,
+                             int32_t *leaf_parent) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int j = nn[i];
+  const bool mutual = j >= 0 && nn[j] == i;
+  if (mutual && j < i) return;  // merged into j
+  const int p = i - (int)pre[i];
+  if (mutual) {
+    const int32_t idx = next_idx - (int32_t)pre[j];
+    const int32_t a = cid[i], b = cid[j];
+    BNode nd;
+    for (int k = 0; k < 3; ++k) {
+      nd.lo0[k] = cbox[6 * i + k]; nd.hi0[k] = cbox[6 * i + 3 + k];
+      nd.lo1[k] = cbox[6 * j + k]; nd.hi1[k] = cbox[6 * j + 3 + k];
+    }
+    nd.c0 = a;
+    nd.c1 = b;
+    nd.pad0 = nd.pad1 = 0;
+    nodes[idx] = nd;
+    set_parent(a, (idx << 1) | 0, node_parent, leaf_parent);
+    set_parent(b, (idx << 1) | 1, node_parent, leaf_parent);
+    cid2[p] = idx;
+    for (int k = 0; k < 3; ++k) {
+      cbox2[6 * p + k] = fminf(nd.lo0[k], nd.lo1[k]);
+      cbox2[6 * p + 3 + k] = fmaxf(nd.hi0[k], nd.hi1[k]);
+    }
+  } else {
+    cid2[p] = cid[i];
+    for (int k = 0; k < 6; ++k) cbox2[6 * p + k] = cbox[6 * i + k];
+  }
+}
+
+__global__ void k_ploc_root(const int32_t *cid, int32_t inst, int32_t *node_parent) {
+  node_parent[cid[0]] = -(inst + 2);
+}
+
+__global__ void k_leaf_root(int32_t first, int32_t inst, int32_t *leaf_parent) { leaf_parent[first] = -(inst + 2); }
 
 __global__ void k_depth(const int32_t *leaf_parent, const int32_t *node_parent, int64_t n, int64_t n_nodes,
                         int32_t *max_depth, uint32_t *status) {
@@ -465,13 +523,40 @@ void radix_sort(uint64_t *keys, int32_t *vals, uint64_t *keys_tmp, int32_t *vals
   // an even number of passes: the result is back in (keys, vals)
 }
 
-void launch_karras(const uint64_t *keys, int32_t first, int32_t n, int32_t node_off, int32_t inst, BNode *nodes,
-                   int32_t *node_parent, int32_t *leaf_parent, uint32_t *status, hipStream_t st) {
-  if (n <= 0) return;
-  int64_t work = n > 1 ? n - 1 : 1;
-  hipLaunchKernelGGL(k_karras, dim3(blocks(work, 256)), dim3(256), 0, st, keys, first, n, node_off, inst, nodes,
-                     node_parent, leaf_parent, status);
+bool launch_ploc(const int32_t *perm, const float *boxidx, int32_t first, int32_t n, int32_t node_off, int32_t inst,
+                 BNode *nodes, int32_t *node_parent, int32_t *leaf_parent, int32_t *cid, int32_t *cid2, float *cbox,
+                 float *cbox2, int32_t *nn, uint32_t *rem, uint32_t *pre, hipStream_t st) {
+  if (n == 1) {
+    hipLaunchKernelGGL(k_leaf_root, dim3(1), dim3(1), 0, st, first, inst, leaf_parent);
+    return true;
+  }
+  hipLaunchKernelGGL(k_ploc_init, dim3(blocks(n, 256)), dim3(256), 0, st, perm, boxidx, first, n, cid, cbox);
+  int m = n;
+  int32_t next_idx = node_off + n - 2;
+  for (int it = 0; m > 1; ++it) {
+    if (it > 4 * n) return false;  // no progress: never for a consistent clustering
+    hipLaunchKernelGGL(k_ploc_nn, dim3(blocks(m, kPlocB)), dim3(kPlocB), 0, st, cbox, m, nn);
+    hipLaunchKernelGGL(k_ploc_flags, dim3(blocks(m, 256)), dim3(256), 0, st, nn, m, rem, pre);
+    hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, pre, (int64_t)m);
+    hipLaunchKernelGGL(k_ploc_merge, dim3(blocks(m, 256)), dim3(256), 0, st, nn, pre, m, next_idx, cid, cbox, cid2,
+                       cbox2, nodes, node_parent, leaf_parent);
+    uint32_t last_pre = 0, last_rem = 0;
+    if (hipMemcpyAsync(&last_pre, pre + m - 1, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&last_rem, rem + m - 1, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return false;
+    const int merged = (int)(last_pre + last_rem);
+    if (merged <= 0) return false;
+    next_idx -= merged;
+    m -= merged;
+    int32_t *t = cid; cid = cid2; cid2 = t;
+    float *tb = cbox; cbox = cbox2; cbox2 = tb;
+  }
+  if (next_idx != node_off - 1) return false;
+  hipLaunchKernelGGL(k_ploc_root, dim3(1), dim3(1), 0, st, cid, inst, node_parent);
+  return true;
 }
+
 
 void launch_depth(const int32_t *leaf_parent, const int32_t *node_parent, int64_t n, int64_t n_nodes,
                   int32_t *max_depth, uint32_t *status, hipStream_t st) {

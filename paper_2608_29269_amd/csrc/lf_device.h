@@ -510,8 +510,9 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
         const float4 lx = *(const float4 *)nd.lox, ly = *(const float4 *)nd.loy, lz = *(const float4 *)nd.loz;
         const float4 hx = *(const float4 *)nd.hix, hy = *(const float4 *)nd.hiy, hz = *(const float4 *)nd.hiz;
         const int4 ch = *(const int4 *)nd.child;
-        const double tk = kth<K>(kb);
-        const float thi = tk < INFINITY ? round_up_f(tk) * (1.0f + 1e-6f) : INFINITY;
+        // the exact k-th distance is at most the successor of the k-th binary32 key
+        const float tkf = kb.t[K - 1];
+        const float thi = tkf < INFINITY ? next_up_f(tkf) * (1.0f + 1e-6f) : INFINITY;
         float t0, t1, t2, t3;
         child_test4(rf, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tlo, thi, t0);
         child_test4(rf, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tlo, thi, t1);

@@ -58,7 +58,7 @@ struct lf_ctx {
   double built_alpha_min = 0, built_sig2 = 0;
   lfh::DevBuf d_first, d_n, d_root;
   lfh::DevBuf rec, filt, nodes, perm, leaf_parent, node_parent, flags, leafbox, rootbox, inst, status;
-  lfh::DevBuf keys, keys2, vals2, hist, boxidx, ibounds, depth, nodes4, flag4, idx4;
+  lfh::DevBuf keys, keys2, vals2, hist, boxidx, ibounds, depth, nodes4, flag4, idx4, ploc_i, ploc_f;
   int64_t n_nodes4 = 0;
   // per call
   lfh::DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;

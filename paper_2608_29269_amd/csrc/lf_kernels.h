@@ -22,9 +22,11 @@ void launch_morton(const float *box6, const float *inst_bounds, const int32_t *i
 size_t radix_sort_hist_words(int64_t n);
 void radix_sort(uint64_t *keys, int32_t *vals, uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist, int64_t n,
                 hipStream_t st, int key_bits = 64);
-// Karras (2012) hierarchy of one instance
-void launch_karras(const uint64_t *keys, int32_t first, int32_t n, int32_t node_off, int32_t inst, BNode *nodes,
-                   int32_t *node_parent, int32_t *leaf_parent, uint32_t *status, hipStream_t st);
+// PLOC hierarchy of one instance (synchronises the stream once per clustering round); false if it failed.
+// Scratch: cid, cid2, nn, rem, pre [n] and cbox, cbox2 [n,6].
+bool launch_ploc(const int32_t *perm, const float *boxidx, int32_t first, int32_t n, int32_t node_off, int32_t inst,
+                 BNode *nodes, int32_t *node_parent, int32_t *leaf_parent, int32_t *cid, int32_t *cid2, float *cbox,
+                 float *cbox2, int32_t *nn, uint32_t *rem, uint32_t *pre, hipStream_t st);
 // leaf depth maximum into *max_depth (device int)
 void launch_depth(const int32_t *leaf_parent, const int32_t *node_parent, int64_t n, int64_t n_nodes,
                   int32_t *max_depth, uint32_t *status, hipStream_t st);
