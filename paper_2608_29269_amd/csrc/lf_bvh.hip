@@ -237,7 +237,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, 
 // cluster list is compacted in order; repeat until one cluster is left.
 // Node indices count down from the end of the instance's node range, so the
 // last merge (the root) gets its first index.
-constexpr int kPlocR = 16;
+constexpr int kPlocR = 16;  // window radius: 32 measures alike, 8 visits 4% more nodes
 constexpr int kPlocB = 256;
 
 __device__ __forceinline__ float box_area(const float *lo, const float *hi) {
@@ -255,7 +255,7 @@ __global__ void k_ploc_init(const int32_t *perm, const float *boxidx, int32_t fi
 }
 
 // nearest neighbour by merged surface area, ties by the (lower, higher) index pair
-__global__ __launch_bounds__(kPlocB) void k_ploc_nn(const float *cbox, int m, int32_t *nn) {
+__global__ __launch_bounds__(kPlocB) void k_ploc_nn(const float *cbox, int m, int rr, int32_t *nn) {
   __shared__ float sb[kPlocB + 2 * kPlocR][6];
   const int base = blockIdx.x * kPlocB;
   for (int j = threadIdx.x; j < kPlocB + 2 * kPlocR; j += kPlocB) {
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kPlocB) void k_ploc_nn(const float *cbox, int m, in
   const float *bi = sb[threadIdx.x + kPlocR];
   float best = INFINITY;
   int bj = -1;
-  for (int dd = -kPlocR; dd <= kPlocR; ++dd) {
+  for (int dd = -rr; dd <= rr; ++dd) {
     const int j = i + dd;
     if (dd == 0 || j < 0 || j >= m) continue;
     const float *bj_ = sb[threadIdx.x + kPlocR + dd];
@@ -497,7 +497,8 @@ void launch_morton(const float *box6, const float *inst_bounds, const int32_t *i
                    int n_inst, int64_t n, uint64_t *keys, int32_t *vals, hipStream_t st) {
   if (n <= 0) return;
   // one coarse spatial level above the size classes: 21% fewer node visits per ray than plain
-  // Morton order on the 1M-surfel scene (0 and 1 measure alike; deeper placements lose most of it)
+  // Morton order on the 1M-surfel scene (0 and 1 measure alike; deeper placements lose most of it);
+  // the clustering of plain Morton order also builds much deeper trees
   constexpr int kSizeLevel = 1;
   hipLaunchKernelGGL(k_morton, dim3(blocks(n, 256)), dim3(256), 0, st, box6, inst_bounds, inst_first, inst_n, n_inst,
                      n, kSizeLevel, keys, vals);
@@ -535,7 +536,7 @@ bool launch_ploc(const int32_t *perm, const float *boxidx, int32_t first, int32_
   int32_t next_idx = node_off + n - 2;
   for (int it = 0; m > 1; ++it) {
     if (it > 4 * n) return false;  // no progress: never for a consistent clustering
-    hipLaunchKernelGGL(k_ploc_nn, dim3(blocks(m, kPlocB)), dim3(kPlocB), 0, st, cbox, m, nn);
+    hipLaunchKernelGGL(k_ploc_nn, dim3(blocks(m, kPlocB)), dim3(kPlocB), 0, st, cbox, m, kPlocR, nn);
     hipLaunchKernelGGL(k_ploc_flags, dim3(blocks(m, 256)), dim3(256), 0, st, nn, m, rem, pre);
     hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, pre, (int64_t)m);
     hipLaunchKernelGGL(k_ploc_merge, dim3(blocks(m, 256)), dim3(256), 0, st, nn, pre, m, next_idx, cid, cbox, cid2,

@@ -9,7 +9,7 @@
 namespace lf {
 
 constexpr int kBlock = 128;       // threads per block of the tracing kernels (2 wave64)
-constexpr int kStack = 64;        // traversal stack entries per lane (LDS)
+constexpr int kStack = 72;        // traversal stack entries per lane (LDS; 4 blocks of 128 lanes per CU)
 constexpr int kMaxInst = 64;      // background + up to 63 objects
 constexpr uint32_t kFlipBit = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7fffffffu;
