@@ -70,11 +70,15 @@ typedef struct {
  * instance (background and each object, in object space): per-surfel trace
  * records, size-extended Morton codes, radix sort, a binary hierarchy by
  * parallel locally-ordered clustering of the sorted boxes (Meister and
- * Bittner 2018), then the bounds and 4-wide nodes.  LF_EUNSUPPORTED if a
- * hierarchy is deeper than the traversal stack. */
+ * Bittner 2018), cut top-down into traversal nodes of up to eight children
+ * (greedy surface-area collapse) placed depth-first with contiguous
+ * children, surfel records reordered to match, then the bounds and the
+ * traversal nodes with child boxes quantised conservatively to 8 bits per
+ * plane.  LF_EUNSUPPORTED if a hierarchy is deeper than the traversal stack. */
 lf_status lf_scene_set(lf_ctx *ctx, const lf_surfels *surfels);
 /* Recomputes trace records and bounds bottom-up after in-place updates of the
- * retained arrays (same n, same object ranges); the hierarchy is kept. */
+ * retained arrays (same n, same object ranges), and re-quantises the
+ * traversal nodes; the hierarchy is kept. */
 lf_status lf_scene_refit(lf_ctx *ctx);
 
 /* Rigid transform T_{k,o} = (R, t) per object for one state k; it moves only
@@ -205,6 +209,9 @@ typedef struct {
   int64_t n_nodes;      /* internal nodes over all instances */
   int32_t max_depth;    /* deepest leaf (root = depth 0) */
   int32_t stack_size;   /* traversal stack entries per ray */
+  int64_t n_wide_nodes; /* traversal nodes over all instances */
+  int32_t wide_levels;  /* levels of the deepest traversal hierarchy */
+  int32_t node_width;   /* children per traversal node */
 } lf_scene_info;
 lf_status lf_scene_get_info(lf_ctx *ctx, lf_scene_info *info);
 
@@ -215,6 +222,15 @@ lf_status lf_scene_get_info(lf_ctx *ctx, lf_scene_info *info);
  * Any pointer may be NULL. */
 lf_status lf_scene_copy_bvh(lf_ctx *ctx, int32_t inst, float *node_boxes, int32_t *children, int32_t *perm,
                             float *leaf_boxes);
+
+/* Copies instance `inst`'s traversal nodes to host memory, decoded: *n_nodes
+ * receives their count m; if slot_boxes / slot_child are not NULL they must
+ * hold m * node_width * 6 floats / m * node_width ints, filled per node and
+ * slot with the decoded binary32 box (lo xyz, hi xyz; the box traversal
+ * tests) and the child (>= 0 traversal node within the instance, < 0 ~leaf
+ * position within the instance, INT32_MIN for a slot without a child or with
+ * an empty box).  Node 0 is the root. */
+lf_status lf_scene_copy_wide(lf_ctx *ctx, int32_t inst, int64_t *n_nodes, float *slot_boxes, int32_t *slot_child);
 
 /* Rays traced by lf_render calls since the previous lf_stats_get: primary
  * rays and secondary rays actually traced (live samples).  Accumulated on the
@@ -227,7 +243,7 @@ typedef struct {
 lf_status lf_stats_get(lf_ctx *ctx, lf_render_stats *stats);
 
 /* Traversal counters accumulated by calls made with LF_FLAG_COUNT since the
- * previous read (synchronous; resets them): [0] primary rays, [1] 4-wide
+ * previous read (synchronous; resets them): [0] primary rays, [1] traversal
  * nodes visited, [2] surfels tested, [3] hits inserted into k-buffers, then
  * [4..7] the same for secondary rays, [8] primary and [9] secondary hits
  * whose binary32 distance key equalled one already held, placed by exact

@@ -106,7 +106,8 @@ class Tracer:
         i = _lib.SceneInfo()
         self._chk(self.L.lf_scene_get_info(self.ctx, C.byref(i)))
         return dict(n_instances=i.n_instances, n_surfels=i.n_surfels, n_nodes=i.n_nodes, max_depth=i.max_depth,
-                    stack_size=i.stack_size)
+                    stack_size=i.stack_size, n_wide_nodes=i.n_wide_nodes, wide_levels=i.wide_levels,
+                    node_width=i.node_width)
 
     def copy_bvh(self, inst: int):
         import numpy as np
@@ -119,6 +120,17 @@ class Tracer:
         self._chk(self.L.lf_scene_copy_bvh(self.ctx, inst, boxes.ctypes.data, ch.ctypes.data, perm.ctypes.data,
                                            leaf.ctypes.data))
         return boxes, ch, perm, leaf
+
+    def copy_wide(self, inst: int):
+        """Decoded traversal nodes of one instance: slot boxes [m, W, 6] and children [m, W]."""
+        import numpy as np
+        m = C.c_int64(0)
+        self._chk(self.L.lf_scene_copy_wide(self.ctx, inst, C.byref(m), None, None))
+        w = self.info()["node_width"]
+        boxes = np.zeros((m.value, w, 6), np.float32)
+        ch = np.zeros((m.value, w), np.int32)
+        self._chk(self.L.lf_scene_copy_wide(self.ctx, inst, C.byref(m), boxes.ctypes.data, ch.ctypes.data))
+        return boxes, ch
 
     # ------------------------------------------------------------------ calls
     @staticmethod

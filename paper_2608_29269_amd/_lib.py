@@ -76,7 +76,8 @@ class GradIn(C.Structure):
 
 class SceneInfo(C.Structure):
     _fields_ = [("n_instances", C.c_int32), ("n_surfels", C.c_int64), ("n_nodes", C.c_int64),
-                ("max_depth", C.c_int32), ("stack_size", C.c_int32)]
+                ("max_depth", C.c_int32), ("stack_size", C.c_int32), ("n_wide_nodes", C.c_int64),
+                ("wide_levels", C.c_int32), ("node_width", C.c_int32)]
 
 
 class RenderStats(C.Structure):
@@ -122,6 +123,7 @@ SIGNATURES = {
     "lf_raygen": (C.c_int, [C.c_void_p, C.POINTER(Camera), C.c_void_p, C.c_void_p]),
     "lf_scene_get_info": (C.c_int, [C.c_void_p, C.POINTER(SceneInfo)]),
     "lf_scene_copy_bvh": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lf_scene_copy_wide": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
     "lf_stats_get": (C.c_int, [C.c_void_p, C.POINTER(RenderStats)]),
     "lf_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "lf_trace_counters": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),

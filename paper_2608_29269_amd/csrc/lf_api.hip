@@ -84,8 +84,8 @@ lf_status refit_impl(lf_ctx *c, double alpha_min, double sig2) {
                    c->node_parent.as<int32_t>(), c->flags.as<int32_t>(), c->n_nodes, c->n_inst,
                    c->nodes.as<lf::BNode>(), c->rec.as<lf::TraceRec>(), c->filt.as<lf::FiltRec>(),
                    c->leafbox.as<float>(), c->rootbox.as<float>(), c->status.as<uint32_t>(), c->stream);
-  lf::launch_collapse(c->nodes.as<lf::BNode>(), c->flag4.as<uint32_t>(), c->idx4.as<uint32_t>(), c->n_nodes,
-                      c->nodes4.as<lf::BNode4>(), c->status.as<uint32_t>(), c->stream);
+  lf::launch_wide_quantize(c->nodes.as<lf::BNode>(), c->winfo.as<lf::WideInfo>(), c->n_wide, c->n_nodes,
+                           c->qnodes.as<lf::QNode>(), c->status.as<uint32_t>(), c->stream);
   c->built_alpha_min = alpha_min;
   c->built_sig2 = sig2;
   return check_hip(c, "refit");
@@ -123,11 +123,11 @@ lf_status camera_args(lf_ctx *c, const lf_camera &cm, lf::CamArgs &ca) {
 void scene_view(const lf_ctx *c, lf::SceneView &S) {
   S.rec = c->rec.as<lf::TraceRec>();
   S.filt = c->filt.as<lf::FiltRec>();
-  S.nodes = c->nodes4.as<lf::BNode4>();
+  S.nodes = c->qnodes.as<lf::QNode>();
   S.inst = nullptr;
   S.n_inst = c->n_inst;
   S.n_rec = (int32_t)c->s.n;
-  S.n_nodes = (int32_t)c->n_nodes4;
+  S.n_nodes = (int32_t)c->n_wide;
   S.mu = c->s.mu; S.q = c->s.q; S.scale = c->s.scale; S.opacity = c->s.opacity;
   S.albedo = c->s.albedo; S.roughness = c->s.roughness; S.metallic = c->s.metallic;
 }
@@ -385,7 +385,7 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
             c->rootbox.ensure(24 * n_inst) && c->inst.ensure(sizeof(lf::InstRec) * n_inst) &&
             c->keys.ensure(8 * n) && c->keys2.ensure(8 * n) && c->vals2.ensure(4 * n) &&
             c->hist.ensure(4 * lf::radix_sort_hist_words(n)) && c->boxidx.ensure(24 * n) &&
-            c->ibounds.ensure(24 * n_inst) && c->depth.ensure(4);
+            c->ibounds.ensure(24 * n_inst) && c->depth.ensure(8);
   if (!ok) return fail(c, LF_ENOMEM, "scene buffers for n=%lld", (long long)n);
   if (hipMemcpy(c->d_first.p, c->h_first.data(), 4 * n_inst, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_n.p, c->h_n.data(), 4 * n_inst, hipMemcpyHostToDevice) != hipSuccess ||
@@ -414,51 +414,84 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
                          pi + n, pf, pf + 6 * n, pi + 2 * n, (uint32_t *)(pi + 3 * n), (uint32_t *)(pi + 4 * n), st))
       return fail(c, LF_EDEVICE, "hierarchy clustering of instance %d failed", i);
   }
-  lf::launch_fill_u32(c->depth.as<uint32_t>(), 0u, 1, st);
+  lf::launch_fill_u32(c->depth.as<uint32_t>(), 0u, 2, st);
   lf::launch_depth(c->leaf_parent.as<int32_t>(), c->node_parent.as<int32_t>(), n, c->n_nodes,
                    c->depth.as<int32_t>(), c->status.as<uint32_t>(), st);
-  // 4-wide hierarchy: index of every even-depth internal node, roots remapped
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      hipMemcpy(&c->max_depth, c->depth.p, 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return check_hip(c, "hierarchy depth");
+  // Traversal nodes: greedy collapse level by level, subtree counts, then
+  // depth-first placement with contiguous children and the matching leaf order.
   const int64_t nn = nodes ? nodes : 1;
-  if (!c->flag4.ensure(4 * nn) || !c->idx4.ensure(4 * nn)) return fail(c, LF_ENOMEM, "4-wide index");
-  lf::launch_wide_index(c->node_parent.as<int32_t>(), c->n_nodes, c->flag4.as<uint32_t>(), c->idx4.as<uint32_t>(),
-                        c->status.as<uint32_t>(), st);
-  c->n_nodes4 = 0;
-  if (nodes > 0) {
-    uint32_t last_idx = 0, last_flag = 0;
-    if (hipStreamSynchronize(st) != hipSuccess ||
-        hipMemcpy(&last_idx, c->idx4.as<uint32_t>() + nodes - 1, 4, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(&last_flag, c->flag4.as<uint32_t>() + nodes - 1, 4, hipMemcpyDeviceToHost) != hipSuccess)
-      return check_hip(c, "4-wide index");
-    c->n_nodes4 = (int64_t)last_idx + last_flag;
-    std::vector<int32_t> root4(n_inst);
-    for (int i = 0; i < n_inst; ++i) {
-      root4[i] = c->h_root[i];
-      if (c->h_n[i] >= 2) {
-        uint32_t r = 0;
-        if (hipMemcpy(&r, c->idx4.as<uint32_t>() + c->h_root[i], 4, hipMemcpyDeviceToHost) != hipSuccess)
-          return check_hip(c, "4-wide roots");
-        root4[i] = (int32_t)r;
-      }
-    }
-    if (hipMemcpy(c->d_root.p, root4.data(), 4 * n_inst, hipMemcpyHostToDevice) != hipSuccess)
-      return check_hip(c, "4-wide roots");
+  const int W = lf::kWide;
+  if (!c->wtmp.ensure(sizeof(int32_t) * ((10 + W) * nn + n)))
+    return fail(c, LF_ENOMEM, "traversal-node scratch for n=%lld", (long long)n);
+  int32_t *level = c->wtmp.as<int32_t>(), *sub_w = level + nn, *sub_l = sub_w + nn, *widx = sub_l + nn;
+  int32_t *dbase = widx + nn, *lbase = dbase + nn;
+  int2 *side_cnt = (int2 *)(lbase + nn);
+  int32_t *slot_src = (int32_t *)(side_cnt + 2 * nn), *newpos = slot_src + W * nn;
+  int32_t *n_levels_d = c->depth.as<int32_t>() + 1;
+  lf::launch_fill_u32((uint32_t *)level, 0xffffffffu, nn, st);
+  lf::launch_wide_roots(c->d_root.as<int32_t>(), c->d_n.as<int32_t>(), n_inst, level, st);
+  for (int32_t it = 0; it <= c->max_depth && nodes > 0; ++it)
+    lf::launch_wide_level(c->nodes.as<lf::BNode>(), c->n_nodes, it, level, slot_src, n_levels_d,
+                          c->status.as<uint32_t>(), st);
+  lf::launch_wide_count(c->leaf_parent.as<int32_t>(), c->node_parent.as<int32_t>(), level, n, c->n_nodes,
+                        c->flags.as<int32_t>(), side_cnt, sub_w, sub_l, c->status.as<uint32_t>(), st);
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      hipMemcpy(&c->wide_levels, n_levels_d, 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return check_hip(c, "traversal nodes");
+  std::vector<int32_t> roots(3 * n_inst, 0), root4(n_inst);
+  int64_t n_wide = 0;
+  c->h_wide_off.assign(n_inst, 0);
+  c->h_wide_n.assign(n_inst, 0);
+  for (int i = 0; i < n_inst; ++i) {
+    root4[i] = c->h_root[i];
+    c->h_wide_off[i] = n_wide;
+    if (c->h_n[i] < 2) continue;
+    int32_t cnt = 0;
+    if (hipMemcpy(&cnt, sub_w + c->h_root[i], 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return check_hip(c, "traversal nodes");
+    if (cnt < 1 || cnt > c->h_n[i]) return fail(c, LF_EDEVICE, "inconsistent traversal-node count %d", cnt);
+    roots[3 * i] = (int32_t)n_wide;
+    roots[3 * i + 1] = (int32_t)n_wide + 1;
+    roots[3 * i + 2] = c->h_first[i];
+    root4[i] = (int32_t)n_wide;
+    c->h_wide_n[i] = cnt;
+    n_wide += cnt;
   }
-  if (!c->nodes4.ensure(sizeof(lf::BNode4) * (c->n_nodes4 ? c->n_nodes4 : 1)))
-    return fail(c, LF_ENOMEM, "4-wide nodes");
+  c->n_wide = n_wide;
+  if (!c->wroots.ensure(sizeof(int32_t) * 3 * n_inst) || !c->winfo.ensure(sizeof(lf::WideInfo) * (n_wide ? n_wide : 1)) ||
+      !c->qnodes.ensure(sizeof(lf::QNode) * (n_wide ? n_wide : 1)))
+    return fail(c, LF_ENOMEM, "traversal nodes");
+  if (hipMemcpy(c->wroots.p, roots.data(), sizeof(int32_t) * 3 * n_inst, hipMemcpyHostToDevice) != hipSuccess)
+    return check_hip(c, "traversal nodes");
+  lf::launch_wide_root_pos(c->d_root.as<int32_t>(), c->d_n.as<int32_t>(), c->wroots.as<int32_t>(), n_inst, widx, dbase,
+                           lbase, st);
+  lf::launch_iota(newpos, n, st);
+  for (int32_t it = 0; it < c->wide_levels; ++it)
+    lf::launch_wide_assign(c->nodes.as<lf::BNode>(), c->n_nodes, n, it, level, slot_src, sub_w, sub_l, widx, dbase,
+                           lbase, newpos, c->winfo.as<lf::WideInfo>(), n_wide, c->status.as<uint32_t>(), st);
+  lf::launch_leaf_reorder(newpos, c->perm.as<int32_t>(), c->leaf_parent.as<int32_t>(), n, c->n_nodes,
+                          c->vals2.as<int32_t>(), (int32_t *)c->keys2.p, c->nodes.as<lf::BNode>(),
+                          c->status.as<uint32_t>(), st);
+  if (hipMemcpyAsync(c->perm.p, c->vals2.p, 4 * (size_t)n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->leaf_parent.p, c->keys2.p, 4 * (size_t)n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->d_root.p, root4.data(), 4 * n_inst, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return check_hip(c, "traversal nodes");
   lf_status s2 = refit_impl(c, dp.alpha_min, sig2);
   if (s2) return s2;
   if (hipStreamSynchronize(st) != hipSuccess) return check_hip(c, "scene build");
-  if (hipMemcpy(&c->max_depth, c->depth.p, 4, hipMemcpyDeviceToHost) != hipSuccess)
-    return check_hip(c, "scene build");
   uint32_t bst = 0;
   if (hipMemcpy(&bst, c->status.p, 4, hipMemcpyDeviceToHost) != hipSuccess) return check_hip(c, "scene build");
   if (bst & lf::kStatusBvhCorrupt) {
     lf::launch_fill_u32(c->status.as<uint32_t>(), 0u, 1, st);
     return fail(c, LF_EDEVICE, "hierarchy build produced an out-of-range index");
   }
-  // a 4-wide step pushes at most three entries and halves the depth
-  if (3 * ((c->max_depth + 1) / 2) > lf::kStack)
-    return fail(c, LF_EUNSUPPORTED, "hierarchy depth %d needs more than the traversal stack (%d)", c->max_depth,
+  // a traversal step pushes at most kWide - 1 entries per level
+  if ((int64_t)(lf::kWide - 1) * c->wide_levels > lf::kStack)
+    return fail(c, LF_EUNSUPPORTED, "%d node levels need more than the traversal stack (%d)", c->wide_levels,
                 lf::kStack);
   c->has_scene = true;
   return check_hip(c, "scene build");
@@ -674,6 +707,9 @@ lf_status lf_scene_get_info(lf_ctx *c, lf_scene_info *info) {
   info->n_nodes = c->n_nodes;
   info->max_depth = c->max_depth;
   info->stack_size = lf::kStack;
+  info->n_wide_nodes = c->n_wide;
+  info->wide_levels = c->wide_levels;
+  info->node_width = lf::kWide;
   return LF_OK;
 }
 
@@ -712,6 +748,44 @@ lf_status lf_scene_copy_bvh(lf_ctx *c, int32_t inst, float *node_boxes, int32_t 
       hipMemcpy(leaf_boxes, c->leafbox.as<float>() + 6 * (int64_t)first, 24 * (size_t)n, hipMemcpyDeviceToHost) !=
           hipSuccess)
     return check_hip(c, "copy bvh");
+  return LF_OK;
+}
+
+lf_status lf_scene_copy_wide(lf_ctx *c, int32_t inst, int64_t *n_nodes, float *slot_boxes, int32_t *slot_child) {
+  if (!c) return LF_EINVAL;
+  if (!c->has_scene) return fail(c, LF_EINVAL, "no scene set");
+  if (inst < 0 || inst >= c->n_inst) return fail(c, LF_EINVAL, "instance %d out of range", inst);
+  if (!n_nodes) return fail(c, LF_EINVAL, "n_nodes is NULL");
+  set_device(c);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "copy wide");
+  const int64_t m = c->h_wide_n[inst], off = c->h_wide_off[inst];
+  *n_nodes = m;
+  if (m == 0 || (!slot_boxes && !slot_child)) return LF_OK;
+  std::vector<lf::QNode> h(m);
+  if (hipMemcpy(h.data(), c->qnodes.as<lf::QNode>() + off, sizeof(lf::QNode) * m, hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return check_hip(c, "copy wide");
+  const int W = lf::kWide;
+  const int32_t first = c->h_first[inst];
+  for (int64_t j = 0; j < m; ++j) {
+    const lf::QNode &q = h[j];
+    int below = 0;
+    for (int i = 0; i < W; ++i) {
+      const bool inner = (q.imask >> i) & 1u, valid = (q.vmask >> i) & 1u;
+      if (slot_boxes) {
+        for (int k = 0; k < 3; ++k) {
+          const float st = std::ldexp(1.0f, q.e[k]);
+          slot_boxes[(j * W + i) * 6 + k] = std::fma((float)q.q[k][i], st, q.p[k]);
+          slot_boxes[(j * W + i) * 6 + 3 + k] = std::fma((float)q.q[3 + k][i], st, q.p[k]);
+        }
+      }
+      if (slot_child)
+        slot_child[j * W + i] = !valid ? INT32_MIN
+                                : inner ? (int32_t)(q.child_base + below - off)
+                                        : ~(q.leaf_base + (i - below) - first);
+      below += inner ? 1 : 0;
+    }
+  }
   return LF_OK;
 }
 

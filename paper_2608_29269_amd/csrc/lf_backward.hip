@@ -237,7 +237,8 @@ __device__ void adjoint_hits(const RenderArgs &a, const GradArgs &G, const AdjSe
 
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_adj_trace(RenderArgs a, GradArgs G) {
-  __shared__ int stk[kStack * kBlock];
+  __shared__ int stk[kStackL * kBlock];
+  __shared__ int lq[kLeafQ * kBlock];
   const int64_t ray = a.n_tiles ? tile_ray(*a.rays.cams) : (int64_t)blockIdx.x * kBlock + threadIdx.x;
   bool active = ray >= 0 && ray < a.R;
   AdjSeed sd = {};
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_trace(RenderArgs a, GradArgs G) 
   const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
   KBufF<K> kb;
   if (active) {
-    trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
+    trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, lq + threadIdx.x, a.status, 0);
     adjoint_hits<K>(a, G, sd, kb, o, d);
   }
 }

@@ -1,13 +1,17 @@
 // lf_bvh.hip -- per-surfel prep, size-extended Morton codes, LSD radix sort,
 // hierarchy by parallel locally-ordered clustering (Meister and Bittner 2018,
 // "Parallel Locally-Ordered Clustering for Bounding Volume Hierarchy
-// Construction"), bottom-up refit and the 4-wide collapse, for gfx950.
+// Construction"), bottom-up refit and the compressed wide traversal nodes,
+// for gfx950.
 //
 // One hierarchy per instance (background and each object, in object space).
-// Leaves hold one surfel; internal nodes store both children's boxes so a
-// traversal step is one 64-byte fetch.  Surfel boxes bound the support
+// Leaves hold one surfel; binary internal nodes store both children's boxes
+// (the refit structure); traversal uses wide nodes cut from it whose child
+// boxes are quantised to 8 bits per plane.  Surfel boxes bound the support
 // ellipse rho^2 <= rho^2_max (3-sigma support and opacity threshold) and are
 // rounded outward to binary32.
+#include <cfloat>
+
 #include "lf_device.h"
 #include "lf_kernels.h"
 
@@ -405,69 +409,285 @@ __global__ void k_refit(SurfelArrays s, double alpha_min, double sig2, const int
   for (int k = 0; k < 3; ++k) { root_box6[6 * inst + k] = lo[k]; root_box6[6 * inst + 3 + k] = hi[k]; }
 }
 
-// depth of every internal node (root = 0) and the flag "starts a 4-wide node"
-__global__ void k_node_depth(const int32_t *node_parent, int64_t n_nodes, uint32_t *flag, uint32_t *status) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_nodes) return;
-  int dep = 0;
-  int p = node_parent[i];
-  while (p >= 0) {
-    if ((p >> 1) >= n_nodes || dep > 4096) {
-      atomicOr(status, kStatusBvhCorrupt);
-      break;
-    }
-    ++dep;
-    p = node_parent[p >> 1];
-  }
-  flag[i] = (dep & 1) == 0 ? 1u : 0u;
+// ---------------------------------------------------------------- wide nodes
+// The binary hierarchy is cut into traversal nodes top-down: starting from a
+// node's two children, the internal child with the largest box surface area
+// (the first of equal ones) is replaced by its two children until kWide slots
+// are filled or only leaves are left (greedy surface-area collapse); every
+// internal slot starts a node of the next level.  One launch per level.
+constexpr int32_t kNoSlot = -1;
+
+__device__ __forceinline__ float side_area(const BNode &nd, int side) {
+  return box_area(side ? nd.lo1 : nd.lo0, side ? nd.hi1 : nd.hi0);
 }
 
-__device__ __forceinline__ void put_child(BNode4 &q, int slot, int32_t child, const float *lo, const float *hi) {
-  q.lox[slot] = lo[0]; q.loy[slot] = lo[1]; q.loz[slot] = lo[2];
-  q.hix[slot] = hi[0]; q.hiy[slot] = hi[1]; q.hiz[slot] = hi[2];
-  q.child[slot] = child;
+__global__ void k_wide_roots(const int32_t *root, const int32_t *cnt, int n_inst, int32_t *level) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_inst && cnt[i] >= 2) level[root[i]] = 0;
 }
 
-// 4-wide node of every even-depth binary node: its leaf children and the
-// children of its internal children, with the boxes the refit stored
-__global__ void k_collapse(const BNode *nodes, const uint32_t *flag, const uint32_t *idx4, int64_t n_nodes,
-                           BNode4 *out, uint32_t *status) {
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_nodes || !flag[b]) return;
+// slots of every node of level `it`; marks their internal slots as level it+1
+__global__ void k_wide_level(const BNode *nodes, int64_t n_nodes, int32_t it, int32_t *level, int32_t *slot_src,
+                             int32_t *n_levels, uint32_t *status) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_nodes || level[b] != it) return;
+  int32_t src[kWide], code[kWide];
+  float area[kWide];
   const BNode nb = nodes[b];
-  BNode4 q;
-  for (int s = 0; s < 4; ++s) {
-    q.lox[s] = q.loy[s] = q.loz[s] = INFINITY;
-    q.hix[s] = q.hiy[s] = q.hiz[s] = -INFINITY;
-    q.child[s] = 0;
-    q.pad[s] = 0;
-  }
-  int slot = 0;
-  for (int side = 0; side < 2; ++side) {
-    const int32_t c = side ? nb.c1 : nb.c0;
-    if (c < 0) {
-      put_child(q, slot++, c, side ? nb.lo1 : nb.lo0, side ? nb.hi1 : nb.hi0);
-      continue;
-    }
-    if (c >= n_nodes) {
+  src[0] = (int32_t)(b << 1); code[0] = nb.c0; area[0] = side_area(nb, 0);
+  src[1] = (int32_t)(b << 1 | 1); code[1] = nb.c1; area[1] = side_area(nb, 1);
+  int m = 2;
+  while (m < kWide) {
+    int j = -1;
+    float best = -1.0f;
+    for (int q = 0; q < m; ++q)
+      if (code[q] >= 0 && area[q] > best) {
+        best = area[q];
+        j = q;
+      }
+    if (j < 0) break;
+    const int32_t x = code[j];
+    if (x >= n_nodes) {  // never taken for a consistent hierarchy
       atomicOr(status, kStatusBvhCorrupt);
       return;
     }
-    const BNode nc = nodes[c];
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const int32_t g = s2 ? nc.c1 : nc.c0;
-      int32_t e = g;
-      if (g >= 0) {
-        if (g >= n_nodes || !flag[g]) {
-          atomicOr(status, kStatusBvhCorrupt);
-          return;
-        }
-        e = (int32_t)idx4[g];
+    const BNode nx = nodes[x];
+    src[j] = x << 1; code[j] = nx.c0; area[j] = side_area(nx, 0);
+    src[m] = x << 1 | 1; code[m] = nx.c1; area[m] = side_area(nx, 1);
+    ++m;
+  }
+  bool inner = false;
+  for (int q = 0; q < kWide; ++q) {
+    slot_src[b * kWide + q] = q < m ? src[q] : kNoSlot;
+    if (q < m && code[q] >= 0) {
+      if (code[q] >= n_nodes) {
+        atomicOr(status, kStatusBvhCorrupt);
+        return;
       }
-      put_child(q, slot++, e, s2 ? nc.lo1 : nc.lo0, s2 ? nc.hi1 : nc.hi0);
+      level[code[q]] = it + 1;
+      inner = true;
     }
   }
-  out[idx4[b]] = q;
+  atomicMax(n_levels, inner ? it + 2 : it + 1);
+}
+
+// per binary node: wide nodes (sub_w) and leaves (sub_l) in its subtree, from
+// the leaves up; the second arriving child combines (release/acquire on the
+// arrival count)
+__global__ void k_wide_count(const int32_t *leaf_parent, const int32_t *node_parent, const int32_t *level, int64_t n,
+                             int64_t n_nodes, int32_t *flags, int2 *side_cnt, int32_t *sub_w, int32_t *sub_l,
+                             uint32_t *status) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= n) return;
+  int w = 0, l = 1;
+  int pp = leaf_parent[pos];
+  int steps = 0;
+  while (pp >= 0) {
+    const int p = pp >> 1, side = pp & 1;
+    if (p >= n_nodes || ++steps > 4096) {
+      atomicOr(status, kStatusBvhCorrupt);
+      return;
+    }
+    side_cnt[2 * p + side] = make_int2(w, l);
+    const int old = __hip_atomic_fetch_add(flags + p, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 0) return;
+    const int2 o = side_cnt[2 * p + (side ^ 1)];
+    w += o.x + (level[p] >= 0 ? 1 : 0);
+    l += o.y;
+    sub_w[p] = w;
+    sub_l[p] = l;
+    pp = node_parent[p];
+  }
+}
+
+// roots[3i..3i+2] = (wide index, first descendant index, first leaf position) of instance i's root
+__global__ void k_wide_root_pos(const int32_t *root, const int32_t *cnt, const int32_t *roots, int n_inst,
+                                int32_t *widx, int32_t *dbase, int32_t *lbase) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst || cnt[i] < 2) return;
+  widx[root[i]] = roots[3 * i];
+  dbase[root[i]] = roots[3 * i + 1];
+  lbase[root[i]] = roots[3 * i + 2];
+}
+
+// Places the nodes of level `it` depth-first with contiguous children: a
+// node's internal children occupy [dbase, dbase + #internal), followed by
+// each child's own descendants in slot order; its leaf slots occupy
+// [lbase, lbase + #leaves), followed by each internal child's leaves.
+// Writes the node's build description and the new position of its leaves.
+__global__ void k_wide_assign(const BNode *nodes, int64_t n_nodes, int64_t n, int32_t it, const int32_t *level,
+                              const int32_t *slot_src, const int32_t *sub_w, const int32_t *sub_l, int32_t *widx,
+                              int32_t *dbase, int32_t *lbase, int32_t *newpos, WideInfo *info, int64_t n_wide,
+                              uint32_t *status) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_nodes || level[b] != it) return;
+  const int32_t me = widx[b], db = dbase[b], lb = lbase[b];
+  if (me < 0 || me >= n_wide) {
+    atomicOr(status, kStatusBvhCorrupt);
+    return;
+  }
+  WideInfo wi;
+  int32_t code[kWide];
+  int m = 0, n_int = 0;
+  wi.imask = 0;
+  for (int q = 0; q < kWide; ++q) {
+    const int32_t sr = slot_src[b * kWide + q];
+    wi.src[q] = sr;
+    code[q] = 0;
+    if (sr == kNoSlot) continue;
+    if ((sr >> 1) >= n_nodes || sr < 0) {
+      atomicOr(status, kStatusBvhCorrupt);
+      return;
+    }
+    const BNode &nd = nodes[sr >> 1];
+    code[q] = (sr & 1) ? nd.c1 : nd.c0;
+    if (code[q] >= 0) {
+      wi.imask |= 1u << q;
+      ++n_int;
+    }
+    m = q + 1;
+  }
+  int32_t dnext = db + n_int, lnext = lb + (m - n_int);
+  int ki = 0, kl = 0;
+  for (int q = 0; q < m; ++q) {
+    const int32_t x = code[q];
+    if (x >= 0) {
+      if (x >= n_nodes) {
+        atomicOr(status, kStatusBvhCorrupt);
+        return;
+      }
+      widx[x] = db + ki++;
+      dbase[x] = dnext;
+      lbase[x] = lnext;
+      dnext += sub_w[x] - 1;
+      lnext += sub_l[x];
+    } else {
+      if (~x >= n) {
+        atomicOr(status, kStatusBvhCorrupt);
+        return;
+      }
+      newpos[~x] = lb + kl++;
+    }
+  }
+  wi.child_base = db;
+  wi.leaf_base = lb;
+  wi.n_slots = (uint32_t)m;
+  info[me] = wi;
+}
+
+// moves every leaf to its new position: the leaf order (perm), the leaf
+// parents and the binary nodes' leaf codes
+__global__ void k_leaf_reorder(const int32_t *newpos, const int32_t *perm, const int32_t *leaf_parent, int64_t n,
+                               int64_t n_nodes, int32_t *perm2, int32_t *leaf_parent2, BNode *nodes,
+                               uint32_t *status) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= n) return;
+  const int32_t np = newpos[pos];
+  if (np < 0 || np >= n) {
+    atomicOr(status, kStatusBvhCorrupt);
+    return;
+  }
+  perm2[np] = perm[pos];
+  const int32_t pp = leaf_parent[pos];
+  leaf_parent2[np] = pp;
+  if (pp >= 0) {
+    if ((pp >> 1) >= n_nodes) {
+      atomicOr(status, kStatusBvhCorrupt);
+      return;
+    }
+    if (pp & 1) nodes[pp >> 1].c1 = ~np;
+    else nodes[pp >> 1].c0 = ~np;
+  }
+}
+
+__global__ void k_iota(int32_t *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+__device__ __forceinline__ float pow2f(int e) { return __uint_as_float((uint32_t)(e + 127) << 23); }
+
+// Quantised traversal nodes from the refitted binary boxes.  Per axis the
+// frame origin is the lower bound of the occupied non-empty slots and the
+// step 2^e the smallest power of two with fmaf(255, 2^e, p) at or above their
+// upper bound; lower codes round down and upper codes up, both checked with
+// the same fused multiply-add the traversal evaluates.  A NaN bound decodes
+// to the whole frame.
+__global__ void k_wide_quantize(const BNode *nodes, const WideInfo *info, int64_t n_wide, int64_t n_nodes,
+                                QNode *out, uint32_t *status) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_wide) return;
+  const WideInfo wi = info[j];
+  float lo[kWide][3], hi[kWide][3];
+  float ulo[3] = {INFINITY, INFINITY, INFINITY}, uhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  uint32_t vmask = 0;
+  for (int q = 0; q < kWide; ++q) {
+    for (int k = 0; k < 3; ++k) {
+      lo[q][k] = INFINITY;
+      hi[q][k] = -INFINITY;
+    }
+    if (q >= (int)wi.n_slots) continue;
+    const int32_t sr = wi.src[q];
+    if (sr < 0 || (sr >> 1) >= n_nodes) {
+      atomicOr(status, kStatusBvhCorrupt);
+      return;
+    }
+    const BNode &nd = nodes[sr >> 1];
+    const float *bl = (sr & 1) ? nd.lo1 : nd.lo0, *bh = (sr & 1) ? nd.hi1 : nd.hi0;
+    bool empty = false;
+    for (int k = 0; k < 3; ++k) {
+      lo[q][k] = bl[k];
+      hi[q][k] = bh[k];
+      empty |= bl[k] > bh[k];
+    }
+    if (empty) continue;
+    vmask |= 1u << q;
+    for (int k = 0; k < 3; ++k) {
+      ulo[k] = fminf(ulo[k], bl[k]);
+      uhi[k] = fmaxf(uhi[k], bh[k]);
+    }
+  }
+  QNode nd;
+  for (int k = 0; k < 3; ++k) {
+    float p = 0.0f;
+    int e = -126;
+    if (vmask) {
+      p = fminf(fmaxf(ulo[k], -FLT_MAX), FLT_MAX);  // NaN -> -FLT_MAX
+      const float ext = uhi[k] - p;
+      if (ext > 0.0f && ext <= FLT_MAX) e = max(-126, ilogbf(ext) - 8);
+      else if (!(ext <= 0.0f)) e = 127;  // infinite or NaN extent
+      while (e < 127 && !(__builtin_fmaf(255.0f, pow2f(e), p) >= uhi[k])) ++e;
+    }
+    const float st = pow2f(e);
+    nd.p[k] = p;
+    nd.e[k] = (int8_t)e;
+    const float top = __builtin_fmaf(255.0f, st, p);
+    for (int q = 0; q < kWide; ++q) {
+      int ql = 255, qh = 0;
+      if ((vmask >> q) & 1u) {
+        const float l = lo[q][k], h = hi[q][k];
+        if (!(l >= p)) {
+          ql = 0;
+        } else {
+          ql = (int)fmin(floor(((double)l - (double)p) / (double)st), 255.0);
+          while (ql > 0 && __builtin_fmaf((float)ql, st, p) > l) --ql;
+        }
+        if (!(h <= top)) {
+          qh = 255;
+        } else {
+          qh = (int)fmax(fmin(ceil(((double)h - (double)p) / (double)st), 255.0), 0.0);
+          while (qh < 255 && __builtin_fmaf((float)qh, st, p) < h) ++qh;
+        }
+      }
+      nd.q[k][q] = (uint8_t)ql;
+      nd.q[3 + k][q] = (uint8_t)qh;
+    }
+  }
+  nd.imask = (uint8_t)wi.imask;
+  nd.child_base = wi.child_base;
+  nd.leaf_base = wi.leaf_base;
+  nd.vmask = vmask;
+  out[j] = nd;
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
@@ -576,19 +796,57 @@ void launch_refit(const SurfelArrays &s, double alpha_min, double sig2, const in
                      node_parent, flags, nodes, n_nodes, n_inst, rec, filt, leaf_box6, root_box6, status);
 }
 
-void launch_wide_index(const int32_t *node_parent, int64_t n_nodes, uint32_t *flag, uint32_t *idx4,
-                       uint32_t *status, hipStream_t st) {
-  if (n_nodes <= 0) return;
-  hipLaunchKernelGGL(k_node_depth, dim3(blocks(n_nodes, 256)), dim3(256), 0, st, node_parent, n_nodes, flag, status);
-  // a failure stays in the runtime's last error, which the caller checks
-  (void)hipMemcpyAsync(idx4, flag, sizeof(uint32_t) * n_nodes, hipMemcpyDeviceToDevice, st);
-  hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, idx4, n_nodes);
+void launch_wide_roots(const int32_t *root, const int32_t *cnt, int n_inst, int32_t *level, hipStream_t st) {
+  hipLaunchKernelGGL(k_wide_roots, dim3(1), dim3(64), 0, st, root, cnt, n_inst, level);
 }
 
-void launch_collapse(const BNode *nodes, const uint32_t *flag, const uint32_t *idx4, int64_t n_nodes, BNode4 *out,
-                     uint32_t *status, hipStream_t st) {
+void launch_wide_level(const BNode *nodes, int64_t n_nodes, int32_t it, int32_t *level, int32_t *slot_src,
+                       int32_t *n_levels, uint32_t *status, hipStream_t st) {
   if (n_nodes <= 0) return;
-  hipLaunchKernelGGL(k_collapse, dim3(blocks(n_nodes, 256)), dim3(256), 0, st, nodes, flag, idx4, n_nodes, out,
+  hipLaunchKernelGGL(k_wide_level, dim3(blocks(n_nodes, 256)), dim3(256), 0, st, nodes, n_nodes, it, level, slot_src,
+                     n_levels, status);
+}
+
+void launch_wide_count(const int32_t *leaf_parent, const int32_t *node_parent, const int32_t *level, int64_t n,
+                       int64_t n_nodes, int32_t *flags, int2 *side_cnt, int32_t *sub_w, int32_t *sub_l,
+                       uint32_t *status, hipStream_t st) {
+  if (n <= 0 || n_nodes <= 0) return;
+  launch_fill_u32((uint32_t *)flags, 0u, n_nodes, st);
+  hipLaunchKernelGGL(k_wide_count, dim3(blocks(n, 256)), dim3(256), 0, st, leaf_parent, node_parent, level, n,
+                     n_nodes, flags, side_cnt, sub_w, sub_l, status);
+}
+
+void launch_wide_root_pos(const int32_t *root, const int32_t *cnt, const int32_t *roots, int n_inst, int32_t *widx,
+                          int32_t *dbase, int32_t *lbase, hipStream_t st) {
+  hipLaunchKernelGGL(k_wide_root_pos, dim3(1), dim3(64), 0, st, root, cnt, roots, n_inst, widx, dbase, lbase);
+}
+
+void launch_wide_assign(const BNode *nodes, int64_t n_nodes, int64_t n, int32_t it, const int32_t *level,
+                        const int32_t *slot_src, const int32_t *sub_w, const int32_t *sub_l, int32_t *widx,
+                        int32_t *dbase, int32_t *lbase, int32_t *newpos, WideInfo *info, int64_t n_wide,
+                        uint32_t *status, hipStream_t st) {
+  if (n_nodes <= 0) return;
+  hipLaunchKernelGGL(k_wide_assign, dim3(blocks(n_nodes, 256)), dim3(256), 0, st, nodes, n_nodes, n, it, level,
+                     slot_src, sub_w, sub_l, widx, dbase, lbase, newpos, info, n_wide, status);
+}
+
+void launch_iota(int32_t *p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_iota, dim3(blocks(n, 256)), dim3(256), 0, st, p, n);
+}
+
+void launch_leaf_reorder(const int32_t *newpos, const int32_t *perm, const int32_t *leaf_parent, int64_t n,
+                         int64_t n_nodes, int32_t *perm2, int32_t *leaf_parent2, BNode *nodes, uint32_t *status,
+                         hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_leaf_reorder, dim3(blocks(n, 256)), dim3(256), 0, st, newpos, perm, leaf_parent, n, n_nodes,
+                     perm2, leaf_parent2, nodes, status);
+}
+
+void launch_wide_quantize(const BNode *nodes, const WideInfo *info, int64_t n_wide, int64_t n_nodes, QNode *out,
+                          uint32_t *status, hipStream_t st) {
+  if (n_wide <= 0) return;
+  hipLaunchKernelGGL(k_wide_quantize, dim3(blocks(n_wide, 256)), dim3(256), 0, st, nodes, info, n_wide, n_nodes, out,
                      status);
 }
 

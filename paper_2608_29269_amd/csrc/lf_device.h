@@ -234,20 +234,17 @@ __device__ __forceinline__ bool slab64(d3 o, d3 d, const double *lo, const doubl
   return tn <= tf;
 }
 
-// Binary32 view of the object-space ray for the slab tests.  The near plane
-// of each axis is the low one for a non-negative direction component and the
-// high one otherwise; near planes are met from origin + pad and far planes
-// from origin - pad (signs follow the direction), i.e. every box is grown by
-// pad, with pad >= the rounding error of the binary32 ray over the instance's
-// parameter range, so a box the exact ray enters is never culled.  A box with
-// lo > hi (empty) always misses.
+// Binary32 view of the object-space ray for the box tests.  Every box is
+// grown by pad >= the distance between the exact ray and this binary32 ray
+// over the instance's parameter range (rounded origin and direction, and the
+// clamping of tiny direction components), so a box the exact ray enters is
+// never culled.
 struct RayF {
-  float nox, noy, noz;   // origin used against near planes
-  float fox, foy, foz;   // origin used against far planes
-  float ix, iy, iz;      // 1/d
-  bool sx, sy, sz;       // d >= 0 per axis
   float ox, oy, oz;      // origin
   float dx, dy, dz;      // direction
+  float ix, iy, iz;      // 1/d
+  bool sx, sy, sz;       // d >= 0 per axis
+  float pad;
   float oabs;            // max |origin component|
 };
 
@@ -261,30 +258,10 @@ __device__ __forceinline__ void make_rayf(d3 oo, d3 dd, double tabs, RayF &rf) {
   rf.dx = (float)dd.x; rf.dy = (float)dd.y; rf.dz = (float)dd.z;
   rf.oabs = fmaxf(fmaxf(fabsf(rf.ox), fabsf(rf.oy)), fabsf(rf.oz));
   const double eo = fmax(fmax(fabs(oo.x - rf.ox), fabs(oo.y - rf.oy)), fabs(oo.z - rf.oz));
-  const double ed = fmax(fmax(fabs(dd.x - rf.dx), fabs(dd.y - rf.dy)), fabs(dd.z - rf.dz));
-  const float pad = (float)((eo + ed * tabs + 1e-30) * 1.001) + 1e-30f;
+  const double ed = fmax(fmax(fabs(dd.x - rf.dx), fabs(dd.y - rf.dy)), fabs(dd.z - rf.dz)) + 1e-20;
+  rf.pad = (float)((eo + ed * tabs + 1e-30) * 1.001) + 1e-30f;
   rf.ix = inv_dir(rf.dx); rf.iy = inv_dir(rf.dy); rf.iz = inv_dir(rf.dz);
   rf.sx = rf.ix >= 0.f; rf.sy = rf.iy >= 0.f; rf.sz = rf.iz >= 0.f;
-  rf.nox = rf.sx ? rf.ox + pad : rf.ox - pad;
-  rf.noy = rf.sy ? rf.oy + pad : rf.oy - pad;
-  rf.noz = rf.sz ? rf.oz + pad : rf.oz - pad;
-  rf.fox = rf.sx ? rf.ox - pad : rf.ox + pad;
-  rf.foy = rf.sy ? rf.oy - pad : rf.oy + pad;
-  rf.foz = rf.sz ? rf.oz - pad : rf.oz + pad;
-}
-
-// one box: entry t, or +inf if the (conservative) test misses
-__device__ __forceinline__ void child_test4(const RayF &r, float lx, float ly, float lz, float hx, float hy, float hz,
-                                            float tlo, float thi, float &tn) {
-  const float nx = r.sx ? lx : hx, fx = r.sx ? hx : lx;
-  const float ny = r.sy ? ly : hy, fy = r.sy ? hy : ly;
-  const float nz = r.sz ? lz : hz, fz = r.sz ? hz : lz;
-  float n = fmaxf(fmaxf((nx - r.nox) * r.ix, (ny - r.noy) * r.iy), fmaxf((nz - r.noz) * r.iz, tlo));
-  float f = fminf(fminf((fx - r.fox) * r.ix, (fy - r.foy) * r.iy), fminf((fz - r.foz) * r.iz, thi));
-  // widen by the rounding of the subtraction, product and reciprocal (Ize 2013)
-  n = n - 1e-6f * fabsf(n);
-  f = f + 1e-6f * fabsf(f);
-  tn = (n <= f) ? n : INFINITY;
 }
 
 __device__ __forceinline__ void cswap(float &ta, int &ca, float &tb, int &cb) {
@@ -295,6 +272,87 @@ __device__ __forceinline__ void cswap(float &ta, int &ca, float &tb, int &cb) {
   cb = sw ? ca : cb;
   ta = t;
   ca = c;
+}
+
+// Distances along one axis in a node's frame: a plane of code q lies at
+// q * C + B, with B the near (Bn) or far (Bf) offset.  C = 2^e / d is exact;
+// E bounds the rounding of the frame origin's distance, of 1/d, of the
+// decoded plane (within half an ulp of the fused multiply-add the build
+// checked) and of the products, so near distances are never overestimated
+// and far ones never underestimated for the box grown by pad.  An axis whose
+// terms are not safely finite is left unconstrained.
+__device__ __forceinline__ void axis_frame(float p, int e, float o, float inv, float pad, float &C, float &Bn,
+                                           float &Bf) {
+  C = __uint_as_float((uint32_t)(e + 127) << 23) * inv;
+  const float ai = fabsf(inv);
+  const float b = (p - o) * inv, g = pad * ai;
+  const float E = 0x1p-20f * __builtin_fmaf(fabsf(p), ai, __builtin_fmaf(255.0f, fabsf(C), fabsf(b)) + g) + 1e-30f;
+  Bn = (b - g) - E;
+  Bf = (b + g) + E;
+  if (!(fabsf(C) <= 0x1p118f) || !(fabsf(Bn) <= 0x1p126f) || !(fabsf(Bf) <= 0x1p126f)) {
+    C = 0.0f;
+    Bn = -INFINITY;
+    Bf = INFINITY;
+  }
+}
+
+// Visits one traversal node: entry t of every slot whose decoded box (grown
+// by pad) the ray enters within [tlo, thi] (else +inf), the slot's child code
+// (>= 0 node, < 0 ~leaf position) and the masks of hit internal and hit leaf
+// slots.
+__device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, float tlo, float thi, float *t,
+                                           int *c, uint32_t &ihit, uint32_t &lhit) {
+  constexpr int kDw = (int)sizeof(QNode) / 4;
+  constexpr int kPw = kWide / 4;  // dwords per plane
+  uint32_t dw[kDw];
+  const uint4 *src = (const uint4 *)node;
+#pragma unroll
+  for (int v = 0; v < kDw / 4; ++v) {
+    const uint4 x = src[v];
+    dw[4 * v] = x.x; dw[4 * v + 1] = x.y; dw[4 * v + 2] = x.z; dw[4 * v + 3] = x.w;
+  }
+  const uint32_t meta = dw[3];
+  float Cx, Cy, Cz, Bnx, Bny, Bnz, Bfx, Bfy, Bfz;
+  axis_frame(__uint_as_float(dw[0]), (int)(int8_t)(meta & 0xffu), rf.ox, rf.ix, rf.pad, Cx, Bnx, Bfx);
+  axis_frame(__uint_as_float(dw[1]), (int)(int8_t)((meta >> 8) & 0xffu), rf.oy, rf.iy, rf.pad, Cy, Bny, Bfy);
+  axis_frame(__uint_as_float(dw[2]), (int)(int8_t)((meta >> 16) & 0xffu), rf.oz, rf.iz, rf.pad, Cz, Bnz, Bfz);
+  const uint32_t imask = meta >> 24;
+  const int cbase = (int)dw[4], lbase = (int)dw[5];
+  const uint32_t vmask = dw[6];
+  // codes of the near and far plane of each axis: lower codes for d >= 0
+  uint32_t nx[kPw], ny[kPw], nz[kPw], fx[kPw], fy[kPw], fz[kPw];
+#pragma unroll
+  for (int w = 0; w < kPw; ++w) {
+    const uint32_t lx = dw[7 + w], ly = dw[7 + kPw + w], lz = dw[7 + 2 * kPw + w];
+    const uint32_t hx = dw[7 + 3 * kPw + w], hy = dw[7 + 4 * kPw + w], hz = dw[7 + 5 * kPw + w];
+    nx[w] = rf.sx ? lx : hx; fx[w] = rf.sx ? hx : lx;
+    ny[w] = rf.sy ? ly : hy; fy[w] = rf.sy ? hy : ly;
+    nz[w] = rf.sz ? lz : hz; fz[w] = rf.sz ? hz : lz;
+  }
+  ihit = 0;
+  lhit = 0;
+#pragma unroll
+  for (int i = 0; i < kWide; ++i) {
+    const int w = i / 4, b = 8 * (i % 4);
+    const float tnx = __builtin_fmaf((float)((nx[w] >> b) & 0xffu), Cx, Bnx);
+    const float tny = __builtin_fmaf((float)((ny[w] >> b) & 0xffu), Cy, Bny);
+    const float tnz = __builtin_fmaf((float)((nz[w] >> b) & 0xffu), Cz, Bnz);
+    const float tfx = __builtin_fmaf((float)((fx[w] >> b) & 0xffu), Cx, Bfx);
+    const float tfy = __builtin_fmaf((float)((fy[w] >> b) & 0xffu), Cy, Bfy);
+    const float tfz = __builtin_fmaf((float)((fz[w] >> b) & 0xffu), Cz, Bfz);
+    float n = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, tlo));
+    float f = fminf(fminf(tfx, tfy), fminf(tfz, thi));
+    // the last fused multiply-add rounds relative to its result
+    n = __builtin_fmaf(-0x1p-20f, fabsf(n), n);
+    f = __builtin_fmaf(0x1p-20f, fabsf(f), f);
+    const bool hit = n <= f && ((vmask >> i) & 1u);
+    t[i] = hit ? n : INFINITY;
+    const int below = __builtin_popcount(imask & ((1u << i) - 1u));
+    const bool inner = (imask >> i) & 1u;
+    c[i] = inner ? cbase + below : ~(lbase + (i - below));
+    ihit |= (hit && inner) ? 1u << i : 0u;
+    lhit |= (hit && !inner) ? 1u << i : 0u;
+  }
 }
 
 // Exact (double) plane intersection and support test of the surfel at leaf
@@ -456,14 +514,31 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 
 // Collects the k closest valid hits of the world ray (o, d) over all
 // instances into kb.  stk points at this lane's first LDS stack slot (stride
-// kBlock).
+// kBlock, kStackL entries; deeper entries go to private scratch) and lq at
+// its first leaf-queue slot (stride kBlock, kLeafQ entries).
+//
+// Traversal of an instance runs in rounds of two phases (after Aila and
+// Laine 2009, "while-while"): in the node phase a lane visits nodes, its hit
+// leaves join its leaf queue and its nearest hit internal child is visited
+// next (the others are pushed), while some lane that can still visit nodes
+// has no leaf queued; a lane pauses while its queue could not take a whole
+// node's leaves.  The leaf phase then tests every queued leaf.  The stack
+// holds internal nodes only.
 template <int K, class B>
-__device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &kb, int *stk, uint32_t *status,
-                      int counter_base = 0) {
+__device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &kb, int *stk, int *lq,
+                      uint32_t *status, int counter_base = 0) {
   kinit<K>(kb, P.k);
   const bool brute = (P.flags & LF_FLAG_BRUTE_FORCE) != 0;
   const float t_min_f = round_down_f(P.t_min);
   uint32_t c_nodes = 0, c_tests = 0, c_ins = 0, c_ties = 0, c_pass = 0, c_hits = 0;
+  auto count_test = [&](int r) {
+    c_ins += r & 1;
+    c_ties += (r >> 1) & 1;
+    c_pass += (r >> 2) & 1;
+    c_hits += r >> 3;
+    ++c_tests;
+  };
+  int spill[kStack - kStackL];
   for (int ii = 0; ii < S.n_inst; ++ii) {
     const InstRec &I = S.inst[ii];
     if (I.n <= 0) continue;
@@ -477,99 +552,87 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
     make_rayf(oo, dd, fmax(fabs(itf), fabs(itn)), rf);
     if (brute) {
       const int end = I.first + I.n <= S.n_rec ? I.first + I.n : S.n_rec;
-      for (int pos = I.first < 0 ? 0 : I.first; pos < end; ++pos) {
-        const int r = test_surfel<K>(S, pos, oo, dd, rf, P.t_min, t_min_f, kb, o, d);
-        c_ins += r & 1;
-        c_ties += (r >> 1) & 1;
-        c_pass += (r >> 2) & 1;
-        c_hits += r >> 3;
-        ++c_tests;
-      }
+      for (int pos = I.first < 0 ? 0 : I.first; pos < end; ++pos)
+        count_test(test_surfel<K>(S, pos, oo, dd, rf, P.t_min, t_min_f, kb, o, d));
       continue;
     }
     const float tlo = (float)(0.5 * P.t_min);
-    // Two phases per round (Aila and Laine 2009, "while-while" with postponed
-    // leaves): lanes step through internal nodes together, each postponing the
-    // first leaf it meets, until no lane of the wave is still without a leaf;
-    // then the wave tests leaves together.  kDone ends a lane; it is never a
-    // leaf (~kDone = INT_MAX >= n_rec).
-    constexpr int kDone = (int)0x80000000;
-    int cur = I.root;
-    int pend = kDone;
+    constexpr int kDone = (int)0x80000000;  // no node to visit
     int sp = 0;
-    while (cur != kDone || pend != kDone) {
-      while (cur >= 0) {
+    auto push = [&](int v) {
+      if (sp < kStackL) stk[sp * kBlock] = v;
+      else spill[sp - kStackL] = v;
+      ++sp;
+    };
+    auto pop = [&]() -> int {
+      --sp;
+      return sp < kStackL ? stk[sp * kBlock] : spill[sp - kStackL];
+    };
+    int cur = I.root;  // >= 0 node, < 0 (one surfel) leaf
+    int qn = 0;
+    if (cur < 0) {
+      lq[0] = cur;
+      qn = 1;
+      cur = kDone;
+    }
+    while (cur != kDone || qn > 0) {
+      // node phase
+      while (true) {
+        const bool can = cur >= 0 && qn <= kLeafQ - kWide;
+        if (!__any(can && qn == 0)) break;
+        if (!can) continue;
         if (cur >= S.n_nodes) {  // never taken for a consistent hierarchy
           atomicOr(status, kStatusBvhCorrupt);
           cur = kDone;
-          pend = kDone;
-          break;
+          continue;
         }
         ++c_nodes;
-        const BNode4 &nd = S.nodes[cur];
-        const float4 lx = *(const float4 *)nd.lox, ly = *(const float4 *)nd.loy, lz = *(const float4 *)nd.loz;
-        const float4 hx = *(const float4 *)nd.hix, hy = *(const float4 *)nd.hiy, hz = *(const float4 *)nd.hiz;
-        const int4 ch = *(const int4 *)nd.child;
         // the exact k-th distance is at most the successor of the k-th binary32 key
         const float tkf = kb.t[K - 1];
         const float thi = tkf < INFINITY ? next_up_f(tkf) * (1.0f + 1e-6f) : INFINITY;
-        float t0, t1, t2, t3;
-        child_test4(rf, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tlo, thi, t0);
-        child_test4(rf, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tlo, thi, t1);
-        child_test4(rf, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, tlo, thi, t2);
-        child_test4(rf, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, tlo, thi, t3);
-        int c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
-        // sort the four (entry t, child) pairs, misses carry +inf
-        cswap(t0, c0, t1, c1);
-        cswap(t2, c2, t3, c3);
-        cswap(t0, c0, t2, c2);
-        cswap(t1, c1, t3, c3);
-        cswap(t1, c1, t2, c2);
-        if (t0 == INFINITY) {
-          cur = sp ? stk[(--sp) * kBlock] : kDone;
-        } else {
-          const int nhit = 1 + (t1 < INFINITY) + (t2 < INFINITY) + (t3 < INFINITY);
-          if (sp + nhit - 1 > kStack) {
-            atomicOr(status, kStatusOverflow);
-            cur = kDone;
-            pend = kDone;
-            break;
+        float ts[kWide];
+        int cs[kWide];
+        uint32_t ih, lh;
+        visit_node(S.nodes + cur, rf, tlo, thi, ts, cs, ih, lh);
+#pragma unroll
+        for (int j = 0; j < kWide; ++j)
+          if ((lh >> j) & 1u) lq[(qn++) * kBlock] = cs[j];
+        if (ih == 0) {
+          cur = sp ? pop() : kDone;
+          continue;
+        }
+        if (sp + __builtin_popcount(ih) - 1 > kStack) {
+          atomicOr(status, kStatusOverflow);
+          cur = kDone;
+          continue;
+        }
+        // the nearest hit internal child next, the others onto the stack
+        float best = INFINITY;
+        int bj = 0;
+#pragma unroll
+        for (int j = 0; j < kWide; ++j)
+          if (((ih >> j) & 1u) && ts[j] < best) {
+            best = ts[j];
+            bj = j;
           }
-          if (t3 < INFINITY) stk[(sp++) * kBlock] = c3;
-          if (t2 < INFINITY) stk[(sp++) * kBlock] = c2;
-          if (t1 < INFINITY) stk[(sp++) * kBlock] = c1;
-          cur = c0;
-        }
-        if (cur < 0 && cur != kDone && pend == kDone) {  // postpone the first leaf, keep traversing
-          pend = cur;
-          cur = sp ? stk[(--sp) * kBlock] : kDone;
-        }
-        if (!__any(pend == kDone && cur >= 0)) break;  // every lane holds a leaf or is done
+#pragma unroll
+        for (int j = 0; j < kWide; ++j)
+          if (((ih >> j) & 1u) && j != bj) push(cs[j]);
+        int nxt = cs[0];
+#pragma unroll
+        for (int j = 1; j < kWide; ++j) nxt = j == bj ? cs[j] : nxt;
+        cur = nxt;
       }
-      // the postponed leaf, then the leaves on top of the stack
-      while (true) {
-        int leaf;
-        if (pend != kDone) {
-          leaf = pend;
-          pend = kDone;
-        } else if (cur < 0 && cur != kDone) {
-          leaf = cur;
-          cur = sp ? stk[(--sp) * kBlock] : kDone;
-        } else {
-          break;
-        }
+      // leaf phase
+      for (int j = 0; j < qn; ++j) {
+        const int leaf = lq[j * kBlock];
         if (~leaf >= S.n_rec) {  // never taken for a consistent hierarchy
           atomicOr(status, kStatusBvhCorrupt);
-          cur = kDone;
-          break;
+          continue;
         }
-        const int r = test_surfel<K>(S, ~leaf, oo, dd, rf, P.t_min, t_min_f, kb, o, d);
-        c_ins += r & 1;
-        c_ties += (r >> 1) & 1;
-        c_pass += (r >> 2) & 1;
-        c_hits += r >> 3;
-        ++c_tests;
+        count_test(test_surfel<K>(S, ~leaf, oo, dd, rf, P.t_min, t_min_f, kb, o, d));
       }
+      qn = 0;
     }
   }
   if (P.counters) {

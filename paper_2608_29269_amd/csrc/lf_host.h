@@ -58,8 +58,11 @@ struct lf_ctx {
   double built_alpha_min = 0, built_sig2 = 0;
   lfh::DevBuf d_first, d_n, d_root;
   lfh::DevBuf rec, filt, nodes, perm, leaf_parent, node_parent, flags, leafbox, rootbox, inst, status;
-  lfh::DevBuf keys, keys2, vals2, hist, boxidx, ibounds, depth, nodes4, flag4, idx4, ploc_i, ploc_f;
-  int64_t n_nodes4 = 0;
+  lfh::DevBuf keys, keys2, vals2, hist, boxidx, ibounds, depth, ploc_i, ploc_f;
+  lfh::DevBuf qnodes, winfo, wtmp, wroots;
+  int64_t n_wide = 0;      // traversal nodes over all instances
+  std::vector<int64_t> h_wide_off, h_wide_n;  // per instance
+  int32_t wide_levels = 0; // levels of the deepest traversal hierarchy
   // per call
   lfh::DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;
   lfh::DevBuf queue, qcount, contrib, frozen, l1acc, cams, rec1, rec2, seeds;
@@ -83,7 +86,7 @@ lf_status fail(lf_ctx *c, lf_status st, const char *fmt, ...);
 // LF_EDEVICE with the pending HIP error, if any.
 lf_status check_hip(lf_ctx *c, const char *where);
 bool set_device(lf_ctx *c);
-// Recomputes trace records, binary bounds and 4-wide nodes for the given
+// Recomputes trace records, binary bounds and traversal nodes for the given
 // opacity threshold and squared support radius (on the context's stream).
 lf_status refit_impl(lf_ctx *c, double alpha_min, double sig2);
 // Validates tracing parameters (k, spp, constants, flags).

@@ -9,7 +9,10 @@
 namespace lf {
 
 constexpr int kBlock = 128;       // threads per block of the tracing kernels (2 wave64)
-constexpr int kStack = 72;        // traversal stack entries per lane (LDS; 4 blocks of 128 lanes per CU)
+constexpr int kWide = 8;          // children per traversal node
+constexpr int kStackL = 48;       // traversal stack entries per lane held in LDS (24 KB per block)
+constexpr int kStack = 192;       // traversal stack entries per lane; those past kStackL in private scratch
+constexpr int kLeafQ = 16;        // leaf-queue entries per lane (LDS, 8 KB per block)
 constexpr int kMaxInst = 64;      // background + up to 63 objects
 constexpr uint32_t kFlipBit = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7fffffffu;
@@ -51,17 +54,36 @@ struct alignas(16) BNode {
 };
 static_assert(sizeof(BNode) == 64, "BNode layout");
 
-// 4-wide node used by traversal, 128 bytes (one cache line): the binary
-// hierarchy collapsed so that every internal node at even depth holds its
-// (up to four) grandchildren.  Child >= 0: 4-wide node index (global); < 0:
-// ~leaf position; unused slots have an empty box (lo > hi).
-struct alignas(16) BNode4 {
-  float lox[4], loy[4], loz[4];
-  float hix[4], hiy[4], hiz[4];
-  int32_t child[4];
-  int32_t pad[4];
+// Traversal node with up to kWide children whose boxes are quantised to 8
+// bits per plane in a per-node frame (compressed wide BVH, Ylitie et al.
+// 2017): on axis a the plane of code q lies at fmaf(q, 2^e[a], p[a]) in
+// binary32.  The build picks every lower code so that this value is at or
+// below the child's lower bound and every upper code so that it is at or
+// above its upper bound, so a decoded box always contains the box it stands
+// for.  Slots 0..m-1 are occupied; internal children are stored contiguously
+// from child_base and leaf children (surfel positions) from leaf_base, both
+// in slot order, so slot i's child is child_base + (internal slots below i)
+// or leaf_base + (leaf slots below i).  80 bytes for kWide = 8.
+struct alignas(16) QNode {
+  float p[3];
+  int8_t e[3];
+  uint8_t imask;          // bit i: slot i holds an internal node
+  int32_t child_base;
+  int32_t leaf_base;
+  uint32_t vmask;         // bit i: slot i holds a child with a non-empty box
+  uint8_t q[6][kWide];    // lower x, y, z then upper x, y, z codes per slot
 };
-static_assert(sizeof(BNode4) == 128, "BNode4 layout");
+static_assert(sizeof(QNode) == (kWide == 8 ? 80 : 64), "QNode layout");
+static_assert(kWide == 4 || kWide == 8, "traversal width");
+
+// Build-time description of one traversal node, kept for every refit: the
+// binary (parent << 1 | side) under which each slot's box is stored (-1:
+// unoccupied), and the node's child and leaf bases.
+struct alignas(16) WideInfo {
+  int32_t src[kWide];
+  int32_t child_base, leaf_base;
+  uint32_t imask, n_slots;
+};
 
 // One instance of the two-level scene for the current state: background
 // (identity) or an object with its rigid transform.
@@ -69,7 +91,7 @@ struct alignas(16) InstRec {
   double R[9];      // object -> world rotation (orthonormalised), row-major
   double t[3];      // object -> world translation
   double lo[3], hi[3];  // world-space bounds of the instance (conservative)
-  int32_t root;     // root 4-wide node (>= 0), ~leaf (< 0) for one surfel; unused if n == 0
+  int32_t root;     // root traversal node (>= 0), ~leaf (< 0) for one surfel; unused if n == 0
   int32_t identity; // 1: background (no transform)
   int32_t first;    // first surfel index / leaf position of the instance
   int32_t n;        // surfel count
@@ -78,11 +100,11 @@ struct alignas(16) InstRec {
 struct SceneView {
   const TraceRec *rec;   // [N] leaf order
   const FiltRec *filt;   // [N] leaf order
-  const BNode4 *nodes;   // 4-wide nodes of all instances
+  const QNode *nodes;    // traversal nodes of all instances
   const InstRec *inst;   // [n_inst]
   int32_t n_inst;
   int32_t n_rec;         // N
-  int32_t n_nodes;       // 4-wide nodes over all instances
+  int32_t n_nodes;       // traversal nodes over all instances
   const float *mu, *q, *scale, *opacity, *albedo, *roughness, *metallic;  // caller arrays (orig index)
 };
 

@@ -35,12 +35,32 @@ void launch_refit(const SurfelArrays &s, double alpha_min, double sig2, const in
                   const int32_t *leaf_parent, const int32_t *node_parent, int32_t *flags, int64_t n_nodes,
                   int n_inst, BNode *nodes, TraceRec *rec, FiltRec *filt, float *leaf_box6, float *root_box6,
                   uint32_t *status, hipStream_t st);
-// 4-wide hierarchy: flags of even-depth internal nodes and their exclusive prefix sum (index of the 4-wide node)
-void launch_wide_index(const int32_t *node_parent, int64_t n_nodes, uint32_t *flag, uint32_t *idx4,
+// Wide traversal nodes (greedy surface-area collapse of the binary hierarchy).
+// level[b] = -1 for every binary node first; roots of instances with >= 2 surfels get level 0
+void launch_wide_roots(const int32_t *root, const int32_t *cnt, int n_inst, int32_t *level, hipStream_t st);
+// slot sources [n_nodes, kWide] of the nodes of level it; *n_levels = max level + 1 (device int)
+void launch_wide_level(const BNode *nodes, int64_t n_nodes, int32_t it, int32_t *level, int32_t *slot_src,
+                       int32_t *n_levels, uint32_t *status, hipStream_t st);
+// wide nodes and leaves in every binary subtree (flags and side_cnt [2 n_nodes] scratch)
+void launch_wide_count(const int32_t *leaf_parent, const int32_t *node_parent, const int32_t *level, int64_t n,
+                       int64_t n_nodes, int32_t *flags, int2 *side_cnt, int32_t *sub_w, int32_t *sub_l,
                        uint32_t *status, hipStream_t st);
-// 4-wide nodes from the refitted binary nodes
-void launch_collapse(const BNode *nodes, const uint32_t *flag, const uint32_t *idx4, int64_t n_nodes, BNode4 *out,
-                     uint32_t *status, hipStream_t st);
+// positions of the instance roots: roots[3i..3i+2] = (wide index, first descendant, first leaf)
+void launch_wide_root_pos(const int32_t *root, const int32_t *cnt, const int32_t *roots, int n_inst, int32_t *widx,
+                          int32_t *dbase, int32_t *lbase, hipStream_t st);
+// places the nodes of level it (build descriptions into info, new leaf positions into newpos)
+void launch_wide_assign(const BNode *nodes, int64_t n_nodes, int64_t n, int32_t it, const int32_t *level,
+                        const int32_t *slot_src, const int32_t *sub_w, const int32_t *sub_l, int32_t *widx,
+                        int32_t *dbase, int32_t *lbase, int32_t *newpos, WideInfo *info, int64_t n_wide,
+                        uint32_t *status, hipStream_t st);
+void launch_iota(int32_t *p, int64_t n, hipStream_t st);
+// leaf order, leaf parents (into perm2 / leaf_parent2) and binary leaf codes after the placement
+void launch_leaf_reorder(const int32_t *newpos, const int32_t *perm, const int32_t *leaf_parent, int64_t n,
+                         int64_t n_nodes, int32_t *perm2, int32_t *leaf_parent2, BNode *nodes, uint32_t *status,
+                         hipStream_t st);
+// quantised traversal nodes from the refitted binary boxes
+void launch_wide_quantize(const BNode *nodes, const WideInfo *info, int64_t n_wide, int64_t n_nodes, QNode *out,
+                          uint32_t *status, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t st);
 
@@ -104,5 +124,6 @@ void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st
 void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st);
 
 inline int kbucket(int k) { return k <= 8 ? 8 : (k <= 16 ? 16 : (k <= 32 ? 32 : 64)); }
+
 
 }  // namespace lf

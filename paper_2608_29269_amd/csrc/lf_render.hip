@@ -296,7 +296,8 @@ __device__ __forceinline__ void finish_primary(const RenderArgs &a, const SceneV
 
 template <int K, bool B>
 __global__ __launch_bounds__(kBlock) void k_trace1(RenderArgs a, bool replay) {
-  __shared__ int stk[kStack * kBlock];
+  __shared__ int stk[kStackL * kBlock];
+  __shared__ int lq[kLeafQ * kBlock];
   int64_t ray = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (!B && a.n_tiles) ray = tile_ray(*a.rays.cams);
   const ReqView v = req_view<B>(a, ray < 0 ? 0 : ray);
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_trace1(RenderArgs a, bool replay) {
   const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
   KBufF<K> kb;
   if (active) {
-    trace<K>(S, a.P, o, d, kb, stk + threadIdx.x, a.status, 0);
+    trace<K>(S, a.P, o, d, kb, stk + threadIdx.x, lq + threadIdx.x, a.status, 0);
     finish_primary<K>(a, S, v, replay, ray, kb, o, d);
   }
 }
@@ -397,7 +398,8 @@ __device__ __forceinline__ void finish_secondary(const RenderArgs &a, const Scen
 
 template <int K, bool B>
 __global__ __launch_bounds__(kBlock) void k_trace2(RenderArgs a) {
-  __shared__ int stk[kStack * kBlock];
+  __shared__ int stk[kStackL * kBlock];
+  __shared__ int lq[kLeafQ * kBlock];
   const uint32_t count = *a.queue_count;
   if (blockIdx.x * kBlock >= count) return;  // whole block past the queue
   const uint32_t slot = blockIdx.x * kBlock + threadIdx.x;
@@ -415,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_trace2(RenderArgs a) {
   if constexpr (B) S.inst = a.slots[a.chunks[e.ray / kChunk].slot].inst;
   KBufF<K> kb;
   if (active) {
-    trace<K>(S, a.P, o, w, kb, stk + threadIdx.x, a.status, 4);
+    trace<K>(S, a.P, o, w, kb, stk + threadIdx.x, lq + threadIdx.x, a.status, 4);
     finish_secondary<K>(a, S, qi, e, kb, o, w);
   }
 }

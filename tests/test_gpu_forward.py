@@ -171,12 +171,43 @@ def test_edge_cases(tracer):
     tracer.sync()
 
 
+def _check_wide(tracer, inst, leaf):
+    """Every decoded slot box of a node reachable from the root contains the
+    exact box of its subtree, and every leaf with a non-empty box is reached
+    exactly once."""
+    wb, wc = tracer.copy_wide(inst)
+    none = np.iinfo(np.int32).min
+    nonempty = np.all(leaf[:, :3] <= leaf[:, 3:], axis=1)
+    seen = np.zeros(len(leaf), int)
+    order, stack = [], [0]
+    while stack:  # pre-order over the reachable nodes
+        x = stack.pop()
+        order.append(x)
+        stack.extend(int(c) for c in wc[x] if c >= 0)
+    assert len(set(order)) == len(order), "a node reached twice"
+    exact = {}
+    for x in reversed(order):  # children before parents
+        lo = np.full(3, np.inf, np.float32)
+        hi = np.full(3, -np.inf, np.float32)
+        for i, c in enumerate(wc[x]):
+            if c == none:
+                continue
+            if c < 0:
+                seen[~c] += 1
+            b = leaf[~c] if c < 0 else exact[int(c)]
+            assert np.all(wb[x, i, :3] <= b[:3]) and np.all(wb[x, i, 3:] >= b[3:]), (x, i)
+            lo, hi = np.minimum(lo, b[:3]), np.maximum(hi, b[3:])
+        exact[x] = np.concatenate([lo, hi])
+    assert np.all(seen[nonempty] == 1) and np.all(seen[~nonempty] == 0)
+
+
 def test_bvh_structure_and_refit(tracer, c2_small):
     wl = c2_small
     ts = upload_scene(tracer, wl.scene)
     info = tracer.info()
-    # a 4-wide traversal step pushes at most 3 entries and covers two levels
-    assert 3 * ((info["max_depth"] + 1) // 2) <= info["stack_size"]
+    # a traversal step pushes at most node_width - 1 entries per level
+    assert (info["node_width"] - 1) * info["wide_levels"] <= info["stack_size"]
+    assert 1 <= info["wide_levels"] <= info["max_depth"]
 
     def check():
         boxes, ch, perm, leaf = tracer.copy_bvh(0)
@@ -201,6 +232,7 @@ def test_bvh_structure_and_refit(tracer, c2_small):
                     assert np.array_equal(boxes[i, s], union(c))
                     stack.append(c)
         assert np.all(seen == 1)
+        _check_wide(tracer, 0, leaf)
     check()
     # in-place update + refit keeps the hierarchy valid and matches the oracle
     rng = np.random.default_rng(3)
