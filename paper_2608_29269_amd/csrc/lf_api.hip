@@ -1,6 +1,7 @@
 // lf_api.hip -- host runtime behind include/lightfuse.h: context, argument
 // validation, library-owned device memory, scene build/refit and the launch
 // sequences of the forward and backward passes.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -235,6 +236,13 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
   a.status = c->status.as<uint32_t>();
   const bool trace2 = !(p->flags & LF_FLAG_NO_SECONDARY);
   const int64_t RS = R * p->spp;
+  // k-buffers handed from the traversal to the compositing launches: one per
+  // primary work item (tile positions or rays) and per secondary queue entry
+  const int64_t items = std::max(a.n_tiles > 0 ? a.n_tiles * lf::kBlock : R, trace2 ? RS : (int64_t)0);
+  if (!c->work.ensure(16) || !c->kbuf.ensure(sizeof(uint32_t) * 2 * lf::kbucket(p->k) * (items > 0 ? items : 1)))
+    return fail(c, LF_ENOMEM, "k-buffers for %lld rays", (long long)items);
+  a.work = c->work.as<uint32_t>();
+  a.kbuf = c->kbuf.as<uint32_t>();
   const int64_t R1 = R > 0 ? R : 1;
   if (!c->rec1.ensure(sizeof(lf::SurfRec) * R1)) return fail(c, LF_ENOMEM, "surface records");
   a.rec1 = c->rec1.as<lf::SurfRec>();

@@ -235,31 +235,57 @@ __device__ void adjoint_hits(const RenderArgs &a, const GradArgs &G, const AdjSe
   }
 }
 
+// rays with a non-zero compositing seed as a pool of work items
+__device__ __forceinline__ int64_t adj_items(const RenderArgs &a) { return a.n_tiles ? a.n_tiles * kBlock : a.R; }
+__device__ __forceinline__ int64_t adj_ray(const RenderArgs &a, int64_t item) {
+  const int64_t ray = a.n_tiles ? tile_ray(*a.rays.cams, item) : item;
+  return (ray >= 0 && ray < a.R && a.seeds[ray].pad[0] != 0.0f) ? ray : -1;
+}
+
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_adj_trace(RenderArgs a, GradArgs G) {
+struct AdjointWork {
+  const RenderArgs &a;
+  __device__ bool begin(int64_t item, d3 &o, d3 &d, const InstRec *&inst) const {
+    const int64_t ray = adj_ray(a, item);
+    if (ray < 0) return false;
+    float of[3], df[3];
+    load_ray(a.rays, ray, of, df);
+    o = mk(of[0], of[1], of[2]);
+    d = mk(df[0], df[1], df[2]);
+    inst = a.S.inst;
+    return true;
+  }
+  __device__ void store(int64_t item, const KBufF<K> &kb) const { store_kbuf<K>(kb, a.kbuf + item * 2 * K); }
+};
+
+template <int K>
+__global__ __launch_bounds__(kBlock, 2) void k_adj_trace(RenderArgs a) {
   __shared__ int stk[kStackL * kBlock];
   __shared__ int lq[kLeafQ * kBlock];
-  const int64_t ray = a.n_tiles ? tile_ray(*a.rays.cams) : (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  bool active = ray >= 0 && ray < a.R;
-  AdjSeed sd = {};
-  if (active) {
-    sd = a.seeds[ray];
-    active = sd.pad[0] != 0.0f;
-  }
-  float of[3] = {0, 0, 0}, df[3] = {0, 0, 1};
-  if (active) load_ray(a.rays, ray, of, df);
-  const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
+  const AdjointWork<K> wk{a};
+  trace_pool<K>(a.S, a.P, wk, adj_items(a), a.work, stk + threadIdx.x, lq + threadIdx.x, a.status, 0);
+}
+
+// compositing adjoint of every seeded ray from its replayed k-buffer
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_adj_hits(RenderArgs a, GradArgs G) {
+  const int64_t item = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (item >= adj_items(a)) return;
+  const int64_t ray = adj_ray(a, item);
+  if (ray < 0) return;
+  float of[3], df[3];
+  load_ray(a.rays, ray, of, df);
   KBufF<K> kb;
-  if (active) {
-    trace<K>(a.S, a.P, o, d, kb, stk + threadIdx.x, lq + threadIdx.x, a.status, 0);
-    adjoint_hits<K>(a, G, sd, kb, o, d);
-  }
+  load_kbuf<K>(kb, a.kbuf + item * 2 * K);
+  adjoint_hits<K>(a, G, a.seeds[ray], kb, mk(of[0], of[1], of[2]), mk(df[0], df[1], df[2]));
 }
 
 template <int K>
 void adjoint_k(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
-  const unsigned nb = a.n_tiles ? (unsigned)a.n_tiles : blocks(a.R, kBlock);
-  hipLaunchKernelGGL(k_adj_trace<K>, dim3(nb), dim3(kBlock), 0, st, a, g);
+  const int64_t items = a.n_tiles ? a.n_tiles * kBlock : a.R;
+  launch_fill_u32(a.work, 0u, 1, st);
+  hipLaunchKernelGGL(k_adj_trace<K>, dim3(pool_blocks<k_adj_trace<K>>(items)), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL(k_adj_hits<K>, dim3(blocks(items, kBlock)), dim3(kBlock), 0, st, a, g);
 }
 
 }  // namespace

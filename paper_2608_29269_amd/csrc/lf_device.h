@@ -119,17 +119,20 @@ __device__ __forceinline__ void load_ray(const RaySource &rs, int64_t id, float 
   }
 }
 
-// Camera ray of this thread in a primary traversal launch over 16x8-pixel
-// tiles (one per 128-thread block; each wave64 covers an 8x8 half, so a
-// wave's rays are spatially compact).  -1 for a thread outside the image.
-__device__ __forceinline__ int64_t tile_ray(const CamArgs &ca) {
+// Camera ray of work item `item` when primary rays are traced in 16x8-pixel
+// tiles: items 128t..128t+127 cover tile t (row-major over each camera's
+// tiles), the first 64 its left 8x8 half, so consecutive items are spatially
+// compact.  -1 for an item outside the image.
+__device__ __forceinline__ int64_t tile_ray(const CamArgs &ca, int64_t item) {
+  const int64_t tile = item / kBlock;
+  const int within = (int)(item % kBlock);
   int c = 0;
-  while (c + 1 < ca.n_cams && (int64_t)blockIdx.x >= ca.tiles[c + 1]) ++c;
-  const int64_t lt = (int64_t)blockIdx.x - ca.tiles[c];
+  while (c + 1 < ca.n_cams && tile >= ca.tiles[c + 1]) ++c;
+  const int64_t lt = tile - ca.tiles[c];
   const int nx = (ca.w[c] + 15) / 16;
   const int tx = (int)(lt % nx), ty = (int)(lt / nx);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int x = tx * 16 + wave * 8 + (lane & 7), y = ty * 8 + (lane >> 3);
+  const int lane = within & 63, half = within >> 6;
+  const int x = tx * 16 + half * 8 + (lane & 7), y = ty * 8 + (lane >> 3);
   if (x >= ca.w[c] || y >= ca.h[c]) return -1;
   return ca.first[c] + (int64_t)y * ca.w[c] + x;
 }
@@ -165,6 +168,31 @@ __device__ __forceinline__ void kinit(KBufF<K> &b, int k) {
 // and keeps t[j] otherwise.  Slots are updated from the top down so t[j-1] is
 // still the old value; every slot's comparisons are independent.  Only used
 // for a key equal to no key in the buffer.
+// k-buffer of one ray in device memory: t[K] then id[K] (2K words)
+template <int K>
+__device__ __forceinline__ void store_kbuf(const KBufF<K> &b, uint32_t *out) {
+  uint4 *o = (uint4 *)out;
+#pragma unroll
+  for (int j = 0; j < K / 4; ++j)
+    o[j] = make_uint4(__float_as_uint(b.t[4 * j]), __float_as_uint(b.t[4 * j + 1]), __float_as_uint(b.t[4 * j + 2]),
+                      __float_as_uint(b.t[4 * j + 3]));
+#pragma unroll
+  for (int j = 0; j < K / 4; ++j) o[K / 4 + j] = make_uint4(b.id[4 * j], b.id[4 * j + 1], b.id[4 * j + 2], b.id[4 * j + 3]);
+}
+
+template <int K>
+__device__ __forceinline__ void load_kbuf(KBufF<K> &b, const uint32_t *in) {
+  const uint4 *p = (const uint4 *)in;
+#pragma unroll
+  for (int j = 0; j < K / 4; ++j) {
+    const uint4 v = p[j];
+    b.t[4 * j] = __uint_as_float(v.x); b.t[4 * j + 1] = __uint_as_float(v.y);
+    b.t[4 * j + 2] = __uint_as_float(v.z); b.t[4 * j + 3] = __uint_as_float(v.w);
+    const uint4 w = p[K / 4 + j];
+    b.id[4 * j] = w.x; b.id[4 * j + 1] = w.y; b.id[4 * j + 2] = w.z; b.id[4 * j + 3] = w.w;
+  }
+}
+
 template <int K>
 __device__ __forceinline__ void kinsert(KBufF<K> &b, float t, uint32_t id) {
 #pragma unroll
@@ -512,25 +540,34 @@ __device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3
 template <int K>
 __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K - 1]; }
 
-// Collects the k closest valid hits of the world ray (o, d) over all
-// instances into kb.  stk points at this lane's first LDS stack slot (stride
-// kBlock, kStackL entries; deeper entries go to private scratch) and lq at
-// its first leaf-queue slot (stride kBlock, kLeafQ entries).
-//
+// Persistent traversal of a pool of `count` work items (rays): every lane
+// holds one ray at a time, collects its k closest valid hits over all
+// instances and stores them with wk.store; a wave refills its idle lanes from
+// the shared counter *next once kRefillIdle of them are idle (or all are), so
+// the rays of a wave need not finish together.  Work supplies
+//   bool begin(int64_t item, d3 &o, d3 &d, const InstRec *&inst)  (false: nothing to trace)
+//   void store(int64_t item, const KBufF<K> &kb)
 // Traversal of an instance runs in rounds of two phases (after Aila and
 // Laine 2009, "while-while"): in the node phase a lane visits nodes, its hit
 // leaves join its leaf queue and its nearest hit internal child is visited
 // next (the others are pushed), while some lane that can still visit nodes
 // has no leaf queued; a lane pauses while its queue could not take a whole
-// node's leaves.  The leaf phase then tests every queued leaf.  The stack
-// holds internal nodes only.
-template <int K, class B>
-__device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &kb, int *stk, int *lq,
-                      uint32_t *status, int counter_base = 0) {
-  kinit<K>(kb, P.k);
+// node's leaves.  The leaf phase then tests every queued leaf.  stk points at
+// this lane's first LDS stack slot (stride kBlock, kStackL entries; deeper
+// entries in private scratch; internal nodes only) and lq at its first
+// leaf-queue slot (stride kBlock, kLeafQ entries).  Every lane leaves once
+// the pool is empty and its last ray is stored.
+constexpr int kRefillIdle = 4;
+
+template <int K, class Work>
+__device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work &wk, int64_t count, uint32_t *next,
+                           int *stk, int *lq, uint32_t *status, int counter_base) {
+  constexpr int kDone = (int)0x80000000;  // no node to visit
   const bool brute = (P.flags & LF_FLAG_BRUTE_FORCE) != 0;
   const float t_min_f = round_down_f(P.t_min);
-  uint32_t c_nodes = 0, c_tests = 0, c_ins = 0, c_ties = 0, c_pass = 0, c_hits = 0;
+  const float tlo = (float)(0.5 * P.t_min);
+  const int lane = (int)(threadIdx.x & 63u);
+  uint32_t c_rays = 0, c_nodes = 0, c_tests = 0, c_ins = 0, c_ties = 0, c_pass = 0, c_hits = 0;
   auto count_test = [&](int r) {
     c_ins += r & 1;
     c_ties += (r >> 1) & 1;
@@ -539,104 +576,151 @@ __device__ void trace(const SceneView &S, const TraceParams &P, d3 o, d3 d, B &k
     ++c_tests;
   };
   int spill[kStack - kStackL];
-  for (int ii = 0; ii < S.n_inst; ++ii) {
-    const InstRec &I = S.inst[ii];
-    if (I.n <= 0) continue;
-    double itn, itf;
-    if (!slab64(o, d, I.lo, I.hi, itn, itf)) continue;
-    if (itf < P.t_min) continue;
-    if (itn > kth<K>(kb) * (1.0 + 1e-6)) continue;
-    d3 oo, dd;
-    to_object(I, o, d, oo, dd);
-    RayF rf;
-    make_rayf(oo, dd, fmax(fabs(itf), fabs(itn)), rf);
-    if (brute) {
-      const int end = I.first + I.n <= S.n_rec ? I.first + I.n : S.n_rec;
-      for (int pos = I.first < 0 ? 0 : I.first; pos < end; ++pos)
-        count_test(test_surfel<K>(S, pos, oo, dd, rf, P.t_min, t_min_f, kb, o, d));
+  int sp = 0;
+  auto push = [&](int v) {
+    if (sp < kStackL) stk[sp * kBlock] = v;
+    else spill[sp - kStackL] = v;
+    ++sp;
+  };
+  auto pop = [&]() -> int {
+    --sp;
+    return sp < kStackL ? stk[sp * kBlock] : spill[sp - kStackL];
+  };
+  SceneView S = S0;
+  KBufF<K> kb;
+  kinit<K>(kb, P.k);
+  int64_t item = -1;
+  bool live = false;       // this lane holds a ray
+  bool exhausted = false;  // the pool is empty (uniform over the wave)
+  int ii = 0;              // the ray's current instance
+  d3 o = mk(0, 0, 0), d = mk(0, 0, 1), oo = o, dd = d;
+  RayF rf;
+  make_rayf(oo, dd, 0.0, rf);
+  int cur = kDone, qn = 0;
+  while (true) {
+    // idle lanes take the next items, one counter update per wave
+    if (!exhausted) {
+      const unsigned long long idle = __ballot(!live);
+      const int n_idle = __popcll(idle);
+      if (n_idle >= kRefillIdle || (n_idle > 0 && !__any(live))) {
+        const int leader = __ffsll((long long)idle) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(next, (uint32_t)n_idle);
+        base = (uint32_t)__shfl((int)base, leader);
+        if ((int64_t)base + n_idle >= count) exhausted = true;
+        if (!live) {
+          const int64_t it = (int64_t)base + __popcll(idle & ((1ull << lane) - 1ull));
+          if (it < count) {
+            item = it;
+            live = wk.begin(item, o, d, S.inst);
+            if (live) {
+              ++c_rays;
+              kinit<K>(kb, P.k);
+              ii = -1;
+              cur = kDone;
+              qn = 0;
+            }
+          }
+        }
+      }
+    }
+    // a lane done with an instance moves to the next one its ray enters, or stores the ray's hits
+    if (live && cur == kDone && qn == 0) {
+      bool found = false;
+      while (++ii < S.n_inst) {
+        const InstRec &I = S.inst[ii];
+        if (I.n <= 0) continue;
+        double itn, itf;
+        if (!slab64(o, d, I.lo, I.hi, itn, itf)) continue;
+        if (itf < P.t_min) continue;
+        if (itn > kth<K>(kb) * (1.0 + 1e-6)) continue;
+        to_object(I, o, d, oo, dd);
+        make_rayf(oo, dd, fmax(fabs(itf), fabs(itn)), rf);
+        found = true;
+        break;
+      }
+      if (!found) {
+        wk.store(item, kb);
+        live = false;
+      } else if (brute) {  // every surfel of the instance; the next round moves on
+        const InstRec &I = S.inst[ii];
+        const int end = I.first + I.n <= S.n_rec ? I.first + I.n : S.n_rec;
+        for (int pos = I.first < 0 ? 0 : I.first; pos < end; ++pos)
+          count_test(test_surfel<K>(S, pos, oo, dd, rf, P.t_min, t_min_f, kb, o, d));
+      } else {
+        cur = S.inst[ii].root;
+        sp = 0;
+        if (cur < 0) {  // a one-surfel instance
+          lq[0] = cur;
+          qn = 1;
+          cur = kDone;
+        }
+      }
+    }
+    if (!__any(live)) {
+      if (exhausted) break;
       continue;
     }
-    const float tlo = (float)(0.5 * P.t_min);
-    constexpr int kDone = (int)0x80000000;  // no node to visit
-    int sp = 0;
-    auto push = [&](int v) {
-      if (sp < kStackL) stk[sp * kBlock] = v;
-      else spill[sp - kStackL] = v;
-      ++sp;
-    };
-    auto pop = [&]() -> int {
-      --sp;
-      return sp < kStackL ? stk[sp * kBlock] : spill[sp - kStackL];
-    };
-    int cur = I.root;  // >= 0 node, < 0 (one surfel) leaf
-    int qn = 0;
-    if (cur < 0) {
-      lq[0] = cur;
-      qn = 1;
-      cur = kDone;
-    }
-    while (cur != kDone || qn > 0) {
-      // node phase
-      while (true) {
-        const bool can = cur >= 0 && qn <= kLeafQ - kWide;
-        if (!__any(can && qn == 0)) break;
-        if (!can) continue;
-        if (cur >= S.n_nodes) {  // never taken for a consistent hierarchy
-          atomicOr(status, kStatusBvhCorrupt);
-          cur = kDone;
-          continue;
-        }
-        ++c_nodes;
-        // the exact k-th distance is at most the successor of the k-th binary32 key
-        const float tkf = kb.t[K - 1];
-        const float thi = tkf < INFINITY ? next_up_f(tkf) * (1.0f + 1e-6f) : INFINITY;
-        float ts[kWide];
-        int cs[kWide];
-        uint32_t ih, lh;
-        visit_node(S.nodes + cur, rf, tlo, thi, ts, cs, ih, lh);
-#pragma unroll
-        for (int j = 0; j < kWide; ++j)
-          if ((lh >> j) & 1u) lq[(qn++) * kBlock] = cs[j];
-        if (ih == 0) {
-          cur = sp ? pop() : kDone;
-          continue;
-        }
-        if (sp + __builtin_popcount(ih) - 1 > kStack) {
-          atomicOr(status, kStatusOverflow);
-          cur = kDone;
-          continue;
-        }
-        // the nearest hit internal child next, the others onto the stack
-        float best = INFINITY;
-        int bj = 0;
-#pragma unroll
-        for (int j = 0; j < kWide; ++j)
-          if (((ih >> j) & 1u) && ts[j] < best) {
-            best = ts[j];
-            bj = j;
-          }
-#pragma unroll
-        for (int j = 0; j < kWide; ++j)
-          if (((ih >> j) & 1u) && j != bj) push(cs[j]);
-        int nxt = cs[0];
-#pragma unroll
-        for (int j = 1; j < kWide; ++j) nxt = j == bj ? cs[j] : nxt;
-        cur = nxt;
+    // node phase
+    while (true) {
+      const bool can = cur >= 0 && qn <= kLeafQ - kWide;
+      if (!__any(can && qn == 0)) break;
+      if (!can) continue;
+      if (cur >= S.n_nodes) {  // never taken for a consistent hierarchy
+        atomicOr(status, kStatusBvhCorrupt);
+        cur = kDone;
+        continue;
       }
-      // leaf phase
-      for (int j = 0; j < qn; ++j) {
-        const int leaf = lq[j * kBlock];
-        if (~leaf >= S.n_rec) {  // never taken for a consistent hierarchy
-          atomicOr(status, kStatusBvhCorrupt);
-          continue;
-        }
-        count_test(test_surfel<K>(S, ~leaf, oo, dd, rf, P.t_min, t_min_f, kb, o, d));
+      ++c_nodes;
+      // the exact k-th distance is at most the successor of the k-th binary32 key
+      const float tkf = kb.t[K - 1];
+      const float thi = tkf < INFINITY ? next_up_f(tkf) * (1.0f + 1e-6f) : INFINITY;
+      float ts[kWide];
+      int cs[kWide];
+      uint32_t ih, lh;
+      visit_node(S.nodes + cur, rf, tlo, thi, ts, cs, ih, lh);
+#pragma unroll
+      for (int j = 0; j < kWide; ++j)
+        if ((lh >> j) & 1u) lq[(qn++) * kBlock] = cs[j];
+      if (ih == 0) {
+        cur = sp ? pop() : kDone;
+        continue;
       }
-      qn = 0;
+      if (sp + __builtin_popcount(ih) - 1 > kStack) {
+        atomicOr(status, kStatusOverflow);
+        cur = kDone;
+        continue;
+      }
+      // the nearest hit internal child next, the others onto the stack
+      float best = INFINITY;
+      int bj = 0;
+#pragma unroll
+      for (int j = 0; j < kWide; ++j)
+        if (((ih >> j) & 1u) && ts[j] < best) {
+          best = ts[j];
+          bj = j;
+        }
+#pragma unroll
+      for (int j = 0; j < kWide; ++j)
+        if (((ih >> j) & 1u) && j != bj) push(cs[j]);
+      int nxt = cs[0];
+#pragma unroll
+      for (int j = 1; j < kWide; ++j) nxt = j == bj ? cs[j] : nxt;
+      cur = nxt;
     }
+    // leaf phase
+    for (int j = 0; j < qn; ++j) {
+      const int leaf = lq[j * kBlock];
+      if (~leaf >= S.n_rec) {  // never taken for a consistent hierarchy
+        atomicOr(status, kStatusBvhCorrupt);
+        continue;
+      }
+      count_test(test_surfel<K>(S, ~leaf, oo, dd, rf, P.t_min, t_min_f, kb, o, d));
+    }
+    qn = 0;
   }
-  if (P.counters) {
-    atomicAdd(P.counters + counter_base + 0, 1ull);
+  if (P.counters && c_rays) {
+    atomicAdd(P.counters + counter_base + 0, (unsigned long long)c_rays);
     atomicAdd(P.counters + counter_base + 1, (unsigned long long)c_nodes);
     atomicAdd(P.counters + counter_base + 2, (unsigned long long)c_tests);
     atomicAdd(P.counters + counter_base + 3, (unsigned long long)c_ins);

@@ -12,7 +12,7 @@ constexpr int kBlock = 128;       // threads per block of the tracing kernels (2
 constexpr int kWide = 8;          // children per traversal node
 constexpr int kStackL = 48;       // traversal stack entries per lane held in LDS (24 KB per block)
 constexpr int kStack = 192;       // traversal stack entries per lane; those past kStackL in private scratch
-constexpr int kLeafQ = 16;        // leaf-queue entries per lane (LDS, 8 KB per block)
+constexpr int kLeafQ = 32;        // leaf-queue entries per lane (LDS, 16 KB per block)
 constexpr int kMaxInst = 64;      // background + up to 63 objects
 constexpr uint32_t kFlipBit = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7fffffffu;

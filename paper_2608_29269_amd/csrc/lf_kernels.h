@@ -1,5 +1,7 @@
 // lf_kernels.h -- host-side launchers of the gfx950 kernels (internal).
 #pragma once
+#include <atomic>
+
 #include "lf_internal.h"
 
 namespace lf {
@@ -96,6 +98,8 @@ struct RenderArgs {
   SecFrozen *frozen;    // [R*S] (backward replay)
   AdjSeed *seeds;       // [R] (backward)
   uint32_t *status;
+  uint32_t *work;       // item counter of the persistent traversal launches (cleared before each)
+  uint32_t *kbuf;       // [items, 2K] k-buffers from traversal to compositing (t[K], then ids[K])
   // per-ray sample stride of contrib / frozen and of the queue capacity (spp, or the batch maximum)
   int32_t spp_stride;
   // continuous batching (NULL for one request): R = kChunk * number of chunks
@@ -124,6 +128,35 @@ void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st
 void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st);
 
 inline int kbucket(int k) { return k <= 8 ? 8 : (k <= 16 ? 16 : (k <= 32 ? 32 : 64)); }
+
+// Blocks of a persistent launch of kernel Kern (kBlock threads): as many as
+// can be resident at once on the current device, at most one per kBlock
+// items, at least one.  The residency is looked up once per device.
+template <auto Kern>
+inline unsigned pool_blocks(int64_t items) {
+  static std::atomic<int> resident[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
+  int nb = (dev >= 0 && dev < 64) ? resident[dev].load(std::memory_order_relaxed) : 0;
+  if (nb <= 0) {
+    int cu = 0, per = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1) {
+      (void)hipGetLastError();
+      cu = 1;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, Kern, kBlock, 0) != hipSuccess || per < 1) {
+      (void)hipGetLastError();
+      per = 1;
+    }
+    nb = cu * per;
+    if (dev >= 0 && dev < 64) resident[dev].store(nb, std::memory_order_relaxed);
+  }
+  const int64_t need = (items + kBlock - 1) / kBlock;
+  return (unsigned)(need < 1 ? 1 : (need < nb ? need : nb));
+}
 
 
 }  // namespace lf

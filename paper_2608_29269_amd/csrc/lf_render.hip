@@ -294,24 +294,60 @@ __device__ __forceinline__ void finish_primary(const RenderArgs &a, const SceneV
   if (a.hit_idx) write_hits<K>(S, kb, a.P.k, a.hit_idx + ray * a.P.k);
 }
 
+// primary rays as a pool of work items: tiles of the cameras, batch chunks, or explicit rays
+template <bool B>
+__device__ __forceinline__ int64_t primary_items(const RenderArgs &a) {
+  return (!B && a.n_tiles) ? a.n_tiles * kBlock : a.R;
+}
+template <bool B>
+__device__ __forceinline__ int64_t primary_ray(const RenderArgs &a, int64_t item) {
+  if constexpr (!B)
+    if (a.n_tiles) return tile_ray(*a.rays.cams, item);
+  return item;
+}
+
 template <int K, bool B>
-__global__ __launch_bounds__(kBlock) void k_trace1(RenderArgs a, bool replay) {
+struct PrimaryWork {
+  const RenderArgs &a;
+  __device__ bool begin(int64_t item, d3 &o, d3 &d, const InstRec *&inst) const {
+    const int64_t ray = primary_ray<B>(a, item);
+    if (ray < 0) return false;
+    const ReqView v = req_view<B>(a, ray);
+    if (!v.valid) return false;
+    float of[3], df[3];
+    req_ray<B>(a, ray, v, of, df);
+    o = mk(of[0], of[1], of[2]);
+    d = mk(df[0], df[1], df[2]);
+    inst = v.inst;
+    return true;
+  }
+  __device__ void store(int64_t item, const KBufF<K> &kb) const { store_kbuf<K>(kb, a.kbuf + item * 2 * K); }
+};
+
+template <int K, bool B>
+__global__ __launch_bounds__(kBlock, 2) void k_trace1(RenderArgs a) {
   __shared__ int stk[kStackL * kBlock];
   __shared__ int lq[kLeafQ * kBlock];
-  int64_t ray = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (!B && a.n_tiles) ray = tile_ray(*a.rays.cams);
-  const ReqView v = req_view<B>(a, ray < 0 ? 0 : ray);
+  const PrimaryWork<K, B> wk{a};
+  trace_pool<K>(a.S, a.P, wk, primary_items<B>(a), a.work, stk + threadIdx.x, lq + threadIdx.x, a.status, 0);
+}
+
+// compositing of every primary ray's k-buffer, record and outputs
+template <int K, bool B>
+__global__ __launch_bounds__(kBlock) void k_composite1(RenderArgs a, bool replay) {
+  const int64_t item = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (item >= primary_items<B>(a)) return;
+  const int64_t ray = primary_ray<B>(a, item);
+  if (ray < 0) return;
+  const ReqView v = req_view<B>(a, ray);
+  if (!v.valid) return;
+  float of[3], df[3];
+  req_ray<B>(a, ray, v, of, df);
+  KBufF<K> kb;
+  load_kbuf<K>(kb, a.kbuf + item * 2 * K);
   SceneView S = a.S;
   S.inst = v.inst;
-  const bool active = ray >= 0 && v.valid;
-  float of[3] = {0, 0, 0}, df[3] = {0, 0, 1};
-  if (active) req_ray<B>(a, ray, v, of, df);
-  const d3 o = mk(of[0], of[1], of[2]), d = mk(df[0], df[1], df[2]);
-  KBufF<K> kb;
-  if (active) {
-    trace<K>(S, a.P, o, d, kb, stk + threadIdx.x, lq + threadIdx.x, a.status, 0);
-    finish_primary<K>(a, S, v, replay, ray, kb, o, d);
-  }
+  finish_primary<K>(a, S, v, replay, ray, kb, mk(of[0], of[1], of[2]), mk(df[0], df[1], df[2]));
 }
 
 // ---------------------------------------------------------------- primary shading
@@ -396,30 +432,40 @@ __device__ __forceinline__ void finish_secondary(const RenderArgs &a, const Scen
   }
 }
 
+// the (regrouped) secondary queue as a pool of work items
 template <int K, bool B>
-__global__ __launch_bounds__(kBlock) void k_trace2(RenderArgs a) {
-  __shared__ int stk[kStackL * kBlock];
-  __shared__ int lq[kLeafQ * kBlock];
-  const uint32_t count = *a.queue_count;
-  if (blockIdx.x * kBlock >= count) return;  // whole block past the queue
-  const uint32_t slot = blockIdx.x * kBlock + threadIdx.x;
-  const bool active = slot < count;
-  const uint32_t qi = active ? (a.order ? (uint32_t)a.order[slot] : slot) : 0u;
-  SecEntry e;
-  e.ray = 0;
-  d3 o = mk(0, 0, 0), w = mk(0, 0, 1);
-  if (active) {
-    e = a.queue[qi];
+struct SecondaryWork {
+  const RenderArgs &a;
+  __device__ bool begin(int64_t item, d3 &o, d3 &w, const InstRec *&inst) const {
+    const SecEntry &e = a.queue[a.order ? (uint32_t)a.order[item] : (uint32_t)item];
     o = mk(e.o[0], e.o[1], e.o[2]);
     w = mk(e.w[0], e.w[1], e.w[2]);
+    if constexpr (B) inst = a.slots[a.chunks[e.ray / kChunk].slot].inst;
+    else inst = a.S.inst;
+    return true;
   }
+  __device__ void store(int64_t item, const KBufF<K> &kb) const { store_kbuf<K>(kb, a.kbuf + item * 2 * K); }
+};
+
+template <int K, bool B>
+__global__ __launch_bounds__(kBlock, 2) void k_trace2(RenderArgs a) {
+  __shared__ int stk[kStackL * kBlock];
+  __shared__ int lq[kLeafQ * kBlock];
+  const SecondaryWork<K, B> wk{a};
+  trace_pool<K>(a.S, a.P, wk, (int64_t)*a.queue_count, a.work, stk + threadIdx.x, lq + threadIdx.x, a.status, 4);
+}
+
+template <int K, bool B>
+__global__ __launch_bounds__(kBlock) void k_composite2(RenderArgs a) {
+  const uint32_t item = blockIdx.x * kBlock + threadIdx.x;
+  if (item >= *a.queue_count) return;
+  const uint32_t qi = a.order ? (uint32_t)a.order[item] : item;
+  const SecEntry e = a.queue[qi];
   SceneView S = a.S;
   if constexpr (B) S.inst = a.slots[a.chunks[e.ray / kChunk].slot].inst;
   KBufF<K> kb;
-  if (active) {
-    trace<K>(S, a.P, o, w, kb, stk + threadIdx.x, lq + threadIdx.x, a.status, 4);
-    finish_secondary<K>(a, S, qi, e, kb, o, w);
-  }
+  load_kbuf<K>(kb, a.kbuf + (int64_t)item * 2 * K);
+  finish_secondary<K>(a, S, qi, e, kb, mk(e.o[0], e.o[1], e.o[2]), mk(e.w[0], e.w[1], e.w[2]));
 }
 
 // ---------------------------------------------------------------- secondary shading
@@ -511,13 +557,17 @@ __global__ void k_zero_f64(double *p) { *p = 0.0; }
 
 template <int K, bool B>
 void trace1_k(const RenderArgs &a, bool replay, hipStream_t st) {
-  const unsigned nb = (!B && a.n_tiles) ? (unsigned)a.n_tiles : blocks(a.R, kBlock);
-  hipLaunchKernelGGL((k_trace1<K, B>), dim3(nb), dim3(kBlock), 0, st, a, replay);
+  const int64_t items = (!B && a.n_tiles) ? a.n_tiles * kBlock : a.R;
+  launch_fill_u32(a.work, 0u, 1, st);
+  hipLaunchKernelGGL((k_trace1<K, B>), dim3(pool_blocks<k_trace1<K, B>>(items)), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL((k_composite1<K, B>), dim3(blocks(items, kBlock)), dim3(kBlock), 0, st, a, replay);
 }
 template <int K, bool B>
 void trace2_k(const RenderArgs &a, hipStream_t st) {
   const int64_t cap = a.R * a.spp_stride;
-  hipLaunchKernelGGL((k_trace2<K, B>), dim3(blocks(cap, kBlock)), dim3(kBlock), 0, st, a);
+  launch_fill_u32(a.work, 0u, 1, st);
+  hipLaunchKernelGGL((k_trace2<K, B>), dim3(pool_blocks<k_trace2<K, B>>(cap)), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL((k_composite2<K, B>), dim3(blocks(cap, kBlock)), dim3(kBlock), 0, st, a);
 }
 template <bool B>
 void trace1_b(const RenderArgs &a, bool replay, hipStream_t st) {
