@@ -256,13 +256,15 @@ lf_status lf_trace_counters(lf_ctx *ctx, uint64_t *counters /*[LF_NUM_COUNTERS]*
 /* Per-phase device timers.  When enabled, every phase below is bracketed by
  * HIP events on the context's stream; lf_profile_read synchronises, returns
  * the accumulated milliseconds and launch counts per phase and resets them.
- * Phases: 0 refit, 1 state and environment tables, 2 primary traversal and
- * compositing, 3 primary shading, 4 secondary regrouping, 5 secondary
- * traversal and compositing, 6 secondary shading, 7 resolve, 8 replay of the
- * primary pass, 9 replay of the secondary pass, 10 shading adjoint,
- * 11 traversal and compositing adjoint, 12 gradient zeroing, 13 loss.
- * Phases 2, 5 and 11 each hold exactly one kernel launch per call. */
-#define LF_NUM_PHASES 14
+ * Phases: 0 refit, 1 state and environment tables, 2 primary traversal,
+ * 3 primary shading, 4 secondary regrouping, 5 secondary traversal,
+ * 6 secondary shading, 7 resolve, 8 replay of the primary pass, 9 replay of
+ * the secondary pass, 10 shading adjoint, 11 replayed traversal of the
+ * seeded rays, 12 gradient zeroing, 13 loss, 14 primary compositing,
+ * 15 secondary compositing, 16 compositing adjoint.  Phases 2, 5 and 11 each
+ * hold one traversal kernel launch per call (after clearing its work counter),
+ * phases 14 to 16 one compositing kernel launch. */
+#define LF_NUM_PHASES 17
 lf_status lf_profile_enable(lf_ctx *ctx, int enable);
 lf_status lf_profile_read(lf_ctx *ctx, double *ms /*[LF_NUM_PHASES]*/, int64_t *count /*[LF_NUM_PHASES]*/);
 

@@ -101,9 +101,9 @@ class ServerStats(C.Structure):
                 ("rays_secondary", C.c_int64), ("iterations", C.c_int64)]
 
 
-NUM_PHASES = 14
+NUM_PHASES = 17
 PHASES = ("refit", "state_env", "trace1", "shade1", "sort2", "trace2", "shade2", "resolve", "replay_primary",
-          "replay_secondary", "adj_shade", "adj_trace", "zero_grads", "loss")
+          "replay_secondary", "adj_shade", "adj_trace", "zero_grads", "loss", "composite1", "composite2", "adj_hits")
 
 # every symbol include/lightfuse.h declares, with its ctypes signature
 SIGNATURES = {

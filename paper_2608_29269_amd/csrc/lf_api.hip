@@ -539,7 +539,11 @@ lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, co
   }
   {
     Phase ph(c, 2);
-    lf::launch_trace1(a, false, c->stream);
+    lf::launch_trace1(a, c->stream);
+  }
+  {
+    Phase ph(c, 14);
+    lf::launch_composite1(a, false, c->stream);
   }
   {
     Phase ph(c, 3);
@@ -553,6 +557,10 @@ lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, co
     {
       Phase ph(c, 5);
       lf::launch_trace2(a, c->stream);
+    }
+    {
+      Phase ph(c, 15);
+      lf::launch_composite2(a, c->stream);
     }
     {
       Phase ph(c, 6);
@@ -601,13 +609,15 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
   a.frozen = trace2 ? c->frozen.as<lf::SecFrozen>() : nullptr;
   {
     Phase ph(c, 8);
-    lf::launch_trace1(a, true, s);
+    lf::launch_trace1(a, s);
+    lf::launch_composite1(a, true, s);
     if (trace2) lf::launch_shade1(a, true, s);
   }
   if (trace2) {
     Phase ph(c, 9);
     sort_secondaries(c, a);
     lf::launch_trace2(a, s);
+    lf::launch_composite2(a, s);
     lf::launch_shade2(a, true, s);
   }
   lf::GradArgs ga{g->d_radiance, g->d_depth, g->d_normal, g->d_alpha, gi->d_mu, gi->d_q, gi->d_scale,
@@ -618,7 +628,11 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
   }
   {
     Phase ph(c, 11);
-    lf::launch_adjoint_trace(a, ga, s);
+    lf::launch_adjoint_trace(a, s);
+  }
+  {
+    Phase ph(c, 16);
+    lf::launch_adjoint_hits(a, ga, s);
   }
   return check_hip(c, "backward");
 }

@@ -237,6 +237,7 @@ __device__ void adjoint_hits(const RenderArgs &a, const GradArgs &G, const AdjSe
 
 // rays with a non-zero compositing seed as a pool of work items
 __device__ __forceinline__ int64_t adj_items(const RenderArgs &a) { return a.n_tiles ? a.n_tiles * kBlock : a.R; }
+inline int64_t adj_items_host(const RenderArgs &a) { return a.n_tiles ? a.n_tiles * kBlock : a.R; }
 __device__ __forceinline__ int64_t adj_ray(const RenderArgs &a, int64_t item) {
   const int64_t ray = a.n_tiles ? tile_ray(*a.rays.cams, item) : item;
   return (ray >= 0 && ray < a.R && a.seeds[ray].pad[0] != 0.0f) ? ray : -1;
@@ -281,11 +282,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_hits(RenderArgs a, GradArgs G) {
 }
 
 template <int K>
-void adjoint_k(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
-  const int64_t items = a.n_tiles ? a.n_tiles * kBlock : a.R;
+void adjoint_trace_k(const RenderArgs &a, hipStream_t st) {
   launch_fill_u32(a.work, 0u, 1, st);
-  hipLaunchKernelGGL(k_adj_trace<K>, dim3(pool_blocks<k_adj_trace<K>>(items)), dim3(kBlock), 0, st, a);
-  hipLaunchKernelGGL(k_adj_hits<K>, dim3(blocks(items, kBlock)), dim3(kBlock), 0, st, a, g);
+  hipLaunchKernelGGL(k_adj_trace<K>, dim3(pool_blocks<k_adj_trace<K>>(adj_items_host(a))), dim3(kBlock), 0, st, a);
+}
+
+template <int K>
+void adjoint_hits_k(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_hits<K>, dim3(blocks(adj_items_host(a), kBlock)), dim3(kBlock), 0, st, a, g);
 }
 
 }  // namespace
@@ -295,13 +299,23 @@ void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st
   hipLaunchKernelGGL(k_adj_shade, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, g);
 }
 
-void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
+void launch_adjoint_trace(const RenderArgs &a, hipStream_t st) {
   if (a.R <= 0) return;
   switch (kbucket(a.P.k)) {
-    case 8: adjoint_k<8>(a, g, st); break;
-    case 16: adjoint_k<16>(a, g, st); break;
-    case 32: adjoint_k<32>(a, g, st); break;
-    default: adjoint_k<64>(a, g, st); break;
+    case 8: adjoint_trace_k<8>(a, st); break;
+    case 16: adjoint_trace_k<16>(a, st); break;
+    case 32: adjoint_trace_k<32>(a, st); break;
+    default: adjoint_trace_k<64>(a, st); break;
+  }
+}
+
+void launch_adjoint_hits(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
+  if (a.R <= 0) return;
+  switch (kbucket(a.P.k)) {
+    case 8: adjoint_hits_k<8>(a, g, st); break;
+    case 16: adjoint_hits_k<16>(a, g, st); break;
+    case 32: adjoint_hits_k<32>(a, g, st); break;
+    default: adjoint_hits_k<64>(a, g, st); break;
   }
 }
 

@@ -106,11 +106,13 @@ struct RenderArgs {
   const ChunkDesc *chunks;
   const BatchSlot *slots;
 };
-// primary: traversal + compositing, then shading
-void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st);
+// primary: traversal (k-buffers into kbuf), compositing, then shading
+void launch_trace1(const RenderArgs &a, hipStream_t st);
+void launch_composite1(const RenderArgs &a, bool replay, hipStream_t st);
 void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st);
-// secondary: traversal + compositing of the queue, then the two environment samples
+// secondary: traversal and compositing of the queue, then the two environment samples
 void launch_trace2(const RenderArgs &a, hipStream_t st);
+void launch_composite2(const RenderArgs &a, hipStream_t st);
 void launch_shade2(const RenderArgs &a, bool replay, hipStream_t st);
 void launch_resolve(const RenderArgs &a, hipStream_t st);
 void launch_accum(unsigned long long *acc, const uint32_t *count, hipStream_t st);
@@ -123,9 +125,10 @@ struct GradArgs {
   const float *d_radiance, *d_depth, *d_normal, *d_alpha;
   float *g_mu, *g_q, *g_scale, *g_opacity, *g_albedo, *g_roughness, *g_metallic, *g_env;
 };
-// shading adjoint (env gradients, compositing seeds) then traversal + compositing adjoint
+// shading adjoint (env gradients, compositing seeds), replayed traversal of the seeded rays, compositing adjoint
 void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st);
-void launch_adjoint_trace(const RenderArgs &a, const GradArgs &g, hipStream_t st);
+void launch_adjoint_trace(const RenderArgs &a, hipStream_t st);
+void launch_adjoint_hits(const RenderArgs &a, const GradArgs &g, hipStream_t st);
 
 inline int kbucket(int k) { return k <= 8 ? 8 : (k <= 16 ? 16 : (k <= 32 ? 32 : 64)); }
 

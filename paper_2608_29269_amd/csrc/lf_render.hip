@@ -556,37 +556,34 @@ __global__ void k_l1_final(const double *acc, int64_t n, float *loss) { *loss = 
 __global__ void k_zero_f64(double *p) { *p = 0.0; }
 
 template <int K, bool B>
-void trace1_k(const RenderArgs &a, bool replay, hipStream_t st) {
+void trace1_k(const RenderArgs &a, hipStream_t st) {
   const int64_t items = (!B && a.n_tiles) ? a.n_tiles * kBlock : a.R;
   launch_fill_u32(a.work, 0u, 1, st);
   hipLaunchKernelGGL((k_trace1<K, B>), dim3(pool_blocks<k_trace1<K, B>>(items)), dim3(kBlock), 0, st, a);
+}
+template <int K, bool B>
+void composite1_k(const RenderArgs &a, bool replay, hipStream_t st) {
+  const int64_t items = (!B && a.n_tiles) ? a.n_tiles * kBlock : a.R;
   hipLaunchKernelGGL((k_composite1<K, B>), dim3(blocks(items, kBlock)), dim3(kBlock), 0, st, a, replay);
 }
 template <int K, bool B>
 void trace2_k(const RenderArgs &a, hipStream_t st) {
-  const int64_t cap = a.R * a.spp_stride;
   launch_fill_u32(a.work, 0u, 1, st);
-  hipLaunchKernelGGL((k_trace2<K, B>), dim3(pool_blocks<k_trace2<K, B>>(cap)), dim3(kBlock), 0, st, a);
-  hipLaunchKernelGGL((k_composite2<K, B>), dim3(blocks(cap, kBlock)), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL((k_trace2<K, B>), dim3(pool_blocks<k_trace2<K, B>>(a.R * a.spp_stride)), dim3(kBlock), 0, st,
+                     a);
 }
-template <bool B>
-void trace1_b(const RenderArgs &a, bool replay, hipStream_t st) {
-  switch (kbucket(a.P.k)) {
-    case 8: trace1_k<8, B>(a, replay, st); break;
-    case 16: trace1_k<16, B>(a, replay, st); break;
-    case 32: trace1_k<32, B>(a, replay, st); break;
-    default: trace1_k<64, B>(a, replay, st); break;
+template <int K, bool B>
+void composite2_k(const RenderArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL((k_composite2<K, B>), dim3(blocks(a.R * a.spp_stride, kBlock)), dim3(kBlock), 0, st, a);
+}
+// fn<K, B>(args...) for the k-buffer size bucket of a.P.k
+#define LF_K_DISPATCH(fn, B, ...)                  \
+  switch (kbucket(a.P.k)) {                        \
+    case 8: fn<8, B>(__VA_ARGS__); break;          \
+    case 16: fn<16, B>(__VA_ARGS__); break;        \
+    case 32: fn<32, B>(__VA_ARGS__); break;        \
+    default: fn<64, B>(__VA_ARGS__); break;        \
   }
-}
-template <bool B>
-void trace2_b(const RenderArgs &a, hipStream_t st) {
-  switch (kbucket(a.P.k)) {
-    case 8: trace2_k<8, B>(a, st); break;
-    case 16: trace2_k<16, B>(a, st); break;
-    case 32: trace2_k<32, B>(a, st); break;
-    default: trace2_k<64, B>(a, st); break;
-  }
-}
 
 }  // namespace
 
@@ -611,10 +608,16 @@ void launch_env_tables(const float *tex, int H, int W, uint32_t flags, double *c
   hipLaunchKernelGGL(k_env_marginal, dim3(1), dim3(256), 0, st, H, flags, roww, cdf_row, scal);
 }
 
-void launch_trace1(const RenderArgs &a, bool replay, hipStream_t st) {
+void launch_trace1(const RenderArgs &a, hipStream_t st) {
   if (a.R <= 0) return;
-  if (a.chunks) trace1_b<true>(a, replay, st);
-  else trace1_b<false>(a, replay, st);
+  if (a.chunks) LF_K_DISPATCH(trace1_k, true, a, st)
+  else LF_K_DISPATCH(trace1_k, false, a, st)
+}
+
+void launch_composite1(const RenderArgs &a, bool replay, hipStream_t st) {
+  if (a.R <= 0) return;
+  if (a.chunks) LF_K_DISPATCH(composite1_k, true, a, replay, st)
+  else LF_K_DISPATCH(composite1_k, false, a, replay, st)
 }
 
 void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st) {
@@ -625,8 +628,14 @@ void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st) {
 
 void launch_trace2(const RenderArgs &a, hipStream_t st) {
   if (a.R <= 0) return;
-  if (a.chunks) trace2_b<true>(a, st);
-  else trace2_b<false>(a, st);
+  if (a.chunks) LF_K_DISPATCH(trace2_k, true, a, st)
+  else LF_K_DISPATCH(trace2_k, false, a, st)
+}
+
+void launch_composite2(const RenderArgs &a, hipStream_t st) {
+  if (a.R <= 0) return;
+  if (a.chunks) LF_K_DISPATCH(composite2_k, true, a, st)
+  else LF_K_DISPATCH(composite2_k, false, a, st)
 }
 
 void launch_shade2(const RenderArgs &a, bool replay, hipStream_t st) {

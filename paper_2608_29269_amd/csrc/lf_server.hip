@@ -226,7 +226,8 @@ bool launch_pass(lf_server *s, Lane &L, const std::vector<lf::SchedTile> &tiles)
   const bool sorted = !(s->cfg.params.flags & LF_FLAG_UNSORTED);
   a.order = sorted ? L.svals.as<int32_t>() : nullptr;
   lf::launch_fill_u32(a.queue_count, 0u, 1, st);
-  lf::launch_trace1(a, false, st);
+  lf::launch_trace1(a, st);
+  lf::launch_composite1(a, false, st);
   lf::launch_shade1(a, false, st);
   if (sorted) {
     const int64_t cap = a.R * a.spp_stride;
@@ -236,6 +237,7 @@ bool launch_pass(lf_server *s, Lane &L, const std::vector<lf::SchedTile> &tiles)
                    L.shist.as<uint32_t>(), cap, st, 32);
   }
   lf::launch_trace2(a, st);
+  lf::launch_composite2(a, st);
   lf::launch_shade2(a, false, st);
   lf::launch_resolve(a, st);
   if (hipMemcpyAsync(&L.h_rb->status, a.status, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
