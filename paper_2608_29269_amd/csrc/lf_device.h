@@ -506,19 +506,18 @@ __device__ __forceinline__ bool kinsert_tied(const SceneView &S, KBufF<K> &b, fl
   return true;
 }
 
-// Tests the surfel at leaf position pos against the object-space ray
-// (o, d) of the world ray (wo, wd) and inserts a valid hit that belongs to the
-// k closest.  Binary32 keys are roundings of the exact distances and rounding
-// is monotone, so a key above the k-th key is beyond the exact k-th distance
-// and distinct keys order exactly; a key equal to one in the buffer is placed
-// by exact keys.  Returns bit 0: inserted, bit 1: placed by exact keys,
-// bit 2: passed the binary32 pre-filter, bit 3: valid hit.
+// Exact (FP64) plane hit and support/threshold test of the surfel at leaf
+// position pos, which passed the pre-filter, against the object-space ray
+// (o, d) of the world ray (wo, wd), and insertion of a valid hit that belongs
+// to the k closest.  Binary32 keys are roundings of the exact distances and
+// rounding is monotone, so a key above the k-th key is beyond the exact k-th
+// distance and distinct keys order exactly; a key equal to one in the buffer
+// is placed by exact keys.  Returns bit 0: inserted, bit 1: placed by exact
+// keys, bit 2: passed the binary32 pre-filter (always set), bit 3: valid hit.
 template <int K>
-__device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3 d, const RayF &rf, double t_min,
-                                           float t_min_f, KBufF<K> &kb, d3 wo, d3 wd) {
+__device__ __forceinline__ int exact_insert(const SceneView &S, int pos, d3 o, d3 d, double t_min, KBufF<K> &kb,
+                                            d3 wo, d3 wd) {
   const float tk = kb.t[K - 1];
-  const float tk_up = tk < INFINITY ? next_up_f(tk) : INFINITY;
-  if (!prefilter(S.filt[pos], rf, t_min_f, tk_up)) return 0;
   double t;
   bool flip;
   if (!exact_hit(S.rec[pos], o, d, t_min, t, flip)) return 4;
@@ -535,6 +534,16 @@ __device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3
   return kinsert_tied<K>(S, kb, tf, t, id, wo, wd) ? 15 : 14;
 }
 
+// Pre-filter, then exact test and insertion, of one surfel (bits as above; 0
+// when the pre-filter rejects it).
+template <int K>
+__device__ __forceinline__ int test_surfel(const SceneView &S, int pos, d3 o, d3 d, const RayF &rf, double t_min,
+                                           float t_min_f, KBufF<K> &kb, d3 wo, d3 wd) {
+  const float tk = kb.t[K - 1];
+  const float tk_up = tk < INFINITY ? next_up_f(tk) : INFINITY;
+  if (!prefilter(S.filt[pos], rf, t_min_f, tk_up)) return 0;
+  return exact_insert<K>(S, pos, o, d, t_min, kb, wo, wd);
+}
 
 
 template <int K>
@@ -708,14 +717,29 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
       for (int j = 1; j < kWide; ++j) nxt = j == bj ? cs[j] : nxt;
       cur = nxt;
     }
-    // leaf phase
-    for (int j = 0; j < qn; ++j) {
-      const int leaf = lq[j * kBlock];
-      if (~leaf >= S.n_rec) {  // never taken for a consistent hierarchy
-        atomicOr(status, kStatusBvhCorrupt);
-        continue;
+    // leaf phase: the binary32 pre-filter over the whole queue, compacting the
+    // survivors to its front, then their exact tests and insertions, so that
+    // the rare exact path runs for many lanes at once
+    {
+      const float tk = kb.t[K - 1];
+      const float tk_up = tk < INFINITY ? next_up_f(tk) : INFINITY;
+      int np = 0;
+      for (int j = 0; j < qn; ++j) {
+        const int leaf = lq[j * kBlock];
+        if (~leaf >= S.n_rec) {  // never taken for a consistent hierarchy
+          atomicOr(status, kStatusBvhCorrupt);
+          continue;
+        }
+        ++c_tests;
+        if (prefilter(S.filt[~leaf], rf, t_min_f, tk_up)) lq[(np++) * kBlock] = leaf;
       }
-      count_test(test_surfel<K>(S, ~leaf, oo, dd, rf, P.t_min, t_min_f, kb, o, d));
+      for (int j = 0; j < np; ++j) {
+        const int r = exact_insert<K>(S, ~lq[j * kBlock], oo, dd, P.t_min, kb, o, d);
+        c_ins += r & 1;
+        c_ties += (r >> 1) & 1;
+        ++c_pass;
+        c_hits += r >> 3;
+      }
     }
     qn = 0;
   }
