@@ -306,9 +306,10 @@ __device__ __forceinline__ void cswap(float &ta, int &ca, float &tb, int &cb) {
 // q * C + B, with B the near (Bn) or far (Bf) offset.  C = 2^e / d is exact;
 // E bounds the rounding of the frame origin's distance, of 1/d, of the
 // decoded plane (within half an ulp of the fused multiply-add the build
-// checked) and of the products, so near distances are never overestimated
-// and far ones never underestimated for the box grown by pad.  An axis whose
-// terms are not safely finite is left unconstrained.
+// checked), of the products and of the per-slot fused multiply-add (at most
+// 2^-24 (255 |C| + |B|)), so near distances are never overestimated and far
+// ones never underestimated for the box grown by pad.  An axis whose terms
+// are not safely finite is left unconstrained.
 __device__ __forceinline__ void axis_frame(float p, int e, float o, float inv, float pad, float &C, float &Bn,
                                            float &Bf) {
   C = __uint_as_float((uint32_t)(e + 127) << 23) * inv;
@@ -368,11 +369,8 @@ __device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, fl
     const float tfx = __builtin_fmaf((float)((fx[w] >> b) & 0xffu), Cx, Bfx);
     const float tfy = __builtin_fmaf((float)((fy[w] >> b) & 0xffu), Cy, Bfy);
     const float tfz = __builtin_fmaf((float)((fz[w] >> b) & 0xffu), Cz, Bfz);
-    float n = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, tlo));
-    float f = fminf(fminf(tfx, tfy), fminf(tfz, thi));
-    // the last fused multiply-add rounds relative to its result
-    n = __builtin_fmaf(-0x1p-20f, fabsf(n), n);
-    f = __builtin_fmaf(0x1p-20f, fabsf(f), f);
+    const float n = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, tlo));
+    const float f = fminf(fminf(tfx, tfy), fminf(tfz, thi));
     const bool hit = n <= f && ((vmask >> i) & 1u);
     t[i] = hit ? n : INFINITY;
     const int below = __builtin_popcount(imask & ((1u << i) - 1u));
@@ -560,8 +558,9 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 // Laine 2009, "while-while"): in the node phase a lane visits nodes, its hit
 // leaves join its leaf queue and its nearest hit internal child is visited
 // next (the others are pushed), while some lane that can still visit nodes
-// has no leaf queued; a lane pauses while its queue could not take a whole
-// node's leaves.  The leaf phase then tests every queued leaf.  stk points at
+// has fewer than kLeafMin leaves queued; a lane pauses while its queue could
+// not take a whole node's leaves.  The leaf phase then tests every queued
+// leaf.  stk points at
 // this lane's first LDS stack slot (stride kBlock, kStackL entries; deeper
 // entries in private scratch; internal nodes only) and lq at its first
 // leaf-queue slot (stride kBlock, kLeafQ entries).  Every lane leaves once
@@ -673,7 +672,7 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
     // node phase
     while (true) {
       const bool can = cur >= 0 && qn <= kLeafQ - kWide;
-      if (!__any(can && qn == 0)) break;
+      if (!__any(can && qn < kLeafMin)) break;
       if (!can) continue;
       if (cur >= S.n_nodes) {  // never taken for a consistent hierarchy
         atomicOr(status, kStatusBvhCorrupt);

@@ -10,9 +10,10 @@ namespace lf {
 
 constexpr int kBlock = 128;       // threads per block of the tracing kernels (2 wave64)
 constexpr int kWide = 8;          // children per traversal node
-constexpr int kStackL = 48;       // traversal stack entries per lane held in LDS (24 KB per block)
+constexpr int kStackL = 32;       // traversal stack entries per lane held in LDS (16 KB per block)
 constexpr int kStack = 192;       // traversal stack entries per lane; those past kStackL in private scratch
-constexpr int kLeafQ = 32;        // leaf-queue entries per lane (LDS, 16 KB per block)
+constexpr int kLeafQ = 48;        // leaf-queue entries per lane (LDS, 24 KB per block)
+constexpr int kLeafMin = 8;       // the node phase goes on while a lane that can visit nodes has fewer queued
 constexpr int kMaxInst = 64;      // background + up to 63 objects
 constexpr uint32_t kFlipBit = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7fffffffu;
