@@ -148,14 +148,61 @@ __global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G) {
   a.seeds[ray] = sd;
 }
 
+// ---------------------------------------------------------------- gradient accumulation
+// The fifteen per-surfel gradient values of one hit, in this order: albedo
+// (3), metallic, roughness, opacity, scale (2), mu (3), raw quaternion (4).
+constexpr int kGradVals = 15;
+
+__device__ __forceinline__ float *grad_slot(const GradArgs &G, int64_t i, int v) {
+  switch (v) {
+    case 0: case 1: case 2: return G.g_albedo + 3 * i + v;
+    case 3: return G.g_metallic + i;
+    case 4: return G.g_roughness + i;
+    case 5: return G.g_opacity + i;
+    case 6: case 7: return G.g_scale + 2 * i + (v - 6);
+    case 8: case 9: case 10: return G.g_mu + 3 * i + (v - 8);
+    default: return G.g_q + 4 * i + (v - 11);
+  }
+}
+
+// Per-block accumulation of hit gradients in an LDS table keyed by surfel
+// (open addressing, a few probes), flushed to device memory with one atomic
+// per surfel and value; a hit that finds no slot goes to device memory
+// directly.  Neighbouring rays of a block meet largely the same surfels, so
+// this replaces most device-scope atomics on shared addresses.
+constexpr int kAggBits = 9;
+constexpr int kAggSlots = 1 << kAggBits;  // 32 KB of LDS per block with the values
+constexpr int kAggProbes = 8;
+
+struct BlockGradTable {
+  int *key;     // [kAggSlots], -1 when free
+  float *val;   // [kGradVals][kAggSlots]
+  const GradArgs &G;
+  __device__ void add(int64_t i, const float *gv) {
+    const uint32_t h = (uint32_t)i * 2654435761u;
+#pragma unroll 1
+    for (int p = 0; p < kAggProbes; ++p) {
+      const int slot = (int)((h >> (32 - kAggBits)) + (uint32_t)p) & (kAggSlots - 1);
+      const int k = atomicCAS(key + slot, -1, (int)i);
+      if (k == -1 || k == (int)i) {
+#pragma unroll
+        for (int v = 0; v < kGradVals; ++v) atomicAdd(val + v * kAggSlots + slot, gv[v]);
+        return;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < kGradVals; ++v) atomicAdd(grad_slot(G, i, v), gv[v]);
+  }
+};
+
 // ---------------------------------------------------------------- compositing adjoint
 // Back to front over the recomputed hit list: with v_j = gA + sum_z gZ . z_j
 // and the suffix V_j = sum_{i>j} w_i v_i,
 //   d/d(alpha_j) = T_j v_j - (V_j + gT T) / (1 - alpha_j),
 // then through the effective opacity and the plane intersection into
 // (mu, q, s, alpha) and through the composited attributes into (a, m, r).
-template <int K, class B>
-__device__ void adjoint_hits(const RenderArgs &a, const GradArgs &G, const AdjSeed &sd, B &kb, d3 o, d3 d) {
+template <int K, class B, class Acc>
+__device__ void adjoint_hits(const RenderArgs &a, const AdjSeed &sd, B &kb, d3 o, d3 d, Acc &acc) {
   const TraceParams &P = a.P;
   const double gA = sd.gA, gT = sd.gT, gZt = sd.gZt, gZm = sd.gZm, gZr = sd.gZr, Tfin = sd.T;
   const d3 gZn = mk(sd.gZn[0], sd.gZn[1], sd.gZn[2]), gZa = mk(sd.gZa[0], sd.gZa[1], sd.gZa[2]);
@@ -177,11 +224,12 @@ __device__ void adjoint_hits(const RenderArgs &a, const GradArgs &G, const AdjSe
     V += wj * vj;
     Tafter = Tj;
     // attributes
-    atomicAdd(G.g_albedo + 3 * i + 0, (float)(gZa.x * wj));
-    atomicAdd(G.g_albedo + 3 * i + 1, (float)(gZa.y * wj));
-    atomicAdd(G.g_albedo + 3 * i + 2, (float)(gZa.z * wj));
-    atomicAdd(G.g_metallic + i, (float)(gZm * wj));
-    atomicAdd(G.g_roughness + i, (float)(gZr * wj));
+    float gv[kGradVals];
+    gv[0] = (float)(gZa.x * wj);
+    gv[1] = (float)(gZa.y * wj);
+    gv[2] = (float)(gZa.z * wj);
+    gv[3] = (float)(gZm * wj);
+    gv[4] = (float)(gZr * wj);
     // frame of the raw quaternion, object-space ray of the hit's instance
     const InstRec &I = a.S.inst[he.inst];
     d3 oo, dd;
@@ -199,11 +247,11 @@ __device__ void adjoint_hits(const RenderArgs &a, const GradArgs &G, const AdjSe
     const double raw = alpha * g;
     // effective opacity alpha_t = min(cap, alpha exp(-rho^2/2))
     const double graw = raw > P.alpha_cap ? 0.0 : gat;
-    atomicAdd(G.g_opacity + i, (float)(graw * g));
+    gv[5] = (float)(graw * g);
     const double grho2 = graw * alpha * g * (-0.5);
     const double gxu = grho2 * 2.0 * xu, gxv = grho2 * 2.0 * xv;
-    atomicAdd(G.g_scale + 2 * i + 0, (float)(-gxu * xu / su));
-    atomicAdd(G.g_scale + 2 * i + 1, (float)(-gxv * xv / sv));
+    gv[6] = (float)(-gxu * xu / su);
+    gv[7] = (float)(-gxv * xv / sv);
     const d3 gdl = (gxu / su) * tu + (gxv / sv) * tv;
     const d3 gtu = (gxu / su) * dl, gtv = (gxv / sv) * dl;
     // dl = o + t d - mu ; t = n.(mu - o) / (n.d) ; composited normal = +-R n
@@ -214,9 +262,9 @@ __device__ void adjoint_hits(const RenderArgs &a, const GradArgs &G, const AdjSe
     if (id & kFlipBit) gno = -gno;
     const d3 gmu = (gt / den) * n - gdl;
     const d3 gnn = gno - (gt / den) * dl;
-    atomicAdd(G.g_mu + 3 * i + 0, (float)gmu.x);
-    atomicAdd(G.g_mu + 3 * i + 1, (float)gmu.y);
-    atomicAdd(G.g_mu + 3 * i + 2, (float)gmu.z);
+    gv[8] = (float)gmu.x;
+    gv[9] = (float)gmu.y;
+    gv[10] = (float)gmu.z;
     // columns (t_u, t_v, n) of rot(q_hat) -> q_hat -> raw q;  G[r][c] row-major
     const double G0 = gtu.x, G1 = gtv.x, G2 = gnn.x, G3 = gtu.y, G4 = gtv.y, G5 = gnn.y, G6 = gtu.z, G7 = gtv.z,
                  G8 = gnn.z;
@@ -228,10 +276,11 @@ __device__ void adjoint_hits(const RenderArgs &a, const GradArgs &G, const AdjSe
     const double gq3 = G0 * (-4 * z) + G1 * (-2 * w) + G2 * (2 * x) + G3 * (2 * w) + G4 * (-4 * z) + G5 * (2 * y) +
                        G6 * (2 * x) + G7 * (2 * y);
     const double pq = gq0 * w + gq1 * x + gq2 * y + gq3 * z;
-    atomicAdd(G.g_q + 4 * i + 0, (float)((gq0 - w * pq) / qlen));
-    atomicAdd(G.g_q + 4 * i + 1, (float)((gq1 - x * pq) / qlen));
-    atomicAdd(G.g_q + 4 * i + 2, (float)((gq2 - y * pq) / qlen));
-    atomicAdd(G.g_q + 4 * i + 3, (float)((gq3 - z * pq) / qlen));
+    gv[11] = (float)((gq0 - w * pq) / qlen);
+    gv[12] = (float)((gq1 - x * pq) / qlen);
+    gv[13] = (float)((gq2 - y * pq) / qlen);
+    gv[14] = (float)((gq3 - z * pq) / qlen);
+    acc.add(i, gv);
   }
 }
 
@@ -270,15 +319,34 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_trace(RenderArgs a) {
 // compositing adjoint of every seeded ray from its replayed k-buffer
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_adj_hits(RenderArgs a, GradArgs G) {
+  __shared__ int key[kAggSlots];
+  __shared__ float val[kGradVals * kAggSlots];
+  for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
+    key[j] = -1;
+#pragma unroll
+    for (int v = 0; v < kGradVals; ++v) val[v * kAggSlots + j] = 0.0f;
+  }
+  __syncthreads();
+  BlockGradTable tab{key, val, G};
   const int64_t item = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (item >= adj_items(a)) return;
-  const int64_t ray = adj_ray(a, item);
-  if (ray < 0) return;
-  float of[3], df[3];
-  load_ray(a.rays, ray, of, df);
-  KBufF<K> kb;
-  load_kbuf<K>(kb, a.kbuf + item * 2 * K);
-  adjoint_hits<K>(a, G, a.seeds[ray], kb, mk(of[0], of[1], of[2]), mk(df[0], df[1], df[2]));
+  const int64_t ray = item < adj_items(a) ? adj_ray(a, item) : -1;
+  if (ray >= 0) {
+    float of[3], df[3];
+    load_ray(a.rays, ray, of, df);
+    KBufF<K> kb;
+    load_kbuf<K>(kb, a.kbuf + item * 2 * K);
+    adjoint_hits<K>(a, a.seeds[ray], kb, mk(of[0], of[1], of[2]), mk(df[0], df[1], df[2]), tab);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
+    const int i = key[j];
+    if (i < 0) continue;
+#pragma unroll
+    for (int v = 0; v < kGradVals; ++v) {
+      const float g = val[v * kAggSlots + j];
+      if (g != 0.0f) atomicAdd(grad_slot(G, i, v), g);
+    }
+  }
 }
 
 template <int K>
