@@ -239,7 +239,7 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
   // k-buffers handed from the traversal to the compositing launches: one per
   // primary work item (tile positions or rays) and per secondary queue entry
   const int64_t items = std::max(a.n_tiles > 0 ? a.n_tiles * lf::kBlock : R, trace2 ? RS : (int64_t)0);
-  if (!c->work.ensure(16) || !c->kbuf.ensure(sizeof(uint32_t) * 2 * lf::kbucket(p->k) * (items > 0 ? items : 1)))
+  if (!c->work.ensure(sizeof(uint32_t) * lf::kPoolParts) || !c->kbuf.ensure(sizeof(uint32_t) * 2 * lf::kbucket(p->k) * (items > 0 ? items : 1)))
     return fail(c, LF_ENOMEM, "k-buffers for %lld rays", (long long)items);
   a.work = c->work.as<uint32_t>();
   a.kbuf = c->kbuf.as<uint32_t>();

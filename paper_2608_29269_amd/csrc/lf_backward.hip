@@ -351,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_hits(RenderArgs a, GradArgs G) {
 
 template <int K>
 void adjoint_trace_k(const RenderArgs &a, hipStream_t st) {
-  launch_fill_u32(a.work, 0u, 1, st);
+  launch_fill_u32(a.work, 0u, kPoolParts, st);
   hipLaunchKernelGGL(k_adj_trace<K>, dim3(pool_blocks<k_adj_trace<K>>(adj_items_host(a))), dim3(kBlock), 0, st, a);
 }
 

@@ -292,16 +292,6 @@ __device__ __forceinline__ void make_rayf(d3 oo, d3 dd, double tabs, RayF &rf) {
   rf.sx = rf.ix >= 0.f; rf.sy = rf.iy >= 0.f; rf.sz = rf.iz >= 0.f;
 }
 
-__device__ __forceinline__ void cswap(float &ta, int &ca, float &tb, int &cb) {
-  const bool sw = tb < ta;
-  const float t = sw ? tb : ta;
-  const int c = sw ? cb : ca;
-  tb = sw ? ta : tb;
-  cb = sw ? ca : cb;
-  ta = t;
-  ca = c;
-}
-
 // Distances along one axis in a node's frame: a plane of code q lies at
 // q * C + B, with B the near (Bn) or far (Bf) offset.  C = 2^e / d is exact;
 // E bounds the rounding of the frame origin's distance, of 1/d, of the
@@ -326,11 +316,13 @@ __device__ __forceinline__ void axis_frame(float p, int e, float o, float inv, f
 }
 
 // Visits one traversal node: entry t of every slot whose decoded box (grown
-// by pad) the ray enters within [tlo, thi] (else +inf), the slot's child code
-// (>= 0 node, < 0 ~leaf position) and the masks of hit internal and hit leaf
-// slots.
+// by pad) the ray enters within [tlo, thi] (else +inf), the masks of hit
+// internal and hit leaf slots, and what locates the children: slot i holds
+// node cbase + (internal slots below i) or leaf position lbase + (leaf slots
+// below i).
 __device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, float tlo, float thi, float *t,
-                                           int *c, uint32_t &ihit, uint32_t &lhit) {
+                                           uint32_t &ihit, uint32_t &lhit, uint32_t &imask, int &cbase,
+                                           int &lbase) {
   constexpr int kDw = (int)sizeof(QNode) / 4;
   constexpr int kPw = kWide / 4;  // dwords per plane
   uint32_t dw[kDw];
@@ -345,8 +337,9 @@ __device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, fl
   axis_frame(__uint_as_float(dw[0]), (int)(int8_t)(meta & 0xffu), rf.ox, rf.ix, rf.pad, Cx, Bnx, Bfx);
   axis_frame(__uint_as_float(dw[1]), (int)(int8_t)((meta >> 8) & 0xffu), rf.oy, rf.iy, rf.pad, Cy, Bny, Bfy);
   axis_frame(__uint_as_float(dw[2]), (int)(int8_t)((meta >> 16) & 0xffu), rf.oz, rf.iz, rf.pad, Cz, Bnz, Bfz);
-  const uint32_t imask = meta >> 24;
-  const int cbase = (int)dw[4], lbase = (int)dw[5];
+  imask = meta >> 24;
+  cbase = (int)dw[4];
+  lbase = (int)dw[5];
   const uint32_t vmask = dw[6];
   // codes of the near and far plane of each axis: lower codes for d >= 0
   uint32_t nx[kPw], ny[kPw], nz[kPw], fx[kPw], fy[kPw], fz[kPw];
@@ -373,12 +366,10 @@ __device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, fl
     const float f = fminf(fminf(tfx, tfy), fminf(tfz, thi));
     const bool hit = n <= f && ((vmask >> i) & 1u);
     t[i] = hit ? n : INFINITY;
-    const int below = __builtin_popcount(imask & ((1u << i) - 1u));
-    const bool inner = (imask >> i) & 1u;
-    c[i] = inner ? cbase + below : ~(lbase + (i - below));
-    ihit |= (hit && inner) ? 1u << i : 0u;
-    lhit |= (hit && !inner) ? 1u << i : 0u;
+    ihit |= hit ? 1u << i : 0u;
   }
+  lhit = ihit & ~imask;
+  ihit &= imask;
 }
 
 // Exact (double) plane intersection and support test of the surfel at leaf
@@ -551,7 +542,8 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 // holds one ray at a time, collects its k closest valid hits over all
 // instances and stores them with wk.store; a wave refills its idle lanes from
 // the shared counter *next once kRefillIdle of them are idle (or all are), so
-// the rays of a wave need not finish together.  Work supplies
+// the rays of a wave need not finish together (see kPoolParts for the
+// counters).  Work supplies
 //   bool begin(int64_t item, d3 &o, d3 &d, const InstRec *&inst)  (false: nothing to trace)
 //   void store(int64_t item, const KBufF<K> &kb)
 // Traversal of an instance runs in rounds of two phases (after Aila and
@@ -600,6 +592,7 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
   int64_t item = -1;
   bool live = false;       // this lane holds a ray
   bool exhausted = false;  // the pool is empty (uniform over the wave)
+  int part = (int)(blockIdx.x % kPoolParts), tried = 0;  // the item range this wave draws from
   int ii = 0;              // the ray's current instance
   d3 o = mk(0, 0, 0), d = mk(0, 0, 1), oo = o, dd = d;
   RayF rf;
@@ -613,12 +606,17 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
       if (n_idle >= kRefillIdle || (n_idle > 0 && !__any(live))) {
         const int leader = __ffsll((long long)idle) - 1;
         uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(next, (uint32_t)n_idle);
+        if (lane == leader) base = atomicAdd(next + part, (uint32_t)n_idle);
         base = (uint32_t)__shfl((int)base, leader);
-        if ((int64_t)base + n_idle >= count) exhausted = true;
+        const int64_t lo = count * part / kPoolParts, hi = count * (part + 1) / kPoolParts;
+        const int64_t first = lo + (int64_t)base;
+        if (first + n_idle >= hi) {  // this range is used up: move to the next one
+          part = part + 1 == kPoolParts ? 0 : part + 1;
+          exhausted = ++tried == kPoolParts;
+        }
         if (!live) {
-          const int64_t it = (int64_t)base + __popcll(idle & ((1ull << lane) - 1ull));
-          if (it < count) {
+          const int64_t it = first + __popcll(idle & ((1ull << lane) - 1ull));
+          if (it < hi) {
             item = it;
             live = wk.begin(item, o, d, S.inst);
             if (live) {
@@ -684,12 +682,14 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
       const float tkf = kb.t[K - 1];
       const float thi = tkf < INFINITY ? next_up_f(tkf) * (1.0f + 1e-6f) : INFINITY;
       float ts[kWide];
-      int cs[kWide];
-      uint32_t ih, lh;
-      visit_node(S.nodes + cur, rf, tlo, thi, ts, cs, ih, lh);
-#pragma unroll
-      for (int j = 0; j < kWide; ++j)
-        if ((lh >> j) & 1u) lq[(qn++) * kBlock] = cs[j];
+      uint32_t ih, lh, im;
+      int cbase, lbase;
+      visit_node(S.nodes + cur, rf, tlo, thi, ts, ih, lh, im, cbase, lbase);
+      // hit leaves join the queue, in slot order
+      for (uint32_t m = lh; m; m &= m - 1u) {
+        const int j = __builtin_ctz(m);
+        lq[(qn++) * kBlock] = ~(lbase + j - __builtin_popcount(im & ((1u << j) - 1u)));
+      }
       if (ih == 0) {
         cur = sp ? pop() : kDone;
         continue;
@@ -708,13 +708,9 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
           best = ts[j];
           bj = j;
         }
-#pragma unroll
-      for (int j = 0; j < kWide; ++j)
-        if (((ih >> j) & 1u) && j != bj) push(cs[j]);
-      int nxt = cs[0];
-#pragma unroll
-      for (int j = 1; j < kWide; ++j) nxt = j == bj ? cs[j] : nxt;
-      cur = nxt;
+      for (uint32_t m = ih & ~(1u << bj); m; m &= m - 1u)
+        push(cbase + __builtin_popcount(im & ((1u << __builtin_ctz(m)) - 1u)));
+      cur = cbase + __builtin_popcount(im & ((1u << bj) - 1u));
     }
     // leaf phase: the binary32 pre-filter over the whole queue, compacting the
     // survivors to its front, then their exact tests and insertions, so that

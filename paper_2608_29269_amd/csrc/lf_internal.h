@@ -14,6 +14,12 @@ constexpr int kStackL = 32;       // traversal stack entries per lane held in LD
 constexpr int kStack = 192;       // traversal stack entries per lane; those past kStackL in private scratch
 constexpr int kLeafQ = 48;        // leaf-queue entries per lane (LDS, 24 KB per block)
 constexpr int kLeafMin = 8;       // the node phase goes on while a lane that can visit nodes has fewer queued
+// Persistent traversal splits its items into kPoolParts contiguous ranges
+// with one counter each; a block starts on range blockIdx % kPoolParts, so
+// with round-robin dispatch of blocks over the eight XCDs each XCD's L2
+// serves one compact range of (sorted) rays at a time; a wave whose range is
+// used up moves on to the next.
+constexpr int kPoolParts = 8;
 constexpr int kMaxInst = 64;      // background + up to 63 objects
 constexpr uint32_t kFlipBit = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7fffffffu;

@@ -98,7 +98,7 @@ struct RenderArgs {
   SecFrozen *frozen;    // [R*S] (backward replay)
   AdjSeed *seeds;       // [R] (backward)
   uint32_t *status;
-  uint32_t *work;       // item counter of the persistent traversal launches (cleared before each)
+  uint32_t *work;       // [kPoolParts] item counters of the persistent traversal launches (cleared before each)
   uint32_t *kbuf;       // [items, 2K] k-buffers from traversal to compositing (t[K], then ids[K])
   // per-ray sample stride of contrib / frozen and of the queue capacity (spp, or the batch maximum)
   int32_t spp_stride;

@@ -558,7 +558,7 @@ __global__ void k_zero_f64(double *p) { *p = 0.0; }
 template <int K, bool B>
 void trace1_k(const RenderArgs &a, hipStream_t st) {
   const int64_t items = (!B && a.n_tiles) ? a.n_tiles * kBlock : a.R;
-  launch_fill_u32(a.work, 0u, 1, st);
+  launch_fill_u32(a.work, 0u, kPoolParts, st);
   hipLaunchKernelGGL((k_trace1<K, B>), dim3(pool_blocks<k_trace1<K, B>>(items)), dim3(kBlock), 0, st, a);
 }
 template <int K, bool B>
@@ -568,7 +568,7 @@ void composite1_k(const RenderArgs &a, bool replay, hipStream_t st) {
 }
 template <int K, bool B>
 void trace2_k(const RenderArgs &a, hipStream_t st) {
-  launch_fill_u32(a.work, 0u, 1, st);
+  launch_fill_u32(a.work, 0u, kPoolParts, st);
   hipLaunchKernelGGL((k_trace2<K, B>), dim3(pool_blocks<k_trace2<K, B>>(a.R * a.spp_stride)), dim3(kBlock), 0, st,
                      a);
 }

@@ -485,7 +485,7 @@ lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **o
          hipHostMalloc((void **)&L.h_rb, sizeof(IterReadback), hipHostMallocDefault) == hipSuccess &&
          L.d_chunks.ensure(sizeof(lf::ChunkDesc) * s->max_chunks) && L.rec1.ensure(sizeof(lf::SurfRec) * B) &&
          L.rec2.ensure(sizeof(lf::SurfRec) * BS) && L.queue.ensure(sizeof(lf::SecEntry) * BS) &&
-         L.qcount.ensure(4) && L.work.ensure(16) &&
+         L.qcount.ensure(4) && L.work.ensure(sizeof(uint32_t) * lf::kPoolParts) &&
          L.kbuf.ensure(sizeof(uint32_t) * 2 * lf::kbucket(s->cfg.params.k) * BS) &&
          L.contrib.ensure(sizeof(float) * 3 * BS) && L.skeys.ensure(8 * BS) && L.skeys2.ensure(8 * BS) &&
          L.svals.ensure(4 * BS) && L.svals2.ensure(4 * BS) && L.shist.ensure(4 * lf::radix_sort_hist_words(BS)) &&
