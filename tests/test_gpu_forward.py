@@ -19,11 +19,11 @@ def tracer():
     return lf.Tracer()
 
 
-def _compare(out, ref, amb, check_sec=False, spp=1):
+def _compare(out, ref, amb, check_sec=False, spp=1, min_ok=0.99):
     T = out["radiance"].device
     g = {k: v.cpu().numpy() for k, v in out.items()}
     ok = ~amb
-    assert ok.mean() > 0.99, f"ambiguous fraction {amb.mean():.4f}"
+    assert ok.mean() >= min_ok, f"ambiguous fraction {amb.mean():.4f}"
     np.testing.assert_array_equal(g["hit_idx"][ok], ref["hit_idx"][ok])
     if check_sec:
         np.testing.assert_array_equal(g["sec_hit_idx"][ok], ref["sec_hit_idx"][ok])
@@ -100,6 +100,36 @@ def test_c2_one_bounce_parity(tracer, c2_small):
     sub = {k: v[pix] for k, v in out.items()}
     _compare(sub, ref, amb, check_sec=True, spp=spp)
     assert (ref["sec_alpha"] > 0).mean() > 0.05  # secondaries really hit geometry
+
+
+@pytest.mark.parametrize("n", [1, 7, 63, 65, 129, 1001])
+def test_persistent_pool_small_and_ragged_counts(tracer, c2_small, n):
+    """Ray counts below, at and just above the eight item ranges and a wave
+    of the persistent traversal: hit lists equal the oracle's."""
+    wl = c2_small
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    cam = st.cameras[0]
+    pix = np.sort(np.random.default_rng(n).choice(cam.w * cam.h, n, replace=False))
+    o, d, _ = oracle.raygen(cam, pix)
+    out = tracer.render(**state_args(tracer, wl.scene, st), rays=(dev(o), dev(d)), k=32, spp=2, seed=4,
+                        hit_idx=True, sec_hit_idx=True)
+    ref = run_oracle(wl.scene, st, o, d, np.arange(n), 32, 2, 4, 0)
+    _compare(out, ref, ambiguous(ref["margins"]), check_sec=True, spp=2, min_ok=0.99 if n > 100 else 0.0)
+
+
+def test_odd_camera_partial_tiles(tracer, c2_small):
+    """A 37x23 camera (partial 16x8 tiles on both edges) traced through the
+    tile-ordered pool equals the oracle on every pixel."""
+    wl = c2_small
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    cam = scenegen.sphere_camera(np.random.default_rng(5), 37, 23, fov_y_deg=55.0)
+    out = tracer.render(**state_args(tracer, wl.scene, st), cameras=[cam], k=32, spp=2, seed=6, hit_idx=True,
+                        sec_hit_idx=True)
+    o, d, ids = oracle.raygen(cam)
+    ref = run_oracle(wl.scene, st, o, d, ids, 32, 2, 6, 0)
+    _compare(out, ref, ambiguous(ref["margins"]), check_sec=True, spp=2)
 
 
 def test_instanced_multi_state_parity(tracer):
