@@ -361,7 +361,7 @@ def source_digest():
 
 
 # Kernels that each own one phase timer (one launch per call) and what they process.
-KERNEL_OF_PHASE = {"trace1": "k_trace1<32, false>", "trace2": "k_trace2<32, false>", "adj_trace": "k_adj_trace<32>",
+KERNEL_OF_PHASE = {"trace1": "k_trace1<32, false>", "trace2": "k_trace2<32, false>",
                    "composite1": "k_composite1<32, false>", "composite2": "k_composite2<32, false>",
                    "adj_hits": "k_adj_hits<32>"}
 
@@ -388,13 +388,11 @@ def kernel_bytes(counts, stats, steps):
         # 44 B queued ray in (origin, direction, id, sample, throughput), geometry per crossed support
         "trace2": 44 + 40 * touch_s,
         "composite2": 20 * comp_s + 60,
-        # 44 B of adjoint seeds in, geometry per crossed support
-        "adj_trace": 44 + 40 * touch_p,
-        # material per composited hit and a 120 B gradient read-modify-write per composited hit
-        "adj_hits": 20 * comp_p + 120 * comp_p,
+        # 44 B of adjoint seeds in, material per composited hit, 120 B gradient read-modify-write per hit
+        "adj_hits": 44 + 20 * comp_p + 120 * comp_p,
     }
     rays = {"trace1": rays_pri, "composite1": rays_pri, "trace2": rays_sec, "composite2": rays_sec,
-            "adj_trace": rays_pri, "adj_hits": rays_pri}
+            "adj_hits": rays_pri}
     return {k: per_ray[k] * rays[k] for k in per_ray}, per_ray, rays
 
 

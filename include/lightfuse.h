@@ -259,11 +259,12 @@ lf_status lf_trace_counters(lf_ctx *ctx, uint64_t *counters /*[LF_NUM_COUNTERS]*
  * Phases: 0 refit, 1 state and environment tables, 2 primary traversal,
  * 3 primary shading, 4 secondary regrouping, 5 secondary traversal,
  * 6 secondary shading, 7 resolve, 8 replay of the primary pass, 9 replay of
- * the secondary pass, 10 shading adjoint, 11 replayed traversal of the
- * seeded rays, 12 gradient zeroing, 13 loss, 14 primary compositing,
- * 15 secondary compositing, 16 compositing adjoint.  Phases 2, 5 and 11 each
- * hold one traversal kernel launch per call (after clearing its work counter),
- * phases 14 to 16 one compositing kernel launch. */
+ * the secondary pass, 10 shading adjoint, 11 unused (the compositing adjoint
+ * reads the hit lists of the replayed primary pass), 12 gradient zeroing,
+ * 13 loss, 14 primary compositing, 15 secondary compositing, 16 compositing
+ * adjoint.  Phases 2 and 5 each hold one traversal kernel launch per call
+ * (after clearing its work counters), phases 14 to 16 one compositing kernel
+ * launch. */
 #define LF_NUM_PHASES 17
 lf_status lf_profile_enable(lf_ctx *ctx, int enable);
 lf_status lf_profile_read(lf_ctx *ctx, double *ms /*[LF_NUM_PHASES]*/, int64_t *count /*[LF_NUM_PHASES]*/);

@@ -103,7 +103,7 @@ class ServerStats(C.Structure):
 
 NUM_PHASES = 17
 PHASES = ("refit", "state_env", "trace1", "shade1", "sort2", "trace2", "shade2", "resolve", "replay_primary",
-          "replay_secondary", "adj_shade", "adj_trace", "zero_grads", "loss", "composite1", "composite2", "adj_hits")
+          "replay_secondary", "adj_shade", "unused11", "zero_grads", "loss", "composite1", "composite2", "adj_hits")
 
 # every symbol include/lightfuse.h declares, with its ctypes signature
 SIGNATURES = {

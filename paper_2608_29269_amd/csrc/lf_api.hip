@@ -237,12 +237,17 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
   const bool trace2 = !(p->flags & LF_FLAG_NO_SECONDARY);
   const int64_t RS = R * p->spp;
   // k-buffers handed from the traversal to the compositing launches: one per
-  // primary work item (tile positions or rays) and per secondary queue entry
-  const int64_t items = std::max(a.n_tiles > 0 ? a.n_tiles * lf::kBlock : R, trace2 ? RS : (int64_t)0);
-  if (!c->work.ensure(sizeof(uint32_t) * lf::kPoolParts) || !c->kbuf.ensure(sizeof(uint32_t) * 2 * lf::kbucket(p->k) * (items > 0 ? items : 1)))
-    return fail(c, LF_ENOMEM, "k-buffers for %lld rays", (long long)items);
+  // primary work item (tile positions or rays; the backward's compositing
+  // adjoint reads those of its replayed primary pass) and per secondary
+  // queue entry
+  const int64_t items1 = a.n_tiles > 0 ? a.n_tiles * lf::kBlock : R, items2 = trace2 ? RS : 0;
+  const size_t kb_bytes = sizeof(uint32_t) * 2 * lf::kbucket(p->k);
+  if (!c->work.ensure(sizeof(uint32_t) * lf::kPoolParts) ||
+      !c->kbuf1.ensure(kb_bytes * (items1 > 0 ? items1 : 1)) || !c->kbuf2.ensure(kb_bytes * (items2 > 0 ? items2 : 1)))
+    return fail(c, LF_ENOMEM, "k-buffers for %lld + %lld rays", (long long)items1, (long long)items2);
   a.work = c->work.as<uint32_t>();
-  a.kbuf = c->kbuf.as<uint32_t>();
+  a.kbuf1 = c->kbuf1.as<uint32_t>();
+  a.kbuf2 = c->kbuf2.as<uint32_t>();
   const int64_t R1 = R > 0 ? R : 1;
   if (!c->rec1.ensure(sizeof(lf::SurfRec) * R1)) return fail(c, LF_ENOMEM, "surface records");
   a.rec1 = c->rec1.as<lf::SurfRec>();
@@ -625,10 +630,6 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
   {
     Phase ph(c, 10);
     lf::launch_adjoint_shade(a, ga, s);
-  }
-  {
-    Phase ph(c, 11);
-    lf::launch_adjoint_trace(a, s);
   }
   {
     Phase ph(c, 16);

@@ -284,7 +284,7 @@ __device__ void adjoint_hits(const RenderArgs &a, const AdjSeed &sd, B &kb, d3 o
   }
 }
 
-// rays with a non-zero compositing seed as a pool of work items
+// the seeded rays among the primary work items (tiles of the cameras or explicit rays)
 __device__ __forceinline__ int64_t adj_items(const RenderArgs &a) { return a.n_tiles ? a.n_tiles * kBlock : a.R; }
 inline int64_t adj_items_host(const RenderArgs &a) { return a.n_tiles ? a.n_tiles * kBlock : a.R; }
 __device__ __forceinline__ int64_t adj_ray(const RenderArgs &a, int64_t item) {
@@ -292,31 +292,9 @@ __device__ __forceinline__ int64_t adj_ray(const RenderArgs &a, int64_t item) {
   return (ray >= 0 && ray < a.R && a.seeds[ray].pad[0] != 0.0f) ? ray : -1;
 }
 
-template <int K>
-struct AdjointWork {
-  const RenderArgs &a;
-  __device__ bool begin(int64_t item, d3 &o, d3 &d, const InstRec *&inst) const {
-    const int64_t ray = adj_ray(a, item);
-    if (ray < 0) return false;
-    float of[3], df[3];
-    load_ray(a.rays, ray, of, df);
-    o = mk(of[0], of[1], of[2]);
-    d = mk(df[0], df[1], df[2]);
-    inst = a.S.inst;
-    return true;
-  }
-  __device__ void store(int64_t item, const KBufF<K> &kb) const { store_kbuf<K>(kb, a.kbuf + item * 2 * K); }
-};
-
-template <int K>
-__global__ __launch_bounds__(kBlock, 2) void k_adj_trace(RenderArgs a) {
-  __shared__ int stk[kStackL * kBlock];
-  __shared__ int lq[kLeafQ * kBlock];
-  const AdjointWork<K> wk{a};
-  trace_pool<K>(a.S, a.P, wk, adj_items(a), a.work, stk + threadIdx.x, lq + threadIdx.x, a.status, 0);
-}
-
-// compositing adjoint of every seeded ray from its replayed k-buffer
+// compositing adjoint of every seeded ray from the k-buffer its replayed
+// primary traversal left in kbuf1 (same rays, scene and constants, so the same
+// hit list)
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_adj_hits(RenderArgs a, GradArgs G) {
   __shared__ int key[kAggSlots];
@@ -334,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_hits(RenderArgs a, GradArgs G) {
     float of[3], df[3];
     load_ray(a.rays, ray, of, df);
     KBufF<K> kb;
-    load_kbuf<K>(kb, a.kbuf + item * 2 * K);
+    load_kbuf<K>(kb, a.kbuf1 + item * 2 * K);
     adjoint_hits<K>(a, a.seeds[ray], kb, mk(of[0], of[1], of[2]), mk(df[0], df[1], df[2]), tab);
   }
   __syncthreads();
@@ -350,12 +328,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_hits(RenderArgs a, GradArgs G) {
 }
 
 template <int K>
-void adjoint_trace_k(const RenderArgs &a, hipStream_t st) {
-  launch_fill_u32(a.work, 0u, kPoolParts, st);
-  hipLaunchKernelGGL(k_adj_trace<K>, dim3(pool_blocks<k_adj_trace<K>>(adj_items_host(a))), dim3(kBlock), 0, st, a);
-}
-
-template <int K>
 void adjoint_hits_k(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_hits<K>, dim3(blocks(adj_items_host(a), kBlock)), dim3(kBlock), 0, st, a, g);
 }
@@ -365,16 +337,6 @@ void adjoint_hits_k(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
 void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
   if (a.R <= 0) return;
   hipLaunchKernelGGL(k_adj_shade, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, g);
-}
-
-void launch_adjoint_trace(const RenderArgs &a, hipStream_t st) {
-  if (a.R <= 0) return;
-  switch (kbucket(a.P.k)) {
-    case 8: adjoint_trace_k<8>(a, st); break;
-    case 16: adjoint_trace_k<16>(a, st); break;
-    case 32: adjoint_trace_k<32>(a, st); break;
-    default: adjoint_trace_k<64>(a, st); break;
-  }
 }
 
 void launch_adjoint_hits(const RenderArgs &a, const GradArgs &g, hipStream_t st) {

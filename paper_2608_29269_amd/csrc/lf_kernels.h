@@ -99,14 +99,15 @@ struct RenderArgs {
   AdjSeed *seeds;       // [R] (backward)
   uint32_t *status;
   uint32_t *work;       // [kPoolParts] item counters of the persistent traversal launches (cleared before each)
-  uint32_t *kbuf;       // [items, 2K] k-buffers from traversal to compositing (t[K], then ids[K])
+  uint32_t *kbuf1;      // [primary items, 2K] k-buffers from traversal to compositing (t[K], then ids[K])
+  uint32_t *kbuf2;      // [secondary items, 2K] the same for the secondary queue
   // per-ray sample stride of contrib / frozen and of the queue capacity (spp, or the batch maximum)
   int32_t spp_stride;
   // continuous batching (NULL for one request): R = kChunk * number of chunks
   const ChunkDesc *chunks;
   const BatchSlot *slots;
 };
-// primary: traversal (k-buffers into kbuf), compositing, then shading
+// primary: traversal (k-buffers into kbuf1), compositing, then shading
 void launch_trace1(const RenderArgs &a, hipStream_t st);
 void launch_composite1(const RenderArgs &a, bool replay, hipStream_t st);
 void launch_shade1(const RenderArgs &a, bool replay, hipStream_t st);
@@ -125,9 +126,9 @@ struct GradArgs {
   const float *d_radiance, *d_depth, *d_normal, *d_alpha;
   float *g_mu, *g_q, *g_scale, *g_opacity, *g_albedo, *g_roughness, *g_metallic, *g_env;
 };
-// shading adjoint (env gradients, compositing seeds), replayed traversal of the seeded rays, compositing adjoint
+// shading adjoint (env gradients, compositing seeds), then the compositing adjoint of the seeded rays from the
+// primary k-buffers (kbuf1) of the replayed primary pass
 void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st);
-void launch_adjoint_trace(const RenderArgs &a, hipStream_t st);
 void launch_adjoint_hits(const RenderArgs &a, const GradArgs &g, hipStream_t st);
 
 inline int kbucket(int k) { return k <= 8 ? 8 : (k <= 16 ? 16 : (k <= 32 ? 32 : 64)); }

@@ -321,7 +321,7 @@ struct PrimaryWork {
     inst = v.inst;
     return true;
   }
-  __device__ void store(int64_t item, const KBufF<K> &kb) const { store_kbuf<K>(kb, a.kbuf + item * 2 * K); }
+  __device__ void store(int64_t item, const KBufF<K> &kb) const { store_kbuf<K>(kb, a.kbuf1 + item * 2 * K); }
 };
 
 template <int K, bool B>
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_composite1(RenderArgs a, bool replay
   float of[3], df[3];
   req_ray<B>(a, ray, v, of, df);
   KBufF<K> kb;
-  load_kbuf<K>(kb, a.kbuf + item * 2 * K);
+  load_kbuf<K>(kb, a.kbuf1 + item * 2 * K);
   SceneView S = a.S;
   S.inst = v.inst;
   finish_primary<K>(a, S, v, replay, ray, kb, mk(of[0], of[1], of[2]), mk(df[0], df[1], df[2]));
@@ -444,7 +444,7 @@ struct SecondaryWork {
     else inst = a.S.inst;
     return true;
   }
-  __device__ void store(int64_t item, const KBufF<K> &kb) const { store_kbuf<K>(kb, a.kbuf + item * 2 * K); }
+  __device__ void store(int64_t item, const KBufF<K> &kb) const { store_kbuf<K>(kb, a.kbuf2 + item * 2 * K); }
 };
 
 template <int K, bool B>
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_composite2(RenderArgs a) {
   SceneView S = a.S;
   if constexpr (B) S.inst = a.slots[a.chunks[e.ray / kChunk].slot].inst;
   KBufF<K> kb;
-  load_kbuf<K>(kb, a.kbuf + (int64_t)item * 2 * K);
+  load_kbuf<K>(kb, a.kbuf2 + (int64_t)item * 2 * K);
   finish_secondary<K>(a, S, qi, e, kb, mk(e.o[0], e.o[1], e.o[2]), mk(e.w[0], e.w[1], e.w[2]));
 }
 

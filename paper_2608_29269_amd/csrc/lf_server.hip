@@ -64,7 +64,7 @@ struct Lane {
   std::vector<lf::SchedTile> tiles;
   lf::ChunkDesc *h_chunks = nullptr;  // pinned
   IterReadback *h_rb = nullptr;       // pinned
-  DevBuf d_chunks, rec1, rec2, queue, qcount, work, kbuf, contrib, skeys, skeys2, svals, svals2, shist, status;
+  DevBuf d_chunks, rec1, rec2, queue, qcount, work, kbuf1, kbuf2, contrib, skeys, skeys2, svals, svals2, shist, status;
 };
 
 }  // namespace
@@ -220,7 +220,8 @@ bool launch_pass(lf_server *s, Lane &L, const std::vector<lf::SchedTile> &tiles)
   a.queue = L.queue.as<lf::SecEntry>();
   a.queue_count = L.qcount.as<uint32_t>();
   a.work = L.work.as<uint32_t>();
-  a.kbuf = L.kbuf.as<uint32_t>();
+  a.kbuf1 = L.kbuf1.as<uint32_t>();
+  a.kbuf2 = L.kbuf2.as<uint32_t>();
   a.contrib = L.contrib.as<float>();
   a.status = L.status.as<uint32_t>();
   const bool sorted = !(s->cfg.params.flags & LF_FLAG_UNSORTED);
@@ -486,7 +487,8 @@ lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **o
          L.d_chunks.ensure(sizeof(lf::ChunkDesc) * s->max_chunks) && L.rec1.ensure(sizeof(lf::SurfRec) * B) &&
          L.rec2.ensure(sizeof(lf::SurfRec) * BS) && L.queue.ensure(sizeof(lf::SecEntry) * BS) &&
          L.qcount.ensure(4) && L.work.ensure(sizeof(uint32_t) * lf::kPoolParts) &&
-         L.kbuf.ensure(sizeof(uint32_t) * 2 * lf::kbucket(s->cfg.params.k) * BS) &&
+         L.kbuf1.ensure(sizeof(uint32_t) * 2 * lf::kbucket(s->cfg.params.k) * B) &&
+         L.kbuf2.ensure(sizeof(uint32_t) * 2 * lf::kbucket(s->cfg.params.k) * BS) &&
          L.contrib.ensure(sizeof(float) * 3 * BS) && L.skeys.ensure(8 * BS) && L.skeys2.ensure(8 * BS) &&
          L.svals.ensure(4 * BS) && L.svals2.ensure(4 * BS) && L.shist.ensure(4 * lf::radix_sort_hist_words(BS)) &&
          L.status.ensure(4);
