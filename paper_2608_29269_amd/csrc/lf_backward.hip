@@ -16,16 +16,46 @@ namespace {
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-__device__ __forceinline__ void env_scatter(const EnvView &E, float *genv, d3 w, d3 g) {
+// Per-block accumulation of environment-texel gradients in an LDS table
+// keyed by texel (open addressing, a few probes), flushed with one atomic per
+// texel and channel; a texel that finds no slot goes to device memory
+// directly.  Importance-sampled directions and the background of
+// neighbouring pixels meet the same texels, so this replaces most
+// device-scope atomics on shared addresses.
+constexpr int kEnvAggBits = 10;
+constexpr int kEnvAggSlots = 1 << kEnvAggBits;  // 16 KB of LDS per block with the values
+constexpr int kEnvAggProbes = 8;
+
+struct BlockEnvTable {
+  int *key;     // [kEnvAggSlots], -1 when free
+  float *val;   // [3][kEnvAggSlots]
+  float *genv;  // [H, W, 3] in device memory
+  __device__ void add(int texel, float gx, float gy, float gz) {
+    const uint32_t h = (uint32_t)texel * 2654435761u;
+#pragma unroll 1
+    for (int p = 0; p < kEnvAggProbes; ++p) {
+      const int slot = (int)((h >> (32 - kEnvAggBits)) + (uint32_t)p) & (kEnvAggSlots - 1);
+      const int k = atomicCAS(key + slot, -1, texel);
+      if (k == -1 || k == texel) {
+        atomicAdd(val + slot, gx);
+        atomicAdd(val + kEnvAggSlots + slot, gy);
+        atomicAdd(val + 2 * kEnvAggSlots + slot, gz);
+        return;
+      }
+    }
+    atomicAdd(genv + 3 * texel + 0, gx);
+    atomicAdd(genv + 3 * texel + 1, gy);
+    atomicAdd(genv + 3 * texel + 2, gz);
+  }
+};
+
+__device__ __forceinline__ void env_scatter(const EnvView &E, BlockEnvTable &acc, d3 w, d3 g) {
   Taps tp;
   env_taps(E, w, tp);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (tp.w[k] == 0.0) continue;
-    float *p = genv + 3 * tp.i[k];
-    atomicAdd(p + 0, (float)(tp.w[k] * g.x));
-    atomicAdd(p + 1, (float)(tp.w[k] * g.y));
-    atomicAdd(p + 2, (float)(tp.w[k] * g.z));
+    acc.add((int)tp.i[k], (float)(tp.w[k] * g.x), (float)(tp.w[k] * g.y), (float)(tp.w[k] * g.z));
   }
 }
 
@@ -74,9 +104,8 @@ __device__ __forceinline__ void fcos_bwd(d3 n, d3 wi, d3 wo, d3 a, double m, dou
 // F_s = K_s f(w_s) (n.w_s) (T2 E(w_s) + ce E(w_e) + cb E(w_b)); environment
 // gradients are scattered here, and the adjoints of the surface record are
 // reduced to the seeds of the compositing adjoint.
-__global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G) {
-  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ray >= a.R) return;
+__device__ __forceinline__ void adj_shade_ray(const RenderArgs &a, const GradArgs &G, int64_t ray,
+                                              BlockEnvTable &acc) {
   const TraceParams &P = a.P;
   const int S = P.spp;
   float of[3], df[3];
@@ -90,7 +119,7 @@ __global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G) {
   if (!(P.flags & LF_FLAG_NO_BACKGROUND)) {
     const d3 Ed = env_eval(a.E, d);
     gT += dot(gL, Ed);
-    env_scatter(a.E, G.g_env, d, rc.T * gL);
+    env_scatter(a.E, acc, d, rc.T * gL);
   }
   AdjSeed sd = {};
   sd.T = (float)rc.T;
@@ -126,9 +155,9 @@ __global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G) {
     const d3 gF = (rc.A / S) * gL;
     const d3 gfc = K_ * mk(gF.x * Lin.x, gF.y * Lin.y, gF.z * Lin.z);
     const d3 gLin = K_ * mk(gF.x * fc.x, gF.y * fc.y, gF.z * fc.z);
-    env_scatter(a.E, G.g_env, w, T2 * gLin);
-    if (has & 1u) env_scatter(a.E, G.g_env, we, mk(ce.x * gLin.x, ce.y * gLin.y, ce.z * gLin.z));
-    if (has & 2u) env_scatter(a.E, G.g_env, wb, mk(cb.x * gLin.x, cb.y * gLin.y, cb.z * gLin.z));
+    env_scatter(a.E, acc, w, T2 * gLin);
+    if (has & 1u) env_scatter(a.E, acc, we, mk(ce.x * gLin.x, ce.y * gLin.y, ce.z * gLin.z));
+    if (has & 2u) env_scatter(a.E, acc, wb, mk(cb.x * gLin.x, cb.y * gLin.y, cb.z * gLin.z));
     fcos_bwd(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags, gfc, gn, ga, gm, gr);
   }
   // normalisation n_bar = N / |N|; z_bar = Z * inv with inv = 1/(A + eps)
@@ -146,6 +175,28 @@ __global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G) {
   sd.gZa[0] = (float)(ga.x * inv); sd.gZa[1] = (float)(ga.y * inv); sd.gZa[2] = (float)(ga.z * inv);
   sd.pad[0] = 1.0f;  // ray has hits
   a.seeds[ray] = sd;
+}
+
+__global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G) {
+  __shared__ int key[kEnvAggSlots];
+  __shared__ float val[3 * kEnvAggSlots];
+  for (int j = threadIdx.x; j < kEnvAggSlots; j += blockDim.x) {
+    key[j] = -1;
+    val[j] = val[kEnvAggSlots + j] = val[2 * kEnvAggSlots + j] = 0.0f;
+  }
+  __syncthreads();
+  BlockEnvTable acc{key, val, G.g_env};
+  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ray < a.R) adj_shade_ray(a, G, ray, acc);
+  __syncthreads();
+  for (int j = threadIdx.x; j < kEnvAggSlots; j += blockDim.x) {
+    const int t = key[j];
+    if (t < 0) continue;
+    for (int c = 0; c < 3; ++c) {
+      const float g = val[c * kEnvAggSlots + j];
+      if (g != 0.0f) atomicAdd(G.g_env + 3 * t + c, g);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- gradient accumulation
