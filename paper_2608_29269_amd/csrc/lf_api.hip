@@ -82,7 +82,7 @@ namespace lfh {
 lf_status refit_impl(lf_ctx *c, double alpha_min, double sig2) {
   Phase ph(c, 0);
   lf::launch_refit(c->s, alpha_min, sig2, c->perm.as<int32_t>(), c->leaf_parent.as<int32_t>(),
-                   c->node_parent.as<int32_t>(), c->flags.as<int32_t>(), c->n_nodes, c->n_inst,
+                   c->node_parent.as<int32_t>(), c->node_order.as<int32_t>(), c->h_level_off, c->n_nodes, c->n_inst,
                    c->nodes.as<lf::BNode>(), c->rec.as<lf::TraceRec>(), c->filt.as<lf::FiltRec>(),
                    c->leafbox.as<float>(), c->rootbox.as<float>(), c->status.as<uint32_t>(), c->stream);
   lf::launch_wide_quantize(c->nodes.as<lf::BNode>(), c->winfo.as<lf::WideInfo>(), c->n_wide, c->n_nodes,
@@ -493,6 +493,27 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
       hipMemcpyAsync(c->d_root.p, root4.data(), 4 * n_inst, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return check_hip(c, "traversal nodes");
+  // binary nodes by depth for the level-by-level refit
+  std::vector<int32_t> h_depth(nodes), h_order(nodes);
+  c->h_level_off.assign(1, 0);
+  if (!c->node_order.ensure(sizeof(int32_t) * nn)) return fail(c, LF_ENOMEM, "refit order");
+  if (nodes > 0) {
+    lf::launch_node_depth(c->node_parent.as<int32_t>(), c->n_nodes, level, c->status.as<uint32_t>(), st);
+    if (hipMemcpy(h_depth.data(), level, sizeof(int32_t) * nodes, hipMemcpyDeviceToHost) != hipSuccess)
+      return check_hip(c, "refit order");
+    int32_t dmax = 0;
+    for (int64_t i = 0; i < nodes; ++i) {
+      if (h_depth[i] < 0 || h_depth[i] > 4096) return fail(c, LF_EDEVICE, "inconsistent node depth");
+      dmax = std::max(dmax, h_depth[i]);
+    }
+    c->h_level_off.assign(dmax + 2, 0);
+    for (int64_t i = 0; i < nodes; ++i) ++c->h_level_off[h_depth[i] + 1];
+    for (int32_t d = 0; d <= dmax; ++d) c->h_level_off[d + 1] += c->h_level_off[d];
+    std::vector<int64_t> fill(c->h_level_off.begin(), c->h_level_off.end() - 1);
+    for (int64_t i = 0; i < nodes; ++i) h_order[fill[h_depth[i]]++] = (int32_t)i;
+    if (hipMemcpy(c->node_order.p, h_order.data(), sizeof(int32_t) * nodes, hipMemcpyHostToDevice) != hipSuccess)
+      return check_hip(c, "refit order");
+  }
   lf_status s2 = refit_impl(c, dp.alpha_min, sig2);
   if (s2) return s2;
   if (hipStreamSynchronize(st) != hipSuccess) return check_hip(c, "scene build");

@@ -366,15 +366,17 @@ __global__ void k_depth(const int32_t *leaf_parent, const int32_t *node_parent, 
   atomicMax(max_depth, dep);
 }
 
-// trace records by leaf position and bounds from the leaves up; a node's
-// second arriving child computes its box (release/acquire on the arrival count)
-__global__ void k_refit(SurfelArrays s, double alpha_min, double sig2, const int32_t *perm,
-                        const int32_t *leaf_parent, const int32_t *node_parent, int32_t *flags, BNode *nodes,
-                        int64_t n_nodes, int n_inst, TraceRec *rec, FiltRec *filt, float *leaf_box6,
-                        float *root_box6, uint32_t *status) {
-  int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Refit in levels: the leaves first (trace and filter records by leaf
+// position, each leaf's box into its parent's slot for it), then one launch
+// per binary depth from the deepest up, each node's box (the union of its
+// two slots) into its parent's slot; kernel boundaries order the levels, so
+// no atomics are needed.  Roots write their instance's bounds.
+__global__ void k_refit_leaves(SurfelArrays s, double alpha_min, double sig2, const int32_t *perm,
+                               const int32_t *leaf_parent, BNode *nodes, int64_t n_nodes, int n_inst, TraceRec *rec,
+                               FiltRec *filt, float *leaf_box6, float *root_box6, uint32_t *status) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (pos >= s.n) return;
-  int orig = perm[pos];
+  const int orig = perm[pos];
   if (orig < 0 || orig >= s.n) {
     atomicOr(status, kStatusBvhCorrupt);
     return;
@@ -384,29 +386,74 @@ __global__ void k_refit(SurfelArrays s, double alpha_min, double sig2, const int
   surfel_prep(s, orig, alpha_min, sig2, r, lo, hi, filt + pos);
   rec[pos] = r;
   for (int k = 0; k < 3; ++k) { leaf_box6[6 * pos + k] = lo[k]; leaf_box6[6 * pos + 3 + k] = hi[k]; }
-  int pp = leaf_parent[pos];
-  int steps = 0;
-  while (pp >= 0) {
-    int p = pp >> 1, side = pp & 1;
-    if (p >= n_nodes || ++steps > 4096) {  // never taken for a consistent hierarchy
+  const int pp = leaf_parent[pos];
+  if (pp >= 0) {
+    if ((pp >> 1) >= n_nodes) {  // never taken for a consistent hierarchy
       atomicOr(status, kStatusBvhCorrupt);
       return;
     }
-    BNode *nd = nodes + p;
-    float *dlo = side ? nd->lo1 : nd->lo0, *dhi = side ? nd->hi1 : nd->hi0;
+    BNode *nd = nodes + (pp >> 1);
+    float *dlo = (pp & 1) ? nd->lo1 : nd->lo0, *dhi = (pp & 1) ? nd->hi1 : nd->hi0;
     for (int k = 0; k < 3; ++k) { dlo[k] = lo[k]; dhi[k] = hi[k]; }
-    int old = __hip_atomic_fetch_add(flags + p, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == 0) return;
-    const float *slo = side ? nd->lo0 : nd->lo1, *shi = side ? nd->hi0 : nd->hi1;
-    for (int k = 0; k < 3; ++k) { lo[k] = fminf(lo[k], slo[k]); hi[k] = fmaxf(hi[k], shi[k]); }
-    pp = node_parent[p];
+    return;
   }
-  int inst = -pp - 2;
+  const int inst = -pp - 2;
   if (inst < 0 || inst >= n_inst) {
     atomicOr(status, kStatusBvhCorrupt);
     return;
   }
   for (int k = 0; k < 3; ++k) { root_box6[6 * inst + k] = lo[k]; root_box6[6 * inst + 3 + k] = hi[k]; }
+}
+
+__global__ void k_refit_level(const int32_t *order, int64_t begin, int64_t end, const int32_t *node_parent,
+                              BNode *nodes, int64_t n_nodes, int n_inst, float *root_box6, uint32_t *status) {
+  const int64_t idx = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= end) return;
+  const int p = order[idx];
+  if (p < 0 || p >= n_nodes) {
+    atomicOr(status, kStatusBvhCorrupt);
+    return;
+  }
+  const BNode nd = nodes[p];
+  float lo[3], hi[3];
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = fminf(nd.lo0[k], nd.lo1[k]);
+    hi[k] = fmaxf(nd.hi0[k], nd.hi1[k]);
+  }
+  const int pp = node_parent[p];
+  if (pp >= 0) {
+    if ((pp >> 1) >= n_nodes) {
+      atomicOr(status, kStatusBvhCorrupt);
+      return;
+    }
+    BNode *q = nodes + (pp >> 1);
+    float *dlo = (pp & 1) ? q->lo1 : q->lo0, *dhi = (pp & 1) ? q->hi1 : q->hi0;
+    for (int k = 0; k < 3; ++k) { dlo[k] = lo[k]; dhi[k] = hi[k]; }
+    return;
+  }
+  const int inst = -pp - 2;
+  if (inst < 0 || inst >= n_inst) {
+    atomicOr(status, kStatusBvhCorrupt);
+    return;
+  }
+  for (int k = 0; k < 3; ++k) { root_box6[6 * inst + k] = lo[k]; root_box6[6 * inst + 3 + k] = hi[k]; }
+}
+
+// depth of every binary internal node (root = 0)
+__global__ void k_node_depth(const int32_t *node_parent, int64_t n_nodes, int32_t *depth, uint32_t *status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_nodes) return;
+  int dep = 0;
+  int p = node_parent[i];
+  while (p >= 0) {
+    if ((p >> 1) >= n_nodes || dep > 4096) {  // never taken for a consistent hierarchy
+      atomicOr(status, kStatusBvhCorrupt);
+      break;
+    }
+    ++dep;
+    p = node_parent[p >> 1];
+  }
+  depth[i] = dep;
 }
 
 // ---------------------------------------------------------------- wide nodes
@@ -786,14 +833,26 @@ void launch_depth(const int32_t *leaf_parent, const int32_t *node_parent, int64_
                      max_depth, status);
 }
 
+void launch_node_depth(const int32_t *node_parent, int64_t n_nodes, int32_t *depth, uint32_t *status,
+                       hipStream_t st) {
+  if (n_nodes <= 0) return;
+  hipLaunchKernelGGL(k_node_depth, dim3(blocks(n_nodes, 256)), dim3(256), 0, st, node_parent, n_nodes, depth, status);
+}
+
 void launch_refit(const SurfelArrays &s, double alpha_min, double sig2, const int32_t *perm,
-                  const int32_t *leaf_parent, const int32_t *node_parent, int32_t *flags, int64_t n_nodes,
-                  int n_inst, BNode *nodes, TraceRec *rec, FiltRec *filt, float *leaf_box6, float *root_box6,
-                  uint32_t *status, hipStream_t st) {
+                  const int32_t *leaf_parent, const int32_t *node_parent, const int32_t *order,
+                  const std::vector<int64_t> &level_off, int64_t n_nodes, int n_inst, BNode *nodes, TraceRec *rec,
+                  FiltRec *filt, float *leaf_box6, float *root_box6, uint32_t *status, hipStream_t st) {
   if (s.n <= 0) return;
-  if (n_nodes > 0) launch_fill_u32((uint32_t *)flags, 0u, n_nodes, st);
-  hipLaunchKernelGGL(k_refit, dim3(blocks(s.n, 256)), dim3(256), 0, st, s, alpha_min, sig2, perm, leaf_parent,
-                     node_parent, flags, nodes, n_nodes, n_inst, rec, filt, leaf_box6, root_box6, status);
+  hipLaunchKernelGGL(k_refit_leaves, dim3(blocks(s.n, 256)), dim3(256), 0, st, s, alpha_min, sig2, perm, leaf_parent,
+                     nodes, n_nodes, n_inst, rec, filt, leaf_box6, root_box6, status);
+  // level_off[d] .. level_off[d + 1]: the nodes of depth d in order; deepest first
+  for (int64_t d = (int64_t)level_off.size() - 2; d >= 0; --d) {
+    const int64_t b = level_off[d], e = level_off[d + 1];
+    if (e > b)
+      hipLaunchKernelGGL(k_refit_level, dim3(blocks(e - b, 256)), dim3(256), 0, st, order, b, e, node_parent, nodes,
+                         n_nodes, n_inst, root_box6, status);
+  }
 }
 
 void launch_wide_roots(const int32_t *root, const int32_t *cnt, int n_inst, int32_t *level, hipStream_t st) {

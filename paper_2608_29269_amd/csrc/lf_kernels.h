@@ -1,6 +1,7 @@
 // lf_kernels.h -- host-side launchers of the gfx950 kernels (internal).
 #pragma once
 #include <atomic>
+#include <vector>
 
 #include "lf_internal.h"
 
@@ -32,11 +33,15 @@ bool launch_ploc(const int32_t *perm, const float *boxidx, int32_t first, int32_
 // leaf depth maximum into *max_depth (device int)
 void launch_depth(const int32_t *leaf_parent, const int32_t *node_parent, int64_t n, int64_t n_nodes,
                   int32_t *max_depth, uint32_t *status, hipStream_t st);
-// trace records + bottom-up bounds
+// depth of every binary internal node (root = 0)
+void launch_node_depth(const int32_t *node_parent, int64_t n_nodes, int32_t *depth, uint32_t *status,
+                       hipStream_t st);
+// trace records + bounds level by level: order lists the internal nodes by depth, level_off[d] the first of
+// depth d (level_off.back() = n_nodes)
 void launch_refit(const SurfelArrays &s, double alpha_min, double sig2, const int32_t *perm,
-                  const int32_t *leaf_parent, const int32_t *node_parent, int32_t *flags, int64_t n_nodes,
-                  int n_inst, BNode *nodes, TraceRec *rec, FiltRec *filt, float *leaf_box6, float *root_box6,
-                  uint32_t *status, hipStream_t st);
+                  const int32_t *leaf_parent, const int32_t *node_parent, const int32_t *order,
+                  const std::vector<int64_t> &level_off, int64_t n_nodes, int n_inst, BNode *nodes, TraceRec *rec,
+                  FiltRec *filt, float *leaf_box6, float *root_box6, uint32_t *status, hipStream_t st);
 // Wide traversal nodes (greedy surface-area collapse of the binary hierarchy).
 // level[b] = -1 for every binary node first; roots of instances with >= 2 surfels get level 0
 void launch_wide_roots(const int32_t *root, const int32_t *cnt, int n_inst, int32_t *level, hipStream_t st);
