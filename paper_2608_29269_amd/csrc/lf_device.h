@@ -266,13 +266,22 @@ __device__ __forceinline__ bool slab64(d3 o, d3 d, const double *lo, const doubl
 // grown by pad >= the distance between the exact ray and this binary32 ray
 // over the instance's parameter range (rounded origin and direction, and the
 // clamping of tiny direction components), so a box the exact ray enters is
-// never culled.
+// never culled.  On axis a a node's plane of code q is met at
+// q * (2^e / d) + fma(p, 1/d, nb) (near planes) or + fma(p, 1/d, fb) (far
+// planes), with nb = -o / d - pad / |d| - E and fb = -o / d + pad / |d| + E;
+// E bounds every rounding in these (of 1/d, the products, the fused
+// multiply-adds and the half ulp between a decoded plane and its real code
+// value) for frame origins and steps within the instance's object-space
+// bounds (|p| <= omag, 255 * 2^e <= 4 oext), so near distances are never
+// overestimated and far ones never underestimated.  An axis whose terms are
+// not safely finite is left unconstrained.
 struct RayF {
   float ox, oy, oz;      // origin
   float dx, dy, dz;      // direction
   float ix, iy, iz;      // 1/d
   bool sx, sy, sz;       // d >= 0 per axis
-  float pad;
+  float nbx, nby, nbz;   // near-plane offsets
+  float fbx, fby, fbz;   // far-plane offsets
   float oabs;            // max |origin component|
 };
 
@@ -281,38 +290,33 @@ __device__ __forceinline__ float inv_dir(float d) {
   return 1.0f / dd;
 }
 
-__device__ __forceinline__ void make_rayf(d3 oo, d3 dd, double tabs, RayF &rf) {
+__device__ __forceinline__ void plane_offsets(float o, float inv, float pad, float omag, float oext, float &nb,
+                                              float &fb) {
+  const float ai = fabsf(inv);
+  const float span = (omag + 4.0f * oext + fabsf(o) + pad) * ai;
+  if (!(span < 0x1p100f)) {
+    nb = -INFINITY;
+    fb = INFINITY;
+    return;
+  }
+  const float E = 0x1p-18f * span + 1e-30f;
+  const float ob = o * inv, g = pad * ai;
+  nb = (-ob - g) - E;
+  fb = (-ob + g) + E;
+}
+
+__device__ __forceinline__ void make_rayf(d3 oo, d3 dd, double tabs, float omag, float oext, RayF &rf) {
   rf.ox = (float)oo.x; rf.oy = (float)oo.y; rf.oz = (float)oo.z;
   rf.dx = (float)dd.x; rf.dy = (float)dd.y; rf.dz = (float)dd.z;
   rf.oabs = fmaxf(fmaxf(fabsf(rf.ox), fabsf(rf.oy)), fabsf(rf.oz));
   const double eo = fmax(fmax(fabs(oo.x - rf.ox), fabs(oo.y - rf.oy)), fabs(oo.z - rf.oz));
   const double ed = fmax(fmax(fabs(dd.x - rf.dx), fabs(dd.y - rf.dy)), fabs(dd.z - rf.dz)) + 1e-20;
-  rf.pad = (float)((eo + ed * tabs + 1e-30) * 1.001) + 1e-30f;
+  const float pad = (float)((eo + ed * tabs + 1e-30) * 1.001) + 1e-30f;
   rf.ix = inv_dir(rf.dx); rf.iy = inv_dir(rf.dy); rf.iz = inv_dir(rf.dz);
   rf.sx = rf.ix >= 0.f; rf.sy = rf.iy >= 0.f; rf.sz = rf.iz >= 0.f;
-}
-
-// Distances along one axis in a node's frame: a plane of code q lies at
-// q * C + B, with B the near (Bn) or far (Bf) offset.  C = 2^e / d is exact;
-// E bounds the rounding of the frame origin's distance, of 1/d, of the
-// decoded plane (within half an ulp of the fused multiply-add the build
-// checked), of the products and of the per-slot fused multiply-add (at most
-// 2^-24 (255 |C| + |B|)), so near distances are never overestimated and far
-// ones never underestimated for the box grown by pad.  An axis whose terms
-// are not safely finite is left unconstrained.
-__device__ __forceinline__ void axis_frame(float p, int e, float o, float inv, float pad, float &C, float &Bn,
-                                           float &Bf) {
-  C = __uint_as_float((uint32_t)(e + 127) << 23) * inv;
-  const float ai = fabsf(inv);
-  const float b = (p - o) * inv, g = pad * ai;
-  const float E = 0x1p-20f * __builtin_fmaf(fabsf(p), ai, __builtin_fmaf(255.0f, fabsf(C), fabsf(b)) + g) + 1e-30f;
-  Bn = (b - g) - E;
-  Bf = (b + g) + E;
-  if (!(fabsf(C) <= 0x1p118f) || !(fabsf(Bn) <= 0x1p126f) || !(fabsf(Bf) <= 0x1p126f)) {
-    C = 0.0f;
-    Bn = -INFINITY;
-    Bf = INFINITY;
-  }
+  plane_offsets(rf.ox, rf.ix, pad, omag, oext, rf.nbx, rf.fbx);
+  plane_offsets(rf.oy, rf.iy, pad, omag, oext, rf.nby, rf.fby);
+  plane_offsets(rf.oz, rf.iz, pad, omag, oext, rf.nbz, rf.fbz);
 }
 
 // Visits one traversal node: entry t of every slot whose decoded box (grown
@@ -333,10 +337,14 @@ __device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, fl
     dw[4 * v] = x.x; dw[4 * v + 1] = x.y; dw[4 * v + 2] = x.z; dw[4 * v + 3] = x.w;
   }
   const uint32_t meta = dw[3];
-  float Cx, Cy, Cz, Bnx, Bny, Bnz, Bfx, Bfy, Bfz;
-  axis_frame(__uint_as_float(dw[0]), (int)(int8_t)(meta & 0xffu), rf.ox, rf.ix, rf.pad, Cx, Bnx, Bfx);
-  axis_frame(__uint_as_float(dw[1]), (int)(int8_t)((meta >> 8) & 0xffu), rf.oy, rf.iy, rf.pad, Cy, Bny, Bfy);
-  axis_frame(__uint_as_float(dw[2]), (int)(int8_t)((meta >> 16) & 0xffu), rf.oz, rf.iz, rf.pad, Cz, Bnz, Bfz);
+  // a plane of code q on axis a is met at q * C_a + B_a (see RayF)
+  const float px = __uint_as_float(dw[0]), py = __uint_as_float(dw[1]), pz = __uint_as_float(dw[2]);
+  const float Cx = __uint_as_float((uint32_t)((int)(int8_t)(meta & 0xffu) + 127) << 23) * rf.ix;
+  const float Cy = __uint_as_float((uint32_t)((int)(int8_t)((meta >> 8) & 0xffu) + 127) << 23) * rf.iy;
+  const float Cz = __uint_as_float((uint32_t)((int)(int8_t)((meta >> 16) & 0xffu) + 127) << 23) * rf.iz;
+  const float Bnx = __builtin_fmaf(px, rf.ix, rf.nbx), Bfx = __builtin_fmaf(px, rf.ix, rf.fbx);
+  const float Bny = __builtin_fmaf(py, rf.iy, rf.nby), Bfy = __builtin_fmaf(py, rf.iy, rf.fby);
+  const float Bnz = __builtin_fmaf(pz, rf.iz, rf.nbz), Bfz = __builtin_fmaf(pz, rf.iz, rf.fbz);
   imask = meta >> 24;
   cbase = (int)dw[4];
   lbase = (int)dw[5];
@@ -596,7 +604,7 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
   int ii = 0;              // the ray's current instance
   d3 o = mk(0, 0, 0), d = mk(0, 0, 1), oo = o, dd = d;
   RayF rf;
-  make_rayf(oo, dd, 0.0, rf);
+  make_rayf(oo, dd, 0.0, 0.0f, 0.0f, rf);
   int cur = kDone, qn = 0;
   while (true) {
     // idle lanes take the next items, one counter update per wave
@@ -641,7 +649,7 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
         if (itf < P.t_min) continue;
         if (itn > kth<K>(kb) * (1.0 + 1e-6)) continue;
         to_object(I, o, d, oo, dd);
-        make_rayf(oo, dd, fmax(fabs(itf), fabs(itn)), rf);
+        make_rayf(oo, dd, fmax(fabs(itf), fabs(itn)), I.omag, I.oext, rf);
         found = true;
         break;
       }

@@ -102,6 +102,9 @@ struct alignas(16) InstRec {
   int32_t identity; // 1: background (no transform)
   int32_t first;    // first surfel index / leaf position of the instance
   int32_t n;        // surfel count
+  float omag;       // largest |coordinate| of the object-space bounds of the instance's surfels
+  float oext;       // their largest extent
+  int32_t pad[2];
 };
 
 struct SceneView {

@@ -73,6 +73,13 @@ __global__ void k_instances(const float *R, const float *t, const float *root_bo
       I.n = 0;
     }
     for (int k = 0; k < 3; ++k) { I.lo[k] = lo[k]; I.hi[k] = hi[k]; }
+    I.omag = 0.0f;
+    I.oext = 0.0f;
+    for (int k = 0; k < 3; ++k) {
+      I.omag = fmaxf(I.omag, fmaxf(fabsf(rb[k]), fabsf(rb[3 + k])));
+      I.oext = fmaxf(I.oext, rb[3 + k] - rb[k]);
+    }
+    I.pad[0] = I.pad[1] = 0;
     out[ii] = I;
     for (int k = 0; k < 3; ++k) { sb[ii][k] = lo[k]; sb[ii][3 + k] = hi[k]; }
   }
