@@ -549,8 +549,8 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 // Persistent traversal of a pool of `count` work items (rays): every lane
 // holds one ray at a time, collects its k closest valid hits over all
 // instances and stores them with wk.store; a wave refills its idle lanes from
-// the shared counter *next once kRefillIdle of them are idle (or all are), so
-// the rays of a wave need not finish together (see kPoolParts for the
+// the shared counter *next once Work::kRefill of them are idle (or all are),
+// so the rays of a wave need not finish together (see kPoolParts for the
 // counters).  Work supplies
 //   bool begin(int64_t item, d3 &o, d3 &d, const InstRec *&inst)  (false: nothing to trace)
 //   void store(int64_t item, const KBufF<K> &kb)
@@ -565,7 +565,6 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 // entries in private scratch; internal nodes only) and lq at its first
 // leaf-queue slot (stride kBlock, kLeafQ entries).  Every lane leaves once
 // the pool is empty and its last ray is stored.
-constexpr int kRefillIdle = 4;
 
 template <int K, class Work>
 __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work &wk, int64_t count, uint32_t *next,
@@ -611,7 +610,7 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
     if (!exhausted) {
       const unsigned long long idle = __ballot(!live);
       const int n_idle = __popcll(idle);
-      if (n_idle >= kRefillIdle || (n_idle > 0 && !__any(live))) {
+      if (n_idle >= Work::kRefill || (n_idle > 0 && !__any(live))) {
         const int leader = __ffsll((long long)idle) - 1;
         uint32_t base = 0;
         if (lane == leader) base = atomicAdd(next + part, (uint32_t)n_idle);

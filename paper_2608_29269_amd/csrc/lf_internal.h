@@ -13,7 +13,7 @@ constexpr int kWide = 8;          // children per traversal node
 constexpr int kStackL = 32;       // traversal stack entries per lane held in LDS (16 KB per block)
 constexpr int kStack = 192;       // traversal stack entries per lane; those past kStackL in private scratch
 constexpr int kLeafQ = 48;        // leaf-queue entries per lane (LDS, 24 KB per block)
-constexpr int kLeafMin = 8;       // the node phase goes on while a lane that can visit nodes has fewer queued
+constexpr int kLeafMin = 12;       // the node phase goes on while a lane that can visit nodes has fewer queued
 // Persistent traversal splits its items into kPoolParts contiguous ranges
 // with one counter each; a block starts on range blockIdx % kPoolParts, so
 // with round-robin dispatch of blocks over the eight XCDs each XCD's L2
