@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=512, help="primary rays of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fwd-steps", type=int, default=5)
+    ap.add_argument("--geo-steps", type=int, default=10, help="timed geometry-refinement steps (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=40, help="requests per serving run (0 = skip)")
     ap.add_argument("--serve-loads", type=str, default="0.8",
                     help="comma-separated arrival rates as fractions of the plain tracer's capacity")
@@ -99,7 +100,11 @@ def main():
     tp = dict(mu=T(tgt_scene.mu), q=T(tgt_scene.q), scale=T(tgt_scene.scale), opacity=T(tgt_scene.opacity),
               albedo=T(tgt_scene.albedo), roughness=T(tgt_scene.roughness), metallic=T(tgt_scene.metallic))
     ttr.set_scene(**tp, object_offset=list(sc.object_offset))
-    target = ttr.render(env, R, t, **cfg)["radiance"].clone()
+    tgt = ttr.render(env, R, t, **cfg)
+    target = tgt["radiance"].clone()
+    # reference maps of the geometry objectives: depth, normals and a coverage-based confidence
+    geo_ref = dict(depth=tgt["depth"].clone(), normal=tgt["normal"].clone(),
+                   conf=(tgt["alpha"] > 0.5).float())
     ttr.sync()
     del ttr
 
@@ -199,6 +204,11 @@ def main():
                "sample": f"{len(pix)} random pixels of the 1024x1024 camera (plus their live secondary rays), "
                          f"fwd+bwd, 1M surfels brute force in FP64, {cdt:.1f} s"}
 
+    geometry = None
+    if args.geo_steps > 0:
+        log("geometry-refinement step")
+        geometry = geometry_bench(lf, tr, env, R, t, cam, wl, params, grads, out, geo_ref, args)
+
     serving = None
     if args.serve_requests > 0:
         serving = serve_bench(tr, sc, args, [float(x) for x in args.serve_loads.split(",") if x],
@@ -231,9 +241,83 @@ def main():
         "phases_ms_per_step": {k_: v[0] / args.steps for k_, v in phases.items() if v[1]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "geometry": geometry,
         "serving": serving,
     }
     print(json.dumps(res))
+
+
+# algorithmic HBM bytes per element of each geometry objective: maps read once, gradient written once
+GEO_BYTES = {"alpha": 8, "scale": 16, "depth": 16, "normal": 36, "depth_normal": 20}
+
+
+def geometry_bench(lf, tr, env, R, t, cam, wl, params, grads, out, ref, args, s_max=0.05, lr=1e-5):
+    """Ray-tracing-oriented geometry refinement (Sec. 3.2, Eq. geometry-objective
+    with unit weights): refit, primary render (depth, normal, alpha), the
+    objectives L_alpha, L_s, L_D, L_N, L_DN, the replayed backward through the
+    depth, normal and alpha maps, and an SGD update of the geometry (position,
+    rotation, scale, opacity).  Also times each objective alone over the
+    1024x1024 maps with the library's phase timers (whole call: zeroing,
+    the streaming pass and the final scalar)."""
+    import torch
+    gcfg = dict(cameras=[cam], k=wl.k, spp=1, seed=wl.seed, flags=lf.FLAG_NO_SECONDARY)
+    geo = ("mu", "q", "scale", "opacity")
+
+    def gstep():
+        tr.refit()
+        tr.render(env, R, t, out=out, **gcfg)
+        lD, gD = tr.loss_depth(out["depth"], ref["depth"], ref["conf"], eps=1e-6)
+        lN, gN = tr.loss_normal(out["normal"], ref["normal"])
+        lDN, gDN = tr.loss_depth_normal(cam, out["depth"], ref["normal"])
+        lA, gA = tr.loss_alpha(out["alpha"])
+        lS, gS = tr.loss_scale(params["scale"], s_max)
+        gD.add_(gDN)
+        tr.render_backward(env, R, t, d_depth=gD, d_normal=gN, d_alpha=gA, grads=grads, **gcfg)
+        with torch.no_grad():
+            grads["scale"].add_(gS)
+            for k_ in geo:
+                params[k_].sub_(lr * grads[k_])
+            params["scale"].clamp_(min=1e-4)
+            params["opacity"].clamp_(1e-4, 1.0)
+        return lD + lN + lDN + lA + lS
+
+    for _ in range(args.warmup):
+        gstep()
+    tr.sync()
+    tr.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.geo_steps):
+        loss = gstep()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = tr.stats()
+    res = {"ms_per_step": dt * 1e3 / args.geo_steps, "rays_per_s": (st["rays_primary"] + st["rays_secondary"]) / dt,
+           "loss": float(loss), "objectives": {}}
+
+    nr = cam.w * cam.h
+    calls = {
+        "alpha": (nr, lambda: tr.loss_alpha(out["alpha"])),
+        "scale": (params["scale"].shape[0], lambda: tr.loss_scale(params["scale"], s_max)),
+        "depth": (nr, lambda: tr.loss_depth(out["depth"], ref["depth"], ref["conf"], eps=1e-6)),
+        "normal": (nr, lambda: tr.loss_normal(out["normal"], ref["normal"])),
+        "depth_normal": (nr, lambda: tr.loss_depth_normal(cam, out["depth"], ref["normal"])),
+    }
+    reps = 50
+    for name, (n, fn) in calls.items():
+        fn()
+        tr.sync()
+        tr.profile(True)
+        tr.profile_read()
+        for _ in range(reps):
+            fn()
+        tr.sync()
+        ms = tr.profile_read()["loss"][0] / reps
+        tr.profile(False)
+        gbs = GEO_BYTES[name] * n / (ms * 1e-3) / 1e9
+        res["objectives"][name] = {"elements": int(n), "ms": ms, "bytes": GEO_BYTES[name] * n, "GB/s": gbs,
+                                   "frac": gbs / HBM_PEAK_GBS}
+    return res
 
 
 def serve_bench(tr, sc, args, loads, policies=(0,)):

@@ -198,6 +198,46 @@ lf_status lf_render_backward(lf_ctx *ctx, const lf_transforms *xf, const lf_envm
  * grad: device [n] or NULL. */
 lf_status lf_l1_loss(lf_ctx *ctx, const float *pred, const float *target, int64_t n, float *loss, float *grad);
 
+/* ---- Geometry-refinement objectives (Sec. 3.1 and 3.2).  Common contract:
+ * every array is a device array; loss is a device float scalar written
+ * asynchronously on the context's stream; grad, when non-NULL, is
+ * OVERWRITTEN with d(loss)/d(first map) (same shape); sums run in binary64;
+ * sign(0) = 0.  The gradients feed lf_render_backward's d_alpha, d_depth and
+ * d_normal.  Errors: LF_EINVAL for NULL maps, n < 0 or an invalid constant. */
+
+/* Coverage term L_alpha = (1/n) sum |A - 1| (Sec. 3.1, Eq. alpha-coverage)
+ * over an accumulated-opacity map alpha [n] (lf_outputs.alpha). */
+lf_status lf_loss_alpha(lf_ctx *ctx, const float *alpha, int64_t n, float *loss, float *grad);
+
+/* Scale regulariser L_s = (1/n) sum_i max(0, max(|s_u|,|s_v|)/s_max - 1)^2
+ * (Sec. 3.1, Eq. scale-regularization) over in-plane scales [n,2]; the
+ * gradient goes to the larger component (the first on a tie).  s_max > 0. */
+lf_status lf_loss_scale(lf_ctx *ctx, const float *scale, int64_t n, float s_max, float *loss, float *grad);
+
+/* Confidence-weighted depth term L_D = sum |C| |D - D*| / (sum |C| |D*| + eps)
+ * (Sec. 3.2, Eq. reconstruction-depth) over a rendered depth map D [n]
+ * (lf_outputs.depth), reference D* [n] and confidence C [n] (NULL: C = 1).
+ * eps > 0. */
+lf_status lf_loss_depth(lf_ctx *ctx, const float *depth, const float *ref, const float *conf, int64_t n, float eps,
+                        float *loss, float *grad);
+
+/* Rendered-normal term L_N = 1 - (1/n) sum <N, N*> (Sec. 3.2,
+ * Eq. reconstruction-normal) over normal maps [n,3] (lf_outputs.normal and
+ * the reference); grad = -N* / n.  n = 0 gives loss 0. */
+lf_status lf_loss_normal(lf_ctx *ctx, const float *normal, const float *ref, int64_t n, float *loss, float *grad);
+
+/* Depth-derived-normal term L_DN = 1 - (1/(w h)) sum <N^D, N*> (Sec. 3.2,
+ * Eq. reconstruction-normal) for the rendered depth map depth [h*w]
+ * (row-major, the rays of `cam` as lf_raygen makes them) and reference
+ * normals ref [h*w,3].  N^D at pixel (x, y) is the unit vector along
+ * (P(x+1,y) - P(x-1,y)) x (P(x,y-1) - P(x,y+1)), P = o + depth * d the point
+ * on the pixel's ray (row 0 at the top), which faces the camera on a smooth
+ * surface; N^D = 0 on the image border, next to a pixel with depth <= 0 (no
+ * surface) or where the cross product vanishes.  grad: d(loss)/d(depth) [h*w].
+ * Errors: LF_EINVAL for an invalid camera or h > 1048560. */
+lf_status lf_loss_depth_normal(lf_ctx *ctx, const lf_camera *cam, const float *depth, const float *ref, float *loss,
+                               float *grad);
+
 /* Pinhole rays of one camera (device o, d: [w*h,3]) exactly as lf_render
  * generates them. */
 lf_status lf_raygen(lf_ctx *ctx, const lf_camera *cam, float *o, float *d);

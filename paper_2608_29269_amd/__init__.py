@@ -40,6 +40,12 @@ def _check_tensor(t, name, shape_tail, n=None):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [{n}, {', '.join(map(str, shape_tail))}]")
 
 
+def _check_f32(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+
+
 def camera_struct(cam) -> _lib.Camera:
     """lf_camera from an object with pose[12], fov_y_deg, w, h."""
     c = _lib.Camera()
@@ -205,6 +211,61 @@ class Tracer:
         loss = torch.empty((), device=self.device)
         grad = torch.empty_like(pred) if want_grad else None
         self._chk(self.L.lf_l1_loss(self.ctx, _ptr(pred), _ptr(target), pred.numel(), _ptr(loss), _ptr(grad)))
+        return loss, grad
+
+    # -- geometry-refinement objectives (Sec. 3.1, 3.2); each returns
+    #    (loss device scalar, gradient w.r.t. the first map or None)
+    def _loss_out(self, like, want_grad):
+        import torch
+        return torch.empty((), device=self.device), (torch.empty_like(like) if want_grad else None)
+
+    def loss_alpha(self, alpha, want_grad=True):
+        """L_alpha = mean |A - 1| over the accumulated-opacity map (Eq. alpha-coverage)."""
+        _check_f32(alpha)
+        loss, grad = self._loss_out(alpha, want_grad)
+        self._chk(self.L.lf_loss_alpha(self.ctx, _ptr(alpha), alpha.numel(), _ptr(loss), _ptr(grad)))
+        return loss, grad
+
+    def loss_scale(self, scale, s_max, want_grad=True):
+        """L_s over in-plane scales [N,2] (Eq. scale-regularization)."""
+        _check_f32(scale)
+        if scale.dim() != 2 or scale.shape[1] != 2:
+            raise ValueError("scale must be [N,2]")
+        loss, grad = self._loss_out(scale, want_grad)
+        self._chk(self.L.lf_loss_scale(self.ctx, _ptr(scale), scale.shape[0], float(s_max), _ptr(loss), _ptr(grad)))
+        return loss, grad
+
+    def loss_depth(self, depth, ref, conf=None, eps=1e-6, want_grad=True):
+        """L_D, confidence-weighted relative L1 on depth (Eq. reconstruction-depth); conf None means 1."""
+        for t in (depth, ref) + ((conf,) if conf is not None else ()):
+            _check_f32(t)
+            if t.numel() != depth.numel():
+                raise ValueError("depth, ref and conf sizes differ")
+        loss, grad = self._loss_out(depth, want_grad)
+        self._chk(self.L.lf_loss_depth(self.ctx, _ptr(depth), _ptr(ref), _ptr(conf), depth.numel(), float(eps),
+                                       _ptr(loss), _ptr(grad)))
+        return loss, grad
+
+    def loss_normal(self, normal, ref, want_grad=True):
+        """L_N = 1 - mean <N, N*> over [P,3] normal maps (Eq. reconstruction-normal)."""
+        _check_f32(normal)
+        _check_f32(ref)
+        if normal.shape != ref.shape or normal.dim() != 2 or normal.shape[1] != 3:
+            raise ValueError("normal and ref must both be [P,3]")
+        loss, grad = self._loss_out(normal, want_grad)
+        self._chk(self.L.lf_loss_normal(self.ctx, _ptr(normal), _ptr(ref), normal.shape[0], _ptr(loss), _ptr(grad)))
+        return loss, grad
+
+    def loss_depth_normal(self, camera, depth, ref, want_grad=True):
+        """L_DN on the normals derived from the rendered depth of `camera` (Eq. reconstruction-normal)."""
+        _check_f32(depth)
+        _check_f32(ref)
+        n = int(camera.w) * int(camera.h)
+        if depth.numel() != n or ref.numel() != 3 * n:
+            raise ValueError("depth must hold w*h values and ref w*h normals")
+        c = camera_struct(camera)
+        loss, grad = self._loss_out(depth, want_grad)
+        self._chk(self.L.lf_loss_depth_normal(self.ctx, C.byref(c), _ptr(depth), _ptr(ref), _ptr(loss), _ptr(grad)))
         return loss, grad
 
     def raygen(self, camera):

@@ -669,11 +669,10 @@ lf_status lf_l1_loss(lf_ctx *c, const float *pred, const float *target, int64_t 
   return check_hip(c, "l1 loss");
 }
 
-lf_status lf_raygen(lf_ctx *c, const lf_camera *cam, float *o, float *d) {
-  if (!c) return LF_EINVAL;
-  if (!cam || !o || !d || cam->w < 1 || cam->h < 1 || !(cam->fov_y_deg > 0.f && cam->fov_y_deg < 180.f))
-    return fail(c, LF_EINVAL, "invalid raygen arguments");
-  set_device(c);
+// Uploads one camera into c->cams (camera 0); validates it first.
+static lf_status upload_camera(lf_ctx *c, const lf_camera *cam) {
+  if (!cam || cam->w < 1 || cam->h < 1 || !(cam->fov_y_deg > 0.f && cam->fov_y_deg < 180.f))
+    return fail(c, LF_EINVAL, "invalid camera");
   lf::CamArgs &ca = c->h_cams;
   memset(&ca, 0, sizeof ca);
   lf_status st = lfh::camera_args(c, *cam, ca);
@@ -681,8 +680,78 @@ lf_status lf_raygen(lf_ctx *c, const lf_camera *cam, float *o, float *d) {
   if (!c->cams.ensure(sizeof(lf::CamArgs))) return fail(c, LF_ENOMEM, "cameras");
   if (hipMemcpyAsync(c->cams.p, &ca, sizeof ca, hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return check_hip(c, "camera upload");
+  return LF_OK;
+}
+
+lf_status lf_raygen(lf_ctx *c, const lf_camera *cam, float *o, float *d) {
+  if (!c) return LF_EINVAL;
+  if (!o || !d) return fail(c, LF_EINVAL, "invalid raygen arguments");
+  set_device(c);
+  lf_status st = upload_camera(c, cam);
+  if (st) return st;
   lf::launch_raygen(c->cams.as<lf::CamArgs>(), (int64_t)cam->w * cam->h, o, d, c->stream);
   return check_hip(c, "raygen");
+}
+
+// ---- geometry-refinement objectives (Sec. 3.1, 3.2)
+static bool loss_acc(lf_ctx *c) { return c->l1acc.ensure(2 * sizeof(double)); }
+
+lf_status lf_loss_alpha(lf_ctx *c, const float *alpha, int64_t n, float *loss, float *grad) {
+  if (!c) return LF_EINVAL;
+  if (!loss || n < 0 || (n > 0 && !alpha)) return fail(c, LF_EINVAL, "invalid coverage-loss arguments");
+  set_device(c);
+  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss accumulator");
+  Phase ph(c, 13);
+  lf::launch_loss_alpha(alpha, n, loss, grad, c->l1acc.as<double>(), c->stream);
+  return check_hip(c, "coverage loss");
+}
+
+lf_status lf_loss_scale(lf_ctx *c, const float *scale, int64_t n, float s_max, float *loss, float *grad) {
+  if (!c) return LF_EINVAL;
+  if (!loss || n < 0 || (n > 0 && !scale) || !(s_max > 0.f) || !std::isfinite(s_max))
+    return fail(c, LF_EINVAL, "invalid scale-loss arguments");
+  set_device(c);
+  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss accumulator");
+  Phase ph(c, 13);
+  lf::launch_loss_scale(scale, n, s_max, loss, grad, c->l1acc.as<double>(), c->stream);
+  return check_hip(c, "scale loss");
+}
+
+lf_status lf_loss_depth(lf_ctx *c, const float *depth, const float *ref, const float *conf, int64_t n, float eps,
+                        float *loss, float *grad) {
+  if (!c) return LF_EINVAL;
+  if (!loss || n < 0 || (n > 0 && (!depth || !ref)) || !(eps > 0.f) || !std::isfinite(eps))
+    return fail(c, LF_EINVAL, "invalid depth-loss arguments");
+  set_device(c);
+  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss accumulator");
+  Phase ph(c, 13);
+  lf::launch_loss_depth(depth, ref, conf, n, eps, loss, grad, c->l1acc.as<double>(), c->stream);
+  return check_hip(c, "depth loss");
+}
+
+lf_status lf_loss_normal(lf_ctx *c, const float *normal, const float *ref, int64_t n, float *loss, float *grad) {
+  if (!c) return LF_EINVAL;
+  if (!loss || n < 0 || (n > 0 && (!normal || !ref))) return fail(c, LF_EINVAL, "invalid normal-loss arguments");
+  set_device(c);
+  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss accumulator");
+  Phase ph(c, 13);
+  lf::launch_loss_normal(normal, ref, n, loss, grad, c->l1acc.as<double>(), c->stream);
+  return check_hip(c, "normal loss");
+}
+
+lf_status lf_loss_depth_normal(lf_ctx *c, const lf_camera *cam, const float *depth, const float *ref, float *loss,
+                               float *grad) {
+  if (!c) return LF_EINVAL;
+  if (!depth || !ref || !loss) return fail(c, LF_EINVAL, "invalid depth-normal-loss arguments");
+  set_device(c);
+  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss accumulator");
+  lf_status st = upload_camera(c, cam);
+  if (st) return st;
+  if (cam->h > 16 * 65535) return fail(c, LF_EINVAL, "depth map taller than %d rows", 16 * 65535);
+  Phase ph(c, 13);
+  lf::launch_loss_depth_normal(c->cams.as<lf::CamArgs>(), cam->w, cam->h, depth, ref, loss, grad,
+                               c->l1acc.as<double>(), c->stream);
+  return check_hip(c, "depth-normal loss");
 }
 
 lf_status lf_stats_get(lf_ctx *c, lf_render_stats *st) {
