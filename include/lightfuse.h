@@ -194,15 +194,15 @@ lf_status lf_render_backward(lf_ctx *ctx, const lf_transforms *xf, const lf_envm
 
 /* Scene-linear L1 objective of inverse rendering (Sec. 3.4,
  * Eq. training-objectives, data term): loss = mean |pred - target| over n
- * values; grad = sign(pred - target)/n (sign(0) = 0).  loss: device scalar;
- * grad: device [n] or NULL. */
+ * values; grad = sign(pred - target)/n (sign(0) = 0).  loss: device scalar
+ * (binary64 sum in a fixed order); grad: device [n] or NULL. */
 lf_status lf_l1_loss(lf_ctx *ctx, const float *pred, const float *target, int64_t n, float *loss, float *grad);
 
 /* ---- Geometry-refinement objectives (Sec. 3.1 and 3.2).  Common contract:
  * every array is a device array; loss is a device float scalar written
  * asynchronously on the context's stream; grad, when non-NULL, is
- * OVERWRITTEN with d(loss)/d(first map) (same shape); sums run in binary64;
- * sign(0) = 0.  The gradients feed lf_render_backward's d_alpha, d_depth and
+ * OVERWRITTEN with d(loss)/d(first map) (same shape); sums run in binary64
+ * in a fixed order, so the loss does not vary from run to run; sign(0) = 0.  The gradients feed lf_render_backward's d_alpha, d_depth and
  * d_normal.  Errors: LF_EINVAL for NULL maps, n < 0 or an invalid constant. */
 
 /* Coverage term L_alpha = (1/n) sum |A - 1| (Sec. 3.1, Eq. alpha-coverage)

@@ -663,9 +663,9 @@ lf_status lf_l1_loss(lf_ctx *c, const float *pred, const float *target, int64_t 
   if (!c) return LF_EINVAL;
   if (!pred || !target || !loss || n < 0) return fail(c, LF_EINVAL, "invalid loss arguments");
   set_device(c);
-  if (!c->l1acc.ensure(sizeof(double))) return fail(c, LF_ENOMEM, "loss accumulator");
+  if (!c->lossbuf.ensure(lf::kLossPartDoubles * sizeof(double))) return fail(c, LF_ENOMEM, "loss scratch");
   Phase ph(c, 13);
-  lf::launch_l1(pred, target, n, loss, grad, c->l1acc.as<double>(), c->stream);
+  lf::launch_l1(pred, target, n, loss, grad, c->lossbuf.as<double>(), c->stream);
   return check_hip(c, "l1 loss");
 }
 
@@ -694,15 +694,15 @@ lf_status lf_raygen(lf_ctx *c, const lf_camera *cam, float *o, float *d) {
 }
 
 // ---- geometry-refinement objectives (Sec. 3.1, 3.2)
-static bool loss_acc(lf_ctx *c) { return c->l1acc.ensure(2 * sizeof(double)); }
+static bool loss_acc(lf_ctx *c) { return c->lossbuf.ensure(lf::kLossPartDoubles * sizeof(double)); }
 
 lf_status lf_loss_alpha(lf_ctx *c, const float *alpha, int64_t n, float *loss, float *grad) {
   if (!c) return LF_EINVAL;
   if (!loss || n < 0 || (n > 0 && !alpha)) return fail(c, LF_EINVAL, "invalid coverage-loss arguments");
   set_device(c);
-  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss accumulator");
+  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss scratch");
   Phase ph(c, 13);
-  lf::launch_loss_alpha(alpha, n, loss, grad, c->l1acc.as<double>(), c->stream);
+  lf::launch_loss_alpha(alpha, n, loss, grad, c->lossbuf.as<double>(), c->stream);
   return check_hip(c, "coverage loss");
 }
 
@@ -711,9 +711,9 @@ lf_status lf_loss_scale(lf_ctx *c, const float *scale, int64_t n, float s_max, f
   if (!loss || n < 0 || (n > 0 && !scale) || !(s_max > 0.f) || !std::isfinite(s_max))
     return fail(c, LF_EINVAL, "invalid scale-loss arguments");
   set_device(c);
-  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss accumulator");
+  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss scratch");
   Phase ph(c, 13);
-  lf::launch_loss_scale(scale, n, s_max, loss, grad, c->l1acc.as<double>(), c->stream);
+  lf::launch_loss_scale(scale, n, s_max, loss, grad, c->lossbuf.as<double>(), c->stream);
   return check_hip(c, "scale loss");
 }
 
@@ -723,9 +723,9 @@ lf_status lf_loss_depth(lf_ctx *c, const float *depth, const float *ref, const f
   if (!loss || n < 0 || (n > 0 && (!depth || !ref)) || !(eps > 0.f) || !std::isfinite(eps))
     return fail(c, LF_EINVAL, "invalid depth-loss arguments");
   set_device(c);
-  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss accumulator");
+  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss scratch");
   Phase ph(c, 13);
-  lf::launch_loss_depth(depth, ref, conf, n, eps, loss, grad, c->l1acc.as<double>(), c->stream);
+  lf::launch_loss_depth(depth, ref, conf, n, eps, loss, grad, c->lossbuf.as<double>(), c->stream);
   return check_hip(c, "depth loss");
 }
 
@@ -733,9 +733,9 @@ lf_status lf_loss_normal(lf_ctx *c, const float *normal, const float *ref, int64
   if (!c) return LF_EINVAL;
   if (!loss || n < 0 || (n > 0 && (!normal || !ref))) return fail(c, LF_EINVAL, "invalid normal-loss arguments");
   set_device(c);
-  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss accumulator");
+  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss scratch");
   Phase ph(c, 13);
-  lf::launch_loss_normal(normal, ref, n, loss, grad, c->l1acc.as<double>(), c->stream);
+  lf::launch_loss_normal(normal, ref, n, loss, grad, c->lossbuf.as<double>(), c->stream);
   return check_hip(c, "normal loss");
 }
 
@@ -744,13 +744,13 @@ lf_status lf_loss_depth_normal(lf_ctx *c, const lf_camera *cam, const float *dep
   if (!c) return LF_EINVAL;
   if (!depth || !ref || !loss) return fail(c, LF_EINVAL, "invalid depth-normal-loss arguments");
   set_device(c);
-  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss accumulator");
+  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss scratch");
   lf_status st = upload_camera(c, cam);
   if (st) return st;
   if (cam->h > 16 * 65535) return fail(c, LF_EINVAL, "depth map taller than %d rows", 16 * 65535);
   Phase ph(c, 13);
   lf::launch_loss_depth_normal(c->cams.as<lf::CamArgs>(), cam->w, cam->h, depth, ref, loss, grad,
-                               c->l1acc.as<double>(), c->stream);
+                               c->lossbuf.as<double>(), c->stream);
   return check_hip(c, "depth-normal loss");
 }
 

@@ -66,7 +66,7 @@ struct lf_ctx {
   int32_t wide_levels = 0; // levels of the deepest traversal hierarchy
   // per call
   lfh::DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;
-  lfh::DevBuf queue, qcount, work, kbuf1, kbuf2, contrib, frozen, l1acc, cams, rec1, rec2, seeds;
+  lfh::DevBuf queue, qcount, work, kbuf1, kbuf2, contrib, frozen, lossbuf, cams, rec1, rec2, seeds;
   lfh::DevBuf bounds, skeys, skeys2, svals, svals2, shist;
   lf::CamArgs h_cams{};
   // ray counters since the last lf_stats_get

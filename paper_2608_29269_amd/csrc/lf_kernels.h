@@ -123,18 +123,20 @@ void launch_shade2(const RenderArgs &a, bool replay, hipStream_t st);
 void launch_resolve(const RenderArgs &a, hipStream_t st);
 void launch_accum(unsigned long long *acc, const uint32_t *count, hipStream_t st);
 void launch_raygen(const CamArgs *cams, int64_t n, float *o, float *d, hipStream_t st);
-void launch_l1(const float *pred, const float *target, int64_t n, float *loss, float *grad, double *acc,
+// training objectives (lf_loss.hip); part: device scratch of kLossPartDoubles doubles
+constexpr int kMaxLossBlocks = 2048;                       // blocks (partial-sum slots) per objective pass
+constexpr int kLossPartDoubles = 2 * kMaxLossBlocks + 2;  // two slot rows, then the totals
+void launch_l1(const float *pred, const float *target, int64_t n, float *loss, float *grad, double *part,
                hipStream_t st);
-// geometry-refinement objectives (lf_loss.hip); acc: device double[2] scratch
-void launch_loss_alpha(const float *alpha, int64_t n, float *loss, float *grad, double *acc, hipStream_t st);
-void launch_loss_scale(const float *scale, int64_t n, float s_max, float *loss, float *grad, double *acc,
+void launch_loss_alpha(const float *alpha, int64_t n, float *loss, float *grad, double *part, hipStream_t st);
+void launch_loss_scale(const float *scale, int64_t n, float s_max, float *loss, float *grad, double *part,
                        hipStream_t st);
 void launch_loss_depth(const float *depth, const float *ref, const float *conf, int64_t n, float eps, float *loss,
-                       float *grad, double *acc, hipStream_t st);
-void launch_loss_normal(const float *normal, const float *ref, int64_t n, float *loss, float *grad, double *acc,
+                       float *grad, double *part, hipStream_t st);
+void launch_loss_normal(const float *normal, const float *ref, int64_t n, float *loss, float *grad, double *part,
                         hipStream_t st);
 void launch_loss_depth_normal(const CamArgs *cams, int w, int h, const float *depth, const float *ref, float *loss,
-                              float *grad, double *acc, hipStream_t st);
+                              float *grad, double *part, hipStream_t st);
 
 // ---- backward (lf_backward.hip)
 struct GradArgs {

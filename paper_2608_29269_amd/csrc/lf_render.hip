@@ -540,29 +540,8 @@ __global__ void k_raygen(const CamArgs *cams, int64_t n, float *o, float *d) {
   raygen_f32(*cams, 0, i, o + 3 * i, d + 3 * i);
 }
 
-__global__ __launch_bounds__(256) void k_l1(const float *pred, const float *target, int64_t n, float *grad,
-                                            double *acc) {
-  __shared__ double part[256];
-  double s = 0.0;
-  double inv = 1.0 / (double)n;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    float d = pred[i] - target[i];
-    s += fabs((double)d);
-    if (grad) grad[i] = (float)((d > 0.f ? 1.0 : (d < 0.f ? -1.0 : 0.0)) * inv);
-  }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicAdd(acc, part[0]);
-}
-
 __global__ void k_accum(unsigned long long *acc, const uint32_t *count) { *acc += *count; }
 
-__global__ void k_l1_final(const double *acc, int64_t n, float *loss) { *loss = (float)(*acc / (double)n); }
-__global__ void k_zero_f64(double *p) { *p = 0.0; }
 
 template <int K, bool B>
 void trace1_k(const RenderArgs &a, hipStream_t st) {
@@ -667,17 +646,6 @@ void launch_raygen(const CamArgs *cams, int64_t n, float *o, float *d, hipStream
 
 void launch_accum(unsigned long long *acc, const uint32_t *count, hipStream_t st) {
   hipLaunchKernelGGL(k_accum, dim3(1), dim3(1), 0, st, acc, count);
-}
-
-void launch_l1(const float *pred, const float *target, int64_t n, float *loss, float *grad, double *acc,
-               hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(1), 0, st, acc);
-  if (n > 0) {
-    unsigned nb = blocks(n, 256);
-    if (nb > 2048) nb = 2048;
-    hipLaunchKernelGGL(k_l1, dim3(nb), dim3(256), 0, st, pred, target, n, grad, acc);
-  }
-  hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(1), 0, st, acc, n > 0 ? n : 1, loss);
 }
 
 }  // namespace lf
