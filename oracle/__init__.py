@@ -21,6 +21,7 @@ NO_SECONDARY = 1 << 0
 NO_BACKGROUND = 1 << 1
 BSDF_ONLY = 1 << 2
 DIFFUSE_ONLY = 1 << 3
+NEE = 1 << 7  # two rays per path sample (next-event + continuation); outputs per slot 2s, 2s+1
 
 M_TGAP_PRI, M_RHO_PRI, M_TGAP_SEC, M_RHO_SEC, M_ENV, M_LOBE, M_COS, M_TMIN = range(8)
 NMARGIN = 8
@@ -135,6 +136,11 @@ class Params:
     secondary_offset: float = 1e-3
     flags: int = 0
 
+    @property
+    def slots(self) -> int:
+        """Secondary-ray slots per primary ray (2 per sample in the two-ray form)."""
+        return self.spp * (2 if self.flags & NEE else 1)
+
     def c(self) -> _Params:
         return _Params(self.k, self.spp, self.seed, self.alpha_min, self.alpha_cap, self.support_sigma,
                        self.eps, self.t_min, self.secondary_offset, self.flags)
@@ -176,10 +182,10 @@ def _rays(o, d, ids):
 def _alloc_out(n, p: Params, lists: bool):
     out = dict(radiance=np.zeros((n, 3)), depth=np.zeros(n), normal=np.zeros((n, 3)), alpha=np.zeros(n),
                transmittance=np.zeros(n), margins=np.zeros((n, NMARGIN)), counts=np.zeros((n, NCOUNT)),
-               sec_alpha=np.zeros((n, p.spp)))
+               sec_alpha=np.zeros((n, p.slots)))
     if lists:
         out["hit_idx"] = np.zeros((n, p.k), dtype=np.int32)
-        out["sec_hit_idx"] = np.zeros((n, p.spp, p.k), dtype=np.int32)
+        out["sec_hit_idx"] = np.zeros((n, p.slots, p.k), dtype=np.int32)
     s = _Outputs(_ptr(out["radiance"]), _ptr(out["depth"]), _ptr(out["normal"]), _ptr(out["alpha"]),
                  _ptr(out["transmittance"]), _ptr(out.get("hit_idx"), _i32p), _ptr(out.get("sec_hit_idx"), _i32p),
                  _ptr(out["sec_alpha"]), _ptr(out["margins"]), _ptr(out["counts"]))

@@ -597,6 +597,7 @@ typedef struct {
   int live;
   double w[3];      /* sampled direction */
   double K;         /* MIS weight over (technique probability x pdf) */
+  double tw;        /* weight of the T2 E(w) term (its MIS weight in the two-ray form, else 1) */
   double T2;        /* transmittance of the secondary trace */
   double ce[3], cb[3]; /* A2 x (frozen non-env factors) of the two secondary env samples */
   double we[3], wb[3];
@@ -605,16 +606,74 @@ typedef struct {
 
 typedef struct {
   hitlist hl;
-  samp *s; /* [S] */
+  samp *s; /* [J] one per slot */
   double margins[ORS_NMARGIN];
   double counts[ORS_NCOUNT];
-  hitlist *shl; /* [S] secondary hit lists (for inspection) */
-  double *sA2;  /* [S] */
+  hitlist *shl; /* [J] secondary hit lists (for inspection) */
+  double *sA2;  /* [J] */
 } frozen;
+
+/* secondary-ray slots per primary ray: S, or 2S for the two-ray form */
+static int n_slots(const ors_params *p) { return p->spp * ((p->flags & ORS_NEE) ? 2 : 1); }
+
+/* Primary direction of slot j and its frozen weights (Eq. path-estimator,
+ * power heuristic).  One-ray form (slot = sample s): technique by u0 with
+ * probabilities (c_env, c_bsdf), K = c_t p_t / ((c_env p_e)^2 + (c_bsdf p_b)^2),
+ * tw = 1.  Two-ray form (Sec. 4.2: one environment next-event sample and one
+ * BSDF continuation per path sample s = j/2, both always drawn): slot 2s
+ * samples the environment (dims 9, 10), K = p_e / (p_e^2 + p_b^2), tw = 1;
+ * slot 2s+1 samples the cosine/GGX mixture (dims 1-3), K = 1/p_b and the
+ * escaping term T2 E(w) carries tw = p_b^2 / (p_e^2 + p_b^2), while the
+ * indirect term at its secondary hit is not MIS-weighted.  Returns 0 for a
+ * dead slot. */
+static int sample_slot(const world *w, const record *rc, const double *wo, int64_t ray_id, int j, frozen *fz,
+                       samp *sp) {
+  const ors_params *p = w->p;
+  const int nee = (p->flags & ORS_NEE) != 0;
+  const int s = nee ? j / 2 : j;
+  const int kind = nee ? 1 + (j & 1) : 0; /* 0 one-ray, 1 next-event, 2 continuation */
+  double qs = q_spec(rc->a, rc->m, p->flags);
+  double pe = 0.0, pb = 0.0;
+  int use_env;
+  if (kind == 0) {
+    use_env = ors_uniform(p->seed, ray_id, s, 0) < w->c_env;
+  } else {
+    use_env = kind == 1;
+    if (use_env && !(w->c_env > 0.0)) return 0;
+  }
+  if (use_env) {
+    const uint32_t da = kind == 1 ? 9 : 2;
+    pe = env_sample_m(w, ors_uniform(p->seed, ray_id, s, da), ors_uniform(p->seed, ray_id, s, da + 1), sp->w,
+                      &fz->margins[ORS_M_ENV]);
+  } else {
+    double u1 = ors_uniform(p->seed, ray_id, s, 1);
+    if (qs > 0.0 && qs < 1.0) fz->margins[ORS_M_LOBE] = dmin(fz->margins[ORS_M_LOBE], fabs(u1 - qs));
+    sample_lobe(rc->n, wo, rc->r, u1 < qs, ors_uniform(p->seed, ray_id, s, 2), ors_uniform(p->seed, ray_id, s, 3),
+                sp->w);
+  }
+  double cosw = dot3(rc->n, sp->w);
+  fz->margins[ORS_M_COS] = dmin(fz->margins[ORS_M_COS], fabs(cosw));
+  if (!(cosw > 0.0)) return 0;
+  pb = ors_pdf_bsdf(rc->n, sp->w, wo, rc->a, rc->m, rc->r, p->flags);
+  if (!use_env) pe = w->c_env > 0.0 ? env_pdf_m(w, sp->w, &fz->margins[ORS_M_ENV]) : 0.0;
+  double pt = use_env ? pe : pb;
+  if (!(pt > 0.0)) return 0;
+  sp->tw = 1.0;
+  if (kind == 0) {
+    double ct = use_env ? w->c_env : w->c_bsdf;
+    double den = (w->c_env * pe) * (w->c_env * pe) + (w->c_bsdf * pb) * (w->c_bsdf * pb);
+    sp->K = ct * pt / den;
+  } else if (kind == 1) {
+    sp->K = pe / (pe * pe + pb * pb);
+  } else {
+    sp->K = 1.0 / pb;
+    sp->tw = pb * pb / (pe * pe + pb * pb);
+  }
+  return 1;
+}
 
 static void decide(const world *w, const double *o, const double *d, int64_t ray_id, cbuf *buf, frozen *fz) {
   const ors_params *p = w->p;
-  int S = p->spp;
   for (int m = 0; m < ORS_NMARGIN; ++m) fz->margins[m] = INFINITY;
   for (int c = 0; c < ORS_NCOUNT; ++c) fz->counts[c] = 0.0;
   trace_stats st = {INFINITY, INFINITY, INFINITY, 0.0};
@@ -630,42 +689,25 @@ static void decide(const world *w, const double *o, const double *d, int64_t ray
   composite(w, &fz->hl, o, d, hv, &rc);
   double wo[3] = {-d[0], -d[1], -d[2]};
   trace_stats st2 = {INFINITY, INFINITY, INFINITY, 0.0};
-  for (int s = 0; s < S; ++s) {
-    samp *sp = &fz->s[s];
+  const int J = n_slots(p);
+  for (int j = 0; j < J; ++j) {
+    samp *sp = &fz->s[j];
     memset(sp, 0, sizeof *sp);
     sp->T2 = 1.0;
-    fz->shl[s].nh = 0;
-    fz->sA2[s] = -1.0;
+    sp->tw = 1.0;
+    fz->shl[j].nh = 0;
+    fz->sA2[j] = -1.0;
     if (fz->hl.nh == 0) continue;
-    double u0 = ors_uniform(p->seed, ray_id, s, 0);
-    double u1 = ors_uniform(p->seed, ray_id, s, 1);
-    double u2 = ors_uniform(p->seed, ray_id, s, 2);
-    double u3 = ors_uniform(p->seed, ray_id, s, 3);
-    int use_env = u0 < w->c_env;
-    double pe = 0.0, pb = 0.0;
-    double qs = q_spec(rc.a, rc.m, p->flags);
-    if (use_env) {
-      pe = env_sample_m(w, u2, u3, sp->w, &fz->margins[ORS_M_ENV]);
-    } else {
-      if (qs > 0.0 && qs < 1.0) fz->margins[ORS_M_LOBE] = dmin(fz->margins[ORS_M_LOBE], fabs(u1 - qs));
-      sample_lobe(rc.n, wo, rc.r, u1 < qs, u2, u3, sp->w);
-    }
-    double cosw = dot3(rc.n, sp->w);
-    fz->margins[ORS_M_COS] = dmin(fz->margins[ORS_M_COS], fabs(cosw));
-    if (!(cosw > 0.0)) continue;
-    pb = ors_pdf_bsdf(rc.n, sp->w, wo, rc.a, rc.m, rc.r, p->flags);
-    if (!use_env) pe = w->c_env > 0.0 ? env_pdf_m(w, sp->w, &fz->margins[ORS_M_ENV]) : 0.0;
-    double ct = use_env ? w->c_env : w->c_bsdf, pt = use_env ? pe : pb;
-    if (!(pt > 0.0)) continue;
-    double den = (w->c_env * pe) * (w->c_env * pe) + (w->c_bsdf * pb) * (w->c_bsdf * pb);
-    sp->K = ct * pt / den; /* power heuristic (beta = 2) over (c_t p_t) */
+    if (!sample_slot(w, &rc, wo, ray_id, j, fz, sp)) continue;
     sp->live = 1;
     fz->counts[ORS_C_ENV] += 1.0;
+    const int s = (p->flags & ORS_NEE) ? j / 2 : j;               /* path sample (uniform stream) */
+    const int indirect = !(p->flags & ORS_NEE) || (j & 1);        /* next-event rays see only E */
     if (p->flags & ORS_NO_SECONDARY) continue;
     /* one secondary ray: visibility and indirect path at once */
     double o2[3];
     for (int c = 0; c < 3; ++c) o2[c] = rc.x[c] + p->secondary_offset * rc.n[c];
-    hitlist *hl2 = &fz->shl[s];
+    hitlist *hl2 = &fz->shl[j];
     trace_decide(w, o2, sp->w, p->k, buf, hl2, &st2);
     fz->counts[ORS_C_SEC_RAYS] += 1.0;
     fz->counts[ORS_C_COMP_SEC] += hl2->nh;
@@ -673,8 +715,8 @@ static void decide(const world *w, const double *o, const double *d, int64_t ray
     record r2;
     composite(w, hl2, o2, sp->w, hv2, &r2);
     sp->T2 = r2.T;
-    fz->sA2[s] = r2.A;
-    if (hl2->nh == 0) continue;
+    fz->sA2[j] = r2.A;
+    if (hl2->nh == 0 || !indirect) continue;
     /* two unshadowed environment samples at the secondary record, combined by
      * the two-sample power heuristic */
     double wo2[3] = {-sp->w[0], -sp->w[1], -sp->w[2]};
@@ -798,7 +840,8 @@ static void evaluate(const world *w, const frozen *fz, const double *o, const do
   composite(w, &fz->hl, o, d, hv, rc);
   double wo[3] = {-d[0], -d[1], -d[2]};
   double Lsurf[3] = {0, 0, 0};
-  for (int s = 0; s < p->spp; ++s) {
+  const int J = n_slots(p);
+  for (int s = 0; s < J; ++s) {
     const samp *sp = &fz->s[s];
     Ls[s][0] = Ls[s][1] = Ls[s][2] = 0.0;
     if (!sp->live) continue;
@@ -808,7 +851,7 @@ static void evaluate(const world *w, const frozen *fz, const double *o, const do
     if (sp->has_b) env_eval(sc->env, sc->env_h, sc->env_w, sp->wb, Eb);
     fcos_eval(rc->n, sp->w, wo, rc->a, rc->m, rc->r, p->flags, fcs[s]);
     for (int c = 0; c < 3; ++c) {
-      Lins[s][c] = sp->T2 * E[c] + sp->ce[c] * Ee[c] + sp->cb[c] * Eb[c];
+      Lins[s][c] = sp->tw * sp->T2 * E[c] + sp->ce[c] * Ee[c] + sp->cb[c] * Eb[c];
       Ls[s][c] = sp->K * fcs[s][c] * Lins[s][c];
       Lsurf[c] += Ls[s][c];
     }
@@ -848,12 +891,12 @@ static void evaluate_bwd(const world *w, const frozen *fz, const double *o, cons
                          double gdepth, const double *gnormal, double galpha, ors_grads *g) {
   const ors_params *p = w->p;
   const ors_scene *sc = w->sc;
-  int S = p->spp;
+  int S = p->spp, J = n_slots(p);
   hitv hv[KMAX];
   record rc;
-  double (*Ls)[3] = (double (*)[3])malloc(sizeof(double) * 3 * S);
-  double (*fcs)[3] = (double (*)[3])malloc(sizeof(double) * 3 * S);
-  double (*Lins)[3] = (double (*)[3])malloc(sizeof(double) * 3 * S);
+  double (*Ls)[3] = (double (*)[3])malloc(sizeof(double) * 3 * J);
+  double (*fcs)[3] = (double (*)[3])malloc(sizeof(double) * 3 * J);
+  double (*Lins)[3] = (double (*)[3])malloc(sizeof(double) * 3 * J);
   pixel px;
   evaluate(w, fz, o, d, hv, &rc, Ls, fcs, Lins, &px);
   double wo[3] = {-d[0], -d[1], -d[2]};
@@ -867,7 +910,7 @@ static void evaluate_bwd(const world *w, const frozen *fz, const double *o, cons
     env_scatter(g->env, H, W, d, ge);
   }
   double gn[3] = {gnormal[0], gnormal[1], gnormal[2]}, ga[3] = {0, 0, 0}, gm = 0.0, gr = 0.0;
-  for (int s = 0; s < S; ++s) {
+  for (int s = 0; s < J; ++s) {
     const samp *sp = &fz->s[s];
     if (!sp->live) continue;
     double gF[3], gfc[3], gLin[3];
@@ -878,7 +921,7 @@ static void evaluate_bwd(const world *w, const frozen *fz, const double *o, cons
       gLin[c] = gF[c] * sp->K * fcs[s][c];
     }
     double ge[3];
-    for (int c = 0; c < 3; ++c) ge[c] = gLin[c] * sp->T2;
+    for (int c = 0; c < 3; ++c) ge[c] = gLin[c] * sp->tw * sp->T2;
     env_scatter(g->env, H, W, sp->w, ge);
     if (sp->has_e) { for (int c = 0; c < 3; ++c) ge[c] = gLin[c] * sp->ce[c]; env_scatter(g->env, H, W, sp->we, ge); }
     if (sp->has_b) { for (int c = 0; c < 3; ++c) ge[c] = gLin[c] * sp->cb[c]; env_scatter(g->env, H, W, sp->wb, ge); }
@@ -984,7 +1027,7 @@ static void frozen_alloc(frozen *f, int S) {
 static void frozen_free(frozen *f) { free(f->s); free(f->shl); free(f->sA2); }
 
 static void write_out(const ors_params *p, const frozen *fz, const pixel *px, int64_t r, ors_outputs *out) {
-  int k = p->k, S = p->spp;
+  int k = p->k, S = n_slots(p);
   if (out->radiance) for (int c = 0; c < 3; ++c) out->radiance[3 * r + c] = px->L[c];
   if (out->depth) out->depth[r] = px->depth;
   if (out->normal) for (int c = 0; c < 3; ++c) out->normal[3 * r + c] = px->normal[c];
@@ -1019,12 +1062,12 @@ static int render_impl(const ors_scene *sc0, const ors_scene *sc, const ors_rays
   {
     cbuf buf = {0, 0, 0};
     frozen fz;
-    frozen_alloc(&fz, p->spp);
+    frozen_alloc(&fz, n_slots(p));
     hitv hv[KMAX];
     record rc;
-    double (*Ls)[3] = (double (*)[3])malloc(sizeof(double) * 3 * p->spp);
-    double (*fcs)[3] = (double (*)[3])malloc(sizeof(double) * 3 * p->spp);
-    double (*Lins)[3] = (double (*)[3])malloc(sizeof(double) * 3 * p->spp);
+    double (*Ls)[3] = (double (*)[3])malloc(sizeof(double) * 3 * n_slots(p));
+    double (*fcs)[3] = (double (*)[3])malloc(sizeof(double) * 3 * n_slots(p));
+    double (*Lins)[3] = (double (*)[3])malloc(sizeof(double) * 3 * n_slots(p));
 #pragma omp for schedule(dynamic, 4)
     for (int64_t r = 0; r < rays->n; ++r) {
       const double *o = rays->o + 3 * r, *d = rays->d + 3 * r;
@@ -1076,7 +1119,7 @@ int ors_backward(const ors_scene *sc, const ors_rays *rays, const ors_params *p,
   {
     cbuf buf = {0, 0, 0};
     frozen fz;
-    frozen_alloc(&fz, p->spp);
+    frozen_alloc(&fz, n_slots(p));
 #pragma omp for schedule(dynamic, 4)
     for (int64_t r = 0; r < rays->n; ++r) {
       const double *o = rays->o + 3 * r, *d = rays->d + 3 * r;

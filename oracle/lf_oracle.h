@@ -50,6 +50,9 @@ extern "C" {
 #define ORS_NO_BACKGROUND (1u << 1) /* drop the T*E(d) background term */
 #define ORS_BSDF_ONLY     (1u << 2) /* never use environment importance sampling */
 #define ORS_DIFFUSE_ONLY  (1u << 3) /* Lambert lobe only (no GGX term, cosine sampling) */
+#define ORS_NEE           (1u << 7) /* two rays per path sample: an environment next-event ray and a
+                                       cosine/GGX continuation, multi-sample power MIS; outputs indexed
+                                       by slot 2s (next-event) and 2s+1 (continuation) */
 
 typedef struct {
   const double *mu;        /* [n,3] centres (object space for object surfels) */
