@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fwd-steps", type=int, default=5)
     ap.add_argument("--geo-steps", type=int, default=10, help="timed geometry-refinement steps (0 = skip)")
+    ap.add_argument("--nee-spp", type=str, default="8,16,32",
+                    help="comma-separated spp of the two-ray estimator's training steps (empty = skip)")
     ap.add_argument("--serve-requests", type=int, default=40, help="requests per serving run (0 = skip)")
     ap.add_argument("--serve-loads", type=str, default="0.8",
                     help="comma-separated arrival rates as fractions of the plain tracer's capacity")
@@ -204,6 +206,12 @@ def main():
                "sample": f"{len(pix)} random pixels of the 1024x1024 camera (plus their live secondary rays), "
                          f"fwd+bwd, 1M surfels brute force in FP64, {cdt:.1f} s"}
 
+    estimator = None
+    nee_spp = [int(x) for x in args.nee_spp.split(",") if x]
+    if nee_spp:
+        log(f"two-ray estimator at spp {nee_spp}")
+        estimator = estimator_bench(lf, tr, env, R, t, cam, wl, params, grads, out, target, nee_spp)
+
     geometry = None
     if args.geo_steps > 0:
         log("geometry-refinement step")
@@ -242,9 +250,50 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "geometry": geometry,
+        "two_ray_estimator": estimator,
         "serving": serving,
     }
     print(json.dumps(res))
+
+
+def estimator_bench(lf, tr, env, R, t, cam, wl, params, grads, out, target, spps, lr=1e-5):
+    """The paper's two-ray estimator (Sec. 4.2: per path sample one
+    environment next-event ray and one cosine/GGX continuation) on the same
+    scene and camera, at the spp of its training schedule (8, 16, 32): one
+    warm-up and one timed training step each (refit, forward, L1, replayed
+    backward, SGD)."""
+    import torch
+    res = {}
+    for spp in spps:
+        cfg = dict(cameras=[cam], k=wl.k, spp=spp, seed=wl.seed, flags=lf.FLAG_NEE)
+
+        def step():
+            tr.refit()
+            tr.render(env, R, t, out=out, **cfg)
+            loss, g = tr.l1_loss(out["radiance"], target)
+            tr.render_backward(env, R, t, d_radiance=g, grads=grads, **cfg)
+            with torch.no_grad():
+                for k_, v in params.items():
+                    v.sub_(lr * grads[k_])
+                params["scale"].clamp_(min=1e-4)
+                params["opacity"].clamp_(1e-4, 1.0)
+                for k_ in ("albedo", "roughness", "metallic"):
+                    params[k_].clamp_(0.0, 1.0)
+            return loss
+
+        step()
+        tr.sync()
+        tr.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = tr.stats()
+        res[str(spp)] = {"ms_per_step": dt * 1e3, "rays_per_s": (st["rays_primary"] + st["rays_secondary"]) / dt,
+                         "secondary_rays_per_step": st["rays_secondary"]}
+        log(f"two-ray spp {spp}: {dt * 1e3:.0f} ms/step, {res[str(spp)]['rays_per_s']:.4g} rays/s")
+    return res
 
 
 # algorithmic HBM bytes per element of each geometry objective: maps read once, gradient written once

@@ -127,6 +127,15 @@ typedef struct {
 #define LF_FLAG_COUNT         (1u << 5) /* accumulate traversal counters (lf_trace_counters) */
 #define LF_FLAG_UNSORTED      (1u << 6) /* trace secondary rays in queue order instead of regrouping them
                                            by direction octant and origin (same results, less coherent) */
+/* The paper's two-ray estimator (Sec. 3.3, Eq. path-estimator; Sec. 4.2): per
+ * path sample s one environment next-event ray (slot 2s, weight p_e/(p_e^2+p_b^2),
+ * its secondary trace used only as transmittance) and one cosine/GGX
+ * continuation (slot 2s+1, weight 1/p_b; the escaping term T2 E(w) carries the
+ * power-heuristic weight p_b^2/(p_e^2+p_b^2), the two environment samples at
+ * its secondary hit do not).  Without it, one ray per sample from one-sample
+ * MIS serves both roles.  Secondary outputs are indexed by slot (2S per ray).
+ * Not accepted by the relight server. */
+#define LF_FLAG_NEE           (1u << 7)
 
 /* Tracing and estimator parameters.  Readings of points the paper leaves
  * open (Sec. 3.2 "finite support", "opacity threshold", epsilon of
@@ -152,7 +161,8 @@ typedef struct {
   float *normal;        /* device [R,3] composited unit normal facing the ray (0 on a miss) */
   float *alpha;         /* device [R]   accumulated opacity A */
   int32_t *hit_idx;     /* device [R,k] primary hit surfel indices in order, -1 padded; or NULL */
-  int32_t *sec_hit_idx; /* device [R,S,k] secondary hit lists (-1 padded, all -1 if not traced); or NULL */
+  int32_t *sec_hit_idx; /* device [R,J,k] secondary hit lists per slot (J = S, or 2S with LF_FLAG_NEE;
+                           -1 padded, all -1 if not traced); or NULL */
 } lf_outputs;
 
 /* Forward render of one state (Sec. 3.2 tracing and compositing; Sec. 3.3

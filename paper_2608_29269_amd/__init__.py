@@ -19,11 +19,11 @@ import ctypes as C
 from typing import Optional, Sequence
 
 from . import _lib
-from ._lib import (FLAG_BRUTE_FORCE, FLAG_COUNT, FLAG_BSDF_ONLY, FLAG_DIFFUSE_ONLY, FLAG_NO_BACKGROUND, FLAG_NO_SECONDARY,
-                   LFError)
+from ._lib import (FLAG_BRUTE_FORCE, FLAG_COUNT, FLAG_BSDF_ONLY, FLAG_DIFFUSE_ONLY, FLAG_NEE, FLAG_NO_BACKGROUND,
+                   FLAG_NO_SECONDARY, LFError)
 
 __all__ = ["Tracer", "RenderFn", "Server", "LFError", "FLAG_NO_SECONDARY", "FLAG_NO_BACKGROUND", "FLAG_BSDF_ONLY",
-           "FLAG_DIFFUSE_ONLY", "FLAG_BRUTE_FORCE", "camera_struct"]
+           "FLAG_DIFFUSE_ONLY", "FLAG_BRUTE_FORCE", "FLAG_NEE", "camera_struct"]
 
 
 def _ptr(t):
@@ -178,7 +178,8 @@ class Tracer:
             if hit_idx:
                 out["hit_idx"] = torch.empty((nr, k), dtype=torch.int32, device=dev)
             if sec_hit_idx:
-                out["sec_hit_idx"] = torch.empty((nr, spp, k), dtype=torch.int32, device=dev)
+                slots = spp * (2 if int(flags) & FLAG_NEE else 1)
+                out["sec_hit_idx"] = torch.empty((nr, slots, k), dtype=torch.int32, device=dev)
         o = _lib.Outputs(_ptr(out["radiance"]), _ptr(out["depth"]), _ptr(out["normal"]), _ptr(out["alpha"]),
                          _ptr(out.get("hit_idx")), _ptr(out.get("sec_hit_idx")))
         self._chk(self.L.lf_render(self.ctx, C.byref(xf), C.byref(em), rp, cams, nc, C.byref(p), C.byref(o)))

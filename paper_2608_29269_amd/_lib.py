@@ -22,6 +22,7 @@ FLAG_DIFFUSE_ONLY = 1 << 3
 FLAG_BRUTE_FORCE = 1 << 4
 FLAG_COUNT = 1 << 5
 FLAG_UNSORTED = 1 << 6
+FLAG_NEE = 1 << 7  # the two-ray estimator: next-event + continuation per sample
 MAX_CAMERAS = 16
 SCHED_SHORTEST_FIRST, SCHED_OLDEST_FIRST, SCHED_ROUND_ROBIN = 0, 1, 2
 

@@ -99,7 +99,7 @@ lf_status validate_params(lf_ctx *c, const lf_params *p) {
   if (!(p->alpha_min > 0.0) || !(p->alpha_cap > 0.0 && p->alpha_cap < 1.0) || !(p->support_sigma > 0.0) ||
       !(p->eps >= 0.0) || !(p->t_min >= 0.0) || !std::isfinite(p->secondary_offset))
     return fail(c, LF_EINVAL, "invalid tracing constants");
-  if (p->flags & ~0x7Fu) return fail(c, LF_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~0xFFu) return fail(c, LF_EINVAL, "unknown flags 0x%x", p->flags);
   return LF_OK;
 }
 
@@ -199,7 +199,8 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
       return check_hip(c, "camera upload");
     a.rays.cams = c->cams.as<lf::CamArgs>();
   }
-  if (R * (int64_t)p->spp >= (int64_t)INT32_MAX) return fail(c, LF_EUNSUPPORTED, "too many rays x samples");
+  const int64_t J = (int64_t)p->spp * ((p->flags & LF_FLAG_NEE) ? 2 : 1);  // secondary slots per ray
+  if (R * J >= (int64_t)INT32_MAX) return fail(c, LF_EUNSUPPORTED, "too many rays x samples");
   a.R = R;
   double sig2 = p->support_sigma * p->support_sigma;
   if (p->alpha_min != c->built_alpha_min || sig2 != c->built_sig2) {
@@ -223,7 +224,7 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
   lfh::scene_view(c, a.S);
   a.S.inst = c->inst.as<lf::InstRec>();
   lfh::trace_params(c, p, a.P);
-  a.spp_stride = p->spp;
+  a.spp_stride = (int32_t)J;
   a.E.tex = env->texels;
   a.E.H = H;
   a.E.W = W;
@@ -235,7 +236,7 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
   a.E.scal = c->env_scal.as<double>();
   a.status = c->status.as<uint32_t>();
   const bool trace2 = !(p->flags & LF_FLAG_NO_SECONDARY);
-  const int64_t RS = R * p->spp;
+  const int64_t RS = R * J;
   // k-buffers handed from the traversal to the compositing launches: one per
   // primary work item (tile positions or rays; the backward's compositing
   // adjoint reads those of its replayed primary pass) and per secondary
@@ -558,10 +559,10 @@ lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, co
   a.sec_hit_idx = out->sec_hit_idx;
   const bool trace2 = !(p->flags & LF_FLAG_NO_SECONDARY);
   if (trace2) {
-    if (!c->contrib.ensure(sizeof(float) * 3 * a.R * p->spp)) return fail(c, LF_ENOMEM, "contributions");
+    if (!c->contrib.ensure(sizeof(float) * 3 * a.R * a.spp_stride)) return fail(c, LF_ENOMEM, "contributions");
     a.contrib = c->contrib.as<float>();
   } else if (out->sec_hit_idx) {
-    lf::launch_fill_u32((uint32_t *)out->sec_hit_idx, 0xffffffffu, a.R * p->spp * p->k, c->stream);
+    lf::launch_fill_u32((uint32_t *)out->sec_hit_idx, 0xffffffffu, a.R * a.spp_stride * p->k, c->stream);
   }
   {
     Phase ph(c, 2);
@@ -630,7 +631,7 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
   const bool trace2 = !(p->flags & LF_FLAG_NO_SECONDARY);
   if (!c->seeds.ensure(sizeof(lf::AdjSeed) * a.R)) return fail(c, LF_ENOMEM, "adjoint seeds");
   a.seeds = c->seeds.as<lf::AdjSeed>();
-  if (trace2 && !c->frozen.ensure(sizeof(lf::SecFrozen) * a.R * p->spp))
+  if (trace2 && !c->frozen.ensure(sizeof(lf::SecFrozen) * a.R * a.spp_stride))
     return fail(c, LF_ENOMEM, "frozen records");
   a.frozen = trace2 ? c->frozen.as<lf::SecFrozen>() : nullptr;
   {

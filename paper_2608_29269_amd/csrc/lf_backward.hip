@@ -100,14 +100,15 @@ __device__ __forceinline__ void fcos_bwd(d3 n, d3 wi, d3 wo, d3 a, double m, dou
 }
 
 // ---------------------------------------------------------------- shading adjoint
-// Per primary ray: reverse of L = A * mean_s F_s + T * E(d) with
-// F_s = K_s f(w_s) (n.w_s) (T2 E(w_s) + ce E(w_e) + cb E(w_b)); environment
+// Per primary ray: reverse of L = A * (1/S) sum_j F_j + T * E(d) over the
+// slots j with F_j = K_j f(w_j) (n.w_j) (tw_j T2 E(w_j) + ce E(w_e) + cb E(w_b))
+// (the replay stores tw_j T2 as its frozen transmittance); environment
 // gradients are scattered here, and the adjoints of the surface record are
 // reduced to the seeds of the compositing adjoint.
 __device__ __forceinline__ void adj_shade_ray(const RenderArgs &a, const GradArgs &G, int64_t ray,
                                               BlockEnvTable &acc) {
   const TraceParams &P = a.P;
-  const int S = P.spp;
+  const int S = P.spp, J = n_slots(P);
   float of[3], df[3];
   load_ray(a.rays, ray, of, df);
   const d3 d = mk(df[0], df[1], df[2]);
@@ -132,15 +133,15 @@ __device__ __forceinline__ void adj_shade_ray(const RenderArgs &a, const GradArg
   const d3 wo = -d;
   d3 ga = mk(0, 0, 0);
   double gm = 0.0, gr = 0.0;
-  for (int s = 0; s < S; ++s) {
+  for (int s = 0; s < J; ++s) {
     d3 w;
-    double K_;
-    if (!primary_sample(a.E, P, rc, wo, ray, s, c_env, w, K_)) continue;
-    double T2 = 1.0;
+    double K_, tw = 1.0;
+    if (!primary_slot(a.E, P, rc, wo, ray, s, c_env, w, K_, tw)) continue;
+    double T2 = tw;
     d3 ce = mk(0, 0, 0), cb = mk(0, 0, 0), we = mk(0, 0, 1), wb = mk(0, 0, 1);
     uint32_t has = 0;
     if (trace2) {
-      const SecFrozen f = a.frozen[ray * S + s];
+      const SecFrozen f = a.frozen[ray * a.spp_stride + s];
       T2 = f.T2;
       ce = ld3(f.ce); cb = ld3(f.cb); we = ld3(f.we); wb = ld3(f.wb);
       has = f.has;

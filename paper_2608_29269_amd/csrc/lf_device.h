@@ -1054,29 +1054,57 @@ __device__ __forceinline__ d3 sample_lobe(d3 n, d3 wo, double r, bool spec, doub
   return (2.0 * oh) * h - wo;
 }
 
-// One primary sample s: technique and direction by one-sample power-heuristic
-// MIS; returns false for a dead sample.  K = c_t p_t / ((c_e p_e)^2 + (c_b p_b)^2).
-__device__ __forceinline__ bool primary_sample(const EnvView &E, const TraceParams &P, const Record &rc, d3 wo,
-                                               int64_t ray, int s, double c_env, d3 &w, double &K) {
+// Secondary-ray slots per primary ray: S, or 2S in the two-ray form.
+__device__ __forceinline__ int n_slots(const TraceParams &P) { return P.spp * ((P.flags & LF_FLAG_NEE) ? 2 : 1); }
+
+// Primary direction of slot j and its frozen weights (Eq. path-estimator,
+// power heuristic); false for a dead slot.  One-ray form (slot = sample s):
+// technique by u0 with probabilities (c_env, 1 - c_env),
+// K = c_t p_t / ((c_e p_e)^2 + (c_b p_b)^2), tw = 1.  Two-ray form (Sec. 4.2;
+// path sample s = j/2, both techniques always drawn): slot 2s samples the
+// environment (dims 9, 10) with K = p_e / (p_e^2 + p_b^2), tw = 1; slot 2s+1
+// samples the cosine/GGX mixture (dims 1-3) with K = 1/p_b, and its escaping
+// term T2 E(w) carries tw = p_b^2 / (p_e^2 + p_b^2) while the indirect term
+// at its secondary hit is not MIS-weighted.
+__device__ __forceinline__ bool primary_slot(const EnvView &E, const TraceParams &P, const Record &rc, d3 wo,
+                                             int64_t ray, int j, double c_env, d3 &w, double &K, double &tw) {
   if (rc.nh == 0) return false;
-  double u0 = urand(P.seed, ray, s, 0), u1 = urand(P.seed, ray, s, 1);
-  double u2 = urand(P.seed, ray, s, 2), u3 = urand(P.seed, ray, s, 3);
-  bool use_env = u0 < c_env;
+  const bool nee = (P.flags & LF_FLAG_NEE) != 0;
+  const int s = nee ? j >> 1 : j;
+  const int kind = nee ? 1 + (j & 1) : 0;  // 0 one-ray, 1 next-event, 2 continuation
+  bool use_env;
+  if (kind == 0) {
+    use_env = urand(P.seed, ray, s, 0) < c_env;
+  } else {
+    use_env = kind == 1;
+    if (use_env && !(c_env > 0.0)) return false;
+  }
   double pe = 0.0, pb;
   if (use_env) {
-    pe = env_sample(E, u2, u3, w);
+    const uint32_t da = kind == 1 ? 9u : 2u;
+    pe = env_sample(E, urand(P.seed, ray, s, da), urand(P.seed, ray, s, da + 1), w);
   } else {
-    double qs = q_spec(rc.a, rc.m, P.flags);
-    w = sample_lobe(rc.n, wo, rc.r, u1 < qs, u2, u3);
+    const double u1 = urand(P.seed, ray, s, 1);
+    const double qs = q_spec(rc.a, rc.m, P.flags);
+    w = sample_lobe(rc.n, wo, rc.r, u1 < qs, urand(P.seed, ray, s, 2), urand(P.seed, ray, s, 3));
   }
   if (!(dot(rc.n, w) > 0.0)) return false;
   pb = pdf_bsdf(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags);
   if (!use_env) pe = c_env > 0.0 ? env_pdf(E, w) : 0.0;
-  double c_bsdf = 1.0 - c_env;
-  double ct = use_env ? c_env : c_bsdf, pt = use_env ? pe : pb;
+  const double pt = use_env ? pe : pb;
   if (!(pt > 0.0)) return false;
-  double den = (c_env * pe) * (c_env * pe) + (c_bsdf * pb) * (c_bsdf * pb);
-  K = ct * pt / den;
+  tw = 1.0;
+  if (kind == 0) {
+    const double c_bsdf = 1.0 - c_env;
+    const double ct = use_env ? c_env : c_bsdf;
+    const double den = (c_env * pe) * (c_env * pe) + (c_bsdf * pb) * (c_bsdf * pb);
+    K = ct * pt / den;
+  } else if (kind == 1) {
+    K = pe / (pe * pe + pb * pb);
+  } else {
+    K = 1.0 / pb;
+    tw = pb * pb / (pe * pe + pb * pb);
+  }
   return true;
 }
 

@@ -152,14 +152,14 @@ struct RaySource {
   const CamArgs *cams;    // device copy of the cameras
 };
 
-// Secondary ray queued by the primary pass (one per live sample).
+// Secondary ray queued by the primary pass (one per live slot).
 struct alignas(16) SecEntry {
   double o[3];
   double w[3];
-  float thr[3];        // K * f * cos * A / S of the primary sample
+  float thr[3];        // K * f * cos * A / S of the primary slot
   int32_t ray;         // primary ray id
-  int32_t s;           // sample index
-  int32_t pad;
+  int32_t s;           // slot: the sample, or 2 * sample + (0 next-event, 1 continuation) in the two-ray form
+  float tw;            // weight of the escaping term T2 E(w) (its MIS weight in the two-ray form, else 1)
 };
 static_assert(sizeof(SecEntry) == 80, "SecEntry layout");
 

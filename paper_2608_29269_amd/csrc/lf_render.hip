@@ -359,7 +359,8 @@ __global__ __launch_bounds__(kBlock) void k_composite1(RenderArgs a, bool replay
 }
 
 // ---------------------------------------------------------------- primary shading
-// Background term, S sampled directions (one-sample MIS), ballot-compacted
+// Background term, the sampled directions of every slot (one-sample MIS, or
+// next-event + continuation per sample in the two-ray form), ballot-compacted
 // enqueue of live secondary rays.  replay = true regenerates the queue only.
 template <bool B>
 __global__ __launch_bounds__(256) void k_shade1(RenderArgs a, bool replay) {
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(256) void k_shade1(RenderArgs a, bool replay) {
   EnvView E;
   TraceParams P;
   req_shading<B>(a, ray, E, P);
-  const int S = P.spp;
+  const int S = P.spp, J = n_slots(P);
   float of[3] = {0, 0, 0}, df[3] = {0, 0, 1};
   if (active) req_ray<B>(a, ray, v, of, df);
   const d3 d = mk(df[0], df[1], df[2]);
@@ -381,15 +382,15 @@ __global__ __launch_bounds__(256) void k_shade1(RenderArgs a, bool replay) {
   d3 L = mk(0, 0, 0);
   if (active && !replay && !(P.flags & LF_FLAG_NO_BACKGROUND)) L = rc.T * env_eval(E, d);
   const bool trace2 = !(P.flags & LF_FLAG_NO_SECONDARY);
-  for (int s = 0; s < S; ++s) {
+  for (int s = 0; s < J; ++s) {
     d3 w = mk(0, 0, 1);
-    double K_ = 0.0;
-    const bool live = active && primary_sample(E, P, rc, wo, v.local, s, c_env, w, K_);
+    double K_ = 0.0, tw = 1.0;
+    const bool live = active && primary_slot(E, P, rc, wo, v.local, s, c_env, w, K_, tw);
     d3 thr = mk(0, 0, 0);
     if (live) thr = (K_ * rc.A / S) * fcos(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags);
     if (!trace2) {
       if (live && !replay) {
-        const d3 Ev = env_eval(E, w);
+        const d3 Ev = tw * env_eval(E, w);
         L = L + mk(thr.x * Ev.x, thr.y * Ev.y, thr.z * Ev.z);
       }
       continue;
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(256) void k_shade1(RenderArgs a, bool replay) {
       e.thr[0] = (float)thr.x; e.thr[1] = (float)thr.y; e.thr[2] = (float)thr.z;
       e.ray = (int32_t)ray;
       e.s = s;
-      e.pad = 0;
+      e.tw = (float)tw;
     }
     wave_append<SecEntry>(live, e, a.queue, a.queue_count);
     if (active && !live) {
@@ -491,12 +492,19 @@ __global__ __launch_bounds__(256) void k_shade2(RenderArgs a, bool replay) {
   const d3 w = mk(e.w[0], e.w[1], e.w[2]);
   const Record r2 = load_record(a.rec2 + qi);
   const double c_env = E.scal[1];
+  const bool nee = (P.flags & LF_FLAG_NEE) != 0;
   SecCoef sc;
-  secondary_coefs(E, P, r2, w, local, e.s, c_env, sc);
+  if (!nee || (e.s & 1)) {  // the indirect term: every ray of the one-ray form, continuations of the two-ray form
+    secondary_coefs(E, P, r2, w, local, nee ? e.s >> 1 : e.s, c_env, sc);
+  } else {
+    sc.ce = sc.cb = sc.we = sc.wb = mk(0, 0, 0);
+    sc.has_e = sc.has_b = false;
+  }
+  const double T2w = (double)e.tw * r2.T;
   const int64_t cs = (int64_t)e.ray * a.spp_stride + e.s;
   if (replay) {
     SecFrozen f;
-    f.T2 = (float)r2.T;
+    f.T2 = (float)T2w;
     f.ce[0] = (float)sc.ce.x; f.ce[1] = (float)sc.ce.y; f.ce[2] = (float)sc.ce.z;
     f.cb[0] = (float)sc.cb.x; f.cb[1] = (float)sc.cb.y; f.cb[2] = (float)sc.cb.z;
     f.we[0] = (float)sc.we.x; f.we[1] = (float)sc.we.y; f.we[2] = (float)sc.we.z;
@@ -505,7 +513,7 @@ __global__ __launch_bounds__(256) void k_shade2(RenderArgs a, bool replay) {
     a.frozen[cs] = f;
     return;
   }
-  d3 Lin = r2.T * env_eval(E, w);
+  d3 Lin = T2w * env_eval(E, w);
   if (sc.has_e) {
     const d3 Ee = env_eval(E, sc.we);
     Lin = Lin + mk(sc.ce.x * Ee.x, sc.ce.y * Ee.y, sc.ce.z * Ee.z);
@@ -525,7 +533,7 @@ __global__ void k_resolve(RenderArgs a) {
   if (ray >= a.R) return;
   const ReqView v = req_view<B>(a, ray);
   if (!v.valid) return;
-  int S = a.P.spp;
+  int S = a.spp_stride;  // slots of every ray (the server's requests use the one-ray form)
   if constexpr (B) S = a.slots[a.chunks[ray / kChunk].slot].spp;
   float *rad = v.radiance + 3 * v.local;
   double L[3] = {rad[0], rad[1], rad[2]};

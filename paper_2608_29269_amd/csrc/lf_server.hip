@@ -433,8 +433,8 @@ lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **o
   p.spp = cfg->max_spp;
   lf_status st = lfh::validate_params(c, &p);
   if (st) return st;
-  if (p.flags & (LF_FLAG_COUNT | LF_FLAG_NO_SECONDARY))
-    return lfh::fail(c, LF_EUNSUPPORTED, "LF_FLAG_COUNT and LF_FLAG_NO_SECONDARY are not served");
+  if (p.flags & (LF_FLAG_COUNT | LF_FLAG_NO_SECONDARY | LF_FLAG_NEE))
+    return lfh::fail(c, LF_EUNSUPPORTED, "LF_FLAG_COUNT, LF_FLAG_NO_SECONDARY and LF_FLAG_NEE are not served");
   if ((int64_t)cfg->batch_rays * cfg->max_spp >= (int64_t)INT32_MAX)
     return lfh::fail(c, LF_EUNSUPPORTED, "batch_rays x max_spp too large");
   if (!lfh::set_device(c)) return lfh::fail(c, LF_EDEVICE, "hipSetDevice");
