@@ -1,4 +1,4 @@
-"""FP64 reference of the geometry-refinement objectives and their gradients.
+"""FP64 reference of the training objectives (geometry refinement, environment TV) and their gradients.
 
 TEST INFRASTRUCTURE ONLY: imported by tests and by the benchmark's CPU leg,
 never by the GPU library or its binding.  Every function is the plain
@@ -11,6 +11,7 @@ by the chain rule; nothing is blocked, fused or reordered.
   normal_loss        Sec. 3.2, Eq. reconstruction-normal (rendered normal)
   depth_normals      the depth-derived normal map of Eq. reconstruction-normal
   depth_normal_loss  Sec. 3.2, Eq. reconstruction-normal (depth-derived normal)
+  tv_loss            Sec. 3.4, Eq. training-objectives (L_TV of the environment map)
 
 Readings of points the paper leaves open:
   * sign(0) = 0 in every L1 gradient;
@@ -22,7 +23,11 @@ Readings of points the paper leaves open:
     the rendered depth along the pixel's ray (y = 0 is the top row), which
     faces the camera on a smooth surface; it is zero on the image border,
     where a neighbour has depth <= 0 (no surface), or where the cross
-    product vanishes.  Both normal objectives average over all H*W pixels.
+    product vanishes.  Both normal objectives average over all H*W pixels;
+  * L_TV (not defined in the paper) is the anisotropic first-order total
+    variation of the lat-long map: |E(y,x+1) - E(y,x)| with x wrapping
+    around in azimuth, plus |E(y+1,x) - E(y,x)| for y < H-1 (no wrap over the
+    poles), summed over channels and divided by 3 H W.
 """
 from __future__ import annotations
 
@@ -139,3 +144,28 @@ def depth_normal_loss(o, d, depth, ref, h, w):
             gP[y - 1, x] += gb
             gP[y + 1, x] -= gb
     return 1.0 - dot / n, (gP * dd).sum(axis=2).reshape(-1)
+
+
+def tv_loss(env):
+    """L_TV of a lat-long environment map [H,W,3] (Eq. training-objectives):
+    returns (loss, dL/denv [H,W,3])."""
+    E = _f64(env)
+    H, W = E.shape[:2]
+    n = 3 * H * W
+    if n == 0:
+        return 0.0, np.zeros_like(E)
+    g = np.zeros_like(E)
+    total = 0.0
+    for y in range(H):
+        for x in range(W):
+            for c in range(3):
+                dh = E[y, (x + 1) % W, c] - E[y, x, c]
+                total += abs(dh)
+                g[y, (x + 1) % W, c] += np.sign(dh)
+                g[y, x, c] -= np.sign(dh)
+                if y + 1 < H:
+                    dv = E[y + 1, x, c] - E[y, x, c]
+                    total += abs(dv)
+                    g[y + 1, x, c] += np.sign(dv)
+                    g[y, x, c] -= np.sign(dv)
+    return total / n, g / n

@@ -199,3 +199,29 @@ def test_depth_normal_gradient_matches_finite_differences():
         assert g[i] == pytest.approx(_fd(f, depth, i, h=1e-7), rel=1e-5, abs=1e-10)
     assert g[5] == 0.0  # every normal that would use it is undefined
     assert np.all(np.isfinite(g))
+
+
+# -- total variation of the environment map (Eq. training-objectives) ------------------
+
+def test_tv_closed_forms():
+    H, W = 6, 10
+    assert OL.tv_loss(np.full((H, W, 3), 2.5))[0] == 0.0
+    E = np.zeros((H, W, 3))
+    E[2, 4, 1] = 3.0  # one hot texel in one channel: two horizontal and two vertical jumps of 3
+    loss, g = OL.tv_loss(E)
+    assert loss == pytest.approx(4 * 3.0 / (3 * H * W), abs=1e-15)
+    assert g[2, 4, 1] == pytest.approx(4 / (3 * H * W)) and g[2, 3, 1] == pytest.approx(-1 / (3 * H * W))
+    # azimuth wraps: a ramp 0..W-1 along x jumps back by W-1 between the last and the first column
+    R = np.tile(np.arange(W, dtype=np.float64)[None, :, None], (H, 1, 3))
+    assert OL.tv_loss(R)[0] == pytest.approx(H * 3 * (2 * (W - 1)) / (3 * H * W))
+    # no wrap over the poles: a ramp along y costs (H-1) per column
+    V = np.tile(np.arange(H, dtype=np.float64)[:, None, None], (1, W, 3))
+    assert OL.tv_loss(V)[0] == pytest.approx(W * 3 * (H - 1) / (3 * H * W))
+    assert OL.tv_loss(np.zeros((1, 1, 3)))[0] == 0.0
+
+
+def test_tv_gradient_matches_finite_differences():
+    E = np.random.default_rng(12).uniform(0, 5, (5, 7, 3))
+    _, g = OL.tv_loss(E)
+    for i in (0, 17, 40, 104):
+        assert g.flat[i] == pytest.approx(_fd(lambda v: OL.tv_loss(v)[0], E, i), rel=1e-6, abs=1e-12)
