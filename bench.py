@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fwd-steps", type=int, default=5)
     ap.add_argument("--geo-steps", type=int, default=10, help="timed geometry-refinement steps (0 = skip)")
+    ap.add_argument("--ir-steps", type=int, default=30,
+                    help="iterations of the staged inverse-rendering loop (0 = skip)")
     ap.add_argument("--nee-spp", type=str, default="8,16,32",
                     help="comma-separated spp of the two-ray estimator's training steps (empty = skip)")
     ap.add_argument("--serve-requests", type=int, default=40, help="requests per serving run (0 = skip)")
@@ -217,6 +219,11 @@ def main():
         log("geometry-refinement step")
         geometry = geometry_bench(lf, tr, env, R, t, cam, wl, params, grads, out, geo_ref, args)
 
+    inverse = None
+    if args.ir_steps > 0:
+        log(f"staged inverse rendering, {args.ir_steps} iterations")
+        inverse = inverse_rendering_bench(lf, tr, sc, wl, params, grads, args)
+
     serving = None
     if args.serve_requests > 0:
         serving = serve_bench(tr, sc, args, [float(x) for x in args.serve_loads.split(",") if x],
@@ -251,6 +258,7 @@ def main():
         "cpu_baseline": cpu,
         "geometry": geometry,
         "two_ray_estimator": estimator,
+        "inverse_rendering": inverse,
         "serving": serving,
     }
     print(json.dumps(res))
@@ -294,6 +302,89 @@ def estimator_bench(lf, tr, env, R, t, cam, wl, params, grads, out, target, spps
                          "secondary_rays_per_step": st["rays_secondary"]}
         log(f"two-ray spp {spp}: {dt * 1e3:.0f} ms/step, {res[str(spp)]['rays_per_s']:.4g} rays/s")
     return res
+
+
+def inverse_rendering_bench(lf, tr, sc, wl, params, grads, args, n_states=3, batch=16384, lam_tv=1e-2,
+                            lr_env=1.0, lr_mat=1e-3):
+    """The staged inverse-rendering loop (Sec. 4.2 implementation details,
+    Eq. training-objectives) as a throughput workload on the resident scene
+    with its geometry fixed: three states, each with its own rigid object
+    transforms, camera and 128x256 environment map (the trainable E_k);
+    targets rendered once from the reference materials and maps.  Every
+    iteration takes one state's image, draws 16,384 of its pixels, traces them
+    with the two-ray estimator, and applies L1 + lambda_E L_TV(E_k) through
+    the replayed backward.  The paper's 15,000-iteration schedule is scaled
+    to the iteration count: lighting only for the first 2/15, then lighting
+    and base colour until 9/15, then all materials; spp 8, 16 from half way,
+    32 from 4/5."""
+    import torch
+    import scenegen
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(4000)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)  # noqa: E731
+    res = args.res
+    states = []
+    for k in range(n_states):
+        R_, t_ = scenegen.random_rigid(rng, sc.n_objects)
+        cam_k = scenegen.sphere_camera(rng, res, res)
+        o, d = tr.raygen(cam_k)
+        states.append(dict(R=T(R_), t=T(t_), env_true=T(scenegen.lognormal_env(rng, 128, 256)), o=o, d=d))
+    # targets: the whole image of each state from the reference materials and maps
+    for stt in states:
+        o_all, d_all = stt["o"], stt["d"]
+        stt["target"] = tr.render(stt["env_true"], stt["R"], stt["t"], rays=(o_all, d_all), k=wl.k, spp=8,
+                                  seed=7, flags=lf.FLAG_NEE)["radiance"].clone()
+        stt["env"] = torch.full_like(stt["env_true"], float(stt["env_true"].mean()))  # trainable E_k
+        stt["g_env"] = torch.empty_like(stt["env"])
+    mats = ("albedo", "roughness", "metallic")
+    ref_mats = {k_: params[k_].clone() for k_ in mats}
+    main_g_env = grads["env"]
+    with torch.no_grad():  # the materials start from a perturbed copy
+        params["albedo"].copy_((ref_mats["albedo"] * 0.5 + 0.25).clamp(0, 1))
+        params["roughness"].fill_(0.5)
+        params["metallic"].fill_(0.1)
+    n_it = args.ir_steps
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    per_bucket = {}
+    tr.sync()
+    tr.stats()
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for it in range(n_it):
+        frac = it / n_it
+        spp = 8 if frac < 0.5 else (16 if frac < 0.8 else 32)
+        unlocked = () if frac < 2 / 15 else (("albedo",) if frac < 0.6 else mats)
+        stt = states[it % n_states]
+        t0 = time.perf_counter()
+        pix = torch.randint(0, res * res, (batch,), device=dev, generator=gen).sort().values
+        o_b, d_b = stt["o"][pix].contiguous(), stt["d"][pix].contiguous()
+        cfg = dict(rays=(o_b, d_b), k=wl.k, spp=spp, seed=100 + it, flags=lf.FLAG_NEE)
+        out = tr.render(stt["env"], stt["R"], stt["t"], **cfg)
+        loss, g = tr.l1_loss(out["radiance"], stt["target"][pix].contiguous())
+        grads["env"] = stt["g_env"]
+        tr.render_backward(stt["env"], stt["R"], stt["t"], d_radiance=g, grads=grads, **cfg)
+        tv, g_tv = tr.loss_tv(stt["env"])
+        with torch.no_grad():
+            stt["env"].sub_(lr_env * (grads["env"] + lam_tv * g_tv)).clamp_(min=0.0)
+            for k_ in unlocked:
+                params[k_].sub_(lr_mat * grads[k_]).clamp_(0.0, 1.0)
+        torch.cuda.synchronize()
+        key = f"spp{spp}_" + ("lighting" if not unlocked else ("lighting+albedo" if len(unlocked) == 1 else "all"))
+        b = per_bucket.setdefault(key, [0, 0.0])
+        b[0] += 1
+        b[1] += time.perf_counter() - t0
+    dt = time.perf_counter() - t_all
+    st = tr.stats()
+    with torch.no_grad():  # restore the reference materials for the legs that follow
+        for k_ in mats:
+            params[k_].copy_(ref_mats[k_])
+    grads["env"] = main_g_env
+    return {"iterations": n_it, "batch_pixels": batch, "states": n_states, "env": [128, 256],
+            "ms_per_iteration": dt * 1e3 / n_it, "iterations_per_s": n_it / dt,
+            "rays_per_s": (st["rays_primary"] + st["rays_secondary"]) / dt, "last_l1": float(loss),
+            "last_tv": float(tv),
+            "ms_per_iteration_by_stage": {k_: v[1] * 1e3 / v[0] for k_, v in per_bucket.items()}}
 
 
 # algorithmic HBM bytes per element of each geometry objective: maps read once, gradient written once

@@ -236,6 +236,14 @@ lf_status lf_loss_depth(lf_ctx *ctx, const float *depth, const float *ref, const
  * the reference); grad = -N* / n.  n = 0 gives loss 0. */
 lf_status lf_loss_normal(lf_ctx *ctx, const float *normal, const float *ref, int64_t n, float *loss, float *grad);
 
+/* Environment regulariser L_TV(E_k) of the inverse-rendering objective
+ * (Sec. 3.4, Eq. training-objectives; the paper does not define it): the
+ * anisotropic first-order total variation of a lat-long map env [h,w,3]
+ * (lf_envmap layout), sum over channels of |E(y,x+1) - E(y,x)| with x wrapping
+ * in azimuth plus |E(y+1,x) - E(y,x)| for y < h-1 (no wrap over the poles),
+ * divided by 3 h w.  grad: [h,w,3] or NULL.  Errors: LF_EINVAL for h or w < 1. */
+lf_status lf_loss_tv(lf_ctx *ctx, const float *env, int32_t h, int32_t w, float *loss, float *grad);
+
 /* Depth-derived-normal term L_DN = 1 - (1/(w h)) sum <N^D, N*> (Sec. 3.2,
  * Eq. reconstruction-normal) for the rendered depth map depth [h*w]
  * (row-major, the rays of `cam` as lf_raygen makes them) and reference

@@ -257,6 +257,15 @@ class Tracer:
         self._chk(self.L.lf_loss_normal(self.ctx, _ptr(normal), _ptr(ref), normal.shape[0], _ptr(loss), _ptr(grad)))
         return loss, grad
 
+    def loss_tv(self, env, want_grad=True):
+        """L_TV of a lat-long environment map [H,W,3] (Eq. training-objectives)."""
+        _check_f32(env)
+        if env.dim() != 3 or env.shape[2] != 3:
+            raise ValueError("env must be [H,W,3]")
+        loss, grad = self._loss_out(env, want_grad)
+        self._chk(self.L.lf_loss_tv(self.ctx, _ptr(env), env.shape[0], env.shape[1], _ptr(loss), _ptr(grad)))
+        return loss, grad
+
     def loss_depth_normal(self, camera, depth, ref, want_grad=True):
         """L_DN on the normals derived from the rendered depth of `camera` (Eq. reconstruction-normal)."""
         _check_f32(depth)

@@ -740,6 +740,16 @@ lf_status lf_loss_normal(lf_ctx *c, const float *normal, const float *ref, int64
   return check_hip(c, "normal loss");
 }
 
+lf_status lf_loss_tv(lf_ctx *c, const float *env, int32_t h, int32_t w, float *loss, float *grad) {
+  if (!c) return LF_EINVAL;
+  if (!env || !loss || h < 1 || w < 1) return fail(c, LF_EINVAL, "invalid TV-loss arguments");
+  set_device(c);
+  if (!loss_acc(c)) return fail(c, LF_ENOMEM, "loss scratch");
+  Phase ph(c, 13);
+  lf::launch_loss_tv(env, h, w, loss, grad, c->lossbuf.as<double>(), c->stream);
+  return check_hip(c, "TV loss");
+}
+
 lf_status lf_loss_depth_normal(lf_ctx *c, const lf_camera *cam, const float *depth, const float *ref, float *loss,
                                float *grad) {
   if (!c) return LF_EINVAL;

@@ -135,6 +135,7 @@ void launch_loss_depth(const float *depth, const float *ref, const float *conf, 
                        float *grad, double *part, hipStream_t st);
 void launch_loss_normal(const float *normal, const float *ref, int64_t n, float *loss, float *grad, double *part,
                         hipStream_t st);
+void launch_loss_tv(const float *env, int h, int w, float *loss, float *grad, double *part, hipStream_t st);
 void launch_loss_depth_normal(const CamArgs *cams, int w, int h, const float *depth, const float *ref, float *loss,
                               float *grad, double *part, hipStream_t st);
 

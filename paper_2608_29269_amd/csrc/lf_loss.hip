@@ -5,6 +5,7 @@
 //   L_D      confidence-weighted relative L1 on depth      (Sec. 3.2, Eq. reconstruction-depth)
 //   L_N      cosine term on the rendered normal map        (Sec. 3.2, Eq. reconstruction-normal)
 //   L_DN     cosine term on the depth-derived normal map   (Sec. 3.2, Eq. reconstruction-normal)
+//   L_TV     total variation of the environment map E_k    (Sec. 3.4, Eq. training-objectives)
 // Each is one streaming pass over its maps (HBM-bound) on at most
 // kMaxLossBlocks blocks: per-element terms are summed in binary64, each
 // block stores its partial sum in its own slot (no atomics: one address hit
@@ -146,6 +147,39 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_normal(const float *normal,
     const double r = ref[k];
     s += (double)normal[k] * r;
     if (grad) grad[k] = (float)(-r * inv_n);
+  }
+  block_store<1>({s}, part);
+}
+
+// L_TV: anisotropic first-order total variation of a lat-long map [H,W,3]:
+// |E(y,x+1) - E(y,x)| with x wrapping in azimuth, plus |E(y+1,x) - E(y,x)| for
+// y < H-1 (no wrap over the poles), over 3 H W values.  One texel per thread:
+// its two forward differences enter the sum, and its gradient gathers the
+// signs of the (at most four) differences it takes part in.
+__device__ inline float sgn_diff(float a, float b) { return (float)((a > b) - (a < b)); }  // sign(a - b)
+
+__global__ __launch_bounds__(kLossBlock) void k_loss_tv(const float *E, int H, int W, double inv_n, float *grad,
+                                                        double *part) {
+  const int64_t n = (int64_t)H * W;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kLossBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kLossBlock) {
+    const int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
+    const int64_t row = (int64_t)y * W;
+    const float *e = E + 3 * i;
+    const float *er = E + 3 * (row + (x + 1 == W ? 0 : x + 1));
+    const float *el = E + 3 * (row + (x == 0 ? W - 1 : x - 1));
+    const bool up = y > 0, down = y + 1 < H;
+    for (int c = 0; c < 3; ++c) {
+      const float v = e[c];
+      s += fabs((double)er[c] - (double)v);
+      if (down) s += fabs((double)e[3 * W + c] - (double)v);
+      if (grad) {
+        float g = sgn_diff(v, el[c]) - sgn_diff(er[c], v);
+        if (up) g += sgn_diff(v, e[c - 3 * W]);
+        if (down) g -= sgn_diff(e[3 * W + c], v);
+        grad[3 * i + c] = (float)((double)g * inv_n);
+      }
+    }
   }
   block_store<1>({s}, part);
 }
@@ -298,6 +332,15 @@ void launch_loss_normal(const float *normal, const float *ref, int64_t n, float 
     hipLaunchKernelGGL(k_loss_normal, dim3(nb), dim3(kLossBlock), 0, st, normal, ref, 3 * n, inv_n, grad, part);
   hipLaunchKernelGGL(k_loss_reduce<1>, dim3(1), dim3(kLossBlock), 0, st, (const double *)part, (int)nb, -inv_n,
                      n > 0 ? 1.0 : 0.0, 0.0, part + 2 * kMaxLossBlocks, loss);
+}
+
+void launch_loss_tv(const float *env, int h, int w, float *loss, float *grad, double *part, hipStream_t st) {
+  const int64_t n = (int64_t)h * w;
+  const unsigned nb = loss_grid(n);
+  const double inv_n = 1.0 / (3.0 * (double)n);
+  hipLaunchKernelGGL(k_loss_tv, dim3(nb), dim3(kLossBlock), 0, st, env, h, w, inv_n, grad, part);
+  hipLaunchKernelGGL(k_loss_reduce<1>, dim3(1), dim3(kLossBlock), 0, st, (const double *)part, (int)nb, inv_n, 0.0, 0.0,
+                     part + 2 * kMaxLossBlocks, loss);
 }
 
 void launch_loss_depth_normal(const CamArgs *cams, int w, int h, const float *depth, const float *ref, float *loss,

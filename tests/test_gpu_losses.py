@@ -88,6 +88,18 @@ def test_normal_loss(tracer, n):
     _close_grad(g, gref)
 
 
+@pytest.mark.parametrize("h,w", [(1, 1), (1, 7), (5, 1), (17, 33), (128, 256), (256, 512)])
+def test_tv_loss(tracer, h, w):
+    rng = np.random.default_rng(h * 1000 + w)
+    E = np.exp(rng.normal(0, 1, (h, w, 3))).astype(np.float32)
+    if h * w > 4:
+        E[h // 2, :, 1] = E[h // 2, 0, 1]  # a constant run: sign(0) = 0 in the gradient
+    loss, g = tracer.loss_tv(dev(E))
+    want, gref = OL.tv_loss(E)
+    _close_loss(loss, want)
+    _close_grad(g, gref)
+
+
 def _depth_scene(cam, rng, holes=True):
     """Smooth depth of a tilted, gently curved surface seen by `cam`, with a
     few pixels without surface (depth 0)."""
