@@ -21,6 +21,7 @@ NO_SECONDARY = 1 << 0
 NO_BACKGROUND = 1 << 1
 BSDF_ONLY = 1 << 2
 DIFFUSE_ONLY = 1 << 3
+SOBOL = 1 << 8  # Owen-scrambled Sobol uniforms instead of the hash
 NEE = 1 << 7  # two rays per path sample (next-event + continuation); outputs per slot 2s, 2s+1
 
 M_TGAP_PRI, M_RHO_PRI, M_TGAP_SEC, M_RHO_SEC, M_ENV, M_LOBE, M_COS, M_TMIN = range(8)
@@ -92,6 +93,14 @@ def lib():
         L.ors_splitmix64.restype = C.c_uint64
         L.ors_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32]
         L.ors_uniform.restype = C.c_double
+        L.ors_sobol.argtypes = [C.c_uint32, C.c_uint32]
+        L.ors_sobol.restype = C.c_uint32
+        L.ors_sobol_poly.argtypes = [C.c_uint32, C.POINTER(C.c_int32), C.POINTER(C.c_uint32)]
+        L.ors_sobol_poly.restype = None
+        L.ors_owen_scramble.argtypes = [C.c_uint32, C.c_uint32]
+        L.ors_owen_scramble.restype = C.c_uint32
+        L.ors_sobol_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32]
+        L.ors_sobol_uniform.restype = C.c_double
         L.ors_quat_to_frame.argtypes = [_dp, _dp, _dp, _dp]
         L.ors_onb.argtypes = [_dp, _dp, _dp]
         L.ors_brdf.argtypes = [_dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_uint32, _dp]
@@ -254,6 +263,27 @@ def splitmix64(x: int) -> int:
 
 def uniform(seed: int, ray: int, sample: int, dim: int) -> float:
     return float(lib().ors_uniform(seed, ray, sample, dim))
+
+
+def sobol(i: int, d: int) -> int:
+    """Raw 32-bit Sobol coordinate of point i in dimension d (< 11)."""
+    return int(lib().ors_sobol(i, d))
+
+
+def sobol_poly(d: int):
+    """(degree s, inner coefficients a) of dimension d's polynomial
+    x^s + a_1 x^(s-1) + ... + a_(s-1) x + 1, a_1 the top bit of a."""
+    s, a = C.c_int32(), C.c_uint32()
+    lib().ors_sobol_poly(d, C.byref(s), C.byref(a))
+    return int(s.value), int(a.value)
+
+
+def owen_scramble(x: int, seed: int) -> int:
+    return int(lib().ors_owen_scramble(x, seed))
+
+
+def sobol_uniform(seed: int, ray: int, sample: int, dim: int) -> float:
+    return float(lib().ors_sobol_uniform(seed, ray, sample, dim))
 
 
 def quat_to_frame(q):

@@ -57,6 +57,91 @@ double ors_uniform(uint64_t seed, uint64_t ray, uint64_t sample, uint32_t dim) {
   return (double)(h >> 40) * (1.0 / 16777216.0);
 }
 
+/* Owen-scrambled Sobol points (Sec. 3.3 PRB paragraph: the forward seed is
+ * recorded and the same Sobol samples are replayed).  Sobol's construction
+ * with the direction numbers of Joe and Kuo (2008) for dimensions 1..10
+ * (primitive polynomial of degree s with inner coefficients a, initial
+ * m_1..m_s), dimension 0 the van der Corput sequence; the point of index i
+ * XORs the direction numbers V_k of the set bits k of i.  Pinned: the
+ * construction (hand-derived first points, nets), primitive polynomials,
+ * valid m_k and 2D projections of t <= 4; that the m_k are Joe and Kuo's
+ * particular choice among valid ones is parity unpinned. */
+#define ORS_SOBOL_DIMS 11
+static const int sob_s[ORS_SOBOL_DIMS] = {0, 1, 2, 3, 3, 4, 4, 5, 5, 5, 5};
+static const uint32_t sob_a[ORS_SOBOL_DIMS] = {0, 0, 1, 1, 2, 1, 4, 2, 4, 7, 11};
+static const uint32_t sob_m[ORS_SOBOL_DIMS][5] = {{0},          {1},          {1, 3},         {1, 3, 1},
+                                                  {1, 1, 1},    {1, 1, 3, 3}, {1, 3, 5, 13},  {1, 1, 5, 5, 17},
+                                                  {1, 1, 5, 5, 5}, {1, 1, 7, 11, 19}, {1, 1, 5, 1, 1}};
+
+/* direction number V_k (k = 1..32) of dimension d, as a 32-bit fraction:
+ * V_k = m_k 2^(32-k), with m_k from the polynomial's recurrence
+ * m_k = 2 a_1 m_(k-1) ^ 4 a_2 m_(k-2) ^ ... ^ 2^(s-1) a_(s-1) m_(k-s+1) ^ 2^s m_(k-s) ^ m_(k-s) */
+static uint32_t sobol_direction(int d, int k) {
+  if (d == 0) return 1u << (32 - k);
+  const int s = sob_s[d];
+  uint64_t m[33];
+  for (int j = 1; j <= 32; ++j) {
+    if (j <= s) {
+      m[j] = sob_m[d][j - 1];
+    } else {
+      uint64_t v = (m[j - s] << s) ^ m[j - s];
+      for (int i = 1; i < s; ++i)
+        if ((sob_a[d] >> (s - 1 - i)) & 1u) v ^= m[j - i] << i;
+      m[j] = v;
+    }
+  }
+  return (uint32_t)(m[k] << (32 - k));
+}
+
+void ors_sobol_poly(uint32_t d, int32_t *degree, uint32_t *inner) {
+  *degree = sob_s[d];
+  *inner = sob_a[d];
+}
+
+uint32_t ors_sobol(uint32_t i, uint32_t d) {
+  uint32_t x = 0;
+  for (int k = 1; k <= 32; ++k)
+    if ((i >> (k - 1)) & 1u) x ^= sobol_direction((int)d, k);
+  return x;
+}
+
+static uint32_t reverse_bits32(uint32_t x) {
+  uint32_t r = 0;
+  for (int b = 0; b < 32; ++b) r |= ((x >> b) & 1u) << (31 - b);
+  return r;
+}
+
+/* nested uniform (Owen) scramble by Burley's hash (2020, "Practical
+ * Hash-based Owen Scrambling"): in bit-reversed order, an add and four
+ * xor-multiplies by even constants, so every bit is flipped by a function
+ * of the bits above it in the original order only */
+uint32_t ors_owen_scramble(uint32_t x, uint32_t seed) {
+  x = reverse_bits32(x);
+  x += seed;
+  x ^= x * 0x6c50b47cu;
+  x ^= x * 0xb82f1e52u;
+  x ^= x * 0xc7afe638u;
+  x ^= x * 0x8d22f6e6u;
+  return reverse_bits32(x);
+}
+
+/* u = 24-bit uniform of (seed, ray, sample, dim): the ray's seed scrambles
+ * the sample index (so every ray uses its own aligned block of the
+ * sequence) and, per dimension, the Sobol coordinate */
+double ors_sobol_uniform(uint64_t seed, uint64_t ray, uint64_t sample, uint32_t dim) {
+  const uint64_t h = ors_splitmix64(seed ^ ors_splitmix64(ray));
+  const uint32_t i = ors_owen_scramble((uint32_t)sample, (uint32_t)h);
+  const uint32_t ds = (uint32_t)(ors_splitmix64(h ^ (0x100000000ull + dim)) >> 32);
+  const uint32_t x = ors_owen_scramble(ors_sobol(i, dim), ds);
+  return (double)(x >> 8) * (1.0 / 16777216.0);
+}
+
+/* the sampler the parameters select */
+static double draw(const ors_params *p, int64_t ray, int s, uint32_t dim) {
+  return (p->flags & ORS_SOBOL) ? ors_sobol_uniform(p->seed, (uint64_t)ray, (uint64_t)s, dim)
+                                : ors_uniform(p->seed, (uint64_t)ray, (uint64_t)s, dim);
+}
+
 /* ------------------------------------------------------------------------ */
 /* frames                                                                   */
 /* ------------------------------------------------------------------------ */
@@ -636,19 +721,19 @@ static int sample_slot(const world *w, const record *rc, const double *wo, int64
   double pe = 0.0, pb = 0.0;
   int use_env;
   if (kind == 0) {
-    use_env = ors_uniform(p->seed, ray_id, s, 0) < w->c_env;
+    use_env = draw(p, ray_id, s, 0) < w->c_env;
   } else {
     use_env = kind == 1;
     if (use_env && !(w->c_env > 0.0)) return 0;
   }
   if (use_env) {
     const uint32_t da = kind == 1 ? 9 : 2;
-    pe = env_sample_m(w, ors_uniform(p->seed, ray_id, s, da), ors_uniform(p->seed, ray_id, s, da + 1), sp->w,
+    pe = env_sample_m(w, draw(p, ray_id, s, da), draw(p, ray_id, s, da + 1), sp->w,
                       &fz->margins[ORS_M_ENV]);
   } else {
-    double u1 = ors_uniform(p->seed, ray_id, s, 1);
+    double u1 = draw(p, ray_id, s, 1);
     if (qs > 0.0 && qs < 1.0) fz->margins[ORS_M_LOBE] = dmin(fz->margins[ORS_M_LOBE], fabs(u1 - qs));
-    sample_lobe(rc->n, wo, rc->r, u1 < qs, ors_uniform(p->seed, ray_id, s, 2), ors_uniform(p->seed, ray_id, s, 3),
+    sample_lobe(rc->n, wo, rc->r, u1 < qs, draw(p, ray_id, s, 2), draw(p, ray_id, s, 3),
                 sp->w);
   }
   double cosw = dot3(rc->n, sp->w);
@@ -721,7 +806,7 @@ static void decide(const world *w, const double *o, const double *d, int64_t ray
      * the two-sample power heuristic */
     double wo2[3] = {-sp->w[0], -sp->w[1], -sp->w[2]};
     if (w->c_env > 0.0) {
-      double u4 = ors_uniform(p->seed, ray_id, s, 4), u5 = ors_uniform(p->seed, ray_id, s, 5);
+      double u4 = draw(p, ray_id, s, 4), u5 = draw(p, ray_id, s, 5);
       double pe2 = env_sample_m(w, u4, u5, sp->we, &fz->margins[ORS_M_ENV]);
       double c2 = dot3(r2.n, sp->we);
       fz->margins[ORS_M_COS] = dmin(fz->margins[ORS_M_COS], fabs(c2));
@@ -736,8 +821,8 @@ static void decide(const world *w, const double *o, const double *d, int64_t ray
       }
     }
     {
-      double u6 = ors_uniform(p->seed, ray_id, s, 6), u7 = ors_uniform(p->seed, ray_id, s, 7),
-             u8 = ors_uniform(p->seed, ray_id, s, 8);
+      double u6 = draw(p, ray_id, s, 6), u7 = draw(p, ray_id, s, 7),
+             u8 = draw(p, ray_id, s, 8);
       double qs2 = q_spec(r2.a, r2.m, p->flags);
       if (qs2 > 0.0 && qs2 < 1.0) fz->margins[ORS_M_LOBE] = dmin(fz->margins[ORS_M_LOBE], fabs(u6 - qs2));
       sample_lobe(r2.n, wo2, r2.r, u6 < qs2, u7, u8, sp->wb);

@@ -50,6 +50,7 @@ extern "C" {
 #define ORS_NO_BACKGROUND (1u << 1) /* drop the T*E(d) background term */
 #define ORS_BSDF_ONLY     (1u << 2) /* never use environment importance sampling */
 #define ORS_DIFFUSE_ONLY  (1u << 3) /* Lambert lobe only (no GGX term, cosine sampling) */
+#define ORS_SOBOL         (1u << 8) /* Owen-scrambled Sobol uniforms instead of the hash */
 #define ORS_NEE           (1u << 7) /* two rays per path sample: an environment next-event ray and a
                                        cosine/GGX continuation, multi-sample power MIS; outputs indexed
                                        by slot 2s (next-event) and 2s+1 (continuation) */
@@ -158,6 +159,10 @@ float ors_tan_half(float fov_y_deg);
 /* sampler (SplitMix64 chain, Steele, Lea & Flood 2014) */
 uint64_t ors_splitmix64(uint64_t x);
 double ors_uniform(uint64_t seed, uint64_t ray, uint64_t sample, uint32_t dim);
+uint32_t ors_sobol(uint32_t i, uint32_t d);                 /* raw Sobol point, d < 11 */
+void ors_sobol_poly(uint32_t d, int32_t *degree, uint32_t *inner); /* its primitive polynomial */
+uint32_t ors_owen_scramble(uint32_t x, uint32_t seed);      /* nested uniform scramble */
+double ors_sobol_uniform(uint64_t seed, uint64_t ray, uint64_t sample, uint32_t dim);
 
 /* building blocks exposed for closed-form tests */
 void ors_quat_to_frame(const double q[4], double tu[3], double tv[3], double n[3]);
