@@ -266,14 +266,14 @@ def main():
 
 def estimator_bench(lf, tr, env, R, t, cam, wl, params, grads, out, target, spps, lr=1e-5):
     """The paper's two-ray estimator (Sec. 4.2: per path sample one
-    environment next-event ray and one cosine/GGX continuation) on the same
-    scene and camera, at the spp of its training schedule (8, 16, 32): one
+    environment next-event ray and one cosine/GGX continuation) with the
+    replayed Owen-scrambled Sobol samples (Sec. 3.3) on the same scene and camera, at the spp of its training schedule (8, 16, 32): one
     warm-up and one timed training step each (refit, forward, L1, replayed
     backward, SGD)."""
     import torch
     res = {}
     for spp in spps:
-        cfg = dict(cameras=[cam], k=wl.k, spp=spp, seed=wl.seed, flags=lf.FLAG_NEE)
+        cfg = dict(cameras=[cam], k=wl.k, spp=spp, seed=wl.seed, flags=lf.FLAG_NEE | lf.FLAG_SOBOL)
 
         def step():
             tr.refit()
@@ -312,7 +312,7 @@ def inverse_rendering_bench(lf, tr, sc, wl, params, grads, args, n_states=3, bat
     transforms, camera and 128x256 environment map (the trainable E_k);
     targets rendered once from the reference materials and maps.  Every
     iteration takes one state's image, draws 16,384 of its pixels, traces them
-    with the two-ray estimator, and applies L1 + lambda_E L_TV(E_k) through
+    with the two-ray estimator and the Sobol sampler, and applies L1 + lambda_E L_TV(E_k) through
     the replayed backward.  The paper's 15,000-iteration schedule is scaled
     to the iteration count: lighting only for the first 2/15, then lighting
     and base colour until 9/15, then all materials; spp 8, 16 from half way,
@@ -333,7 +333,7 @@ def inverse_rendering_bench(lf, tr, sc, wl, params, grads, args, n_states=3, bat
     for stt in states:
         o_all, d_all = stt["o"], stt["d"]
         stt["target"] = tr.render(stt["env_true"], stt["R"], stt["t"], rays=(o_all, d_all), k=wl.k, spp=8,
-                                  seed=7, flags=lf.FLAG_NEE)["radiance"].clone()
+                                  seed=7, flags=lf.FLAG_NEE | lf.FLAG_SOBOL)["radiance"].clone()
         stt["env"] = torch.full_like(stt["env_true"], float(stt["env_true"].mean()))  # trainable E_k
         stt["g_env"] = torch.empty_like(stt["env"])
     mats = ("albedo", "roughness", "metallic")
@@ -359,7 +359,7 @@ def inverse_rendering_bench(lf, tr, sc, wl, params, grads, args, n_states=3, bat
         t0 = time.perf_counter()
         pix = torch.randint(0, res * res, (batch,), device=dev, generator=gen).sort().values
         o_b, d_b = stt["o"][pix].contiguous(), stt["d"][pix].contiguous()
-        cfg = dict(rays=(o_b, d_b), k=wl.k, spp=spp, seed=100 + it, flags=lf.FLAG_NEE)
+        cfg = dict(rays=(o_b, d_b), k=wl.k, spp=spp, seed=100 + it, flags=lf.FLAG_NEE | lf.FLAG_SOBOL)
         out = tr.render(stt["env"], stt["R"], stt["t"], **cfg)
         loss, g = tr.l1_loss(out["radiance"], stt["target"][pix].contiguous())
         grads["env"] = stt["g_env"]

@@ -136,6 +136,14 @@ typedef struct {
  * MIS serves both roles.  Secondary outputs are indexed by slot (2S per ray).
  * Not accepted by the relight server. */
 #define LF_FLAG_NEE           (1u << 7)
+/* Owen-scrambled Sobol uniforms (Sec. 3.3 PRB paragraph: the seed is
+ * recorded and the same Sobol samples replayed) instead of the SplitMix64
+ * hash: Sobol points of 11 dimensions (van der Corput, then Joe and Kuo's
+ * 2008 direction numbers), the sample index and each coordinate
+ * nested-uniform scrambled by Burley's hash (2020) seeded per ray, 24-bit
+ * uniforms; the samples of one ray form an aligned block of the sequence,
+ * so power-of-two spp are stratified in every dimension. */
+#define LF_FLAG_SOBOL         (1u << 8)
 
 /* Tracing and estimator parameters.  Readings of points the paper leaves
  * open (Sec. 3.2 "finite support", "opacity threshold", epsilon of

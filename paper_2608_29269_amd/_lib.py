@@ -23,6 +23,7 @@ FLAG_BRUTE_FORCE = 1 << 4
 FLAG_COUNT = 1 << 5
 FLAG_UNSORTED = 1 << 6
 FLAG_NEE = 1 << 7  # the two-ray estimator: next-event + continuation per sample
+FLAG_SOBOL = 1 << 8  # Owen-scrambled Sobol uniforms instead of the hash
 MAX_CAMERAS = 16
 SCHED_SHORTEST_FIRST, SCHED_OLDEST_FIRST, SCHED_ROUND_ROBIN = 0, 1, 2
 

@@ -99,7 +99,7 @@ lf_status validate_params(lf_ctx *c, const lf_params *p) {
   if (!(p->alpha_min > 0.0) || !(p->alpha_cap > 0.0 && p->alpha_cap < 1.0) || !(p->support_sigma > 0.0) ||
       !(p->eps >= 0.0) || !(p->t_min >= 0.0) || !std::isfinite(p->secondary_offset))
     return fail(c, LF_EINVAL, "invalid tracing constants");
-  if (p->flags & ~0xFFu) return fail(c, LF_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~0x1FFu) return fail(c, LF_EINVAL, "unknown flags 0x%x", p->flags);
   return LF_OK;
 }
 

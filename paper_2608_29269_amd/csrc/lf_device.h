@@ -55,6 +55,73 @@ __device__ __forceinline__ double urand(uint64_t seed, uint64_t ray, uint64_t s,
   return (double)(h >> 40) * (1.0 / 16777216.0);
 }
 
+// Owen-scrambled Sobol uniforms (the replayed Sobol samples of the PRB
+// paragraph, Sec. 3.3).  Direction numbers of 11 dimensions: dimension 0 is
+// van der Corput; dimensions 1..10 use the primitive polynomials and initial
+// numbers of Joe and Kuo (2008), degree s, inner coefficients a (a_1 the top
+// bit), m_1..m_s, extended by V_k = a_1 V_(k-1) ^ ... ^ a_(s-1) V_(k-s+1) ^
+// V_(k-s) ^ (V_(k-s) >> s) on the 32-bit fractions V_k = m_k 2^(32-k).
+struct SobolDirections {
+  uint32_t v[11][32];  // v[d][k-1] = V_k
+};
+
+constexpr SobolDirections sobol_directions() {
+  constexpr int deg[11] = {0, 1, 2, 3, 3, 4, 4, 5, 5, 5, 5};
+  constexpr uint32_t inner[11] = {0, 0, 1, 1, 2, 1, 4, 2, 4, 7, 11};
+  constexpr uint32_t init[11][5] = {{0}, {1}, {1, 3}, {1, 3, 1}, {1, 1, 1}, {1, 1, 3, 3}, {1, 3, 5, 13},
+                                    {1, 1, 5, 5, 17}, {1, 1, 5, 5, 5}, {1, 1, 7, 11, 19}, {1, 1, 5, 1, 1}};
+  SobolDirections t{};
+  for (int k = 1; k <= 32; ++k) t.v[0][k - 1] = 1u << (32 - k);
+  for (int d = 1; d < 11; ++d) {
+    const int s = deg[d];
+    for (int k = 1; k <= 32; ++k) {
+      uint32_t v = 0;
+      if (k <= s) {
+        v = init[d][k - 1] << (32 - k);
+      } else {
+        v = t.v[d][k - s - 1] ^ (t.v[d][k - s - 1] >> s);
+        for (int j = 1; j < s; ++j)
+          if ((inner[d] >> (s - 1 - j)) & 1u) v ^= t.v[d][k - j - 1];
+      }
+      t.v[d][k - 1] = v;
+    }
+  }
+  return t;
+}
+
+__constant__ SobolDirections kSobol = sobol_directions();
+
+__device__ __forceinline__ uint32_t sobol32(uint32_t i, int d) {
+  uint32_t x = 0;
+  for (int k = 0; i; ++k, i >>= 1)
+    if (i & 1u) x ^= kSobol.v[d][k];
+  return x;
+}
+
+// Nested uniform (Owen) scramble by Burley's hash ("Practical Hash-based Owen
+// Scrambling", 2020): in bit-reversed order an add and four xor-multiplies by
+// even constants, so each bit is flipped by a function of the bits above it.
+__device__ __forceinline__ uint32_t owen32(uint32_t x, uint32_t seed) {
+  x = __builtin_bitreverse32(x);
+  x += seed;
+  x ^= x * 0x6c50b47cu;
+  x ^= x * 0xb82f1e52u;
+  x ^= x * 0xc7afe638u;
+  x ^= x * 0x8d22f6e6u;
+  return __builtin_bitreverse32(x);
+}
+
+// 24-bit uniform of (seed, ray, sample, dim): the ray's hash scrambles the
+// sample index (each ray draws an aligned block of the sequence) and, per
+// dimension, the coordinate.
+__device__ __forceinline__ double sobol_u(uint64_t seed, uint64_t ray, uint64_t s, uint32_t dim) {
+  const uint64_t h = splitmix64(seed ^ splitmix64(ray));
+  const uint32_t i = owen32((uint32_t)s, (uint32_t)h);
+  const uint32_t ds = (uint32_t)(splitmix64(h ^ (0x100000000ull + dim)) >> 32);
+  return (double)(owen32(sobol32(i, (int)dim), ds) >> 8) * (1.0 / 16777216.0);
+}
+
+
 // ------------------------------------------------------------------ frames
 // columns of the rotation of a unit quaternion (w,x,y,z)
 __device__ __forceinline__ void quat_frame(double w, double x, double y, double z, d3 &tu, d3 &tv, d3 &n) {
@@ -1054,6 +1121,12 @@ __device__ __forceinline__ d3 sample_lobe(d3 n, d3 wo, double r, bool spec, doub
   return (2.0 * oh) * h - wo;
 }
 
+// The uniform of (ray, sample, dim) from the sampler the flags select.
+__device__ __forceinline__ double draw(const TraceParams &P, int64_t ray, int s, uint32_t dim) {
+  return (P.flags & LF_FLAG_SOBOL) ? sobol_u(P.seed, (uint64_t)ray, (uint64_t)s, dim)
+                                   : urand(P.seed, (uint64_t)ray, (uint64_t)s, dim);
+}
+
 // Secondary-ray slots per primary ray: S, or 2S in the two-ray form.
 __device__ __forceinline__ int n_slots(const TraceParams &P) { return P.spp * ((P.flags & LF_FLAG_NEE) ? 2 : 1); }
 
@@ -1074,7 +1147,7 @@ __device__ __forceinline__ bool primary_slot(const EnvView &E, const TraceParams
   const int kind = nee ? 1 + (j & 1) : 0;  // 0 one-ray, 1 next-event, 2 continuation
   bool use_env;
   if (kind == 0) {
-    use_env = urand(P.seed, ray, s, 0) < c_env;
+    use_env = draw(P, ray, s, 0) < c_env;
   } else {
     use_env = kind == 1;
     if (use_env && !(c_env > 0.0)) return false;
@@ -1082,11 +1155,11 @@ __device__ __forceinline__ bool primary_slot(const EnvView &E, const TraceParams
   double pe = 0.0, pb;
   if (use_env) {
     const uint32_t da = kind == 1 ? 9u : 2u;
-    pe = env_sample(E, urand(P.seed, ray, s, da), urand(P.seed, ray, s, da + 1), w);
+    pe = env_sample(E, draw(P, ray, s, da), draw(P, ray, s, da + 1), w);
   } else {
-    const double u1 = urand(P.seed, ray, s, 1);
+    const double u1 = draw(P, ray, s, 1);
     const double qs = q_spec(rc.a, rc.m, P.flags);
-    w = sample_lobe(rc.n, wo, rc.r, u1 < qs, urand(P.seed, ray, s, 2), urand(P.seed, ray, s, 3));
+    w = sample_lobe(rc.n, wo, rc.r, u1 < qs, draw(P, ray, s, 2), draw(P, ray, s, 3));
   }
   if (!(dot(rc.n, w) > 0.0)) return false;
   pb = pdf_bsdf(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags);
@@ -1125,7 +1198,7 @@ __device__ __forceinline__ void secondary_coefs(const EnvView &E, const TracePar
   if (r2.nh == 0) return;
   d3 wo2 = -w;
   if (c_env > 0.0) {
-    double u4 = urand(P.seed, ray, s, 4), u5 = urand(P.seed, ray, s, 5);
+    double u4 = draw(P, ray, s, 4), u5 = draw(P, ray, s, 5);
     double pe2 = env_sample(E, u4, u5, sc.we);
     double c2 = dot(r2.n, sc.we);
     if (c2 > 0.0 && pe2 > 0.0) {
@@ -1136,7 +1209,7 @@ __device__ __forceinline__ void secondary_coefs(const EnvView &E, const TracePar
       sc.has_e = true;
     }
   }
-  double u6 = urand(P.seed, ray, s, 6), u7 = urand(P.seed, ray, s, 7), u8 = urand(P.seed, ray, s, 8);
+  double u6 = draw(P, ray, s, 6), u7 = draw(P, ray, s, 7), u8 = draw(P, ray, s, 8);
   double qs2 = q_spec(r2.a, r2.m, P.flags);
   sc.wb = sample_lobe(r2.n, wo2, r2.r, u6 < qs2, u7, u8);
   double c2 = dot(r2.n, sc.wb);

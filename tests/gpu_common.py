@@ -47,7 +47,7 @@ def ambiguous(margins, include_secondary=True):
 
 
 def oracle_flags(flags):
-    return int(flags) & (0xF | oracle.NEE)
+    return int(flags) & (0xF | oracle.NEE | oracle.SOBOL)
 
 
 def run_oracle(scene, state, o, d, ids, k, spp, seed, flags, threads=0, lists=True):
