@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=40, help="requests per serving run (0 = skip)")
     ap.add_argument("--serve-loads", type=str, default="0.8",
                     help="comma-separated arrival rates as fractions of the plain tracer's capacity")
-    ap.add_argument("--serve-policies", type=str, default="0",
+    ap.add_argument("--serve-policies", type=str, default="0,1",
                     help="comma-separated pass-filling policies (0 shortest first, 1 oldest first, 2 round robin)")
     ap.add_argument("--serve-batch", type=int, default=1048576, help="primary rays per batched pass")
     ap.add_argument("--serve-in-flight", type=int, default=2, help="concurrent passes (one stream each)")

@@ -104,3 +104,41 @@ def test_full_size_gradients_from_sampled_pixels(tracer, which):
     tracer.sync()
     for name in ("mu", "q", "scale", "opacity", "albedo", "roughness", "metallic", "env"):
         _grad_check(g[name].cpu().numpy(), g_ref[name], name)
+
+
+def test_full_size_two_ray_sobol_step_on_sampled_pixels(tracer):
+    """The benchmark's two-ray leg at its first spp: 1M surfels, 1024^2,
+    next-event + continuation per sample with Owen-scrambled Sobol samples
+    (LF_FLAG_NEE | LF_FLAG_SOBOL), spp 8 (16 secondary slots per ray):
+    forward outputs and gradients from an upstream on sampled pixels."""
+    wl = scenegen.make_workload(5)
+    st = wl.states[0]
+    cams = st.cameras
+    spp, flags = 8, oracle.NEE | oracle.SOBOL
+    upload_scene(tracer, wl.scene)
+    args = state_args(tracer, wl.scene, st)
+    out = tracer.render(**args, cameras=cams, k=wl.k, spp=spp, seed=wl.seed, flags=flags)
+    tracer.sync()
+    ids, o, d = _sampled_rays(cams, N_SAMPLE, 7)
+    sa = oracle.SceneArrays(wl.scene, st.R, st.t, st.env)
+    p = oracle.Params(k=wl.k, spp=spp, seed=wl.seed, flags=flags)
+    ref = oracle.render(sa, o, d, ids, p, lists=False)
+    amb = ambiguous(ref["margins"])
+    ok = ~amb
+    assert ok.mean() >= 0.9, amb.mean()
+    for key in ("radiance", "depth", "normal", "alpha"):
+        g = out[key].cpu().numpy()[ids]
+        assert rel_close(g[ok], ref[key][ok], RTOL) < RTOL, key
+    n = cams[0].w * cams[0].h
+    rng = np.random.default_rng(8)
+    up = rng.standard_normal((N_SAMPLE, 3))
+    up[amb] = 0.0
+    up = up.astype(np.float32)
+    full = np.zeros((n, 3), np.float32)
+    full[ids] = up
+    g_ref = oracle.backward(sa, o, d, ids, p, g_radiance=up)
+    g = tracer.render_backward(**args, cameras=cams, k=wl.k, spp=spp, seed=wl.seed, flags=flags,
+                               d_radiance=dev(full))
+    tracer.sync()
+    for name in ("mu", "q", "scale", "opacity", "albedo", "roughness", "metallic", "env"):
+        _grad_check(g[name].cpu().numpy(), g_ref[name], name)
