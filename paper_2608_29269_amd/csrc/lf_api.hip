@@ -434,21 +434,47 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
   if (hipStreamSynchronize(st) != hipSuccess ||
       hipMemcpy(&c->max_depth, c->depth.p, 4, hipMemcpyDeviceToHost) != hipSuccess)
     return check_hip(c, "hierarchy depth");
-  // Traversal nodes: greedy collapse level by level, subtree counts, then
-  // depth-first placement with contiguous children and the matching leaf order.
+  // Traversal nodes: surface-area-cost collapse (costs bottom-up by binary
+  // depth, then expansion level by level), subtree counts, then depth-first
+  // placement with contiguous children and the matching leaf order.
   const int64_t nn = nodes ? nodes : 1;
   const int W = lf::kWide;
-  if (!c->wtmp.ensure(sizeof(int32_t) * ((10 + W) * nn + n)))
+  if (!c->wtmp.ensure(sizeof(int32_t) * ((10 + W) * nn + n)) || !c->wdp.ensure((sizeof(float) * W + 16) * nn))
     return fail(c, LF_ENOMEM, "traversal-node scratch for n=%lld", (long long)n);
   int32_t *level = c->wtmp.as<int32_t>(), *sub_w = level + nn, *sub_l = sub_w + nn, *widx = sub_l + nn;
   int32_t *dbase = widx + nn, *lbase = dbase + nn;
   int2 *side_cnt = (int2 *)(lbase + nn);
   int32_t *slot_src = (int32_t *)(side_cnt + 2 * nn), *newpos = slot_src + W * nn;
   int32_t *n_levels_d = c->depth.as<int32_t>() + 1;
+  float *wcost = c->wdp.as<float>();
+  uint8_t *wchoice = (uint8_t *)(wcost + W * nn);
+  // binary nodes by depth for the level-by-level refit
+  std::vector<int32_t> h_depth(nodes), h_order(nodes);
+  c->h_level_off.assign(1, 0);
+  if (!c->node_order.ensure(sizeof(int32_t) * nn)) return fail(c, LF_ENOMEM, "refit order");
+  if (nodes > 0) {
+    lf::launch_node_depth(c->node_parent.as<int32_t>(), c->n_nodes, level, c->status.as<uint32_t>(), st);
+    if (hipMemcpy(h_depth.data(), level, sizeof(int32_t) * nodes, hipMemcpyDeviceToHost) != hipSuccess)
+      return check_hip(c, "refit order");
+    int32_t dmax = 0;
+    for (int64_t i = 0; i < nodes; ++i) {
+      if (h_depth[i] < 0 || h_depth[i] > 4096) return fail(c, LF_EDEVICE, "inconsistent node depth");
+      dmax = std::max(dmax, h_depth[i]);
+    }
+    c->h_level_off.assign(dmax + 2, 0);
+    for (int64_t i = 0; i < nodes; ++i) ++c->h_level_off[h_depth[i] + 1];
+    for (int32_t d = 0; d <= dmax; ++d) c->h_level_off[d + 1] += c->h_level_off[d];
+    std::vector<int64_t> fill(c->h_level_off.begin(), c->h_level_off.end() - 1);
+    for (int64_t i = 0; i < nodes; ++i) h_order[fill[h_depth[i]]++] = (int32_t)i;
+    if (hipMemcpy(c->node_order.p, h_order.data(), sizeof(int32_t) * nodes, hipMemcpyHostToDevice) != hipSuccess)
+      return check_hip(c, "refit order");
+  }
+  lf::launch_wide_cost(c->nodes.as<lf::BNode>(), c->n_nodes, c->node_order.as<int32_t>(), c->h_level_off, wcost,
+                       wchoice, c->status.as<uint32_t>(), st);
   lf::launch_fill_u32((uint32_t *)level, 0xffffffffu, nn, st);
   lf::launch_wide_roots(c->d_root.as<int32_t>(), c->d_n.as<int32_t>(), n_inst, level, st);
   for (int32_t it = 0; it <= c->max_depth && nodes > 0; ++it)
-    lf::launch_wide_level(c->nodes.as<lf::BNode>(), c->n_nodes, it, level, slot_src, n_levels_d,
+    lf::launch_wide_level(c->nodes.as<lf::BNode>(), c->n_nodes, it, wchoice, level, slot_src, n_levels_d,
                           c->status.as<uint32_t>(), st);
   lf::launch_wide_count(c->leaf_parent.as<int32_t>(), c->node_parent.as<int32_t>(), level, n, c->n_nodes,
                         c->flags.as<int32_t>(), side_cnt, sub_w, sub_l, c->status.as<uint32_t>(), st);
@@ -494,27 +520,6 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
       hipMemcpyAsync(c->d_root.p, root4.data(), 4 * n_inst, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return check_hip(c, "traversal nodes");
-  // binary nodes by depth for the level-by-level refit
-  std::vector<int32_t> h_depth(nodes), h_order(nodes);
-  c->h_level_off.assign(1, 0);
-  if (!c->node_order.ensure(sizeof(int32_t) * nn)) return fail(c, LF_ENOMEM, "refit order");
-  if (nodes > 0) {
-    lf::launch_node_depth(c->node_parent.as<int32_t>(), c->n_nodes, level, c->status.as<uint32_t>(), st);
-    if (hipMemcpy(h_depth.data(), level, sizeof(int32_t) * nodes, hipMemcpyDeviceToHost) != hipSuccess)
-      return check_hip(c, "refit order");
-    int32_t dmax = 0;
-    for (int64_t i = 0; i < nodes; ++i) {
-      if (h_depth[i] < 0 || h_depth[i] > 4096) return fail(c, LF_EDEVICE, "inconsistent node depth");
-      dmax = std::max(dmax, h_depth[i]);
-    }
-    c->h_level_off.assign(dmax + 2, 0);
-    for (int64_t i = 0; i < nodes; ++i) ++c->h_level_off[h_depth[i] + 1];
-    for (int32_t d = 0; d <= dmax; ++d) c->h_level_off[d + 1] += c->h_level_off[d];
-    std::vector<int64_t> fill(c->h_level_off.begin(), c->h_level_off.end() - 1);
-    for (int64_t i = 0; i < nodes; ++i) h_order[fill[h_depth[i]]++] = (int32_t)i;
-    if (hipMemcpy(c->node_order.p, h_order.data(), sizeof(int32_t) * nodes, hipMemcpyHostToDevice) != hipSuccess)
-      return check_hip(c, "refit order");
-  }
   lf_status s2 = refit_impl(c, dp.alpha_min, sig2);
   if (s2) return s2;
   if (hipStreamSynchronize(st) != hipSuccess) return check_hip(c, "scene build");

@@ -457,15 +457,33 @@ __global__ void k_node_depth(const int32_t *node_parent, int64_t n_nodes, int32_
 }
 
 // ---------------------------------------------------------------- wide nodes
-// The binary hierarchy is cut into traversal nodes top-down: starting from a
-// node's two children, the internal child with the largest box surface area
-// (the first of equal ones) is replaced by its two children until kWide slots
-// are filled or only leaves are left (greedy surface-area collapse); every
-// internal slot starts a node of the next level.  One launch per level.
+// The binary hierarchy is cut into traversal nodes of up to kWide slots by the
+// surface-area cost (after Ylitie, Karras and Laine 2017).  Bottom-up over the
+// binary depths, every internal node n gets C(n, i), i = 1..kWide: the least
+// cost of covering its subtree with at most i slots of the node above it, where
+// a traversal node costs kCostNode times its box area plus the cost of its own
+// kWide slots, and a surfel in a slot costs kCostLeaf times its box area:
+//   D(n, j) = min over k of C'(left, k) + C'(right, j - k)   (n opened into j slots)
+//   C(n, 1) = kCostNode A(n) + D(n, kWide)                   (n a traversal node)
+//   C(n, i) = min(C(n, i - 1), D(n, i))
+// with C'(leaf, k) = kCostLeaf A(leaf) for every k >= 1.  Top-down, one launch
+// per traversal level, each traversal node expands its recorded choices into
+// its slots; every internal slot starts a node of the next level.
 constexpr int32_t kNoSlot = -1;
+constexpr float kCostNode = 1.0f;  // a visit of one traversal node (all kWide slot tests)
+constexpr float kCostLeaf = 0.3f;  // a surfel in a slot whose box is hit (queue entry and pre-filter)
 
 __device__ __forceinline__ float side_area(const BNode &nd, int side) {
   return box_area(side ? nd.lo1 : nd.lo0, side ? nd.hi1 : nd.hi0);
+}
+
+__device__ __forceinline__ float node_area(const BNode &nd) {
+  float lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = fminf(nd.lo0[a], nd.lo1[a]);
+    hi[a] = fmaxf(nd.hi0[a], nd.hi1[a]);
+  }
+  return box_area(lo, hi);
 }
 
 __global__ void k_wide_roots(const int32_t *root, const int32_t *cnt, int n_inst, int32_t *level) {
@@ -473,48 +491,104 @@ __global__ void k_wide_roots(const int32_t *root, const int32_t *cnt, int n_inst
   if (i < n_inst && cnt[i] >= 2) level[root[i]] = 0;
 }
 
-// slots of every node of level `it`; marks their internal slots as level it+1
-__global__ void k_wide_level(const BNode *nodes, int64_t n_nodes, int32_t it, int32_t *level, int32_t *slot_src,
-                             int32_t *n_levels, uint32_t *status) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_nodes || level[b] != it) return;
-  int32_t src[kWide], code[kWide];
-  float area[kWide];
-  const BNode nb = nodes[b];
-  src[0] = (int32_t)(b << 1); code[0] = nb.c0; area[0] = side_area(nb, 0);
-  src[1] = (int32_t)(b << 1 | 1); code[1] = nb.c1; area[1] = side_area(nb, 1);
-  int m = 2;
-  while (m < kWide) {
-    int j = -1;
-    float best = -1.0f;
-    for (int q = 0; q < m; ++q)
-      if (code[q] >= 0 && area[q] > best) {
-        best = area[q];
-        j = q;
-      }
-    if (j < 0) break;
-    const int32_t x = code[j];
-    if (x >= n_nodes) {  // never taken for a consistent hierarchy
+// costs of the nodes of one binary depth (order[0..count)); deeper depths are
+// done.  cost[n * kWide + i - 1] = C(n, i); choice[n * 16 + i - 1] is the split
+// k of D(n, i) that C(n, i) takes, or 0 where it takes C(n, i - 1) (i = 1: the
+// node itself); choice[n * 16 + kWide] is the split of D(n, kWide).
+__global__ void k_wide_cost(const BNode *nodes, const int32_t *order, int64_t count, int64_t n_nodes, float *cost,
+                            uint8_t *choice, uint32_t *status) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const int32_t n = order[t];
+  const BNode nd = nodes[n];
+  float cc[2][kWide];
+  for (int side = 0; side < 2; ++side) {
+    const int32_t c = side ? nd.c1 : nd.c0;
+    if (c >= n_nodes) {  // never taken for a consistent hierarchy
       atomicOr(status, kStatusBvhCorrupt);
       return;
     }
-    const BNode nx = nodes[x];
-    src[j] = x << 1; code[j] = nx.c0; area[j] = side_area(nx, 0);
-    src[m] = x << 1 | 1; code[m] = nx.c1; area[m] = side_area(nx, 1);
-    ++m;
+    if (c < 0) {
+      const float leaf = kCostLeaf * side_area(nd, side);
+      for (int i = 0; i < kWide; ++i) cc[side][i] = leaf;
+    } else {
+      for (int i = 0; i < kWide; ++i) cc[side][i] = cost[(int64_t)c * kWide + i];
+    }
   }
+  float D[kWide + 1];
+  uint8_t Dk[kWide + 1];
+  for (int j = 2; j <= kWide; ++j) {
+    D[j] = INFINITY;
+    Dk[j] = 1;
+    for (int k = 1; k < j; ++k) {
+      const float v = cc[0][k - 1] + cc[1][j - k - 1];
+      if (v < D[j]) {
+        D[j] = v;
+        Dk[j] = (uint8_t)k;
+      }
+    }
+  }
+  float C = kCostNode * node_area(nd) + D[kWide];
+  cost[(int64_t)n * kWide] = C;
+  choice[(int64_t)n * 16] = 0;
+  for (int i = 2; i <= kWide; ++i) {
+    uint8_t ch = 0;
+    if (D[i] < C) {
+      C = D[i];
+      ch = Dk[i];
+    }
+    cost[(int64_t)n * kWide + i - 1] = C;
+    choice[(int64_t)n * 16 + i - 1] = ch;
+  }
+  choice[(int64_t)n * 16 + kWide] = Dk[kWide];
+}
+
+// slots of the traversal nodes of level it: node b is opened into D(b, kWide)
+__global__ void k_wide_level(const BNode *nodes, int64_t n_nodes, int32_t it, const uint8_t *choice, int32_t *level,
+                             int32_t *slot_src, int32_t *n_levels, uint32_t *status) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_nodes || level[b] != it) return;
+  // pending (binary node, slots) pairs whose subtree is opened into that many slots
+  int32_t pn[kWide];
+  int pj[kWide];
+  int np = 1, m = 0;
+  pn[0] = (int32_t)b;
+  pj[0] = kWide;
   bool inner = false;
-  for (int q = 0; q < kWide; ++q) {
-    slot_src[b * kWide + q] = q < m ? src[q] : kNoSlot;
-    if (q < m && code[q] >= 0) {
-      if (code[q] >= n_nodes) {
+  int32_t src[kWide];
+  while (np > 0) {
+    --np;
+    const int32_t p = pn[np];
+    const int j = pj[np];
+    const BNode nd = nodes[p];
+    const int k = choice[(int64_t)p * 16 + (p == (int32_t)b && j == kWide ? kWide : j - 1)];
+    for (int side = 0; side < 2; ++side) {
+      const int32_t c = side ? nd.c1 : nd.c0;
+      int i = side ? j - k : k;
+      if (c >= n_nodes || k < 1 || k >= j || m >= kWide) {  // never taken for a consistent hierarchy
         atomicOr(status, kStatusBvhCorrupt);
         return;
       }
-      level[code[q]] = it + 1;
-      inner = true;
+      if (c >= 0)
+        while (i > 1 && choice[(int64_t)c * 16 + i - 1] == 0) --i;
+      if (c < 0 || i == 1) {
+        src[m++] = (int32_t)(p << 1 | side);
+        if (c >= 0) {
+          level[c] = it + 1;
+          inner = true;
+        }
+      } else {
+        if (np >= kWide) {
+          atomicOr(status, kStatusBvhCorrupt);
+          return;
+        }
+        pn[np] = c;
+        pj[np] = i;
+        ++np;
+      }
     }
   }
+  for (int q = 0; q < kWide; ++q) slot_src[b * kWide + q] = q < m ? src[q] : kNoSlot;
   atomicMax(n_levels, inner ? it + 2 : it + 1);
 }
 
@@ -859,11 +933,21 @@ void launch_wide_roots(const int32_t *root, const int32_t *cnt, int n_inst, int3
   hipLaunchKernelGGL(k_wide_roots, dim3(1), dim3(64), 0, st, root, cnt, n_inst, level);
 }
 
-void launch_wide_level(const BNode *nodes, int64_t n_nodes, int32_t it, int32_t *level, int32_t *slot_src,
-                       int32_t *n_levels, uint32_t *status, hipStream_t st) {
+void launch_wide_cost(const BNode *nodes, int64_t n_nodes, const int32_t *order, const std::vector<int64_t> &level_off,
+                      float *cost, uint8_t *choice, uint32_t *status, hipStream_t st) {
+  for (int64_t d = (int64_t)level_off.size() - 2; d >= 0; --d) {
+    const int64_t cnt = level_off[d + 1] - level_off[d];
+    if (cnt > 0)
+      hipLaunchKernelGGL(k_wide_cost, dim3(blocks(cnt, 256)), dim3(256), 0, st, nodes, order + level_off[d], cnt,
+                         n_nodes, cost, choice, status);
+  }
+}
+
+void launch_wide_level(const BNode *nodes, int64_t n_nodes, int32_t it, const uint8_t *choice, int32_t *level,
+                       int32_t *slot_src, int32_t *n_levels, uint32_t *status, hipStream_t st) {
   if (n_nodes <= 0) return;
-  hipLaunchKernelGGL(k_wide_level, dim3(blocks(n_nodes, 256)), dim3(256), 0, st, nodes, n_nodes, it, level, slot_src,
-                     n_levels, status);
+  hipLaunchKernelGGL(k_wide_level, dim3(blocks(n_nodes, 256)), dim3(256), 0, st, nodes, n_nodes, it, choice, level,
+                     slot_src, n_levels, status);
 }
 
 void launch_wide_count(const int32_t *leaf_parent, const int32_t *node_parent, const int32_t *level, int64_t n,

@@ -59,7 +59,7 @@ struct lf_ctx {
   lfh::DevBuf d_first, d_n, d_root;
   lfh::DevBuf rec, filt, nodes, perm, leaf_parent, node_parent, flags, leafbox, rootbox, inst, status;
   lfh::DevBuf keys, keys2, vals2, hist, boxidx, ibounds, depth, ploc_i, ploc_f;
-  lfh::DevBuf qnodes, winfo, wtmp, wroots, node_order;
+  lfh::DevBuf qnodes, winfo, wtmp, wdp, wroots, node_order;
   std::vector<int64_t> h_level_off;  // node_order[h_level_off[d] ..): the binary internal nodes of depth d
   int64_t n_wide = 0;      // traversal nodes over all instances
   std::vector<int64_t> h_wide_off, h_wide_n;  // per instance

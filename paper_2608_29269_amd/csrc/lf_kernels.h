@@ -42,12 +42,16 @@ void launch_refit(const SurfelArrays &s, double alpha_min, double sig2, const in
                   const int32_t *leaf_parent, const int32_t *node_parent, const int32_t *order,
                   const std::vector<int64_t> &level_off, int64_t n_nodes, int n_inst, BNode *nodes, TraceRec *rec,
                   FiltRec *filt, float *leaf_box6, float *root_box6, uint32_t *status, hipStream_t st);
-// Wide traversal nodes (greedy surface-area collapse of the binary hierarchy).
+// Wide traversal nodes (surface-area-cost collapse of the binary hierarchy).
 // level[b] = -1 for every binary node first; roots of instances with >= 2 surfels get level 0
 void launch_wide_roots(const int32_t *root, const int32_t *cnt, int n_inst, int32_t *level, hipStream_t st);
+// collapse costs and choices of every binary node, deepest depth first (order / level_off as for the refit);
+// cost [n_nodes, kWide] floats, choice [n_nodes, 16] bytes
+void launch_wide_cost(const BNode *nodes, int64_t n_nodes, const int32_t *order, const std::vector<int64_t> &level_off,
+                      float *cost, uint8_t *choice, uint32_t *status, hipStream_t st);
 // slot sources [n_nodes, kWide] of the nodes of level it; *n_levels = max level + 1 (device int)
-void launch_wide_level(const BNode *nodes, int64_t n_nodes, int32_t it, int32_t *level, int32_t *slot_src,
-                       int32_t *n_levels, uint32_t *status, hipStream_t st);
+void launch_wide_level(const BNode *nodes, int64_t n_nodes, int32_t it, const uint8_t *choice, int32_t *level,
+                       int32_t *slot_src, int32_t *n_levels, uint32_t *status, hipStream_t st);
 // wide nodes and leaves in every binary subtree (flags and side_cnt [2 n_nodes] scratch)
 void launch_wide_count(const int32_t *leaf_parent, const int32_t *node_parent, const int32_t *level, int64_t n,
                        int64_t n_nodes, int32_t *flags, int2 *side_cnt, int32_t *sub_w, int32_t *sub_l,
