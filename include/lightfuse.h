@@ -70,9 +70,10 @@ typedef struct {
  * instance (background and each object, in object space): per-surfel trace
  * records, size-extended Morton codes, radix sort, a binary hierarchy by
  * parallel locally-ordered clustering of the sorted boxes (Meister and
- * Bittner 2018), cut top-down into traversal nodes of up to eight children
- * (greedy surface-area collapse) placed depth-first with contiguous
- * children, surfel records reordered to match, then the bounds and the
+ * Bittner 2018), cut into traversal nodes of up to eight children by a
+ * surface-area-cost dynamic programme (after Ylitie, Karras and Laine 2017)
+ * and placed depth-first with contiguous children, surfel records reordered
+ * to match, then the bounds and the
  * traversal nodes with child boxes quantised conservatively to 8 bits per
  * plane.  LF_EUNSUPPORTED if a hierarchy is deeper than the traversal stack. */
 lf_status lf_scene_set(lf_ctx *ctx, const lf_surfels *surfels);
