@@ -349,6 +349,8 @@ def inverse_rendering_bench(lf, tr, sc, wl, params, grads, args, n_states=3, bat
     per_bucket = {}
     tr.sync()
     tr.stats()
+    tr.profile(True)
+    tr.profile_read()
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for it in range(n_it):
@@ -375,6 +377,8 @@ def inverse_rendering_bench(lf, tr, sc, wl, params, grads, args, n_states=3, bat
         b[0] += 1
         b[1] += time.perf_counter() - t0
     dt = time.perf_counter() - t_all
+    phases = tr.profile_read()
+    tr.profile(False)
     st = tr.stats()
     with torch.no_grad():  # restore the reference materials for the legs that follow
         for k_ in mats:
@@ -384,7 +388,8 @@ def inverse_rendering_bench(lf, tr, sc, wl, params, grads, args, n_states=3, bat
             "ms_per_iteration": dt * 1e3 / n_it, "iterations_per_s": n_it / dt,
             "rays_per_s": (st["rays_primary"] + st["rays_secondary"]) / dt, "last_l1": float(loss),
             "last_tv": float(tv),
-            "ms_per_iteration_by_stage": {k_: v[1] * 1e3 / v[0] for k_, v in per_bucket.items()}}
+            "ms_per_iteration_by_stage": {k_: v[1] * 1e3 / v[0] for k_, v in per_bucket.items()},
+            "phases_ms_per_iteration": {k_: v[0] / n_it for k_, v in phases.items() if v[1]}}
 
 
 # algorithmic HBM bytes per element of each geometry objective: maps read once, gradient written once
