@@ -38,12 +38,11 @@ __device__ __forceinline__ void surfel_prep(const SurfelArrays &s, int64_t i, do
   r.rho2max = rho2max;
   if (filt) {
     FiltRec f;
-    f.v0 = make_float4((float)n.x, (float)n.y, (float)n.z, (float)r.a[0]);
-    f.v1 = make_float4((float)r.a[1], (float)r.a[2], (float)r.b[0], (float)r.b[1]);
-    f.v2 = make_float4((float)r.b[2], r.mu[0], r.mu[1], r.mu[2]);
     const bool ok = rho2max >= 0.0;
-    f.v3 = make_float4(ok ? round_up_f(rho2max) : -1.0f, ok ? round_up_f(sqrt(rho2max)) : 0.0f,
-                       round_up_f(1.0 / fmin(su, sv)), 0.0f);
+    f.v0 = make_float4((float)r.a[0], (float)r.a[1], (float)r.a[2], r.mu[0]);
+    f.v1 = make_float4((float)r.b[0], (float)r.b[1], (float)r.b[2], r.mu[1]);
+    f.v2 = make_float4(r.mu[2], ok ? round_up_f(rho2max) : -1.0f, ok ? round_up_f(sqrt(rho2max)) : 0.0f,
+                       round_up_f(1.0 / fmin(su, sv)));
     *filt = f;
   }
   if (!(rho2max >= 0.0)) {  // never valid (also NaN): empty box

@@ -42,13 +42,14 @@ struct alignas(16) TraceRec {
 };
 static_assert(sizeof(TraceRec) == 96, "TraceRec layout");
 
-// Binary32 copy of the trace record used by the pre-filter, 64 bytes:
-// v0 = (n.x, n.y, n.z, a.x), v1 = (a.y, a.z, b.x, b.y), v2 = (b.z, mu.x, mu.y, mu.z),
-// v3 = (rho2max rounded up, sqrt(rho2max) rounded up, max(|a|,|b|) rounded up, 0).
+// Binary32 copy of the trace record used by the pre-filter, 48 bytes (the
+// plane normal is recomputed from a x b, which keeps more records in cache):
+// v0 = (a.x, a.y, a.z, mu.x), v1 = (b.x, b.y, b.z, mu.y),
+// v2 = (mu.z, rho2max rounded up, sqrt(rho2max) rounded up, max(|a|,|b|) rounded up).
 struct alignas(16) FiltRec {
-  float4 v0, v1, v2, v3;
+  float4 v0, v1, v2;
 };
-static_assert(sizeof(FiltRec) == 64, "FiltRec layout");
+static_assert(sizeof(FiltRec) == 48, "FiltRec layout");
 
 // Binary BVH node holding both children's boxes (one 64-byte fetch per
 // visited node).  Child >= 0: internal node index (global); < 0: ~leaf

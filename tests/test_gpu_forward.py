@@ -335,3 +335,51 @@ def test_key_collisions_are_resolved_exactly(tracer):
     np.testing.assert_array_equal(out["hit_idx"].cpu().numpy(), ref["hit_idx"])
     for key in ("depth", "normal", "alpha"):
         assert rel_close(out[key].cpu().numpy(), ref[key], RTOL) < RTOL, key
+
+
+def test_prefilter_keeps_hits_at_the_support_edge_and_t_min(tracer):
+    """Rays aimed just inside a surfel's support edge (local radius
+    (1 - delta) rho_max, delta from 1e-6 to 1e-3) at steep to grazing angles,
+    over scales from 1e-3 to 10 and distances up to 300 scales, plus rays
+    whose hit lies just beyond t_min: the binary32 pre-filter must pass every
+    such hit, so the hit lists equal the oracle's.  A pre-filter whose error
+    bound were too small would drop some of these surfels."""
+    from tests.helpers import make_scene
+    rng = np.random.default_rng(21)
+    n = 800
+    mu = rng.uniform(-20, 20, (n, 3))
+    q = scenegen.uniform_quaternions(rng, n)
+    scale = np.exp(rng.uniform(np.log(1e-3), np.log(10.0), (n, 2)))
+    opac = rng.uniform(0.05, 1.0, n)
+    sc = make_scene(mu, q=q, scale=scale, opacity=opac)
+    mu32, q32, s32 = sc.mu.astype(np.float64), sc.q.astype(np.float64), sc.scale.astype(np.float64)
+    a32 = sc.opacity.astype(np.float64)
+    o = np.zeros((n, 3))
+    d = np.zeros((n, 3))
+    for i in range(n):
+        tu, tv, nrm = oracle.quat_to_frame(q32[i])
+        rho_max = np.sqrt(min(9.0, 2.0 * np.log(255.0 * a32[i])))
+        rho = (1.0 - 10.0 ** rng.uniform(-6, -3)) * rho_max
+        ph = rng.uniform(0, 2 * np.pi)
+        x = mu32[i] + rho * (np.cos(ph) * s32[i, 0] * tu + np.sin(ph) * s32[i, 1] * tv)
+        while True:  # |cos| between 0.02 (grazing) and 1
+            w = rng.normal(size=3)
+            w /= np.linalg.norm(w)
+            if abs(w @ nrm) >= 0.02:
+                break
+        if i % 8 == 0:
+            dist = 1e-4 * (1.0 + 10.0 ** rng.uniform(-3, -1))  # just beyond t_min
+        else:
+            dist = s32[i].min() * 10.0 ** rng.uniform(-1, 2.5)
+        o[i], d[i] = x - dist * w, w
+    o32, d32 = o.astype(np.float32), d.astype(np.float32)
+    upload_scene(tracer, sc)
+    env = scenegen.constant_env(1.0, 8, 16)
+    out = tracer.render(env=dev(env), rays=(dev(o32), dev(d32)), k=16, spp=1, seed=1, flags=1, hit_idx=True)
+    st = scenegen.State(R=np.zeros((0, 3, 3), np.float32), t=np.zeros((0, 3), np.float32), env=env, cameras=[])
+    ref = run_oracle(sc, st, o32, d32, np.arange(n), 16, 1, 1, 1)
+    amb = ambiguous(ref["margins"], include_secondary=False)
+    own = (ref["hit_idx"] == np.arange(n)[:, None]).any(1)
+    assert own.mean() > 0.8, own.mean()  # the aimed-at surfel really is hit
+    assert amb.mean() < 0.05
+    np.testing.assert_array_equal(out["hit_idx"].cpu().numpy()[~amb], ref["hit_idx"][~amb])
