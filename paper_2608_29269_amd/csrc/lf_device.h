@@ -588,12 +588,12 @@ __device__ __forceinline__ bool kinsert_tied(const SceneView &S, KBufF<K> &b, fl
 // is placed by exact keys.  Returns bit 0: inserted, bit 1: placed by exact
 // keys, bit 2: passed the binary32 pre-filter (always set), bit 3: valid hit.
 template <int K>
-__device__ __forceinline__ int exact_insert(const SceneView &S, int pos, d3 o, d3 d, double t_min, KBufF<K> &kb,
-                                            d3 wo, d3 wd) {
+__device__ __forceinline__ int exact_insert_rec(const SceneView &S, const TraceRec &rec, int pos, d3 o, d3 d,
+                                                double t_min, KBufF<K> &kb, d3 wo, d3 wd) {
   const float tk = kb.t[K - 1];
   double t;
   bool flip;
-  if (!exact_hit(S.rec[pos], o, d, t_min, t, flip)) return 4;
+  if (!exact_hit(rec, o, d, t_min, t, flip)) return 4;
   const float tf = (float)t;
   if (tf > tk) return 12;
   const uint32_t id = (uint32_t)pos | (flip ? kFlipBit : 0u);
@@ -605,6 +605,12 @@ __device__ __forceinline__ int exact_insert(const SceneView &S, int pos, d3 o, d
     return 13;
   }
   return kinsert_tied<K>(S, kb, tf, t, id, wo, wd) ? 15 : 14;
+}
+
+template <int K>
+__device__ __forceinline__ int exact_insert(const SceneView &S, int pos, d3 o, d3 d, double t_min, KBufF<K> &kb,
+                                            d3 wo, d3 wd) {
+  return exact_insert_rec<K>(S, S.rec[pos], pos, o, d, t_min, kb, wo, wd);
 }
 
 // Pre-filter, then exact test and insertion, of one surfel (bits as above; 0
@@ -630,6 +636,7 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 // counters).  Work supplies
 //   bool begin(int64_t item, d3 &o, d3 &d, const InstRec *&inst)  (false: nothing to trace)
 //   void store(int64_t item, const KBufF<K> &kb)
+//   static constexpr int kRefill; static constexpr bool kPrefetch (see the exact loop)
 // Traversal of an instance runs in rounds of two phases (after Aila and
 // Laine 2009, "while-while"): in the node phase a lane visits nodes, its hit
 // leaves join its leaf queue and its nearest hit internal child is visited
@@ -830,8 +837,20 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
         ++c_tests;
         if (prefilter(S.filt[~leaf], rf, t_min_f, tk_up)) lq[(np++) * kBlock] = leaf;
       }
+      // with Work::kPrefetch the next survivor's record is loaded while the
+      // current one is tested (few lanes take this loop at once, so its
+      // loads are exposed; worth it for secondary rays, not camera rays)
+      TraceRec rnext;
+      if (Work::kPrefetch && np > 0) rnext = S.rec[~lq[0]];
       for (int j = 0; j < np; ++j) {
-        const int r = exact_insert<K>(S, ~lq[j * kBlock], oo, dd, P.t_min, kb, o, d);
+        int r;
+        if constexpr (Work::kPrefetch) {
+          const TraceRec rcur = rnext;
+          if (j + 1 < np) rnext = S.rec[~lq[(j + 1) * kBlock]];
+          r = exact_insert_rec<K>(S, rcur, ~lq[j * kBlock], oo, dd, P.t_min, kb, o, d);
+        } else {
+          r = exact_insert<K>(S, ~lq[j * kBlock], oo, dd, P.t_min, kb, o, d);
+        }
         c_ins += r & 1;
         c_ties += (r >> 1) & 1;
         ++c_pass;

@@ -316,6 +316,7 @@ __device__ __forceinline__ int64_t primary_ray(const RenderArgs &a, int64_t item
 template <int K, bool B>
 struct PrimaryWork {
   static constexpr int kRefill = 16;  // camera rays of a wave stay alike; refill in larger groups
+  static constexpr bool kPrefetch = false;
   const RenderArgs &a;
   __device__ bool begin(int64_t item, d3 &o, d3 &d, const InstRec *&inst) const {
     const int64_t ray = primary_ray<B>(a, item);
@@ -445,6 +446,7 @@ __device__ __forceinline__ void finish_secondary(const RenderArgs &a, const Scen
 template <int K, bool B>
 struct SecondaryWork {
   static constexpr int kRefill = 8;
+  static constexpr bool kPrefetch = true;
   const RenderArgs &a;
   __device__ bool begin(int64_t item, d3 &o, d3 &w, const InstRec *&inst) const {
     const SecEntry &e = a.queue[a.order ? (uint32_t)a.order[item] : (uint32_t)item];
