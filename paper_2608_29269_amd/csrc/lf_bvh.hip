@@ -190,6 +190,68 @@ __global__ __launch_bounds__(1024) void k_rs_scan(uint32_t *a, int64_t len) {
   }
 }
 
+// Exclusive scan of a long array in three launches: tile sums, a one-block
+// scan of the sums, then each tile scanned from its offset.  Tiles of
+// SC_TILE words; a thread owns SC_ITEMS consecutive words of its tile.
+constexpr int SC_THREADS = 256;
+constexpr int SC_ITEMS = 16;
+constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_tile_sums(const uint32_t *a, int64_t len, uint32_t *sums) {
+  __shared__ uint32_t ws[SC_THREADS / 64];
+  const int64_t base = (int64_t)blockIdx.x * SC_TILE;
+  uint32_t s = 0;
+  for (int r = 0; r < SC_ITEMS; ++r) {
+    const int64_t i = base + r * SC_THREADS + threadIdx.x;
+    if (i < len) s += a[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < SC_THREADS / 64; ++w) t += ws[w];
+    sums[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_tile_apply(uint32_t *a, int64_t len, const uint32_t *offs) {
+  __shared__ uint32_t ts[SC_THREADS];
+  const int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+  uint32_t v[SC_ITEMS], s = 0;
+#pragma unroll
+  for (int r = 0; r < SC_ITEMS; ++r) {
+    v[r] = base + r < len ? a[base + r] : 0u;
+    s += v[r];
+  }
+  ts[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < SC_THREADS; off <<= 1) {
+    const uint32_t x = threadIdx.x >= (unsigned)off ? ts[threadIdx.x - off] : 0u;
+    __syncthreads();
+    ts[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint32_t run = offs[blockIdx.x] + (threadIdx.x ? ts[threadIdx.x - 1] : 0u);
+#pragma unroll
+  for (int r = 0; r < SC_ITEMS; ++r) {
+    if (base + r < len) a[base + r] = run;
+    run += v[r];
+  }
+}
+
+// exclusive scan of a[0..len) in place; sums: scratch of scan_scratch_words(len) words
+void exclusive_scan(uint32_t *a, int64_t len, uint32_t *sums, hipStream_t st) {
+  const int64_t nt = (len + SC_TILE - 1) / SC_TILE;
+  if (nt <= 1) {
+    hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, a, len);
+    return;
+  }
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nt), dim3(SC_THREADS), 0, st, (const uint32_t *)a, len, sums);
+  hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, sums, nt);
+  hipLaunchKernelGGL(k_scan_tile_apply, dim3((unsigned)nt), dim3(SC_THREADS), 0, st, a, len, (const uint32_t *)sums);
+}
+
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout,
                                                            int32_t *vout, int64_t n, int shift,
                                                            const uint32_t *offs, int nb) {
@@ -844,7 +906,10 @@ void launch_morton(const float *box6, const float *inst_bounds, const int32_t *i
                      n, kSizeLevel, keys, vals);
 }
 
-size_t radix_sort_hist_words(int64_t n) { return (size_t)256 * blocks(n > 0 ? n : 1, RS_TILE); }
+size_t radix_sort_hist_words(int64_t n) {
+  const size_t h = (size_t)256 * blocks(n > 0 ? n : 1, RS_TILE);
+  return h + h / SC_TILE + 1;  // digit counts, then the scan's tile sums
+}
 
 void radix_sort(uint64_t *keys, int32_t *vals, uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist, int64_t n,
                 hipStream_t st, int key_bits) {
@@ -856,7 +921,7 @@ void radix_sort(uint64_t *keys, int32_t *vals, uint64_t *keys_tmp, int32_t *vals
   for (int pass = 0; pass < passes; ++pass) {
     int shift = 8 * pass;
     hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, st, ka, n, shift, hist, nb);
-    hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, hist, (int64_t)256 * nb);
+    exclusive_scan(hist, (int64_t)256 * nb, hist + (int64_t)256 * nb, st);
     hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, st, ka, va, kb, vb, n, shift, hist, nb);
     uint64_t *tk = ka; ka = kb; kb = tk;
     int32_t *tv = va; va = vb; vb = tv;
