@@ -315,7 +315,7 @@ __device__ __forceinline__ int64_t primary_ray(const RenderArgs &a, int64_t item
 
 template <int K, bool B>
 struct PrimaryWork {
-  static constexpr int kRefill = 16;  // camera rays of a wave stay alike; refill in larger groups
+  static constexpr int kRefill = 24;  // camera rays of a wave stay alike; refill in larger groups
   static constexpr bool kPrefetch = false;
   const RenderArgs &a;
   __device__ bool begin(int64_t item, d3 &o, d3 &d, const InstRec *&inst) const {
