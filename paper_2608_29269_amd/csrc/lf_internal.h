@@ -10,9 +10,9 @@ namespace lf {
 
 constexpr int kBlock = 128;       // threads per block of the tracing kernels (2 wave64)
 constexpr int kWide = 8;          // children per traversal node
-constexpr int kStackL = 32;       // traversal stack entries per lane held in LDS (16 KB per block)
+constexpr int kStackL = 24;       // traversal stack entries per lane held in LDS (12 KB per block)
 constexpr int kStack = 192;       // traversal stack entries per lane; those past kStackL in private scratch
-constexpr int kLeafQ = 48;        // leaf-queue entries per lane (LDS, 24 KB per block)
+constexpr int kLeafQ = 56;        // leaf-queue entries per lane (LDS, 28 KB per block)
 constexpr int kLeafMin = 12;       // the node phase goes on while a lane that can visit nodes has fewer queued
 // Persistent traversal splits its items into kPoolParts contiguous ranges
 // with one counter each; a block starts on range blockIdx % kPoolParts, so
