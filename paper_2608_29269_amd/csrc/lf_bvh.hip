@@ -302,7 +302,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, 
 // cluster list is compacted in order; repeat until one cluster is left.
 // Node indices count down from the end of the instance's node range, so the
 // last merge (the root) gets its first index.
-constexpr int kPlocR = 32;  // window radius: 1% faster traversal than 16 with 8-wide nodes
+constexpr int kPlocR = 128;  // window radius: traversal 4% faster than with 32, build 128 instead of 84 ms at 1M
 constexpr int kPlocB = 256;
 
 __device__ __forceinline__ float box_area(const float *lo, const float *hi) {
