@@ -137,3 +137,28 @@ def test_bad_request_fails_alone_and_errors_are_reported(setup):
     tr.refit()  # allowed again once the server is gone
     ref = _alone(tr, good)
     assert np.array_equal(got["radiance"].cpu().numpy(), ref["radiance"].cpu().numpy())
+
+
+def test_served_with_sobol_samples_equals_rendered_alone(setup):
+    """The server takes the Owen-scrambled Sobol sampler (LF_FLAG_SOBOL) from
+    its configuration; a request served in a mix still equals, bit for bit,
+    the same request rendered alone with that sampler."""
+    import paper_2608_29269_amd as lf
+    tr, wl = setup
+    reqs = _requests(5, seed=3)
+    srv = lf.Server(tr, max_slots=2, tile_rays=256, batch_rays=1024, max_spp=4, max_in_flight=2,
+                    flags=lf.FLAG_SOBOL)
+    try:
+        tickets = [srv.submit(dev(q.env), q.camera, R=dev(q.R), t=dev(q.t), spp=q.spp, seed=q.seed) for q in reqs]
+        outs = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    for q, got in zip(reqs, outs):
+        ref = tr.render(dev(q.env), R=dev(q.R), t=dev(q.t), cameras=[q.camera], k=32, spp=q.spp, seed=q.seed,
+                        flags=lf.FLAG_SOBOL)
+        plain = _alone(tr, q)
+        for key in ("radiance", "depth", "normal", "alpha"):
+            a, b = got[key].cpu().numpy(), ref[key].cpu().numpy()
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (key, q.camera.w, q.camera.h, q.spp)
+        if q.spp > 1:  # the sampler is in effect
+            assert not np.array_equal(got["radiance"].cpu().numpy(), plain["radiance"].cpu().numpy())
