@@ -655,6 +655,17 @@ def roofline(phases, counts, stats, args, nr):
                 out["traffic"] = e.get("hbm_bytes_per_launch")
         except (OSError, ValueError):
             out["traffic"] = None
+    # the kernel is latency- and ALU-bound: its VALU issue fraction from the SQ counters (same digest rule)
+    sf = os.path.join(ROOT, "profiles", "sq.json")
+    if os.path.exists(sf):
+        try:
+            sj = json.load(open(sf))
+            e = sj.get("kernels", {}).get(out["kernel"])
+            if e and sj.get("source_digest") == source_digest():
+                out["valu_issue_per_wave"] = e["valu_issue_per_wave"]
+                out["valu_issue_per_simd"] = e["valu_issue_per_wave"] * e["waves_per_simd"]
+        except (OSError, ValueError, KeyError):
+            pass
     return out
 
 
