@@ -632,6 +632,7 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 // holds one ray at a time, collects its k closest valid hits over all
 // instances and stores them with wk.store; a wave refills its idle lanes from
 // the shared counter *next once Work::kRefill of them are idle (or all are),
+// taking at most its even share of `count` over the grid's waves at a time,
 // so the rays of a wave need not finish together (see kPoolParts for the
 // counters).  Work supplies
 //   bool begin(int64_t item, d3 &o, d3 &d, const InstRec *&inst)  (false: nothing to trace)
@@ -688,6 +689,11 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
   RayF rf;
   make_rayf(oo, dd, 0.0, 0.0f, 0.0f, rf);
   int cur = kDone, qn = 0;
+  // a wave takes at most its even share of the items at a time: when there are
+  // fewer items than lanes in the grid, every wave gets a few rays instead of
+  // a quarter of the waves holding 64 each, which shortens the longest wave
+  const int64_t n_waves = (int64_t)gridDim.x * (kBlock / 64);
+  const int cap = (int)min((int64_t)64, max((int64_t)1, (count + n_waves - 1) / n_waves));
   while (true) {
     // idle lanes take the next items, one counter update per wave
     if (!exhausted) {
@@ -696,17 +702,19 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
       if (n_idle >= Work::kRefill || (n_idle > 0 && !__any(live))) {
         const int leader = __ffsll((long long)idle) - 1;
         uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(next + part, (uint32_t)n_idle);
+        const int take = n_idle < cap ? n_idle : cap;
+        if (lane == leader) base = atomicAdd(next + part, (uint32_t)take);
         base = (uint32_t)__shfl((int)base, leader);
         const int64_t lo = count * part / kPoolParts, hi = count * (part + 1) / kPoolParts;
         const int64_t first = lo + (int64_t)base;
-        if (first + n_idle >= hi) {  // this range is used up: move to the next one
+        if (first + take >= hi) {  // this range is used up: move to the next one
           part = part + 1 == kPoolParts ? 0 : part + 1;
           exhausted = ++tried == kPoolParts;
         }
         if (!live) {
-          const int64_t it = first + __popcll(idle & ((1ull << lane) - 1ull));
-          if (it < hi) {
+          const int rk = __popcll(idle & ((1ull << lane) - 1ull));
+          const int64_t it = first + rk;
+          if (rk < take && it < hi) {
             item = it;
             live = wk.begin(item, o, d, S.inst);
             if (live) {

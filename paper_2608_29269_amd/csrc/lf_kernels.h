@@ -156,8 +156,11 @@ void launch_adjoint_hits(const RenderArgs &a, const GradArgs &g, hipStream_t st)
 inline int kbucket(int k) { return k <= 8 ? 8 : (k <= 16 ? 16 : (k <= 32 ? 32 : 64)); }
 
 // Blocks of a persistent launch of kernel Kern (kBlock threads): as many as
-// can be resident at once on the current device, at most one per kBlock
-// items, at least one.  The residency is looked up once per device.
+// can be resident at once on the current device, at most one per
+// kPoolItemsPerBlock items, at least one.  The residency is looked up once per
+// device.  Small launches spread thinly (8 items per wave): they are bound by
+// their longest rays, not by issue, and a wave lasts as long as its slowest lane.
+constexpr int kPoolItemsPerBlock = 16;
 template <auto Kern>
 inline unsigned pool_blocks(int64_t items) {
   static std::atomic<int> resident[64];
@@ -180,7 +183,7 @@ inline unsigned pool_blocks(int64_t items) {
     nb = cu * per;
     if (dev >= 0 && dev < 64) resident[dev].store(nb, std::memory_order_relaxed);
   }
-  const int64_t need = (items + kBlock - 1) / kBlock;
+  const int64_t need = (items + kPoolItemsPerBlock - 1) / kPoolItemsPerBlock;
   return (unsigned)(need < 1 ? 1 : (need < nb ? need : nb));
 }
 
