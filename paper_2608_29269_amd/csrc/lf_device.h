@@ -817,20 +817,20 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
       const float tk = kb.t[K - 1];
       const float tk_up = tk < INFINITY ? next_up_f(tk) : INFINITY;
       int np = 0;
-      // two records in flight per step
+      // four records in flight per step
       int j = 0;
-      for (; j + 2 <= qn; j += 2) {
-        int lv[2];
-        FiltRec fr[2];
+      for (; j + 4 <= qn; j += 4) {
+        int lv[4];
+        FiltRec fr[4];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < 4; ++u) {
           lv[u] = lq[(j + u) * kBlock];
           const bool okp = ~lv[u] < S.n_rec;
           if (!okp) atomicOr(status, kStatusBvhCorrupt);
           fr[u] = S.filt[okp ? ~lv[u] : 0];
         }
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < 4; ++u) {
           const bool okp = ~lv[u] < S.n_rec;
           c_tests += okp ? 1u : 0u;
           if (okp && prefilter(fr[u], rf, t_min_f, tk_up)) lq[(np++) * kBlock] = lv[u];
