@@ -118,6 +118,26 @@ def test_persistent_pool_small_and_ragged_counts(tracer, c2_small, n):
     _compare(out, ref, ambiguous(ref["margins"]), check_sec=True, spp=2, min_ok=0.99 if n > 100 else 0.0)
 
 
+@pytest.mark.parametrize("n", [40000, 140000])
+def test_persistent_pool_wave_shares(tracer, c2_small, n):
+    """Ray counts at which each wave of the resident grid takes a share of
+    about 20 items, and above one item per lane of the whole grid (lanes
+    refill from the pool): sampled hit lists equal the oracle's."""
+    wl = c2_small
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    cam = scenegen.sphere_camera(np.random.default_rng(n), 512, 512)
+    pix = np.sort(np.random.default_rng(n + 1).choice(cam.w * cam.h, n, replace=False))
+    o, d, _ = oracle.raygen(cam, pix)
+    out = tracer.render(**state_args(tracer, wl.scene, st), rays=(dev(o), dev(d)), k=32, spp=2, seed=4,
+                        hit_idx=True, sec_hit_idx=True)
+    sub = np.sort(np.random.default_rng(n + 2).choice(n, 2000, replace=False))
+    ref = run_oracle(wl.scene, st, o[sub], d[sub], sub, 32, 2, 4, 0)
+    got = {k: v.cpu()[sub] for k, v in out.items()}
+    _compare(got, ref, ambiguous(ref["margins"]), check_sec=True, spp=2)
+    assert (ref["alpha"] > 0).mean() > 0.2  # the sample really sees the scene
+
+
 def test_odd_camera_partial_tiles(tracer, c2_small):
     """A 37x23 camera (partial 16x8 tiles on both edges) traced through the
     tile-ordered pool equals the oracle on every pixel."""
