@@ -214,7 +214,8 @@ lf_status lf_render_backward(lf_ctx *ctx, const lf_transforms *xf, const lf_envm
 /* Scene-linear L1 objective of inverse rendering (Sec. 3.4,
  * Eq. training-objectives, data term): loss = mean |pred - target| over n
  * values; grad = sign(pred - target)/n (sign(0) = 0).  loss: device scalar
- * (binary64 sum in a fixed order); grad: device [n] or NULL. */
+ * (binary64 sum in a fixed order; 0 for n = 0, where pred and target may be
+ * NULL); grad: device [n] or NULL.  LF_EINVAL for n < 0 or a missing pointer. */
 lf_status lf_l1_loss(lf_ctx *ctx, const float *pred, const float *target, int64_t n, float *loss, float *grad);
 
 /* ---- Geometry-refinement objectives (Sec. 3.1 and 3.2).  Common contract:

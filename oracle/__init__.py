@@ -76,52 +76,59 @@ def lib():
         if not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
-        L = C.CDLL(LIB_PATH)
-        L.ors_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), C.POINTER(_Params), C.POINTER(_Outputs), C.c_int]
-        L.ors_render.restype = C.c_int
-        L.ors_frozen_eval.argtypes = [C.POINTER(_Scene), C.POINTER(_Scene), C.POINTER(_Rays), C.POINTER(_Params),
-                                      C.POINTER(_Outputs), C.c_int]
-        L.ors_frozen_eval.restype = C.c_int
-        L.ors_backward.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), C.POINTER(_Params), C.POINTER(_Upstream),
-                                   C.POINTER(_Grads), C.c_int]
-        L.ors_backward.restype = C.c_int
-        L.ors_raygen.argtypes = [_fp, C.c_float, C.c_int32, C.c_int32, _i64p, C.c_int64, _fp, _fp]
-        L.ors_raygen.restype = None
-        L.ors_tan_half.argtypes = [C.c_float]
-        L.ors_tan_half.restype = C.c_float
-        L.ors_splitmix64.argtypes = [C.c_uint64]
-        L.ors_splitmix64.restype = C.c_uint64
-        L.ors_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32]
-        L.ors_uniform.restype = C.c_double
-        L.ors_sobol.argtypes = [C.c_uint32, C.c_uint32]
-        L.ors_sobol.restype = C.c_uint32
-        L.ors_sobol_poly.argtypes = [C.c_uint32, C.POINTER(C.c_int32), C.POINTER(C.c_uint32)]
-        L.ors_sobol_poly.restype = None
-        L.ors_owen_scramble.argtypes = [C.c_uint32, C.c_uint32]
-        L.ors_owen_scramble.restype = C.c_uint32
-        L.ors_sobol_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32]
-        L.ors_sobol_uniform.restype = C.c_double
-        L.ors_quat_to_frame.argtypes = [_dp, _dp, _dp, _dp]
-        L.ors_onb.argtypes = [_dp, _dp, _dp]
-        L.ors_brdf.argtypes = [_dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_uint32, _dp]
-        L.ors_ggx_D.argtypes = [C.c_double, C.c_double]
-        L.ors_ggx_D.restype = C.c_double
-        L.ors_smith_G1.argtypes = [C.c_double, C.c_double]
-        L.ors_smith_G1.restype = C.c_double
-        L.ors_q_spec.argtypes = [_dp, C.c_double, C.c_uint32]
-        L.ors_q_spec.restype = C.c_double
-        L.ors_pdf_bsdf.argtypes = [_dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_uint32]
-        L.ors_pdf_bsdf.restype = C.c_double
-        L.ors_sample_bsdf.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_uint32, C.c_double, C.c_double,
-                                      C.c_double, _dp]
-        L.ors_sample_bsdf.restype = C.c_int
-        L.ors_env_pdf.argtypes = [C.POINTER(_Scene), _dp]
-        L.ors_env_pdf.restype = C.c_double
-        L.ors_env_sample.argtypes = [C.POINTER(_Scene), C.c_double, C.c_double, _dp]
-        L.ors_env_sample.restype = C.c_double
-        L.ors_env_lookup.argtypes = [C.POINTER(_Scene), _dp, _dp]
-        _lib = L
+        _lib = bind(LIB_PATH)
     return _lib
+
+
+def bind(path: str):
+    """Loads an oracle build at `path` and declares its C signatures (the
+    tests also bind deliberately broken copies to show that the pins catch
+    them)."""
+    L = C.CDLL(path)
+    L.ors_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), C.POINTER(_Params), C.POINTER(_Outputs), C.c_int]
+    L.ors_render.restype = C.c_int
+    L.ors_frozen_eval.argtypes = [C.POINTER(_Scene), C.POINTER(_Scene), C.POINTER(_Rays), C.POINTER(_Params),
+                                  C.POINTER(_Outputs), C.c_int]
+    L.ors_frozen_eval.restype = C.c_int
+    L.ors_backward.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), C.POINTER(_Params), C.POINTER(_Upstream),
+                               C.POINTER(_Grads), C.c_int]
+    L.ors_backward.restype = C.c_int
+    L.ors_raygen.argtypes = [_fp, C.c_float, C.c_int32, C.c_int32, _i64p, C.c_int64, _fp, _fp]
+    L.ors_raygen.restype = None
+    L.ors_tan_half.argtypes = [C.c_float]
+    L.ors_tan_half.restype = C.c_float
+    L.ors_splitmix64.argtypes = [C.c_uint64]
+    L.ors_splitmix64.restype = C.c_uint64
+    L.ors_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32]
+    L.ors_uniform.restype = C.c_double
+    L.ors_sobol.argtypes = [C.c_uint32, C.c_uint32]
+    L.ors_sobol.restype = C.c_uint32
+    L.ors_sobol_poly.argtypes = [C.c_uint32, C.POINTER(C.c_int32), C.POINTER(C.c_uint32)]
+    L.ors_sobol_poly.restype = None
+    L.ors_owen_scramble.argtypes = [C.c_uint32, C.c_uint32]
+    L.ors_owen_scramble.restype = C.c_uint32
+    L.ors_sobol_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32]
+    L.ors_sobol_uniform.restype = C.c_double
+    L.ors_quat_to_frame.argtypes = [_dp, _dp, _dp, _dp]
+    L.ors_onb.argtypes = [_dp, _dp, _dp]
+    L.ors_brdf.argtypes = [_dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_uint32, _dp]
+    L.ors_ggx_D.argtypes = [C.c_double, C.c_double]
+    L.ors_ggx_D.restype = C.c_double
+    L.ors_smith_G1.argtypes = [C.c_double, C.c_double]
+    L.ors_smith_G1.restype = C.c_double
+    L.ors_q_spec.argtypes = [_dp, C.c_double, C.c_uint32]
+    L.ors_q_spec.restype = C.c_double
+    L.ors_pdf_bsdf.argtypes = [_dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_uint32]
+    L.ors_pdf_bsdf.restype = C.c_double
+    L.ors_sample_bsdf.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_uint32, C.c_double, C.c_double,
+                                  C.c_double, _dp]
+    L.ors_sample_bsdf.restype = C.c_int
+    L.ors_env_pdf.argtypes = [C.POINTER(_Scene), _dp]
+    L.ors_env_pdf.restype = C.c_double
+    L.ors_env_sample.argtypes = [C.POINTER(_Scene), C.c_double, C.c_double, _dp]
+    L.ors_env_sample.restype = C.c_double
+    L.ors_env_lookup.argtypes = [C.POINTER(_Scene), _dp, _dp]
+    return L
 
 
 def _d(a):

@@ -13,14 +13,15 @@ SRC = os.path.join(HERE, "lf_oracle.c")
 LIB = os.path.join(HERE, "liblf_oracle.so")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, src: str = SRC, out: str = LIB) -> str:
+    """Compiles `src` (default: the oracle) into the shared library `out`."""
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wno-unused-function", SRC, "-o", LIB + ".tmp", "-lm"]
+           "-fno-fast-math", "-Wall", "-Wno-unused-function", "-I", HERE, src, "-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -5,6 +5,7 @@ never by the GPU library or its binding.  Every function is the plain
 definition of one objective written out in NumPy float64, with the gradient
 by the chain rule; nothing is blocked, fused or reordered.
 
+  l1_loss            Sec. 3.4, Eq. training-objectives (scene-linear HDR data term)
   coverage_loss      Sec. 3.1, Eq. alpha-coverage
   scale_loss         Sec. 3.1, Eq. scale-regularization
   depth_loss         Sec. 3.2, Eq. reconstruction-depth
@@ -15,6 +16,8 @@ by the chain rule; nothing is blocked, fused or reordered.
 
 Readings of points the paper leaves open:
   * sign(0) = 0 in every L1 gradient;
+  * the data term is the mean over every pixel and colour channel of the
+    absolute difference of the linear (not tonemapped) radiances;
   * the infinity norm of the scale pair is max(|s_u|, |s_v|); its gradient
     goes to the first component attaining the maximum;
   * the confidence enters the depth objective as |C| (the L1 norm of C*x);
@@ -36,6 +39,20 @@ import numpy as np
 
 def _f64(a):
     return np.asarray(a, dtype=np.float64)
+
+
+def l1_loss(pred, target):
+    """L1^HDR = (1/n) * sum |L - L*| over all n = pixels x channels values of
+    the scene-linear radiance (Sec. 3.4, Eq. training-objectives, data term);
+    returns (loss, dL/dpred) with the gradient sign(L - L*)/n."""
+    p, t = _f64(pred).reshape(-1), _f64(target).reshape(-1)
+    if p.shape != t.shape:
+        raise ValueError("pred and target sizes differ")
+    n = p.size
+    if n == 0:
+        return 0.0, np.zeros(0)
+    r = p - t
+    return float(np.abs(r).sum() / n), np.sign(r) / n
 
 
 def coverage_loss(alpha):

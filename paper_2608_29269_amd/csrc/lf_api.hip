@@ -667,7 +667,7 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
 
 lf_status lf_l1_loss(lf_ctx *c, const float *pred, const float *target, int64_t n, float *loss, float *grad) {
   if (!c) return LF_EINVAL;
-  if (!pred || !target || !loss || n < 0) return fail(c, LF_EINVAL, "invalid loss arguments");
+  if (!loss || n < 0 || (n > 0 && (!pred || !target))) return fail(c, LF_EINVAL, "invalid loss arguments");
   set_device(c);
   if (!c->lossbuf.ensure(lf::kLossPartDoubles * sizeof(double))) return fail(c, LF_ENOMEM, "loss scratch");
   Phase ph(c, 13);

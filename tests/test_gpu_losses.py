@@ -36,6 +36,25 @@ def _close_grad(gpu, ref, rtol=1e-6):
     assert np.all(np.abs(a - ref) <= rtol * np.abs(ref) + floor + 1e-30), np.abs(a - ref).max()
 
 
+@pytest.mark.parametrize("n", SIZES + (3 * 1024 * 1024,))
+def test_l1_loss(tracer, n):
+    # the scene-linear data term (Sec. 3.4, Eq. training-objectives) at the
+    # sizes of a ragged launch and of a 1024x1024 RGB image, with exact ties
+    rng = np.random.default_rng(400 + n)
+    t = np.exp(rng.normal(0, 1.5, n)).astype(np.float32)  # HDR magnitudes
+    p = (t * np.exp(rng.normal(0, 0.2, n))).astype(np.float32)
+    p[: n // 9] = t[: n // 9]  # exact pixels: sign(0) = 0
+    loss, g = tracer.l1_loss(dev(p), dev(t))
+    ref, gref = OL.l1_loss(p, t)
+    _close_loss(loss, ref)
+    a = g.cpu().numpy().astype(np.float64)
+    # sign(r)/n rounded once to binary32: equal to the reference within half an ulp
+    assert np.array_equal(np.sign(a), np.sign(gref))
+    assert np.all(np.abs(a - gref) <= 2.0 ** -24 * np.abs(gref)), np.abs(a - gref).max()
+    lossonly, none = tracer.l1_loss(dev(p), dev(t), want_grad=False)
+    assert none is None and float(lossonly) == float(loss)
+
+
 @pytest.mark.parametrize("n", SIZES)
 def test_coverage_loss(tracer, n):
     rng = np.random.default_rng(n)

@@ -29,6 +29,41 @@ def _pinhole(h, w, fov_deg=50.0, eye=(0.3, -0.2, 4.0)):
     return o.reshape(-1, 3), d.reshape(-1, 3), r, (2 * th * w / h / w, -2 * th / h)
 
 
+# -- scene-linear L1 data term (Sec. 3.4, Eq. training-objectives) ------------
+
+def test_l1_closed_forms():
+    # a constant offset c on every value: loss |c|, gradient sign(c)/n
+    t = np.random.default_rng(1).uniform(0, 5, (10, 3))
+    for c in (0.75, -2.5):
+        loss, g = OL.l1_loss(t + c, t)
+        assert loss == pytest.approx(abs(c), rel=1e-13)
+        assert np.array_equal(g, np.full(30, np.sign(c) / 30))
+    # the mean runs over pixels x channels: one channel of one pixel off by d
+    p = t.copy()
+    p[4, 1] += 3.0
+    loss, g = OL.l1_loss(p, t)
+    assert loss == pytest.approx(3.0 / 30, rel=1e-13)
+    assert g[4 * 3 + 1] == 1.0 / 30 and np.count_nonzero(g) == 1
+    # exact ties: sign(0) = 0
+    loss, g = OL.l1_loss(t, t)
+    assert loss == 0.0 and not g.any()
+    assert OL.l1_loss(np.zeros(0), np.zeros(0))[0] == 0.0
+    # HDR values are not tonemapped: the loss is linear in a common scale
+    q = np.random.default_rng(2).uniform(0, 1, 30)
+    assert OL.l1_loss(1e3 * q, 1e3 * t)[0] == pytest.approx(1e3 * OL.l1_loss(q, t)[0], rel=1e-13)
+    with pytest.raises(ValueError):
+        OL.l1_loss(np.zeros(3), np.zeros(4))
+
+
+def test_l1_gradient_matches_finite_differences():
+    rng = np.random.default_rng(3)
+    t = rng.uniform(0, 4, 50)
+    p = t + rng.choice([-1.0, 1.0], 50) * rng.uniform(0.1, 1.0, 50)  # every residual away from the kink
+    _, g = OL.l1_loss(p, t)
+    for i in (0, 17, 49):
+        assert g[i] == pytest.approx(_fd(lambda v: OL.l1_loss(v, t)[0], p, i), rel=1e-7)
+
+
 # -- coverage (Eq. alpha-coverage) -------------------------------------------
 
 def test_coverage_closed_forms():
