@@ -276,7 +276,8 @@ typedef struct {
   int64_t n_surfels;
   int64_t n_nodes;      /* internal nodes over all instances */
   int32_t max_depth;    /* deepest leaf (root = depth 0) */
-  int32_t stack_size;   /* traversal stack entries per ray */
+  int32_t stack_size;   /* traversal stack entries per ray (one per level above the current node: the
+                           scene set fails with LF_EUNSUPPORTED if wide_levels - 1 exceeds it) */
   int64_t n_wide_nodes; /* traversal nodes over all instances */
   int32_t wide_levels;  /* levels of the deepest traversal hierarchy */
   int32_t node_width;   /* children per traversal node */
@@ -317,8 +318,10 @@ lf_status lf_stats_get(lf_ctx *ctx, lf_render_stats *stats);
  * whose binary32 distance key equalled one already held, placed by exact
  * FP64 keys, [10] primary and [11] secondary surfel tests that passed the
  * binary32 pre-filter, [12] primary and [13] secondary valid hits found
- * (support and threshold met, before truncation to k). */
-#define LF_NUM_COUNTERS 14
+ * (support and threshold met, before truncation to k), [14] primary and
+ * [15] secondary traversal stack pushes, [16] primary and [17] secondary
+ * deepest traversal stack reached (a maximum, not a sum). */
+#define LF_NUM_COUNTERS 18
 lf_status lf_trace_counters(lf_ctx *ctx, uint64_t *counters /*[LF_NUM_COUNTERS]*/);
 
 /* Per-phase device timers.  When enabled, every phase below is bracketed by

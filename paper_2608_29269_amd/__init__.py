@@ -296,11 +296,11 @@ class Tracer:
         return dict(rays_primary=st.rays_primary, rays_secondary=st.rays_secondary)
 
     def trace_counters(self) -> dict:
-        c = (C.c_uint64 * 14)()
+        c = (C.c_uint64 * _lib.NUM_COUNTERS)()
         self._chk(self.L.lf_trace_counters(self.ctx, c))
         keys = ("rays", "nodes", "tests", "inserts")
         p, s_ = dict(zip(keys, c[:4])), dict(zip(keys, c[4:8]))
-        for i, name in enumerate(("ties", "prefilter_pass", "valid_hits")):
+        for i, name in enumerate(("ties", "prefilter_pass", "valid_hits", "stack_pushes", "stack_deepest")):
             p[name], s_[name] = c[8 + 2 * i], c[9 + 2 * i]
         return {"primary": p, "secondary": s_}
 

@@ -529,10 +529,14 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
     lf::launch_fill_u32(c->status.as<uint32_t>(), 0u, 1, st);
     return fail(c, LF_EDEVICE, "hierarchy build produced an out-of-range index");
   }
-  // a traversal step pushes at most kWide - 1 entries per level
-  if ((int64_t)(lf::kWide - 1) * c->wide_levels > lf::kStack)
-    return fail(c, LF_EUNSUPPORTED, "%d node levels need more than the traversal stack (%d)", c->wide_levels,
-                lf::kStack);
+  // the traversal stack holds one entry per level above the current node,
+  // naming a node by 24 bits
+  if (c->wide_levels - 1 > lf::kStackL)
+    return fail(c, LF_EUNSUPPORTED, "%d node levels need more than the traversal stack (%d entries)",
+                c->wide_levels, lf::kStackL);
+  if (c->n_wide >= lf::kMaxWideNodes)
+    return fail(c, LF_EUNSUPPORTED, "%lld traversal nodes exceed the stack encoding (%d)", (long long)c->n_wide,
+                lf::kMaxWideNodes);
   c->has_scene = true;
   return check_hip(c, "scene build");
 }
@@ -835,7 +839,7 @@ lf_status lf_scene_get_info(lf_ctx *c, lf_scene_info *info) {
   info->n_surfels = c->s.n;
   info->n_nodes = c->n_nodes;
   info->max_depth = c->max_depth;
-  info->stack_size = lf::kStack;
+  info->stack_size = lf::kStackL;
   info->n_wide_nodes = c->n_wide;
   info->wide_levels = c->wide_levels;
   info->node_width = lf::kWide;

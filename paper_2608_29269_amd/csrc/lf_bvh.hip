@@ -708,27 +708,32 @@ __global__ void k_wide_assign(const BNode *nodes, int64_t n_nodes, int64_t n, in
     atomicOr(status, kStatusBvhCorrupt);
     return;
   }
+  // The occupied slots, internal children first (a stable partition of the
+  // collapse's slot order): internal slot j then holds node child_base + j
+  // and leaf slot j leaf leaf_base + j - #internal, and the traversal stack
+  // can name a node's unvisited internal children by a mask of slots.
   WideInfo wi;
-  int32_t code[kWide];
+  int32_t code[kWide], srcs[kWide];
   int m = 0, n_int = 0;
-  wi.imask = 0;
-  for (int q = 0; q < kWide; ++q) {
-    const int32_t sr = slot_src[b * kWide + q];
-    wi.src[q] = sr;
-    code[q] = 0;
-    if (sr == kNoSlot) continue;
-    if ((sr >> 1) >= n_nodes || sr < 0) {
-      atomicOr(status, kStatusBvhCorrupt);
-      return;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int q = 0; q < kWide; ++q) {
+      const int32_t sr = slot_src[b * kWide + q];
+      if (sr == kNoSlot) continue;
+      if ((sr >> 1) >= n_nodes || sr < 0) {
+        atomicOr(status, kStatusBvhCorrupt);
+        return;
+      }
+      const BNode &nd = nodes[sr >> 1];
+      const int32_t c = (sr & 1) ? nd.c1 : nd.c0;
+      if ((c >= 0) != (pass == 0)) continue;
+      srcs[m] = sr;
+      code[m] = c;
+      ++m;
+      n_int += c >= 0;
     }
-    const BNode &nd = nodes[sr >> 1];
-    code[q] = (sr & 1) ? nd.c1 : nd.c0;
-    if (code[q] >= 0) {
-      wi.imask |= 1u << q;
-      ++n_int;
-    }
-    m = q + 1;
   }
+  for (int q = 0; q < kWide; ++q) wi.src[q] = q < m ? srcs[q] : kNoSlot;
+  wi.imask = (1u << n_int) - 1u;
   int32_t dnext = db + n_int, lnext = lb + (m - n_int);
   int ki = 0, kl = 0;
   for (int q = 0; q < m; ++q) {

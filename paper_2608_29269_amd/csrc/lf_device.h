@@ -644,10 +644,13 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 // next (the others are pushed), while some lane that can still visit nodes
 // has fewer than kLeafMin leaves queued; a lane pauses while its queue could
 // not take a whole node's leaves.  The leaf phase then tests every queued
-// leaf.  stk points at
-// this lane's first LDS stack slot (stride kBlock, kStackL entries; deeper
-// entries in private scratch; internal nodes only) and lq at its first
-// leaf-queue slot (stride kBlock, kLeafQ entries).  Every lane leaves once
+// leaf.  stk points at this lane's first LDS stack slot (stride kBlock,
+// kStackL entries) and lq at its first leaf-queue slot (stride kBlock,
+// kLeafQ entries).  A node's internal children occupy its first slots, so a
+// stack entry names all the hit internal children of one visited node that
+// are still to be visited: (child_base << 8) | slot mask.  The stack thus
+// holds at most one entry per level above the current node, and the build
+// guarantees that the hierarchy is shallow enough.  Every lane leaves once
 // the pool is empty and its last ray is stored.
 
 template <int K, class Work>
@@ -658,7 +661,8 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
   const float t_min_f = round_down_f(P.t_min);
   const float tlo = (float)(0.5 * P.t_min);
   const int lane = (int)(threadIdx.x & 63u);
-  uint32_t c_rays = 0, c_nodes = 0, c_tests = 0, c_ins = 0, c_ties = 0, c_pass = 0, c_hits = 0;
+  uint32_t c_rays = 0, c_nodes = 0, c_tests = 0, c_ins = 0, c_ties = 0, c_pass = 0, c_hits = 0, c_push = 0;
+  int c_deep = 0;
   auto count_test = [&](int r) {
     c_ins += r & 1;
     c_ties += (r >> 1) & 1;
@@ -666,16 +670,15 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
     c_hits += r >> 3;
     ++c_tests;
   };
-  int spill[kStack - kStackL];
   int sp = 0;
-  auto push = [&](int v) {
-    if (sp < kStackL) stk[sp * kBlock] = v;
-    else spill[sp - kStackL] = v;
-    ++sp;
-  };
+  // next node to visit from the top entry: its lowest remaining slot; the
+  // entry goes once its mask is empty
   auto pop = [&]() -> int {
-    --sp;
-    return sp < kStackL ? stk[sp * kBlock] : spill[sp - kStackL];
+    int *e = stk + (sp - 1) * kBlock;
+    const uint32_t v = (uint32_t)*e, m = v & 0xffu, rest = m & (m - 1u);
+    if (rest) *e = (int)((v & ~0xffu) | rest);
+    else --sp;
+    return (int)(v >> 8) + __builtin_ctz(m);
   };
   SceneView S = S0;
   KBufF<K> kb;
@@ -783,21 +786,15 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
       uint32_t ih, lh, im;
       int cbase, lbase;
       visit_node(S.nodes + cur, rf, tlo, thi, ts, ih, lh, im, cbase, lbase);
-      // hit leaves join the queue, in slot order
-      for (uint32_t m = lh; m; m &= m - 1u) {
-        const int j = __builtin_ctz(m);
-        lq[(qn++) * kBlock] = ~(lbase + j - __builtin_popcount(im & ((1u << j) - 1u)));
-      }
+      // hit leaves join the queue, in slot order (leaf slots follow the
+      // node's internal ones)
+      const int leaf0 = lbase - __builtin_popcount(im);
+      for (uint32_t m = lh; m; m &= m - 1u) lq[(qn++) * kBlock] = ~(leaf0 + __builtin_ctz(m));
       if (ih == 0) {
         cur = sp ? pop() : kDone;
         continue;
       }
-      if (sp + __builtin_popcount(ih) - 1 > kStack) {
-        atomicOr(status, kStatusOverflow);
-        cur = kDone;
-        continue;
-      }
-      // the nearest hit internal child next, the others onto the stack
+      // the nearest hit internal child next, the others onto the stack as one entry
       float best = INFINITY;
       int bj = 0;
 #pragma unroll
@@ -806,9 +803,18 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
           best = ts[j];
           bj = j;
         }
-      for (uint32_t m = ih & ~(1u << bj); m; m &= m - 1u)
-        push(cbase + __builtin_popcount(im & ((1u << __builtin_ctz(m)) - 1u)));
-      cur = cbase + __builtin_popcount(im & ((1u << bj) - 1u));
+      const uint32_t rest = ih & ~(1u << bj);
+      if (rest) {
+        if (sp >= kStackL) {  // never taken for a hierarchy the build accepted
+          atomicOr(status, kStatusOverflow);
+          cur = kDone;
+          continue;
+        }
+        stk[(sp++) * kBlock] = (int)(((uint32_t)cbase << 8) | rest);
+        ++c_push;
+        c_deep = sp > c_deep ? sp : c_deep;
+      }
+      cur = cbase + bj;
     }
     // the leaf phase runs at a raised wave priority: its burst of independent
     // record loads then issues ahead of the other wave's node-phase arithmetic
@@ -852,21 +858,26 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
       // with Work::kPrefetch the next survivor's record is loaded while the
       // current one is tested (few lanes take this loop at once, so its
       // loads are exposed; worth it for secondary rays, not camera rays)
-      TraceRec rnext;
-      if (Work::kPrefetch && np > 0) rnext = S.rec[~lq[0]];
-      for (int j = 0; j < np; ++j) {
-        int r;
-        if constexpr (Work::kPrefetch) {
-          const TraceRec rcur = rnext;
-          if (j + 1 < np) rnext = S.rec[~lq[(j + 1) * kBlock]];
-          r = exact_insert_rec<K>(S, rcur, ~lq[j * kBlock], oo, dd, P.t_min, kb, o, d);
-        } else {
-          r = exact_insert<K>(S, ~lq[j * kBlock], oo, dd, P.t_min, kb, o, d);
-        }
+      // (the prefetched record lives only inside this block: a record held
+      // over from an earlier round would stay live across the node phase
+      // and be spilled to scratch there)
+      auto count_exact = [&](int r) {
         c_ins += r & 1;
         c_ties += (r >> 1) & 1;
         ++c_pass;
         c_hits += r >> 3;
+      };
+      if constexpr (Work::kPrefetch) {
+        if (np > 0) {
+          TraceRec rnext = S.rec[~lq[0]];
+          for (int j = 0; j < np; ++j) {
+            const TraceRec rcur = rnext;
+            if (j + 1 < np) rnext = S.rec[~lq[(j + 1) * kBlock]];
+            count_exact(exact_insert_rec<K>(S, rcur, ~lq[j * kBlock], oo, dd, P.t_min, kb, o, d));
+          }
+        }
+      } else {
+        for (int j = 0; j < np; ++j) count_exact(exact_insert<K>(S, ~lq[j * kBlock], oo, dd, P.t_min, kb, o, d));
       }
     }
     __builtin_amdgcn_s_setprio(0);
@@ -880,6 +891,8 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
     atomicAdd(P.counters + 8 + counter_base / 4, (unsigned long long)c_ties);
     atomicAdd(P.counters + 10 + counter_base / 4, (unsigned long long)c_pass);
     atomicAdd(P.counters + 12 + counter_base / 4, (unsigned long long)c_hits);
+    atomicAdd(P.counters + 14 + counter_base / 4, (unsigned long long)c_push);
+    atomicMax(P.counters + 16 + counter_base / 4, (unsigned long long)c_deep);
   }
 }
 

@@ -10,8 +10,9 @@ namespace lf {
 
 constexpr int kBlock = 128;       // threads per block of the tracing kernels (2 wave64)
 constexpr int kWide = 8;          // children per traversal node
-constexpr int kStackL = 24;       // traversal stack entries per lane held in LDS (12 KB per block)
-constexpr int kStack = 192;       // traversal stack entries per lane; those past kStackL in private scratch
+constexpr int kStackL = 24;       // traversal stack entries per lane, in LDS (12 KB per block): one per
+                                  // level above the current node, so hierarchies of up to kStackL + 1 levels
+constexpr int kMaxWideNodes = 1 << 24;  // a stack entry holds a node index in 24 bits
 constexpr int kLeafQ = 56;        // leaf-queue entries per lane (LDS, 28 KB per block)
 constexpr int kLeafMin = 12;       // the node phase goes on while a lane that can visit nodes has fewer queued
 // Persistent traversal splits its items into kPoolParts contiguous ranges
@@ -68,14 +69,14 @@ static_assert(sizeof(BNode) == 64, "BNode layout");
 // binary32.  The build picks every lower code so that this value is at or
 // below the child's lower bound and every upper code so that it is at or
 // above its upper bound, so a decoded box always contains the box it stands
-// for.  Slots 0..m-1 are occupied; internal children are stored contiguously
-// from child_base and leaf children (surfel positions) from leaf_base, both
-// in slot order, so slot i's child is child_base + (internal slots below i)
-// or leaf_base + (leaf slots below i).  80 bytes for kWide = 8.
+// for.  Slots 0..m-1 are occupied, internal children first: slot i < n_int
+// (n_int = popcount(imask), imask = (1 << n_int) - 1) holds node
+// child_base + i, slot i >= n_int holds leaf (surfel position)
+// leaf_base + i - n_int.  80 bytes for kWide = 8.
 struct alignas(16) QNode {
   float p[3];
   int8_t e[3];
-  uint8_t imask;          // bit i: slot i holds an internal node
+  uint8_t imask;          // bit i: slot i holds an internal node (the first slots)
   int32_t child_base;
   int32_t leaf_base;
   uint32_t vmask;         // bit i: slot i holds a child with a non-empty box
@@ -124,7 +125,7 @@ struct TraceParams {
   uint64_t seed;
   double alpha_min, alpha_cap, sig2, eps, t_min, sec_off;
   uint32_t flags;
-  unsigned long long *counters;  // [8] traversal counters when LF_FLAG_COUNT is set
+  unsigned long long *counters;  // [LF_NUM_COUNTERS] traversal counters when LF_FLAG_COUNT is set
 };
 
 struct EnvView {

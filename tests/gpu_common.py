@@ -63,3 +63,27 @@ def rel_close(gpu, ref, rtol, floor_frac=1e-3):
     floor = floor_frac * max(float(np.abs(ref).mean()), 1e-30)
     err = np.abs(gpu - ref) / np.maximum(np.abs(ref), floor)
     return float(err.max()) if err.size else 0.0
+
+
+GRAD_TOL = 1e-3  # relative, norm-wise per tensor and element-wise with a floor of 1e-3 * max|ref|
+
+
+def grad_check(g_gpu, g_ref, name, tol=GRAD_TOL, nonzero=False):
+    """Gradient parity: |a - b| <= tol |b| norm-wise, and element-wise
+    |a_i - b_i| <= tol * max(|b_i|, 1e-3 max|b|).  Prints both errors and
+    the worst element."""
+    a = np.asarray(g_gpu, np.float64).ravel()
+    b = np.asarray(g_ref, np.float64).ravel()
+    nb = np.linalg.norm(b)
+    if nonzero:
+        assert nb > 0, name
+    if nb == 0:
+        assert np.abs(a).max(initial=0.0) == 0, name
+        return
+    floor = 1e-3 * np.abs(b).max()
+    err = np.abs(a - b) / np.maximum(np.abs(b), floor)
+    i = int(np.argmax(err))
+    print(f"{name}: norm-wise {np.linalg.norm(a - b) / nb:.2e}, element-wise {err.max():.2e} "
+          f"(element {i}: gpu {a[i]:.6e} ref {b[i]:.6e}, max|ref| {np.abs(b).max():.3e})", flush=True)
+    assert np.linalg.norm(a - b) <= tol * nb, (name, np.linalg.norm(a - b) / nb)
+    assert err.max() <= tol, (name, err.max(), i)

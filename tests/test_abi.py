@@ -107,3 +107,13 @@ def test_server_null_paths_and_defaults(lib):
     assert (cfg.max_slots, cfg.tile_rays, cfg.batch_rays, cfg.max_spp) == (16, 65536, 1048576, 4)
     assert cfg.hbm_budget_bytes == 16 << 30 and cfg.tile_rays % 128 == 0 and cfg.batch_rays % 128 == 0
     assert cfg.params.k == 32 and cfg.params.alpha_min == 1.0 / 255.0
+
+
+def test_binding_constants_match_the_header():
+    from paper_2608_29269_amd import _lib
+    src = open(HEADER).read()
+    assert int(re.search(r"#define LF_NUM_COUNTERS (\d+)", src).group(1)) == _lib.NUM_COUNTERS
+    for name in ("NO_SECONDARY", "NO_BACKGROUND", "BSDF_ONLY", "DIFFUSE_ONLY", "BRUTE_FORCE", "COUNT", "UNSORTED",
+                 "NEE", "SOBOL"):
+        m = re.search(r"#define LF_FLAG_%s\s+\(1u << (\d+)\)" % name, src)
+        assert m and getattr(_lib, "FLAG_" + name) == 1 << int(m.group(1)), name

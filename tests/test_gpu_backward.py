@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import scenegen
-from tests.gpu_common import ambiguous, dev, state_args, upload_scene
+from tests.gpu_common import grad_check, ambiguous, dev, state_args, upload_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -21,25 +21,20 @@ def tracer():
 
 
 def _grad_check(g_gpu, g_ref, name):
-    a = np.asarray(g_gpu, np.float64).ravel()
-    b = np.asarray(g_ref, np.float64).ravel()
-    nb = np.linalg.norm(b)
-    if nb == 0:
-        assert np.abs(a).max() == 0, name
-        return
-    assert np.linalg.norm(a - b) <= TOL * nb, (name, np.linalg.norm(a - b) / nb)
-    floor = 1e-3 * np.abs(b).max()
-    err = np.abs(a - b) / np.maximum(np.abs(b), floor)
-    assert err.max() <= 2e-2, (name, err.max())  # elementwise, floored at 1e-3 max|g|
+    grad_check(g_gpu, g_ref, name)
 
 
-@pytest.mark.parametrize("which,scale,res,spp,flags", [
-    (3, 0.02, 40, 1, 0),    # surface-like training step (6k surfels)
-    (1, 1.0, 32, 2, 1),     # volume, primary-only shading
-    (4, 0.01, 32, 2, 0),    # instanced objects, one bounce
+@pytest.mark.parametrize("which,scale,res,spp,flags,k", [
+    (3, 0.02, 40, 1, 0, None),    # surface-like training step (6k surfels)
+    (1, 1.0, 32, 2, 1, None),     # volume, primary-only shading
+    (4, 0.01, 32, 2, 0, None),    # instanced objects, one bounce
+    (3, 0.02, 40, 2, 0, 8),       # the k-buffer instantiations below and above 32
+    (3, 0.02, 40, 2, 0, 64),
 ])
-def test_adjoint_matches_oracle(tracer, which, scale, res, spp, flags):
+def test_adjoint_matches_oracle(tracer, which, scale, res, spp, flags, k):
     wl = scenegen.make_workload(which, scale=scale, resolution=res)
+    if k is not None:
+        wl.k = k
     st = wl.states[0]
     env = st.env if st.env.shape[0] <= 64 else scenegen.lognormal_env(np.random.default_rng(5), 32, 64)
     st = scenegen.State(R=st.R, t=st.t, env=env, cameras=st.cameras)

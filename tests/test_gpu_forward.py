@@ -102,6 +102,50 @@ def test_c2_one_bounce_parity(tracer, c2_small):
     assert (ref["sec_alpha"] > 0).mean() > 0.05  # secondaries really hit geometry
 
 
+@pytest.mark.parametrize("k", [12, 48, 64])
+def test_one_bounce_parity_at_other_k(tracer, c2_small, k):
+    """One-bounce forward at k in the 16- and 64-entry k-buffer
+    instantiations (the secondary traversal and compositing kernels are
+    compiled per bucket): primary and per-slot secondary hit lists and the
+    outputs equal the oracle's."""
+    wl = c2_small
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    cam = st.cameras[0]
+    out = tracer.render(**state_args(tracer, wl.scene, st), cameras=[cam], k=k, spp=2, seed=wl.seed + k,
+                        hit_idx=True, sec_hit_idx=True)
+    pix = np.arange(k % 5, cam.w * cam.h, 5)
+    o, d, ids = oracle.raygen(cam, pix)
+    ref = run_oracle(wl.scene, st, o, d, ids, k, 2, wl.seed + k, 0)
+    _compare({key: v[pix] for key, v in out.items()}, ref, ambiguous(ref["margins"]), check_sec=True, spp=2)
+    assert (ref["sec_alpha"] > 0).mean() > 0.05
+
+
+def test_traversal_stack_reaches_its_deepest_entries(tracer, c2_small):
+    """The traversal stack keeps one LDS entry per level above the current
+    node; on a 20k-surfel surface scene the primary and secondary traversals
+    of a parity-checked render fill it to within one entry of the deepest
+    level the hierarchy has, so every stack slot in use is compared."""
+    import paper_2608_29269_amd as lf
+    wl = c2_small
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    info = tracer.info()
+    cam = st.cameras[0]
+    tracer.trace_counters()
+    out = tracer.render(**state_args(tracer, wl.scene, st), cameras=[cam], k=32, spp=2, seed=8,
+                        hit_idx=True, sec_hit_idx=True, flags=lf._lib.FLAG_COUNT)
+    cnt = tracer.trace_counters()
+    print(info, cnt, flush=True)
+    for side in ("primary", "secondary"):
+        assert cnt[side]["stack_pushes"] > 0
+        assert info["wide_levels"] - 2 <= cnt[side]["stack_deepest"] <= info["wide_levels"] - 1, (side, cnt, info)
+    pix = np.arange(1, cam.w * cam.h, 4)
+    o, d, ids = oracle.raygen(cam, pix)
+    ref = run_oracle(wl.scene, st, o, d, ids, 32, 2, 8, 0)
+    _compare({key: v[pix] for key, v in out.items()}, ref, ambiguous(ref["margins"]), check_sec=True, spp=2)
+
+
 @pytest.mark.parametrize("n", [1, 7, 63, 65, 129, 1001])
 def test_persistent_pool_small_and_ragged_counts(tracer, c2_small, n):
     """Ray counts below, at and just above the eight item ranges and a wave
@@ -235,6 +279,9 @@ def _check_wide(tracer, inst, leaf):
         order.append(x)
         stack.extend(int(c) for c in wc[x] if c >= 0)
     assert len(set(order)) == len(order), "a node reached twice"
+    for x in order:  # internal children occupy a node's first slots
+        kinds = [0 if c >= 0 else 1 for c in wc[x] if c != none]
+        assert kinds == sorted(kinds), (x, wc[x])
     exact = {}
     for x in reversed(order):  # children before parents
         lo = np.full(3, np.inf, np.float32)
@@ -255,8 +302,8 @@ def test_bvh_structure_and_refit(tracer, c2_small):
     wl = c2_small
     ts = upload_scene(tracer, wl.scene)
     info = tracer.info()
-    # a traversal step pushes at most node_width - 1 entries per level
-    assert (info["node_width"] - 1) * info["wide_levels"] <= info["stack_size"]
+    # the traversal stack holds one entry per level above the current node
+    assert info["wide_levels"] - 1 <= info["stack_size"]
     assert 1 <= info["wide_levels"] <= info["max_depth"]
 
     def check():

@@ -9,13 +9,13 @@ import pytest
 
 import oracle
 import scenegen
-from tests.gpu_common import ambiguous, dev, rel_close, run_oracle, state_args, upload_scene
+from tests.gpu_common import grad_check, ambiguous, dev, rel_close, run_oracle, state_args, upload_scene
 
 pytestmark = pytest.mark.gpu
 
 RTOL = 1e-4
 GTOL = 1e-3
-N_SAMPLE = 48
+N_SAMPLE = 256
 
 
 @pytest.fixture(scope="module")
@@ -47,29 +47,24 @@ def test_full_size_forward_on_sampled_pixels(tracer, which, state):
           f"{st.cameras[0].w}x{st.cameras[0].h}, S={wl.spp}", flush=True)
     upload_scene(tracer, wl.scene)
     out = tracer.render(**state_args(tracer, wl.scene, st), cameras=st.cameras, k=wl.k, spp=wl.spp,
-                        seed=wl.seed + state)
+                        seed=wl.seed + state, hit_idx=True, sec_hit_idx=True)
     tracer.sync()
     ids, o, d = _sampled_rays(st.cameras, N_SAMPLE, which * 10 + state)
     ref = run_oracle(wl.scene, st, o, d, ids, wl.k, wl.spp, wl.seed + state, 0)
     amb = ambiguous(ref["margins"])
     ok = ~amb
-    assert ok.mean() >= 0.9, amb.mean()
+    print(f"ambiguous {int(amb.sum())} of {N_SAMPLE}", flush=True)
+    assert amb.sum() <= 2, amb.sum()
+    # primary and per-slot secondary hit lists of the sampled rays, as the benchmark launches them
+    np.testing.assert_array_equal(out["hit_idx"].cpu().numpy()[ids][ok], ref["hit_idx"][ok])
+    np.testing.assert_array_equal(out["sec_hit_idx"].cpu().numpy()[ids][ok], ref["sec_hit_idx"][ok])
     for key in ("radiance", "depth", "normal", "alpha"):
         g = out[key].cpu().numpy()[ids]
         assert rel_close(g[ok], ref[key][ok], RTOL) < RTOL, key
 
 
 def _grad_check(g_gpu, g_ref, name):
-    a = np.asarray(g_gpu, np.float64).ravel()
-    b = np.asarray(g_ref, np.float64).ravel()
-    nb = np.linalg.norm(b)
-    if nb == 0:
-        assert np.abs(a).max() == 0, name
-        return
-    assert np.linalg.norm(a - b) <= GTOL * nb, (name, np.linalg.norm(a - b) / nb)
-    floor = 1e-3 * np.abs(b).max()
-    err = np.abs(a - b) / np.maximum(np.abs(b), floor)
-    assert err.max() <= 2e-2, (name, err.max())
+    grad_check(g_gpu, g_ref, name)
 
 
 @pytest.mark.parametrize("which", [3, 5])
@@ -125,7 +120,8 @@ def test_full_size_two_ray_sobol_step_on_sampled_pixels(tracer):
     ref = oracle.render(sa, o, d, ids, p, lists=False)
     amb = ambiguous(ref["margins"])
     ok = ~amb
-    assert ok.mean() >= 0.9, amb.mean()
+    print(f"ambiguous {int(amb.sum())} of {N_SAMPLE}", flush=True)
+    assert amb.sum() <= 2, amb.sum()
     for key in ("radiance", "depth", "normal", "alpha"):
         g = out[key].cpu().numpy()[ids]
         assert rel_close(g[ok], ref[key][ok], RTOL) < RTOL, key
