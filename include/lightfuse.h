@@ -145,6 +145,19 @@ typedef struct {
  * uniforms; the samples of one ray form an aligned block of the sequence,
  * so power-of-two spp are stratified in every dimension. */
 #define LF_FLAG_SOBOL         (1u << 8)
+/* Order-fixed gradient sums in lf_render_backward (Sec. 3.3 PRB paragraph:
+ * the replay must reproduce the same path and the same gradient).  Every
+ * per-hit and per-environment-tap contribution is written as a binary64
+ * record at a position fixed by its ray and its rank within the ray; the
+ * records are sorted by target (surfel or texel) with a stable radix sort
+ * and each target's records are summed in binary64 in record order, then
+ * rounded once to binary32.  Gradients are then bitwise reproducible from
+ * run to run.  Costs about 128 B of device scratch per (work item x k
+ * bucket) and 32 B per (ray x 4 (1 + 3 J)) environment taps (LF_ENOMEM if
+ * that cannot be allocated, LF_EUNSUPPORTED past 2^31 records).  Without
+ * it the same contributions are summed by per-block LDS tables and float
+ * atomics, whose order varies between runs.  No effect on lf_render. */
+#define LF_FLAG_DETERMINISTIC (1u << 9)
 
 /* Tracing and estimator parameters.  Readings of points the paper leaves
  * open (Sec. 3.2 "finite support", "opacity threshold", epsilon of

@@ -19,11 +19,11 @@ import ctypes as C
 from typing import Optional, Sequence
 
 from . import _lib
-from ._lib import (FLAG_BRUTE_FORCE, FLAG_COUNT, FLAG_BSDF_ONLY, FLAG_DIFFUSE_ONLY, FLAG_NEE, FLAG_NO_BACKGROUND,
-                   FLAG_NO_SECONDARY, FLAG_SOBOL, LFError)
+from ._lib import (FLAG_BRUTE_FORCE, FLAG_COUNT, FLAG_BSDF_ONLY, FLAG_DETERMINISTIC, FLAG_DIFFUSE_ONLY, FLAG_NEE,
+                   FLAG_NO_BACKGROUND, FLAG_NO_SECONDARY, FLAG_SOBOL, LFError)
 
 __all__ = ["Tracer", "RenderFn", "Server", "LFError", "FLAG_NO_SECONDARY", "FLAG_NO_BACKGROUND", "FLAG_BSDF_ONLY",
-           "FLAG_DIFFUSE_ONLY", "FLAG_BRUTE_FORCE", "FLAG_NEE", "FLAG_SOBOL", "camera_struct"]
+           "FLAG_DIFFUSE_ONLY", "FLAG_BRUTE_FORCE", "FLAG_NEE", "FLAG_SOBOL", "FLAG_DETERMINISTIC", "camera_struct"]
 
 
 def _ptr(t):

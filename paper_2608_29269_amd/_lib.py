@@ -24,6 +24,7 @@ FLAG_COUNT = 1 << 5
 FLAG_UNSORTED = 1 << 6
 FLAG_NEE = 1 << 7  # the two-ray estimator: next-event + continuation per sample
 FLAG_SOBOL = 1 << 8  # Owen-scrambled Sobol uniforms instead of the hash
+FLAG_DETERMINISTIC = 1 << 9  # order-fixed binary64 gradient sums in the backward
 MAX_CAMERAS = 16
 SCHED_SHORTEST_FIRST, SCHED_OLDEST_FIRST, SCHED_ROUND_ROBIN = 0, 1, 2
 

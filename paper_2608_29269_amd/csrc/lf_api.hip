@@ -99,7 +99,7 @@ lf_status validate_params(lf_ctx *c, const lf_params *p) {
   if (!(p->alpha_min > 0.0) || !(p->alpha_cap > 0.0 && p->alpha_cap < 1.0) || !(p->support_sigma > 0.0) ||
       !(p->eps >= 0.0) || !(p->t_min >= 0.0) || !std::isfinite(p->secondary_offset))
     return fail(c, LF_EINVAL, "invalid tracing constants");
-  if (p->flags & ~0x1FFu) return fail(c, LF_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~0x3FFu) return fail(c, LF_EINVAL, "unknown flags 0x%x", p->flags);
   return LF_OK;
 }
 
@@ -610,6 +610,45 @@ lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, co
   return check_hip(c, "render");
 }
 
+// Smallest b with 2^b > n: keys below 2^b sort in ceil(b / 16) * 2 radix passes
+// and 2^b - 1 marks unused records.
+static int key_bits(int64_t n) {
+  int b = 1;
+  while (b < 62 && ((int64_t)1 << b) <= n) ++b;
+  return b;
+}
+
+// Scratch of the order-fixed adjoint (LF_FLAG_DETERMINISTIC) for the call a.
+static lf_status deterministic_buffers(lf_ctx *c, const lf::RenderArgs &a, int64_t texels, lf::DetArgs &d) {
+  const int64_t J = (int64_t)a.P.spp * ((a.P.flags & LF_FLAG_NEE) ? 2 : 1);
+  d.n_hit = lf::adjoint_items(a) * lf::kbucket(a.P.k);
+  d.env_cap = (int)(4 * (1 + 3 * J));
+  d.n_env = a.R * d.env_cap;
+  if (d.n_hit >= ((int64_t)1 << 31) || d.n_env >= ((int64_t)1 << 31))
+    return fail(c, LF_EUNSUPPORTED, "deterministic gradients take at most 2^31 records (%lld hit, %lld env)",
+                (long long)d.n_hit, (long long)d.n_env);
+  d.hit_bits = key_bits(c->s.n);
+  d.env_bits = key_bits(texels);
+  d.hit_unused = ((uint64_t)1 << d.hit_bits) - 1;
+  d.env_unused = ((uint64_t)1 << d.env_bits) - 1;
+  const int64_t nmax = d.n_hit > d.n_env ? d.n_hit : d.n_env;
+  if (!c->det_key.ensure(8 * nmax) || !c->det_key2.ensure(8 * nmax) || !c->det_idx.ensure(4 * nmax) ||
+      !c->det_idx2.ensure(4 * nmax) || !c->det_hval.ensure(sizeof(double) * 15 * d.n_hit) ||
+      !c->det_eval.ensure(sizeof(double) * 3 * d.n_env) ||
+      !c->det_hist.ensure(4 * lf::radix_sort_hist_words(nmax)))
+    return fail(c, LF_ENOMEM, "deterministic gradient records (%lld hit, %lld env)", (long long)d.n_hit,
+                (long long)d.n_env);
+  // the two sorts run one after the other on the stream, so they share the key and index buffers
+  d.hit_key = d.env_key = c->det_key.as<uint64_t>();
+  d.hit_key2 = d.env_key2 = c->det_key2.as<uint64_t>();
+  d.hit_idx = d.env_idx = c->det_idx.as<int32_t>();
+  d.hit_idx2 = d.env_idx2 = c->det_idx2.as<int32_t>();
+  d.hit_val = c->det_hval.as<double>();
+  d.env_val = c->det_eval.as<double>();
+  d.hist = c->det_hist.as<uint32_t>();
+  return LF_OK;
+}
+
 lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, const lf_rays *rays,
                              const lf_camera *cams, int32_t n_cams, const lf_params *p, const lf_grad_out *g,
                              lf_grad_in *gi) {
@@ -658,6 +697,20 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
   }
   lf::GradArgs ga{g->d_radiance, g->d_depth, g->d_normal, g->d_alpha, gi->d_mu, gi->d_q, gi->d_scale,
                   gi->d_opacity, gi->d_albedo, gi->d_roughness, gi->d_metallic, gi->d_env};
+  if (p->flags & LF_FLAG_DETERMINISTIC) {
+    lf::DetArgs d;
+    st = deterministic_buffers(c, a, (int64_t)env->h * env->w, d);
+    if (st) return st;
+    {
+      Phase ph(c, 10);
+      lf::launch_adjoint_shade_det(a, ga, d, s);
+    }
+    {
+      Phase ph(c, 16);
+      lf::launch_adjoint_hits_det(a, ga, d, s);
+    }
+    return check_hip(c, "backward");
+  }
   {
     Phase ph(c, 10);
     lf::launch_adjoint_shade(a, ga, s);

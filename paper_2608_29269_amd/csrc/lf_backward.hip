@@ -30,7 +30,8 @@ struct BlockEnvTable {
   int *key;     // [kEnvAggSlots], -1 when free
   float *val;   // [3][kEnvAggSlots]
   float *genv;  // [H, W, 3] in device memory
-  __device__ void add(int texel, float gx, float gy, float gz) {
+  __device__ void add(int texel, double dx, double dy, double dz) {
+    const float gx = (float)dx, gy = (float)dy, gz = (float)dz;
     const uint32_t h = (uint32_t)texel * 2654435761u;
 #pragma unroll 1
     for (int p = 0; p < kEnvAggProbes; ++p) {
@@ -49,13 +50,37 @@ struct BlockEnvTable {
   }
 };
 
-__device__ __forceinline__ void env_scatter(const EnvView &E, BlockEnvTable &acc, d3 w, d3 g) {
+// Order-fixed accumulation (LF_FLAG_DETERMINISTIC): every contribution is
+// written as a record at a position fixed by its ray (or work item) and its
+// rank within that ray, keyed by its target (environment texel or surfel);
+// the records are then sorted by key with a stable radix sort, so each
+// target's records stay in position order, and every target's sum is taken
+// in binary64 in that order and rounded once.  The result does not depend
+// on scheduling.
+struct EnvRecords {
+  uint64_t *key;  // [rays * cap] texel of each record
+  int32_t *idx;   // [rays * cap] the record's own position (the sort's payload)
+  double *val;    // [rays * cap][3]
+  int64_t base;   // first record of this ray
+  int n;          // records written so far
+  __device__ void add(int texel, double gx, double gy, double gz) {
+    const int64_t r = base + n++;
+    key[r] = (uint64_t)texel;
+    idx[r] = (int32_t)r;
+    val[3 * r] = gx;
+    val[3 * r + 1] = gy;
+    val[3 * r + 2] = gz;
+  }
+};
+
+template <class EAcc>
+__device__ __forceinline__ void env_scatter(const EnvView &E, EAcc &acc, d3 w, d3 g) {
   Taps tp;
   env_taps(E, w, tp);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (tp.w[k] == 0.0) continue;
-    acc.add((int)tp.i[k], (float)(tp.w[k] * g.x), (float)(tp.w[k] * g.y), (float)(tp.w[k] * g.z));
+    acc.add((int)tp.i[k], tp.w[k] * g.x, tp.w[k] * g.y, tp.w[k] * g.z);
   }
 }
 
@@ -105,8 +130,8 @@ __device__ __forceinline__ void fcos_bwd(d3 n, d3 wi, d3 wo, d3 a, double m, dou
 // (the replay stores tw_j T2 as its frozen transmittance); environment
 // gradients are scattered here, and the adjoints of the surface record are
 // reduced to the seeds of the compositing adjoint.
-__device__ __forceinline__ void adj_shade_ray(const RenderArgs &a, const GradArgs &G, int64_t ray,
-                                              BlockEnvTable &acc) {
+template <class EAcc>
+__device__ __forceinline__ void adj_shade_ray(const RenderArgs &a, const GradArgs &G, int64_t ray, EAcc &acc) {
   const TraceParams &P = a.P;
   const int S = P.spp, J = n_slots(P);
   float of[3], df[3];
@@ -200,6 +225,19 @@ __global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G) {
   }
 }
 
+// deterministic form: each ray's environment records (at most 4 taps per
+// lookup, 1 + 3 J lookups), unused positions keyed past every texel
+__global__ __launch_bounds__(256) void k_adj_shade_det(RenderArgs a, GradArgs G, DetArgs d) {
+  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ray >= a.R) return;
+  EnvRecords acc{d.env_key, d.env_idx, d.env_val, ray * d.env_cap, 0};
+  adj_shade_ray(a, G, ray, acc);
+  for (int j = acc.n; j < d.env_cap; ++j) {
+    d.env_key[acc.base + j] = d.env_unused;
+    d.env_idx[acc.base + j] = (int32_t)(acc.base + j);
+  }
+}
+
 // ---------------------------------------------------------------- gradient accumulation
 // The fifteen per-surfel gradient values of one hit, in this order: albedo
 // (3), metallic, roughness, opacity, scale (2), mu (3), raw quaternion (4).
@@ -230,7 +268,10 @@ struct BlockGradTable {
   int *key;     // [kAggSlots], -1 when free
   float *val;   // [kGradVals][kAggSlots]
   const GradArgs &G;
-  __device__ void add(int64_t i, const float *gv) {
+  __device__ void add(int64_t i, const double *dv, int /*slot*/) {
+    float gv[kGradVals];
+#pragma unroll
+    for (int v = 0; v < kGradVals; ++v) gv[v] = (float)dv[v];
     const uint32_t h = (uint32_t)i * 2654435761u;
 #pragma unroll 1
     for (int p = 0; p < kAggProbes; ++p) {
@@ -244,6 +285,21 @@ struct BlockGradTable {
     }
 #pragma unroll
     for (int v = 0; v < kGradVals; ++v) atomicAdd(grad_slot(G, i, v), gv[v]);
+  }
+};
+
+// deterministic form: one record per hit slot of each work item
+struct HitRecords {
+  uint64_t *key;  // [items * K] surfel of each record
+  int32_t *idx;   // [items * K] the record's own position
+  double *val;    // [items * K][kGradVals]
+  int64_t base;   // first record of this item
+  __device__ void add(int64_t i, const double *gv, int slot) {
+    const int64_t r = base + slot;
+    key[r] = (uint64_t)i;
+    idx[r] = (int32_t)r;
+#pragma unroll
+    for (int v = 0; v < kGradVals; ++v) val[kGradVals * r + v] = gv[v];
   }
 };
 
@@ -276,12 +332,12 @@ __device__ void adjoint_hits(const RenderArgs &a, const AdjSeed &sd, B &kb, d3 o
     V += wj * vj;
     Tafter = Tj;
     // attributes
-    float gv[kGradVals];
-    gv[0] = (float)(gZa.x * wj);
-    gv[1] = (float)(gZa.y * wj);
-    gv[2] = (float)(gZa.z * wj);
-    gv[3] = (float)(gZm * wj);
-    gv[4] = (float)(gZr * wj);
+    double gv[kGradVals];
+    gv[0] = gZa.x * wj;
+    gv[1] = gZa.y * wj;
+    gv[2] = gZa.z * wj;
+    gv[3] = gZm * wj;
+    gv[4] = gZr * wj;
     // frame of the raw quaternion, object-space ray of the hit's instance
     const InstRec &I = a.S.inst[he.inst];
     d3 oo, dd;
@@ -299,11 +355,11 @@ __device__ void adjoint_hits(const RenderArgs &a, const AdjSeed &sd, B &kb, d3 o
     const double raw = alpha * g;
     // effective opacity alpha_t = min(cap, alpha exp(-rho^2/2))
     const double graw = raw > P.alpha_cap ? 0.0 : gat;
-    gv[5] = (float)(graw * g);
+    gv[5] = graw * g;
     const double grho2 = graw * alpha * g * (-0.5);
     const double gxu = grho2 * 2.0 * xu, gxv = grho2 * 2.0 * xv;
-    gv[6] = (float)(-gxu * xu / su);
-    gv[7] = (float)(-gxv * xv / sv);
+    gv[6] = -gxu * xu / su;
+    gv[7] = -gxv * xv / sv;
     const d3 gdl = (gxu / su) * tu + (gxv / sv) * tv;
     const d3 gtu = (gxu / su) * dl, gtv = (gxv / sv) * dl;
     // dl = o + t d - mu ; t = n.(mu - o) / (n.d) ; composited normal = +-R n
@@ -314,9 +370,9 @@ __device__ void adjoint_hits(const RenderArgs &a, const AdjSeed &sd, B &kb, d3 o
     if (id & kFlipBit) gno = -gno;
     const d3 gmu = (gt / den) * n - gdl;
     const d3 gnn = gno - (gt / den) * dl;
-    gv[8] = (float)gmu.x;
-    gv[9] = (float)gmu.y;
-    gv[10] = (float)gmu.z;
+    gv[8] = gmu.x;
+    gv[9] = gmu.y;
+    gv[10] = gmu.z;
     // columns (t_u, t_v, n) of rot(q_hat) -> q_hat -> raw q;  G[r][c] row-major
     const double G0 = gtu.x, G1 = gtv.x, G2 = gnn.x, G3 = gtu.y, G4 = gtv.y, G5 = gnn.y, G6 = gtu.z, G7 = gtv.z,
                  G8 = gnn.z;
@@ -328,11 +384,11 @@ __device__ void adjoint_hits(const RenderArgs &a, const AdjSeed &sd, B &kb, d3 o
     const double gq3 = G0 * (-4 * z) + G1 * (-2 * w) + G2 * (2 * x) + G3 * (2 * w) + G4 * (-4 * z) + G5 * (2 * y) +
                        G6 * (2 * x) + G7 * (2 * y);
     const double pq = gq0 * w + gq1 * x + gq2 * y + gq3 * z;
-    gv[11] = (float)((gq0 - w * pq) / qlen);
-    gv[12] = (float)((gq1 - x * pq) / qlen);
-    gv[13] = (float)((gq2 - y * pq) / qlen);
-    gv[14] = (float)((gq3 - z * pq) / qlen);
-    acc.add(i, gv);
+    gv[11] = (gq0 - w * pq) / qlen;
+    gv[12] = (gq1 - x * pq) / qlen;
+    gv[13] = (gq2 - y * pq) / qlen;
+    gv[14] = (gq3 - z * pq) / qlen;
+    acc.add(i, gv, it);
   }
 }
 
@@ -379,12 +435,99 @@ __global__ __launch_bounds__(kBlock) void k_adj_hits(RenderArgs a, GradArgs G) {
   }
 }
 
+// deterministic form: K records per work item, unused slots keyed past every surfel
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_adj_hits_det(RenderArgs a, GradArgs G, DetArgs d) {
+  const int64_t item = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (item >= adj_items(a)) return;
+  const int64_t base = item * K;
+  for (int j = 0; j < K; ++j) {
+    d.hit_key[base + j] = d.hit_unused;
+    d.hit_idx[base + j] = (int32_t)(base + j);
+  }
+  const int64_t ray = adj_ray(a, item);
+  if (ray < 0) return;
+  float of[3], df[3];
+  load_ray(a.rays, ray, of, df);
+  KBufF<K> kb;
+  load_kbuf<K>(kb, a.kbuf1 + item * 2 * K);
+  HitRecords acc{d.hit_key, d.hit_idx, d.hit_val, base};
+  adjoint_hits<K>(a, a.seeds[ray], kb, mk(of[0], of[1], of[2]), mk(df[0], df[1], df[2]), acc);
+}
+
+// One thread per sorted record; the first record of each key sums the
+// key's records in sorted (= position) order in binary64 and writes the
+// rounded sums over the target's zero-initialised gradients.
+__global__ void k_det_reduce_hits(const uint64_t *key, const int32_t *idx, int64_t n, uint64_t unused,
+                                  const double *val, GradArgs G) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint64_t k = key[p];
+  if (k == unused || (p > 0 && key[p - 1] == k)) return;
+  double s[kGradVals];
+#pragma unroll
+  for (int v = 0; v < kGradVals; ++v) s[v] = 0.0;
+  for (int64_t q = p; q < n && key[q] == k; ++q) {
+    const double *r = val + (int64_t)kGradVals * idx[q];
+#pragma unroll
+    for (int v = 0; v < kGradVals; ++v) s[v] += r[v];
+  }
+#pragma unroll
+  for (int v = 0; v < kGradVals; ++v) *grad_slot(G, (int64_t)k, v) = (float)s[v];
+}
+
+__global__ void k_det_reduce_env(const uint64_t *key, const int32_t *idx, int64_t n, uint64_t unused,
+                                 const double *val, float *genv) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint64_t k = key[p];
+  if (k == unused || (p > 0 && key[p - 1] == k)) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int64_t q = p; q < n && key[q] == k; ++q) {
+    const double *r = val + 3 * (int64_t)idx[q];
+    s0 += r[0];
+    s1 += r[1];
+    s2 += r[2];
+  }
+  genv[3 * k] = (float)s0;
+  genv[3 * k + 1] = (float)s1;
+  genv[3 * k + 2] = (float)s2;
+}
+
 template <int K>
 void adjoint_hits_k(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_hits<K>, dim3(blocks(adj_items_host(a), kBlock)), dim3(kBlock), 0, st, a, g);
 }
 
+template <int K>
+void adjoint_hits_det_k(const RenderArgs &a, const GradArgs &g, const DetArgs &d, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_hits_det<K>, dim3(blocks(adj_items_host(a), kBlock)), dim3(kBlock), 0, st, a, g, d);
+}
+
 }  // namespace
+
+int64_t adjoint_items(const RenderArgs &a) { return adj_items_host(a); }
+
+void launch_adjoint_shade_det(const RenderArgs &a, const GradArgs &g, const DetArgs &d, hipStream_t st) {
+  if (a.R <= 0) return;
+  hipLaunchKernelGGL(k_adj_shade_det, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, g, d);
+  radix_sort(d.env_key, d.env_idx, d.env_key2, d.env_idx2, d.hist, d.n_env, st, d.env_bits);
+  hipLaunchKernelGGL(k_det_reduce_env, dim3(blocks(d.n_env, 256)), dim3(256), 0, st, (const uint64_t *)d.env_key,
+                     (const int32_t *)d.env_idx, d.n_env, d.env_unused, (const double *)d.env_val, g.g_env);
+}
+
+void launch_adjoint_hits_det(const RenderArgs &a, const GradArgs &g, const DetArgs &d, hipStream_t st) {
+  if (a.R <= 0) return;
+  switch (kbucket(a.P.k)) {
+    case 8: adjoint_hits_det_k<8>(a, g, d, st); break;
+    case 16: adjoint_hits_det_k<16>(a, g, d, st); break;
+    case 32: adjoint_hits_det_k<32>(a, g, d, st); break;
+    default: adjoint_hits_det_k<64>(a, g, d, st); break;
+  }
+  radix_sort(d.hit_key, d.hit_idx, d.hit_key2, d.hit_idx2, d.hist, d.n_hit, st, d.hit_bits);
+  hipLaunchKernelGGL(k_det_reduce_hits, dim3(blocks(d.n_hit, 256)), dim3(256), 0, st, (const uint64_t *)d.hit_key,
+                     (const int32_t *)d.hit_idx, d.n_hit, d.hit_unused, (const double *)d.hit_val, g);
+}
 
 void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
   if (a.R <= 0) return;

@@ -68,6 +68,7 @@ struct lf_ctx {
   lfh::DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;
   lfh::DevBuf queue, qcount, work, kbuf1, kbuf2, contrib, frozen, lossbuf, cams, rec1, rec2, seeds;
   lfh::DevBuf bounds, skeys, skeys2, svals, svals2, shist;
+  lfh::DevBuf det_key, det_key2, det_idx, det_idx2, det_hval, det_eval, det_hist;  // LF_FLAG_DETERMINISTIC
   lf::CamArgs h_cams{};
   // ray counters since the last lf_stats_get
   int64_t acc_primary = 0;

@@ -152,6 +152,28 @@ struct GradArgs {
 // primary k-buffers (kbuf1) of the replayed primary pass
 void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st);
 void launch_adjoint_hits(const RenderArgs &a, const GradArgs &g, hipStream_t st);
+// Order-fixed (LF_FLAG_DETERMINISTIC) form of the two adjoints: contributions
+// go to records at fixed positions, are sorted by target and summed in
+// binary64 per target (see lf_backward.hip).  Buffers owned by the caller.
+struct DetArgs {
+  uint64_t *hit_key, *hit_key2;   // [n_hit] surfel keys, sort scratch
+  int32_t *hit_idx, *hit_idx2;    // [n_hit] record positions, sort scratch
+  double *hit_val;                // [n_hit][15]
+  int64_t n_hit;                  // adjoint_items x k bucket
+  uint64_t hit_unused;            // key of an unused record: 2^hit_bits - 1 > every surfel index
+  int hit_bits;
+  uint64_t *env_key, *env_key2;
+  int32_t *env_idx, *env_idx2;
+  double *env_val;                // [n_env][3]
+  int64_t n_env;                  // rays x env_cap
+  int env_cap;                    // records per ray: 4 taps x (1 + 3 x secondary slots)
+  uint64_t env_unused;
+  int env_bits;
+  uint32_t *hist;                 // radix_sort_hist_words(max(n_hit, n_env))
+};
+int64_t adjoint_items(const RenderArgs &a);  // work items of the compositing adjoint
+void launch_adjoint_shade_det(const RenderArgs &a, const GradArgs &g, const DetArgs &d, hipStream_t st);
+void launch_adjoint_hits_det(const RenderArgs &a, const GradArgs &g, const DetArgs &d, hipStream_t st);
 
 inline int kbucket(int k) { return k <= 8 ? 8 : (k <= 16 ? 16 : (k <= 32 ? 32 : 64)); }
 

@@ -114,6 +114,6 @@ def test_binding_constants_match_the_header():
     src = open(HEADER).read()
     assert int(re.search(r"#define LF_NUM_COUNTERS (\d+)", src).group(1)) == _lib.NUM_COUNTERS
     for name in ("NO_SECONDARY", "NO_BACKGROUND", "BSDF_ONLY", "DIFFUSE_ONLY", "BRUTE_FORCE", "COUNT", "UNSORTED",
-                 "NEE", "SOBOL"):
+                 "NEE", "SOBOL", "DETERMINISTIC"):
         m = re.search(r"#define LF_FLAG_%s\s+\(1u << (\d+)\)" % name, src)
         assert m and getattr(_lib, "FLAG_" + name) == 1 << int(m.group(1)), name

@@ -24,14 +24,18 @@ def _grad_check(g_gpu, g_ref, name):
     grad_check(g_gpu, g_ref, name)
 
 
-@pytest.mark.parametrize("which,scale,res,spp,flags,k", [
+CASES = [
     (3, 0.02, 40, 1, 0, None),    # surface-like training step (6k surfels)
     (1, 1.0, 32, 2, 1, None),     # volume, primary-only shading
     (4, 0.01, 32, 2, 0, None),    # instanced objects, one bounce
     (3, 0.02, 40, 2, 0, 8),       # the k-buffer instantiations below and above 32
     (3, 0.02, 40, 2, 0, 64),
-])
-def test_adjoint_matches_oracle(tracer, which, scale, res, spp, flags, k):
+]
+
+
+def _adjoint_case(which, scale, res, spp, flags, k):
+    """A small workload, a random upstream gradient (zero on legitimately
+    ambiguous rays, on both sides) and the oracle's FP64 adjoint."""
     wl = scenegen.make_workload(which, scale=scale, resolution=res)
     if k is not None:
         wl.k = k
@@ -48,18 +52,56 @@ def test_adjoint_matches_oracle(tracer, which, scale, res, spp, flags, k):
     rng = np.random.default_rng(which)
     up = dict(radiance=rng.standard_normal((n, 3)), depth=rng.standard_normal(n), normal=rng.standard_normal((n, 3)),
               alpha=rng.standard_normal(n))
-    for k in up:
-        up[k][amb] = 0.0  # legitimately ambiguous rays are excluded on both sides
-        up[k] = up[k].astype(np.float32)
+    for key in up:
+        up[key][amb] = 0.0
+        up[key] = up[key].astype(np.float32)
     g_ref = oracle.backward(sa, o, d, ids, p, g_radiance=up["radiance"], g_depth=up["depth"],
                             g_normal=up["normal"], g_alpha=up["alpha"])
-    upload_scene(tracer, wl.scene)
+    return wl, st, cam, up, g_ref
+
+
+def _gpu_adjoint(tracer, wl, st, cam, up, spp, flags):
     g = tracer.render_backward(**state_args(tracer, wl.scene, st), cameras=[cam], k=wl.k, spp=spp, seed=wl.seed,
                                flags=flags, d_radiance=dev(up["radiance"]), d_depth=dev(up["depth"]),
                                d_normal=dev(up["normal"]), d_alpha=dev(up["alpha"]))
     tracer.sync()
+    return {key: v.cpu().numpy() for key, v in g.items()}
+
+
+@pytest.mark.parametrize("which,scale,res,spp,flags,k", CASES)
+def test_adjoint_matches_oracle(tracer, which, scale, res, spp, flags, k):
+    wl, st, cam, up, g_ref = _adjoint_case(which, scale, res, spp, flags, k)
+    upload_scene(tracer, wl.scene)
+    g = _gpu_adjoint(tracer, wl, st, cam, up, spp, flags)
     for name in GROUPS:
-        _grad_check(g[name].cpu().numpy(), g_ref[name], name)
+        _grad_check(g[name], g_ref[name], name)
+
+
+@pytest.mark.parametrize("which,scale,res,spp,flags,k", CASES)
+def test_deterministic_adjoint_matches_oracle_and_repeats_bitwise(tracer, which, scale, res, spp, flags, k):
+    """With LF_FLAG_DETERMINISTIC every gradient is a binary64 sum in a fixed
+    order rounded once: within 1e-3 of the oracle element by element, and
+    bitwise the same on a second run (and after an atomic-path run in
+    between, which leaves no state behind)."""
+    import paper_2608_29269_amd as lf
+    wl, st, cam, up, g_ref = _adjoint_case(which, scale, res, spp, flags, k)
+    upload_scene(tracer, wl.scene)
+    det = flags | lf.FLAG_DETERMINISTIC
+    g1 = _gpu_adjoint(tracer, wl, st, cam, up, spp, det)
+    for name in GROUPS:
+        _grad_check(g1[name], g_ref[name], name)
+    ga = _gpu_adjoint(tracer, wl, st, cam, up, spp, flags)
+    g2 = _gpu_adjoint(tracer, wl, st, cam, up, spp, det)
+    for name in GROUPS:
+        assert np.array_equal(g1[name].view(np.uint32), g2[name].view(np.uint32)), name
+        # the float-atomic path sums the same contributions in another order
+        grad_check(ga[name], g1[name], name)
+
+
+def torch_equal(x, y):
+    """Bitwise equality of two float32 tensors."""
+    import torch
+    return bool(torch.equal(x.reshape(-1).view(torch.int32), y.reshape(-1).view(torch.int32)))
 
 
 def test_gradients_overwrite(tracer):
@@ -75,6 +117,15 @@ def test_gradients_overwrite(tracer):
                                 grads=g1)
     for k in a:
         np.testing.assert_allclose(g2[k].cpu().numpy(), a[k].cpu().numpy(), rtol=1e-5, atol=1e-6)
+    # order-fixed sums: the overwritten gradients are bitwise those of a fresh call
+    import paper_2608_29269_amd as lf
+    g3 = tracer.render_backward(**args, cameras=st.cameras, k=16, spp=1, seed=1, flags=1 | lf.FLAG_DETERMINISTIC,
+                                d_radiance=up)
+    b = {k: v.clone() for k, v in g3.items()}
+    g4 = tracer.render_backward(**args, cameras=st.cameras, k=16, spp=1, seed=1, flags=1 | lf.FLAG_DETERMINISTIC,
+                                d_radiance=up, grads=g3)
+    for k in b:
+        assert torch_equal(g4[k], b[k]), k
 
 
 def test_autograd_function_and_l1(tracer):

@@ -67,10 +67,13 @@ def _grad_check(g_gpu, g_ref, name):
     grad_check(g_gpu, g_ref, name)
 
 
-@pytest.mark.parametrize("which", [3, 5])
-def test_full_size_gradients_from_sampled_pixels(tracer, which):
+@pytest.mark.parametrize("which,det", [(3, False), (5, False), (5, True)])
+def test_full_size_gradients_from_sampled_pixels(tracer, which, det):
     """The training-step configuration (300k surfels, 4 x 800^2, S=1) and the
-    benchmark configuration (1M surfels, 1024^2, S=4)."""
+    benchmark configuration (1M surfels, 1024^2, S=4), the latter also with
+    order-fixed gradient sums (LF_FLAG_DETERMINISTIC)."""
+    import paper_2608_29269_amd as lf
+    flags = lf.FLAG_DETERMINISTIC if det else 0
     wl = scenegen.make_workload(which)
     st = wl.states[0]
     upload_scene(tracer, wl.scene)
@@ -94,7 +97,7 @@ def test_full_size_gradients_from_sampled_pixels(tracer, which):
     g_ref = oracle.backward(sa, o, d, ids, p, g_radiance=up["radiance"], g_depth=up["depth"],
                             g_normal=up["normal"], g_alpha=up["alpha"])
     g = tracer.render_backward(**state_args(tracer, wl.scene, st), cameras=cams, k=wl.k, spp=wl.spp,
-                               seed=wl.seed, d_radiance=full["radiance"], d_depth=full["depth"],
+                               seed=wl.seed, flags=flags, d_radiance=full["radiance"], d_depth=full["depth"],
                                d_normal=full["normal"], d_alpha=full["alpha"])
     tracer.sync()
     for name in ("mu", "q", "scale", "opacity", "albedo", "roughness", "metallic", "env"):
