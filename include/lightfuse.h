@@ -231,6 +231,20 @@ lf_status lf_render_backward(lf_ctx *ctx, const lf_transforms *xf, const lf_envm
  * NULL); grad: device [n] or NULL.  LF_EINVAL for n < 0 or a missing pointer. */
 lf_status lf_l1_loss(lf_ctx *ctx, const float *pred, const float *target, int64_t n, float *loss, float *grad);
 
+/* lf_l1_loss for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result bit for bit, but the partial sums live in
+ * a library-owned device array of 2 x 2048 + 2 doubles (32 KB) that each
+ * device holds for the life of the process, located by
+ * lf_create; no allocation, no free, no event.  Any n >= 0 fits (the grid
+ * is capped at 2048 blocks, one partial-sum slot each).  Every call on one
+ * device shares that array (each call overwrites what it reads, so nothing
+ * needs clearing): calls that overlap on one device, from any contexts or
+ * streams, race and must be ordered by the caller.  Arguments, ownership and
+ * errors as for lf_l1_loss; LF_EDEVICE if the array was not located. */
+lf_status lf_l1_loss_noalloc(lf_ctx *ctx, const float *pred, const float *target, int64_t n, float *loss,
+                             float *grad);
+
 /* ---- Geometry-refinement objectives (Sec. 3.1 and 3.2).  Common contract:
  * every array is a device array; loss is a device float scalar written
  * asynchronously on the context's stream; grad, when non-NULL, is

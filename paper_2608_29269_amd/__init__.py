@@ -214,6 +214,15 @@ class Tracer:
         self._chk(self.L.lf_l1_loss(self.ctx, _ptr(pred), _ptr(target), pred.numel(), _ptr(loss), _ptr(grad)))
         return loss, grad
 
+    def l1_loss_noalloc(self, pred, target, loss, grad=None):
+        """lf_l1_loss_noalloc: the L1 objective into caller-provided outputs
+        (loss: device scalar, grad: like pred or None), no device allocation."""
+        if pred.shape != target.shape or (grad is not None and grad.shape != pred.shape):
+            raise ValueError("pred, target and grad shapes differ")
+        self._chk(self.L.lf_l1_loss_noalloc(self.ctx, _ptr(pred), _ptr(target), pred.numel(), _ptr(loss),
+                                            _ptr(grad)))
+        return loss, grad
+
     # -- geometry-refinement objectives (Sec. 3.1, 3.2); each returns
     #    (loss device scalar, gradient w.r.t. the first map or None)
     def _loss_out(self, like, want_grad):

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -299,6 +300,40 @@ void lf_params_default(lf_params *p) {
   p->flags = 0;
 }
 
+// ---- device scratch of the allocation-free L1 objective (lf_l1_loss_noalloc)
+// The partial sums of one objective pass (one slot per block of a grid capped
+// at kMaxLossBlocks, then the totals) live in this file-scope array: each
+// device holds its own copy for the life of the process, and every call on a
+// device shares it.  In host code `scratch` names a host-side stand-in, so
+// kernels receive the device address looked up by lf_create instead.
+static __device__ __align__(256) double scratch[lf::kLossPartDoubles];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxScratchDevices] = {};  // device address of `scratch` on each device
+
+// Looks up the device's copy of `scratch` once, with that device current.
+bool scratch_lookup(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return false;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return true;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return false;
+  }
+  g_scratch[device] = (double *)p;
+  return true;
+}
+
+double *scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[device];
+}
+}  // namespace
+
 lf_status lf_create(lf_ctx **out, int device, void *hip_stream) {
   if (!out) return LF_EINVAL;
   *out = nullptr;
@@ -310,8 +345,8 @@ lf_status lf_create(lf_ctx **out, int device, void *hip_stream) {
   lf_ctx *c = new lf_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
-  if (!set_device(c) || !c->status.ensure(sizeof(uint32_t)) || !c->acc_secondary.ensure(8) ||
-      !c->counters.ensure(8 * LF_NUM_COUNTERS)) {
+  if (!set_device(c) || !scratch_lookup(device) || !c->status.ensure(sizeof(uint32_t)) ||
+      !c->acc_secondary.ensure(8) || !c->counters.ensure(8 * LF_NUM_COUNTERS)) {
     delete c;
     return LF_EDEVICE;
   }
@@ -730,6 +765,17 @@ lf_status lf_l1_loss(lf_ctx *c, const float *pred, const float *target, int64_t 
   Phase ph(c, 13);
   lf::launch_l1(pred, target, n, loss, grad, c->lossbuf.as<double>(), c->stream);
   return check_hip(c, "l1 loss");
+}
+
+lf_status lf_l1_loss_noalloc(lf_ctx *c, const float *pred, const float *target, int64_t n, float *loss,
+                             float *grad) {
+  if (!c) return LF_EINVAL;
+  if (!loss || n < 0 || (n > 0 && (!pred || !target))) return fail(c, LF_EINVAL, "invalid loss arguments");
+  double *part = scratch_ptr(c->device);
+  if (!part) return fail(c, LF_EDEVICE, "no loss scratch on device %d", c->device);
+  set_device(c);
+  lf::launch_l1(pred, target, n, loss, grad, part, c->stream);
+  return check_hip(c, "l1 loss (no allocation)");
 }
 
 // Uploads one camera into c->cams (camera 0); validates it first.
