@@ -21,6 +21,9 @@
 //                      starting after the request served last.
 //  - An iteration's tiles complete together; a request completes when all of
 //    its rays have completed, which frees its slot and its budget.
+//  - A request whose pass failed (fail()) gets no further tiles; it
+//    completes, failed, once every tile already launched for it has retired,
+//    so no pass still in flight writes into its outputs after it is reported.
 #pragma once
 #include <stdint.h>
 
@@ -80,6 +83,7 @@ class Scheduler {
       sl.cost = w.cost;
       sl.next = 0;
       sl.done = 0;
+      sl.failed = false;
       sl.wpr = w.wpr;
       sl.seq = seq_++;
       used_ += w.cost;
@@ -130,6 +134,19 @@ class Scheduler {
     return tiles;
   }
 
+  // A pass holding tiles of the request in `slot` failed: plan no more of
+  // its rays.  It completes (from retire) when the tiles already launched
+  // have all retired, the failed pass's included.
+  void fail(int slot) {
+    if (slot < 0 || slot >= cfg_.max_slots) return;
+    Slot &sl = slots_[slot];
+    if (!sl.busy || sl.failed) return;
+    sl.failed = true;
+    sl.rays = sl.next;
+  }
+
+  bool failed(int slot) const { return slot >= 0 && slot < cfg_.max_slots && slots_[slot].failed; }
+
   // The iteration that held `tiles` has finished; returns (slot, ticket) of
   // the requests it completed (their slots and budget are released).
   std::vector<std::pair<int, uint64_t>> retire(const std::vector<SchedTile> &tiles) {
@@ -175,6 +192,7 @@ class Scheduler {
   };
   struct Slot {
     bool busy = false;
+    bool failed = false;
     uint64_t ticket = 0;
     int64_t rays = 0, cost = 0, next = 0, done = 0, wpr = 1;
     uint64_t seq = 0;

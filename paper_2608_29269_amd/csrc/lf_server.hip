@@ -84,6 +84,7 @@ struct lf_server {
   std::unordered_map<uint64_t, TicketRec> tickets;
   uint64_t next_ticket = 1;
   std::vector<uint64_t> slot_ticket;
+  std::vector<lf_status> slot_fail;  // status of a failed pass of the slot's request, until it completes
   std::vector<SlotDev> slots;
   std::vector<Lane> lanes;
   lf::BatchSlot *h_slots = nullptr;   // [max_slots] pinned staging of the slot table
@@ -267,17 +268,25 @@ bool retire(lf_server *s, Lane &L) {
   std::lock_guard<std::mutex> lk(s->mu);
   s->rays_secondary += rb.secondaries;
   if (st != LF_OK) {
-    // a device condition ends every request of the pass
-    for (const lf::SchedTile &tl : L.tiles) finish_ticket(s, s->slot_ticket[tl.slot], st, t);
+    // a device condition ends every request of the pass: none is planned
+    // again, and each is reported once its other passes in flight are done
+    for (const lf::SchedTile &tl : L.tiles) {
+      s->sched.fail(tl.slot);
+      if (s->slot_fail[tl.slot] == LF_OK) s->slot_fail[tl.slot] = st;
+    }
     s->err = "device status set during a batched pass";
   }
   for (auto &done : s->sched.retire(L.tiles)) {
-    // the request's own instance status (all of its passes have completed, so the word is final)
-    uint32_t ist = 0;
-    if (hipMemcpy(&ist, s->slots[done.first].status.p, 4, hipMemcpyDeviceToHost) != hipSuccess) return false;
-    const lf_status rs = status_of(ist);
-    if (rs != LF_OK) s->err = "degenerate or non-finite object transform";
-    s->rays_primary += s->tickets[done.second].rays;
+    lf_status rs = s->slot_fail[done.first];
+    s->slot_fail[done.first] = LF_OK;
+    if (rs == LF_OK) {
+      // the request's own instance status (all of its passes have completed, so the word is final)
+      uint32_t ist = 0;
+      if (hipMemcpy(&ist, s->slots[done.first].status.p, 4, hipMemcpyDeviceToHost) != hipSuccess) return false;
+      rs = status_of(ist);
+      if (rs != LF_OK) s->err = "degenerate or non-finite object transform";
+      else s->rays_primary += s->tickets[done.second].rays;
+    }
     finish_ticket(s, done.second, rs, t);
   }
   L.tiles.clear();
@@ -458,6 +467,7 @@ lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **o
   sc.chunk = lf::kChunk;
   s->sched = lf::Scheduler(sc);
   s->slot_ticket.assign(cfg->max_slots, 0);
+  s->slot_fail.assign(cfg->max_slots, LF_OK);
   s->slots = std::vector<SlotDev>(cfg->max_slots);
   s->lanes = std::vector<Lane>(cfg->max_in_flight);
   const int64_t B = cfg->batch_rays;

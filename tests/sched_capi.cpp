@@ -72,6 +72,8 @@ int sched_retire(void *s, const int64_t *tiles, int n_tiles, int64_t *out, int c
   return n;
 }
 
+void sched_fail(void *s, int slot) { ((lf::Scheduler *)s)->fail(slot); }
+int sched_failed(void *s, int slot) { return ((lf::Scheduler *)s)->failed(slot) ? 1 : 0; }
 int sched_active(void *s) { return ((lf::Scheduler *)s)->active(); }
 int sched_pending(void *s) { return ((lf::Scheduler *)s)->pending(); }
 int64_t sched_used(void *s) { return ((lf::Scheduler *)s)->used(); }

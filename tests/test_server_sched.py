@@ -29,6 +29,7 @@ def S(tmp_path_factory):
         getattr(L, f).argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int]
     L.sched_retire.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int64), C.c_int]
     L.sched_active.argtypes = L.sched_pending.argtypes = L.sched_used.argtypes = [C.c_void_p]
+    L.sched_fail.argtypes = L.sched_failed.argtypes = [C.c_void_p, C.c_int]
     L.sched_used.restype = C.c_int64
     return L
 
@@ -60,6 +61,12 @@ class Sched:
         out = (C.c_int64 * 256)()
         n = self.L.sched_retire(self.h, arr, len(tiles), out, 128)
         return [(out[2 * i], out[2 * i + 1]) for i in range(n)]
+
+    def fail(self, slot):
+        self.L.sched_fail(self.h, slot)
+
+    def failed(self, slot):
+        return bool(self.L.sched_failed(self.h, slot))
 
     active = property(lambda self: self.L.sched_active(self.h))
     pending = property(lambda self: self.L.sched_pending(self.h))
@@ -213,3 +220,48 @@ def test_round_robin_serves_everyone(S):
             served[slot] += 1
         s.retire(tiles)
     assert served.min() == 4 and served.max() == 4
+
+
+@pytest.mark.parametrize("policy", [SHORTEST, OLDEST, ROUND_ROBIN])
+def test_failed_pass_stops_planning_and_waits_for_passes_in_flight(S, policy):
+    """A pass that latched a device status fails its requests: none of them
+    is planned again, and each completes (slot and budget released) only
+    when every pass already launched with its tiles has retired, so no pass
+    in flight writes into a request after it is reported."""
+    s = Sched(S, max_slots=2, budget=100, tile=256, batch=1024, policy=policy)
+    assert s.submit(1, 4096, cost=30) == 0 and s.submit(2, 256, cost=30) == 0
+    adm = dict((t, sl) for sl, t in s.admit())
+    a = adm[1]
+    p1 = s.plan()  # two passes in flight, both holding tiles of request 1
+    p2 = s.plan()
+    assert any(t[0] == a for t in p1) and any(t[0] == a for t in p2)
+    # pass 1 fails: request 1 is failed, but pass 2 still writes into it
+    for t in p1:
+        s.fail(t[0])
+    assert s.failed(a)
+    done1 = s.retire(p1)
+    assert all(tk != 1 for _, tk in done1), done1
+    assert s.used >= 30  # request 1 still holds its budget
+    # no further tiles of request 1
+    for _ in range(20):
+        p = s.plan()
+        assert all(t[0] != a for t in p), p
+        if not p:
+            break
+        s.retire(p)
+    # the last pass holding its tiles retires: now request 1 completes
+    done2 = s.retire(p2)
+    assert (a, 1) in done2, done2
+    assert not any(tk == 1 for _, tk in s.retire([])), "reported twice"
+    # the freed slot takes a new request
+    assert s.submit(3, 256, cost=30) == 0
+    assert any(tk == 3 for _, tk in s.admit())
+
+
+def test_failing_a_request_with_nothing_in_flight(S):
+    s = Sched(S, max_slots=1, budget=100, tile=256, batch=512, policy=OLDEST)
+    s.submit(1, 1024, cost=10)
+    (sl, _), = s.admit()
+    p = s.plan()
+    s.fail(sl)
+    assert s.retire(p) == [(sl, 1)] and s.used == 0 and s.active == 0
