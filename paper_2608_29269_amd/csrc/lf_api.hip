@@ -565,7 +565,7 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
     return fail(c, LF_EDEVICE, "hierarchy build produced an out-of-range index");
   }
   // the traversal stack holds one entry per level above the current node,
-  // naming a node by 24 bits
+  // naming a node by 23 bits
   if (c->wide_levels - 1 > lf::kStackL)
     return fail(c, LF_EUNSUPPORTED, "%d node levels need more than the traversal stack (%d entries)",
                 c->wide_levels, lf::kStackL);

@@ -732,8 +732,46 @@ __global__ void k_wide_assign(const BNode *nodes, int64_t n_nodes, int64_t n, in
       n_int += c >= 0;
     }
   }
+  // Internal children in order of their box centres along the axis on which
+  // those centres spread most (insertion sort, stable); the traversal visits
+  // a node's remaining children in this order or its reverse, whichever runs
+  // along the ray, so nearer subtrees tend to come first.
+  int axis = 0;
+  if (n_int > 1) {
+    float cen[kWide][3], cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int q = 0; q < n_int; ++q) {
+      const BNode &nd = nodes[srcs[q] >> 1];
+      const float *bl = (srcs[q] & 1) ? nd.lo1 : nd.lo0, *bh = (srcs[q] & 1) ? nd.hi1 : nd.hi0;
+      for (int k = 0; k < 3; ++k) {
+        const float c = 0.5f * bl[k] + 0.5f * bh[k];
+        cen[q][k] = c == c ? c : 0.0f;
+        cmin[k] = fminf(cmin[k], cen[q][k]);
+        cmax[k] = fmaxf(cmax[k], cen[q][k]);
+      }
+    }
+    float best = -1.0f;
+    for (int k = 0; k < 3; ++k)
+      if (cmax[k] - cmin[k] > best) {
+        best = cmax[k] - cmin[k];
+        axis = k;
+      }
+    for (int q = 1; q < n_int; ++q) {
+      const int32_t sq = srcs[q], cq = code[q];
+      const float key = cen[q][axis];
+      float c3[3] = {cen[q][0], cen[q][1], cen[q][2]};
+      int j = q;
+      for (; j > 0 && cen[j - 1][axis] > key; --j) {
+        srcs[j] = srcs[j - 1];
+        code[j] = code[j - 1];
+        for (int k = 0; k < 3; ++k) cen[j][k] = cen[j - 1][k];
+      }
+      srcs[j] = sq;
+      code[j] = cq;
+      for (int k = 0; k < 3; ++k) cen[j][k] = c3[k];
+    }
+  }
   for (int q = 0; q < kWide; ++q) wi.src[q] = q < m ? srcs[q] : kNoSlot;
-  wi.imask = (1u << n_int) - 1u;
+  wi.imask = ((1u << n_int) - 1u) | ((uint32_t)axis << 8);
   int32_t dnext = db + n_int, lnext = lb + (m - n_int);
   int ki = 0, kl = 0;
   for (int q = 0; q < m; ++q) {
@@ -873,7 +911,7 @@ __global__ void k_wide_quantize(const BNode *nodes, const WideInfo *info, int64_
   nd.imask = (uint8_t)wi.imask;
   nd.child_base = wi.child_base;
   nd.leaf_base = wi.leaf_base;
-  nd.vmask = vmask;
+  nd.vmask = vmask | (((wi.imask >> 8) & 3u) << 8);
   out[j] = nd;
 }
 

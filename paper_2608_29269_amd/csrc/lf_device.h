@@ -393,7 +393,7 @@ __device__ __forceinline__ void make_rayf(d3 oo, d3 dd, double tabs, float omag,
 // below i).
 __device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, float tlo, float thi, float *t,
                                            uint32_t &ihit, uint32_t &lhit, uint32_t &imask, int &cbase,
-                                           int &lbase) {
+                                           int &lbase, bool &desc) {
   constexpr int kDw = (int)sizeof(QNode) / 4;
   constexpr int kPw = kWide / 4;  // dwords per plane
   uint32_t dw[kDw];
@@ -416,6 +416,10 @@ __device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, fl
   cbase = (int)dw[4];
   lbase = (int)dw[5];
   const uint32_t vmask = dw[6];
+  // the internal children run along the ray in descending slot order when
+  // the ray points down the node's order axis
+  const uint32_t oax = (vmask >> 8) & 3u;
+  desc = oax == 0 ? !rf.sx : (oax == 1 ? !rf.sy : !rf.sz);
   // codes of the near and far plane of each axis: lower codes for d >= 0
   uint32_t nx[kPw], ny[kPw], nz[kPw], fx[kPw], fy[kPw], fz[kPw];
 #pragma unroll
@@ -648,10 +652,12 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 // kStackL entries) and lq at its first leaf-queue slot (stride kBlock,
 // kLeafQ entries).  A node's internal children occupy its first slots, so a
 // stack entry names all the hit internal children of one visited node that
-// are still to be visited: (child_base << 8) | slot mask.  The stack thus
-// holds at most one entry per level above the current node, and the build
-// guarantees that the hierarchy is shallow enough.  Every lane leaves once
-// the pool is empty and its last ray is stored.
+// are still to be visited: (descending << 31) | (child_base << 8) | slot
+// mask, taken lowest slot first, or highest first when descending (the
+// children are ordered along an axis; descending when the ray points down
+// it).  The stack thus holds at most one entry per level above the current
+// node, and the build guarantees that the hierarchy is shallow enough.
+// Every lane leaves once the pool is empty and its last ray is stored.
 
 template <int K, class Work>
 __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work &wk, int64_t count, uint32_t *next,
@@ -675,10 +681,12 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
   // entry goes once its mask is empty
   auto pop = [&]() -> int {
     int *e = stk + (sp - 1) * kBlock;
-    const uint32_t v = (uint32_t)*e, m = v & 0xffu, rest = m & (m - 1u);
+    const uint32_t v = (uint32_t)*e, m = v & 0xffu;
+    const int b = (v >> 31) ? 31 - __builtin_clz(m) : __builtin_ctz(m);
+    const uint32_t rest = m & ~(1u << b);
     if (rest) *e = (int)((v & ~0xffu) | rest);
     else --sp;
-    return (int)(v >> 8) + __builtin_ctz(m);
+    return (int)((v >> 8) & 0x7fffffu) + b;
   };
   SceneView S = S0;
   KBufF<K> kb;
@@ -785,7 +793,8 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
       float ts[kWide];
       uint32_t ih, lh, im;
       int cbase, lbase;
-      visit_node(S.nodes + cur, rf, tlo, thi, ts, ih, lh, im, cbase, lbase);
+      bool desc;
+      visit_node(S.nodes + cur, rf, tlo, thi, ts, ih, lh, im, cbase, lbase, desc);
       // hit leaves join the queue, in slot order (leaf slots follow the
       // node's internal ones)
       const int leaf0 = lbase - __builtin_popcount(im);
@@ -810,7 +819,7 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
           cur = kDone;
           continue;
         }
-        stk[(sp++) * kBlock] = (int)(((uint32_t)cbase << 8) | rest);
+        stk[(sp++) * kBlock] = (int)((desc ? 0x80000000u : 0u) | ((uint32_t)cbase << 8) | rest);
         ++c_push;
         c_deep = sp > c_deep ? sp : c_deep;
       }

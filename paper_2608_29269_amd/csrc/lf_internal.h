@@ -12,7 +12,7 @@ constexpr int kBlock = 128;       // threads per block of the tracing kernels (2
 constexpr int kWide = 8;          // children per traversal node
 constexpr int kStackL = 24;       // traversal stack entries per lane, in LDS (12 KB per block): one per
                                   // level above the current node, so hierarchies of up to kStackL + 1 levels
-constexpr int kMaxWideNodes = 1 << 24;  // a stack entry holds a node index in 24 bits
+constexpr int kMaxWideNodes = 1 << 23;  // a stack entry holds a node index in 23 bits
 constexpr int kLeafQ = 56;        // leaf-queue entries per lane (LDS, 28 KB per block)
 constexpr int kLeafMin = 12;       // the node phase goes on while a lane that can visit nodes has fewer queued
 // Persistent traversal splits its items into kPoolParts contiguous ranges
@@ -72,14 +72,15 @@ static_assert(sizeof(BNode) == 64, "BNode layout");
 // for.  Slots 0..m-1 are occupied, internal children first: slot i < n_int
 // (n_int = popcount(imask), imask = (1 << n_int) - 1) holds node
 // child_base + i, slot i >= n_int holds leaf (surfel position)
-// leaf_base + i - n_int.  80 bytes for kWide = 8.
+// leaf_base + i - n_int.  The internal children are ordered by their box
+// centres along axis (vmask >> 8) & 3.  80 bytes for kWide = 8.
 struct alignas(16) QNode {
   float p[3];
   int8_t e[3];
   uint8_t imask;          // bit i: slot i holds an internal node (the first slots)
   int32_t child_base;
   int32_t leaf_base;
-  uint32_t vmask;         // bit i: slot i holds a child with a non-empty box
+  uint32_t vmask;         // bit i < 8: slot i holds a child with a non-empty box; bits 8-9: order axis
   uint8_t q[6][kWide];    // lower x, y, z then upper x, y, z codes per slot
 };
 static_assert(sizeof(QNode) == (kWide == 8 ? 80 : 64), "QNode layout");
