@@ -47,7 +47,13 @@ def parse():
     ap.add_argument("--spp", type=int, default=4)
     ap.add_argument("--res", type=int, default=1024)
     ap.add_argument("--scale", type=float, default=1.0, help="surfel-count scale (1.0 = 1M surfels)")
-    ap.add_argument("--cpu-sample", type=int, default=4096, help="primary rays of the CPU-baseline sample")
+    ap.add_argument("--cpu-sample", type=int, default=1024,
+                    help="primary rays of the CPU-baseline sample on all cores (median of 3 runs)")
+    ap.add_argument("--cpu-sample-1core", type=int, default=128,
+                    help="primary rays of the single-core CPU-baseline sample (median of 3 runs; 0 = skip)")
+    ap.add_argument("--s1-steps", type=int, default=3, help="timed steps of the S = 1 leg (0 = skip)")
+    ap.add_argument("--config-rows", type=str, default="1,2,3,4",
+                    help="comma-separated configurations C1-C4 timed as secondary rows (empty = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fwd-steps", type=int, default=5)
     ap.add_argument("--geo-steps", type=int, default=10, help="timed geometry-refinement steps (0 = skip)")
@@ -55,8 +61,8 @@ def parse():
                     help="iterations of the staged inverse-rendering loop (0 = skip)")
     ap.add_argument("--nee-spp", type=str, default="8,16,32",
                     help="comma-separated spp of the two-ray estimator's training steps (empty = skip)")
-    ap.add_argument("--serve-requests", type=int, default=40, help="requests per serving run (0 = skip)")
-    ap.add_argument("--serve-loads", type=str, default="0.8",
+    ap.add_argument("--serve-requests", type=int, default=300, help="requests per serving run (0 = skip)")
+    ap.add_argument("--serve-loads", type=str, default="0.5,0.8",
                     help="comma-separated arrival rates as fractions of the plain tracer's capacity")
     ap.add_argument("--serve-policies", type=str, default="0,1",
                     help="comma-separated pass-filling policies (0 shortest first, 1 oldest first, 2 round robin)")
@@ -191,22 +197,23 @@ def main():
     counts = None
     if not args.no_cpu_baseline:
         log(f"forward: {fwd_rays_s:.4g} rays/s; CPU oracle on {args.cpu_sample} rays")
-        import oracle
-        rng = np.random.default_rng(0)
-        pix = np.sort(rng.choice(nr, args.cpu_sample, replace=False))
-        o, d, ids = oracle.raygen(cam, pix)
-        sa = oracle.SceneArrays(sc, st.R, st.t, st.env)
-        p = oracle.Params(k=wl.k, spp=args.spp, seed=wl.seed)
-        c0 = time.perf_counter()
-        ref = oracle.render(sa, o, d, ids, p, lists=False)
-        oracle.backward(sa, o, d, ids, p, g_radiance=np.sign(ref["radiance"]) / (3.0 * nr))
-        cdt = time.perf_counter() - c0
-        counts = ref["counts"]
-        crays = len(pix) + counts[:, oracle.C_SEC_RAYS].sum()
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-        cpu = {"value": float(crays / cdt), "unit": "rays/s", "cores": int(threads), "kind": "oracle",
-               "sample": f"{len(pix)} random pixels of the 1024x1024 camera (plus their live secondary rays), "
-                         f"fwd+bwd, 1M surfels brute force in FP64, {cdt:.1f} s"}
+        v, secs, counts = cpu_oracle_rate(sc, st, cam, wl, args.spp, args.cpu_sample, threads, nr, seed=0)
+        cpu = {"value": v, "unit": "rays/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"{args.cpu_sample} random pixels of the 1024x1024 camera (plus their live secondary "
+                         f"rays), fwd+bwd, 1M surfels brute force in FP64; median of 3 runs "
+                         f"({', '.join(f'{x:.1f}' for x in secs)} s)"}
+        if args.cpu_sample_1core > 0:
+            log(f"CPU oracle on one core, {args.cpu_sample_1core} rays")
+            v1, secs1, _ = cpu_oracle_rate(sc, st, cam, wl, args.spp, args.cpu_sample_1core, 1, nr, seed=1)
+            cpu["single_core"] = {"value": v1, "cores": 1,
+                                  "sample": f"{args.cpu_sample_1core} random pixels, same work; median of 3 "
+                                            f"runs ({', '.join(f'{x:.1f}' for x in secs1)} s)"}
+
+    s1 = None
+    if args.s1_steps > 0:
+        log("S = 1 leg")
+        s1 = s1_bench(tr, env, R, t, cam, wl, params, grads, out, target, args.s1_steps)
 
     estimator = None
     nee_spp = [int(x) for x in args.nee_spp.split(",") if x]
@@ -229,7 +236,16 @@ def main():
         serving = serve_bench(tr, sc, args, [float(x) for x in args.serve_loads.split(",") if x],
                               [int(x) for x in args.serve_policies.split(",") if x])
 
-    roof = roofline(phases, counts, stats, args, nr)
+    rows = None
+    cfg_rows = [int(x) for x in args.config_rows.split(",") if x]
+    if cfg_rows:
+        log(f"configuration rows {cfg_rows}")
+        del tr
+        torch.cuda.empty_cache()
+        rows = config_rows(lf, cfg_rows)
+
+    copy_gbs = copy_bandwidth(torch)
+    roof = roofline(phases, counts, stats, args, nr, copy_gbs)
     res = {
         "metric": "rays/s fwd+bwd at 1M surfels",
         "value": float(value),
@@ -248,6 +264,8 @@ def main():
                                "refit + forward + L1 + replayed backward + SGD per step",
                    "surfels": int(sc.n), "resolution": [cam.w, cam.h], "k": wl.k, "spp": args.spp},
         "fwd_rays_per_s": float(fwd_rays_s),
+        "s1": s1,
+        "config_rows": rows,
         "rays_per_step": {"primary": stats["rays_primary"] / args.steps,
                           "secondary": stats["rays_secondary"] / args.steps},
         "bvh_build_ms": build_ms,
@@ -262,6 +280,162 @@ def main():
         "serving": serving,
     }
     print(json.dumps(res))
+
+
+def cpu_oracle_rate(sc, st, cam, wl, spp, n_pix, threads, nr, seed):
+    """The FP64 oracle's fwd+bwd rays/s on n_pix random pixels of the camera
+    (plus their live secondary rays) with `threads` OpenMP threads: median of
+    3 runs.  Also returns the per-ray counts of the first run."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    pix = np.sort(rng.choice(nr, n_pix, replace=False))
+    o, d, ids = oracle.raygen(cam, pix)
+    sa = oracle.SceneArrays(sc, st.R, st.t, st.env)
+    p = oracle.Params(k=wl.k, spp=spp, seed=wl.seed)
+    rates, secs, counts = [], [], None
+    for _ in range(3):
+        c0 = time.perf_counter()
+        ref = oracle.render(sa, o, d, ids, p, lists=False, threads=threads)
+        oracle.backward(sa, o, d, ids, p, g_radiance=np.sign(ref["radiance"]) / (3.0 * nr), threads=threads)
+        cdt = time.perf_counter() - c0
+        if counts is None:
+            counts = ref["counts"]
+        rays = len(pix) + ref["counts"][:, oracle.C_SEC_RAYS].sum()
+        rates.append(rays / cdt)
+        secs.append(cdt)
+    return float(np.median(rates)), secs, counts
+
+
+def s1_bench(tr, env, R, t, cam, wl, params, grads, out, target, steps, lr=1e-5):
+    """M1 (forward) and M2 (fwd+bwd) rays/s at S = 1 on the benchmark scene
+    and camera: one warm-up, then `steps` timed steps of each."""
+    import torch
+    cfg = dict(cameras=[cam], k=wl.k, spp=1, seed=wl.seed)
+
+    def step():
+        tr.refit()
+        tr.render(env, R, t, out=out, **cfg)
+        loss, g = tr.l1_loss(out["radiance"], target)
+        tr.render_backward(env, R, t, d_radiance=g, grads=grads, **cfg)
+        with torch.no_grad():
+            for k_, v in params.items():
+                v.sub_(lr * grads[k_])
+            params["scale"].clamp_(min=1e-4)
+            params["opacity"].clamp_(1e-4, 1.0)
+            for k_ in ("albedo", "roughness", "metallic"):
+                params[k_].clamp_(0.0, 1.0)
+
+    step()
+    tr.sync()
+    tr.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = tr.stats()
+    fb = (st["rays_primary"] + st["rays_secondary"]) / dt
+    tr.render(env, R, t, out=out, **cfg)
+    tr.sync()
+    tr.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.refit()
+        tr.render(env, R, t, out=out, **cfg)
+    torch.cuda.synchronize()
+    dtf = time.perf_counter() - t0
+    sf = tr.stats()
+    res = {"fwd_bwd_rays_per_s": fb, "fwd_bwd_ms_per_step": dt * 1e3 / steps,
+           "fwd_rays_per_s": (sf["rays_primary"] + sf["rays_secondary"]) / dtf,
+           "fwd_ms": dtf * 1e3 / steps, "secondary_rays_per_step": sf["rays_secondary"] / steps}
+    log(f"S=1: fwd+bwd {fb:.4g} rays/s, fwd {res['fwd_rays_per_s']:.4g} rays/s")
+    return res
+
+
+def config_rows(lf, which, steps=3):
+    """Secondary rows: configurations C1-C4 at their full sizes, each in its
+    own context.  C1 (4k volume surfels, 64x64, k=16, primary only) and C2
+    (200k surface surfels, 800x800, S=1) forward; C3 (300k surfels, 4 x
+    800x800, S=1) the training step against a render of the perturbed
+    scene; C4 (500k + 8 x 20k instanced surfels, 4 states at 1024x1024, S=4)
+    forward and backward of every state with its own transforms and map.
+    One warm-up, then `steps` timed repetitions; rays are traced rays."""
+    import torch
+    import scenegen
+    dev = torch.device("cuda", 0)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)  # noqa: E731
+    rows = {}
+    for i in which:
+        wl = scenegen.make_workload(i)
+        sc = wl.scene
+        tr = lf.Tracer(0)
+        p = dict(mu=T(sc.mu), q=T(sc.q), scale=T(sc.scale), opacity=T(sc.opacity), albedo=T(sc.albedo),
+                 roughness=T(sc.roughness), metallic=T(sc.metallic))
+        tr.set_scene(**p, object_offset=list(sc.object_offset))
+        sts = [(T(s_.env), T(s_.R) if sc.n_objects else None, T(s_.t) if sc.n_objects else None, s_.cameras)
+               for s_ in wl.states]
+        flags = lf.FLAG_NO_SECONDARY if wl.no_secondary else 0
+        targets = None
+        if i == 3:  # L1 target rendered from the perturbed scene and map
+            ttr = lf.Tracer(0)
+            ts_ = wl.target_scene
+            ttr.set_scene(T(ts_.mu), T(ts_.q), T(ts_.scale), T(ts_.opacity), T(ts_.albedo), T(ts_.roughness),
+                          T(ts_.metallic), list(ts_.object_offset))
+            targets = [ttr.render(T(wl.target_envs[0]), None, None, cameras=sts[0][3], k=wl.k, spp=wl.spp,
+                                  seed=wl.seed)["radiance"].clone()]
+            ttr.sync()
+            del ttr
+
+        def run():
+            for j, (env, R, t, cams) in enumerate(sts):
+                out = tr.render(env, R, t, cameras=cams, k=wl.k, spp=wl.spp, seed=wl.seed + j, flags=flags)
+                if i in (3, 4):
+                    tgt = targets[j] if targets else torch.zeros_like(out["radiance"])
+                    _, g = tr.l1_loss(out["radiance"], tgt)
+                    tr.render_backward(env, R, t, cameras=cams, k=wl.k, spp=wl.spp, seed=wl.seed + j, flags=flags,
+                                       d_radiance=g)
+
+        run()
+        tr.sync()
+        tr.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = tr.stats()
+        rays = st["rays_primary"] + st["rays_secondary"]
+        rows[f"C{i}"] = {"workload": wl.name, "surfels": int(sc.n), "pass": "fwd+bwd" if i in (3, 4) else "fwd",
+                         "rays_per_s": rays / dt, "ms_per_step": dt * 1e3 / steps,
+                         "rays_per_step": rays / steps}
+        log(f"C{i}: {rows[f'C{i}']['rays_per_s']:.4g} rays/s, {dt * 1e3 / steps:.1f} ms per step")
+        tr.sync()
+        del tr
+        torch.cuda.empty_cache()
+    return rows
+
+
+def copy_bandwidth(torch):
+    """Device-to-device copy of 1 GiB: bytes read + written over the median
+    of 5 timed copies (HIP events on torch's stream)."""
+    src = torch.empty(1 << 28, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    times = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    gbs = 2.0 * src.numel() * 4 / (float(np.median(times)) * 1e-3) / 1e9
+    del src, dst
+    return gbs
 
 
 def estimator_bench(lf, tr, env, R, t, cam, wl, params, grads, out, target, spps, lr=1e-5):
@@ -628,15 +802,19 @@ def kernel_bytes(counts, stats, steps):
     return {k: per_ray[k] * rays[k] for k in per_ray}, per_ray, rays
 
 
-def roofline(phases, counts, stats, args, nr):
+def roofline(phases, counts, stats, args, nr, copy_gbs=None):
     """Roofline of the dominant kernel: algorithmic bytes per launch over its
     average launch duration, measured with HIP events on the library's stream
-    (each of these phases holds exactly one launch per call)."""
+    (each of these phases holds exactly one launch per call).  Also against
+    the measured device-to-device copy bandwidth, and with the counter
+    evidence (HBM traffic, L2 hit rate, VALU issue) taken at the current
+    kernel sources."""
     cand = {k: v for k, v in phases.items() if k in KERNEL_OF_PHASE and v[1]}
     name, (ms, n) = max(cand.items(), key=lambda kv: kv[1][0])
     avg_ms = ms / n
     out = {"bound": "hbm", "kernel": KERNEL_OF_PHASE[name], "phase": name, "avg_ms": avg_ms, "achieved": None,
-           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None}
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None, "l2_hit_rate": None,
+           "copy_GBs": copy_gbs}
     if counts is None:
         return out
     per_launch, per_ray, rays = kernel_bytes(counts, stats, args.steps)
@@ -646,6 +824,17 @@ def roofline(phases, counts, stats, args, nr):
     out.update(achieved=float(achieved), frac=float(achieved / HBM_PEAK_GBS),
                alg_bytes_per_launch=float(per_launch[name]), alg_bytes_per_ray=float(per_ray[name]),
                rays_per_launch=float(rays[name]))
+    if copy_gbs:
+        out["frac_of_copy"] = float(achieved / copy_gbs)
+    lf_ = os.path.join(ROOT, "profiles", "l2.json")
+    if os.path.exists(lf_):
+        try:
+            lj = json.load(open(lf_))
+            e = lj.get("kernels", {}).get(out["kernel"])
+            if e and lj.get("source_digest") == source_digest():
+                out["l2_hit_rate"] = e["hit_rate"]
+        except (OSError, ValueError, KeyError):
+            out["l2_hit_rate"] = None
     tf = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tf):
         try:

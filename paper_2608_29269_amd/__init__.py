@@ -309,7 +309,8 @@ class Tracer:
         self._chk(self.L.lf_trace_counters(self.ctx, c))
         keys = ("rays", "nodes", "tests", "inserts")
         p, s_ = dict(zip(keys, c[:4])), dict(zip(keys, c[4:8]))
-        for i, name in enumerate(("ties", "prefilter_pass", "valid_hits", "stack_pushes", "stack_deepest")):
+        for i, name in enumerate(("ties", "prefilter_pass", "valid_hits", "stack_pushes", "stack_deepest",
+                                  "hinted", "hint_retries")):
             p[name], s_[name] = c[8 + 2 * i], c[9 + 2 * i]
         return {"primary": p, "secondary": s_}
 

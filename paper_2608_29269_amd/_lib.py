@@ -105,7 +105,7 @@ class ServerStats(C.Structure):
 
 
 NUM_PHASES = 17
-NUM_COUNTERS = 18  # LF_NUM_COUNTERS
+NUM_COUNTERS = 22  # LF_NUM_COUNTERS
 PHASES = ("refit", "state_env", "trace1", "shade1", "sort2", "trace2", "shade2", "resolve", "replay_primary",
           "replay_secondary", "adj_shade", "unused11", "zero_grads", "loss", "composite1", "composite2", "adj_hits")
 

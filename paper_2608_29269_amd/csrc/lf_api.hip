@@ -81,6 +81,8 @@ struct Phase {
 namespace lfh {
 
 lf_status refit_impl(lf_ctx *c, double alpha_min, double sig2) {
+  ++c->scene_epoch;
+  c->sig_valid = false;
   Phase ph(c, 0);
   lf::launch_refit(c->s, alpha_min, sig2, c->perm.as<int32_t>(), c->leaf_parent.as<int32_t>(),
                    c->node_parent.as<int32_t>(), c->node_order.as<int32_t>(), c->h_level_off, c->n_nodes, c->n_inst,
@@ -257,6 +259,8 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
     if (!c->queue.ensure(sizeof(lf::SecEntry) * (RS > 0 ? RS : 1)) || !c->qcount.ensure(sizeof(uint32_t)) ||
         !c->rec2.ensure(sizeof(lf::SurfRec) * (RS > 0 ? RS : 1)))
       return fail(c, LF_ENOMEM, "secondary queue");
+    if (!c->hint2.ensure(sizeof(float) * (RS > 0 ? RS : 1))) return fail(c, LF_ENOMEM, "secondary bounds");
+    a.hint2 = c->hint2.as<float>();
     a.queue = c->queue.as<lf::SecEntry>();
     a.queue_count = c->qcount.as<uint32_t>();
     a.rec2 = c->rec2.as<lf::SurfRec>();
@@ -270,6 +274,40 @@ lf_status prepare(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, cons
     }
   }
   return check_hip(c, "prepare");
+}
+
+// Signature of a render call whose arguments prepare() accepted (cameras
+// as uploaded to c->h_cams).
+lfh::CallSig call_sig(const lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, const lf_rays *rays,
+                      const lf_params *p) {
+  lfh::CallSig g;
+  memset(&g, 0, sizeof g);  // padding included, so signatures compare with memcmp
+  if (rays) {
+    g.ro = rays->o;
+    g.rd = rays->d;
+    g.n = rays->n;
+  } else {
+    g.cams = c->h_cams;
+  }
+  g.k = p->k;
+  g.spp = p->spp;
+  g.seed = p->seed;
+  g.flags = p->flags & ~(LF_FLAG_COUNT | LF_FLAG_DETERMINISTIC);
+  g.alpha_min = p->alpha_min;
+  g.alpha_cap = p->alpha_cap;
+  g.sigma = p->support_sigma;
+  g.eps = p->eps;
+  g.t_min = p->t_min;
+  g.sec_off = p->secondary_offset;
+  g.env = env->texels;
+  g.h = env->h;
+  g.w = env->w;
+  if (c->n_inst > 1 && xf) {
+    g.R = xf->R;
+    g.t = xf->t;
+  }
+  g.epoch = c->scene_epoch;
+  return g;
 }
 
 // regroups the secondary queue by direction octant and origin for coherent traversal
@@ -589,10 +627,15 @@ lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, co
   if (!c) return LF_EINVAL;
   if (!out) return fail(c, LF_EINVAL, "outputs struct is NULL");
   set_device(c);
+  const bool had_sig = c->sig_valid;
+  c->sig_valid = false;
   lf::RenderArgs a;
   lf_status st = prepare(c, xf, env, rays, cams, n_cams, p, a);
   if (st) return st;
   if (a.R == 0) return LF_OK;
+  // the same rays as the previous call: start each from its earlier k-th distance
+  const lfh::CallSig sig = call_sig(c, xf, env, rays, p);
+  a.use_hint = had_sig && memcmp(&sig, &c->last_sig, sizeof sig) == 0;
   if (!out->radiance || !out->depth || !out->normal || !out->alpha)
     return fail(c, LF_EINVAL, "radiance, depth, normal and alpha outputs are required");
   a.radiance = out->radiance;
@@ -642,7 +685,22 @@ lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, co
     lf::launch_accum(c->acc_secondary.as<unsigned long long>(), a.queue_count, c->stream);
   }
   c->acc_primary += a.R;
-  return check_hip(c, "render");
+  st = check_hip(c, "render");
+  if (st == LF_OK) {
+    c->last_sig = sig;
+    c->sig_valid = true;
+  }
+  return st;
+}
+
+// A backward call that ran: its replay left the k-buffers of its own rays.
+static lf_status backward_done(lf_ctx *c, const lfh::CallSig &sig) {
+  const lf_status st = check_hip(c, "backward");
+  if (st == LF_OK) {
+    c->last_sig = sig;
+    c->sig_valid = true;
+  }
+  return st;
 }
 
 // Smallest b with 2^b > n: keys below 2^b sort in ceil(b / 16) * 2 radix passes
@@ -693,9 +751,15 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
       !gi->d_metallic || !gi->d_env)
     return fail(c, LF_EINVAL, "all eight gradient outputs are required");
   set_device(c);
+  const bool had_sig = c->sig_valid;
+  c->sig_valid = false;
   lf::RenderArgs a;
   lf_status st = prepare(c, xf, env, rays, cams, n_cams, p, a);
   if (st) return st;
+  // the replay traces the rays of the forward call with the same arguments:
+  // each starts from the k-th distance that call left in the k-buffers
+  const lfh::CallSig sig = call_sig(c, xf, env, rays, p);
+  a.use_hint = had_sig && memcmp(&sig, &c->last_sig, sizeof sig) == 0;
   const int64_t n = c->s.n;
   hipStream_t s = c->stream;
   {
@@ -744,7 +808,7 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
       Phase ph(c, 16);
       lf::launch_adjoint_hits_det(a, ga, d, s);
     }
-    return check_hip(c, "backward");
+    return backward_done(c, sig);
   }
   {
     Phase ph(c, 10);
@@ -754,7 +818,7 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
     Phase ph(c, 16);
     lf::launch_adjoint_hits(a, ga, s);
   }
-  return check_hip(c, "backward");
+  return backward_done(c, sig);
 }
 
 lf_status lf_l1_loss(lf_ctx *c, const float *pred, const float *target, int64_t n, float *loss, float *grad) {

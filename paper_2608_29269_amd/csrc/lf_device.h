@@ -599,7 +599,8 @@ __device__ __forceinline__ int exact_insert_rec(const SceneView &S, const TraceR
   bool flip;
   if (!exact_hit(rec, o, d, t_min, t, flip)) return 4;
   const float tf = (float)t;
-  if (tf > tk) return 12;
+  // beyond the k-th key, or at the key of a bound sentinel still in the k-th slot
+  if (tf > tk || (tf == tk && kb.id[K - 1] == kIdMask)) return 12;
   const uint32_t id = (uint32_t)pos | (flip ? kFlipBit : 0u);
   bool tie = false;
 #pragma unroll
@@ -641,6 +642,7 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 // counters).  Work supplies
 //   bool begin(int64_t item, d3 &o, d3 &d, const InstRec *&inst)  (false: nothing to trace)
 //   void store(int64_t item, const KBufF<K> &kb)
+//   float hint(int64_t item)  (a k-th distance the ray had before, or +inf)
 //   static constexpr int kRefill; static constexpr bool kPrefetch (see the exact loop)
 // Traversal of an instance runs in rounds of two phases (after Aila and
 // Laine 2009, "while-while"): in the node phase a lane visits nodes, its hit
@@ -658,6 +660,15 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 // it).  The stack thus holds at most one entry per level above the current
 // node, and the build guarantees that the hierarchy is shallow enough.
 // Every lane leaves once the pool is empty and its last ray is stored.
+//
+// With a finite hint h the ray starts with its empty k-buffer slots keyed
+// at B = the binary32 successor of h instead of +inf, so nodes and surfels
+// beyond B are culled from the start; a hit keyed at B or beyond is not
+// taken while such a bound sentinel holds the k-th slot.  If a sentinel
+// still holds the k-th slot when the ray is done, fewer than k valid hits
+// lie below B, and the ray is traced again from the start with +inf; else
+// its k hits are exactly the k nearest (every hit below B was found).  So
+// the result never depends on the hint, only the work does.
 
 template <int K, class Work>
 __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work &wk, int64_t count, uint32_t *next,
@@ -668,6 +679,8 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
   const float tlo = (float)(0.5 * P.t_min);
   const int lane = (int)(threadIdx.x & 63u);
   uint32_t c_rays = 0, c_nodes = 0, c_tests = 0, c_ins = 0, c_ties = 0, c_pass = 0, c_hits = 0, c_push = 0;
+  uint32_t c_hinted = 0, c_retry = 0;
+  bool bounded = false;  // the ray's k-buffer started from a finite bound
   int c_deep = 0;
   auto count_test = [&](int r) {
     c_ins += r & 1;
@@ -731,6 +744,14 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
             if (live) {
               ++c_rays;
               kinit<K>(kb, P.k);
+              const float h = wk.hint(item);
+              bounded = h >= 0.0f && h < INFINITY;
+              if (bounded) {
+                const float bnd = next_up_f(h);
+#pragma unroll
+                for (int j = 0; j < K; ++j) kb.t[j] = kb.t[j] == INFINITY ? bnd : kb.t[j];
+                ++c_hinted;
+              }
               ii = -1;
               cur = kDone;
               qn = 0;
@@ -754,7 +775,15 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
         found = true;
         break;
       }
-      if (!found) {
+      if (!found && bounded && kb.id[K - 1] == kIdMask) {
+        // fewer than k valid hits below the bound: trace the ray again without it
+        bounded = false;
+        ++c_retry;
+        kinit<K>(kb, P.k);
+        ii = -1;
+        cur = kDone;
+        qn = 0;
+      } else if (!found) {
         wk.store(item, kb);
         live = false;
       } else if (brute) {  // every surfel of the instance; the next round moves on
@@ -902,6 +931,8 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
     atomicAdd(P.counters + 12 + counter_base / 4, (unsigned long long)c_hits);
     atomicAdd(P.counters + 14 + counter_base / 4, (unsigned long long)c_push);
     atomicMax(P.counters + 16 + counter_base / 4, (unsigned long long)c_deep);
+    atomicAdd(P.counters + 18 + counter_base / 4, (unsigned long long)c_hinted);
+    atomicAdd(P.counters + 20 + counter_base / 4, (unsigned long long)c_retry);
   }
 }
 

@@ -41,6 +41,23 @@ struct DevBuf {
 
 constexpr double kPiHost = 3.14159265358979323846;
 
+// What fixes the rays a render call traces and their order: a call with
+// the same signature as the previous one on the context traces the same
+// primary and secondary rays in the same order.
+struct CallSig {
+  const void *ro, *rd;
+  int64_t n;
+  lf::CamArgs cams;
+  int32_t k, spp;
+  uint64_t seed;
+  uint32_t flags;  // without the flags that leave the traced rays unchanged
+  double alpha_min, alpha_cap, sigma, eps, t_min, sec_off;
+  const void *env;
+  int32_t h, w;
+  const void *R, *t;
+  uint64_t epoch;  // scene generation (set, refit)
+};
+
 }  // namespace lfh
 
 struct lf_ctx {
@@ -66,9 +83,13 @@ struct lf_ctx {
   int32_t wide_levels = 0; // levels of the deepest traversal hierarchy
   // per call
   lfh::DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;
-  lfh::DevBuf queue, qcount, work, kbuf1, kbuf2, contrib, frozen, lossbuf, cams, rec1, rec2, seeds;
+  lfh::DevBuf queue, qcount, work, kbuf1, kbuf2, hint2, contrib, frozen, lossbuf, cams, rec1, rec2, seeds;
   lfh::DevBuf bounds, skeys, skeys2, svals, svals2, shist;
   lfh::DevBuf det_key, det_key2, det_idx, det_idx2, det_hval, det_eval, det_hist;  // LF_FLAG_DETERMINISTIC
+  // the k-buffers in kbuf1 / kbuf2 belong to the last render call with this signature
+  uint64_t scene_epoch = 0;
+  bool sig_valid = false;
+  lfh::CallSig last_sig;
   lf::CamArgs h_cams{};
   // ray counters since the last lf_stats_get
   int64_t acc_primary = 0;

@@ -110,8 +110,13 @@ struct RenderArgs {
   uint32_t *work;       // [kPoolParts] item counters of the persistent traversal launches (cleared before each)
   uint32_t *kbuf1;      // [primary items, 2K] k-buffers from traversal to compositing (t[K], then ids[K])
   uint32_t *kbuf2;      // [secondary items, 2K] the same for the secondary queue
+  float *hint2;         // [R*S] k-th distance of each (ray, slot)'s secondary trace (its queue position varies)
   // per-ray sample stride of contrib / frozen and of the queue capacity (spp, or the batch maximum)
   int32_t spp_stride;
+  // 1: kbuf1 and hint2 hold the k-th distances of an earlier call that traced the same rays (the
+  // forward before its replay); each ray then starts from its earlier k-th distance as a culling
+  // bound and is traced again without it if fewer than k hits lie below the bound
+  int32_t use_hint;
   // continuous batching (NULL for one request): R = kChunk * number of chunks
   const ChunkDesc *chunks;
   const BatchSlot *slots;

@@ -331,6 +331,11 @@ struct PrimaryWork {
     return true;
   }
   __device__ void store(int64_t item, const KBufF<K> &kb) const { store_kbuf<K>(kb, a.kbuf1 + item * 2 * K); }
+  // the k-th distance this item's ray had in the earlier call, or +inf
+  __device__ float hint(int64_t item) const {
+    if (B || !a.use_hint) return INFINITY;
+    return __uint_as_float(a.kbuf1[item * 2 * K + K - 1]);
+  }
 };
 
 template <int K, bool B>
@@ -456,7 +461,21 @@ struct SecondaryWork {
     else inst = a.S.inst;
     return true;
   }
-  __device__ void store(int64_t item, const KBufF<K> &kb) const { store_kbuf<K>(kb, a.kbuf2 + item * 2 * K); }
+  // the k-th distance is also kept per (ray, slot), which identifies the
+  // secondary ray across calls (its queue position depends on the order of
+  // the appends)
+  __device__ void store(int64_t item, const KBufF<K> &kb) const {
+    store_kbuf<K>(kb, a.kbuf2 + item * 2 * K);
+    if (!B) {
+      const SecEntry &e = a.queue[a.order ? (uint32_t)a.order[item] : (uint32_t)item];
+      a.hint2[(int64_t)e.ray * a.spp_stride + e.s] = kb.t[K - 1];
+    }
+  }
+  __device__ float hint(int64_t item) const {
+    if (B || !a.use_hint) return INFINITY;
+    const SecEntry &e = a.queue[a.order ? (uint32_t)a.order[item] : (uint32_t)item];
+    return a.hint2[(int64_t)e.ray * a.spp_stride + e.s];
+  }
 };
 
 template <int K, bool B>

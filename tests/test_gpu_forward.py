@@ -211,13 +211,33 @@ def test_instanced_multi_state_parity(tracer):
 
 
 def test_forward_is_deterministic(tracer, c2_small):
+    """Two renders with the same arguments give bitwise the same outputs and
+    hit lists; the second one starts every ray from the k-th distance the
+    first found (a culling bound that never changes the result)."""
+    import paper_2608_29269_amd as lf
     wl = c2_small
     st = wl.states[0]
     upload_scene(tracer, wl.scene)
-    a = tracer.render(**state_args(tracer, wl.scene, st), cameras=st.cameras, k=32, spp=4, seed=1)
-    b = tracer.render(**state_args(tracer, wl.scene, st), cameras=st.cameras, k=32, spp=4, seed=1)
+    args = state_args(tracer, wl.scene, st)
+    cfg = dict(cameras=st.cameras, k=32, spp=4, seed=1, hit_idx=True, sec_hit_idx=True)
+    a = tracer.render(**args, **cfg)
+    tracer.trace_counters()
+    b = tracer.render(**args, **cfg, flags=lf.FLAG_COUNT)
+    cnt = tracer.trace_counters()
+    assert cnt["primary"]["hinted"] > 0 and cnt["secondary"]["hinted"] > 0, cnt
     for key in a:
         assert np.array_equal(a[key].cpu().numpy(), b[key].cpu().numpy()), key
+    # the map changes in place: the secondary rays differ, their bounds are
+    # stale and are caught; the outputs equal a render with no bounds
+    args["env"].pow_(1.5)
+    tracer.trace_counters()
+    c = tracer.render(**args, **cfg, flags=lf.FLAG_COUNT)
+    cnt = tracer.trace_counters()
+    assert cnt["secondary"]["hint_retries"] > 0, cnt
+    tracer.refit()
+    d = tracer.render(**args, **cfg)
+    for key in c:
+        assert np.array_equal(c[key].cpu().numpy(), d[key].cpu().numpy()), key
 
 
 def test_flags_furnace_on_gpu(tracer):
