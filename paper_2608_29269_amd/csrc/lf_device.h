@@ -222,9 +222,13 @@ struct KBufF {
 
 template <int K>
 __device__ __forceinline__ void kinit(KBufF<K> &b, int k) {
+  // k is made opaque here, so the sentinels are set where the buffer starts
+  // instead of being computed once and kept (spilled) for every later start
+  int kk = k;
+  asm volatile("" : "+s"(kk));
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    b.t[j] = j < K - k ? -INFINITY : INFINITY;
+    b.t[j] = j < K - kk ? -INFINITY : INFINITY;
     b.id[j] = kIdMask;
   }
 }
