@@ -349,9 +349,9 @@ lf_status lf_stats_get(lf_ctx *ctx, lf_render_stats *stats);
  * [15] secondary traversal stack pushes, [16] primary and [17] secondary
  * deepest traversal stack reached (a maximum, not a sum), [18] primary and
  * [19] secondary rays that started from the k-th distance of the same ray
- * in the previous call (the replay of lf_render_backward after lf_render
- * with the same arguments), [20] primary and [21] secondary rays of those
- * traced again without it (fewer than k hits below it). */
+ * in the previous call (the replay of an lf_render_backward directly after
+ * the lf_render with the same arguments), [20] primary and [21] secondary
+ * rays of those traced again without it (fewer than k hits below it). */
 #define LF_NUM_COUNTERS 22
 lf_status lf_trace_counters(lf_ctx *ctx, uint64_t *counters /*[LF_NUM_COUNTERS]*/);
 

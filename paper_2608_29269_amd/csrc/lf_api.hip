@@ -627,15 +627,13 @@ lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, co
   if (!c) return LF_EINVAL;
   if (!out) return fail(c, LF_EINVAL, "outputs struct is NULL");
   set_device(c);
-  const bool had_sig = c->sig_valid;
   c->sig_valid = false;
   lf::RenderArgs a;
   lf_status st = prepare(c, xf, env, rays, cams, n_cams, p, a);
   if (st) return st;
   if (a.R == 0) return LF_OK;
-  // the same rays as the previous call: start each from its earlier k-th distance
+  // a backward with the same arguments may start its replay from this call's k-th distances
   const lfh::CallSig sig = call_sig(c, xf, env, rays, p);
-  a.use_hint = had_sig && memcmp(&sig, &c->last_sig, sizeof sig) == 0;
   if (!out->radiance || !out->depth || !out->normal || !out->alpha)
     return fail(c, LF_EINVAL, "radiance, depth, normal and alpha outputs are required");
   a.radiance = out->radiance;
@@ -693,14 +691,11 @@ lf_status lf_render(lf_ctx *c, const lf_transforms *xf, const lf_envmap *env, co
   return st;
 }
 
-// A backward call that ran: its replay left the k-buffers of its own rays.
+// A backward call that ran; the next one does not start from its k-buffers.
 static lf_status backward_done(lf_ctx *c, const lfh::CallSig &sig) {
-  const lf_status st = check_hip(c, "backward");
-  if (st == LF_OK) {
-    c->last_sig = sig;
-    c->sig_valid = true;
-  }
-  return st;
+  (void)sig;
+  c->sig_valid = false;
+  return check_hip(c, "backward");
 }
 
 // Smallest b with 2^b > n: keys below 2^b sort in ceil(b / 16) * 2 radix passes
@@ -756,8 +751,10 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
   lf::RenderArgs a;
   lf_status st = prepare(c, xf, env, rays, cams, n_cams, p, a);
   if (st) return st;
-  // the replay traces the rays of the forward call with the same arguments:
-  // each starts from the k-th distance that call left in the k-buffers
+  // the replay traces the rays of the forward call just before it with the
+  // same arguments: each starts from the k-th distance that call left in the
+  // k-buffers (only then: equal pointers need not mean equal contents, and
+  // a wrong bound costs a retrace)
   const lfh::CallSig sig = call_sig(c, xf, env, rays, p);
   a.use_hint = had_sig && memcmp(&sig, &c->last_sig, sizeof sig) == 0;
   const int64_t n = c->s.n;

@@ -665,7 +665,8 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 // node, and the build guarantees that the hierarchy is shallow enough.
 // Every lane leaves once the pool is empty and its last ray is stored.
 //
-// With a finite hint h the ray starts with its empty k-buffer slots keyed
+// With a finite hint h (the k-th distance the forward call before a
+// backward found for the same ray) the ray starts with its empty k-buffer slots keyed
 // at B = the binary32 successor of h instead of +inf, so nodes and surfels
 // beyond B are culled from the start; a hit keyed at B or beyond is not
 // taken while such a bound sentinel holds the k-th slot.  If a sentinel

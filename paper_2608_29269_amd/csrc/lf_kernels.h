@@ -113,8 +113,8 @@ struct RenderArgs {
   float *hint2;         // [R*S] k-th distance of each (ray, slot)'s secondary trace (its queue position varies)
   // per-ray sample stride of contrib / frozen and of the queue capacity (spp, or the batch maximum)
   int32_t spp_stride;
-  // 1: kbuf1 and hint2 hold the k-th distances of an earlier call that traced the same rays (the
-  // forward before its replay); each ray then starts from its earlier k-th distance as a culling
+  // 1 (the replay of a backward right after the forward with the same arguments): kbuf1 and hint2
+  // hold that forward's k-th distances; each ray starts from its earlier k-th distance as a culling
   // bound and is traced again without it if fewer than k hits lie below the bound
   int32_t use_hint;
   // continuous batching (NULL for one request): R = kChunk * number of chunks

@@ -178,7 +178,8 @@ def test_replay_from_the_forward_k_th_distances_is_exact(tracer):
     tracer.render(**args, **cfg, flags=lf.FLAG_COUNT)
     g = tracer.render_backward(**args, **cfg, flags=det, d_radiance=up)
     cnt = tracer.trace_counters()
-    assert cnt["primary"]["hinted"] > 0.5 * n and cnt["secondary"]["hinted"] > 0, cnt
+    # only rays whose forward filled all k slots carry a finite bound
+    assert 0 < cnt["primary"]["hinted"] <= n and cnt["secondary"]["hinted"] > 0, cnt
     for key in g_ref:
         assert torch_equal(g[key], g_ref[key]), key
     # stale bounds: the map changes in place between forward and backward

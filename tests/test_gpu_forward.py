@@ -212,8 +212,9 @@ def test_instanced_multi_state_parity(tracer):
 
 def test_forward_is_deterministic(tracer, c2_small):
     """Two renders with the same arguments give bitwise the same outputs and
-    hit lists; the second one starts every ray from the k-th distance the
-    first found (a culling bound that never changes the result)."""
+    hit lists.  A forward never starts its rays from the k-th distances of an
+    earlier call (only the replay of a backward directly after its forward
+    does), neither after a forward nor after a backward."""
     import paper_2608_29269_amd as lf
     wl = c2_small
     st = wl.states[0]
@@ -224,20 +225,18 @@ def test_forward_is_deterministic(tracer, c2_small):
     tracer.trace_counters()
     b = tracer.render(**args, **cfg, flags=lf.FLAG_COUNT)
     cnt = tracer.trace_counters()
-    assert cnt["primary"]["hinted"] > 0 and cnt["secondary"]["hinted"] > 0, cnt
+    assert cnt["primary"]["hinted"] == 0 and cnt["secondary"]["hinted"] == 0, cnt
     for key in a:
         assert np.array_equal(a[key].cpu().numpy(), b[key].cpu().numpy()), key
-    # the map changes in place: the secondary rays differ, their bounds are
-    # stale and are caught; the outputs equal a render with no bounds
-    args["env"].pow_(1.5)
+    n = st.cameras[0].w * st.cameras[0].h * len(st.cameras)
+    tracer.render_backward(**{k: v for k, v in cfg.items() if k not in ("hit_idx", "sec_hit_idx")}, **args,
+                           d_radiance=dev(np.ones((n, 3), np.float32)))
     tracer.trace_counters()
     c = tracer.render(**args, **cfg, flags=lf.FLAG_COUNT)
     cnt = tracer.trace_counters()
-    assert cnt["secondary"]["hint_retries"] > 0, cnt
-    tracer.refit()
-    d = tracer.render(**args, **cfg)
-    for key in c:
-        assert np.array_equal(c[key].cpu().numpy(), d[key].cpu().numpy()), key
+    assert cnt["primary"]["hinted"] == 0 and cnt["secondary"]["hinted"] == 0, cnt
+    for key in a:
+        assert np.array_equal(a[key].cpu().numpy(), c[key].cpu().numpy()), key
 
 
 def test_flags_furnace_on_gpu(tracer):
