@@ -15,7 +15,8 @@
  *    found on the device (invalid transforms, traversal-stack overflow) are
  *    latched in a device status word and returned by the next lf_sync.
  *  - Arrays are row-major and contiguous; float is IEEE binary32.
- *  - A context is not thread-safe; use one context per host thread/stream.
+ *  - A context is not thread-safe; use one context per host thread/stream
+ *    (lf_abort excepted).
  */
 #ifndef LIGHTFUSE_H
 #define LIGHTFUSE_H
@@ -32,7 +33,9 @@ typedef enum {
   LF_EDEVICE = 3,      /* HIP runtime error */
   LF_EBUSY = 4,        /* server queue full */
   LF_EOVERFLOW = 5,    /* traversal stack or queue overflow seen on the device */
-  LF_EUNSUPPORTED = 6  /* valid but unsupported configuration (e.g. k > 64, BVH deeper than the stack) */
+  LF_EUNSUPPORTED = 6, /* valid but unsupported configuration (e.g. k > 64, BVH deeper than the stack) */
+  LF_EABORTED = 7,     /* work cut short by lf_abort (latched; outputs of the affected calls undefined) */
+  LF_ETIMEOUT = 8      /* lf_sync_timeout gave up waiting and cut the work short */
 } lf_status;
 
 typedef struct lf_ctx lf_ctx;
@@ -43,8 +46,25 @@ lf_status lf_create(lf_ctx **out, int device, void *hip_stream);
 void lf_destroy(lf_ctx *ctx);
 /* Message of the last non-OK status of this context (never NULL). */
 const char *lf_last_error(const lf_ctx *ctx);
-/* Waits for the context's stream and returns (then clears) any latched device status. */
+/* Waits for the context's stream and returns (then clears) any latched device
+ * status; LF_EABORTED if lf_abort cut work short.  Clears the abort request
+ * once the stream has drained. */
 lf_status lf_sync(lf_ctx *ctx);
+/* Failure detection for the persistent traversal pools.  lf_abort raises the
+ * context's abort word (fine-grained host memory that the tracing kernels
+ * read while they refill their lanes, every eighth refill of a wave): every
+ * ray not yet finished is then stored with an empty hit list and no further
+ * traversal is done, so each kernel of the calls already enqueued still
+ * completes normally, quickly, and with every buffer it hands on well formed;
+ * their outputs are undefined and the next lf_sync returns LF_EABORTED.
+ * Calls enqueued before that lf_sync are cut short too.  Safe to call from
+ * any host thread, also while another thread waits in lf_sync.  Relight
+ * server passes do not read the word. */
+lf_status lf_abort(lf_ctx *ctx);
+/* lf_sync with a host watchdog: polls the stream; if it has not drained
+ * after timeout_ms (>= 0), raises the abort word, waits for the cut-short
+ * work, clears the word and the latched status and returns LF_ETIMEOUT. */
+lf_status lf_sync_timeout(lf_ctx *ctx, double timeout_ms);
 
 /* ---------------------------------------------------------------------------
  * Scene: shared background B plus M movable objects O_o, each a set of 2D

@@ -296,8 +296,20 @@ class Tracer:
         self._chk(self.L.lf_raygen(self.ctx, C.byref(c), _ptr(o), _ptr(d)))
         return o, d
 
-    def sync(self):
-        self._chk(self.L.lf_sync(self.ctx))
+    def sync(self, timeout_ms=None):
+        """Waits for the context's stream (lf_sync); with timeout_ms, a host
+        watchdog cuts the traversal short after that long (lf_sync_timeout,
+        LF_ETIMEOUT)."""
+        if timeout_ms is None:
+            self._chk(self.L.lf_sync(self.ctx))
+        else:
+            self._chk(self.L.lf_sync_timeout(self.ctx, float(timeout_ms)))
+
+    def abort(self):
+        """Raises the context's abort word (lf_abort; any thread): the work
+        already enqueued drains without further traversal and the next sync
+        raises LF_EABORTED."""
+        self._chk(self.L.lf_abort(self.ctx))
 
     def stats(self) -> dict:
         st = _lib.RenderStats()

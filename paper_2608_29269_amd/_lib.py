@@ -11,9 +11,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblightfuse.so")
 
-LF_OK, LF_EINVAL, LF_ENOMEM, LF_EDEVICE, LF_EBUSY, LF_EOVERFLOW, LF_EUNSUPPORTED = range(7)
+LF_OK, LF_EINVAL, LF_ENOMEM, LF_EDEVICE, LF_EBUSY, LF_EOVERFLOW, LF_EUNSUPPORTED, LF_EABORTED, LF_ETIMEOUT = range(9)
 STATUS_NAMES = {0: "LF_OK", 1: "LF_EINVAL", 2: "LF_ENOMEM", 3: "LF_EDEVICE", 4: "LF_EBUSY", 5: "LF_EOVERFLOW",
-                6: "LF_EUNSUPPORTED"}
+                6: "LF_EUNSUPPORTED", 7: "LF_EABORTED", 8: "LF_ETIMEOUT"}
 
 FLAG_NO_SECONDARY = 1 << 0
 FLAG_NO_BACKGROUND = 1 << 1
@@ -115,6 +115,8 @@ SIGNATURES = {
     "lf_destroy": (None, [C.c_void_p]),
     "lf_last_error": (C.c_char_p, [C.c_void_p]),
     "lf_sync": (C.c_int, [C.c_void_p]),
+    "lf_abort": (C.c_int, [C.c_void_p]),
+    "lf_sync_timeout": (C.c_int, [C.c_void_p, C.c_double]),
     "lf_scene_set": (C.c_int, [C.c_void_p, C.POINTER(Surfels)]),
     "lf_scene_refit": (C.c_int, [C.c_void_p]),
     "lf_params_default": (None, [C.POINTER(Params)]),

@@ -2,12 +2,14 @@
 // validation, library-owned device memory, scene build/refit and the launch
 // sequences of the forward and backward passes.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "lf_host.h"
@@ -148,6 +150,7 @@ void trace_params(const lf_ctx *c, const lf_params *p, lf::TraceParams &P) {
   P.sec_off = p->secondary_offset;
   P.flags = p->flags;
   P.counters = (p->flags & LF_FLAG_COUNT) ? c->counters.as<unsigned long long>() : nullptr;
+  P.abort = c->abort_d;
 }
 
 bool ensure_env_tables(DevBuf &cdf_row, DevBuf &cdf_col, DevBuf &lum, DevBuf &rowsum, DevBuf &roww, DevBuf &scal,
@@ -388,6 +391,19 @@ lf_status lf_create(lf_ctx **out, int device, void *hip_stream) {
     delete c;
     return LF_EDEVICE;
   }
+  // the abort word: host memory the kernels read uncached, so a store from
+  // any host thread reaches traversal loops that are already running
+  void *ab = nullptr, *ab_d = nullptr;
+  if (hipHostMalloc(&ab, sizeof(uint32_t), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer(&ab_d, ab, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    if (ab) (void)hipHostFree(ab);
+    delete c;
+    return LF_EDEVICE;
+  }
+  c->abort_h = (uint32_t *)ab;
+  c->abort_d = (const uint32_t *)ab_d;
+  __atomic_store_n(c->abort_h, 0u, __ATOMIC_SEQ_CST);
   lf::launch_fill_u32(c->status.as<uint32_t>(), 0u, 1, c->stream);
   lf::launch_fill_u32(c->acc_secondary.as<uint32_t>(), 0u, 2, c->stream);
   lf::launch_fill_u32(c->counters.as<uint32_t>(), 0u, 2 * LF_NUM_COUNTERS, c->stream);
@@ -409,15 +425,16 @@ void lf_destroy(lf_ctx *c) {
     (void)hipEventDestroy(pe.second.second);
   }
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  if (c->abort_h) (void)hipHostFree(c->abort_h);
   delete c;
 }
 
 const char *lf_last_error(const lf_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
-lf_status lf_sync(lf_ctx *c) {
-  if (!c) return LF_EINVAL;
-  set_device(c);
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "sync");
+// The stream has drained: clears the abort request, then returns (and
+// clears) the latched device status.
+static lf_status drained(lf_ctx *c) {
+  __atomic_store_n(c->abort_h, 0u, __ATOMIC_SEQ_CST);
   uint32_t st = 0;
   if (hipMemcpy(&st, c->status.p, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return check_hip(c, "sync");
   if (st) {
@@ -426,8 +443,42 @@ lf_status lf_sync(lf_ctx *c) {
     if (st & lf::kStatusOverflow) return fail(c, LF_EOVERFLOW, "traversal stack overflow on the device");
     if (st & lf::kStatusBadTransform) return fail(c, LF_EINVAL, "degenerate or non-finite object transform");
     if (st & lf::kStatusBvhCorrupt) return fail(c, LF_EDEVICE, "out-of-range hierarchy index on the device");
+    if (st & lf::kStatusAborted) return fail(c, LF_EABORTED, "traversal cut short by lf_abort");
   }
   return LF_OK;
+}
+
+lf_status lf_sync(lf_ctx *c) {
+  if (!c) return LF_EINVAL;
+  set_device(c);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "sync");
+  return drained(c);
+}
+
+lf_status lf_abort(lf_ctx *c) {
+  if (!c) return LF_EINVAL;
+  __atomic_store_n(c->abort_h, 1u, __ATOMIC_SEQ_CST);
+  return LF_OK;
+}
+
+lf_status lf_sync_timeout(lf_ctx *c, double timeout_ms) {
+  if (!c) return LF_EINVAL;
+  if (!(timeout_ms >= 0.0)) return fail(c, LF_EINVAL, "timeout_ms must be >= 0");
+  set_device(c);
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t q = hipStreamQuery(c->stream);
+    if (q == hipSuccess) return drained(c);
+    if (q != hipErrorNotReady) return check_hip(c, "sync");
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (ms >= timeout_ms) break;
+    std::this_thread::sleep_for(std::chrono::microseconds(50));
+  }
+  // the watchdog fires: cut the traversal short and wait for what is enqueued
+  __atomic_store_n(c->abort_h, 1u, __ATOMIC_SEQ_CST);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "sync");
+  (void)drained(c);
+  return fail(c, LF_ETIMEOUT, "work not done after %.3f ms: cut short", timeout_ms);
 }
 
 lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {

@@ -682,6 +682,11 @@ __device__ __forceinline__ double kth(const KBufF<K> &b) { return (double)b.t[K 
 // lie below B, and the ray is traced again from the start with +inf; else
 // its k hits are exactly the k nearest (every hit below B was found).  So
 // the result never depends on the hint, only the work does.
+//
+// When the host raises the abort word (P.abort, read every eighth refill of
+// a wave), the wave stores every ray it holds or takes from then on with an
+// empty hit list and traverses nothing more, so the kernel drains quickly
+// and the buffers it hands on stay well formed; kStatusAborted is latched.
 
 template <int K, class Work>
 __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work &wk, int64_t count, uint32_t *next,
@@ -695,6 +700,8 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
   uint32_t c_hinted = 0, c_retry = 0;
   bool bounded = false;  // the ray's k-buffer started from a finite bound
   int c_deep = 0;
+  bool aborted = false;  // the host's abort word was seen (uniform over the wave)
+  uint32_t refills = 0;
   auto count_test = [&](int r) {
     c_ins += r & 1;
     c_ties += (r >> 1) & 1;
@@ -738,6 +745,18 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
       const int n_idle = __popcll(idle);
       if (n_idle >= Work::kRefill || (n_idle > 0 && !__any(live))) {
         const int leader = __ffsll((long long)idle) - 1;
+        if (P.abort && !aborted && (refills++ & 7u) == 0 &&
+            __hip_atomic_load(P.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) {
+          aborted = true;
+          if (lane == leader) atomicOr(status, kStatusAborted);
+          if (live) {  // the ray in flight is given up: stored with no hits
+            kinit<K>(kb, P.k);
+            wk.store(item, kb);
+            live = false;
+          }
+          cur = kDone;
+          qn = 0;
+        }
         uint32_t base = 0;
         const int take = n_idle < cap ? n_idle : cap;
         if (lane == leader) base = atomicAdd(next + part, (uint32_t)take);
@@ -748,13 +767,17 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
           part = part + 1 == kPoolParts ? 0 : part + 1;
           exhausted = ++tried == kPoolParts;
         }
-        if (!live) {
+        if ((idle >> lane) & 1ull) {  // the lanes idle at the ballot (not those just given up)
           const int rk = __popcll(idle & ((1ull << lane) - 1ull));
           const int64_t it = first + rk;
           if (rk < take && it < hi) {
             item = it;
             live = wk.begin(item, o, d, S.inst);
-            if (live) {
+            if (live && aborted) {
+              kinit<K>(kb, P.k);
+              wk.store(item, kb);
+              live = false;
+            } else if (live) {
               ++c_rays;
               kinit<K>(kb, P.k);
               const float h = wk.hint(item);

@@ -63,6 +63,9 @@ struct CallSig {
 struct lf_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // abort word: pinned, mapped, coherent host memory the tracing kernels poll
+  uint32_t *abort_h = nullptr;
+  const uint32_t *abort_d = nullptr;
   std::string err;
   // scene
   bool has_scene = false;

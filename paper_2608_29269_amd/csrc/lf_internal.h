@@ -28,7 +28,8 @@ constexpr uint32_t kIdMask = 0x7fffffffu;
 // Status bits latched on the device.
 constexpr uint32_t kStatusOverflow = 1u;
 constexpr uint32_t kStatusBadTransform = 2u;
-constexpr uint32_t kStatusBvhCorrupt = 4u;   // an index read from the hierarchy was out of range
+constexpr uint32_t kStatusBvhCorrupt = 4u;
+constexpr uint32_t kStatusAborted = 8u;      // the host's abort word cut the traversal short   // an index read from the hierarchy was out of range
 
 // Per-surfel trace record, stored in leaf (Morton) order: everything the
 // ray-surfel decision needs, in double precision so that hit sets and their
@@ -127,6 +128,7 @@ struct TraceParams {
   double alpha_min, alpha_cap, sig2, eps, t_min, sec_off;
   uint32_t flags;
   unsigned long long *counters;  // [LF_NUM_COUNTERS] traversal counters when LF_FLAG_COUNT is set
+  const uint32_t *abort;         // device view of the host's abort word (fine-grained), or null
 };
 
 struct EnvView {

@@ -210,6 +210,7 @@ bool launch_pass(lf_server *s, Lane &L, const std::vector<lf::SchedTile> &tiles)
   memset(&a, 0, sizeof a);
   lfh::scene_view(c, a.S);
   lfh::trace_params(c, &s->cfg.params, a.P);
+  a.P.abort = nullptr;  // server passes do not read the context's abort word
   a.P.spp = s->cfg.max_spp;  // replaced per request in the shading passes
   a.P.counters = nullptr;
   a.spp_stride = s->cfg.max_spp;

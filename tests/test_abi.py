@@ -50,6 +50,8 @@ def test_null_context_paths(lib):
     assert lib.lf_sync(None) == 1
     assert lib.lf_scene_refit(None) == 1
     assert lib.lf_create(None, 0, None) == 1
+    assert lib.lf_abort(None) == 1
+    assert lib.lf_sync_timeout(None, C.c_double(1.0)) == 1
 
 
 def test_struct_sizes_match_header(lib):
@@ -117,3 +119,12 @@ def test_binding_constants_match_the_header():
                  "NEE", "SOBOL", "DETERMINISTIC"):
         m = re.search(r"#define LF_FLAG_%s\s+\(1u << (\d+)\)" % name, src)
         assert m and getattr(_lib, "FLAG_" + name) == 1 << int(m.group(1)), name
+
+
+def test_status_codes_match_the_header():
+    from paper_2608_29269_amd import _lib
+    src = open(HEADER).read()
+    codes = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"\b(LF_[A-Z]+) = (\d+)", src))
+    assert codes["LF_OK"] == 0 and len(codes) == len(_lib.STATUS_NAMES)
+    for name, v in codes.items():
+        assert getattr(_lib, name) == v and _lib.STATUS_NAMES[v] == name, name
