@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--serve-policies", type=str, default="0,1",
                     help="comma-separated pass-filling policies (0 shortest first, 1 oldest first, 2 round robin)")
     ap.add_argument("--serve-batch", type=int, default=1048576, help="primary rays per batched pass")
-    ap.add_argument("--serve-in-flight", type=int, default=2, help="concurrent passes (one stream each)")
+    ap.add_argument("--serve-in-flight", type=int, default=3, help="concurrent passes (one stream each)")
     ap.add_argument("--serve-only", action="store_true", help="skip the fwd+bwd and CPU legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device (calibrates HBM byte counters)")

@@ -28,8 +28,8 @@ constexpr uint32_t kIdMask = 0x7fffffffu;
 // Status bits latched on the device.
 constexpr uint32_t kStatusOverflow = 1u;
 constexpr uint32_t kStatusBadTransform = 2u;
-constexpr uint32_t kStatusBvhCorrupt = 4u;
-constexpr uint32_t kStatusAborted = 8u;      // the host's abort word cut the traversal short   // an index read from the hierarchy was out of range
+constexpr uint32_t kStatusBvhCorrupt = 4u;   // an index read from the hierarchy was out of range
+constexpr uint32_t kStatusAborted = 8u;      // the host's abort word cut the traversal short
 
 // Per-surfel trace record, stored in leaf (Morton) order: everything the
 // ray-surfel decision needs, in double precision so that hit sets and their
