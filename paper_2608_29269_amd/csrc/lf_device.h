@@ -391,12 +391,11 @@ __device__ __forceinline__ void make_rayf(d3 oo, d3 dd, double tabs, float omag,
 }
 
 // Visits one traversal node: the masks of the internal and leaf slots whose
-// decoded boxes (grown by pad) the ray enters within [tlo, thi], the hit
-// internal slot entered first (near; entry distances within 8 ulps go to the
-// lower slot; meaningful when ihit != 0), and what locates the children:
-// slot i holds node cbase + (internal slots below i) or leaf position
-// lbase + (leaf slots below i).
-__device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, float tlo, float thi, int &near,
+// decoded boxes (grown by pad) the ray enters within [tlo, thi], each slot's
+// entry distance t (meaningful for hit slots; >= tlo), and what locates the
+// children: slot i holds node cbase + (internal slots below i) or leaf
+// position lbase + (leaf slots below i).
+__device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, float tlo, float thi, float *t,
                                            uint32_t &ihit, uint32_t &lhit, uint32_t &imask, int &cbase,
                                            int &lbase, bool &desc) {
   constexpr int kDw = (int)sizeof(QNode) / 4;
@@ -435,8 +434,7 @@ __device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, fl
     ny[w] = rf.sy ? ly : hy; fy[w] = rf.sy ? hy : ly;
     nz[w] = rf.sz ? lz : hz; fz[w] = rf.sz ? hz : lz;
   }
-  const int n_int = __builtin_popcount(imask);
-  uint32_t hits = 0, key[kWide];
+  uint32_t hits = 0;
 #pragma unroll
   for (int i = 0; i < kWide; ++i) {
     const int w = i / 4, b = 8 * (i % 4);
@@ -448,16 +446,9 @@ __device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, fl
     const float tfz = __builtin_fmaf((float)((fz[w] >> b) & 0xffu), Cz, Bfz);
     const float n = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, tlo));
     const float f = fminf(fminf(tfx, tfy), fminf(tfz, thi));
-    const bool hit = n <= f;
-    hits |= hit ? 1u << i : 0u;
-    // entry distances are >= tlo >= 0, so their bit patterns order as they do
-    // (a -0 orders last, which only changes the visiting order); the low three
-    // bits carry the slot, and a node's internal slots are its first n_int
-    key[i] = hit && i < n_int ? (__float_as_uint(n) & ~7u) | (uint32_t)i : 0xffffffffu;
+    hits |= n <= f ? 1u << i : 0u;
+    t[i] = n;
   }
-  static_assert(kWide == 8, "the reduction below is written for eight slots");
-  const uint32_t best = min(min(min(key[0], key[1]), min(key[2], key[3])), min(min(key[4], key[5]), min(key[6], key[7])));
-  near = (int)(best & 7u);
   hits &= vmask;
   lhit = hits & ~imask;
   ihit = hits & imask;
@@ -855,10 +846,11 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
       // the exact k-th distance is at most the successor of the k-th binary32 key
       const float tkf = kb.t[K - 1];
       const float thi = tkf < INFINITY ? next_up_f(tkf) * (1.0f + 1e-6f) : INFINITY;
+      float ts[kWide];
       uint32_t ih, lh, im;
-      int cbase, lbase, bj;
+      int cbase, lbase;
       bool desc;
-      visit_node(S.nodes + cur, rf, tlo, thi, bj, ih, lh, im, cbase, lbase, desc);
+      visit_node(S.nodes + cur, rf, tlo, thi, ts, ih, lh, im, cbase, lbase, desc);
       // hit leaves join the queue, in slot order (leaf slots follow the
       // node's internal ones)
       const int leaf0 = lbase - __builtin_popcount(im);
@@ -868,6 +860,18 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
         continue;
       }
       // the nearest hit internal child next, the others onto the stack as one entry
+      int bj = __builtin_ctz(ih);
+      if (ih & (ih - 1u)) {
+        // entry distances are >= tlo >= 0, so their bit patterns order as
+        // they do (a -0 orders last, which only changes the visiting order);
+        // the low three bits carry the slot (ties within 8 ulps go to the lower)
+        uint32_t key[kWide];
+#pragma unroll
+        for (int j = 0; j < kWide; ++j)
+          key[j] = ((ih >> j) & 1u) ? (__float_as_uint(ts[j]) & ~7u) | (uint32_t)j : 0xffffffffu;
+        static_assert(kWide == 8, "the reduction below is written for eight slots");
+        bj = (int)(min(min(min(key[0], key[1]), min(key[2], key[3])), min(min(key[4], key[5]), min(key[6], key[7]))) & 7u);
+      }
       const uint32_t rest = ih & ~(1u << bj);
       if (rest) {
         if (sp >= kStackL) {  // never taken for a hierarchy the build accepted
