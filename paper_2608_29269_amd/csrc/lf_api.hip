@@ -12,6 +12,8 @@
 #include <thread>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "lf_host.h"
 #include "lf_kernels.h"
 
@@ -60,18 +62,28 @@ hipEvent_t take_event(lf_ctx *c) {
   return e;
 }
 
-// Brackets one phase with events when profiling is enabled.
+// Names of the phases (lf_profile_enable), also the roctx ranges that
+// bracket their host-side launches for a tracer's marker view.
+const char *const kPhaseName[LF_NUM_PHASES] = {
+    "lf:refit",          "lf:state_env",  "lf:trace1",    "lf:shade1",     "lf:sort2",       "lf:trace2",
+    "lf:shade2",         "lf:resolve",    "lf:replay_primary", "lf:replay_secondary", "lf:adj_shade", "lf:unused",
+    "lf:zero_grads",     "lf:loss",       "lf:composite1", "lf:composite2", "lf:adj_hits"};
+
+// Brackets one phase with a roctx range and, when profiling is enabled, with
+// events on the stream.
 struct Phase {
   lf_ctx *c;
   int id;
   hipEvent_t a = nullptr, b = nullptr;
   Phase(lf_ctx *c_, int id_) : c(c_), id(id_) {
+    roctxRangePushA(kPhaseName[id]);
     if (!c->profiling) return;
     a = take_event(c);
     b = take_event(c);
     if (a) (void)hipEventRecord(a, c->stream);
   }
   ~Phase() {
+    roctxRangePop();
     if (!c->profiling || !a || !b) return;
     (void)hipEventRecord(b, c->stream);
     c->pending.push_back({id, {a, b}});
