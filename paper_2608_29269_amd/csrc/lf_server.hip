@@ -65,6 +65,7 @@ struct Lane {
   lf::ChunkDesc *h_chunks = nullptr;  // pinned
   IterReadback *h_rb = nullptr;       // pinned
   DevBuf d_chunks, rec1, rec2, queue, qcount, work, kbuf1, kbuf2, contrib, skeys, skeys2, svals, svals2, shist, status;
+  DevBuf hint2;  // k-th distance per (ray, slot), written by the single-request kernels
 };
 
 }  // namespace
@@ -186,7 +187,10 @@ bool stage_slot(lf_server *s, int slot, const lf_request &r, hipStream_t st) {
   return hipGetLastError() == hipSuccess;
 }
 
-// Launches one batched pass over the tiles on lane L.
+// Launches one batched pass over the tiles on lane L.  A pass that holds one
+// whole request runs the single-request kernels instead (those of lf_render,
+// with the request's slot data as their arguments): the same results, without
+// each ray looking up its chunk and slot.
 bool launch_pass(lf_server *s, Lane &L, const std::vector<lf::SchedTile> &tiles) {
   lf_ctx *c = s->ctx;
   hipStream_t st = L.stream;
@@ -228,13 +232,37 @@ bool launch_pass(lf_server *s, Lane &L, const std::vector<lf::SchedTile> &tiles)
   a.status = L.status.as<uint32_t>();
   const bool sorted = !(s->cfg.params.flags & LF_FLAG_UNSORTED);
   a.order = sorted ? L.svals.as<int32_t>() : nullptr;
+  const lf::SchedTile &t0 = tiles[0];
+  const lf::CamArgs &hc0 = s->h_cams[t0.slot];
+  const bool whole = tiles.size() == 1 && t0.first == 0 && t0.n == hc0.tiles[1] * lf::kChunk;
+  const double *bounds6 = nullptr;
+  if (whole) {
+    const lf::BatchSlot &hs = s->h_slots[t0.slot];
+    a.chunks = nullptr;
+    a.slots = nullptr;
+    a.S.inst = hs.inst;
+    a.E = hs.E;
+    a.P.seed = hs.seed;
+    a.P.spp = hs.spp;
+    a.spp_stride = hs.spp;
+    a.rays.cams = hs.cam;
+    a.n_tiles = hc0.tiles[1];
+    a.R = hc0.first[1];
+    a.radiance = hs.radiance;
+    a.depth = hs.depth;
+    a.normal = hs.normal;
+    a.alpha = hs.alpha;
+    a.hint2 = L.hint2.as<float>();
+    a.use_hint = 0;
+    bounds6 = hs.bounds;
+  }
   lf::launch_fill_u32(a.queue_count, 0u, 1, st);
   lf::launch_trace1(a, st);
   lf::launch_composite1(a, false, st);
   lf::launch_shade1(a, false, st);
   if (sorted) {
     const int64_t cap = a.R * a.spp_stride;
-    lf::launch_secondary_keys(a.queue, a.queue_count, cap, nullptr, a.chunks, a.slots, L.skeys.as<uint64_t>(),
+    lf::launch_secondary_keys(a.queue, a.queue_count, cap, bounds6, a.chunks, a.slots, L.skeys.as<uint64_t>(),
                               L.svals.as<int32_t>(), st);
     lf::radix_sort(L.skeys.as<uint64_t>(), L.svals.as<int32_t>(), L.skeys2.as<uint64_t>(), L.svals2.as<int32_t>(),
                    L.shist.as<uint32_t>(), cap, st, 32);
@@ -502,7 +530,7 @@ lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **o
          L.kbuf2.ensure(sizeof(uint32_t) * 2 * lf::kbucket(s->cfg.params.k) * BS) &&
          L.contrib.ensure(sizeof(float) * 3 * BS) && L.skeys.ensure(8 * BS) && L.skeys2.ensure(8 * BS) &&
          L.svals.ensure(4 * BS) && L.svals2.ensure(4 * BS) && L.shist.ensure(4 * lf::radix_sort_hist_words(BS)) &&
-         L.status.ensure(4);
+         L.status.ensure(4) && L.hint2.ensure(sizeof(float) * BS);
     if (ok) {
       lf::launch_fill_u32(L.status.as<uint32_t>(), 0u, 1, L.stream);
       ok = hipStreamSynchronize(L.stream) == hipSuccess;

@@ -162,3 +162,28 @@ def test_served_with_sobol_samples_equals_rendered_alone(setup):
             assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (key, q.camera.w, q.camera.h, q.spp)
         if q.spp > 1:  # the sampler is in effect
             assert not np.array_equal(got["radiance"].cpu().numpy(), plain["radiance"].cpu().numpy())
+
+
+@pytest.mark.parametrize("lanes", [1, 3])
+def test_lone_whole_requests_equal_rendered_alone(setup, lanes):
+    """A pass that holds one whole request runs the single-request kernels
+    with the request's slot data; served one at a time (each its own pass),
+    every request equals lf_render of it bit for bit, also with several lanes
+    staging and running in turn."""
+    import paper_2608_29269_amd as lf
+    tr, wl = setup
+    reqs = _requests(6, seed=7)
+    srv = lf.Server(tr, max_slots=2, tile_rays=65536, batch_rays=1 << 20, max_spp=4, policy=1, max_in_flight=lanes)
+    outs = []
+    try:
+        for q in reqs:
+            outs.append(srv.wait(srv.submit(dev(q.env), q.camera, R=dev(q.R), t=dev(q.t), spp=q.spp, seed=q.seed)))
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["completed"] == len(reqs) and st["iterations"] == len(reqs)
+    for q, got in zip(reqs, outs):
+        ref = _alone(tr, q)
+        for key in ("radiance", "depth", "normal", "alpha"):
+            a, b = got[key].cpu().numpy(), ref[key].cpu().numpy()
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (key, q.camera.w, q.camera.h, q.spp)
