@@ -149,14 +149,17 @@ def test_autograd_function_and_l1(tracer):
     assert env.grad is not None and float(env.grad.abs().sum()) > 0
 
 
-def test_replay_from_the_forward_k_th_distances_is_exact(tracer):
+@pytest.mark.parametrize("k,extra", [(32, 0), (12, 0), (64, 0), (32, "nee_sobol")])
+def test_replay_from_the_forward_k_th_distances_is_exact(tracer, k, extra):
     """The replay of a backward that follows a forward with the same
     arguments starts each ray from the k-th distance the forward found (a
     culling bound; a ray with fewer than k hits below it is traced again
     without it).  Its gradients equal, bit for bit, those of a backward that
     has no forward before it, with order-fixed sums; also when the
     environment was changed in place in between, so that the secondary rays
-    differ and the bounds are wrong for many of them."""
+    differ and the bounds are wrong for many of them.  Also at k-buffer
+    buckets whose first slots hold -inf sentinels (k = 12 of 16), at k = 64,
+    and for the two-ray estimator with Sobol samples (two slots per sample)."""
     import paper_2608_29269_amd as lf
     wl = scenegen.make_workload(2, scale=0.1, resolution=96)  # 20k surface surfels
     st = wl.states[0]
@@ -165,8 +168,9 @@ def test_replay_from_the_forward_k_th_distances_is_exact(tracer):
     cam = st.cameras[0]
     n = cam.w * cam.h
     up = dev(np.random.default_rng(3).standard_normal((n, 3)).astype(np.float32))
-    cfg = dict(cameras=[cam], k=32, spp=2, seed=5)
-    det = lf.FLAG_DETERMINISTIC | lf.FLAG_COUNT
+    fl = (lf.FLAG_NEE | lf.FLAG_SOBOL) if extra == "nee_sobol" else 0
+    cfg = dict(cameras=[cam], k=k, spp=2, seed=5)
+    det = lf.FLAG_DETERMINISTIC | lf.FLAG_COUNT | fl
 
     def fresh_backward():
         tracer.refit()  # a new scene generation: nothing carried over
@@ -175,28 +179,30 @@ def test_replay_from_the_forward_k_th_distances_is_exact(tracer):
 
     g_ref = fresh_backward()
     tracer.trace_counters()
-    tracer.render(**args, **cfg, flags=lf.FLAG_COUNT)
+    tracer.render(**args, **cfg, flags=lf.FLAG_COUNT | fl)
     g = tracer.render_backward(**args, **cfg, flags=det, d_radiance=up)
     cnt = tracer.trace_counters()
-    # only rays whose forward filled all k slots carry a finite bound
-    assert 0 < cnt["primary"]["hinted"] <= n and cnt["secondary"]["hinted"] > 0, cnt
+    # only rays whose forward filled all k slots carry a finite bound (at
+    # k = 64 few secondary rays of this scene have that many hits)
+    assert 0 < cnt["primary"]["hinted"] <= n, cnt
+    assert k > 32 or cnt["secondary"]["hinted"] > 0, cnt
     for key in g_ref:
         assert torch_equal(g[key], g_ref[key]), key
     # stale bounds: the map changes in place between forward and backward
-    tracer.render(**args, **cfg)
+    tracer.render(**args, **cfg, flags=fl)
     args["env"].mul_(1.7).add_(0.3 * dev(np.random.default_rng(4).random(st.env.shape).astype(np.float32)))
     g_ref2 = fresh_backward()
-    tracer.render(**args, **cfg)
+    tracer.render(**args, **cfg, flags=fl)
     args["env"].mul_(1.0)  # same pointer, same contents
     g2 = tracer.render_backward(**args, **cfg, flags=det, d_radiance=up)
     for key in g_ref2:
         assert torch_equal(g2[key], g_ref2[key]), key
-    tracer.render(**args, **cfg)
+    tracer.render(**args, **cfg, flags=fl)
     args["env"].pow_(1.5)  # same pointer, new contents: the importance sampling and the secondary rays change
     tracer.trace_counters()
     g3 = tracer.render_backward(**args, **cfg, flags=det, d_radiance=up)
     cnt = tracer.trace_counters()
-    assert cnt["secondary"]["hint_retries"] > 0, cnt  # wrong bounds are caught and retraced
+    assert k > 32 or cnt["secondary"]["hint_retries"] > 0, cnt  # wrong bounds are caught and retraced
     g_ref3 = fresh_backward()
     for key in g_ref3:
         assert torch_equal(g3[key], g_ref3[key]), key
