@@ -35,6 +35,32 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 
+class Marker:
+    """A roctx range around a timed region (rocprofv3 --marker-trace shows it,
+    so a kernel trace can be cut to one leg); a no-op without the library."""
+    _lib = None
+
+    def __init__(self, name):
+        self.name = name.encode()
+
+    def __enter__(self):
+        if Marker._lib is None:
+            import ctypes
+            try:
+                Marker._lib = ctypes.CDLL("librocprofiler-sdk-roctx.so.1")
+                Marker._lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+            except OSError:
+                Marker._lib = False
+        if Marker._lib:
+            Marker._lib.roctxRangePushA(self.name)
+        return self
+
+    def __exit__(self, *exc):
+        if Marker._lib:
+            Marker._lib.roctxRangePop()
+        return False
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -468,8 +494,9 @@ def estimator_bench(lf, tr, env, R, t, cam, wl, params, grads, out, target, spps
         tr.stats()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
+        with Marker(f"bench:two_ray_spp{spp}"):
+            step()
+            torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st = tr.stats()
         res[str(spp)] = {"ms_per_step": dt * 1e3, "rays_per_s": (st["rays_primary"] + st["rays_secondary"]) / dt,
@@ -527,29 +554,30 @@ def inverse_rendering_bench(lf, tr, sc, wl, params, grads, args, n_states=3, bat
     tr.profile_read()
     torch.cuda.synchronize()
     t_all = time.perf_counter()
-    for it in range(n_it):
-        frac = it / n_it
-        spp = 8 if frac < 0.5 else (16 if frac < 0.8 else 32)
-        unlocked = () if frac < 2 / 15 else (("albedo",) if frac < 0.6 else mats)
-        stt = states[it % n_states]
-        t0 = time.perf_counter()
-        pix = torch.randint(0, res * res, (batch,), device=dev, generator=gen).sort().values
-        o_b, d_b = stt["o"][pix].contiguous(), stt["d"][pix].contiguous()
-        cfg = dict(rays=(o_b, d_b), k=wl.k, spp=spp, seed=100 + it, flags=lf.FLAG_NEE | lf.FLAG_SOBOL)
-        out = tr.render(stt["env"], stt["R"], stt["t"], **cfg)
-        loss, g = tr.l1_loss(out["radiance"], stt["target"][pix].contiguous())
-        grads["env"] = stt["g_env"]
-        tr.render_backward(stt["env"], stt["R"], stt["t"], d_radiance=g, grads=grads, **cfg)
-        tv, g_tv = tr.loss_tv(stt["env"])
-        with torch.no_grad():
-            stt["env"].sub_(lr_env * (grads["env"] + lam_tv * g_tv)).clamp_(min=0.0)
-            for k_ in unlocked:
-                params[k_].sub_(lr_mat * grads[k_]).clamp_(0.0, 1.0)
-        torch.cuda.synchronize()
-        key = f"spp{spp}_" + ("lighting" if not unlocked else ("lighting+albedo" if len(unlocked) == 1 else "all"))
-        b = per_bucket.setdefault(key, [0, 0.0])
-        b[0] += 1
-        b[1] += time.perf_counter() - t0
+    with Marker("bench:inverse_rendering"):
+        for it in range(n_it):
+            frac = it / n_it
+            spp = 8 if frac < 0.5 else (16 if frac < 0.8 else 32)
+            unlocked = () if frac < 2 / 15 else (("albedo",) if frac < 0.6 else mats)
+            stt = states[it % n_states]
+            t0 = time.perf_counter()
+            pix = torch.randint(0, res * res, (batch,), device=dev, generator=gen).sort().values
+            o_b, d_b = stt["o"][pix].contiguous(), stt["d"][pix].contiguous()
+            cfg = dict(rays=(o_b, d_b), k=wl.k, spp=spp, seed=100 + it, flags=lf.FLAG_NEE | lf.FLAG_SOBOL)
+            out = tr.render(stt["env"], stt["R"], stt["t"], **cfg)
+            loss, g = tr.l1_loss(out["radiance"], stt["target"][pix].contiguous())
+            grads["env"] = stt["g_env"]
+            tr.render_backward(stt["env"], stt["R"], stt["t"], d_radiance=g, grads=grads, **cfg)
+            tv, g_tv = tr.loss_tv(stt["env"])
+            with torch.no_grad():
+                stt["env"].sub_(lr_env * (grads["env"] + lam_tv * g_tv)).clamp_(min=0.0)
+                for k_ in unlocked:
+                    params[k_].sub_(lr_mat * grads[k_]).clamp_(0.0, 1.0)
+            torch.cuda.synchronize()
+            key = f"spp{spp}_" + ("lighting" if not unlocked else ("lighting+albedo" if len(unlocked) == 1 else "all"))
+            b = per_bucket.setdefault(key, [0, 0.0])
+            b[0] += 1
+            b[1] += time.perf_counter() - t0
     dt = time.perf_counter() - t_all
     phases = tr.profile_read()
     tr.profile(False)
@@ -606,9 +634,10 @@ def geometry_bench(lf, tr, env, R, t, cam, wl, params, grads, out, ref, args, s_
     tr.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.geo_steps):
-        loss = gstep()
-    torch.cuda.synchronize()
+    with Marker("bench:geometry"):
+        for _ in range(args.geo_steps):
+            loss = gstep()
+        torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = tr.stats()
     res = {"ms_per_step": dt * 1e3 / args.geo_steps, "rays_per_s": (st["rays_primary"] + st["rays_secondary"]) / dt,
