@@ -87,10 +87,10 @@ def parse():
                     help="iterations of the staged inverse-rendering loop (0 = skip)")
     ap.add_argument("--nee-spp", type=str, default="8,16,32",
                     help="comma-separated spp of the two-ray estimator's training steps (empty = skip)")
-    ap.add_argument("--serve-requests", type=int, default=300, help="requests per serving run (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=500, help="requests per serving run (0 = skip)")
     ap.add_argument("--serve-loads", type=str, default="0.5,0.8",
                     help="comma-separated arrival rates as fractions of the plain tracer's capacity")
-    ap.add_argument("--serve-policies", type=str, default="0,1",
+    ap.add_argument("--serve-policies", type=str, default="1",
                     help="comma-separated pass-filling policies (0 shortest first, 1 oldest first, 2 round robin)")
     ap.add_argument("--serve-batch", type=int, default=1048576, help="primary rays per batched pass")
     ap.add_argument("--serve-in-flight", type=int, default=3, help="concurrent passes (one stream each)")

@@ -433,7 +433,7 @@ typedef struct {
   int32_t batch_rays;       /* primary rays per iteration, multiple of 128, >= tile_rays (default 1048576) */
   int32_t max_spp;          /* largest S a request may ask for, 1..64 (default 4) */
   int32_t max_pending;      /* waiting requests before lf_server_submit returns LF_EBUSY (default 4096) */
-  int32_t policy;           /* LF_SCHED_* (default LF_SCHED_SHORTEST_FIRST) */
+  int32_t policy;           /* LF_SCHED_* (default LF_SCHED_OLDEST_FIRST) */
   int32_t max_in_flight;    /* passes running at once, 1..4, each on its own stream with its own
                                scratch (default 2): the latency-bound tail of one pass overlaps
                                the next, and a new arrival starts on a free lane */

@@ -343,7 +343,7 @@ class Server:
     Request tensors are kept alive here until the request has completed."""
 
     def __init__(self, tracer: Tracer, max_slots=16, hbm_budget_bytes=16 << 30, tile_rays=65536,
-                 batch_rays=1048576, max_spp=4, max_pending=4096, policy=_lib.SCHED_SHORTEST_FIRST,
+                 batch_rays=1048576, max_spp=4, max_pending=4096, policy=_lib.SCHED_OLDEST_FIRST,
                  max_in_flight=2, k=32, flags=0, **kw):
         self.L = tracer.L
         self.tracer = tracer

@@ -448,7 +448,7 @@ void lf_server_config_default(lf_server_config *cfg) {
   cfg->batch_rays = 1048576;
   cfg->max_spp = 4;
   cfg->max_pending = 4096;
-  cfg->policy = LF_SCHED_SHORTEST_FIRST;
+  cfg->policy = LF_SCHED_OLDEST_FIRST;
   cfg->max_in_flight = 2;
   lf_params_default(&cfg->params);
 }

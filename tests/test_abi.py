@@ -109,6 +109,7 @@ def test_server_null_paths_and_defaults(lib):
     assert (cfg.max_slots, cfg.tile_rays, cfg.batch_rays, cfg.max_spp) == (16, 65536, 1048576, 4)
     assert cfg.hbm_budget_bytes == 16 << 30 and cfg.tile_rays % 128 == 0 and cfg.batch_rays % 128 == 0
     assert cfg.params.k == 32 and cfg.params.alpha_min == 1.0 / 255.0
+    assert cfg.policy == _lib.SCHED_OLDEST_FIRST and cfg.max_in_flight == 2
 
 
 def test_binding_constants_match_the_header():
