@@ -111,3 +111,27 @@ def test_watchdog_cuts_a_long_render_short(tracer):
     tracer.sync()
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_watchdog_arguments_and_an_idle_stream(tracer):
+    """A negative timeout is an argument error (nothing waits, nothing is
+    cut short); an idle stream passes the watchdog at once, also with the
+    abort word raised (it is cleared, as lf_sync clears it)."""
+    import paper_2608_29269_amd as lf
+    from paper_2608_29269_amd import _lib
+    with pytest.raises(lf.LFError) as e:
+        tracer.sync(timeout_ms=-1.0)
+    assert _status(e) == _lib.LF_EINVAL
+    tracer.sync(timeout_ms=0.0)
+    tracer.abort()
+    tracer.sync(timeout_ms=1000.0)
+    wl = scenegen.make_workload(1, scale=0.25, resolution=16)
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    args = state_args(tracer, wl.scene, st)
+    a = _outputs(tracer.render(**args, cameras=st.cameras, k=16, spp=1, seed=2, flags=1))
+    tracer.sync(timeout_ms=60000.0)
+    b = _outputs(tracer.render(**args, cameras=st.cameras, k=16, spp=1, seed=2, flags=1))
+    tracer.sync()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
