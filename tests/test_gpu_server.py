@@ -187,3 +187,25 @@ def test_lone_whole_requests_equal_rendered_alone(setup, lanes):
         for key in ("radiance", "depth", "normal", "alpha"):
             a, b = got[key].cpu().numpy(), ref[key].cpu().numpy()
             assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (key, q.camera.w, q.camera.h, q.spp)
+
+
+@pytest.mark.parametrize("k", [6, 12, 48])
+def test_served_at_other_k_buckets_equals_rendered_alone(setup, k):
+    """The batched kernels at the other k-buffer instantiations (8, 16 and 64
+    slots: k = 6, 12 and 48 leave sentinel slots in front), in a mix of
+    requests that share passes, equal lf_render of each request at the same k,
+    bit for bit."""
+    import paper_2608_29269_amd as lf
+    tr, wl = setup
+    reqs = _requests(5, seed=20 + k)
+    srv = lf.Server(tr, max_slots=3, tile_rays=256, batch_rays=1024, max_spp=4, policy=1, max_in_flight=2, k=k)
+    try:
+        tickets = [srv.submit(dev(q.env), q.camera, R=dev(q.R), t=dev(q.t), spp=q.spp, seed=q.seed) for q in reqs]
+        outs = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    for q, got in zip(reqs, outs):
+        ref = tr.render(dev(q.env), R=dev(q.R), t=dev(q.t), cameras=[q.camera], k=k, spp=q.spp, seed=q.seed)
+        for key in ("radiance", "depth", "normal", "alpha"):
+            a, b = got[key].cpu().numpy(), ref[key].cpu().numpy()
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (key, k, q.camera.w, q.camera.h, q.spp)
