@@ -19,22 +19,29 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 // Per-block accumulation of environment-texel gradients in an LDS table
 // keyed by texel (open addressing, a few probes), flushed with one atomic per
 // texel and channel; a texel that finds no slot goes to device memory
-// directly.  Importance-sampled directions and the background of
-// neighbouring pixels meet the same texels, so this replaces most
-// device-scope atomics on shared addresses.
-constexpr int kEnvAggBits = 10;
-constexpr int kEnvAggSlots = 1 << kEnvAggBits;  // 16 KB of LDS per block with the values
+// directly.  The background of neighbouring pixels meets the same few
+// texels, and so do importance-sampled directions where the map is bright,
+// so this replaces most device-scope atomics on shared addresses.  Other
+// texels a block rarely meets twice: they go to device memory directly and
+// leave the table's slots to the ones that repeat.
+constexpr int kEnvAggBits = 11;
+constexpr int kEnvAggSlots = 1 << kEnvAggBits;  // 32 KB of LDS per block with the values
 constexpr int kEnvAggProbes = 8;
+constexpr double kEnvHot = 16.0;  // pooled: luminance at least this many times the map's mean
 
 struct BlockEnvTable {
   int *key;     // [kEnvAggSlots], -1 when free
   float *val;   // [3][kEnvAggSlots]
   float *genv;  // [H, W, 3] in device memory
-  __device__ void add(int texel, double dx, double dy, double dz) {
+  const double *lum;  // [H, W] clamped texel luminance
+  double lum_hot;     // texels at or above it are pooled
+  // repeats: the caller expects the texel again within the block
+  __device__ void add(int texel, double dx, double dy, double dz, bool repeats) {
     const float gx = (float)dx, gy = (float)dy, gz = (float)dz;
     const uint32_t h = (uint32_t)texel * 2654435761u;
+    const int probes = repeats || lum[texel] >= lum_hot ? kEnvAggProbes : 0;
 #pragma unroll 1
-    for (int p = 0; p < kEnvAggProbes; ++p) {
+    for (int p = 0; p < probes; ++p) {
       const int slot = (int)((h >> (32 - kEnvAggBits)) + (uint32_t)p) & (kEnvAggSlots - 1);
       const int k = atomicCAS(key + slot, -1, texel);
       if (k == -1 || k == texel) {
@@ -63,7 +70,7 @@ struct EnvRecords {
   double *val;    // [rays * cap][3]
   int64_t base;   // first record of this ray
   int n;          // records written so far
-  __device__ void add(int texel, double gx, double gy, double gz) {
+  __device__ void add(int texel, double gx, double gy, double gz, bool) {
     const int64_t r = base + n++;
     key[r] = (uint64_t)texel;
     idx[r] = (int32_t)r;
@@ -74,13 +81,13 @@ struct EnvRecords {
 };
 
 template <class EAcc>
-__device__ __forceinline__ void env_scatter(const EnvView &E, EAcc &acc, d3 w, d3 g) {
+__device__ __forceinline__ void env_scatter(const EnvView &E, EAcc &acc, d3 w, d3 g, bool repeats) {
   Taps tp;
   env_taps(E, w, tp);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (tp.w[k] == 0.0) continue;
-    acc.add((int)tp.i[k], tp.w[k] * g.x, tp.w[k] * g.y, tp.w[k] * g.z);
+    acc.add((int)tp.i[k], tp.w[k] * g.x, tp.w[k] * g.y, tp.w[k] * g.z, repeats);
   }
 }
 
@@ -145,7 +152,7 @@ __device__ __forceinline__ void adj_shade_ray(const RenderArgs &a, const GradArg
   if (!(P.flags & LF_FLAG_NO_BACKGROUND)) {
     const d3 Ed = env_eval(a.E, d);
     gT += dot(gL, Ed);
-    env_scatter(a.E, acc, d, rc.T * gL);
+    env_scatter(a.E, acc, d, rc.T * gL, true);
   }
   AdjSeed sd = {};
   sd.T = (float)rc.T;
@@ -181,9 +188,9 @@ __device__ __forceinline__ void adj_shade_ray(const RenderArgs &a, const GradArg
     const d3 gF = (rc.A / S) * gL;
     const d3 gfc = K_ * mk(gF.x * Lin.x, gF.y * Lin.y, gF.z * Lin.z);
     const d3 gLin = K_ * mk(gF.x * fc.x, gF.y * fc.y, gF.z * fc.z);
-    env_scatter(a.E, acc, w, T2 * gLin);
-    if (has & 1u) env_scatter(a.E, acc, we, mk(ce.x * gLin.x, ce.y * gLin.y, ce.z * gLin.z));
-    if (has & 2u) env_scatter(a.E, acc, wb, mk(cb.x * gLin.x, cb.y * gLin.y, cb.z * gLin.z));
+    env_scatter(a.E, acc, w, T2 * gLin, false);
+    if (has & 1u) env_scatter(a.E, acc, we, mk(ce.x * gLin.x, ce.y * gLin.y, ce.z * gLin.z), false);
+    if (has & 2u) env_scatter(a.E, acc, wb, mk(cb.x * gLin.x, cb.y * gLin.y, cb.z * gLin.z), false);
     fcos_bwd(rc.n, w, wo, rc.a, rc.m, rc.r, P.flags, gfc, gn, ga, gm, gr);
   }
   // normalisation n_bar = N / |N|; z_bar = Z * inv with inv = 1/(A + eps)
@@ -211,7 +218,9 @@ __global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G) {
     val[j] = val[kEnvAggSlots + j] = val[2 * kEnvAggSlots + j] = 0.0f;
   }
   __syncthreads();
-  BlockEnvTable acc{key, val, G.g_env};
+  // the map's mean luminance weighted as the sampler weights rows (by sin theta), over the texels
+  const double mean = a.E.scal[0] / ((double)a.E.H * a.E.W);
+  BlockEnvTable acc{key, val, G.g_env, a.E.lum, kEnvHot * mean};
   const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ray < a.R) adj_shade_ray(a, G, ray, acc);
   __syncthreads();
