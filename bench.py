@@ -103,8 +103,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the tracer replicates the scene per GPU and has no "
-              "multi-GPU path in this build; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (each GPU would hold its "
+              "own copy of the scene and trace its share of the rays); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_probe:
