@@ -471,33 +471,6 @@ def test_prefilter_keeps_hits_at_the_support_edge_and_t_min(tracer):
     np.testing.assert_array_equal(out["hit_idx"].cpu().numpy()[~amb], ref["hit_idx"][~amb])
 
 
-def _degenerate_scene():
-    """A stack of surfels along +z with degenerate members, above 200 random
-    ones: opacity below alpha_min (no support), an unnormalised quaternion
-    (5 x a unit one), a needle (one scale 1e-6), a surfel edge-on to the rays,
-    one whose plane holds some rays' origins, a huge one (scales 50), one at
-    opacity 1 (capped at alpha_cap), and two identical surfels."""
-    from tests.helpers import make_scene
-    rng = np.random.default_rng(5)
-    c, s = np.cos(0.3), np.sin(0.3)
-    r4 = np.cos(np.pi / 4)
-    mu = [[0, 0, 0.0], [0, 0, 0.2], [0, 0, 0.4], [0, 0, 0.6], [0, 0, 0.8], [0, 0, 1.0], [0, 0, 1.2],
-          [0.01, 0, 1.4], [0.01, 0, 1.4]]
-    q = [[1, 0, 0, 0], [5 * c, 5 * s, 0, 0], [1, 0, 0, 0], [r4, r4, 0, 0], [1, 0, 0, 0], [1, 0, 0, 0],
-         [1, 0, 0, 0], [1, 0, 0, 0], [1, 0, 0, 0]]
-    scale = [[0.3, 0.3], [0.3, 0.2], [1e-6, 0.2], [0.3, 0.3], [0.3, 0.3], [50.0, 50.0], [0.3, 0.3],
-             [0.25, 0.25], [0.25, 0.25]]
-    opac = [0.002, 0.6, 0.9, 0.8, 0.5, 0.3, 1.0, 0.4, 0.4]
-    m = 200
-    mu = np.concatenate([np.array(mu), np.c_[rng.uniform(-1, 1, (m, 2)), rng.uniform(1.8, 3.0, m)]])
-    q = np.concatenate([np.array(q, float), scenegen.uniform_quaternions(rng, m)])
-    scale = np.concatenate([np.array(scale), np.exp(rng.uniform(np.log(0.05), np.log(0.4), (m, 2)))])
-    opac = np.concatenate([opac, rng.uniform(0.05, 1.0, m)])
-    n = len(mu)
-    return make_scene(mu, q=q, scale=scale, opacity=opac, albedo=rng.uniform(0, 1, (n, 3)),
-                      roughness=rng.uniform(0.05, 1, n), metallic=rng.uniform(0, 1, n))
-
-
 def test_degenerate_surfels_match_the_oracle(tracer):
     """One-bounce parity (primary and secondary hit lists, outputs) on a
     scene with degenerate surfels, and what the method fixes for them: a
@@ -505,15 +478,9 @@ def test_degenerate_surfels_match_the_oracle(tracer):
     a ray starting on a surfel's plane does not hit it (t = 0 < t_min), and
     two identical surfels sit next to each other in every list, the lower
     index first."""
-    sc = _degenerate_scene()
-    g = np.linspace(-0.3, 0.3, 24)
-    X, Y = np.meshgrid(g, g)
-    d = np.c_[0.05 * X.ravel(), 0.05 * Y.ravel(), np.ones(X.size)]
-    d /= np.linalg.norm(d, axis=1, keepdims=True)
-    o = np.c_[X.ravel(), Y.ravel(), np.full(X.size, -2.0)]
-    o2 = np.c_[np.random.default_rng(6).uniform(-0.2, 0.2, (64, 2)), np.full(64, 0.8)]  # on surfel 4's plane
-    o = np.concatenate([o, o2]).astype(np.float32)
-    d = np.concatenate([d, np.tile([0.0, 0.0, 1.0], (64, 1))]).astype(np.float32)
+    from tests.helpers import degenerate_scene, degenerate_rays
+    sc = degenerate_scene()
+    o, d = degenerate_rays()
     env = scenegen.lognormal_env(np.random.default_rng(7), 16, 32)
     upload_scene(tracer, sc)
     out = tracer.render(env=dev(env), rays=(dev(o), dev(d)), k=16, spp=2, seed=3, hit_idx=True, sec_hit_idx=True)
