@@ -820,6 +820,12 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
   // a wrong bound costs a retrace)
   const lfh::CallSig sig = call_sig(c, xf, env, rays, p);
   a.use_hint = had_sig && memcmp(&sig, &c->last_sig, sizeof sig) == 0;
+  // the order-fixed form's record limit and buffers before any work is enqueued
+  lf::DetArgs det;
+  if ((p->flags & LF_FLAG_DETERMINISTIC) && a.R > 0) {
+    st = deterministic_buffers(c, a, (int64_t)env->h * env->w, det);
+    if (st) return st;
+  }
   const int64_t n = c->s.n;
   hipStream_t s = c->stream;
   {
@@ -857,16 +863,13 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
   lf::GradArgs ga{g->d_radiance, g->d_depth, g->d_normal, g->d_alpha, gi->d_mu, gi->d_q, gi->d_scale,
                   gi->d_opacity, gi->d_albedo, gi->d_roughness, gi->d_metallic, gi->d_env};
   if (p->flags & LF_FLAG_DETERMINISTIC) {
-    lf::DetArgs d;
-    st = deterministic_buffers(c, a, (int64_t)env->h * env->w, d);
-    if (st) return st;
     {
       Phase ph(c, 10);
-      lf::launch_adjoint_shade_det(a, ga, d, s);
+      lf::launch_adjoint_shade_det(a, ga, det, s);
     }
     {
       Phase ph(c, 16);
-      lf::launch_adjoint_hits_det(a, ga, d, s);
+      lf::launch_adjoint_hits_det(a, ga, det, s);
     }
     return backward_done(c, sig);
   }

@@ -497,3 +497,34 @@ def test_degenerate_surfels_match_the_oracle(tracer):
     assert both.all()
     assert np.array_equal(np.argmax(h == 8, axis=1), np.argmax(h == 7, axis=1) + 1)
     assert (ref["sec_alpha"] > 0).mean() > 0.2
+
+
+def test_size_limits_are_reported_before_any_work(tracer):
+    """Ray ids are 32-bit: a call with rays x secondary slots at or past
+    2^31 - 1 is refused with LF_EUNSUPPORTED by the host checks, before any
+    buffer is sized or kernel launched (so the cameras below cost nothing),
+    and the context serves the next call as before."""
+    import paper_2608_29269_amd as lf
+    from paper_2608_29269_amd import _lib
+    wl = scenegen.make_workload(1, scale=0.25, resolution=16)
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    args = state_args(tracer, wl.scene, st)
+    ref = tracer.render(**args, cameras=st.cameras, k=16, spp=1, seed=2, flags=1)
+    ref = {key: v.cpu().numpy() for key, v in ref.items()}
+    big = scenegen.look_at_camera(np.array([0.0, 0.0, 3.0]), 46341, 46341)  # 2^31 + 4,280 pixels
+    half = scenegen.look_at_camera(np.array([0.0, 0.0, 3.0]), 32768, 32768)  # 2^30 pixels, x 2 slots
+    for cam, spp, flags in ((big, 1, 1), (half, 2, 0), (half, 1, int(lf.FLAG_NEE))):
+        dummy = dev(np.zeros((1, 3), np.float32))
+        out = dict(radiance=dummy, depth=dummy, normal=dummy, alpha=dummy)  # never written: the call is refused
+        with pytest.raises(lf.LFError) as e:
+            tracer.render(**args, cameras=[cam], k=16, spp=spp, seed=2, flags=flags, out=out)
+        assert e.value.status == _lib.LF_EUNSUPPORTED, (cam.w, spp, flags)
+        with pytest.raises(lf.LFError) as e:
+            tracer.render_backward(**args, cameras=[cam], k=16, spp=spp, seed=2, flags=flags,
+                                   d_radiance=None)
+        assert e.value.status == _lib.LF_EUNSUPPORTED
+    again = tracer.render(**args, cameras=st.cameras, k=16, spp=1, seed=2, flags=1)
+    tracer.sync()
+    for key in ref:
+        assert np.array_equal(again[key].cpu().numpy(), ref[key]), key
