@@ -95,7 +95,10 @@ typedef struct {
  * and placed depth-first with contiguous children, surfel records reordered
  * to match, then the bounds and the
  * traversal nodes with child boxes quantised conservatively to 8 bits per
- * plane.  LF_EUNSUPPORTED if a hierarchy is deeper than the traversal stack. */
+ * plane.  Synchronous: it first waits for the work already on the context's
+ * stream (which reads the buffers it rebuilds) and returns once the hierarchy
+ * is built.  LF_EUNSUPPORTED if a hierarchy is deeper than the traversal
+ * stack. */
 lf_status lf_scene_set(lf_ctx *ctx, const lf_surfels *surfels);
 /* Recomputes trace records and bounds bottom-up after in-place updates of the
  * retained arrays (same n, same object ranges), and re-quantises the

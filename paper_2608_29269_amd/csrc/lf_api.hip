@@ -510,6 +510,9 @@ lf_status lf_scene_set(lf_ctx *c, const lf_surfels *sf) {
     if (off[i + 1] < off[i]) return fail(c, LF_EINVAL, "object_offset must be non-decreasing");
   if (c->servers > 0) return fail(c, LF_EBUSY, "a relight server is reading the scene");
   set_device(c);
+  // calls still running on the stream read the buffers rebuilt below (some
+  // of them written by copies that the stream does not order)
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "scene set");
   c->has_scene = false;
   c->s = lf::SurfelArrays{sf->mu, sf->q, sf->scale, sf->opacity, sf->albedo, sf->roughness, sf->metallic, sf->n};
   c->n_inst = n_inst;
