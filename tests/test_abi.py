@@ -129,3 +129,26 @@ def test_status_codes_match_the_header():
     assert codes["LF_OK"] == 0 and len(codes) == len(_lib.STATUS_NAMES)
     for name, v in codes.items():
         assert getattr(_lib, name) == v and _lib.STATUS_NAMES[v] == name, name
+
+
+def compile_c_demo(tmp_path):
+    """Builds tests/c_abi_demo.c with gcc against the header, the built
+    library and the HIP runtime (C API only)."""
+    import subprocess
+    from paper_2608_29269_amd import _lib
+    lib_dir = os.path.dirname(_lib.LIB_PATH)
+    exe = tmp_path / "c_abi_demo"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                           "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"),
+                           os.path.join(ROOT, "tests", "c_abi_demo.c"), "-L" + lib_dir, "-llightfuse",
+                           "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath," + lib_dir, "-Wl,-rpath,/opt/rocm/lib", "-lm",
+                           "-o", str(exe)])
+    return exe
+
+
+def test_c_caller_compiles_and_links(lib, tmp_path):
+    """A plain C99 program that drives the whole boundary (scene, render,
+    backward, errors) compiles warning-free against the header and links
+    against the library (it runs in the GPU tests)."""
+    assert compile_c_demo(tmp_path).exists()
+
