@@ -877,8 +877,12 @@ lf_status lf_render_backward(lf_ctx *c, const lf_transforms *xf, const lf_envmap
     return backward_done(c, sig);
   }
   {
+    // partial copies of the environment gradient, as many as fit in 256 MB
+    const int64_t m = (int64_t)3 * env->h * env->w;
+    int copies = (int)std::min<int64_t>(lf::kEnvGradCopies, ((int64_t)256 << 20) / (4 * m));
+    if (copies > 1 && !c->env_part.ensure(sizeof(float) * copies * m)) copies = 1;
     Phase ph(c, 10);
-    lf::launch_adjoint_shade(a, ga, s);
+    lf::launch_adjoint_shade(a, ga, copies > 1 ? c->env_part.as<float>() : nullptr, copies, s);
   }
   {
     Phase ph(c, 16);

@@ -210,7 +210,10 @@ __device__ __forceinline__ void adj_shade_ray(const RenderArgs &a, const GradArg
   a.seeds[ray] = sd;
 }
 
-__global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G) {
+// Every block adds its texel gradients to copy blockIdx % copies of the map
+// in G.g_env: device-scope atomics from all blocks on the bright texels would
+// otherwise serialise on single addresses.
+__global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G, int copies) {
   __shared__ int key[kEnvAggSlots];
   __shared__ float val[3 * kEnvAggSlots];
   for (int j = threadIdx.x; j < kEnvAggSlots; j += blockDim.x) {
@@ -220,7 +223,8 @@ __global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G) {
   __syncthreads();
   // the map's mean luminance weighted as the sampler weights rows (by sin theta), over the texels
   const double mean = a.E.scal[0] / ((double)a.E.H * a.E.W);
-  BlockEnvTable acc{key, val, G.g_env, a.E.lum, kEnvHot * mean};
+  float *genv = G.g_env + (int64_t)(blockIdx.x % (unsigned)copies) * 3 * a.E.H * a.E.W;
+  BlockEnvTable acc{key, val, genv, a.E.lum, kEnvHot * mean};
   const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ray < a.R) adj_shade_ray(a, G, ray, acc);
   __syncthreads();
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(256) void k_adj_shade(RenderArgs a, GradArgs G) {
     if (t < 0) continue;
     for (int c = 0; c < 3; ++c) {
       const float g = val[c * kEnvAggSlots + j];
-      if (g != 0.0f) atomicAdd(G.g_env + 3 * t + c, g);
+      if (g != 0.0f) atomicAdd(genv + 3 * t + c, g);
     }
   }
 }
@@ -538,9 +542,28 @@ void launch_adjoint_hits_det(const RenderArgs &a, const GradArgs &g, const DetAr
                      (const int32_t *)d.hit_idx, d.n_hit, d.hit_unused, (const double *)d.hit_val, g);
 }
 
-void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st) {
+// g_env[i] = the copies' values at i, added in copy order
+__global__ void k_env_copies_sum(const float *part, int64_t m, int copies, float *genv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  float s = 0.0f;
+  for (int x = 0; x < copies; ++x) s += part[x * m + i];
+  genv[i] = s;
+}
+
+void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, float *part, int copies, hipStream_t st) {
   if (a.R <= 0) return;
-  hipLaunchKernelGGL(k_adj_shade, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, g);
+  if (copies <= 1 || !part) {
+    hipLaunchKernelGGL(k_adj_shade, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, g, 1);
+    return;
+  }
+  const int64_t m = (int64_t)3 * a.E.H * a.E.W;
+  launch_fill_f32(part, 0.0f, copies * m, st);
+  GradArgs gp = g;
+  gp.g_env = part;
+  hipLaunchKernelGGL(k_adj_shade, dim3(blocks(a.R, 256)), dim3(256), 0, st, a, gp, copies);
+  hipLaunchKernelGGL(k_env_copies_sum, dim3(blocks(m, 256)), dim3(256), 0, st, (const float *)part, m, copies,
+                     g.g_env);
 }
 
 void launch_adjoint_hits(const RenderArgs &a, const GradArgs &g, hipStream_t st) {

@@ -87,6 +87,7 @@ struct lf_ctx {
   // per call
   lfh::DevBuf env_cdf_row, env_cdf_col, env_lum, env_rowsum, env_roww, env_scal;
   lfh::DevBuf queue, qcount, work, kbuf1, kbuf2, hint2, contrib, frozen, lossbuf, cams, rec1, rec2, seeds;
+  lfh::DevBuf env_part;  // partial copies of the environment gradient (shading adjoint)
   lfh::DevBuf bounds, skeys, skeys2, svals, svals2, shist;
   lfh::DevBuf det_key, det_key2, det_idx, det_idx2, det_hval, det_eval, det_hist;  // LF_FLAG_DETERMINISTIC
   // the k-buffers in kbuf1 / kbuf2 belong to the last render call with this signature

@@ -155,7 +155,11 @@ struct GradArgs {
 };
 // shading adjoint (env gradients, compositing seeds), then the compositing adjoint of the seeded rays from the
 // primary k-buffers (kbuf1) of the replayed primary pass
-void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, hipStream_t st);
+// Environment gradients go to `copies` zeroed partial maps in part (block b
+// adds to copy b % copies; copies = 1: straight to g.g_env, part unused),
+// which are then summed into g.g_env in copy order.
+constexpr int kEnvGradCopies = 16;
+void launch_adjoint_shade(const RenderArgs &a, const GradArgs &g, float *part, int copies, hipStream_t st);
 void launch_adjoint_hits(const RenderArgs &a, const GradArgs &g, hipStream_t st);
 // Order-fixed (LF_FLAG_DETERMINISTIC) form of the two adjoints: contributions
 // go to records at fixed positions, are sorted by target and summed in
