@@ -719,13 +719,14 @@ def serve_bench(tr, sc, args, loads, policies=(0,)):
         tr.stats()
         lat = []
         t_start = time.perf_counter()
-        for q, d in zip(reqs, dv):
-            now = time.perf_counter() - t_start
-            if now < q.arrival_s:
-                time.sleep(q.arrival_s - now)
-            tr.render(d["env"], d["R"], d["t"], cameras=[q.camera], k=32, spp=q.spp, seed=q.seed, out=d["out"])
-            torch.cuda.synchronize()
-            lat.append(time.perf_counter() - t_start - q.arrival_s)
+        with Marker(f"bench:serve_plain_load{load}"):
+            for q, d in zip(reqs, dv):
+                now = time.perf_counter() - t_start
+                if now < q.arrival_s:
+                    time.sleep(q.arrival_s - now)
+                tr.render(d["env"], d["R"], d["t"], cameras=[q.camera], k=32, spp=q.spp, seed=q.seed, out=d["out"])
+                torch.cuda.synchronize()
+                lat.append(time.perf_counter() - t_start - q.arrival_s)
         span = time.perf_counter() - t_start - reqs[0].arrival_s
         ps = tr.stats()
         plain = {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(np.mean(lat)) * 1e3,
@@ -739,14 +740,15 @@ def serve_bench(tr, sc, args, loads, policies=(0,)):
                             max_in_flight=args.serve_in_flight)
             tickets = []
             t_start = time.perf_counter()
-            for q, d in zip(reqs, dv):
-                now = time.perf_counter() - t_start
-                if now < q.arrival_s:
-                    time.sleep(q.arrival_s - now)
-                tickets.append(srv.submit(d["env"], q.camera, R=d["R"], t=d["t"], spp=q.spp, seed=q.seed,
-                                          out=d["out"]))
-            for tk in tickets:
-                srv.wait(tk)
+            with Marker(f"bench:serve_{POLICY_NAMES[policy]}_load{load}"):
+                for q, d in zip(reqs, dv):
+                    now = time.perf_counter() - t_start
+                    if now < q.arrival_s:
+                        time.sleep(q.arrival_s - now)
+                    tickets.append(srv.submit(d["env"], q.camera, R=d["R"], t=d["t"], spp=q.spp, seed=q.seed,
+                                              out=d["out"]))
+                for tk in tickets:
+                    srv.wait(tk)
             slat = [srv.latency_ms(tk) / 1e3 for tk in tickets]
             st = srv.stats()
             srv.close()

@@ -449,7 +449,8 @@ void lf_server_config_default(lf_server_config *cfg);
  * completed (lf_server_poll reports done or lf_server_wait returned). */
 typedef struct {
   lf_transforms xf;   /* host or device [M,3,3] and [M,3] (NULL if M == 0) */
-  lf_envmap env;      /* host or device texels; copied into the request's slot on admission */
+  lf_envmap env;      /* host or device texels; host arrays (texels, transforms) are copied into
+                         the request's slot on admission, device arrays are read in place */
   lf_camera cam;      /* one pinhole camera; R = cam.w * cam.h rays, ids from 0 */
   int32_t spp;        /* S, 1..max_spp */
   uint64_t seed;      /* sampler seed */

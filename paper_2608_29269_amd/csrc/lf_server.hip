@@ -64,7 +64,8 @@ struct Lane {
   std::vector<lf::SchedTile> tiles;
   lf::ChunkDesc *h_chunks = nullptr;  // pinned
   IterReadback *h_rb = nullptr;       // pinned
-  DevBuf d_chunks, rec1, rec2, queue, qcount, work, kbuf1, kbuf2, contrib, skeys, skeys2, svals, svals2, shist, status;
+  DevBuf d_chunks, rec1, rec2, queue, work, kbuf1, kbuf2, contrib, skeys, skeys2, svals, svals2, shist;
+  DevBuf rbd;  // IterReadback on the device: the pass's status word, then its secondary-queue count
   DevBuf hint2;  // k-th distance per (ray, slot), written by the single-request kernels
 };
 
@@ -131,34 +132,62 @@ void finish_ticket(lf_server *s, uint64_t t, lf_status st, double when) {
   }
 }
 
-// Stages an admitted request into its slot on stream st: transforms, camera,
-// environment copy, instance records, sampling tables and the slot table
-// entry; records the slot's staged event.
+// True if p is device memory of the server's device, which the kernels can
+// read in place (host memory is copied in; the caller keeps every buffer of
+// a request valid until it completes either way).
+bool device_resident(const void *p, int device) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice && at.device == device;
+}
+
+// Stages an admitted request into its slot on stream st: transforms and
+// environment (read in place from device memory, else copied in), camera,
+// instance records, sampling tables and the slot table entry; records the
+// slot's staged event.  Every copy here runs as a small kernel that may wait
+// for a compute unit the passes in flight hold, so device inputs are not copied.
 bool stage_slot(lf_server *s, int slot, const lf_request &r, hipStream_t st) {
   lf_ctx *c = s->ctx;
   SlotDev &sd = s->slots[slot];
   const int M = c->n_inst - 1;
   const int H = r.env.h, W = r.env.w;
-  if (!sd.xf.ensure(sizeof(float) * 12 * (M > 0 ? M : 1)) || !sd.tex.ensure(sizeof(float) * 3 * (size_t)H * W) ||
+  const bool env_dev = device_resident(r.env.texels, c->device);
+  const bool xf_dev = M > 0 && device_resident(r.xf.R, c->device) && device_resident(r.xf.t, c->device);
+  if (!sd.xf.ensure(sizeof(float) * 12 * (M > 0 ? M : 1)) ||
+      (!env_dev && !sd.tex.ensure(sizeof(float) * 3 * (size_t)H * W)) ||
       !lfh::ensure_env_tables(sd.cdf_row, sd.cdf_col, sd.lum, sd.rowsum, sd.roww, sd.scal, H, W))
     return false;
-  float *xf = sd.xf.as<float>();
-  if (M > 0) {
+  const float *xR = nullptr, *xt = nullptr;
+  if (M > 0 && xf_dev) {
+    xR = r.xf.R;
+    xt = r.xf.t;
+  } else if (M > 0) {
+    float *xf = sd.xf.as<float>();
     if (hipMemcpyAsync(xf, r.xf.R, sizeof(float) * 9 * M, hipMemcpyDefault, st) != hipSuccess ||
         hipMemcpyAsync(xf + 9 * M, r.xf.t, sizeof(float) * 3 * M, hipMemcpyDefault, st) != hipSuccess)
       return false;
+    xR = xf;
+    xt = xf + 9 * M;
   }
-  if (hipMemcpyAsync(sd.tex.p, r.env.texels, sizeof(float) * 3 * (size_t)H * W, hipMemcpyDefault, st) != hipSuccess)
-    return false;
+  const float *tex = r.env.texels;
+  if (!env_dev) {
+    if (hipMemcpyAsync(sd.tex.p, r.env.texels, sizeof(float) * 3 * (size_t)H * W, hipMemcpyDefault, st) !=
+        hipSuccess)
+      return false;
+    tex = sd.tex.as<float>();
+  }
   lf::CamArgs &ca = s->h_cams[slot];
   memset(&ca, 0, sizeof ca);
   if (lfh::camera_args(nullptr, r.cam, ca) != LF_OK) return false;  // validated at submission
   if (hipMemcpyAsync(sd.cam.p, &ca, sizeof ca, hipMemcpyHostToDevice, st) != hipSuccess) return false;
   lf::launch_fill_u32(sd.status.as<uint32_t>(), 0u, 1, st);
-  lf::launch_instances(M > 0 ? xf : nullptr, M > 0 ? xf + 9 * M : nullptr, c->rootbox.as<float>(),
+  lf::launch_instances(xR, xt, c->rootbox.as<float>(),
                        c->d_first.as<int32_t>(), c->d_n.as<int32_t>(), c->d_root.as<int32_t>(), c->n_inst,
                        sd.inst.as<lf::InstRec>(), sd.bounds.as<double>(), sd.status.as<uint32_t>(), st);
-  lf::launch_env_tables(sd.tex.as<float>(), H, W, s->cfg.params.flags, sd.cdf_row.as<double>(),
+  lf::launch_env_tables(tex, H, W, s->cfg.params.flags, sd.cdf_row.as<double>(),
                         sd.cdf_col.as<double>(), sd.lum.as<double>(), sd.rowsum.as<double>(), sd.roww.as<double>(),
                         sd.scal.as<double>(), st);
   lf::BatchSlot &b = s->h_slots[slot];
@@ -166,7 +195,7 @@ bool stage_slot(lf_server *s, int slot, const lf_request &r, hipStream_t st) {
   b.inst = sd.inst.as<lf::InstRec>();
   b.bounds = sd.bounds.as<double>();
   b.cam = sd.cam.as<lf::CamArgs>();
-  b.E.tex = sd.tex.as<float>();
+  b.E.tex = tex;
   b.E.H = H;
   b.E.W = W;
   b.E.cdf_row = sd.cdf_row.as<double>();
@@ -224,12 +253,12 @@ bool launch_pass(lf_server *s, Lane &L, const std::vector<lf::SchedTile> &tiles)
   a.rec1 = L.rec1.as<lf::SurfRec>();
   a.rec2 = L.rec2.as<lf::SurfRec>();
   a.queue = L.queue.as<lf::SecEntry>();
-  a.queue_count = L.qcount.as<uint32_t>();
+  a.queue_count = L.rbd.as<uint32_t>() + 1;
   a.work = L.work.as<uint32_t>();
   a.kbuf1 = L.kbuf1.as<uint32_t>();
   a.kbuf2 = L.kbuf2.as<uint32_t>();
   a.contrib = L.contrib.as<float>();
-  a.status = L.status.as<uint32_t>();
+  a.status = L.rbd.as<uint32_t>();
   const bool sorted = !(s->cfg.params.flags & LF_FLAG_UNSORTED);
   a.order = sorted ? L.svals.as<int32_t>() : nullptr;
   const lf::SchedTile &t0 = tiles[0];
@@ -271,9 +300,10 @@ bool launch_pass(lf_server *s, Lane &L, const std::vector<lf::SchedTile> &tiles)
   lf::launch_composite2(a, st);
   lf::launch_shade2(a, false, st);
   lf::launch_resolve(a, st);
-  if (hipMemcpyAsync(&L.h_rb->status, a.status, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(&L.h_rb->secondaries, a.queue_count, 4, hipMemcpyDeviceToHost, st) != hipSuccess)
-    return false;
+  // one copy for both words (each copy here is a small kernel that waits for
+  // a compute unit the other lanes' traversals may hold)
+  static_assert(sizeof(IterReadback) == 8, "readback layout");
+  if (hipMemcpyAsync(L.h_rb, L.rbd.p, sizeof(IterReadback), hipMemcpyDeviceToHost, st) != hipSuccess) return false;
   lf::launch_fill_u32(a.status, 0u, 1, st);
   if (hipEventRecord(L.done, st) != hipSuccess) return false;
   L.tiles = tiles;
@@ -525,14 +555,14 @@ lf_status lf_server_create(lf_ctx *c, const lf_server_config *cfg, lf_server **o
          hipHostMalloc((void **)&L.h_rb, sizeof(IterReadback), hipHostMallocDefault) == hipSuccess &&
          L.d_chunks.ensure(sizeof(lf::ChunkDesc) * s->max_chunks) && L.rec1.ensure(sizeof(lf::SurfRec) * B) &&
          L.rec2.ensure(sizeof(lf::SurfRec) * BS) && L.queue.ensure(sizeof(lf::SecEntry) * BS) &&
-         L.qcount.ensure(4) && L.work.ensure(sizeof(uint32_t) * lf::kPoolParts) &&
+         L.rbd.ensure(sizeof(IterReadback)) && L.work.ensure(sizeof(uint32_t) * lf::kPoolParts) &&
          L.kbuf1.ensure(sizeof(uint32_t) * 2 * lf::kbucket(s->cfg.params.k) * B) &&
          L.kbuf2.ensure(sizeof(uint32_t) * 2 * lf::kbucket(s->cfg.params.k) * BS) &&
          L.contrib.ensure(sizeof(float) * 3 * BS) && L.skeys.ensure(8 * BS) && L.skeys2.ensure(8 * BS) &&
          L.svals.ensure(4 * BS) && L.svals2.ensure(4 * BS) && L.shist.ensure(4 * lf::radix_sort_hist_words(BS)) &&
-         L.status.ensure(4) && L.hint2.ensure(sizeof(float) * BS);
+         L.hint2.ensure(sizeof(float) * BS);
     if (ok) {
-      lf::launch_fill_u32(L.status.as<uint32_t>(), 0u, 1, L.stream);
+      lf::launch_fill_u32(L.rbd.as<uint32_t>(), 0u, 2, L.stream);
       ok = hipStreamSynchronize(L.stream) == hipSuccess;
     }
   }
