@@ -454,6 +454,61 @@ __device__ __forceinline__ void visit_node(const QNode *node, const RayF &rf, fl
   ihit = hits & imask;
 }
 
+constexpr int kNodeDw = (int)sizeof(QNode) / 4;
+
+// The same test on a node's words already loaded (dw[kNodeDw]), for the
+// wave-packet traversal, whose node words come through the scalar cache.
+__device__ __forceinline__ void visit_node_dw(const uint32_t *dw, const RayF &rf, float tlo, float thi, float *t,
+                                              uint32_t &ihit, uint32_t &lhit, uint32_t &imask, int &cbase,
+                                              int &lbase, bool &desc) {
+  constexpr int kPw = kWide / 4;  // dwords per plane
+  const uint32_t meta = dw[3];
+  // a plane of code q on axis a is met at q * C_a + B_a (see RayF)
+  const float px = __uint_as_float(dw[0]), py = __uint_as_float(dw[1]), pz = __uint_as_float(dw[2]);
+  const float Cx = __uint_as_float((uint32_t)((int)(int8_t)(meta & 0xffu) + 127) << 23) * rf.ix;
+  const float Cy = __uint_as_float((uint32_t)((int)(int8_t)((meta >> 8) & 0xffu) + 127) << 23) * rf.iy;
+  const float Cz = __uint_as_float((uint32_t)((int)(int8_t)((meta >> 16) & 0xffu) + 127) << 23) * rf.iz;
+  const float Bnx = __builtin_fmaf(px, rf.ix, rf.nbx), Bfx = __builtin_fmaf(px, rf.ix, rf.fbx);
+  const float Bny = __builtin_fmaf(py, rf.iy, rf.nby), Bfy = __builtin_fmaf(py, rf.iy, rf.fby);
+  const float Bnz = __builtin_fmaf(pz, rf.iz, rf.nbz), Bfz = __builtin_fmaf(pz, rf.iz, rf.fbz);
+  imask = meta >> 24;
+  cbase = (int)dw[4];
+  lbase = (int)dw[5];
+  const uint32_t vmask = dw[6];
+  // the internal children run along the ray in descending slot order when
+  // the ray points down the node's order axis
+  const uint32_t oax = (vmask >> 8) & 3u;
+  desc = oax == 0 ? !rf.sx : (oax == 1 ? !rf.sy : !rf.sz);
+  // codes of the near and far plane of each axis: lower codes for d >= 0
+  uint32_t nx[kPw], ny[kPw], nz[kPw], fx[kPw], fy[kPw], fz[kPw];
+#pragma unroll
+  for (int w = 0; w < kPw; ++w) {
+    const uint32_t lx = dw[7 + w], ly = dw[7 + kPw + w], lz = dw[7 + 2 * kPw + w];
+    const uint32_t hx = dw[7 + 3 * kPw + w], hy = dw[7 + 4 * kPw + w], hz = dw[7 + 5 * kPw + w];
+    nx[w] = rf.sx ? lx : hx; fx[w] = rf.sx ? hx : lx;
+    ny[w] = rf.sy ? ly : hy; fy[w] = rf.sy ? hy : ly;
+    nz[w] = rf.sz ? lz : hz; fz[w] = rf.sz ? hz : lz;
+  }
+  uint32_t hits = 0;
+#pragma unroll
+  for (int i = 0; i < kWide; ++i) {
+    const int w = i / 4, b = 8 * (i % 4);
+    const float tnx = __builtin_fmaf((float)((nx[w] >> b) & 0xffu), Cx, Bnx);
+    const float tny = __builtin_fmaf((float)((ny[w] >> b) & 0xffu), Cy, Bny);
+    const float tnz = __builtin_fmaf((float)((nz[w] >> b) & 0xffu), Cz, Bnz);
+    const float tfx = __builtin_fmaf((float)((fx[w] >> b) & 0xffu), Cx, Bfx);
+    const float tfy = __builtin_fmaf((float)((fy[w] >> b) & 0xffu), Cy, Bfy);
+    const float tfz = __builtin_fmaf((float)((fz[w] >> b) & 0xffu), Cz, Bfz);
+    const float n = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, tlo));
+    const float f = fminf(fminf(tfx, tfy), fminf(tfz, thi));
+    hits |= n <= f ? 1u << i : 0u;
+    t[i] = n;
+  }
+  hits &= vmask;
+  lhit = hits & ~imask;
+  ihit = hits & imask;
+}
+
 // Exact (double) plane intersection and support test of the surfel at leaf
 // position pos against the object-space ray (o, d).  Returns false if the
 // surfel is not hit; otherwise t and the flip bit.
@@ -951,6 +1006,264 @@ __device__ void trace_pool(const SceneView &S0, const TraceParams &P, const Work
     }
     __builtin_amdgcn_s_setprio(0);
     qn = 0;
+  }
+  if (P.counters && c_rays) {
+    atomicAdd(P.counters + counter_base + 0, (unsigned long long)c_rays);
+    atomicAdd(P.counters + counter_base + 1, (unsigned long long)c_nodes);
+    atomicAdd(P.counters + counter_base + 2, (unsigned long long)c_tests);
+    atomicAdd(P.counters + counter_base + 3, (unsigned long long)c_ins);
+    atomicAdd(P.counters + 8 + counter_base / 4, (unsigned long long)c_ties);
+    atomicAdd(P.counters + 10 + counter_base / 4, (unsigned long long)c_pass);
+    atomicAdd(P.counters + 12 + counter_base / 4, (unsigned long long)c_hits);
+    atomicAdd(P.counters + 14 + counter_base / 4, (unsigned long long)c_push);
+    atomicMax(P.counters + 16 + counter_base / 4, (unsigned long long)c_deep);
+    atomicAdd(P.counters + 18 + counter_base / 4, (unsigned long long)c_hinted);
+    atomicAdd(P.counters + 20 + counter_base / 4, (unsigned long long)c_retry);
+  }
+}
+
+// ------------------------------------------------------------ wave packets
+// N dwords at a wave-uniform address, read through the scalar data cache
+// (loads from the constant address space with a uniform address are scalar).
+template <int N>
+__device__ __forceinline__ void load_uniform(const void *p, uint32_t *out) {
+  const __attribute__((address_space(4))) uint32_t *q = (const __attribute__((address_space(4))) uint32_t *)p;
+#pragma unroll
+  for (int i = 0; i < N; ++i) out[i] = q[i];
+}
+
+// OR over the wave's lanes of an 8-bit mask per lane.
+__device__ __forceinline__ uint32_t wave_or8(uint32_t m) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) r |= __ballot((m >> j) & 1u) != 0ull ? (1u << j) : 0u;
+  return r;
+}
+
+// First item of range `part` of a pool split into kPoolParts ranges that
+// start at multiples of 64 (one wave packet).
+__device__ __forceinline__ int64_t packet_part_lo(int64_t count, int part) {
+  return part >= kPoolParts ? count : ((count * part / kPoolParts) & ~(int64_t)63);
+}
+
+// Traversal of a pool of coherent rays as wave packets: a wave takes 64
+// consecutive items (half a 16x8-pixel tile of camera rays: 8x8 pixels) and
+// its lanes walk one node sequence together.  A node is visited when any
+// lane's ray entered its box; every lane tests the node's child boxes with its
+// own ray and its own current k-th distance, and a leaf any lane entered is
+// tested by each lane that entered it, at once, so the node, filter record
+// and trace record come through the scalar cache once per wave.  The next
+// node is the hit internal child nearest along the first visiting lane's ray;
+// the other hit internal children of all lanes are pushed as one entry on a
+// per-wave LDS stack (wstk, kStackL entries) in the format of trace_pool and
+// taken along the node's order axis.  Each lane still tests every surfel its own traversal would
+// (it takes part in every node its ray entered) and some more, with the same
+// pre-filter, exact test and insertion, so its k-buffer ends exactly as with
+// trace_pool; hints, retries, the abort word and the counters follow
+// trace_pool too.
+template <int K, class Work>
+__device__ void trace_packet(const SceneView &S0, const TraceParams &P, const Work &wk, int64_t count,
+                             uint32_t *next, int *wstk, uint32_t *status, int counter_base) {
+  constexpr int kDone = (int)0x80000000;
+  const float t_min_f = round_down_f(P.t_min);
+  const float tlo = (float)(0.5 * P.t_min);
+  const int lane = (int)(threadIdx.x & 63u);
+  uint32_t c_rays = 0, c_nodes = 0, c_tests = 0, c_ins = 0, c_ties = 0, c_pass = 0, c_hits = 0, c_push = 0;
+  uint32_t c_hinted = 0, c_retry = 0;
+  int c_deep = 0;
+  auto count_exact = [&](int r) {
+    c_ins += r & 1;
+    c_ties += (r >> 1) & 1;
+    ++c_pass;
+    c_hits += r >> 3;
+  };
+  SceneView S = S0;
+  int part = (int)(blockIdx.x % kPoolParts), tried = 0;
+  bool aborted = false;
+  uint32_t takes = 0;
+  while (tried < kPoolParts) {
+    if (P.abort && !aborted && (takes & 7u) == 0 &&
+        __hip_atomic_load(P.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) {
+      aborted = true;
+      if (lane == 0) atomicOr(status, kStatusAborted);
+    }
+    ++takes;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(next + part, 64u);
+    base = (uint32_t)__shfl((int)base, 0);
+    const int64_t hi = packet_part_lo(count, part + 1);
+    const int64_t first = packet_part_lo(count, part) + (int64_t)base;
+    if (first >= hi) {  // this range is used up: move to the next one
+      part = part + 1 == kPoolParts ? 0 : part + 1;
+      ++tried;
+      continue;
+    }
+    const int64_t item = first + lane;
+    d3 o = mk(0, 0, 0), d = mk(0, 0, 1);
+    const InstRec *inst = S0.inst;
+    const bool live = item < hi && wk.begin(item, o, d, inst);
+    KBufF<K> kb;
+    kinit<K>(kb, P.k);
+    const unsigned long long lv = __ballot(live);
+    if (lv == 0ull) continue;
+    if (aborted) {  // stored with no hits, nothing traversed
+      if (live) wk.store(item, kb);
+      continue;
+    }
+    // the rays of a packet belong to one request: its instance records
+    {
+      const int ldr = __ffsll((long long)lv) - 1;
+      const uint64_t ip = (uint64_t)inst;
+      const uint32_t ilo = (uint32_t)__shfl((int)(uint32_t)ip, ldr), ihi = (uint32_t)__shfl((int)(uint32_t)(ip >> 32), ldr);
+      S.inst = (const InstRec *)(((uint64_t)ihi << 32) | ilo);
+    }
+    bool bounded = false;
+    if (live) {
+      ++c_rays;
+      const float h = wk.hint(item);
+      bounded = h >= 0.0f && h < INFINITY;
+      if (bounded) {
+        const float bnd = next_up_f(h);
+#pragma unroll
+        for (int j = 0; j < K; ++j) kb.t[j] = kb.t[j] == INFINITY ? bnd : kb.t[j];
+        ++c_hinted;
+      }
+    }
+    bool act = live;
+    for (int round = 0; round < 2; ++round) {
+      if (!__any(act)) break;
+      for (int ii = 0; ii < S.n_inst; ++ii) {
+        const InstRec &I = S.inst[ii];
+        if (I.n <= 0) continue;
+        bool in = false;
+        d3 oo = o, dd = d;
+        RayF rf;
+        if (act) {
+          double itn, itf;
+          in = slab64(o, d, I.lo, I.hi, itn, itf) && itf >= P.t_min && !(itn > kth<K>(kb) * (1.0 + 1e-6));
+          if (in) {
+            to_object(I, o, d, oo, dd);
+            make_rayf(oo, dd, fmax(fabs(itf), fabs(itn)), I.omag, I.oext, rf);
+          }
+        }
+        if (!__any(in)) continue;
+        const int root = I.root;
+        if (root < 0) {  // a one-surfel instance
+          if (in) {
+            const int r = test_surfel<K>(S, ~root, oo, dd, rf, P.t_min, t_min_f, kb, o, d);
+            ++c_tests;
+            if (r) count_exact(r);
+          }
+          continue;
+        }
+        int sp = 0, cur = root;
+        while (true) {
+          if (cur < 0 || cur >= S.n_nodes) {  // never taken for a consistent hierarchy
+            if (lane == 0) atomicOr(status, kStatusBvhCorrupt);
+            break;
+          }
+          uint32_t dw[kNodeDw];
+          load_uniform<kNodeDw>(S.nodes + __builtin_amdgcn_readfirstlane(cur), dw);
+          const uint32_t im = dw[3] >> 24;
+          const int cbase = (int)dw[4], lbase = (int)dw[5];
+          uint32_t ih = 0, lh = 0;
+          bool desc = false;
+          float tsv[kWide];
+          if (in) {
+            ++c_nodes;
+            const float tkf = kb.t[K - 1];
+            const float thi = tkf < INFINITY ? next_up_f(tkf) * (1.0f + 1e-6f) : INFINITY;
+            uint32_t im2;
+            int cb2, lb2;
+            visit_node_dw(dw, rf, tlo, thi, tsv, ih, lh, im2, cb2, lb2, desc);
+          }
+          // leaves some lane entered, in slot order (leaf slots follow the internal ones)
+          const int leaf0 = lbase - __builtin_popcount(im);
+          for (uint32_t m = wave_or8(lh); m; m &= m - 1u) {
+            const int j = __builtin_ctz(m);
+            const int pos = __builtin_amdgcn_readfirstlane(leaf0 + j);
+            if (pos < 0 || pos >= S.n_rec) {  // never taken for a consistent hierarchy
+              if (lane == 0) atomicOr(status, kStatusBvhCorrupt);
+              continue;
+            }
+            uint32_t fw[12];
+            load_uniform<12>(S.filt + pos, fw);
+            FiltRec fr;
+            fr.v0 = make_float4(__uint_as_float(fw[0]), __uint_as_float(fw[1]), __uint_as_float(fw[2]),
+                                __uint_as_float(fw[3]));
+            fr.v1 = make_float4(__uint_as_float(fw[4]), __uint_as_float(fw[5]), __uint_as_float(fw[6]),
+                                __uint_as_float(fw[7]));
+            fr.v2 = make_float4(__uint_as_float(fw[8]), __uint_as_float(fw[9]), __uint_as_float(fw[10]),
+                                __uint_as_float(fw[11]));
+            bool pass = false;
+            if ((lh >> j) & 1u) {
+              ++c_tests;
+              const float tk = kb.t[K - 1];
+              pass = prefilter(fr, rf, t_min_f, tk < INFINITY ? next_up_f(tk) : INFINITY);
+            }
+            if (__any(pass)) {
+              uint32_t rw[sizeof(TraceRec) / 4];
+              load_uniform<sizeof(TraceRec) / 4>(S.rec + pos, rw);
+              TraceRec rec;
+              __builtin_memcpy(&rec, rw, sizeof rec);
+              if (pass) count_exact(exact_insert_rec<K>(S, rec, pos, oo, dd, P.t_min, kb, o, d));
+            }
+          }
+          const uint32_t iu = wave_or8(ih);
+          if (iu == 0) {  // next from the stack's top entry
+            cur = kDone;
+            if (sp > 0) {
+              const uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane(wstk[sp - 1]), mk8 = v & 0xffu;
+              const int b = (v >> 31) ? 31 - __builtin_clz(mk8) : __builtin_ctz(mk8);
+              const uint32_t rest = mk8 & ~(1u << b);
+              if (rest) {
+                if (lane == 0) wstk[sp - 1] = (int)((v & ~0xffu) | rest);
+              } else {
+                --sp;
+              }
+              cur = (int)((v >> 8) & 0x7fffffu) + b;
+            }
+            if (cur == kDone) break;
+            continue;
+          }
+          // next, the child nearest along the first visiting lane's ray (its
+          // own hit children keyed as in trace_pool); the others of every
+          // lane onto the stack as one entry, taken along the node's axis in
+          // the direction that lane's ray runs
+          const int ldr = __ffsll((long long)__ballot(ih != 0u)) - 1;
+          const bool dsc = __shfl((int)desc, ldr) != 0;
+          int bl = dsc ? 31 - __builtin_clz(ih | 1u) : __builtin_ctz(ih | 0x100u);
+          if (ih & (ih - 1u)) {
+            uint32_t key[kWide];
+#pragma unroll
+            for (int j = 0; j < kWide; ++j)
+              key[j] = ((ih >> j) & 1u) ? (__float_as_uint(tsv[j]) & ~7u) | (uint32_t)j : 0xffffffffu;
+            bl = (int)(min(min(min(key[0], key[1]), min(key[2], key[3])), min(min(key[4], key[5]), min(key[6], key[7]))) & 7u);
+          }
+          const int bj = __shfl(bl, ldr);
+          const uint32_t rest = iu & ~(1u << bj);
+          if (rest) {
+            if (sp >= kStackL) {  // never taken for a hierarchy the build accepted
+              if (lane == 0) atomicOr(status, kStatusOverflow);
+              break;
+            }
+            if (lane == 0) wstk[sp] = (int)((dsc ? 0x80000000u : 0u) | ((uint32_t)cbase << 8) | rest);
+            ++sp;
+            if (in) ++c_push;
+            c_deep = sp > c_deep ? sp : c_deep;
+          }
+          cur = cbase + bj;
+        }
+      }
+      // fewer than k valid hits below a ray's bound: it is traced again without it
+      act = act && bounded && kb.id[K - 1] == kIdMask;
+      if (act) {
+        bounded = false;
+        ++c_retry;
+        kinit<K>(kb, P.k);
+      }
+    }
+    if (live) wk.store(item, kb);
   }
   if (P.counters && c_rays) {
     atomicAdd(P.counters + counter_base + 0, (unsigned long long)c_rays);

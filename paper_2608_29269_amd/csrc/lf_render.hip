@@ -346,6 +346,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_trace1(RenderArgs a) {
   trace_pool<K>(a.S, a.P, wk, primary_items<B>(a), a.work, stk + threadIdx.x, lq + threadIdx.x, a.status, 0);
 }
 
+// the same as wave packets, for camera tiles and batch chunks (8x8 pixels per wave)
+template <int K, bool B>
+__global__ __launch_bounds__(kBlock, 2) void k_trace1p(RenderArgs a) {
+  __shared__ int wstk[(kBlock / 64) * kStackL];
+  const PrimaryWork<K, B> wk{a};
+  trace_packet<K>(a.S, a.P, wk, primary_items<B>(a), a.work, wstk + (threadIdx.x / 64) * kStackL, a.status, 0);
+}
+
 // compositing of every primary ray's k-buffer, record and outputs
 template <int K, bool B>
 __global__ __launch_bounds__(kBlock) void k_composite1(RenderArgs a, bool replay) {
@@ -576,7 +584,10 @@ template <int K, bool B>
 void trace1_k(const RenderArgs &a, hipStream_t st) {
   const int64_t items = (!B && a.n_tiles) ? a.n_tiles * kBlock : a.R;
   launch_fill_u32(a.work, 0u, kPoolParts, st);
-  hipLaunchKernelGGL((k_trace1<K, B>), dim3(pool_blocks<k_trace1<K, B>>(items)), dim3(kBlock), 0, st, a);
+  if ((B || a.n_tiles) && !(a.P.flags & LF_FLAG_BRUTE_FORCE))  // coherent camera rays
+    hipLaunchKernelGGL((k_trace1p<K, B>), dim3(pool_blocks<k_trace1p<K, B>>(items)), dim3(kBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_trace1<K, B>), dim3(pool_blocks<k_trace1<K, B>>(items)), dim3(kBlock), 0, st, a);
 }
 template <int K, bool B>
 void composite1_k(const RenderArgs &a, bool replay, hipStream_t st) {

@@ -85,6 +85,24 @@ def test_bvh_traversal_equals_brute_force(tracer, c2_small):
         assert np.array_equal(a[key].cpu().numpy(), b[key].cpu().numpy()), key
 
 
+def test_wave_packet_and_per_lane_traversals_agree(tracer, c2_small):
+    """Camera tiles are traced as wave packets (one node sequence per 8x8
+    pixels), explicit rays one per lane.  The camera's own rays passed as
+    explicit rays (the same ids) give bitwise the same primary and secondary
+    hit lists and outputs."""
+    wl = c2_small
+    st = wl.states[0]
+    upload_scene(tracer, wl.scene)
+    cam = st.cameras[0]
+    args = state_args(tracer, wl.scene, st)
+    a = tracer.render(**args, cameras=[cam], k=32, spp=2, seed=4, hit_idx=True, sec_hit_idx=True)
+    o, d = tracer.raygen(cam)
+    b = tracer.render(**args, rays=(o, d), k=32, spp=2, seed=4, hit_idx=True, sec_hit_idx=True)
+    for key in a:
+        assert np.array_equal(a[key].cpu().numpy(), b[key].cpu().numpy()), key
+    assert (a["hit_idx"].cpu().numpy() >= 0).any()
+
+
 def test_c2_one_bounce_parity(tracer, c2_small):
     wl = c2_small
     st = wl.states[0]
