@@ -798,7 +798,7 @@ def source_digest():
 
 
 # Kernels that each own one phase timer (one launch per call) and what they process.
-KERNEL_OF_PHASE = {"trace1": "k_trace1<32, false>", "trace2": "k_trace2<32, false>",
+KERNEL_OF_PHASE = {"trace1": "k_trace1p<32, false>", "trace2": "k_trace2<32, false>",
                    "composite1": "k_composite1<32, false>", "composite2": "k_composite2<32, false>",
                    "adj_hits": "k_adj_hits<32>"}
 
