@@ -584,7 +584,12 @@ template <int K, bool B>
 void trace1_k(const RenderArgs &a, hipStream_t st) {
   const int64_t items = (!B && a.n_tiles) ? a.n_tiles * kBlock : a.R;
   launch_fill_u32(a.work, 0u, kPoolParts, st);
-  if ((B || a.n_tiles) && !(a.P.flags & LF_FLAG_BRUTE_FORCE))  // coherent camera rays
+  // coherent camera rays as wave packets once every resident block has some
+  // to take; smaller launches are bound by their slowest rays, and one ray per
+  // lane spreads them thinner
+  bool packets = (B || a.n_tiles) && !(a.P.flags & LF_FLAG_BRUTE_FORCE);
+  if (packets) packets = items >= (int64_t)pool_blocks<k_trace1p<K, B>>(INT64_MAX / 4) * kBlock;
+  if (packets)
     hipLaunchKernelGGL((k_trace1p<K, B>), dim3(pool_blocks<k_trace1p<K, B>>(items)), dim3(kBlock), 0, st, a);
   else
     hipLaunchKernelGGL((k_trace1<K, B>), dim3(pool_blocks<k_trace1<K, B>>(items)), dim3(kBlock), 0, st, a);

@@ -86,21 +86,29 @@ def test_bvh_traversal_equals_brute_force(tracer, c2_small):
 
 
 def test_wave_packet_and_per_lane_traversals_agree(tracer, c2_small):
-    """Camera tiles are traced as wave packets (one node sequence per 8x8
-    pixels), explicit rays one per lane.  The camera's own rays passed as
-    explicit rays (the same ids) give bitwise the same primary and secondary
-    hit lists and outputs."""
+    """Large camera launches are traced as wave packets (one node sequence
+    per 8x8 pixels), explicit rays one per lane.  At 512x512 the camera's own
+    rays passed as explicit rays (the same ids) give bitwise the same primary
+    and secondary hit lists and outputs; the per-ray node counts differ, so
+    the two traversals really ran."""
+    import paper_2608_29269_amd as lf
     wl = c2_small
     st = wl.states[0]
     upload_scene(tracer, wl.scene)
-    cam = st.cameras[0]
+    cam = scenegen.sphere_camera(np.random.default_rng(12), 512, 512)
     args = state_args(tracer, wl.scene, st)
-    a = tracer.render(**args, cameras=[cam], k=32, spp=2, seed=4, hit_idx=True, sec_hit_idx=True)
+    tracer.trace_counters()
+    a = tracer.render(**args, cameras=[cam], k=32, spp=2, seed=4, hit_idx=True, sec_hit_idx=True,
+                      flags=lf.FLAG_COUNT)
+    ca = tracer.trace_counters()
     o, d = tracer.raygen(cam)
-    b = tracer.render(**args, rays=(o, d), k=32, spp=2, seed=4, hit_idx=True, sec_hit_idx=True)
+    b = tracer.render(**args, rays=(o, d), k=32, spp=2, seed=4, hit_idx=True, sec_hit_idx=True,
+                      flags=lf.FLAG_COUNT)
+    cb = tracer.trace_counters()
     for key in a:
         assert np.array_equal(a[key].cpu().numpy(), b[key].cpu().numpy()), key
     assert (a["hit_idx"].cpu().numpy() >= 0).any()
+    assert ca["primary"]["rays"] == cb["primary"]["rays"] and ca["primary"]["nodes"] != cb["primary"]["nodes"], (ca, cb)
 
 
 def test_c2_one_bounce_parity(tracer, c2_small):
