@@ -85,15 +85,19 @@ def test_bvh_traversal_equals_brute_force(tracer, c2_small):
         assert np.array_equal(a[key].cpu().numpy(), b[key].cpu().numpy()), key
 
 
-def test_wave_packet_and_per_lane_traversals_agree(tracer, c2_small):
+@pytest.mark.parametrize("scene", ["c2_small", "instanced"])
+def test_wave_packet_and_per_lane_traversals_agree(tracer, c2_small, scene):
     """Large camera launches are traced as wave packets (one node sequence
     per 8x8 pixels), explicit rays one per lane.  At 512x512 the camera's own
     rays passed as explicit rays (the same ids) give bitwise the same primary
-    and secondary hit lists and outputs; the per-ray node counts differ, so
-    the two traversals really ran."""
+    and secondary hit lists and outputs, on a surface scene and on an
+    instanced one with moved objects; the per-ray node counts differ, so the
+    two traversals really ran.  The replayed backward (order-fixed sums)
+    gives bitwise the same gradients too: its primary replay runs each
+    traversal from the forward's k-th distances."""
     import paper_2608_29269_amd as lf
-    wl = c2_small
-    st = wl.states[0]
+    wl = c2_small if scene == "c2_small" else scenegen.make_workload(4, scale=0.02, resolution=48)
+    st = wl.states[0] if scene == "c2_small" else wl.states[2]
     upload_scene(tracer, wl.scene)
     cam = scenegen.sphere_camera(np.random.default_rng(12), 512, 512)
     args = state_args(tracer, wl.scene, st)
@@ -109,6 +113,15 @@ def test_wave_packet_and_per_lane_traversals_agree(tracer, c2_small):
         assert np.array_equal(a[key].cpu().numpy(), b[key].cpu().numpy()), key
     assert (a["hit_idx"].cpu().numpy() >= 0).any()
     assert ca["primary"]["rays"] == cb["primary"]["rays"] and ca["primary"]["nodes"] != cb["primary"]["nodes"], (ca, cb)
+    up = dev(np.random.default_rng(3).standard_normal((o.shape[0], 3)).astype(np.float32))
+    det = int(lf.FLAG_DETERMINISTIC)
+    tracer.render(**args, cameras=[cam], k=32, spp=2, seed=4)
+    ga = tracer.render_backward(**args, cameras=[cam], k=32, spp=2, seed=4, flags=det, d_radiance=up)
+    ga = {key: v.cpu().numpy() for key, v in ga.items()}
+    tracer.render(**args, rays=(o, d), k=32, spp=2, seed=4)
+    gb = tracer.render_backward(**args, rays=(o, d), k=32, spp=2, seed=4, flags=det, d_radiance=up)
+    for key, v in gb.items():
+        assert np.array_equal(ga[key], v.cpu().numpy()), key
 
 
 def test_c2_one_bounce_parity(tracer, c2_small):
