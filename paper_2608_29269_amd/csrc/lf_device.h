@@ -1032,12 +1032,18 @@ __device__ __forceinline__ void load_uniform(const void *p, uint32_t *out) {
   for (int i = 0; i < N; ++i) out[i] = q[i];
 }
 
-// OR over the wave's lanes of an 8-bit mask per lane.
-__device__ __forceinline__ uint32_t wave_or8(uint32_t m) {
-  uint32_t r = 0;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) r |= __ballot((m >> j) & 1u) != 0ull ? (1u << j) : 0u;
-  return r;
+// OR of v over the 64 lanes of a wave whose lanes are all active: within
+// each row of 16 lanes by DPP shifts, then across rows by the row
+// broadcasts, so lane 63 holds the result.
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  int x = (int)v;
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane(x, 63);
 }
 
 // First item of range `part` of a pool split into kPoolParts ranges that
@@ -1177,9 +1183,12 @@ __device__ void trace_packet(const SceneView &S0, const TraceParams &P, const Wo
             int cb2, lb2;
             visit_node_dw(dw, rf, tlo, thi, tsv, ih, lh, im2, cb2, lb2, desc);
           }
-          // leaves some lane entered, in slot order (leaf slots follow the internal ones)
+          // the leaf and internal slots some lane entered (every lane of the wave runs this)
+          const uint32_t hu = wave_or(lh | (ih << 8));
+          const uint32_t iu = hu >> 8;
+          // leaves, in slot order (leaf slots follow the internal ones)
           const int leaf0 = lbase - __builtin_popcount(im);
-          for (uint32_t m = wave_or8(lh); m; m &= m - 1u) {
+          for (uint32_t m = hu & 0xffu; m; m &= m - 1u) {
             const int j = __builtin_ctz(m);
             const int pos = __builtin_amdgcn_readfirstlane(leaf0 + j);
             if (pos < 0 || pos >= S.n_rec) {  // never taken for a consistent hierarchy
@@ -1209,7 +1218,6 @@ __device__ void trace_packet(const SceneView &S0, const TraceParams &P, const Wo
               if (pass) count_exact(exact_insert_rec<K>(S, rec, pos, oo, dd, P.t_min, kb, o, d));
             }
           }
-          const uint32_t iu = wave_or8(ih);
           if (iu == 0) {  // next from the stack's top entry
             cur = kDone;
             if (sp > 0) {
