@@ -85,21 +85,22 @@ def test_bvh_traversal_equals_brute_force(tracer, c2_small):
         assert np.array_equal(a[key].cpu().numpy(), b[key].cpu().numpy()), key
 
 
-@pytest.mark.parametrize("scene", ["c2_small", "instanced"])
-def test_wave_packet_and_per_lane_traversals_agree(tracer, c2_small, scene):
+@pytest.mark.parametrize("scene,w,h", [("c2_small", 512, 512), ("instanced", 512, 512), ("c2_small", 601, 433)])
+def test_wave_packet_and_per_lane_traversals_agree(tracer, c2_small, scene, w, h):
     """Large camera launches are traced as wave packets (one node sequence
     per 8x8 pixels), explicit rays one per lane.  At 512x512 the camera's own
     rays passed as explicit rays (the same ids) give bitwise the same primary
     and secondary hit lists and outputs, on a surface scene and on an
-    instanced one with moved objects; the per-ray node counts differ, so the
-    two traversals really ran.  The replayed backward (order-fixed sums)
+    instanced one with moved objects, and at 601x433, whose last tile column
+    and row are partial (packets with idle lanes); the per-ray node counts
+    differ, so the two traversals really ran.  The replayed backward (order-fixed sums)
     gives bitwise the same gradients too: its primary replay runs each
     traversal from the forward's k-th distances."""
     import paper_2608_29269_amd as lf
     wl = c2_small if scene == "c2_small" else scenegen.make_workload(4, scale=0.02, resolution=48)
     st = wl.states[0] if scene == "c2_small" else wl.states[2]
     upload_scene(tracer, wl.scene)
-    cam = scenegen.sphere_camera(np.random.default_rng(12), 512, 512)
+    cam = scenegen.sphere_camera(np.random.default_rng(12), w, h)
     args = state_args(tracer, wl.scene, st)
     tracer.trace_counters()
     a = tracer.render(**args, cameras=[cam], k=32, spp=2, seed=4, hit_idx=True, sec_hit_idx=True,
